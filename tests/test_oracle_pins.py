@@ -1,0 +1,559 @@
+"""Pins of the CPU oracle against things other than itself: library routines (numpy, scipy,
+PyTorch's Philox engine, exact rational arithmetic), closed forms, brute force on tiny
+inputs and invariants that follow from the paper's definitions (Li, arXiv:1704.03217)."""
+import math
+import os
+import subprocess
+import tempfile
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+import synth
+from conftest import base_params
+
+RNG = np.random.default_rng(12345)
+
+
+# --------------------------------------------------------------------------------------
+# borders, pyramid, gradient image (Sec. III-A, III-D)
+# --------------------------------------------------------------------------------------
+
+def test_reflect101_is_numpy_reflect():
+    for n in range(1, 8):
+        pad = 3 * n + 12
+        ext = np.pad(np.arange(n), pad, mode="reflect")
+        for i in range(-pad, n + pad):
+            assert oracle.reflect101(i, n) == ext[i + pad], (i, n)
+
+
+def _binomial(k):
+    """binomial taps of length k from repeated [1, 1] convolutions (library routine)"""
+    t = np.array([1])
+    for _ in range(k - 1):
+        t = np.convolve(t, [1, 1])
+    return t
+
+
+@pytest.mark.parametrize("shape", [(9, 11, 3), (16, 16, 3), (7, 13, 1), (31, 20, 3)])
+def test_pyr_down_is_binomial_filter_and_decimation(shape):
+    img = RNG.integers(0, 256, shape, dtype=np.uint8)
+    got = oracle.pyr_down(img[..., 0] if shape[2] == 1 else img)
+    b5 = _binomial(5)
+    k = np.outer(b5, b5)
+    assert k.sum() == 256
+    chans = [img[..., c].astype(np.int64) for c in range(shape[2])]
+    exp = [((ndimage.correlate(c, k, mode="mirror") + 128) >> 8)[::2, ::2] for c in chans]
+    exp = np.stack(exp, -1).astype(np.uint8)
+    assert got.reshape(exp.shape).shape == ((shape[0] + 1) // 2, (shape[1] + 1) // 2, shape[2])
+    np.testing.assert_array_equal(got.reshape(exp.shape), exp)
+
+
+def test_pyr_down_keeps_constants():
+    for v in (0, 1, 127, 255):
+        img = np.full((13, 21, 3), v, np.uint8)
+        assert (oracle.pyr_down(img) == v).all()
+
+
+def test_gray_keeps_gray_inputs():
+    v = np.arange(256, dtype=np.uint8)
+    img = np.repeat(v[None, :, None], 3, axis=2)
+    np.testing.assert_array_equal(oracle.gray(img)[0], v)
+
+
+@pytest.mark.parametrize("shape", [(12, 17, 3), (8, 9, 1), (25, 6, 3)])
+def test_gradient_s3_is_scipy_sobel(shape):
+    img = RNG.integers(0, 256, shape, dtype=np.uint8)
+    G = oracle.gradient_image(img[..., 0] if shape[2] == 1 else img, 3)
+    ch = shape[2]
+    for c in range(ch):
+        I = img[..., c].astype(np.int64)
+        np.testing.assert_array_equal(G[..., c], ndimage.sobel(I, axis=1, mode="mirror"))
+        np.testing.assert_array_equal(G[..., ch + c], ndimage.sobel(I, axis=0, mode="mirror"))
+
+
+@pytest.mark.parametrize("shape", [(12, 17, 3), (9, 9, 1), (20, 31, 3)])
+def test_gradient_s5_is_s3_of_binomial_smoothed(shape):
+    """S=5 Sobel = S=3 Sobel after one more [1 2 1] x [1 2 1] smoothing; with mirror borders
+    the identity also holds at the border (the even extension commutes with both)."""
+    img = RNG.integers(0, 256, shape, dtype=np.uint8)
+    G = oracle.gradient_image(img[..., 0] if shape[2] == 1 else img, 5)
+    ch = shape[2]
+    b3 = _binomial(3)
+    for c in range(ch):
+        I = img[..., c].astype(np.int64)
+        S = ndimage.correlate(I, np.outer(b3, b3), mode="mirror")
+        np.testing.assert_array_equal(G[..., c], ndimage.sobel(S, axis=1, mode="mirror"))
+        np.testing.assert_array_equal(G[..., ch + c], ndimage.sobel(S, axis=0, mode="mirror"))
+
+
+@pytest.mark.parametrize("ksize,gain", [(3, 8), (5, 128)])
+def test_gradient_ramp_closed_form(ksize, gain):
+    """On I = a x + b y the interior gradient is (gain a, gain b) with gain = 8 (S=3) or 128
+    (S=5); the sign is positive where intensity rises."""
+    h, w = 20, 24
+    for a, b in ((1, 0), (0, 2), (3, -2), (-4, 5), (-2, -3)):
+        yy, xx = np.mgrid[0:h, 0:w]
+        I = 120 + a * xx + b * yy
+        assert I.min() >= 0 and I.max() <= 255
+        img = np.repeat(I[..., None], 3, axis=2).astype(np.uint8)
+        G = oracle.gradient_image(img, ksize)
+        k = ksize // 2
+        inner = G[k:h - k, k:w - k]
+        assert (inner[..., 0:3] == gain * a).all() and (inner[..., 3:6] == gain * b).all()
+
+
+def test_gradient_bounds():
+    img = np.zeros((12, 12, 3), np.uint8)
+    img[:, 6:] = 255
+    G = oracle.gradient_image(img, 5)
+    assert np.abs(G).max() == 48 * 255
+
+
+def test_direction_unit_vectors():
+    G = RNG.integers(-12240, 12241, (40, 40, 6)).astype(np.int16)
+    G[::3, ::5] = 0
+    G[1, 1, 0] = 1
+    G[1, 1, 3] = 12240
+    U = oracle.direction(G)
+    assert U.dtype == np.float32
+    for c in range(3):
+        gx = G[..., c].astype(np.float64)
+        gy = G[..., 3 + c].astype(np.float64)
+        ux = U[..., c].astype(np.float64)
+        uy = U[..., 3 + c].astype(np.float64)
+        nz = (gx != 0) | (gy != 0)
+        assert (ux[~nz] == 0).all() and (uy[~nz] == 0).all()
+        np.testing.assert_allclose(ux[nz] ** 2 + uy[nz] ** 2, 1.0, atol=3e-7)
+        ang = np.arctan2(gy[nz], gx[nz])
+        np.testing.assert_allclose(np.arctan2(uy[nz], ux[nz]), ang, atol=1e-6)
+        # nonzero components are at least 2^-14 in magnitude (used by the exact distance)
+        comp = np.abs(np.concatenate([ux[nz], uy[nz]]))
+        assert comp[comp > 0].min() >= 2.0 ** -14
+
+
+# --------------------------------------------------------------------------------------
+# patch distance (Eq. 3, absolute-difference reading)
+# --------------------------------------------------------------------------------------
+
+def _brute_dist(Ga, Gb, P, xa, ya, xb, yb):
+    h, w = Ga.shape[:2]
+    o = np.arange(-(P // 2), (P + 1) // 2)
+    ya_i = np.clip(ya + o, 0, h - 1)[:, None]
+    xa_i = np.clip(xa + o, 0, w - 1)[None, :]
+    yb_i = np.clip(yb + o, 0, h - 1)[:, None]
+    xb_i = np.clip(xb + o, 0, w - 1)[None, :]
+    return Ga[ya_i, xa_i].astype(np.float64), Gb[yb_i, xb_i].astype(np.float64)
+
+
+@pytest.mark.parametrize("P", [1, 4, 5, 8, 11, 15, 16])
+def test_dist_i16_brute_force(P):
+    h, w = 19, 23
+    Ga = RNG.integers(-12240, 12241, (h, w, 6)).astype(np.int16)
+    Gb = RNG.integers(-12240, 12241, (h, w, 6)).astype(np.int16)
+    pts = [(0, 0), (w - 1, h - 1), (3, 17), (22, 0)] + [tuple(RNG.integers(0, (w, h))) for _ in range(20)]
+    for (xa, ya) in pts:
+        xb, yb = int(RNG.integers(0, w)), int(RNG.integers(0, h))
+        A, B = _brute_dist(Ga, Gb, P, int(xa), int(ya), xb, yb)
+        assert oracle.dist(Ga, Gb, P, int(xa), int(ya), xb, yb) == int(np.abs(A - B).sum())
+        # symmetric in its arguments, zero on identical patches
+        assert oracle.dist(Gb, Ga, P, xb, yb, int(xa), int(ya)) == oracle.dist(Ga, Gb, P, int(xa), int(ya), xb, yb)
+        assert oracle.dist(Ga, Ga, P, int(xa), int(ya), int(xa), int(ya)) == 0
+
+
+def test_dist_f32_is_exact_sum_rounded_once():
+    h, w = 17, 21
+    G1 = RNG.integers(-12240, 12241, (h, w, 6)).astype(np.int16)
+    G2 = RNG.integers(-12240, 12241, (h, w, 6)).astype(np.int16)
+    G1[::4] = 0
+    U1, U2 = oracle.direction(G1), oracle.direction(G2)
+    for _ in range(40):
+        xa, ya, xb, yb = (int(v) for v in RNG.integers(0, [w, h, w, h]))
+        P = int(RNG.choice([3, 8, 16]))
+        A, B = _brute_dist(U1, U2, P, xa, ya, xb, yb)
+        exact = math.fsum(abs(Fraction(float(a)) - Fraction(float(b))) for a, b in zip(A.ravel(), B.ravel()))
+        assert oracle.dist(U1, U2, P, xa, ya, xb, yb) == np.float32(exact)
+
+
+# --------------------------------------------------------------------------------------
+# random numbers (Eq. 5 needs uniform R_i; Philox4x32-10 supplies them)
+# --------------------------------------------------------------------------------------
+
+PHILOX_HARNESS = r"""
+#include <ATen/core/PhiloxRNGEngine.h>
+#include <cstdio>
+#include <cstdlib>
+int main(int argc, char** argv) {
+  for (int a = 1; a + 2 < argc; a += 3) {
+    at::philox_engine e(strtoull(argv[a], 0, 0), strtoull(argv[a + 1], 0, 0), strtoull(argv[a + 2], 0, 0));
+    for (int i = 0; i < 4; i++) printf("%u ", e());
+    printf("\n");
+  }
+}
+"""
+
+
+def _torch_include():
+    import torch
+    inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    return inc if os.path.exists(os.path.join(inc, "ATen", "core", "PhiloxRNGEngine.h")) else None
+
+
+@pytest.mark.skipif(_torch_include() is None, reason="PyTorch headers not installed")
+def test_philox_matches_pytorch_engine():
+    """PyTorch's header-only philox_engine(seed, subsequence, offset) produces Philox4x32-10
+    of counter {offset lo, offset hi, subsequence lo, subsequence hi} under key {seed lo,
+    seed hi}."""
+    cases = [(0, 0, 0), (2**64 - 1, 2**64 - 1, 2**64 - 1)]
+    cases += [tuple(int(v) for v in RNG.integers(0, 2**64, 3, dtype=np.uint64)) for _ in range(30)]
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "p.cpp")
+        exe = os.path.join(d, "p")
+        open(src, "w").write(PHILOX_HARNESS)
+        subprocess.check_call(["g++", "-O1", "-std=c++17", "-I", _torch_include(), src, "-o", exe])
+        outs = subprocess.check_output([exe] + [str(v) for c in cases for v in c]).decode().split("\n")
+    for (seed, sub, off), line in zip(cases, outs):
+        ref = [int(v) for v in line.split()]
+        ctr = [off & 0xFFFFFFFF, off >> 32, sub & 0xFFFFFFFF, sub >> 32]
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        assert list(oracle.philox(ctr, key)) == ref
+
+
+def _search_exact(u, W, i):
+    R = Fraction(2 * u + 1, 2**32) - 1
+    return math.floor(R * W / 2**i)
+
+
+def test_search_offset_is_exact_floor():
+    us = [0, 1, 2, 2**30 - 1, 2**30, 2**31 - 1, 2**31, 2**31 + 1, 3 * 2**30, 2**32 - 2, 2**32 - 1]
+    us += [int(v) for v in RNG.integers(0, 2**32, 300, dtype=np.int64)]
+    for W in (1, 2, 3, 5, 13, 16, 100, 1023):
+        nI = int(math.floor(math.log2(W))) + 1
+        for i in range(nI):
+            vals = set()
+            for u in us:
+                v = oracle.search_offset(u, W, i)
+                assert v == _search_exact(u, W, i), (u, W, i)
+                vals.add(v)
+            lim = math.ceil(W / 2**i)
+            assert min(vals) >= -lim and max(vals) <= lim - 1
+    # W = 2: {-2..1} for i = 0 and {-1, 0} for i = 1, equally likely
+    assert {oracle.search_offset(u, 2, 0) for u in (0, 2**30, 2**31, 3 * 2**30)} == {-2, -1, 0, 1}
+    assert {oracle.search_offset(u, 2, 1) for u in (0, 2**31)} == {-1, 0}
+
+
+def test_init_offset_is_exact_and_uniform():
+    for R in (0, 1, 5, 13, 16, 300):
+        for u in [0, 2**32 - 1] + [int(v) for v in RNG.integers(0, 2**32, 200, dtype=np.int64)]:
+            exp = math.floor(Fraction(u, 2**32) * (2 * R + 1)) - R
+            assert oracle.init_offset(u, R) == exp
+    # chi-square over Philox draws
+    R = 5
+    words = np.concatenate([oracle.philox([i, 7, 0, 0], [99, 0]) for i in range(3000)])
+    vals = np.array([oracle.init_offset(int(u), R) for u in words])
+    cnt = np.bincount(vals + R, minlength=2 * R + 1)
+    exp = len(vals) / (2 * R + 1)
+    chi2 = ((cnt - exp) ** 2 / exp).sum()
+    assert chi2 < 35.0   # 10 dof, p ~ 1e-4
+
+
+# --------------------------------------------------------------------------------------
+# seed grid
+# --------------------------------------------------------------------------------------
+
+def test_grid_nearest_brute_force():
+    for stride in range(1, 6):
+        for n in range(1, 25):
+            cnt = oracle.grid_count(n, stride)
+            pos = [oracle.grid_pos(i, n, stride) for i in range(cnt)]
+            assert all(0 <= p < n for p in pos) and pos == sorted(set(pos))
+            assert pos[0] == min(stride // 2, n - 1)
+            if cnt > 1:
+                assert all(b - a == stride for a, b in zip(pos, pos[1:]))
+                assert n - 1 - pos[-1] < stride
+            for x in range(n):
+                d = [abs(x - p) for p in pos]
+                best = min(d)
+                exp = max(i for i in range(cnt) if d[i] == best)
+                assert oracle.grid_nearest(x, cnt, stride) == exp, (stride, n, x)
+
+
+# --------------------------------------------------------------------------------------
+# the whole method on small inputs
+# --------------------------------------------------------------------------------------
+
+def _features(img, ksize=5):
+    return oracle.gradient_image(img, ksize)
+
+
+def _cost_volume(Ga, Gb, P, pts):
+    """D(p, q) for every seed p in pts and every pixel q of Gb (numpy brute force)."""
+    h, w = Gb.shape[:2]
+    o = np.arange(-(P // 2), (P + 1) // 2)
+    yy, xx = np.mgrid[0:h, 0:w]
+    # patches of every q: (h, w, P, P, C)
+    qy = np.clip(yy[..., None, None] + o[:, None], 0, h - 1)
+    qx = np.clip(xx[..., None, None] + o[None, :], 0, w - 1)
+    PB = Gb[qy, qx].astype(np.int64)
+    out = []
+    for (x, y) in pts:
+        A = Ga[np.clip(y + o, 0, h - 1)[:, None], np.clip(x + o, 0, w - 1)[None, :]].astype(np.int64)
+        out.append(np.abs(PB - A).sum(axis=(2, 3, 4)))
+    return np.array(out)
+
+
+def _seed_pts(w, h, stride):
+    nx, ny = oracle.grid_count(w, stride), oracle.grid_count(h, stride)
+    return [(oracle.grid_pos(i, w, stride), oracle.grid_pos(j, h, stride)) for j in range(ny) for i in range(nx)]
+
+
+@pytest.mark.parametrize("seed,P", [(1, 8), (2, 5), (3, 1)])
+def test_exhaustive_init_is_brute_force_argmin(seed, P):
+    pair = synth.rect_pair(seed, 20, 24, n_rect=2, dmax=4)
+    p = base_params(levels=1, iters=[0], init_mode=1, max_disp=0, patch_fwd=P, patch_bwd=P)
+    r = oracle.match(p, pair.img1, pair.img2)
+    G1, G2 = _features(pair.img1), _features(pair.img2)
+    h, w = G1.shape[:2]
+    pts = _seed_pts(w, h, 3)
+    for d, (Ga, Gb) in enumerate(((G1, G2), (G2, G1))):
+        vol = _cost_volume(Ga, Gb, P, pts)
+        st = r["levels"][d][0]
+        for s, (x, y) in enumerate(pts):
+            flat = vol[s].ravel()            # row-major over (qy, qx): dy outer, dx inner
+            k = int(np.argmin(flat))         # first minimum
+            qy, qx = divmod(k, w)
+            assert (st[s, 0], st[s, 1]) == (qx - x, qy - y)
+            assert st[s, 2] == flat[k]
+    # every window position inside the image is evaluated exactly once per seed
+    assert r["n_evals"] == 2 * len(pts) * w * h
+
+
+def test_patchmatch_never_beats_brute_force():
+    pair = synth.rect_pair(7, 24, 32, n_rect=2, dmax=5)
+    p = base_params(levels=1, iters=[8], max_disp=0, rng_seed=77)
+    r = oracle.match(p, pair.img1, pair.img2)
+    G1, G2 = _features(pair.img1), _features(pair.img2)
+    h, w = G1.shape[:2]
+    pts = _seed_pts(w, h, 3)
+    vol = _cost_volume(G1, G2, 8, pts)
+    st = r["levels"][0][0]
+    hits = 0
+    for s, (x, y) in enumerate(pts):
+        assert st[s, 3] & oracle.F_INIT
+        dx, dy = st[s, 0], st[s, 1]
+        assert 0 <= x + dx < w and 0 <= y + dy < h
+        assert st[s, 2] == vol[s, y + dy, x + dx]        # stored distance is D(p, p + d)
+        assert st[s, 2] >= vol[s].min()
+        hits += st[s, 2] == vol[s].min()
+    assert hits >= 0.8 * len(pts)
+
+
+def test_distance_non_increasing_over_iterations():
+    pair = synth.config_pair(1)
+    prev = None
+    for k in range(0, 5):
+        p = base_params(levels=1, iters=[k], max_disp=8, rng_seed=5)
+        r = oracle.match(p, pair.img1[:96, :128], pair.img2[:96, :128])
+        st = r["levels"][0][0]
+        if prev is not None:
+            assert (st[:, 2] <= prev[:, 2]).all()
+            assert (st[:, 2] < prev[:, 2]).any() or k > 3
+        prev = st
+
+
+def _interior(pts, w, h, d, margin):
+    out = []
+    for s, (x, y) in enumerate(pts):
+        if margin <= x < w - margin and margin <= y < h - margin and \
+           margin <= x + d[0] < w - margin and margin <= y + d[1] < h - margin:
+            out.append(s)
+    return out
+
+
+@pytest.mark.parametrize("dx,dy,L,init_mode", [(5, -3, 1, 1), (-7, 2, 1, 0), (10, -6, 2, 0),
+                                                (12, 8, 3, 0), (0, 0, 2, 0), (0, 0, 1, 1)])
+def test_translation_recovered_exactly(dx, dy, L, init_mode):
+    """An integer translation is recovered exactly at interior seeds (distance 0, inlier) and
+    the backward field is its negative. Below the top level the translation must be divisible
+    by 2^level for the coarser images to be exact translations too."""
+    h, w = 72, 96
+    pair = synth.translate_pair(11 + dx, h, w, dx, dy)
+    p = base_params(levels=L, iters=[8] * L, max_disp=16, init_mode=init_mode, rng_seed=3)
+    r = oracle.match(p, pair.img1, pair.img2)
+    pts = _seed_pts(w, h, 3)
+    margin = 4 + 3 + 1
+    st_f, st_b = r["levels"][0][0], r["levels"][1][0]
+    fin = _interior(pts, w, h, (dx, dy), margin)
+    bin_ = _interior(pts, w, h, (-dx, -dy), margin)
+    assert len(fin) > 100
+    for s in fin:
+        assert (st_f[s, 0], st_f[s, 1], st_f[s, 2]) == (dx, dy, 0)
+        assert st_f[s, 3] & oracle.F_INLIER
+    for s in bin_:
+        assert (st_b[s, 0], st_b[s, 1], st_b[s, 2]) == (-dx, -dy, 0)
+
+
+def _nearest_idx(x, n, stride):
+    pos = np.array([oracle.grid_pos(i, 10**9, stride) for i in range(n)])
+    d = np.abs(pos[None, :] - np.asarray(x)[:, None])
+    # ties toward the larger index
+    return (d.shape[1] - 1 - np.argmin(d[:, ::-1], axis=1))
+
+
+def _geom(r, l):
+    return r["geometry"][l]
+
+
+@pytest.mark.parametrize("tau", [1, 3, 10**6])
+def test_consistency_and_record_invariants(tau):
+    """Re-derive Step 2-3 (check + Eq. 7) and Eq. 8 from the oracle's own per-level output."""
+    pair = synth.config_pair(1)
+    p = base_params(levels=4, iters=[3, 3, 3, 3], max_disp=20, consistency_px=tau, rng_seed=9)
+    r = oracle.match(p, pair.img1, pair.img2)
+    L = p["levels"]
+    for l in range(L):
+        lw, lh, nx, ny = _geom(r, l)
+        xs = np.array([oracle.grid_pos(i, lw, 3) for i in range(nx)])
+        ys = np.array([oracle.grid_pos(j, lh, 3) for j in range(ny)])
+        px = np.tile(xs, ny)
+        py = np.repeat(ys, nx)
+        carried = l <= L - 3                      # record carried into levels below m-1
+        for d in range(2):
+            a, b = r["levels"][d][l], r["levels"][1 - d][l]
+            init = (a[:, 3] & oracle.F_INIT) > 0
+            qx, qy = px + a[:, 0], py + a[:, 1]
+            oi = _nearest_idx(qx, nx, 3)
+            oj = _nearest_idx(qy, ny, 3)
+            os_ = oj * nx + oi
+            binit = (b[os_, 3] & oracle.F_INIT) > 0
+            ex = a[:, 0] + b[os_, 0]
+            ey = a[:, 1] + b[os_, 1]
+            cons = init & binit & (ex.astype(np.int64) ** 2 + ey.astype(np.int64) ** 2 <= tau * tau)
+            rec = (a[:, 3] & oracle.F_RECORD) > 0
+            inl = (a[:, 3] & oracle.F_INLIER) > 0
+            exp = cons & rec if carried else cons
+            np.testing.assert_array_equal(inl, exp)
+            if not carried:
+                assert not rec.any()
+            else:
+                # Eq. 8 toward the finer level: record = parent's inlier state
+                pw, ph, pnx, pny = _geom(r, l + 1)
+                pi = _nearest_idx(px // 2, pnx, 3)
+                pj = _nearest_idx(py // 2, pny, 3)
+                par_inl = (r["levels"][d][l + 1][pj * pnx + pi, 3] & oracle.F_INLIER) > 0
+                np.testing.assert_array_equal(rec, par_inl)
+            if tau >= 10**6:
+                np.testing.assert_array_equal(inl, init & binit & (rec if carried else True))
+
+
+def test_level_down_transition():
+    """With no iterations at the finer level, its field is exactly Eq. 6 toward k = j-1:
+    twice the parent's displacement (clamped) where the parent is an inlier, else
+    uninitialised; the stored distance is D(p, p+d)."""
+    pair = synth.config_pair(1)
+    p = base_params(levels=3, iters=[0, 0, 4], max_disp=20, rng_seed=4)
+    r = oracle.match(p, pair.img1, pair.img2)
+    for l in (1, 0):
+        lw, lh, nx, ny = _geom(r, l)
+        pw, ph, pnx, pny = _geom(r, l + 1)
+        img1 = pair.img1
+        img2 = pair.img2
+        for _ in range(l):
+            img1, img2 = oracle.pyr_down(img1), oracle.pyr_down(img2)
+        G = [_features(img1), _features(img2)]
+        for d in range(2):
+            st = r["levels"][d][l]
+            par = r["levels"][d][l + 1]
+            for s in range(nx * ny):
+                i, j = s % nx, s // nx
+                x, y = oracle.grid_pos(i, lw, 3), oracle.grid_pos(j, lh, 3)
+                ps = oracle.grid_nearest(y // 2, pny, 3) * pnx + oracle.grid_nearest(x // 2, pnx, 3)
+                if par[ps, 3] & oracle.F_INLIER:
+                    ex = min(max(x + 2 * par[ps, 0], 0), lw - 1) - x
+                    ey = min(max(y + 2 * par[ps, 1], 0), lh - 1) - y
+                    assert st[s, 3] & oracle.F_INIT
+                    assert (st[s, 0], st[s, 1]) == (ex, ey)
+                    A, B = _brute_dist(G[d], G[1 - d], 8, x, y, x + ex, y + ey)
+                    assert st[s, 2] == int(np.abs(A - B).sum())
+                else:
+                    assert not st[s, 3] & oracle.F_INIT
+
+
+@pytest.mark.parametrize("t", [0, 1, 2, 3])
+def test_propagation_direction_order(t):
+    """Eq. 4 with the FlowFields order of (Delta_x, Delta_y): starting from a single
+    initialised seed, one synchronous iteration spreads it two grid steps along -Delta
+    (first the opposite colour, then the seed's own colour), and a raster pass along the
+    same direction fills the whole quadrant."""
+    h, w = 60, 60
+    img = synth.texture(np.random.default_rng(1), h, w)
+    G = _features(img)
+    nx = ny = oracle.grid_count(w, 3)
+    i0, j0 = 10, 9
+    st = dict(dx=np.zeros(nx * ny), dy=np.zeros(nx * ny), dist=np.zeros(nx * ny),
+              init=np.zeros(nx * ny))
+    st["init"][j0 * nx + i0] = 1
+    p = base_params(levels=1)
+    sx, sy = [(1, 1), (-1, -1), (-1, 1), (1, -1)][t]   # direction of spreading = Delta
+    out, _ = oracle.sweep(p, G, G, st, W=1, t0=t, n_iter=1)
+    got = {(s % nx, s // nx) for s in np.nonzero(out["init"])[0]}
+    exp = {(i0, j0), (i0 + sx, j0), (i0, j0 + sy), (i0 + 2 * sx, j0), (i0 + sx, j0 + sy), (i0, j0 + 2 * sy)}
+    assert got == exp
+    out, _ = oracle.sweep(p, G, G, st, W=1, t0=t, n_iter=1, schedule=oracle.SCAN)
+    got = {(s % nx, s // nx) for s in np.nonzero(out["init"])[0]}
+    exp = {(i, j) for i in range(nx) for j in range(ny) if (i - i0) * sx >= 0 and (j - j0) * sy >= 0}
+    assert got == exp
+
+
+def test_scan_and_sync_schedules_agree_statistically():
+    pair = synth.config_pair(1)
+    p = base_params(levels=3, iters=[4, 4, 4], max_disp=20, rng_seed=1000)
+    a = oracle.match(p, pair.img1, pair.img2, schedule=oracle.SYNC)["fwd"]
+    b = oracle.match(p, pair.img1, pair.img2, schedule=oracle.SCAN)["fwd"]
+    ia, ib = (a["flags"] & 2) > 0, (b["flags"] & 2) > 0
+    assert abs(ia.mean() - ib.mean()) < 0.05
+    both = ia & ib
+    same = (a["x2"] == b["x2"]) & (a["y2"] == b["y2"])
+    assert same[both].mean() > 0.95
+
+
+def test_output_and_compaction():
+    pair = synth.config_pair(1)
+    p = base_params(rng_seed=1000)
+    r = oracle.match(p, pair.img1, pair.img2)
+    f = r["fwd"]
+    inl = (f["flags"] & 2) > 0
+    assert r["n_inliers"] == inl.sum()
+    np.testing.assert_array_equal(r["compact"], f[inl])
+    lv = r["levels"][0][0]
+    init = (lv[:, 3] & 1) > 0
+    np.testing.assert_array_equal(f["x2"] - f["x1"], np.where(init, lv[:, 0], 0))
+    np.testing.assert_array_equal(f["dist"], lv[:, 2])
+    assert (f["dist"][~init] == 0x7FFFFFFF).all()
+    # quality on the synthetic pair: most inliers within 1 px of the ground truth
+    gt = pair.flow[f["y1"], f["x1"]]
+    err = np.hypot(f["x2"] - f["x1"] - gt[:, 0], f["y2"] - f["y1"] - gt[:, 1])
+    assert inl.mean() > 0.7 and (err[inl] < 1).mean() > 0.95
+
+
+def test_direction_variant_runs_and_matches_translation():
+    h, w = 60, 72
+    pair = synth.translate_pair(4, h, w, 6, -2)
+    p = base_params(levels=2, iters=[4, 4], max_disp=12, feature=1, rng_seed=8)
+    r = oracle.match(p, pair.img1, pair.img2)
+    pts = _seed_pts(w, h, 3)
+    st = r["levels"][0][0]
+    for s in _interior(pts, w, h, (6, -2), 8):
+        assert (st[s, 0], st[s, 1]) == (6, -2)
+        assert np.int32(st[s, 2]).view(np.float32) == 0.0
+
+
+def test_invalid_parameters_rejected():
+    img = np.zeros((20, 20, 3), np.uint8)
+    for bad in (dict(levels=0), dict(levels=9), dict(seed_stride=0), dict(patch_fwd=17),
+                dict(sobel_ksize=7), dict(radius=0), dict(feature=5), dict(iters=[300, 4, 4])):
+        with pytest.raises(ValueError):
+            oracle.match(base_params(**bad), img, img)
