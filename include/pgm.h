@@ -1,0 +1,163 @@
+/*
+ * pgm.h -- C ABI of libpgm, pyramidal gradient matching on AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Y. Li, "Pyramidal Gradient Matching for Optical Flow Estimation"
+ * (arXiv:1704.03217): two images in, the gradient image of every level of their pyramids
+ * (Sec. III-A, Eq. 1-2; Sec. III-D), coarse-to-fine limited PatchMatch (Sec. III-B, Eq. 3-5)
+ * on a regular seed grid, a forward-backward consistency check with an outlier record at
+ * every level (Sec. III-C/D, Eq. 6-8), and the level-0 matches on the grid out (Sec. III-G).
+ *
+ * Conventions for every entry point
+ *  - Image and output pointers passed to pgm_match are DEVICE pointers owned by the caller
+ *    (e.g. torch tensors). Pointers named host_* are host pointers owned by the caller.
+ *  - Images are interleaved RGB uint8 (HWC), `pitch_bytes` apart between rows (>= 3*w).
+ *  - A context owns one device workspace allocated once by pgm_create; pgm_match never
+ *    allocates device memory and returns PGM_ENOMEM when the workspace is too small.
+ *  - pgm_match is asynchronous on the caller's HIP stream (a hipStream_t passed as void*;
+ *    NULL is the default stream). Argument errors are reported synchronously; device errors
+ *    are reported by the call that observes them. Calls on one context must not overlap:
+ *    use one context per stream / host thread.
+ *  - All functions return a pgm_status; pgm_last_error() describes the last failure of a
+ *    context in text.
+ */
+#ifndef PGM_H
+#define PGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define PGM_API __attribute__((visibility("default")))
+#else
+#define PGM_API
+#endif
+
+typedef int32_t pgm_status;
+enum {
+    PGM_OK = 0,
+    PGM_EINVAL = -1,       /* invalid argument (bad sizes, parameters or null pointers)   */
+    PGM_ENOMEM = -2,       /* the context's workspace is smaller than pgm_query's figure  */
+    PGM_EDEVICE = -3,      /* a HIP runtime error (message in pgm_last_error)             */
+    PGM_EUNSUPPORTED = -5  /* valid but not supported by this build                       */
+};
+
+enum { PGM_FEAT_INT16 = 0,     /* full gradient image, int16 (PGM-C / PGM-G, Sec. III-F)      */
+       PGM_FEAT_F32_DIR = 1 }; /* direction-only unit gradients, float (PGM-CD / PGM-GD)      */
+enum { PGM_RGB = 0, PGM_GRAY = 1 };                    /* 6- or 2-channel gradient image       */
+enum { PGM_INIT_RANDOM = 0, PGM_INIT_EXHAUSTIVE = 1 }; /* initial field at the coarsest level  */
+
+#define PGM_MAX_LEVELS 8
+
+/* flags of a match */
+#define PGM_FLAG_INIT   1u  /* the field is initialised at this seed                         */
+#define PGM_FLAG_INLIER 2u  /* the outlier record says "no" after the last update (Eq. 7)    */
+#define PGM_FLAG_RECORD 4u  /* the record propagated into this level said "no" (Eq. 8)       */
+
+/* Matching parameters (Sec. IV lists the paper's values: W=2, S=5, L=3, s=1/2, N=2, m=2,
+ * 6 iterations at full resolution and 4 elsewhere; patch radius 7 forward / 5 backward). */
+typedef struct {
+    int32_t levels;                  /* L, pyramid levels, 1..8; the coarsest is m = L-1     */
+    int32_t seed_stride;             /* seed grid spacing in pixels, >= 1 (1 = dense field)  */
+    int32_t patch_fwd, patch_bwd;    /* patch side of the forward / backward field, 1..16    */
+    int32_t iters[PGM_MAX_LEVELS];   /* propagation-search iterations per level (0 = full)   */
+    int32_t radius;                  /* W of Eq. 5 below the initial field, >= 1             */
+    int32_t max_disp;                /* |d| bound at full resolution for the initial field;  */
+                                     /* 0 = the whole image                                  */
+    int32_t sobel_ksize;             /* S of Eq. 1: 3 or 5                                   */
+    int32_t feature;                 /* PGM_FEAT_*                                           */
+    int32_t color;                   /* PGM_RGB or PGM_GRAY                                  */
+    int32_t fwd_bwd;                 /* 1 = forward-backward consistency check at each level */
+    int32_t consistency_px;          /* tau: consistent iff |d_fwd + d_bwd|^2 <= tau^2      */
+    int32_t init_mode;               /* PGM_INIT_*                                           */
+    int32_t refine_rounds;           /* N of Sec. III-D: round trips between m and m-1       */
+    uint64_t rng_seed;               /* key of the counter-based random generator            */
+} pgm_params;
+
+/* One match on the level-0 seed grid: seed (x1, y1) in the first image of the pair and its
+ * match (x2, y2) in the second. dist is the patch distance (int32 sum of absolute gradient
+ * differences, or the bits of a float for PGM_FEAT_F32_DIR); 0x7FFFFFFF and (x2, y2) =
+ * (x1, y1) where the field is uninitialised. flags: PGM_FLAG_*. 24 bytes. */
+typedef struct { int32_t x1, y1, x2, y2, dist; uint32_t flags; } pgm_match_t;
+
+/* Sizes for an image size and parameter set. */
+typedef struct {
+    int32_t levels;
+    int32_t level_w[PGM_MAX_LEVELS], level_h[PGM_MAX_LEVELS];   /* image size per level     */
+    int32_t level_nx[PGM_MAX_LEVELS], level_ny[PGM_MAX_LEVELS]; /* seed grid per level      */
+    int32_t nx, ny;                  /* level-0 grid: pgm_match writes nx*ny matches          */
+    uint64_t workspace_bytes;        /* device workspace pgm_match needs for one pair         */
+} pgm_sizes;
+
+/* Presets. */
+enum {
+    PGM_PRESET_PAPER = 0,    /* Sec. IV parameters on a dense field (stride 1, P 15 / 11)    */
+    PGM_PRESET_CONFIG1 = 1,  /* 256x192 pairs: L=3, stride 3, 8x8, 4 iterations, |d|<=20    */
+    PGM_PRESET_CONFIG2 = 2,  /* 1024x436 pairs: L=5, stride 3, 8x8, 6 iterations, |d|<=200  */
+    PGM_PRESET_CONFIG3 = 3   /* 1242x375 pairs, direction-only float features, |d|<=250     */
+};
+
+/* Fill *p with a preset. Host only. PGM_EINVAL for an unknown preset or p == NULL. */
+PGM_API pgm_status pgm_default_params(pgm_params* p, int32_t preset);
+
+/* Validate parameters for a w x h pair and report the grid and workspace sizes (Sec. III-D:
+ * level l is ceil(w / 2^l) x ceil(h / 2^l)). Host only, no device work. */
+PGM_API pgm_status pgm_query(const pgm_params* p, int32_t w, int32_t h, pgm_sizes* out);
+
+/* Create a context on HIP device `device` with a device workspace of `workspace_bytes`
+ * (0 picks 256 MiB). The context owns the workspace until pgm_destroy. */
+PGM_API pgm_status pgm_create(int32_t device, uint64_t workspace_bytes, void** out_ctx);
+
+/* Match one pair (the whole method of Sec. III on the GPU).
+ *  img1, img2      device, HWC RGB uint8, w x h, rows pitch_bytes apart (may alias).
+ *  out_fwd         device, nx*ny pgm_match_t, forward matches (image 1 -> image 2).
+ *  out_bwd         device or NULL, nx*ny backward matches (image 2 -> image 1).
+ *  out_n_inliers   device or NULL, one int32: the number of forward inliers.
+ *  out_compact     device or NULL, nx*ny pgm_match_t: forward inliers in row-major seed
+ *                  order, the first *out_n_inliers entries valid (Sec. III-G hands these to
+ *                  the interpolator).
+ *  out_n_evals     device or NULL, one uint64: patch-distance evaluations are ADDED to it.
+ *  stream          hipStream_t or NULL.
+ * The context's workspace keeps every level's state until the next call (pgm_dump_*). */
+PGM_API pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const uint8_t* img2,
+                     int32_t w, int32_t h, int32_t pitch_bytes, pgm_match_t* out_fwd,
+                     pgm_match_t* out_bwd, int32_t* out_n_inliers, pgm_match_t* out_compact,
+                     uint64_t* out_n_evals, void* stream);
+
+/* Debug copies of the last pgm_match's intermediate state into host memory; each waits for
+ * the last call's stream to finish.
+ *  pgm_dump_level:    level_nx*level_ny records of 4 int32 {dx, dy, dist, flags} of field
+ *                     `dir` (0 forward, 1 backward) after the level's last update.
+ *  pgm_dump_gradient: level_w*level_h*2C values of image `image` (0 or 1) at `level`, int16
+ *                     (PGM_FEAT_INT16) or float, channel order [Gx_0..Gx_C-1, Gy_0..Gy_C-1].
+ *  pgm_dump_pyramid:  level_w*level_h*3 uint8 of image `image` at `level`. */
+PGM_API pgm_status pgm_dump_level(void* ctx, int32_t level, int32_t dir, int32_t* host_out);
+PGM_API pgm_status pgm_dump_gradient(void* ctx, int32_t level, int32_t image, void* host_out);
+PGM_API pgm_status pgm_dump_pyramid(void* ctx, int32_t level, int32_t image, uint8_t* host_out);
+
+/* Per-kernel timing for measurement. While enabled, pgm_match records HIP events around
+ * every kernel launch on the caller's stream and counts the distance evaluations of each
+ * kernel kind. pgm_profile(ctx, 1) enables and clears the totals, pgm_profile(ctx, 0)
+ * disables. pgm_profile_read waits for the last call's stream and returns, for one kind,
+ * the number of launches, their summed duration in milliseconds and their summed distance
+ * evaluations since the last clear. Kinds: */
+enum { PGM_K_PYRAMID = 0, PGM_K_GRADIENT = 1, PGM_K_RNG = 2, PGM_K_INIT = 3, PGM_K_DOWN = 4,
+       PGM_K_UP = 5, PGM_K_SWEEP = 6, PGM_K_CHECK = 7, PGM_K_OUTPUT = 8, PGM_K_COMPACT = 9,
+       PGM_K_KINDS = 10 };
+PGM_API pgm_status pgm_profile(void* ctx, int32_t enable);
+PGM_API pgm_status pgm_profile_read(void* ctx, int32_t kind, int64_t* host_launches,
+                                    double* host_total_ms, uint64_t* host_evals);
+
+/* Text of the last error of ctx (or of the last failed pgm_create when ctx is NULL). */
+PGM_API const char* pgm_last_error(void* ctx);
+
+/* Free the workspace and the context. Waits for the context's work to finish. */
+PGM_API void pgm_destroy(void* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PGM_H */

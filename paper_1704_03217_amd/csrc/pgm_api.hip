@@ -1,0 +1,596 @@
+// C ABI of libpgm (declared in include/pgm.h): parameter validation, workspace layout, the
+// level schedule of Sec. III-D and the kernel launches of one pair.
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "pgm_internal.h"
+
+using namespace pgm;
+
+namespace {
+
+struct Layout {
+    int L = 0, ch = 3, C2 = 6, esize = 2, f32 = 0;
+    int lw[PGM_MAX_LEVELS], lh[PGM_MAX_LEVELS], lnx[PGM_MAX_LEVELS], lny[PGM_MAX_LEVELS];
+    size_t pyr[2][PGM_MAX_LEVELS];                       // level >= 1 RGB images
+    size_t grad[2][PGM_MAX_LEVELS];                      // padded gradient images
+    size_t disp[2][PGM_MAX_LEVELS], dist[2][PGM_MAX_LEVELS], flags[2][PGM_MAX_LEVELS];
+    size_t rnd = 0, rnd_init = 0;
+    // stages of the schedule
+    int nst = 0;
+    int st_level[MAX_STAGES], st_enter[MAX_STAGES], st_W[MAX_STAGES], st_nI[MAX_STAGES];
+    long long st_base[MAX_STAGES];                       // short2 offset of the stage's offsets
+    long long rnd_items = 0;                             // Philox calls for the search offsets
+    int R_top = 0;
+    size_t total = 0;
+};
+
+enum { ENTER_INIT = 0, ENTER_DOWN_F = 1, ENTER_DOWN_FO = 2, ENTER_UP_FO = 3 };
+
+size_t take(size_t& cur, size_t bytes)
+{
+    size_t at = (cur + 255) & ~(size_t)255;
+    cur = at + bytes;
+    return at;
+}
+
+int grid_count(int n, int stride)
+{
+    int off = stride / 2;
+    return n - 1 < off ? 1 : (n - 1 - off) / stride + 1;
+}
+
+int n_offsets(int W)   // floor(log2 W) + 1 candidates of Eq. 5
+{
+    int n = 1;
+    while ((2 << (n - 1)) <= W) n++;
+    return n;
+}
+
+const char* validate(const pgm_params* p, int w, int h)
+{
+    if (!p) return "null parameters";
+    if (w < 1 || h < 1 || w > 16384 || h > 16384) return "image size must be within 1..16384";
+    if (p->levels < 1 || p->levels > PGM_MAX_LEVELS) return "levels must be within 1..8";
+    if (p->seed_stride < 1 || p->seed_stride > 64) return "seed_stride must be within 1..64";
+    if (p->patch_fwd < 1 || p->patch_fwd > 16 || p->patch_bwd < 1 || p->patch_bwd > 16)
+        return "patch sides must be within 1..16";
+    for (int l = 0; l < p->levels; l++)
+        if (p->iters[l] < 0 || p->iters[l] > 255) return "iterations must be within 0..255";
+    if (p->radius < 1 || p->radius > 16384) return "radius must be within 1..16384";
+    if (p->max_disp < 0 || p->max_disp > 65535) return "max_disp must be within 0..65535";
+    if (p->sobel_ksize != 3 && p->sobel_ksize != 5) return "sobel_ksize must be 3 or 5";
+    if (p->feature != PGM_FEAT_INT16 && p->feature != PGM_FEAT_F32_DIR) return "unknown feature";
+    if (p->color != PGM_RGB && p->color != PGM_GRAY) return "unknown color";
+    if (p->fwd_bwd != 0 && p->fwd_bwd != 1) return "fwd_bwd must be 0 or 1";
+    if (p->consistency_px < 0 || p->consistency_px > 46340) return "consistency_px must be within 0..46340";
+    if (p->init_mode != PGM_INIT_RANDOM && p->init_mode != PGM_INIT_EXHAUSTIVE) return "unknown init_mode";
+    if (p->refine_rounds < 0 || p->refine_rounds > 16) return "refine_rounds must be within 0..16";
+    if (p->refine_rounds > 0 && p->levels < 2) return "refinement needs at least two levels";
+    return nullptr;
+}
+
+void plan(const pgm_params* p, int w, int h, Layout& Y)
+{
+    Y = Layout();
+    Y.L = p->levels;
+    Y.ch = p->color == PGM_GRAY ? 1 : 3;
+    Y.C2 = 2 * Y.ch;
+    Y.f32 = p->feature == PGM_FEAT_F32_DIR;
+    Y.esize = Y.f32 ? 4 : 2;
+    int cw = w, chh = h;
+    for (int l = 0; l < Y.L; l++) {
+        Y.lw[l] = cw; Y.lh[l] = chh;
+        Y.lnx[l] = grid_count(cw, p->seed_stride);
+        Y.lny[l] = grid_count(chh, p->seed_stride);
+        cw = (cw + 1) / 2; chh = (chh + 1) / 2;
+    }
+    const int m = Y.L - 1;
+    if (p->max_disp <= 0) Y.R_top = Y.lw[m] > Y.lh[m] ? Y.lw[m] : Y.lh[m];
+    else Y.R_top = (p->max_disp + (1 << m) - 1) >> m;
+
+    // Sec. III-D: initial field at m, N refinement round trips between m and m-1 carrying
+    // field and record, the field alone from m to m-1, then field and record to level 0.
+    auto add = [&](int level, int enter) { Y.st_level[Y.nst] = level; Y.st_enter[Y.nst] = enter; Y.nst++; };
+    add(m, ENTER_INIT);
+    for (int k = 0; k < p->refine_rounds; k++) { add(m - 1, ENTER_DOWN_FO); add(m, ENTER_UP_FO); }
+    for (int l = m - 1; l >= 0; l--) add(l, l == m - 1 ? ENTER_DOWN_F : ENTER_DOWN_FO);
+
+    size_t cur = 0;
+    for (int im = 0; im < 2; im++)
+        for (int l = 0; l < Y.L; l++) {
+            Y.pyr[im][l] = l ? take(cur, (size_t)Y.lw[l] * Y.lh[l] * 3) : 0;
+            Y.grad[im][l] = take(cur, (size_t)(Y.lw[l] + 2 * PAD) * (Y.lh[l] + 2 * PAD) * Y.C2 * Y.esize);
+        }
+    for (int d = 0; d < 2; d++)
+        for (int l = 0; l < Y.L; l++) {
+            size_t n = (size_t)Y.lnx[l] * Y.lny[l];
+            Y.disp[d][l] = take(cur, n * 4);
+            Y.dist[d][l] = take(cur, n * 4);
+            Y.flags[d][l] = take(cur, n);
+        }
+    long long base = 0;
+    for (int k = 0; k < Y.nst; k++) {
+        const int l = Y.st_level[k];
+        const bool rand_init = Y.st_enter[k] == ENTER_INIT && p->init_mode == PGM_INIT_RANDOM;
+        Y.st_W[k] = rand_init ? (Y.R_top > 0 ? Y.R_top : 1) : p->radius;
+        Y.st_nI[k] = n_offsets(Y.st_W[k]);
+        Y.st_base[k] = base;
+        const long long n = (long long)Y.lnx[l] * Y.lny[l];
+        base += 2LL * p->iters[l] * n * Y.st_nI[k];
+        Y.rnd_items += 2LL * n * p->iters[l] * ((Y.st_nI[k] + 1) / 2);
+    }
+    Y.rnd = take(cur, (size_t)base * sizeof(short2) + 4);
+    Y.rnd_init = take(cur, (size_t)2 * Y.lnx[m] * Y.lny[m] * sizeof(short2));
+    Y.total = (cur + 255) & ~(size_t)255;
+}
+
+void fill_sizes(const Layout& Y, pgm_sizes* s)
+{
+    memset(s, 0, sizeof *s);
+    s->levels = Y.L;
+    for (int l = 0; l < Y.L; l++) {
+        s->level_w[l] = Y.lw[l]; s->level_h[l] = Y.lh[l];
+        s->level_nx[l] = Y.lnx[l]; s->level_ny[l] = Y.lny[l];
+    }
+    s->nx = Y.lnx[0]; s->ny = Y.lny[0];
+    s->workspace_bytes = Y.total;
+}
+
+}  // namespace
+
+struct pgm_ctx_s {
+    int device = 0;
+    uint8_t* ws = nullptr;
+    size_t ws_bytes = 0;
+    std::string err;
+    // the last pgm_match, for the dump entry points
+    bool have_last = false;
+    Layout last;
+    pgm_params last_p;
+    hipStream_t last_stream = nullptr;
+    const uint8_t* last_img[2] = {nullptr, nullptr};
+    int last_pitch = 0;
+    int rec_valid[PGM_MAX_LEVELS];
+    // profiling (pgm_profile): events around launches and per-kind evaluation counters
+    bool prof = false;
+    unsigned long long* prof_evals = nullptr;     // PGM_K_KINDS device counters
+    std::vector<hipEvent_t> events;               // pool, reused after each clear
+    size_t next_event = 0;
+    struct Rec { int kind; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+};
+
+static std::string g_create_error;
+
+static pgm_status fail(pgm_ctx_s* c, pgm_status st, const std::string& msg)
+{
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+#define PGM_HIP(ctx, expr)                                                                      \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((ctx), PGM_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_));    \
+    } while (0)
+
+extern "C" {
+
+pgm_status pgm_default_params(pgm_params* p, int32_t preset)
+{
+    if (!p) return PGM_EINVAL;
+    memset(p, 0, sizeof *p);
+    p->levels = 3;
+    p->seed_stride = 3;
+    p->patch_fwd = p->patch_bwd = 8;
+    for (int l = 0; l < PGM_MAX_LEVELS; l++) p->iters[l] = 4;
+    p->radius = 2;
+    p->max_disp = 20;
+    p->sobel_ksize = 5;
+    p->feature = PGM_FEAT_INT16;
+    p->color = PGM_RGB;
+    p->fwd_bwd = 1;
+    p->consistency_px = 1;
+    p->init_mode = PGM_INIT_RANDOM;
+    p->refine_rounds = 0;
+    switch (preset) {
+    case PGM_PRESET_PAPER:   // Sec. IV: W=2, S=5, L=3, N=2, 6 / 4 iterations; r = 7 / 5
+        p->seed_stride = 1;
+        p->patch_fwd = 15;
+        p->patch_bwd = 11;
+        p->iters[0] = 6;
+        p->max_disp = 0;
+        p->refine_rounds = 2;
+        p->rng_seed = 0;
+        return PGM_OK;
+    case PGM_PRESET_CONFIG1:
+        p->rng_seed = 1000;
+        return PGM_OK;
+    case PGM_PRESET_CONFIG2:
+    case PGM_PRESET_CONFIG3:
+        p->levels = 5;
+        for (int l = 0; l < PGM_MAX_LEVELS; l++) p->iters[l] = 6;
+        p->max_disp = preset == PGM_PRESET_CONFIG2 ? 200 : 250;
+        p->feature = preset == PGM_PRESET_CONFIG2 ? PGM_FEAT_INT16 : PGM_FEAT_F32_DIR;
+        p->rng_seed = preset == PGM_PRESET_CONFIG2 ? 2000 : 3000;
+        return PGM_OK;
+    default:
+        return PGM_EINVAL;
+    }
+}
+
+pgm_status pgm_query(const pgm_params* p, int32_t w, int32_t h, pgm_sizes* out)
+{
+    if (!out) return PGM_EINVAL;
+    if (validate(p, w, h)) return PGM_EINVAL;
+    Layout Y;
+    plan(p, w, h, Y);
+    fill_sizes(Y, out);
+    return PGM_OK;
+}
+
+pgm_status pgm_create(int32_t device, uint64_t workspace_bytes, void** out_ctx)
+{
+    if (!out_ctx) return fail(nullptr, PGM_EINVAL, "out_ctx is null");
+    *out_ctx = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return fail(nullptr, PGM_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= n) return fail(nullptr, PGM_EINVAL, "device index out of range");
+    pgm_ctx_s* c = new pgm_ctx_s();
+    c->device = device;
+    c->ws_bytes = workspace_bytes ? workspace_bytes : (256ull << 20);
+    e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->ws, c->ws_bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->prof_evals, PGM_K_KINDS * sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        if (c->ws) (void)hipFree(c->ws);
+        std::string msg = std::string("workspace allocation failed: ") + hipGetErrorString(e);
+        delete c;
+        return fail(nullptr, e == hipErrorOutOfMemory ? PGM_ENOMEM : PGM_EDEVICE, msg);
+    }
+    *out_ctx = c;
+    return PGM_OK;
+}
+
+void pgm_destroy(void* ctx)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->prof_evals) (void)hipFree(c->prof_evals);
+    for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
+    delete c;
+}
+
+const char* pgm_last_error(void* ctx)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const uint8_t* img2,
+                     int32_t w, int32_t h, int32_t pitch_bytes, pgm_match_t* out_fwd,
+                     pgm_match_t* out_bwd, int32_t* out_n_inliers, pgm_match_t* out_compact,
+                     uint64_t* out_n_evals, void* stream)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    if (!c) return PGM_EINVAL;
+    if (const char* why = validate(p, w, h)) return fail(c, PGM_EINVAL, why);
+    if (!img1 || !img2 || !out_fwd) return fail(c, PGM_EINVAL, "img1, img2 and out_fwd must not be null");
+    if (pitch_bytes < 3 * w) return fail(c, PGM_EINVAL, "pitch_bytes must be at least 3 * w");
+    Layout Y;
+    plan(p, w, h, Y);
+    if (Y.total > c->ws_bytes)
+        return fail(c, PGM_ENOMEM, "workspace of " + std::to_string(c->ws_bytes) + " bytes is smaller than the " +
+                                       std::to_string(Y.total) + " bytes this pair needs");
+    hipStream_t s = (hipStream_t)stream;
+    PGM_HIP(c, hipSetDevice(c->device));
+    uint8_t* ws = c->ws;
+    unsigned long long* nev = (unsigned long long*)out_n_evals;
+    // with profiling on, every launch is bracketed by two events on the caller's stream
+    auto event = [&](hipEvent_t* ev) -> hipError_t {
+        if (c->next_event == c->events.size()) {
+            hipEvent_t e;
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return err;
+            c->events.push_back(e);
+        }
+        *ev = c->events[c->next_event++];
+        return hipSuccess;
+    };
+    auto timed = [&](int kind, auto&& launch) -> hipError_t {
+        if (!c->prof) return launch();
+        pgm_ctx_s::Rec r;
+        r.kind = kind;
+        hipError_t e = event(&r.a);
+        if (e == hipSuccess) e = event(&r.b);
+        if (e == hipSuccess) e = hipEventRecord(r.a, s);
+        if (e == hipSuccess) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(r.b, s);
+        if (e == hipSuccess) c->recs.push_back(r);
+        return e;
+    };
+    auto kcount = [&](int kind) { return c->prof ? c->prof_evals + kind : (unsigned long long*)nullptr; };
+
+    // image pyramids and gradient pyramids of both images (Sec. III-D, III-A)
+    const uint8_t* lvl[2] = {img1, img2};
+    int pitch = pitch_bytes;
+    for (int l = 0; l < Y.L; l++) {
+        if (l > 0) {
+            uint8_t* d0 = ws + Y.pyr[0][l];
+            uint8_t* d1 = ws + Y.pyr[1][l];
+            PGM_HIP(c, timed(PGM_K_PYRAMID, [&] { return launch_pyr_down(lvl[0], lvl[1], pitch, Y.lw[l - 1], Y.lh[l - 1], d0, d1, s); }));
+            lvl[0] = d0; lvl[1] = d1;
+            pitch = Y.lw[l] * 3;
+        }
+        PGM_HIP(c, timed(PGM_K_GRADIENT, [&] {
+                       return launch_gradient(lvl[0], lvl[1], pitch, Y.lw[l], Y.lh[l], ws + Y.grad[0][l],
+                                              ws + Y.grad[1][l], p->color == PGM_GRAY, p->sobel_ksize, Y.f32, s);
+                   }));
+    }
+
+    // every random number of the pair
+    RngArgs ra;
+    memset(&ra, 0, sizeof ra);
+    ra.nstages = Y.nst;
+    for (int k = 0; k < Y.nst; k++) {
+        const int l = Y.st_level[k];
+        ra.st[k].n = Y.lnx[l] * Y.lny[l];
+        ra.st[k].iters = p->iters[l];
+        ra.st[k].nI = Y.st_nI[k];
+        ra.st[k].W = Y.st_W[k];
+        ra.st[k].level = l;
+        ra.st[k].stage = k;
+        ra.st[k].base = Y.st_base[k];
+    }
+    ra.total_items = Y.rnd_items;
+    ra.table = (short2*)(ws + Y.rnd);
+    ra.init = (short2*)(ws + Y.rnd_init);
+    const int m = Y.L - 1;
+    ra.n_top = p->init_mode == PGM_INIT_RANDOM ? Y.lnx[m] * Y.lny[m] : 0;
+    ra.R_top = Y.R_top;
+    ra.top_level = m;
+    ra.key0 = (uint32_t)p->rng_seed;
+    ra.key1 = (uint32_t)(p->rng_seed >> 32);
+    PGM_HIP(c, timed(PGM_K_RNG, [&] { return launch_rng(ra, s); }));
+
+    auto geo = [&](int l) {
+        Geo g;
+        g.w = Y.lw[l]; g.h = Y.lh[l]; g.pw = Y.lw[l] + 2 * PAD;
+        g.nx = Y.lnx[l]; g.ny = Y.lny[l];
+        g.stride = p->seed_stride; g.off = p->seed_stride / 2;
+        return g;
+    };
+    auto field = [&](int d, int l) {
+        Field f;
+        f.disp = (uint32_t*)(ws + Y.disp[d][l]);
+        f.dist = (uint32_t*)(ws + Y.dist[d][l]);
+        f.flags = ws + Y.flags[d][l];
+        return f;
+    };
+    auto gorigin = [&](int im, int l) {
+        return (const void*)(ws + Y.grad[im][l] + ((size_t)PAD * (Y.lw[l] + 2 * PAD) + PAD) * Y.C2 * Y.esize);
+    };
+    auto dirargs = [&](int d, int l, int k) {
+        DirArgs a;
+        a.Ga = gorigin(d, l);
+        a.Gb = gorigin(1 - d, l);
+        a.f = field(d, l);
+        a.rnd = (const short2*)(ws + Y.rnd) + Y.st_base[k] + (long long)d * p->iters[l] * Y.lnx[l] * Y.lny[l] * Y.st_nI[k];
+        a.rnd0 = (const short2*)(ws + Y.rnd_init) + (size_t)d * Y.lnx[m] * Y.lny[m];
+        a.P = d == 0 ? p->patch_fwd : p->patch_bwd;
+        return a;
+    };
+    // both directions share a launch when their patch sides select the same kernel variant
+    auto variant = [](int P) { return P == 8 ? 0 : P < 8 ? 1 : P == 16 ? 2 : 3; };
+    const bool shared = variant(p->patch_fwd) == variant(p->patch_bwd);
+
+    int rec_valid[PGM_MAX_LEVELS] = {0};
+    for (int k = 0; k < Y.nst; k++) {
+        const int l = Y.st_level[k];
+        const Geo g = geo(l);
+        const int enter = Y.st_enter[k];
+        for (int pass = 0; pass < (shared ? 1 : 2); pass++) {
+            const int nd = shared ? 2 : 1;
+            const int d0 = shared ? 0 : pass;
+            if (enter == ENTER_INIT) {
+                InitArgs a;
+                memset(&a, 0, sizeof a);
+                for (int q = 0; q < nd; q++) a.d[q] = dirargs(d0 + q, l, k);
+                a.g = g;
+                a.exhaustive = p->init_mode == PGM_INIT_EXHAUSTIVE;
+                a.R = Y.R_top;
+                a.n_evals = nev;
+                a.n_evals2 = kcount(PGM_K_INIT);
+                PGM_HIP(c, timed(PGM_K_INIT, [&] { return launch_init(a, Y.C2, Y.f32, nd, s); }));
+            } else {
+                TransArgs a;
+                memset(&a, 0, sizeof a);
+                const int src = enter == ENTER_UP_FO ? l - 1 : l + 1;
+                for (int q = 0; q < nd; q++) {
+                    a.d[q] = dirargs(d0 + q, l, k);
+                    a.src[q] = field(d0 + q, src);
+                }
+                a.g = g;
+                a.gs = geo(src);
+                a.carry_record = enter != ENTER_DOWN_F;
+                a.n_evals = nev;
+                if (enter == ENTER_UP_FO) {
+                    a.n_evals2 = kcount(PGM_K_UP);
+                    PGM_HIP(c, timed(PGM_K_UP, [&] { return launch_up(a, Y.C2, Y.f32, nd, s); }));
+                } else {
+                    a.n_evals2 = kcount(PGM_K_DOWN);
+                    PGM_HIP(c, timed(PGM_K_DOWN, [&] { return launch_down(a, Y.C2, Y.f32, nd, s); }));
+                }
+            }
+        }
+        // Step 1: iterations of propagation and limited random search, red then black
+        for (int t = 0; t < p->iters[l]; t++)
+            for (int colour = 0; colour < 2; colour++)
+                for (int pass = 0; pass < (shared ? 1 : 2); pass++) {
+                    const int nd = shared ? 2 : 1;
+                    const int d0 = shared ? 0 : pass;
+                    SweepArgs a;
+                    memset(&a, 0, sizeof a);
+                    for (int q = 0; q < nd; q++) a.d[q] = dirargs(d0 + q, l, k);
+                    a.g = g;
+                    a.t = t;
+                    a.colour = colour;
+                    a.nI = Y.st_nI[k];
+                    a.n_evals = nev;
+                    a.n_evals2 = kcount(PGM_K_SWEEP);
+                    PGM_HIP(c, timed(PGM_K_SWEEP, [&] { return launch_sweep(a, Y.C2, Y.f32, nd, s); }));
+                }
+        // Step 2-3
+        CheckArgs ca;
+        ca.f[0] = field(0, l);
+        ca.f[1] = field(1, l);
+        ca.g = g;
+        ca.fwd_bwd = p->fwd_bwd;
+        ca.tau2 = p->consistency_px * p->consistency_px;
+        ca.rec_valid = enter == ENTER_DOWN_FO || enter == ENTER_UP_FO;
+        rec_valid[l] = ca.rec_valid;
+        PGM_HIP(c, timed(PGM_K_CHECK, [&] { return launch_check(ca, s); }));
+    }
+
+    // level-0 matches on the grid (Sec. III-G)
+    const Geo g0 = geo(0);
+    PGM_HIP(c, timed(PGM_K_OUTPUT, [&] { return launch_output(field(0, 0), g0, out_fwd, s); }));
+    if (out_bwd) PGM_HIP(c, timed(PGM_K_OUTPUT, [&] { return launch_output(field(1, 0), g0, out_bwd, s); }));
+    if (out_compact || out_n_inliers)
+        PGM_HIP(c, timed(PGM_K_COMPACT, [&] {
+                       return launch_compact(out_fwd, g0.nx * g0.ny, out_compact, out_n_inliers, s);
+                   }));
+
+    c->have_last = true;
+    c->last = Y;
+    c->last_p = *p;
+    c->last_stream = s;
+    c->last_img[0] = img1;
+    c->last_img[1] = img2;
+    c->last_pitch = pitch_bytes;
+    memcpy(c->rec_valid, rec_valid, sizeof rec_valid);
+    return PGM_OK;
+}
+
+static pgm_status dump_prep(pgm_ctx_s* c, int level)
+{
+    if (!c) return PGM_EINVAL;
+    if (!c->have_last) return fail(c, PGM_EINVAL, "no pgm_match has run on this context");
+    if (level < 0 || level >= c->last.L) return fail(c, PGM_EINVAL, "level out of range");
+    PGM_HIP(c, hipSetDevice(c->device));
+    PGM_HIP(c, hipStreamSynchronize(c->last_stream));
+    return PGM_OK;
+}
+
+pgm_status pgm_dump_level(void* ctx, int32_t level, int32_t dir, int32_t* host_out)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    pgm_status st = dump_prep(c, level);
+    if (st != PGM_OK) return st;
+    if ((dir != 0 && dir != 1) || !host_out) return fail(c, PGM_EINVAL, "bad dir or null output");
+    const Layout& Y = c->last;
+    const size_t n = (size_t)Y.lnx[level] * Y.lny[level];
+    std::string buf(n * 9, '\0');
+    uint32_t* disp = (uint32_t*)&buf[0];
+    uint32_t* dist = disp + n;
+    uint8_t* flags = (uint8_t*)(dist + n);
+    PGM_HIP(c, hipMemcpy(disp, c->ws + Y.disp[dir][level], n * 4, hipMemcpyDeviceToHost));
+    PGM_HIP(c, hipMemcpy(dist, c->ws + Y.dist[dir][level], n * 4, hipMemcpyDeviceToHost));
+    PGM_HIP(c, hipMemcpy(flags, c->ws + Y.flags[dir][level], n, hipMemcpyDeviceToHost));
+    for (size_t s = 0; s < n; s++) {
+        const bool init = disp[s] != UNINIT;
+        host_out[4 * s + 0] = init ? (int32_t)(int16_t)(disp[s] & 0xFFFF) : 0;
+        host_out[4 * s + 1] = init ? (int32_t)(int16_t)(disp[s] >> 16) : 0;
+        host_out[4 * s + 2] = init ? (int32_t)dist[s] : (int32_t)NO_DIST;
+        host_out[4 * s + 3] = (int32_t)((init ? PGM_FLAG_INIT : 0u) | ((flags[s] & ST_INL) ? PGM_FLAG_INLIER : 0u) |
+                                        ((flags[s] & ST_REC) ? PGM_FLAG_RECORD : 0u));
+    }
+    return PGM_OK;
+}
+
+pgm_status pgm_dump_gradient(void* ctx, int32_t level, int32_t image, void* host_out)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    pgm_status st = dump_prep(c, level);
+    if (st != PGM_OK) return st;
+    if ((image != 0 && image != 1) || !host_out) return fail(c, PGM_EINVAL, "bad image or null output");
+    const Layout& Y = c->last;
+    const int w = Y.lw[level], h = Y.lh[level], pw = w + 2 * PAD;
+    const size_t row = (size_t)w * Y.C2 * Y.esize;
+    for (int y = 0; y < h; y++) {
+        const uint8_t* src = c->ws + Y.grad[image][level] + (((size_t)(y + PAD) * pw + PAD) * Y.C2) * Y.esize;
+        PGM_HIP(c, hipMemcpy((uint8_t*)host_out + y * row, src, row, hipMemcpyDeviceToHost));
+    }
+    if (!Y.f32) {
+        uint16_t* v = (uint16_t*)host_out;
+        for (size_t k = 0; k < (size_t)w * h * Y.C2; k++) v[k] = (uint16_t)((int)v[k] - (int)BIAS);
+    }
+    return PGM_OK;
+}
+
+pgm_status pgm_dump_pyramid(void* ctx, int32_t level, int32_t image, uint8_t* host_out)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    pgm_status st = dump_prep(c, level);
+    if (st != PGM_OK) return st;
+    if ((image != 0 && image != 1) || !host_out) return fail(c, PGM_EINVAL, "bad image or null output");
+    const Layout& Y = c->last;
+    const int w = Y.lw[level], h = Y.lh[level];
+    if (level == 0) {
+        PGM_HIP(c, hipMemcpy2D(host_out, (size_t)w * 3, c->last_img[image], c->last_pitch, (size_t)w * 3, h,
+                               hipMemcpyDeviceToHost));
+    } else {
+        PGM_HIP(c, hipMemcpy(host_out, c->ws + Y.pyr[image][level], (size_t)w * h * 3, hipMemcpyDeviceToHost));
+    }
+    return PGM_OK;
+}
+
+pgm_status pgm_profile(void* ctx, int32_t enable)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    if (!c || (enable != 0 && enable != 1)) return PGM_EINVAL;
+    PGM_HIP(c, hipSetDevice(c->device));
+    if (enable) {
+        PGM_HIP(c, hipDeviceSynchronize());
+        PGM_HIP(c, hipMemset(c->prof_evals, 0, PGM_K_KINDS * sizeof(unsigned long long)));
+        c->recs.clear();
+        c->next_event = 0;
+    }
+    c->prof = enable != 0;
+    return PGM_OK;
+}
+
+pgm_status pgm_profile_read(void* ctx, int32_t kind, int64_t* host_launches, double* host_total_ms,
+                            uint64_t* host_evals)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    if (!c || kind < 0 || kind >= PGM_K_KINDS) return PGM_EINVAL;
+    PGM_HIP(c, hipSetDevice(c->device));
+    PGM_HIP(c, hipDeviceSynchronize());
+    int64_t n = 0;
+    double ms = 0.0;
+    for (const pgm_ctx_s::Rec& r : c->recs) {
+        if (r.kind != kind) continue;
+        float t = 0.0f;
+        PGM_HIP(c, hipEventElapsedTime(&t, r.a, r.b));
+        ms += t;
+        n++;
+    }
+    unsigned long long ev[PGM_K_KINDS];
+    PGM_HIP(c, hipMemcpy(ev, c->prof_evals, sizeof ev, hipMemcpyDeviceToHost));
+    if (host_launches) *host_launches = n;
+    if (host_total_ms) *host_total_ms = ms;
+    if (host_evals) *host_evals = ev[kind];
+    return PGM_OK;
+}
+
+}  // extern "C"

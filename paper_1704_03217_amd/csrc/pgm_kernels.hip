@@ -1,0 +1,765 @@
+// HIP kernels of libpgm for gfx950 (CDNA4): pyramidal gradient matching
+// (Y. Li, "Pyramidal Gradient Matching for Optical Flow Estimation", arXiv:1704.03217).
+//
+// Matching kernels assign one group of LPS lanes (8 for patches up to 8 pixels, 16 up to 16)
+// to each seed of the grid: lane r holds row r of the seed's patch of the first gradient
+// image in registers for the whole launch, reads row r of a candidate patch of the second
+// image, and the patch distance is the DPP sum over the group. Candidates of one seed are
+// evaluated one after another in the order of the paper's candidate sets, so every seed's
+// decision sequence is exactly the sequential one; seeds of one colour of the red-black
+// checkerboard are independent and run in parallel.
+#include "pgm_internal.h"
+
+namespace pgm {
+
+// ---------------------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------------------
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ __forceinline__ uint32_t pack_d(int dx, int dy)
+{
+    return (uint32_t)(uint16_t)(int16_t)dx | ((uint32_t)(uint16_t)(int16_t)dy << 16);
+}
+__device__ __forceinline__ int d_x(uint32_t v) { return (int)(int16_t)(uint16_t)(v & 0xFFFFu); }
+__device__ __forceinline__ int d_y(uint32_t v) { return (int)(int16_t)(uint16_t)(v >> 16); }
+
+// clamp the target p + d into the image and return the clamped displacement
+__device__ __forceinline__ uint32_t target(int px, int py, int dx, int dy, const Geo& g)
+{
+    return pack_d(clampi(px + dx, 0, g.w - 1) - px, clampi(py + dy, 0, g.h - 1) - py);
+}
+
+__device__ __forceinline__ int grid_pos(int i, int n, const Geo& g)
+{
+    int p = g.off + i * g.stride;
+    return p < n - 1 ? p : n - 1;
+}
+
+// index of the grid seed nearest to pixel x >= 0 (ties go to the larger index)
+__device__ __forceinline__ int grid_near(int x, int nseeds, const Geo& g)
+{
+    unsigned num = (unsigned)(2 * (x - g.off) + g.stride);   // >= 0 because off <= stride/2
+    int i = (int)(num / (unsigned)(2 * g.stride));
+    return i < nseeds - 1 ? i : nseeds - 1;
+}
+
+// reflect-101 index into [0, n)
+__device__ __forceinline__ int mirror(int i, int n)
+{
+    if (n == 1) return 0;
+    int period = 2 * (n - 1);
+    int m = i < 0 ? -i : i;
+    m %= period;
+    return m < n ? m : period - m;
+}
+
+// Philox4x32 with ten rounds (Salmon, Moraes, Dror and Shaw, SC'11).
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        uint32_t lo0 = m0 * c.x, hi0 = __umulhi(m0, c.x);
+        uint32_t lo1 = m1 * c.z, hi1 = __umulhi(m1, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// DPP sums over groups of 8 or 16 consecutive lanes; every lane receives the group total.
+template <int LPS>
+__device__ __forceinline__ uint32_t group_sum(uint32_t v)
+{
+    v += __builtin_amdgcn_update_dpp(0u, v, 0xB1, 0xF, 0xF, false);    // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x4E, 0xF, 0xF, false);    // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x141, 0xF, 0xF, false);   // row_half_mirror
+    if (LPS == 16) v += __builtin_amdgcn_update_dpp(0u, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    return v;
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)b, CTRL, 0xF, 0xF, false);
+    uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int LPS>
+__device__ __forceinline__ double group_sum(double v)
+{
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    if (LPS == 16) v += dpp_f64<0x140>(v);
+    return v;
+}
+
+// ---------------------------------------------------------------------------------------
+// one lane's patch row: the first image's row stays in registers, candidate rows stream in
+// ---------------------------------------------------------------------------------------
+
+// Integer gradients, biased u16, two per dword; C2 channels per pixel (C2 even).
+// v_sad_u16 adds |a.lo16 - b.lo16| + |a.hi16 - b.hi16| (unsigned halves) to its accumulator,
+// so one instruction covers two gradient values of a packed dword.
+template <int C2, int PMAX, bool FIXED>
+struct IntRow {
+    static constexpr int NW = PMAX * C2 / 2;
+    using Elem = uint32_t;
+    using Acc = uint32_t;
+    uint32_t a[NW];
+
+    __device__ __forceinline__ void load(const uint32_t* row, int P)
+    {
+        const int nw = P * (C2 / 2);
+#pragma unroll
+        for (int k = 0; k < NW; k++) a[k] = (FIXED || k < nw) ? row[k] : 0u;
+    }
+    __device__ __forceinline__ uint32_t sad(const uint32_t* row, int P) const
+    {
+        const int nw = P * (C2 / 2);
+        uint32_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < NW; k++)
+            if (FIXED || k < nw) acc = __builtin_amdgcn_sad_u16(a[k], row[k], acc);
+        return acc;
+    }
+    static __device__ __forceinline__ const uint32_t* at(const void* G, const Geo& g, int x, int y)
+    {
+        return (const uint32_t*)G + ((ptrdiff_t)y * g.pw + x) * (C2 / 2);
+    }
+    template <int LPS>
+    static __device__ __forceinline__ uint32_t finish(uint32_t partial) { return group_sum<LPS>(partial); }
+};
+
+// Direction-only float features. The components are unit-vector coordinates (zero or of
+// magnitude >= 2^-14), so every difference and the sum over a patch are exact in double and
+// the rounded float result does not depend on the order of summation.
+template <int C2, int PMAX, bool FIXED>
+struct F32Row {
+    static constexpr int NE = PMAX * C2;
+    using Acc = double;
+    double a[NE];
+
+    __device__ __forceinline__ void load(const float* row, int P)
+    {
+        const int ne = P * C2;
+#pragma unroll
+        for (int k = 0; k < NE; k++) a[k] = (FIXED || k < ne) ? (double)row[k] : 0.0;
+    }
+    __device__ __forceinline__ double sad(const float* row, int P) const
+    {
+        const int ne = P * C2;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < NE; k++)
+            if (FIXED || k < ne) acc += fabs((double)row[k] - a[k]);
+        return acc;
+    }
+    static __device__ __forceinline__ const float* at(const void* G, const Geo& g, int x, int y)
+    {
+        return (const float*)G + ((ptrdiff_t)y * g.pw + x) * C2;
+    }
+    template <int LPS>
+    static __device__ __forceinline__ uint32_t finish(double partial)
+    {
+        return __float_as_uint((float)group_sum<LPS>(partial));
+    }
+};
+
+template <int C2, int PMAX, bool FIXED, bool F32>
+using RowT = typename std::conditional<F32, F32Row<C2, PMAX, FIXED>, IntRow<C2, PMAX, FIXED>>::type;
+
+// Patch distance of Eq. 3 (absolute differences) between the patch held by the group and
+// the patch of the other image at (qx, qy); every lane of the group gets the result.
+template <class Row, int LPS>
+__device__ __forceinline__ uint32_t patch_cost(const Row& A, const void* Gb, const Geo& g, int P,
+                                               int r, int qx, int qy)
+{
+    const int half = P >> 1;
+    const int rr = r < P ? r : P - 1;
+    typename Row::Acc part = A.sad(Row::at(Gb, g, qx - half, qy + rr - half), P);
+    if (r >= P) part = typename Row::Acc(0);
+    return Row::template finish<LPS>(part);
+}
+
+template <class Row>
+__device__ __forceinline__ void load_own(Row& A, const void* Ga, const Geo& g, int P, int r, int px, int py)
+{
+    const int half = P >> 1;
+    const int rr = r < P ? r : P - 1;
+    A.load(Row::at(Ga, g, px - half, py + rr - half), P);
+}
+
+// sum per-group evaluation counts over the wave and add them to the global counters
+__device__ __forceinline__ void count_evals(unsigned long long* n1, unsigned long long* n2, uint32_t nev,
+                                            bool leader)
+{
+    if (!n1 && !n2) return;
+    uint32_t v = leader ? nev : 0u;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) {
+        if (n1) atomicAdd(n1, (unsigned long long)v);
+        if (n2) atomicAdd(n2, (unsigned long long)v);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Step 1 (Sec. III-B): one colour of one propagation + limited random search iteration
+// ---------------------------------------------------------------------------------------
+
+template <int C2, int PMAX, bool FIXED, bool F32>
+__global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
+{
+    using Row = RowT<C2, PMAX, FIXED, F32>;
+    constexpr int LPS = PMAX;
+    constexpr int GPB = 256 / LPS;
+    const Geo& g = a.g;
+    const DirArgs& D = a.d[blockIdx.y];
+    const int r = threadIdx.x % LPS;
+    const int gid = blockIdx.x * GPB + threadIdx.x / LPS;
+    const int hx = (g.nx + 1) >> 1;
+    const int j = gid / hx;
+    const int i = 2 * (gid - j * hx) + ((a.colour + j) & 1);
+    uint32_t nev = 0;
+    if (j < g.ny && i < g.nx) {
+        const int s = j * g.nx + i;
+        const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
+        const int P = D.P;
+        Row A;
+        load_own(A, D.Ga, g, P, r, px, py);
+        uint32_t cur = D.f.disp[s];
+        uint32_t cd = D.f.dist[s];
+        bool init = cur != UNINIT, changed = false;
+
+        // Eq. 4: Omega = {F(p), F(p - Dx) + Dx, F(p - Dy) + Dy} with the FlowFields order
+        // (1,0),(0,1) -> (-1,0),(0,-1) -> (-1,0),(0,1) -> (1,0),(0,-1); members whose
+        // neighbour is uninitialised are ignored.
+        const int k = a.t & 3;
+        const int sx = (k == 0 || k == 3) ? 1 : -1;
+        const int sy = (k == 0 || k == 2) ? 1 : -1;
+#pragma unroll
+        for (int m = 0; m < 2; m++) {
+            const int ni = m == 0 ? i - sx : i;
+            const int nj = m == 0 ? j : j - sy;
+            if (ni < 0 || nj < 0 || ni >= g.nx || nj >= g.ny) continue;
+            const uint32_t nd = D.f.disp[nj * g.nx + ni];
+            if (nd == UNINIT) continue;
+            const uint32_t cand = target(px, py, d_x(nd), d_y(nd), g);
+            if (init && cand == cur) continue;
+            const uint32_t e = patch_cost<Row, LPS>(A, D.Gb, g, P, r, px + d_x(cand), py + d_y(cand));
+            nev++;
+            if (!init || e < cd) { cur = cand; cd = e; init = true; changed = true; }
+        }
+        // Eq. 5: Psi = {F(p)} + {F(p) + floor(R_i W / 2^i)}, around the propagated match
+        if (init) {
+            const short2* R = D.rnd + ((size_t)a.t * (size_t)(g.nx * g.ny) + s) * a.nI;
+            const int cx = d_x(cur), cy = d_y(cur);
+            for (int ii = 0; ii < a.nI; ii++) {
+                const short2 o = R[ii];
+                const uint32_t cand = target(px, py, cx + o.x, cy + o.y, g);
+                if (cand == cur) continue;
+                const uint32_t e = patch_cost<Row, LPS>(A, D.Gb, g, P, r, px + d_x(cand), py + d_y(cand));
+                nev++;
+                if (e < cd) { cur = cand; cd = e; changed = true; }
+            }
+        }
+        if (changed && r == 0) {
+            D.f.disp[s] = cur;
+            D.f.dist[s] = cd;
+        }
+    }
+    count_evals(a.n_evals, a.n_evals2, nev, r == 0);
+}
+
+// ---------------------------------------------------------------------------------------
+// initial field at the coarsest level: random displacement in [-R, R]^2 (drawn by k_rng) or
+// the exact best displacement in that window (dy outer, dx inner, strictly smaller wins)
+// ---------------------------------------------------------------------------------------
+
+template <int C2, int PMAX, bool FIXED, bool F32>
+__global__ __launch_bounds__(256) void k_init(InitArgs a)
+{
+    using Row = RowT<C2, PMAX, FIXED, F32>;
+    constexpr int LPS = PMAX;
+    constexpr int GPB = 256 / LPS;
+    const Geo& g = a.g;
+    const DirArgs& D = a.d[blockIdx.y];
+    const int r = threadIdx.x % LPS;
+    const int s = blockIdx.x * GPB + threadIdx.x / LPS;
+    uint32_t nev = 0;
+    if (s < g.nx * g.ny) {
+        const int i = s % g.nx, j = s / g.nx;
+        const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
+        const int P = D.P;
+        Row A;
+        load_own(A, D.Ga, g, P, r, px, py);
+        uint32_t best = UNINIT, bd = NO_DIST;
+        if (!a.exhaustive) {
+            const short2 o = D.rnd0[s];
+            best = target(px, py, o.x, o.y, g);
+            bd = patch_cost<Row, LPS>(A, D.Gb, g, P, r, px + d_x(best), py + d_y(best));
+            nev++;
+        } else {
+            // the window clipped to the image, in the same (dy outer, dx inner) order
+            const int y0 = max(-a.R, -py), y1 = min(a.R, g.h - 1 - py);
+            const int x0 = max(-a.R, -px), x1 = min(a.R, g.w - 1 - px);
+            for (int dy = y0; dy <= y1; dy++) {
+                for (int dx = x0; dx <= x1; dx++) {
+                    const uint32_t e = patch_cost<Row, LPS>(A, D.Gb, g, P, r, px + dx, py + dy);
+                    nev++;
+                    if (best == UNINIT || e < bd) { best = pack_d(dx, dy); bd = e; }
+                }
+            }
+        }
+        if (r == 0) {
+            D.f.disp[s] = best;
+            D.f.dist[s] = bd;
+            D.f.flags[s] = 0;
+        }
+    }
+    count_evals(a.n_evals, a.n_evals2, nev, r == 0);
+}
+
+// ---------------------------------------------------------------------------------------
+// Step 4-5 toward the finer level (Eq. 6 with eta = s, Eq. 8): the child takes twice the
+// displacement of the nearest parent seed to (x/2, y/2) if that parent is an inlier
+// ---------------------------------------------------------------------------------------
+
+template <int C2, int PMAX, bool FIXED, bool F32>
+__global__ __launch_bounds__(256) void k_down(TransArgs a)
+{
+    using Row = RowT<C2, PMAX, FIXED, F32>;
+    constexpr int LPS = PMAX;
+    constexpr int GPB = 256 / LPS;
+    const Geo& g = a.g;
+    const DirArgs& D = a.d[blockIdx.y];
+    const Field& S = a.src[blockIdx.y];
+    const int r = threadIdx.x % LPS;
+    const int s = blockIdx.x * GPB + threadIdx.x / LPS;
+    uint32_t nev = 0;
+    if (s < g.nx * g.ny) {
+        const int i = s % g.nx, j = s / g.nx;
+        const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
+        const int ps = grid_near(py >> 1, a.gs.ny, a.gs) * a.gs.nx + grid_near(px >> 1, a.gs.nx, a.gs);
+        const bool par_inl = (S.flags[ps] & ST_INL) != 0;
+        uint32_t disp = UNINIT, dist = NO_DIST;
+        if (par_inl) {
+            const uint32_t pd = S.disp[ps];
+            disp = target(px, py, 2 * d_x(pd), 2 * d_y(pd), g);
+            Row A;
+            load_own(A, D.Ga, g, D.P, r, px, py);
+            dist = patch_cost<Row, LPS>(A, D.Gb, g, D.P, r, px + d_x(disp), py + d_y(disp));
+            nev++;
+        }
+        if (r == 0) {
+            D.f.disp[s] = disp;
+            D.f.dist[s] = dist;
+            D.f.flags[s] = (a.carry_record && par_inl) ? ST_REC : 0;
+        }
+    }
+    count_evals(a.n_evals, a.n_evals2, nev, r == 0);
+}
+
+// ---------------------------------------------------------------------------------------
+// Step 4-5 toward the coarser level (Eq. 6 with eta = 1/s, Eq. 8): the mean displacement of
+// the inlier children divided by 2, rounded to nearest with ties away from zero
+// ---------------------------------------------------------------------------------------
+
+__device__ __forceinline__ int div_round(int num, int den)   // den > 0
+{
+    int a = num < 0 ? -num : num;
+    int q = (2 * a + den) / (2 * den);
+    return num < 0 ? -q : q;
+}
+
+template <int C2, int PMAX, bool FIXED, bool F32>
+__global__ __launch_bounds__(256) void k_up(TransArgs a)
+{
+    using Row = RowT<C2, PMAX, FIXED, F32>;
+    constexpr int LPS = PMAX;
+    constexpr int GPB = 256 / LPS;
+    const Geo& g = a.g;     // coarse level being entered
+    const Geo& f = a.gs;    // finer source level
+    const DirArgs& D = a.d[blockIdx.y];
+    const Field& S = a.src[blockIdx.y];
+    const int r = threadIdx.x % LPS;
+    const int s = blockIdx.x * GPB + threadIdx.x / LPS;
+    uint32_t nev = 0;
+    if (s < g.nx * g.ny) {
+        const int ci = s % g.nx, cj = s / g.nx;
+        const int px = grid_pos(ci, g.w, g), py = grid_pos(cj, g.h, g);
+        int sx = 0, sy = 0, cnt = 0;
+        // children: finer seeds whose nearest coarse seed (as in k_down) is this one
+        for (int fj = max(0, 2 * cj - 3); fj <= min(f.ny - 1, 2 * cj + 4); fj++) {
+            const int fy = grid_pos(fj, f.h, f);
+            if (grid_near(fy >> 1, g.ny, g) != cj) continue;
+            for (int fi = max(0, 2 * ci - 3); fi <= min(f.nx - 1, 2 * ci + 4); fi++) {
+                const int fx = grid_pos(fi, f.w, f);
+                if (grid_near(fx >> 1, g.nx, g) != ci) continue;
+                const int fs = fj * f.nx + fi;
+                if (!(S.flags[fs] & ST_INL)) continue;
+                const uint32_t d = S.disp[fs];
+                sx += d_x(d); sy += d_y(d); cnt++;
+            }
+        }
+        uint32_t disp = UNINIT, dist = NO_DIST;
+        if (cnt > 0) {
+            disp = target(px, py, div_round(sx, 2 * cnt), div_round(sy, 2 * cnt), g);
+            Row A;
+            load_own(A, D.Ga, g, D.P, r, px, py);
+            dist = patch_cost<Row, LPS>(A, D.Gb, g, D.P, r, px + d_x(disp), py + d_y(disp));
+            nev++;
+        }
+        if (r == 0) {
+            D.f.disp[s] = disp;
+            D.f.dist[s] = dist;
+            D.f.flags[s] = cnt > 0 ? ST_REC : 0;
+        }
+    }
+    count_evals(a.n_evals, a.n_evals2, nev, r == 0);
+}
+
+// ---------------------------------------------------------------------------------------
+// Step 2-3: forward-backward consistency check and the record update of Eq. 7
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_check(CheckArgs a)
+{
+    const Geo& g = a.g;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.nx * g.ny) return;
+    const Field& F = a.f[blockIdx.y];
+    const Field& O = a.f[1 - blockIdx.y];
+    const uint32_t d = F.disp[s];
+    bool ok = d != UNINIT;
+    if (ok && a.fwd_bwd) {
+        const int i = s % g.nx, j = s / g.nx;
+        const int qx = grid_pos(i, g.w, g) + d_x(d), qy = grid_pos(j, g.h, g) + d_y(d);
+        const uint32_t od = O.disp[grid_near(qy, g.ny, g) * g.nx + grid_near(qx, g.nx, g)];
+        if (od == UNINIT) ok = false;
+        else {
+            const int ex = d_x(d) + d_x(od), ey = d_y(d) + d_y(od);
+            ok = ex * ex + ey * ey <= a.tau2;
+        }
+    }
+    const uint8_t fl = F.flags[s];
+    const bool inl = a.rec_valid ? (ok && (fl & ST_REC)) : ok;
+    F.flags[s] = (uint8_t)((fl & ST_REC) | (inl ? ST_INL : 0));
+}
+
+// ---------------------------------------------------------------------------------------
+// output on the level-0 grid and the compaction of forward inliers (Sec. III-G)
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_output(Field f, Geo g, pgm_match_t* out)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.nx * g.ny) return;
+    const int i = s % g.nx, j = s / g.nx;
+    const uint32_t d = f.disp[s];
+    const uint8_t fl = f.flags[s];
+    pgm_match_t m;
+    m.x1 = grid_pos(i, g.w, g);
+    m.y1 = grid_pos(j, g.h, g);
+    const bool init = d != UNINIT;
+    m.x2 = m.x1 + (init ? d_x(d) : 0);
+    m.y2 = m.y1 + (init ? d_y(d) : 0);
+    m.dist = init ? (int32_t)f.dist[s] : (int32_t)NO_DIST;
+    m.flags = (init ? PGM_FLAG_INIT : 0u) | ((fl & ST_INL) ? PGM_FLAG_INLIER : 0u) |
+              ((fl & ST_REC) ? PGM_FLAG_RECORD : 0u);
+    out[s] = m;
+}
+
+// single work-group stable compaction: each thread owns a contiguous run of seeds
+__global__ __launch_bounds__(1024) void k_compact(const pgm_match_t* dense, int n, pgm_match_t* out,
+                                                 int32_t* n_out)
+{
+    __shared__ int wsum[16];
+    const int tid = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int b = min(n, tid * per), e = min(n, b + per);
+    int c = 0;
+    for (int s = b; s < e; s++) c += (dense[s].flags & PGM_FLAG_INLIER) ? 1 : 0;
+    // inclusive scan within the wave
+    const int lane = tid & 63, wv = tid >> 6;
+    int x = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int before = 0;
+    for (int k = 0; k < wv; k++) before += wsum[k];
+    int pos = before + x - c;
+    if (out)
+        for (int s = b; s < e; s++)
+            if (dense[s].flags & PGM_FLAG_INLIER) out[pos++] = dense[s];
+    if (tid == 1023 && n_out) *n_out = before + x;
+}
+
+// ---------------------------------------------------------------------------------------
+// image pyramid (Sec. III-D): 5x5 binomial, decimation by 2, reflect-101 borders
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_pyr(const uint8_t* src0, const uint8_t* src1, int pitch,
+                                             int w, int h, uint8_t* dst0, uint8_t* dst1)
+{
+    const int w2 = (w + 1) >> 1, h2 = (h + 1) >> 1;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= w2 || y >= h2) return;
+    const uint8_t* src = blockIdx.z ? src1 : src0;
+    uint8_t* dst = blockIdx.z ? dst1 : dst0;
+    const int tap[5] = {1, 4, 6, 4, 1};
+    int acc[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+        const uint8_t* row = src + (size_t)mirror(2 * y + i - 2, h) * pitch;
+        int racc[3] = {0, 0, 0};
+#pragma unroll
+        for (int jj = 0; jj < 5; jj++) {
+            const uint8_t* px = row + 3 * mirror(2 * x + jj - 2, w);
+            racc[0] += tap[jj] * px[0];
+            racc[1] += tap[jj] * px[1];
+            racc[2] += tap[jj] * px[2];
+        }
+        acc[0] += tap[i] * racc[0];
+        acc[1] += tap[i] * racc[1];
+        acc[2] += tap[i] * racc[2];
+    }
+    uint8_t* o = dst + ((size_t)y * w2 + x) * 3;
+    o[0] = (uint8_t)((acc[0] + 128) >> 8);
+    o[1] = (uint8_t)((acc[1] + 128) >> 8);
+    o[2] = (uint8_t)((acc[2] + 128) >> 8);
+}
+
+// ---------------------------------------------------------------------------------------
+// gradient image (Sec. III-A, Eq. 1-2) written with a replicated PAD border
+// ---------------------------------------------------------------------------------------
+
+template <int KS, bool GRAY, bool F32>
+__global__ __launch_bounds__(256) void k_gradient(const uint8_t* img0, const uint8_t* img1, int pitch,
+                                                  int w, int h, void* G0, void* G1)
+{
+    constexpr int CH = GRAY ? 1 : 3;
+    constexpr int C2 = 2 * CH;
+    const int pw = w + 2 * PAD, ph = h + 2 * PAD;
+    const int X = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int Y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (X >= pw || Y >= ph) return;
+    const uint8_t* img = blockIdx.z ? img1 : img0;
+    void* G = blockIdx.z ? G1 : G0;
+    const int x = clampi(X - PAD, 0, w - 1), y = clampi(Y - PAD, 0, h - 1);
+    // smoothing and derivative taps of the size-KS Sobel operator
+    const int sm3[3] = {1, 2, 1}, dv3[3] = {-1, 0, 1};
+    const int sm5[5] = {1, 4, 6, 4, 1}, dv5[5] = {-1, -2, 0, 2, 1};
+    int gx[CH], gy[CH];
+#pragma unroll
+    for (int c = 0; c < CH; c++) { gx[c] = 0; gy[c] = 0; }
+#pragma unroll
+    for (int i = 0; i < KS; i++) {
+        const uint8_t* row = img + (size_t)mirror(y + i - KS / 2, h) * pitch;
+        int rs[CH], rd[CH];
+#pragma unroll
+        for (int c = 0; c < CH; c++) { rs[c] = 0; rd[c] = 0; }
+#pragma unroll
+        for (int jj = 0; jj < KS; jj++) {
+            const uint8_t* p = row + 3 * mirror(x + jj - KS / 2, w);
+            const int sm = KS == 3 ? sm3[jj] : sm5[jj];
+            const int dv = KS == 3 ? dv3[jj] : dv5[jj];
+            if (GRAY) {
+                const int v = (77 * p[0] + 150 * p[1] + 29 * p[2] + 128) >> 8;
+                rs[0] += sm * v;
+                rd[0] += dv * v;
+            } else {
+#pragma unroll
+                for (int c = 0; c < CH; c++) { rs[c] += sm * p[c]; rd[c] += dv * p[c]; }
+            }
+        }
+        const int smi = KS == 3 ? sm3[i] : sm5[i];
+        const int dvi = KS == 3 ? dv3[i] : dv5[i];
+#pragma unroll
+        for (int c = 0; c < CH; c++) { gx[c] += smi * rd[c]; gy[c] += dvi * rs[c]; }
+    }
+    const size_t o = ((size_t)Y * pw + X) * C2;
+    if (!F32) {
+        uint16_t* out = (uint16_t*)G + o;
+#pragma unroll
+        for (int c = 0; c < CH; c++) {
+            out[c] = (uint16_t)(gx[c] + (int)BIAS);
+            out[CH + c] = (uint16_t)(gy[c] + (int)BIAS);
+        }
+    } else {
+        float* out = (float*)G + o;
+#pragma unroll
+        for (int c = 0; c < CH; c++) {
+            float ux = 0.0f, uy = 0.0f;
+            if (gx[c] != 0 || gy[c] != 0) {
+                const double n = sqrt((double)gx[c] * gx[c] + (double)gy[c] * gy[c]);
+                ux = (float)((double)gx[c] / n);
+                uy = (float)((double)gy[c] / n);
+            }
+            out[c] = ux;
+            out[CH + c] = uy;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// random numbers of a whole pair: initial displacements and every random-search offset
+// ---------------------------------------------------------------------------------------
+
+__device__ __forceinline__ int search_off(uint32_t u, int W, int i)
+{
+    // floor(R W / 2^i) with R = (2u + 1) / 2^32 - 1, in exact integer arithmetic
+    const long long A = (long long)(2ull * u + 1ull) * W - ((long long)W << 32);
+    return (int)(A >> (32 + i));
+}
+
+__global__ __launch_bounds__(256) void k_rng(RngArgs a)
+{
+    long long item = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item < 2LL * a.n_top) {
+        const int dir = (int)(item / a.n_top), s = (int)(item % a.n_top);
+        const uint4 u = philox4x32_10(
+            make_uint4((uint32_t)s, ((uint32_t)a.top_level << 8) | ((uint32_t)dir << 16), 0u, 0u), a.key0, a.key1);
+        const uint32_t span = 2u * (uint32_t)a.R_top + 1u;
+        a.init[item] = make_short2((short)((int)__umulhi(u.x, span) - a.R_top), (short)((int)__umulhi(u.y, span) - a.R_top));
+        return;
+    }
+    item -= 2LL * a.n_top;
+    for (int k = 0; k < a.nstages; k++) {
+        const RngStage& S = a.st[k];
+        const int nB = (S.nI + 1) >> 1;
+        const long long cnt = 2LL * S.n * S.iters * nB;
+        if (item >= cnt) { item -= cnt; continue; }
+        const int b = (int)(item % nB);
+        long long rest = item / nB;
+        const int s = (int)(rest % S.n);
+        rest /= S.n;
+        const int t = (int)(rest % S.iters);
+        const int dir = (int)(rest / S.iters);
+        const uint32_t w1 = (uint32_t)t | ((uint32_t)S.level << 8) | ((uint32_t)dir << 16) | (1u << 24);
+        const uint4 u = philox4x32_10(make_uint4((uint32_t)s, w1, (uint32_t)b, (uint32_t)S.stage), a.key0, a.key1);
+        short2* out = a.table + S.base + (((long long)dir * S.iters + t) * S.n + s) * S.nI;
+        const int i0 = 2 * b;
+        out[i0] = make_short2((short)search_off(u.x, S.W, i0), (short)search_off(u.y, S.W, i0));
+        if (i0 + 1 < S.nI)
+            out[i0 + 1] = make_short2((short)search_off(u.z, S.W, i0 + 1), (short)search_off(u.w, S.W, i0 + 1));
+        return;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------------------
+
+hipError_t launch_pyr_down(const uint8_t* src0, const uint8_t* src1, int pitch, int w, int h,
+                           uint8_t* dst0, uint8_t* dst1, hipStream_t s)
+{
+    const int w2 = (w + 1) / 2, h2 = (h + 1) / 2;
+    dim3 grid((w2 + 63) / 64, (h2 + 3) / 4, 2);
+    hipLaunchKernelGGL(k_pyr, grid, dim3(256), 0, s, src0, src1, pitch, w, h, dst0, dst1);
+    return hipGetLastError();
+}
+
+hipError_t launch_gradient(const uint8_t* img0, const uint8_t* img1, int pitch, int w, int h,
+                           void* G0, void* G1, int gray, int ksize, int f32, hipStream_t s)
+{
+    dim3 grid((w + 2 * PAD + 63) / 64, (h + 2 * PAD + 3) / 4, 2);
+#define PGM_GRAD(KS, GR, F)                                                                     \
+    if (ksize == KS && !!gray == GR && !!f32 == F) {                                             \
+        hipLaunchKernelGGL((k_gradient<KS, GR, F>), grid, dim3(256), 0, s, img0, img1, pitch, w, \
+                           h, G0, G1);                                                           \
+        return hipGetLastError();                                                                \
+    }
+    PGM_GRAD(3, false, false) PGM_GRAD(3, false, true) PGM_GRAD(3, true, false) PGM_GRAD(3, true, true)
+    PGM_GRAD(5, false, false) PGM_GRAD(5, false, true) PGM_GRAD(5, true, false) PGM_GRAD(5, true, true)
+#undef PGM_GRAD
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rng(const RngArgs& a, hipStream_t s)
+{
+    const long long items = 2LL * a.n_top + a.total_items;
+    if (items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rng, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Kernel variants: patch side exactly 8 or 16 (fully unrolled rows), or any side up to 8 /
+// up to 16 with masked rows; 6 or 2 gradient channels; integer or float features.
+#define PGM_DISPATCH(KERNEL, ARGS, NGROUPS, NDIR)                                               \
+    do {                                                                                         \
+        const int P = (ARGS).d[0].P;                                                             \
+        const int pmax = P <= 8 ? 8 : 16;                                                        \
+        const bool fixed = P == pmax;                                                            \
+        const int gpb = 256 / pmax;                                                              \
+        dim3 grid((unsigned)(((NGROUPS) + gpb - 1) / gpb), (unsigned)(NDIR));                    \
+        if ((NGROUPS) <= 0) return hipSuccess;                                                   \
+        PGM_V(KERNEL, 6, 8, true) PGM_V(KERNEL, 6, 8, false) PGM_V(KERNEL, 6, 16, true)           \
+        PGM_V(KERNEL, 6, 16, false) PGM_V(KERNEL, 2, 8, true) PGM_V(KERNEL, 2, 8, false)          \
+        PGM_V(KERNEL, 2, 16, true) PGM_V(KERNEL, 2, 16, false)                                    \
+        return hipErrorInvalidValue;                                                             \
+    } while (0)
+
+#define PGM_V(KERNEL, C2_, PM_, FX_)                                                             \
+    if (C2 == C2_ && pmax == PM_ && fixed == FX_) {                                              \
+        if (f32) hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, true>), grid, dim3(256), 0, s, a);    \
+        else hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, false>), grid, dim3(256), 0, s, a);       \
+        return hipGetLastError();                                                                \
+    }
+
+hipError_t launch_sweep(const SweepArgs& a, int C2, int f32, int ndir, hipStream_t s)
+{
+    PGM_DISPATCH(k_sweep, a, a.g.ny * ((a.g.nx + 1) / 2), ndir);
+}
+
+hipError_t launch_init(const InitArgs& a, int C2, int f32, int ndir, hipStream_t s)
+{
+    PGM_DISPATCH(k_init, a, a.g.nx * a.g.ny, ndir);
+}
+
+hipError_t launch_down(const TransArgs& a, int C2, int f32, int ndir, hipStream_t s)
+{
+    PGM_DISPATCH(k_down, a, a.g.nx * a.g.ny, ndir);
+}
+
+hipError_t launch_up(const TransArgs& a, int C2, int f32, int ndir, hipStream_t s)
+{
+    PGM_DISPATCH(k_up, a, a.g.nx * a.g.ny, ndir);
+}
+
+#undef PGM_V
+#undef PGM_DISPATCH
+
+hipError_t launch_check(const CheckArgs& a, hipStream_t s)
+{
+    const int n = a.g.nx * a.g.ny;
+    hipLaunchKernelGGL(k_check, dim3((n + 255) / 256, 2), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_output(const Field& f, const Geo& g, pgm_match_t* out, hipStream_t s)
+{
+    const int n = g.nx * g.ny;
+    hipLaunchKernelGGL(k_output, dim3((n + 255) / 256), dim3(256), 0, s, f, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const pgm_match_t* dense, int n, pgm_match_t* out, int32_t* n_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, dense, n, out, n_out);
+    return hipGetLastError();
+}
+
+}  // namespace pgm

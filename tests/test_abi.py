@@ -1,0 +1,128 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared entry point, its
+struct layouts agree with the binding, presets and sizes agree with the oracle's geometry,
+and invalid arguments are rejected without device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1704_03217_amd as pgm
+from conftest import CONFIG_PARAMS, ROOT, base_params
+
+HEADER = os.path.join(ROOT, "include", "pgm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return re.findall(r"PGM_API\s+[\w\s\*]+?\b(pgm_\w+)\s*\(", src)
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert set(names) == set(pgm.EXPORTS)
+    L = pgm.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.check_output(["nm", "-D", "--defined-only", pgm.LIB_PATH]).decode()
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert set(names) <= exported
+
+
+def test_struct_layout_matches_header():
+    prog = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "pgm.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pgm_params), offsetof(pgm_params, iters),
+         offsetof(pgm_params, rng_seed), sizeof(pgm_match_t), sizeof(pgm_sizes),
+         offsetof(pgm_sizes, workspace_bytes));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "l.c")
+        exe = os.path.join(d, "l")
+        open(src, "w").write(prog)
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
+        got = [int(v) for v in subprocess.check_output([exe]).split()]
+    exp = [C.sizeof(pgm.pgm_params), pgm.pgm_params.iters.offset, pgm.pgm_params.rng_seed.offset,
+           pgm.MATCH_BYTES, C.sizeof(pgm.pgm_sizes), pgm.pgm_sizes.workspace_bytes.offset]
+    assert got == exp
+    assert pgm.MATCH_DTYPE.itemsize == pgm.MATCH_BYTES
+
+
+@pytest.mark.parametrize("preset,cfg", [(pgm.PRESET_CONFIG1, 1), (pgm.PRESET_CONFIG2, 2), (pgm.PRESET_CONFIG3, 3)])
+def test_presets_match_workload_parameters(preset, cfg):
+    d = pgm.params_dict(pgm.pgm_default_params(preset))
+    assert d == CONFIG_PARAMS[cfg]
+
+
+def test_paper_preset():
+    d = pgm.params_dict(pgm.pgm_default_params(pgm.PRESET_PAPER))
+    # Sec. IV: W=2, S=5, L=3, N=2, 6 iterations at full resolution and 4 elsewhere; r = 7 / 5
+    assert (d["radius"], d["sobel_ksize"], d["levels"], d["refine_rounds"]) == (2, 5, 3, 2)
+    assert d["iters"] == [6, 4, 4]
+    assert (d["patch_fwd"], d["patch_bwd"]) == (15, 11)
+    assert d["seed_stride"] == 1
+
+
+@pytest.mark.parametrize("w,h,L,stride", [(1024, 436, 5, 3), (1242, 375, 5, 3), (256, 192, 3, 3),
+                                          (1, 1, 1, 3), (17, 9, 3, 2), (640, 480, 8, 1), (16384, 12, 2, 5)])
+def test_query_geometry_matches_oracle(w, h, L, stride):
+    p = base_params(levels=L, seed_stride=stride, iters=[2] * L)
+    s = pgm.pgm_query(p, w, h)
+    geo = oracle.geometry(p, w, h)
+    assert s.levels == L
+    for l, (lw, lh, nx, ny) in enumerate(geo):
+        assert (s.level_w[l], s.level_h[l], s.level_nx[l], s.level_ny[l]) == (lw, lh, nx, ny)
+    assert (s.nx, s.ny) == geo[0][2:]
+    assert s.workspace_bytes > 0
+
+
+def test_query_workspace_of_config2_is_modest():
+    s = pgm.pgm_query(CONFIG_PARAMS[2], 1024, 436)
+    assert s.nx * s.ny == 49445
+    assert s.workspace_bytes < 64 << 20
+
+
+@pytest.mark.parametrize("bad", [dict(levels=0), dict(levels=9), dict(seed_stride=0), dict(patch_fwd=0),
+                                 dict(patch_bwd=17), dict(iters=[256, 1, 1]), dict(radius=0),
+                                 dict(sobel_ksize=7), dict(feature=2), dict(color=3), dict(fwd_bwd=2),
+                                 dict(consistency_px=-1), dict(init_mode=2), dict(refine_rounds=17),
+                                 dict(levels=1, iters=[1], refine_rounds=1), dict(max_disp=-1)])
+def test_query_rejects_invalid_parameters(bad):
+    with pytest.raises(pgm.PGMError) as e:
+        pgm.pgm_query(base_params(**bad), 64, 64)
+    assert e.value.status == pgm.PGM_EINVAL
+
+
+@pytest.mark.parametrize("w,h", [(0, 10), (10, 0), (16385, 10), (10, 16385)])
+def test_query_rejects_bad_sizes(w, h):
+    with pytest.raises(pgm.PGMError):
+        pgm.pgm_query(base_params(), w, h)
+
+
+def test_null_arguments_rejected_without_device_work():
+    L = pgm.lib()
+    assert L.pgm_default_params(None, 1) == pgm.PGM_EINVAL
+    assert L.pgm_default_params(C.byref(pgm.pgm_params()), 99) == pgm.PGM_EINVAL
+    assert L.pgm_query(None, 10, 10, C.byref(pgm.pgm_sizes())) == pgm.PGM_EINVAL
+    assert L.pgm_query(C.byref(pgm.params(base_params())), 10, 10, None) == pgm.PGM_EINVAL
+    assert L.pgm_create(0, 0, None) == pgm.PGM_EINVAL
+    p = pgm.params(base_params())
+    assert L.pgm_match(None, C.byref(p), None, None, 10, 10, 30, None, None, None, None, None, None) == pgm.PGM_EINVAL
+    assert L.pgm_dump_level(None, 0, 0, None) == pgm.PGM_EINVAL
+    L.pgm_destroy(None)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(pgm, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(pgm, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        pgm.lib()

@@ -1,0 +1,179 @@
+"""GPU parity: libpgm (HIP, gfx950) against the CPU oracle's synchronous schedule.
+
+The integer path must agree bit for bit in every level's displacements, distances and
+flags, in the level-0 outputs, the compacted inliers and the number of distance
+evaluations. The direction-only float path computes its patch distances exactly (see the
+kernels), so it is held to the same bar.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1704_03217_amd as pgm
+import synth
+from conftest import CONFIG_PARAMS, base_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def matcher():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    m = pgm.Matcher(0, 768 << 20)
+    yield m
+    m.close()
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_run(m, params, img1, img2):
+    torch = m.torch
+    t1 = torch.from_numpy(np.ascontiguousarray(img1)).cuda()
+    t2 = torch.from_numpy(np.ascontiguousarray(img2)).cuda()
+    o = m.match(params, t1, t2)
+    torch.cuda.synchronize()
+    n_in = int(o["n_inliers"].item())
+    return dict(fwd=m.to_numpy(o["fwd"]), bwd=m.to_numpy(o["bwd"]), n_inliers=n_in,
+                compact=m.to_numpy(o["compact"], n_in), n_evals=int(o["n_evals"].item()), sizes=o["sizes"])
+
+
+def compare(m, params, img1, img2, name, levels=True, features=True):
+    _say(f"[gpu parity] {name} {img1.shape[1]}x{img1.shape[0]} params={params}")
+    g = gpu_run(m, params, img1, img2)
+    r = oracle.match(params, img1, img2, schedule=oracle.SYNC)
+    L = params["levels"]
+    if features:
+        check_features(m, params, img1, img2, name)
+    if levels:
+        problems = []
+        for l in reversed(range(L)):          # coarse to fine: the first divergence comes first
+            for d in range(2):
+                got = m.dump_level(l, d)
+                exp = r["levels"][d][l]
+                if not np.array_equal(got, exp):
+                    bad = np.nonzero((got != exp).any(axis=1))[0]
+                    problems.append(f"level {l} dir {d}: {len(bad)} of {len(exp)} seeds differ; first {bad[:5]}: "
+                                    f"gpu {got[bad[:3]].tolist()} oracle {exp[bad[:3]].tolist()}")
+        assert not problems, f"{name}: " + " | ".join(problems)
+    for key in ("fwd", "bwd"):
+        assert np.array_equal(g[key], r[key]), f"{name}: {key} output differs"
+    assert g["n_inliers"] == r["n_inliers"]
+    assert np.array_equal(g["compact"], r["compact"])
+    assert g["n_evals"] == r["n_evals"], (g["n_evals"], r["n_evals"])
+    return g, r
+
+
+def check_features(m, params, img1, img2, name):
+    """Pyramid (Sec. III-D) and gradient image (Eq. 1-2) of every level, bit-exact."""
+    L = params["levels"]
+    f32 = params["feature"] == 1
+    ch = 1 if params["color"] == 1 else 3
+    ims = [np.ascontiguousarray(img1), np.ascontiguousarray(img2)]
+    problems = []
+    for l in range(L):
+        if l > 0:
+            ims = [oracle.pyr_down(x) for x in ims]
+        for k in range(2):
+            gp = m.dump_pyramid(l, k)
+            if not np.array_equal(gp, ims[k]):
+                problems.append(f"pyramid level {l} image {k}: {(gp != ims[k]).sum()} values differ")
+            src = oracle.gray(ims[k]) if ch == 1 else ims[k]
+            G = oracle.gradient_image(src, params["sobel_ksize"])
+            if f32:
+                G = oracle.direction(G)
+            got = m.dump_gradient(l, k, 2 * ch, f32)
+            a, b = (got.view(np.uint32), G.view(np.uint32)) if f32 else (got, G)
+            if not np.array_equal(a, b):
+                bad = np.argwhere(a != b)
+                problems.append(f"gradient level {l} image {k}: {len(bad)} values differ, first {bad[:3].tolist()} "
+                                f"gpu {[got[tuple(i)] for i in bad[:3]]} oracle {[G[tuple(i)] for i in bad[:3]]}")
+    assert not problems, f"{name}: " + " | ".join(problems)
+
+
+CASES = {
+    "config1": (lambda: synth.config_pair(1), CONFIG_PARAMS[1]),
+    "config1_s3_patch5_11": (lambda: synth.config_pair(1), base_params(sobel_ksize=3, patch_fwd=5, patch_bwd=11, rng_seed=7)),
+    "config1_gray": (lambda: synth.config_pair(1), base_params(color=1, rng_seed=8)),
+    "config1_refine2": (lambda: synth.config_pair(1), base_params(refine_rounds=2, rng_seed=9)),
+    "config1_patch16_tau0": (lambda: synth.config_pair(1), base_params(patch_fwd=16, patch_bwd=16, consistency_px=0, rng_seed=10)),
+    "config1_patch1_nofb": (lambda: synth.config_pair(1), base_params(patch_fwd=1, patch_bwd=1, fwd_bwd=0, rng_seed=11)),
+    "config1_patch15_paper_like": (lambda: synth.config_pair(1), base_params(patch_fwd=15, patch_bwd=11, iters=[6, 4, 4], refine_rounds=2, rng_seed=12)),
+    "dense_stride1": (lambda: synth.rect_pair(5, 48, 64, dmax=6), base_params(seed_stride=1, max_disp=6, rng_seed=13)),
+    "stride2_even": (lambda: synth.rect_pair(6, 50, 70, dmax=8), base_params(seed_stride=2, max_disp=8, rng_seed=14)),
+    "exhaustive": (lambda: synth.rect_pair(3, 32, 40, dmax=4), base_params(levels=2, iters=[3, 3], init_mode=1, max_disp=6, rng_seed=15)),
+    "exhaustive_whole_image": (lambda: synth.rect_pair(4, 20, 24, n_rect=2, dmax=4), base_params(levels=1, iters=[2], init_mode=1, max_disp=0)),
+    "tiny_1x1": (lambda: synth.rect_pair(1, 1, 1, n_rect=0, dmax=1), base_params(levels=1, iters=[2])),
+    "tiny_3x2": (lambda: synth.rect_pair(1, 2, 3, n_rect=0, dmax=1), base_params(levels=2, iters=[2, 2], max_disp=2)),
+    "ragged_17x9": (lambda: synth.rect_pair(2, 9, 17, n_rect=1, dmax=3), base_params(levels=3, iters=[3, 3, 3], max_disp=4)),
+    "ragged_101x67": (lambda: synth.rect_pair(3, 67, 101, dmax=10), base_params(levels=4, iters=[2, 3, 4, 5], max_disp=12)),
+    "wide_16384x12": (lambda: synth.rect_pair(9, 12, 16384, n_rect=2, dmax=20), base_params(levels=2, iters=[2, 2], max_disp=20, seed_stride=5)),
+    "translation": (lambda: synth.translate_pair(3, 72, 96, 10, -6), base_params(levels=2, iters=[8, 8], max_disp=16)),
+    "identical": (lambda: (lambda p: synth.Pair(p.img1, p.img1, p.flow, p.valid))(synth.config_pair(1)), base_params(rng_seed=3)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pipeline_bit_exact(matcher, name):
+    make, params = CASES[name]
+    pair = make()
+    compare(matcher, params, pair.img1, pair.img2, name)
+
+
+def test_config2_full_size_bit_exact(matcher):
+    pair = synth.config_pair(2)
+    g, r = compare(matcher, CONFIG_PARAMS[2], pair.img1, pair.img2, "config2")
+    assert g["fwd"].shape[0] == 49445
+
+
+def test_config3_direction_full_size(matcher):
+    pair = synth.config_pair(3)
+    compare(matcher, CONFIG_PARAMS[3], pair.img1, pair.img2, "config3")
+
+
+def test_direction_small_variants(matcher):
+    pair = synth.config_pair(1)
+    compare(matcher, base_params(feature=1, rng_seed=21), pair.img1, pair.img2, "dir_rgb")
+    compare(matcher, base_params(feature=1, color=1, patch_fwd=11, patch_bwd=7, rng_seed=22), pair.img1, pair.img2, "dir_gray")
+
+
+def test_repeatable_and_context_reuse(matcher):
+    a = synth.config_pair(1)
+    b = synth.rect_pair(77, 100, 150, dmax=12)
+    p = CONFIG_PARAMS[1]
+    g1 = gpu_run(matcher, p, a.img1, a.img2)
+    gpu_run(matcher, base_params(levels=2, iters=[3, 3], rng_seed=5), b.img1, b.img2)
+    g2 = gpu_run(matcher, p, a.img1, a.img2)
+    assert np.array_equal(g1["fwd"], g2["fwd"]) and np.array_equal(g1["bwd"], g2["bwd"])
+    assert g1["n_evals"] == g2["n_evals"]
+
+
+def test_pitched_input(matcher):
+    torch = matcher.torch
+    pair = synth.config_pair(1)
+    h, w = pair.img1.shape[:2]
+    big1 = torch.zeros((h, w + 13, 3), dtype=torch.uint8, device="cuda")
+    big2 = torch.zeros((h, w + 13, 3), dtype=torch.uint8, device="cuda")
+    big1[:, :w] = torch.from_numpy(pair.img1).cuda()
+    big2[:, :w] = torch.from_numpy(pair.img2).cuda()
+    o = matcher.match(CONFIG_PARAMS[1], big1[:, :w], big2[:, :w])
+    torch.cuda.synchronize()
+    r = oracle.match(CONFIG_PARAMS[1], pair.img1, pair.img2)
+    assert np.array_equal(matcher.to_numpy(o["fwd"]), r["fwd"])
+
+
+def test_workspace_too_small_is_enomem(matcher):
+    torch = matcher.torch
+    small = pgm.Matcher(0, 1 << 16)
+    try:
+        img = torch.zeros((64, 64, 3), dtype=torch.uint8, device="cuda")
+        with pytest.raises(pgm.PGMError) as e:
+            small.match(base_params(), img, img)
+        assert e.value.status == pgm.PGM_ENOMEM
+    finally:
+        small.close()
