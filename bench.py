@@ -4,7 +4,8 @@
 One step = one whole pass of the method (pyramids, gradient images, random numbers,
 coarse-to-fine PatchMatch with the forward-backward check at every level, level-0 output and
 compaction) over one synthetic 1024x436 RGB pair already resident in HBM, issued as plain
-per-pair launches on one stream. Prints one JSON line.
+per-pair launches on one stream (`value`). A second pass runs the same method on B pairs per
+step through pgm_match_batch (`batched`). Prints one JSON line.
 
 Measurement: the timed region is bracketed by torch.cuda.synchronize(). The dominant kernel
 (the propagation + random-search half-sweep) is then timed live with HIP events around each
@@ -25,8 +26,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "image pairs/s at 1024x436 plain vs batched; p50/p99 served latency"
-# MI355X: 256 CUs x 4 SIMD16 x 2.4 GHz lane operations per second (one v_sad_u16 per lane-clock)
+# MI355X: 256 CUs x 4 SIMD16 x 2.4 GHz = 39.3 T lane operations per second. One v_sad_u16 per
+# lane-clock adds two absolute differences of packed 16-bit gradients, so an 8x8 patch of 6
+# channels (384 absolute differences) is 192 such operations.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+OPS_PER_EVAL = 8 * 8 * 6 // 2
 
 
 def parse():
@@ -38,7 +42,44 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
+    ap.add_argument("--batch", type=int, default=32, help="pairs per step of the batched pass (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=20)
     return ap.parse_args()
+
+
+def sweep_roofline(pgm, ctx, steps, run, torch):
+    """Run `steps` steps with per-launch HIP events on; return (roofline of k_sweep, per-kind
+    breakdown). achieved = evaluations x 192 / launches / average launch duration."""
+    pgm.pgm_profile(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        run(k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    breakdown = {}
+    for kind, name in enumerate(pgm.KIND_NAMES):
+        n, ms, ev = pgm.pgm_profile_read(ctx, kind)
+        if n:
+            breakdown[name] = dict(launches_per_step=n / steps, ms_per_step=ms / steps,
+                                   avg_launch_us=1000.0 * ms / n, evals=ev)
+    pgm.pgm_profile(ctx, False)
+    sw = breakdown.get("sweep")
+    roof = None
+    if sw:
+        n_launch = sw["launches_per_step"] * steps
+        ops_per_launch = sw["evals"] * float(OPS_PER_EVAL) / n_launch
+        achieved = ops_per_launch / (sw["avg_launch_us"] * 1e-6) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "kernel": "k_sweep (propagation + random search half-sweep)",
+                "op": "v_sad_u16 (two 16-bit absolute differences), 192 per 8x8x6 patch distance",
+                "avg_launch_us": round(sw["avg_launch_us"], 3),
+                "ops_per_launch": round(ops_per_launch),
+                "profiled_ms_per_step": round(1000.0 * (t1 - t0) / steps, 4)}
+    kernels = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+               for k, v in breakdown.items()}
+    return roof, kernels
 
 
 def main():
@@ -88,36 +129,46 @@ def main():
     value = args.steps / elapsed
     n_inl = int(outs[0]["n_inliers"].item())
 
-    roofline = None
-    breakdown = {}
+    roofline, kernels = None, {}
     if not args.no_profile_pass:
         print(f"[bench] profiled pass of {args.steps} steps (HIP events around every launch)", file=sys.stderr,
               flush=True)
-        pgm.pgm_profile(m.ctx, True)
+        roofline, kernels = sweep_roofline(pgm, m.ctx, args.steps, step, torch)
+
+    batched = None
+    if args.batch > 0:
+        B = args.batch
+        print(f"[bench] batched pass: {B} pairs per step, {args.batch_steps} steps", file=sys.stderr, flush=True)
+        s_q = pgm.pgm_query(params, w, h)
+        mb = pgm.Matcher(0, s_q.workspace_shared_bytes + B * s_q.workspace_pair_bytes + (1 << 20))
+        A = torch.stack([imgs[k % len(imgs)][0] for k in range(B)]).contiguous()
+        Bm = torch.stack([imgs[k % len(imgs)][1] for k in range(B)]).contiguous()
+        ob = mb.outputs_batch(params, w, h, B)
+
+        def bstep(k):
+            mb.match_batch_into(params, A, Bm, ob, stream=stream)
+
+        for k in range(max(2, args.warmup // 4)):
+            bstep(k)
         torch.cuda.synchronize()
-        tp0 = time.perf_counter()
-        for k in range(args.steps):
-            step(k)
+        ob["n_evals"].zero_()
         torch.cuda.synchronize()
-        tp1 = time.perf_counter()
-        for kind, name in enumerate(pgm.KIND_NAMES):
-            n, ms, ev = pgm.pgm_profile_read(m.ctx, kind)
-            if n:
-                breakdown[name] = dict(launches_per_step=n / args.steps, ms_per_step=ms / args.steps,
-                                       avg_launch_us=1000.0 * ms / n, evals=ev)
-        pgm.pgm_profile(m.ctx, False)
-        sw = breakdown.get("sweep")
-        if sw:
-            n_launch = sw["launches_per_step"] * args.steps
-            avg_s = sw["avg_launch_us"] * 1e-6
-            ops_per_launch = sw["evals"] * 384.0 / n_launch         # 8x8 patch x 6 channels
-            achieved = ops_per_launch / avg_s / 1e12
-            roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                        "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                        "kernel": "k_sweep (propagation + random search half-sweep)",
-                        "avg_launch_us": round(sw["avg_launch_us"], 3),
-                        "ops_per_launch": round(ops_per_launch),
-                        "profiled_ms_per_step": round(1000.0 * (tp1 - tp0) / args.steps, 4)}
+        b0 = time.perf_counter()
+        for k in range(args.batch_steps):
+            bstep(k)
+        torch.cuda.synchronize()
+        b1 = time.perf_counter()
+        bev = int(ob["n_evals"].item())
+        # every pair of the batch equals its plain result
+        same = bool(torch.equal(ob["fwd"][: outs[0]["fwd"].numel()], outs[0]["fwd"]))
+        broof, bkern = (None, {})
+        if not args.no_profile_pass:
+            broof, bkern = sweep_roofline(pgm, mb.ctx, args.batch_steps, bstep, torch)
+        batched = {"value": round(B * args.batch_steps / (b1 - b0), 3), "unit": "pairs/s", "global_batch": B,
+                   "steps": args.batch_steps, "ms_per_step": round(1000.0 * (b1 - b0) / args.batch_steps, 4),
+                   "dist_evals_per_s": round(bev / (b1 - b0), 1), "pair0_equals_plain": same,
+                   "roofline": broof, "kernels": bkern}
+        mb.close()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -157,8 +208,8 @@ def main():
         "dist_evals_per_pair": evals / args.steps,
         "n_inliers_pair0": n_inl,
         "roofline": roofline,
-        "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                    for k, v in breakdown.items()},
+        "kernels": kernels,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     m.close()

@@ -90,6 +90,9 @@ typedef struct {
     int32_t level_nx[PGM_MAX_LEVELS], level_ny[PGM_MAX_LEVELS]; /* seed grid per level      */
     int32_t nx, ny;                  /* level-0 grid: pgm_match writes nx*ny matches          */
     uint64_t workspace_bytes;        /* device workspace pgm_match needs for one pair         */
+    uint64_t workspace_shared_bytes; /* part of it shared by all pairs of a batch (random    */
+                                     /* numbers); a batch of n pairs needs                    */
+    uint64_t workspace_pair_bytes;   /* shared + n * pair bytes                               */
 } pgm_sizes;
 
 /* Presets. */
@@ -126,6 +129,20 @@ PGM_API pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1
                      int32_t w, int32_t h, int32_t pitch_bytes, pgm_match_t* out_fwd,
                      pgm_match_t* out_bwd, int32_t* out_n_inliers, pgm_match_t* out_compact,
                      uint64_t* out_n_evals, void* stream);
+
+/* Match n_pairs pairs of the same size and parameters in one pass: every kernel launch of the
+ * method covers all pairs (the pair is one more dimension of each grid), so launch latency is
+ * paid once per batch. Pair k's images are img1 + k * image_stride_bytes and
+ * img2 + k * image_stride_bytes (stride >= pitch_bytes * h); its outputs are out_* + k * nx * ny
+ * matches and out_n_inliers[k]; out_n_evals receives the total. Each pair's results are
+ * identical to those of pgm_match on that pair alone (the random numbers depend only on the
+ * parameters). The workspace must hold workspace_shared_bytes + n_pairs * workspace_pair_bytes
+ * (pgm_query), else PGM_ENOMEM. The dump entry points then show pair 0. */
+PGM_API pgm_status pgm_match_batch(void* ctx, const pgm_params* p, int32_t n_pairs, const uint8_t* img1,
+                                   const uint8_t* img2, int32_t w, int32_t h, int32_t pitch_bytes,
+                                   int64_t image_stride_bytes, pgm_match_t* out_fwd, pgm_match_t* out_bwd,
+                                   int32_t* out_n_inliers, pgm_match_t* out_compact, uint64_t* out_n_evals,
+                                   void* stream);
 
 /* Debug copies of the last pgm_match's intermediate state into host memory; each waits for
  * the last call's stream to finish.

@@ -47,6 +47,8 @@ class pgm_sizes(C.Structure):
         ("level_nx", C.c_int32 * MAX_LEVELS), ("level_ny", C.c_int32 * MAX_LEVELS),
         ("nx", C.c_int32), ("ny", C.c_int32),
         ("workspace_bytes", C.c_uint64),
+        ("workspace_shared_bytes", C.c_uint64),
+        ("workspace_pair_bytes", C.c_uint64),
     ]
 
 
@@ -54,7 +56,7 @@ MATCH_DTYPE = np.dtype([("x1", "<i4"), ("y1", "<i4"), ("x2", "<i4"), ("y2", "<i4
                         ("dist", "<i4"), ("flags", "<u4")])
 MATCH_BYTES = 24
 
-EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_dump_level",
+EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_match_batch", "pgm_dump_level",
            "pgm_dump_gradient", "pgm_dump_pyramid", "pgm_profile", "pgm_profile_read",
            "pgm_last_error", "pgm_destroy")
 
@@ -90,6 +92,9 @@ def lib():
         L.pgm_match.argtypes = [V, C.POINTER(pgm_params), V, V, C.c_int32, C.c_int32, C.c_int32,
                                 V, V, V, V, V, V]
         L.pgm_match.restype = C.c_int32
+        L.pgm_match_batch.argtypes = [V, C.POINTER(pgm_params), C.c_int32, V, V, C.c_int32, C.c_int32,
+                                      C.c_int32, C.c_int64, V, V, V, V, V, V]
+        L.pgm_match_batch.restype = C.c_int32
         L.pgm_dump_level.argtypes = [V, C.c_int32, C.c_int32, V]
         L.pgm_dump_level.restype = C.c_int32
         L.pgm_dump_gradient.argtypes = [V, C.c_int32, C.c_int32, V]
@@ -164,6 +169,16 @@ def pgm_match(ctx, p, img1: int, img2: int, w: int, h: int, pitch_bytes: int, ou
     """All pointer arguments are integer device addresses (or None)."""
     return _check(lib().pgm_match(ctx, C.byref(_as_params(p)), img1, img2, w, h, pitch_bytes, out_fwd,
                                   out_bwd, out_n_inliers, out_compact, out_n_evals, stream), ctx)
+
+
+def pgm_match_batch(ctx, p, n_pairs: int, img1: int, img2: int, w: int, h: int, pitch_bytes: int,
+                    image_stride_bytes: int, out_fwd: int, out_bwd: int | None = None,
+                    out_n_inliers: int | None = None, out_compact: int | None = None,
+                    out_n_evals: int | None = None, stream: int | None = None):
+    """All pointer arguments are integer device addresses (or None)."""
+    return _check(lib().pgm_match_batch(ctx, C.byref(_as_params(p)), n_pairs, img1, img2, w, h, pitch_bytes,
+                                        image_stride_bytes, out_fwd, out_bwd, out_n_inliers, out_compact,
+                                        out_n_evals, stream), ctx)
 
 
 def pgm_dump_level(ctx, level: int, dir: int, n: int) -> np.ndarray:
@@ -264,6 +279,42 @@ class Matcher:
         h, w = img1.shape[:2]
         o = self.outputs(p, w, h, bwd, compact, count_evals)
         return self.match_into(p, img1, img2, o)
+
+    def outputs_batch(self, p, w, h, n_pairs, bwd=True, compact=True, count_evals=True):
+        torch = self.torch
+        s = pgm_query(p, w, h)
+        n = s.nx * s.ny
+        dev = torch.device("cuda", self.device)
+        o = dict(sizes=s, n=n, n_pairs=n_pairs)
+        o["fwd"] = torch.empty(n_pairs * n * 6, dtype=torch.int32, device=dev)
+        o["bwd"] = torch.empty(n_pairs * n * 6, dtype=torch.int32, device=dev) if bwd else None
+        o["n_inliers"] = torch.zeros(n_pairs, dtype=torch.int32, device=dev) if compact else None
+        o["compact"] = torch.empty(n_pairs * n * 6, dtype=torch.int32, device=dev) if compact else None
+        o["n_evals"] = torch.zeros(1, dtype=torch.int64, device=dev) if count_evals else None
+        return o
+
+    def match_batch_into(self, p, img1, img2, o, stream=None):
+        """img1, img2: (B, h, w, 3) uint8 CUDA tensors with the same strides."""
+        torch = self.torch
+        assert img1.is_cuda and img1.dtype == torch.uint8 and img1.dim() == 4 and img1.shape[3] == 3
+        assert img2.shape == img1.shape and img2.dtype == torch.uint8
+        assert img1.stride()[1:] == img2.stride()[1:] and img1.stride(0) == img2.stride(0)
+        assert img1.stride(3) == 1 and img1.stride(2) == 3
+        B, h, w = img1.shape[:3]
+        assert B == o["n_pairs"]
+        ptr = lambda t: None if t is None else t.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        pgm_match_batch(self.ctx, p, B, img1.data_ptr(), img2.data_ptr(), w, h, img1.stride(1),
+                        img1.stride(0), o["fwd"].data_ptr(), ptr(o["bwd"]), ptr(o["n_inliers"]),
+                        ptr(o["compact"]), ptr(o["n_evals"]), stream)
+        self.last_sizes = o["sizes"]
+        return o
+
+    def match_batch(self, p, img1, img2, bwd=True, compact=True, count_evals=True):
+        B, h, w = img1.shape[:3]
+        o = self.outputs_batch(p, w, h, B, bwd, compact, count_evals)
+        return self.match_batch_into(p, img1, img2, o)
 
     @staticmethod
     def to_numpy(t, count=None):

@@ -24,8 +24,28 @@ struct Layout {
     long long st_base[MAX_STAGES];                       // short2 offset of the stage's offsets
     long long rnd_items = 0;                             // Philox calls for the search offsets
     int R_top = 0;
-    size_t total = 0;
+    // per-block evaluation counts of the matching launches, one table per kernel kind
+    // (init, down, up, sweep), and the per-block inlier counts of the level-0 output
+    size_t cnt[4] = {0, 0, 0, 0};
+    long long cnt_cap[4] = {0, 0, 0, 0};
+    size_t blockcnt = 0;
+    // the random-number table is shared by all pairs of a batch; everything else is per pair
+    // (offsets above are relative to the pair's slice, except rnd / rnd_init)
+    size_t shared_bytes = 0, pair_bytes = 0;
+    size_t total = 0;   // shared + one pair
 };
+
+enum { CNT_INIT = 0, CNT_DOWN = 1, CNT_UP = 2, CNT_SWEEP = 3 };
+
+// both directions share a launch when their patch sides select the same kernel variant
+int variant(int P) { return P == 8 ? 0 : P < 8 ? 1 : P == 16 ? 2 : 3; }
+
+// work-groups launched for `groups` seeds in both directions
+long long dir_blocks(const pgm_params* p, int groups)
+{
+    if (variant(p->patch_fwd) == variant(p->patch_bwd)) return 2LL * match_blocks(groups, p->patch_fwd);
+    return (long long)match_blocks(groups, p->patch_fwd) + match_blocks(groups, p->patch_bwd);
+}
 
 enum { ENTER_INIT = 0, ENTER_DOWN_F = 1, ENTER_DOWN_FO = 2, ENTER_UP_FO = 3 };
 
@@ -98,7 +118,25 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
     for (int k = 0; k < p->refine_rounds; k++) { add(m - 1, ENTER_DOWN_FO); add(m, ENTER_UP_FO); }
     for (int l = m - 1; l >= 0; l--) add(l, l == m - 1 ? ENTER_DOWN_F : ENTER_DOWN_FO);
 
+    // shared slice: random numbers
+    long long base = 0;
+    for (int k = 0; k < Y.nst; k++) {
+        const int l = Y.st_level[k];
+        const bool rand_init = Y.st_enter[k] == ENTER_INIT && p->init_mode == PGM_INIT_RANDOM;
+        Y.st_W[k] = rand_init ? (Y.R_top > 0 ? Y.R_top : 1) : p->radius;
+        Y.st_nI[k] = n_offsets(Y.st_W[k]);
+        Y.st_base[k] = base;
+        const long long n = (long long)Y.lnx[l] * Y.lny[l];
+        base += 2LL * p->iters[l] * n * Y.st_nI[k];
+        Y.rnd_items += 2LL * n * p->iters[l] * ((Y.st_nI[k] + 1) / 2);
+    }
     size_t cur = 0;
+    Y.rnd = take(cur, (size_t)base * sizeof(short2) + 4);
+    Y.rnd_init = take(cur, (size_t)2 * Y.lnx[m] * Y.lny[m] * sizeof(short2));
+    Y.shared_bytes = (cur + 255) & ~(size_t)255;
+
+    // per-pair slice
+    cur = 0;
     for (int im = 0; im < 2; im++)
         for (int l = 0; l < Y.L; l++) {
             Y.pyr[im][l] = l ? take(cur, (size_t)Y.lw[l] * Y.lh[l] * 3) : 0;
@@ -111,20 +149,19 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
             Y.dist[d][l] = take(cur, n * 4);
             Y.flags[d][l] = take(cur, n);
         }
-    long long base = 0;
     for (int k = 0; k < Y.nst; k++) {
         const int l = Y.st_level[k];
-        const bool rand_init = Y.st_enter[k] == ENTER_INIT && p->init_mode == PGM_INIT_RANDOM;
-        Y.st_W[k] = rand_init ? (Y.R_top > 0 ? Y.R_top : 1) : p->radius;
-        Y.st_nI[k] = n_offsets(Y.st_W[k]);
-        Y.st_base[k] = base;
-        const long long n = (long long)Y.lnx[l] * Y.lny[l];
-        base += 2LL * p->iters[l] * n * Y.st_nI[k];
-        Y.rnd_items += 2LL * n * p->iters[l] * ((Y.st_nI[k] + 1) / 2);
+        const int kind = Y.st_enter[k] == ENTER_INIT ? CNT_INIT : Y.st_enter[k] == ENTER_UP_FO ? CNT_UP : CNT_DOWN;
+        Y.cnt_cap[kind] += dir_blocks(p, Y.lnx[l] * Y.lny[l]);
+        auto sb = [&](int P) { return (long long)sweep_blocks(Y.lnx[l], Y.lny[l], P); };
+        const long long per_sweep = variant(p->patch_fwd) == variant(p->patch_bwd) ? 2 * sb(p->patch_fwd)
+                                                                                   : sb(p->patch_fwd) + sb(p->patch_bwd);
+        Y.cnt_cap[CNT_SWEEP] += 2LL * p->iters[l] * per_sweep;
     }
-    Y.rnd = take(cur, (size_t)base * sizeof(short2) + 4);
-    Y.rnd_init = take(cur, (size_t)2 * Y.lnx[m] * Y.lny[m] * sizeof(short2));
-    Y.total = (cur + 255) & ~(size_t)255;
+    for (int k = 0; k < 4; k++) Y.cnt[k] = take(cur, (size_t)Y.cnt_cap[k] * 4 + 4);
+    Y.blockcnt = take(cur, (size_t)((Y.lnx[0] * Y.lny[0] + 255) / 256) * 4);
+    Y.pair_bytes = (cur + 255) & ~(size_t)255;
+    Y.total = Y.shared_bytes + Y.pair_bytes;
 }
 
 void fill_sizes(const Layout& Y, pgm_sizes* s)
@@ -137,6 +174,8 @@ void fill_sizes(const Layout& Y, pgm_sizes* s)
     }
     s->nx = Y.lnx[0]; s->ny = Y.lny[0];
     s->workspace_bytes = Y.total;
+    s->workspace_shared_bytes = Y.shared_bytes;
+    s->workspace_pair_bytes = Y.pair_bytes;
 }
 
 }  // namespace
@@ -276,24 +315,28 @@ const char* pgm_last_error(void* ctx)
     return c ? c->err.c_str() : g_create_error.c_str();
 }
 
-pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const uint8_t* img2,
-                     int32_t w, int32_t h, int32_t pitch_bytes, pgm_match_t* out_fwd,
-                     pgm_match_t* out_bwd, int32_t* out_n_inliers, pgm_match_t* out_compact,
-                     uint64_t* out_n_evals, void* stream)
+static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, const uint8_t* img1,
+                             const uint8_t* img2, int32_t w, int32_t h, int32_t pitch_bytes,
+                             int64_t image_stride_bytes, pgm_match_t* out_fwd, pgm_match_t* out_bwd,
+                             int32_t* out_n_inliers, pgm_match_t* out_compact, uint64_t* out_n_evals,
+                             hipStream_t s)
 {
-    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
-    if (!c) return PGM_EINVAL;
     if (const char* why = validate(p, w, h)) return fail(c, PGM_EINVAL, why);
+    if (npairs < 1) return fail(c, PGM_EINVAL, "n_pairs must be at least 1");
     if (!img1 || !img2 || !out_fwd) return fail(c, PGM_EINVAL, "img1, img2 and out_fwd must not be null");
     if (pitch_bytes < 3 * w) return fail(c, PGM_EINVAL, "pitch_bytes must be at least 3 * w");
+    if (npairs > 1 && image_stride_bytes < (int64_t)pitch_bytes * h)
+        return fail(c, PGM_EINVAL, "image_stride_bytes must be at least pitch_bytes * h");
     Layout Y;
     plan(p, w, h, Y);
-    if (Y.total > c->ws_bytes)
+    const size_t need = Y.shared_bytes + (size_t)npairs * Y.pair_bytes;
+    if (need > c->ws_bytes)
         return fail(c, PGM_ENOMEM, "workspace of " + std::to_string(c->ws_bytes) + " bytes is smaller than the " +
-                                       std::to_string(Y.total) + " bytes this pair needs");
-    hipStream_t s = (hipStream_t)stream;
+                                       std::to_string(need) + " bytes this batch needs");
     PGM_HIP(c, hipSetDevice(c->device));
-    uint8_t* ws = c->ws;
+    uint8_t* ws = c->ws;                          // shared slice
+    uint8_t* pw0 = c->ws + Y.shared_bytes;        // pair 0's slice
+    const long long zs = (long long)Y.pair_bytes;
     unsigned long long* nev = (unsigned long long*)out_n_evals;
     // with profiling on, every launch is bracketed by two events on the caller's stream
     auto event = [&](hipEvent_t* ev) -> hipError_t {
@@ -318,26 +361,41 @@ pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const 
         if (e == hipSuccess) c->recs.push_back(r);
         return e;
     };
-    auto kcount = [&](int kind) { return c->prof ? c->prof_evals + kind : (unsigned long long*)nullptr; };
+    // evaluation counts: each matching launch stores one count per work-group into its kind's
+    // table (per pair); k_count adds them up at the end
+    const bool counting = nev || c->prof;
+    long long cnt_off[4] = {0, 0, 0, 0};
+    auto ctable = [&](int kind, long long blocks) -> uint32_t* {
+        if (!counting) return nullptr;
+        uint32_t* t = (uint32_t*)(pw0 + Y.cnt[kind]) + cnt_off[kind];
+        cnt_off[kind] += blocks;
+        return t;
+    };
 
     // image pyramids and gradient pyramids of both images (Sec. III-D, III-A)
     const uint8_t* lvl[2] = {img1, img2};
     int pitch = pitch_bytes;
+    long long src_zs = image_stride_bytes;
     for (int l = 0; l < Y.L; l++) {
         if (l > 0) {
-            uint8_t* d0 = ws + Y.pyr[0][l];
-            uint8_t* d1 = ws + Y.pyr[1][l];
-            PGM_HIP(c, timed(PGM_K_PYRAMID, [&] { return launch_pyr_down(lvl[0], lvl[1], pitch, Y.lw[l - 1], Y.lh[l - 1], d0, d1, s); }));
+            uint8_t* d0 = pw0 + Y.pyr[0][l];
+            uint8_t* d1 = pw0 + Y.pyr[1][l];
+            PGM_HIP(c, timed(PGM_K_PYRAMID, [&] {
+                           return launch_pyr_down(lvl[0], lvl[1], src_zs, pitch, Y.lw[l - 1], Y.lh[l - 1], d0, d1, zs,
+                                                  npairs, s);
+                       }));
             lvl[0] = d0; lvl[1] = d1;
             pitch = Y.lw[l] * 3;
+            src_zs = zs;
         }
         PGM_HIP(c, timed(PGM_K_GRADIENT, [&] {
-                       return launch_gradient(lvl[0], lvl[1], pitch, Y.lw[l], Y.lh[l], ws + Y.grad[0][l],
-                                              ws + Y.grad[1][l], p->color == PGM_GRAY, p->sobel_ksize, Y.f32, s);
+                       return launch_gradient(lvl[0], lvl[1], src_zs, pitch, Y.lw[l], Y.lh[l], pw0 + Y.grad[0][l],
+                                              pw0 + Y.grad[1][l], zs, npairs, p->color == PGM_GRAY, p->sobel_ksize,
+                                              Y.f32, s);
                    }));
     }
 
-    // every random number of the pair
+    // every random number, shared by the pairs (they depend only on the parameters)
     RngArgs ra;
     memset(&ra, 0, sizeof ra);
     ra.nstages = Y.nst;
@@ -371,13 +429,13 @@ pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const 
     };
     auto field = [&](int d, int l) {
         Field f;
-        f.disp = (uint32_t*)(ws + Y.disp[d][l]);
-        f.dist = (uint32_t*)(ws + Y.dist[d][l]);
-        f.flags = ws + Y.flags[d][l];
+        f.disp = (uint32_t*)(pw0 + Y.disp[d][l]);
+        f.dist = (uint32_t*)(pw0 + Y.dist[d][l]);
+        f.flags = pw0 + Y.flags[d][l];
         return f;
     };
     auto gorigin = [&](int im, int l) {
-        return (const void*)(ws + Y.grad[im][l] + ((size_t)PAD * (Y.lw[l] + 2 * PAD) + PAD) * Y.C2 * Y.esize);
+        return (const void*)(pw0 + Y.grad[im][l] + ((size_t)PAD * (Y.lw[l] + 2 * PAD) + PAD) * Y.C2 * Y.esize);
     };
     auto dirargs = [&](int d, int l, int k) {
         DirArgs a;
@@ -389,9 +447,14 @@ pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const 
         a.P = d == 0 ? p->patch_fwd : p->patch_bwd;
         return a;
     };
-    // both directions share a launch when their patch sides select the same kernel variant
-    auto variant = [](int P) { return P == 8 ? 0 : P < 8 ? 1 : P == 16 ? 2 : 3; };
     const bool shared = variant(p->patch_fwd) == variant(p->patch_bwd);
+    auto batch = [&](int nd) {
+        Batch b;
+        b.npairs = npairs;
+        b.ndir = nd;
+        b.zs = zs;
+        return b;
+    };
 
     int rec_valid[PGM_MAX_LEVELS] = {0};
     for (int k = 0; k < Y.nst; k++) {
@@ -406,11 +469,11 @@ pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const 
                 memset(&a, 0, sizeof a);
                 for (int q = 0; q < nd; q++) a.d[q] = dirargs(d0 + q, l, k);
                 a.g = g;
+                a.b = batch(nd);
                 a.exhaustive = p->init_mode == PGM_INIT_EXHAUSTIVE;
                 a.R = Y.R_top;
-                a.n_evals = nev;
-                a.n_evals2 = kcount(PGM_K_INIT);
-                PGM_HIP(c, timed(PGM_K_INIT, [&] { return launch_init(a, Y.C2, Y.f32, nd, s); }));
+                a.cnt = ctable(CNT_INIT, (long long)nd * match_blocks(g.nx * g.ny, a.d[0].P));
+                PGM_HIP(c, timed(PGM_K_INIT, [&] { return launch_init(a, Y.C2, Y.f32, s); }));
             } else {
                 TransArgs a;
                 memset(&a, 0, sizeof a);
@@ -421,14 +484,15 @@ pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const 
                 }
                 a.g = g;
                 a.gs = geo(src);
+                a.b = batch(nd);
                 a.carry_record = enter != ENTER_DOWN_F;
-                a.n_evals = nev;
+                const long long nb = (long long)nd * match_blocks(g.nx * g.ny, a.d[0].P);
                 if (enter == ENTER_UP_FO) {
-                    a.n_evals2 = kcount(PGM_K_UP);
-                    PGM_HIP(c, timed(PGM_K_UP, [&] { return launch_up(a, Y.C2, Y.f32, nd, s); }));
+                    a.cnt = ctable(CNT_UP, nb);
+                    PGM_HIP(c, timed(PGM_K_UP, [&] { return launch_up(a, Y.C2, Y.f32, s); }));
                 } else {
-                    a.n_evals2 = kcount(PGM_K_DOWN);
-                    PGM_HIP(c, timed(PGM_K_DOWN, [&] { return launch_down(a, Y.C2, Y.f32, nd, s); }));
+                    a.cnt = ctable(CNT_DOWN, nb);
+                    PGM_HIP(c, timed(PGM_K_DOWN, [&] { return launch_down(a, Y.C2, Y.f32, s); }));
                 }
             }
         }
@@ -442,18 +506,19 @@ pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const 
                     memset(&a, 0, sizeof a);
                     for (int q = 0; q < nd; q++) a.d[q] = dirargs(d0 + q, l, k);
                     a.g = g;
+                    a.b = batch(nd);
                     a.t = t;
                     a.colour = colour;
                     a.nI = Y.st_nI[k];
-                    a.n_evals = nev;
-                    a.n_evals2 = kcount(PGM_K_SWEEP);
-                    PGM_HIP(c, timed(PGM_K_SWEEP, [&] { return launch_sweep(a, Y.C2, Y.f32, nd, s); }));
+                    a.cnt = ctable(CNT_SWEEP, (long long)nd * sweep_blocks(g.nx, g.ny, a.d[0].P));
+                    PGM_HIP(c, timed(PGM_K_SWEEP, [&] { return launch_sweep(a, Y.C2, Y.f32, s); }));
                 }
         // Step 2-3
         CheckArgs ca;
         ca.f[0] = field(0, l);
         ca.f[1] = field(1, l);
         ca.g = g;
+        ca.b = batch(2);
         ca.fwd_bwd = p->fwd_bwd;
         ca.tau2 = p->consistency_px * p->consistency_px;
         ca.rec_valid = enter == ENTER_DOWN_FO || enter == ENTER_UP_FO;
@@ -462,13 +527,42 @@ pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const 
     }
 
     // level-0 matches on the grid (Sec. III-G)
-    const Geo g0 = geo(0);
-    PGM_HIP(c, timed(PGM_K_OUTPUT, [&] { return launch_output(field(0, 0), g0, out_fwd, s); }));
-    if (out_bwd) PGM_HIP(c, timed(PGM_K_OUTPUT, [&] { return launch_output(field(1, 0), g0, out_bwd, s); }));
-    if (out_compact || out_n_inliers)
-        PGM_HIP(c, timed(PGM_K_COMPACT, [&] {
-                       return launch_compact(out_fwd, g0.nx * g0.ny, out_compact, out_n_inliers, s);
-                   }));
+    const bool compact = out_compact || out_n_inliers;
+    OutArgs oa;
+    memset(&oa, 0, sizeof oa);
+    oa.g = geo(0);
+    oa.b = batch(1);
+    oa.f = field(0, 0);
+    oa.out = out_fwd;
+    oa.blockcnt = compact ? (uint32_t*)(pw0 + Y.blockcnt) : nullptr;
+    PGM_HIP(c, timed(PGM_K_OUTPUT, [&] { return launch_output(oa, s); }));
+    if (out_bwd) {
+        OutArgs ob = oa;
+        ob.f = field(1, 0);
+        ob.out = out_bwd;
+        ob.blockcnt = nullptr;
+        PGM_HIP(c, timed(PGM_K_OUTPUT, [&] { return launch_output(ob, s); }));
+    }
+    if (compact) {
+        oa.dense = out_fwd;
+        oa.compact = out_compact;
+        oa.n_out = out_n_inliers;
+        PGM_HIP(c, timed(PGM_K_COMPACT, [&] { return launch_compact(oa, s); }));
+    }
+    if (counting) {
+        CountArgs ca;
+        const int kinds[4] = {PGM_K_INIT, PGM_K_DOWN, PGM_K_UP, PGM_K_SWEEP};
+        for (int k = 0; k < 4; k++) {
+            ca.table[k] = (const uint32_t*)(pw0 + Y.cnt[k]);
+            ca.n[k] = cnt_off[k];
+            ca.kind[k] = kinds[k];
+        }
+        ca.npairs = npairs;
+        ca.zs = zs;
+        ca.user = nev;
+        ca.prof = c->prof ? c->prof_evals : nullptr;
+        PGM_HIP(c, launch_count(ca, s));
+    }
 
     c->have_last = true;
     c->last = Y;
@@ -479,6 +573,29 @@ pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const 
     c->last_pitch = pitch_bytes;
     memcpy(c->rec_valid, rec_valid, sizeof rec_valid);
     return PGM_OK;
+}
+
+pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const uint8_t* img2,
+                     int32_t w, int32_t h, int32_t pitch_bytes, pgm_match_t* out_fwd,
+                     pgm_match_t* out_bwd, int32_t* out_n_inliers, pgm_match_t* out_compact,
+                     uint64_t* out_n_evals, void* stream)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    if (!c) return PGM_EINVAL;
+    return match_impl(c, p, 1, img1, img2, w, h, pitch_bytes, 0, out_fwd, out_bwd, out_n_inliers, out_compact,
+                      out_n_evals, (hipStream_t)stream);
+}
+
+pgm_status pgm_match_batch(void* ctx, const pgm_params* p, int32_t n_pairs, const uint8_t* img1,
+                           const uint8_t* img2, int32_t w, int32_t h, int32_t pitch_bytes,
+                           int64_t image_stride_bytes, pgm_match_t* out_fwd, pgm_match_t* out_bwd,
+                           int32_t* out_n_inliers, pgm_match_t* out_compact, uint64_t* out_n_evals,
+                           void* stream)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    if (!c) return PGM_EINVAL;
+    return match_impl(c, p, n_pairs, img1, img2, w, h, pitch_bytes, image_stride_bytes, out_fwd, out_bwd,
+                      out_n_inliers, out_compact, out_n_evals, (hipStream_t)stream);
 }
 
 static pgm_status dump_prep(pgm_ctx_s* c, int level)
@@ -503,9 +620,9 @@ pgm_status pgm_dump_level(void* ctx, int32_t level, int32_t dir, int32_t* host_o
     uint32_t* disp = (uint32_t*)&buf[0];
     uint32_t* dist = disp + n;
     uint8_t* flags = (uint8_t*)(dist + n);
-    PGM_HIP(c, hipMemcpy(disp, c->ws + Y.disp[dir][level], n * 4, hipMemcpyDeviceToHost));
-    PGM_HIP(c, hipMemcpy(dist, c->ws + Y.dist[dir][level], n * 4, hipMemcpyDeviceToHost));
-    PGM_HIP(c, hipMemcpy(flags, c->ws + Y.flags[dir][level], n, hipMemcpyDeviceToHost));
+    PGM_HIP(c, hipMemcpy(disp, c->ws + Y.shared_bytes + Y.disp[dir][level], n * 4, hipMemcpyDeviceToHost));
+    PGM_HIP(c, hipMemcpy(dist, c->ws + Y.shared_bytes + Y.dist[dir][level], n * 4, hipMemcpyDeviceToHost));
+    PGM_HIP(c, hipMemcpy(flags, c->ws + Y.shared_bytes + Y.flags[dir][level], n, hipMemcpyDeviceToHost));
     for (size_t s = 0; s < n; s++) {
         const bool init = disp[s] != UNINIT;
         host_out[4 * s + 0] = init ? (int32_t)(int16_t)(disp[s] & 0xFFFF) : 0;
@@ -527,7 +644,7 @@ pgm_status pgm_dump_gradient(void* ctx, int32_t level, int32_t image, void* host
     const int w = Y.lw[level], h = Y.lh[level], pw = w + 2 * PAD;
     const size_t row = (size_t)w * Y.C2 * Y.esize;
     for (int y = 0; y < h; y++) {
-        const uint8_t* src = c->ws + Y.grad[image][level] + (((size_t)(y + PAD) * pw + PAD) * Y.C2) * Y.esize;
+        const uint8_t* src = c->ws + Y.shared_bytes + Y.grad[image][level] + (((size_t)(y + PAD) * pw + PAD) * Y.C2) * Y.esize;
         PGM_HIP(c, hipMemcpy((uint8_t*)host_out + y * row, src, row, hipMemcpyDeviceToHost));
     }
     if (!Y.f32) {
@@ -549,7 +666,7 @@ pgm_status pgm_dump_pyramid(void* ctx, int32_t level, int32_t image, uint8_t* ho
         PGM_HIP(c, hipMemcpy2D(host_out, (size_t)w * 3, c->last_img[image], c->last_pitch, (size_t)w * 3, h,
                                hipMemcpyDeviceToHost));
     } else {
-        PGM_HIP(c, hipMemcpy(host_out, c->ws + Y.pyr[image][level], (size_t)w * h * 3, hipMemcpyDeviceToHost));
+        PGM_HIP(c, hipMemcpy(host_out, c->ws + Y.shared_bytes + Y.pyr[image][level], (size_t)w * h * 3, hipMemcpyDeviceToHost));
     }
     return PGM_OK;
 }

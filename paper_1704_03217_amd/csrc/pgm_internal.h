@@ -49,35 +49,56 @@ struct Geo {
     int stride, off;       // grid spacing and first seed position
 };
 
+// Pairs of one batch: every per-pair workspace pointer of the kernel arguments points into
+// pair 0's slice; pair z's is `zs` bytes further (the random-number table is shared).
+struct Batch {
+    int npairs;
+    int ndir;              // directions covered by the launch (1 or 2)
+    long long zs;          // workspace bytes per pair
+};
+
 struct SweepArgs {
     DirArgs d[2];
     Geo g;
+    Batch b;
     int t, colour, nI;
-    unsigned long long* n_evals;     // caller's counter (or null)
-    unsigned long long* n_evals2;    // per-kind profiling counter (or null)
+    uint32_t* cnt;         // per-block evaluation counts of this launch, pair 0 (or null)
 };
 
 struct InitArgs {
     DirArgs d[2];
     Geo g;
+    Batch b;
     int exhaustive, R;
-    unsigned long long* n_evals;
-    unsigned long long* n_evals2;
+    uint32_t* cnt;
 };
 
 struct TransArgs {         // level-down (to the finer level) or level-up (to the coarser)
     DirArgs d[2];          // the level being entered
     Field src[2];          // the level the field comes from
     Geo g, gs;             // geometry of the entered level and of the source level
+    Batch b;
     int carry_record;
-    unsigned long long* n_evals;
-    unsigned long long* n_evals2;
+    uint32_t* cnt;
 };
 
 struct CheckArgs {
     Field f[2];
     Geo g;
+    Batch b;
     int fwd_bwd, tau2, rec_valid;
+};
+
+struct OutArgs {
+    Field f;               // level-0 field of one direction, pair 0
+    Geo g;
+    Batch b;
+    pgm_match_t* out;      // pair z writes out + z * nx * ny
+    uint32_t* blockcnt;    // per-block inlier counts, pair 0 (or null)
+    // compaction
+    const pgm_match_t* dense;
+    pgm_match_t* compact;  // pair z writes compact + z * nx * ny (or null)
+    int32_t* n_out;        // pair z writes n_out[z] (or null)
 };
 
 struct RngStage {
@@ -95,19 +116,44 @@ struct RngArgs {
     uint32_t key0, key1;
 };
 
+struct CountArgs {
+    static constexpr int KINDS = 4;      // init, down, up, sweep
+    const uint32_t* table[KINDS];        // pair 0
+    long long n[KINDS];
+    int npairs;
+    long long zs;
+    int kind[KINDS];                     // PGM_K_* of each table
+    unsigned long long* user;            // caller's counter (or null)
+    unsigned long long* prof;            // PGM_K_KINDS profiling counters (or null)
+};
+
+// Work-groups of a matching kernel: 256 threads, one seed per 8 lanes (patch side <= 8) or
+// per 16 lanes (side <= 16).
+inline int match_blocks(int groups, int P)
+{
+    const int gpb = 256 / (P <= 8 ? 8 : 16);
+    return (groups + gpb - 1) / gpb;
+}
+
+// Work-groups of one half-sweep launch per direction and pair.
+inline int sweep_blocks(int nx, int ny, int P) { return match_blocks(ny * ((nx + 1) / 2), P); }
+
 // Launch wrappers (pgm_kernels.hip). Each returns hipSuccess or the launch error.
-hipError_t launch_pyr_down(const uint8_t* src0, const uint8_t* src1, int pitch, int w, int h,
-                           uint8_t* dst0, uint8_t* dst1, hipStream_t s);
-hipError_t launch_gradient(const uint8_t* img0, const uint8_t* img1, int pitch, int w, int h,
-                           void* G0, void* G1, int gray, int ksize, int f32, hipStream_t s);
+// Per-image pointers are those of pair 0; pair z's source is src_zs bytes further and its
+// destination dst_zs bytes further.
+hipError_t launch_pyr_down(const uint8_t* src0, const uint8_t* src1, long long src_zs, int pitch, int w, int h,
+                           uint8_t* dst0, uint8_t* dst1, long long dst_zs, int npairs, hipStream_t s);
+hipError_t launch_gradient(const uint8_t* img0, const uint8_t* img1, long long src_zs, int pitch, int w, int h,
+                           void* G0, void* G1, long long dst_zs, int npairs, int gray, int ksize, int f32,
+                           hipStream_t s);
 hipError_t launch_rng(const RngArgs& a, hipStream_t s);
-hipError_t launch_init(const InitArgs& a, int C2, int f32, int ndir, hipStream_t s);
-hipError_t launch_sweep(const SweepArgs& a, int C2, int f32, int ndir, hipStream_t s);
-hipError_t launch_down(const TransArgs& a, int C2, int f32, int ndir, hipStream_t s);
-hipError_t launch_up(const TransArgs& a, int C2, int f32, int ndir, hipStream_t s);
+hipError_t launch_init(const InitArgs& a, int C2, int f32, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs& a, int C2, int f32, hipStream_t s);
+hipError_t launch_down(const TransArgs& a, int C2, int f32, hipStream_t s);
+hipError_t launch_up(const TransArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);
-hipError_t launch_output(const Field& f, const Geo& g, pgm_match_t* out, hipStream_t s);
-hipError_t launch_compact(const pgm_match_t* dense, int n, pgm_match_t* out, int32_t* n_out,
-                          hipStream_t s);
+hipError_t launch_output(const OutArgs& a, hipStream_t s);
+hipError_t launch_compact(const OutArgs& a, hipStream_t s);
+hipError_t launch_count(const CountArgs& a, hipStream_t s);
 
 }  // namespace pgm

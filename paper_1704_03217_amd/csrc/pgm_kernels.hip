@@ -101,7 +101,10 @@ __device__ __forceinline__ double group_sum(double v)
 }
 
 // ---------------------------------------------------------------------------------------
-// one lane's patch row: the first image's row stays in registers, candidate rows stream in
+// one lane's patch column: lane c of a seed's group holds pixel column c of every row of the
+// seed's first-image patch in registers and streams the same column of candidate patches.
+// The group's lanes read each patch row as one contiguous segment (96 bytes for 8 RGB
+// gradient pixels), so a wave's load touches few cache lines.
 // ---------------------------------------------------------------------------------------
 
 // Integer gradients, biased u16, two per dword; C2 channels per pixel (C2 even).
@@ -109,30 +112,33 @@ __device__ __forceinline__ double group_sum(double v)
 // so one instruction covers two gradient values of a packed dword.
 template <int C2, int PMAX, bool FIXED>
 struct IntRow {
-    static constexpr int NW = PMAX * C2 / 2;
-    using Elem = uint32_t;
+    static constexpr int W3 = C2 / 2;   // dwords per pixel
     using Acc = uint32_t;
-    uint32_t a[NW];
+    uint32_t a[PMAX][W3];
 
-    __device__ __forceinline__ void load(const uint32_t* row, int P)
+    // base: this lane's pixel of the patch's first row; pitch: dwords per image row
+    __device__ __forceinline__ void load(const uint32_t* base, ptrdiff_t pitch, int P)
     {
-        const int nw = P * (C2 / 2);
 #pragma unroll
-        for (int k = 0; k < NW; k++) a[k] = (FIXED || k < nw) ? row[k] : 0u;
+        for (int y = 0; y < PMAX; y++)
+#pragma unroll
+            for (int w = 0; w < W3; w++) a[y][w] = (FIXED || y < P) ? base[y * pitch + w] : 0u;
     }
-    __device__ __forceinline__ uint32_t sad(const uint32_t* row, int P) const
+    __device__ __forceinline__ uint32_t sad(const uint32_t* base, ptrdiff_t pitch, int P) const
     {
-        const int nw = P * (C2 / 2);
         uint32_t acc = 0;
 #pragma unroll
-        for (int k = 0; k < NW; k++)
-            if (FIXED || k < nw) acc = __builtin_amdgcn_sad_u16(a[k], row[k], acc);
+        for (int y = 0; y < PMAX; y++)
+            if (FIXED || y < P)
+#pragma unroll
+                for (int w = 0; w < W3; w++) acc = __builtin_amdgcn_sad_u16(a[y][w], base[y * pitch + w], acc);
         return acc;
     }
     static __device__ __forceinline__ const uint32_t* at(const void* G, const Geo& g, int x, int y)
     {
-        return (const uint32_t*)G + ((ptrdiff_t)y * g.pw + x) * (C2 / 2);
+        return (const uint32_t*)G + ((ptrdiff_t)y * g.pw + x) * W3;
     }
+    static __device__ __forceinline__ ptrdiff_t pitch(const Geo& g) { return (ptrdiff_t)g.pw * W3; }
     template <int LPS>
     static __device__ __forceinline__ uint32_t finish(uint32_t partial) { return group_sum<LPS>(partial); }
 };
@@ -142,29 +148,31 @@ struct IntRow {
 // the rounded float result does not depend on the order of summation.
 template <int C2, int PMAX, bool FIXED>
 struct F32Row {
-    static constexpr int NE = PMAX * C2;
     using Acc = double;
-    double a[NE];
+    double a[PMAX][C2];
 
-    __device__ __forceinline__ void load(const float* row, int P)
+    __device__ __forceinline__ void load(const float* base, ptrdiff_t pitch, int P)
     {
-        const int ne = P * C2;
 #pragma unroll
-        for (int k = 0; k < NE; k++) a[k] = (FIXED || k < ne) ? (double)row[k] : 0.0;
+        for (int y = 0; y < PMAX; y++)
+#pragma unroll
+            for (int c = 0; c < C2; c++) a[y][c] = (FIXED || y < P) ? (double)base[y * pitch + c] : 0.0;
     }
-    __device__ __forceinline__ double sad(const float* row, int P) const
+    __device__ __forceinline__ double sad(const float* base, ptrdiff_t pitch, int P) const
     {
-        const int ne = P * C2;
         double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < NE; k++)
-            if (FIXED || k < ne) acc += fabs((double)row[k] - a[k]);
+        for (int y = 0; y < PMAX; y++)
+            if (FIXED || y < P)
+#pragma unroll
+                for (int c = 0; c < C2; c++) acc += fabs((double)base[y * pitch + c] - a[y][c]);
         return acc;
     }
     static __device__ __forceinline__ const float* at(const void* G, const Geo& g, int x, int y)
     {
         return (const float*)G + ((ptrdiff_t)y * g.pw + x) * C2;
     }
+    static __device__ __forceinline__ ptrdiff_t pitch(const Geo& g) { return (ptrdiff_t)g.pw * C2; }
     template <int LPS>
     static __device__ __forceinline__ uint32_t finish(double partial)
     {
@@ -176,14 +184,15 @@ template <int C2, int PMAX, bool FIXED, bool F32>
 using RowT = typename std::conditional<F32, F32Row<C2, PMAX, FIXED>, IntRow<C2, PMAX, FIXED>>::type;
 
 // Patch distance of Eq. 3 (absolute differences) between the patch held by the group and
-// the patch of the other image at (qx, qy); every lane of the group gets the result.
+// the patch of the other image at (qx, qy); every lane of the group gets the result. Lanes
+// past the patch side read a valid column and add nothing.
 template <class Row, int LPS>
 __device__ __forceinline__ uint32_t patch_cost(const Row& A, const void* Gb, const Geo& g, int P,
                                                int r, int qx, int qy)
 {
     const int half = P >> 1;
-    const int rr = r < P ? r : P - 1;
-    typename Row::Acc part = A.sad(Row::at(Gb, g, qx - half, qy + rr - half), P);
+    const int rc = r < P ? r : P - 1;
+    typename Row::Acc part = A.sad(Row::at(Gb, g, qx - half + rc, qy - half), Row::pitch(g), P);
     if (r >= P) part = typename Row::Acc(0);
     return Row::template finish<LPS>(part);
 }
@@ -192,22 +201,67 @@ template <class Row>
 __device__ __forceinline__ void load_own(Row& A, const void* Ga, const Geo& g, int P, int r, int px, int py)
 {
     const int half = P >> 1;
-    const int rr = r < P ? r : P - 1;
-    A.load(Row::at(Ga, g, px - half, py + rr - half), P);
+    const int rc = r < P ? r : P - 1;
+    A.load(Row::at(Ga, g, px - half + rc, py - half), Row::pitch(g), P);
 }
 
-// sum per-group evaluation counts over the wave and add them to the global counters
-__device__ __forceinline__ void count_evals(unsigned long long* n1, unsigned long long* n2, uint32_t nev,
-                                            bool leader)
+// Logical block of a 1-D launch over nbx x ndir x npairs work-groups. Consecutive work-group
+// ids are dealt round robin to the 8 XCDs; this remap hands every XCD one contiguous range of
+// logical ids (a band of seeds of one pair, or whole pairs of a batch), so each XCD's L2
+// caches a compact part of the gradient images.
+struct LBlock {
+    int x, dir, z;
+};
+__device__ __forceinline__ LBlock logical_block(int nbx, int ndir)
 {
-    if (!n1 && !n2) return;
+    const int N = gridDim.x, L = blockIdx.x;
+    const int j = L & 7, q = (N + 7) >> 3, r = N & 7;
+    int id = (r == 0 || j < r) ? j * q + (L >> 3) : r * q + (j - r) * (q - 1) + (L >> 3);
+    LBlock b;
+    b.x = id % nbx;
+    id /= nbx;
+    b.dir = id % ndir;
+    b.z = id / ndir;
+    return b;
+}
+
+template <class T>
+__device__ __forceinline__ T* zoff(T* p, size_t off)
+{
+    return p ? (T*)((const char*)p + off) : p;
+}
+
+__device__ __forceinline__ Field pair_field(const Field& f, size_t off)
+{
+    Field r;
+    r.disp = zoff(f.disp, off);
+    r.dist = zoff(f.dist, off);
+    r.flags = zoff(f.flags, off);
+    return r;
+}
+
+__device__ __forceinline__ DirArgs pair_dir(const DirArgs& d, size_t off)
+{
+    DirArgs r = d;
+    r.Ga = zoff(d.Ga, off);
+    r.Gb = zoff(d.Gb, off);
+    r.f = pair_field(d.f, off);
+    return r;   // the random-number table is shared by all pairs
+}
+
+// Sum the per-group evaluation counts of the work-group and store the total in its slot of
+// the launch's count table (no atomics: one kernel adds the slots up at the end). Every
+// thread of the block must call it.
+__device__ __forceinline__ void count_evals(uint32_t* cnt, int slot, uint32_t nev, bool leader)
+{
+    if (!cnt) return;   // uniform over the launch
+    __shared__ uint32_t wsum[4];
     uint32_t v = leader ? nev : 0u;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0 && v) {
-        if (n1) atomicAdd(n1, (unsigned long long)v);
-        if (n2) atomicAdd(n2, (unsigned long long)v);
-    }
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[slot] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -221,9 +275,12 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     constexpr int LPS = PMAX;
     constexpr int GPB = 256 / LPS;
     const Geo& g = a.g;
-    const DirArgs& D = a.d[blockIdx.y];
+    const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
+    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
+    const DirArgs D = pair_dir(a.d[lb.dir], zo);
     const int r = threadIdx.x % LPS;
-    const int gid = blockIdx.x * GPB + threadIdx.x / LPS;
+    const int gid = lb.x * GPB + threadIdx.x / LPS;
     const int hx = (g.nx + 1) >> 1;
     const int j = gid / hx;
     const int i = 2 * (gid - j * hx) + ((a.colour + j) & 1);
@@ -275,7 +332,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             D.f.dist[s] = cd;
         }
     }
-    count_evals(a.n_evals, a.n_evals2, nev, r == 0);
+    count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, r == 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -290,9 +347,12 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
     constexpr int LPS = PMAX;
     constexpr int GPB = 256 / LPS;
     const Geo& g = a.g;
-    const DirArgs& D = a.d[blockIdx.y];
+    const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
+    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
+    const DirArgs D = pair_dir(a.d[lb.dir], zo);
     const int r = threadIdx.x % LPS;
-    const int s = blockIdx.x * GPB + threadIdx.x / LPS;
+    const int s = lb.x * GPB + threadIdx.x / LPS;
     uint32_t nev = 0;
     if (s < g.nx * g.ny) {
         const int i = s % g.nx, j = s / g.nx;
@@ -324,7 +384,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
             D.f.flags[s] = 0;
         }
     }
-    count_evals(a.n_evals, a.n_evals2, nev, r == 0);
+    count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, r == 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -339,10 +399,13 @@ __global__ __launch_bounds__(256) void k_down(TransArgs a)
     constexpr int LPS = PMAX;
     constexpr int GPB = 256 / LPS;
     const Geo& g = a.g;
-    const DirArgs& D = a.d[blockIdx.y];
-    const Field& S = a.src[blockIdx.y];
+    const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
+    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
+    const DirArgs D = pair_dir(a.d[lb.dir], zo);
+    const Field S = pair_field(a.src[lb.dir], zo);
     const int r = threadIdx.x % LPS;
-    const int s = blockIdx.x * GPB + threadIdx.x / LPS;
+    const int s = lb.x * GPB + threadIdx.x / LPS;
     uint32_t nev = 0;
     if (s < g.nx * g.ny) {
         const int i = s % g.nx, j = s / g.nx;
@@ -364,7 +427,7 @@ __global__ __launch_bounds__(256) void k_down(TransArgs a)
             D.f.flags[s] = (a.carry_record && par_inl) ? ST_REC : 0;
         }
     }
-    count_evals(a.n_evals, a.n_evals2, nev, r == 0);
+    count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, r == 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -387,10 +450,13 @@ __global__ __launch_bounds__(256) void k_up(TransArgs a)
     constexpr int GPB = 256 / LPS;
     const Geo& g = a.g;     // coarse level being entered
     const Geo& f = a.gs;    // finer source level
-    const DirArgs& D = a.d[blockIdx.y];
-    const Field& S = a.src[blockIdx.y];
+    const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
+    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
+    const DirArgs D = pair_dir(a.d[lb.dir], zo);
+    const Field S = pair_field(a.src[lb.dir], zo);
     const int r = threadIdx.x % LPS;
-    const int s = blockIdx.x * GPB + threadIdx.x / LPS;
+    const int s = lb.x * GPB + threadIdx.x / LPS;
     uint32_t nev = 0;
     if (s < g.nx * g.ny) {
         const int ci = s % g.nx, cj = s / g.nx;
@@ -423,7 +489,7 @@ __global__ __launch_bounds__(256) void k_up(TransArgs a)
             D.f.flags[s] = cnt > 0 ? ST_REC : 0;
         }
     }
-    count_evals(a.n_evals, a.n_evals2, nev, r == 0);
+    count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, r == 0);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -435,8 +501,9 @@ __global__ __launch_bounds__(256) void k_check(CheckArgs a)
     const Geo& g = a.g;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.nx * g.ny) return;
-    const Field& F = a.f[blockIdx.y];
-    const Field& O = a.f[1 - blockIdx.y];
+    const size_t zo = (size_t)blockIdx.z * (size_t)a.b.zs;
+    const Field F = pair_field(a.f[blockIdx.y], zo);
+    const Field O = pair_field(a.f[1 - blockIdx.y], zo);
     const uint32_t d = F.disp[s];
     bool ok = d != UNINIT;
     if (ok && a.fwd_bwd) {
@@ -458,67 +525,106 @@ __global__ __launch_bounds__(256) void k_check(CheckArgs a)
 // output on the level-0 grid and the compaction of forward inliers (Sec. III-G)
 // ---------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_output(Field f, Geo g, pgm_match_t* out)
+__global__ __launch_bounds__(256) void k_output(OutArgs a)
 {
+    const Geo& g = a.g;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= g.nx * g.ny) return;
-    const int i = s % g.nx, j = s / g.nx;
-    const uint32_t d = f.disp[s];
-    const uint8_t fl = f.flags[s];
-    pgm_match_t m;
-    m.x1 = grid_pos(i, g.w, g);
-    m.y1 = grid_pos(j, g.h, g);
-    const bool init = d != UNINIT;
-    m.x2 = m.x1 + (init ? d_x(d) : 0);
-    m.y2 = m.y1 + (init ? d_y(d) : 0);
-    m.dist = init ? (int32_t)f.dist[s] : (int32_t)NO_DIST;
-    m.flags = (init ? PGM_FLAG_INIT : 0u) | ((fl & ST_INL) ? PGM_FLAG_INLIER : 0u) |
-              ((fl & ST_REC) ? PGM_FLAG_RECORD : 0u);
-    out[s] = m;
+    const int n = g.nx * g.ny;
+    const size_t zo = (size_t)blockIdx.z * (size_t)a.b.zs;
+    const Field f = pair_field(a.f, zo);
+    pgm_match_t* out = a.out + (size_t)blockIdx.z * n;
+    bool inl = false;
+    if (s < n) {
+        const int i = s % g.nx, j = s / g.nx;
+        const uint32_t d = f.disp[s];
+        const uint8_t fl = f.flags[s];
+        pgm_match_t m;
+        m.x1 = grid_pos(i, g.w, g);
+        m.y1 = grid_pos(j, g.h, g);
+        const bool init = d != UNINIT;
+        m.x2 = m.x1 + (init ? d_x(d) : 0);
+        m.y2 = m.y1 + (init ? d_y(d) : 0);
+        m.dist = init ? (int32_t)f.dist[s] : (int32_t)NO_DIST;
+        m.flags = (init ? PGM_FLAG_INIT : 0u) | ((fl & ST_INL) ? PGM_FLAG_INLIER : 0u) |
+                  ((fl & ST_REC) ? PGM_FLAG_RECORD : 0u);
+        out[s] = m;
+        inl = (fl & ST_INL) != 0;
+    }
+    if (a.blockcnt) {   // uniform over the launch
+        const int c = __syncthreads_count(inl);
+        if (threadIdx.x == 0) zoff(a.blockcnt, zo)[blockIdx.x] = (uint32_t)c;
+    }
 }
 
-// single work-group stable compaction: each thread owns a contiguous run of seeds
-__global__ __launch_bounds__(1024) void k_compact(const pgm_match_t* dense, int n, pgm_match_t* out,
-                                                 int32_t* n_out)
+// Stable compaction of the forward inliers: block b owns the same 256 seeds as block b of
+// k_output, starts at the sum of the inlier counts of the blocks before it and ranks its
+// inliers with wave ballots.
+__global__ __launch_bounds__(256) void k_compact(OutArgs a)
 {
-    __shared__ int wsum[16];
-    const int tid = threadIdx.x;
-    const int per = (n + 1023) / 1024;
-    const int b = min(n, tid * per), e = min(n, b + per);
-    int c = 0;
-    for (int s = b; s < e; s++) c += (dense[s].flags & PGM_FLAG_INLIER) ? 1 : 0;
-    // inclusive scan within the wave
-    const int lane = tid & 63, wv = tid >> 6;
-    int x = c;
+    __shared__ uint32_t part[4], wtot[4];
+    const int n = a.g.nx * a.g.ny;
+    const size_t zo = (size_t)blockIdx.z * (size_t)a.b.zs;
+    const uint32_t* blockcnt = zoff(a.blockcnt, zo);
+    const pgm_match_t* dense = a.dense + (size_t)blockIdx.z * n;
+    pgm_match_t* out = a.compact ? a.compact + (size_t)blockIdx.z * n : nullptr;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t v = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) v += blockcnt[b];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[wv] = x;
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    const bool inl = s < n && (dense[s].flags & PGM_FLAG_INLIER);
+    const unsigned long long mask = __ballot(inl);
+    if (lane == 0) { part[wv] = v; wtot[wv] = (uint32_t)__popcll(mask); }
     __syncthreads();
-    int before = 0;
-    for (int k = 0; k < wv; k++) before += wsum[k];
-    int pos = before + x - c;
-    if (out)
-        for (int s = b; s < e; s++)
-            if (dense[s].flags & PGM_FLAG_INLIER) out[pos++] = dense[s];
-    if (tid == 1023 && n_out) *n_out = before + x;
+    const uint32_t prefix = part[0] + part[1] + part[2] + part[3];
+    uint32_t before = 0;
+    for (int k = 0; k < wv; k++) before += wtot[k];
+    const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    if (inl && out) out[prefix + before + rank] = dense[s];
+    if (a.n_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+        a.n_out[blockIdx.z] = (int32_t)(prefix + wtot[0] + wtot[1] + wtot[2] + wtot[3]);
+}
+
+// Add up the count tables of a pair: per kernel kind (for profiling) and in total (for the
+// caller's counter). Blocks take strided slices; one atomic per block and kind.
+__global__ __launch_bounds__(256) void k_count(CountArgs a)
+{
+    __shared__ unsigned long long ws[4];
+    unsigned long long total = 0;
+    for (int k = 0; k < CountArgs::KINDS; k++) {
+        unsigned long long v = 0;
+        for (int z = 0; z < a.npairs; z++) {
+            const uint32_t* t = zoff(a.table[k], (size_t)z * (size_t)a.zs);
+            for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.n[k]; i += (long long)gridDim.x * 256)
+                v += t[i];
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+        __syncthreads();
+        const unsigned long long sum = ws[0] + ws[1] + ws[2] + ws[3];
+        __syncthreads();
+        if (threadIdx.x == 0 && a.prof && sum) atomicAdd(a.prof + a.kind[k], sum);
+        total += sum;
+    }
+    if (threadIdx.x == 0 && a.user && total) atomicAdd(a.user, total);
 }
 
 // ---------------------------------------------------------------------------------------
 // image pyramid (Sec. III-D): 5x5 binomial, decimation by 2, reflect-101 borders
 // ---------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_pyr(const uint8_t* src0, const uint8_t* src1, int pitch,
-                                             int w, int h, uint8_t* dst0, uint8_t* dst1)
+__global__ __launch_bounds__(256) void k_pyr(const uint8_t* src0, const uint8_t* src1, long long src_zs, int pitch,
+                                             int w, int h, uint8_t* dst0, uint8_t* dst1, long long dst_zs)
 {
     const int w2 = (w + 1) >> 1, h2 = (h + 1) >> 1;
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= w2 || y >= h2) return;
-    const uint8_t* src = blockIdx.z ? src1 : src0;
-    uint8_t* dst = blockIdx.z ? dst1 : dst0;
+    const size_t pair = blockIdx.z >> 1;
+    const uint8_t* src = ((blockIdx.z & 1) ? src1 : src0) + pair * (size_t)src_zs;
+    uint8_t* dst = ((blockIdx.z & 1) ? dst1 : dst0) + pair * (size_t)dst_zs;
     const int tap[5] = {1, 4, 6, 4, 1};
     int acc[3] = {0, 0, 0};
 #pragma unroll
@@ -547,8 +653,8 @@ __global__ __launch_bounds__(256) void k_pyr(const uint8_t* src0, const uint8_t*
 // ---------------------------------------------------------------------------------------
 
 template <int KS, bool GRAY, bool F32>
-__global__ __launch_bounds__(256) void k_gradient(const uint8_t* img0, const uint8_t* img1, int pitch,
-                                                  int w, int h, void* G0, void* G1)
+__global__ __launch_bounds__(256) void k_gradient(const uint8_t* img0, const uint8_t* img1, long long src_zs,
+                                                  int pitch, int w, int h, void* G0, void* G1, long long dst_zs)
 {
     constexpr int CH = GRAY ? 1 : 3;
     constexpr int C2 = 2 * CH;
@@ -556,8 +662,9 @@ __global__ __launch_bounds__(256) void k_gradient(const uint8_t* img0, const uin
     const int X = blockIdx.x * 64 + (threadIdx.x & 63);
     const int Y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (X >= pw || Y >= ph) return;
-    const uint8_t* img = blockIdx.z ? img1 : img0;
-    void* G = blockIdx.z ? G1 : G0;
+    const size_t pair = blockIdx.z >> 1;
+    const uint8_t* img = ((blockIdx.z & 1) ? img1 : img0) + pair * (size_t)src_zs;
+    void* G = zoff((blockIdx.z & 1) ? G1 : G0, pair * (size_t)dst_zs);
     const int x = clampi(X - PAD, 0, w - 1), y = clampi(Y - PAD, 0, h - 1);
     // smoothing and derivative taps of the size-KS Sobel operator
     const int sm3[3] = {1, 2, 1}, dv3[3] = {-1, 0, 1};
@@ -663,24 +770,25 @@ __global__ __launch_bounds__(256) void k_rng(RngArgs a)
 // launch wrappers
 // ---------------------------------------------------------------------------------------
 
-hipError_t launch_pyr_down(const uint8_t* src0, const uint8_t* src1, int pitch, int w, int h,
-                           uint8_t* dst0, uint8_t* dst1, hipStream_t s)
+hipError_t launch_pyr_down(const uint8_t* src0, const uint8_t* src1, long long src_zs, int pitch, int w, int h,
+                           uint8_t* dst0, uint8_t* dst1, long long dst_zs, int npairs, hipStream_t s)
 {
     const int w2 = (w + 1) / 2, h2 = (h + 1) / 2;
-    dim3 grid((w2 + 63) / 64, (h2 + 3) / 4, 2);
-    hipLaunchKernelGGL(k_pyr, grid, dim3(256), 0, s, src0, src1, pitch, w, h, dst0, dst1);
+    dim3 grid((w2 + 63) / 64, (h2 + 3) / 4, 2 * npairs);
+    hipLaunchKernelGGL(k_pyr, grid, dim3(256), 0, s, src0, src1, src_zs, pitch, w, h, dst0, dst1, dst_zs);
     return hipGetLastError();
 }
 
-hipError_t launch_gradient(const uint8_t* img0, const uint8_t* img1, int pitch, int w, int h,
-                           void* G0, void* G1, int gray, int ksize, int f32, hipStream_t s)
+hipError_t launch_gradient(const uint8_t* img0, const uint8_t* img1, long long src_zs, int pitch, int w, int h,
+                           void* G0, void* G1, long long dst_zs, int npairs, int gray, int ksize, int f32,
+                           hipStream_t s)
 {
-    dim3 grid((w + 2 * PAD + 63) / 64, (h + 2 * PAD + 3) / 4, 2);
-#define PGM_GRAD(KS, GR, F)                                                                     \
-    if (ksize == KS && !!gray == GR && !!f32 == F) {                                             \
-        hipLaunchKernelGGL((k_gradient<KS, GR, F>), grid, dim3(256), 0, s, img0, img1, pitch, w, \
-                           h, G0, G1);                                                           \
-        return hipGetLastError();                                                                \
+    dim3 grid((w + 2 * PAD + 63) / 64, (h + 2 * PAD + 3) / 4, 2 * npairs);
+#define PGM_GRAD(KS, GR, F)                                                                       \
+    if (ksize == KS && !!gray == GR && !!f32 == F) {                                               \
+        hipLaunchKernelGGL((k_gradient<KS, GR, F>), grid, dim3(256), 0, s, img0, img1, src_zs, pitch, w, \
+                           h, G0, G1, dst_zs);                                                     \
+        return hipGetLastError();                                                                  \
     }
     PGM_GRAD(3, false, false) PGM_GRAD(3, false, true) PGM_GRAD(3, true, false) PGM_GRAD(3, true, true)
     PGM_GRAD(5, false, false) PGM_GRAD(5, false, true) PGM_GRAD(5, true, false) PGM_GRAD(5, true, true)
@@ -698,13 +806,12 @@ hipError_t launch_rng(const RngArgs& a, hipStream_t s)
 
 // Kernel variants: patch side exactly 8 or 16 (fully unrolled rows), or any side up to 8 /
 // up to 16 with masked rows; 6 or 2 gradient channels; integer or float features.
-#define PGM_DISPATCH(KERNEL, ARGS, NGROUPS, NDIR)                                               \
+#define PGM_DISPATCH(KERNEL, ARGS, NGROUPS)                                               \
     do {                                                                                         \
         const int P = (ARGS).d[0].P;                                                             \
         const int pmax = P <= 8 ? 8 : 16;                                                        \
         const bool fixed = P == pmax;                                                            \
-        const int gpb = 256 / pmax;                                                              \
-        dim3 grid((unsigned)(((NGROUPS) + gpb - 1) / gpb), (unsigned)(NDIR));                    \
+        dim3 grid((unsigned)((long long)match_blocks((NGROUPS), P) * (ARGS).b.ndir * (ARGS).b.npairs)); \
         if ((NGROUPS) <= 0) return hipSuccess;                                                   \
         PGM_V(KERNEL, 6, 8, true) PGM_V(KERNEL, 6, 8, false) PGM_V(KERNEL, 6, 16, true)           \
         PGM_V(KERNEL, 6, 16, false) PGM_V(KERNEL, 2, 8, true) PGM_V(KERNEL, 2, 8, false)          \
@@ -719,24 +826,24 @@ hipError_t launch_rng(const RngArgs& a, hipStream_t s)
         return hipGetLastError();                                                                \
     }
 
-hipError_t launch_sweep(const SweepArgs& a, int C2, int f32, int ndir, hipStream_t s)
+hipError_t launch_sweep(const SweepArgs& a, int C2, int f32, hipStream_t s)
 {
-    PGM_DISPATCH(k_sweep, a, a.g.ny * ((a.g.nx + 1) / 2), ndir);
+    PGM_DISPATCH(k_sweep, a, a.g.ny * ((a.g.nx + 1) / 2));
 }
 
-hipError_t launch_init(const InitArgs& a, int C2, int f32, int ndir, hipStream_t s)
+hipError_t launch_init(const InitArgs& a, int C2, int f32, hipStream_t s)
 {
-    PGM_DISPATCH(k_init, a, a.g.nx * a.g.ny, ndir);
+    PGM_DISPATCH(k_init, a, a.g.nx * a.g.ny);
 }
 
-hipError_t launch_down(const TransArgs& a, int C2, int f32, int ndir, hipStream_t s)
+hipError_t launch_down(const TransArgs& a, int C2, int f32, hipStream_t s)
 {
-    PGM_DISPATCH(k_down, a, a.g.nx * a.g.ny, ndir);
+    PGM_DISPATCH(k_down, a, a.g.nx * a.g.ny);
 }
 
-hipError_t launch_up(const TransArgs& a, int C2, int f32, int ndir, hipStream_t s)
+hipError_t launch_up(const TransArgs& a, int C2, int f32, hipStream_t s)
 {
-    PGM_DISPATCH(k_up, a, a.g.nx * a.g.ny, ndir);
+    PGM_DISPATCH(k_up, a, a.g.nx * a.g.ny);
 }
 
 #undef PGM_V
@@ -745,20 +852,30 @@ hipError_t launch_up(const TransArgs& a, int C2, int f32, int ndir, hipStream_t 
 hipError_t launch_check(const CheckArgs& a, hipStream_t s)
 {
     const int n = a.g.nx * a.g.ny;
-    hipLaunchKernelGGL(k_check, dim3((n + 255) / 256, 2), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_check, dim3((n + 255) / 256, 2, a.b.npairs), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_output(const Field& f, const Geo& g, pgm_match_t* out, hipStream_t s)
+hipError_t launch_output(const OutArgs& a, hipStream_t s)
 {
-    const int n = g.nx * g.ny;
-    hipLaunchKernelGGL(k_output, dim3((n + 255) / 256), dim3(256), 0, s, f, g, out);
+    const int n = a.g.nx * a.g.ny;
+    hipLaunchKernelGGL(k_output, dim3((n + 255) / 256, 1, a.b.npairs), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const pgm_match_t* dense, int n, pgm_match_t* out, int32_t* n_out, hipStream_t s)
+hipError_t launch_compact(const OutArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, dense, n, out, n_out);
+    const int n = a.g.nx * a.g.ny;
+    hipLaunchKernelGGL(k_compact, dim3((n + 255) / 256, 1, a.b.npairs), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const CountArgs& a, hipStream_t s)
+{
+    long long n = 0;
+    for (int k = 0; k < CountArgs::KINDS; k++) n = n > a.n[k] ? n : a.n[k];
+    const int blocks = (int)std::min<long long>(64, std::max<long long>(1, (n + 2047) / 2048));
+    hipLaunchKernelGGL(k_count, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -39,9 +39,9 @@ def test_struct_layout_matches_header():
 #include <stddef.h>
 #include "pgm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pgm_params), offsetof(pgm_params, iters),
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(pgm_params), offsetof(pgm_params, iters),
          offsetof(pgm_params, rng_seed), sizeof(pgm_match_t), sizeof(pgm_sizes),
-         offsetof(pgm_sizes, workspace_bytes));
+         offsetof(pgm_sizes, workspace_bytes), offsetof(pgm_sizes, workspace_pair_bytes));
   return 0;
 }
 """
@@ -52,7 +52,8 @@ int main(void) {
         subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
         got = [int(v) for v in subprocess.check_output([exe]).split()]
     exp = [C.sizeof(pgm.pgm_params), pgm.pgm_params.iters.offset, pgm.pgm_params.rng_seed.offset,
-           pgm.MATCH_BYTES, C.sizeof(pgm.pgm_sizes), pgm.pgm_sizes.workspace_bytes.offset]
+           pgm.MATCH_BYTES, C.sizeof(pgm.pgm_sizes), pgm.pgm_sizes.workspace_bytes.offset,
+           pgm.pgm_sizes.workspace_pair_bytes.offset]
     assert got == exp
     assert pgm.MATCH_DTYPE.itemsize == pgm.MATCH_BYTES
 
@@ -83,6 +84,7 @@ def test_query_geometry_matches_oracle(w, h, L, stride):
         assert (s.level_w[l], s.level_h[l], s.level_nx[l], s.level_ny[l]) == (lw, lh, nx, ny)
     assert (s.nx, s.ny) == geo[0][2:]
     assert s.workspace_bytes > 0
+    assert s.workspace_bytes == s.workspace_shared_bytes + s.workspace_pair_bytes
 
 
 def test_query_workspace_of_config2_is_modest():
@@ -117,6 +119,8 @@ def test_null_arguments_rejected_without_device_work():
     assert L.pgm_create(0, 0, None) == pgm.PGM_EINVAL
     p = pgm.params(base_params())
     assert L.pgm_match(None, C.byref(p), None, None, 10, 10, 30, None, None, None, None, None, None) == pgm.PGM_EINVAL
+    assert L.pgm_match_batch(None, C.byref(p), 2, None, None, 10, 10, 30, 300, None, None, None, None, None,
+                             None) == pgm.PGM_EINVAL
     assert L.pgm_dump_level(None, 0, 0, None) == pgm.PGM_EINVAL
     L.pgm_destroy(None)
 

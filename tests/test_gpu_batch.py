@@ -1,0 +1,90 @@
+"""GPU: pgm_match_batch. Every pair of a batch must give exactly what pgm_match gives for that
+pair alone, which is exactly the oracle's synchronous schedule."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1704_03217_amd as pgm
+import synth
+from conftest import CONFIG_PARAMS, base_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def matcher():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    m = pgm.Matcher(0, 1536 << 20)
+    yield m
+    m.close()
+
+
+def run_batch(m, params, pairs):
+    torch = m.torch
+    a = torch.from_numpy(np.stack([p.img1 for p in pairs])).cuda()
+    b = torch.from_numpy(np.stack([p.img2 for p in pairs])).cuda()
+    o = m.match_batch(params, a, b)
+    torch.cuda.synchronize()
+    n = o["n"]
+    fwd = m.to_numpy(o["fwd"]).reshape(len(pairs), n)
+    bwd = m.to_numpy(o["bwd"]).reshape(len(pairs), n)
+    comp = m.to_numpy(o["compact"]).reshape(len(pairs), n)
+    nin = o["n_inliers"].cpu().numpy()
+    return fwd, bwd, comp, nin, int(o["n_evals"].item())
+
+
+@pytest.mark.parametrize("case", ["config1_x3", "patch5_11_gray_x4", "refine_x2", "direction_x2"])
+def test_batch_equals_oracle_per_pair(matcher, case):
+    if case == "config1_x3":
+        pairs = [synth.config_pair(1, i) for i in range(3)]
+        params = CONFIG_PARAMS[1]
+    elif case == "patch5_11_gray_x4":
+        pairs = [synth.rect_pair(50 + i, 120, 160, dmax=12) for i in range(4)]
+        params = base_params(patch_fwd=5, patch_bwd=11, color=1, max_disp=12, rng_seed=31)
+    elif case == "refine_x2":
+        pairs = [synth.config_pair(1, i) for i in range(2)]
+        params = base_params(refine_rounds=2, rng_seed=32)
+    else:
+        pairs = [synth.config_pair(1, i) for i in range(2)]
+        params = base_params(feature=1, rng_seed=33)
+    print(f"[gpu batch] {case}", file=sys.stderr, flush=True)
+    fwd, bwd, comp, nin, nev = run_batch(matcher, params, pairs)
+    total = 0
+    for k, pr in enumerate(pairs):
+        r = oracle.match(params, pr.img1, pr.img2, trace=False)
+        assert np.array_equal(fwd[k], r["fwd"]), f"pair {k} fwd"
+        assert np.array_equal(bwd[k], r["bwd"]), f"pair {k} bwd"
+        assert nin[k] == r["n_inliers"], f"pair {k} inliers"
+        assert np.array_equal(comp[k, : nin[k]], r["compact"]), f"pair {k} compact"
+        total += r["n_evals"]
+    assert nev == total
+
+
+def test_batch_config2_size(matcher):
+    pairs = [synth.config_pair(2, i) for i in range(2)]
+    print("[gpu batch] config2_x2", file=sys.stderr, flush=True)
+    fwd, bwd, comp, nin, nev = run_batch(matcher, CONFIG_PARAMS[2], pairs)
+    for k, pr in enumerate(pairs):
+        r = oracle.match(CONFIG_PARAMS[2], pr.img1, pr.img2, trace=False)
+        assert np.array_equal(fwd[k], r["fwd"]) and np.array_equal(bwd[k], r["bwd"])
+        assert nin[k] == r["n_inliers"]
+
+
+def test_batch_too_large_is_enomem(matcher):
+    torch = matcher.torch
+    s = pgm.pgm_query(CONFIG_PARAMS[1], 256, 192)
+    small = pgm.Matcher(0, s.workspace_shared_bytes + 2 * s.workspace_pair_bytes)
+    try:
+        img = torch.zeros((3, 192, 256, 3), dtype=torch.uint8, device="cuda")
+        with pytest.raises(pgm.PGMError) as e:
+            small.match_batch(CONFIG_PARAMS[1], img, img)
+        assert e.value.status == pgm.PGM_ENOMEM
+        ok = small.match_batch(CONFIG_PARAMS[1], img[:2], img[:2])   # exactly fits
+        torch.cuda.synchronize()
+        assert ok["n_inliers"].shape[0] == 2
+    finally:
+        small.close()
