@@ -615,28 +615,41 @@ __global__ __launch_bounds__(256) void k_count(CountArgs a)
 // image pyramid (Sec. III-D): 5x5 binomial, decimation by 2, reflect-101 borders
 // ---------------------------------------------------------------------------------------
 
+// A work-group computes 64 x 4 output pixels from a staged (2*64+3) x (2*4+3) block of source
+// pixels (reflect-101 applied at load time, one dword per RGB pixel).
+constexpr int PY_TW = 64, PY_TH = 4, PY_SU = 2 * PY_TW + 3, PY_SV = 2 * PY_TH + 3;
+
 __global__ __launch_bounds__(256) void k_pyr(const uint8_t* src0, const uint8_t* src1, long long src_zs, int pitch,
                                              int w, int h, uint8_t* dst0, uint8_t* dst1, long long dst_zs)
 {
+    __shared__ uint32_t tile[PY_SV][PY_SU];
     const int w2 = (w + 1) >> 1, h2 = (h + 1) >> 1;
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (x >= w2 || y >= h2) return;
+    const int X0 = blockIdx.x * PY_TW, Y0 = blockIdx.y * PY_TH;
     const size_t pair = blockIdx.z >> 1;
     const uint8_t* src = ((blockIdx.z & 1) ? src1 : src0) + pair * (size_t)src_zs;
     uint8_t* dst = ((blockIdx.z & 1) ? dst1 : dst0) + pair * (size_t)dst_zs;
+    const int xlo = 2 * X0 - 2, ylo = 2 * Y0 - 2;
+    for (int e = threadIdx.x; e < PY_SU * PY_SV; e += 256) {
+        const int v = e / PY_SU, u = e - v * PY_SU;
+        const uint8_t* p = src + (size_t)mirror(ylo + v, h) * pitch + 3 * (size_t)mirror(xlo + u, w);
+        tile[v][u] = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+    }
+    __syncthreads();
+    const int x = X0 + (threadIdx.x & (PY_TW - 1));
+    const int y = Y0 + (threadIdx.x / PY_TW);
+    if (x >= w2 || y >= h2) return;
     const int tap[5] = {1, 4, 6, 4, 1};
     int acc[3] = {0, 0, 0};
+    const int u0 = 2 * (x - X0), v0 = 2 * (y - Y0);
 #pragma unroll
     for (int i = 0; i < 5; i++) {
-        const uint8_t* row = src + (size_t)mirror(2 * y + i - 2, h) * pitch;
         int racc[3] = {0, 0, 0};
 #pragma unroll
         for (int jj = 0; jj < 5; jj++) {
-            const uint8_t* px = row + 3 * mirror(2 * x + jj - 2, w);
-            racc[0] += tap[jj] * px[0];
-            racc[1] += tap[jj] * px[1];
-            racc[2] += tap[jj] * px[2];
+            const uint32_t t = tile[v0 + i][u0 + jj];
+            racc[0] += tap[jj] * (int)(t & 0xFFu);
+            racc[1] += tap[jj] * (int)((t >> 8) & 0xFFu);
+            racc[2] += tap[jj] * (int)((t >> 16) & 0xFFu);
         }
         acc[0] += tap[i] * racc[0];
         acc[1] += tap[i] * racc[1];
@@ -652,20 +665,46 @@ __global__ __launch_bounds__(256) void k_pyr(const uint8_t* src0, const uint8_t*
 // gradient image (Sec. III-A, Eq. 1-2) written with a replicated PAD border
 // ---------------------------------------------------------------------------------------
 
+// A work-group computes 64 x 4 pixels of the padded gradient image. It first stages the source
+// pixels its 5x5 windows read -- border rules (clamp for the padding, reflect-101 for the
+// filter) applied once at load time -- in LDS, one dword per pixel (R | G << 8 | B << 16, or the
+// integer luma), then every thread forms its Sobel sums from LDS.
+constexpr int GR_TW = 64, GR_TH = 4;
+
 template <int KS, bool GRAY, bool F32>
 __global__ __launch_bounds__(256) void k_gradient(const uint8_t* img0, const uint8_t* img1, long long src_zs,
                                                   int pitch, int w, int h, void* G0, void* G1, long long dst_zs)
 {
     constexpr int CH = GRAY ? 1 : 3;
     constexpr int C2 = 2 * CH;
+    constexpr int K = KS / 2;
+    constexpr int NUX = GR_TW + 2 * K, NVX = GR_TH + 2 * K;
+    __shared__ uint32_t tile[NVX][NUX];
     const int pw = w + 2 * PAD, ph = h + 2 * PAD;
-    const int X = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int Y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (X >= pw || Y >= ph) return;
+    const int X0 = blockIdx.x * GR_TW, Y0 = blockIdx.y * GR_TH;
     const size_t pair = blockIdx.z >> 1;
     const uint8_t* img = ((blockIdx.z & 1) ? img1 : img0) + pair * (size_t)src_zs;
     void* G = zoff((blockIdx.z & 1) ? G1 : G0, pair * (size_t)dst_zs);
-    const int x = clampi(X - PAD, 0, w - 1), y = clampi(Y - PAD, 0, h - 1);
+    // source columns / rows the tile needs: clamp of the padded coordinates, widened by K
+    const int xlo = clampi(X0 - PAD, 0, w - 1) - K;
+    const int xhi = clampi(min(X0 + GR_TW - 1, pw - 1) - PAD, 0, w - 1) + K;
+    const int ylo = clampi(Y0 - PAD, 0, h - 1) - K;
+    const int yhi = clampi(min(Y0 + GR_TH - 1, ph - 1) - PAD, 0, h - 1) + K;
+    const int NU = xhi - xlo + 1, NV = yhi - ylo + 1;
+    for (int e = threadIdx.x; e < NU * NV; e += 256) {
+        const int v = e / NU, u = e - v * NU;
+        const uint8_t* p = img + (size_t)mirror(ylo + v, h) * pitch + 3 * (size_t)mirror(xlo + u, w);
+        uint32_t val;
+        if (GRAY) val = (uint32_t)((77 * p[0] + 150 * p[1] + 29 * p[2] + 128) >> 8);
+        else val = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+        tile[v][u] = val;
+    }
+    __syncthreads();
+    const int X = X0 + (threadIdx.x & (GR_TW - 1));
+    const int Y = Y0 + (threadIdx.x / GR_TW);
+    if (X >= pw || Y >= ph) return;
+    const int u0 = clampi(X - PAD, 0, w - 1) - K - xlo;
+    const int v0 = clampi(Y - PAD, 0, h - 1) - K - ylo;
     // smoothing and derivative taps of the size-KS Sobel operator
     const int sm3[3] = {1, 2, 1}, dv3[3] = {-1, 0, 1};
     const int sm5[5] = {1, 4, 6, 4, 1}, dv5[5] = {-1, -2, 0, 2, 1};
@@ -674,22 +713,19 @@ __global__ __launch_bounds__(256) void k_gradient(const uint8_t* img0, const uin
     for (int c = 0; c < CH; c++) { gx[c] = 0; gy[c] = 0; }
 #pragma unroll
     for (int i = 0; i < KS; i++) {
-        const uint8_t* row = img + (size_t)mirror(y + i - KS / 2, h) * pitch;
         int rs[CH], rd[CH];
 #pragma unroll
         for (int c = 0; c < CH; c++) { rs[c] = 0; rd[c] = 0; }
 #pragma unroll
         for (int jj = 0; jj < KS; jj++) {
-            const uint8_t* p = row + 3 * mirror(x + jj - KS / 2, w);
+            const uint32_t t = tile[v0 + i][u0 + jj];
             const int sm = KS == 3 ? sm3[jj] : sm5[jj];
             const int dv = KS == 3 ? dv3[jj] : dv5[jj];
-            if (GRAY) {
-                const int v = (77 * p[0] + 150 * p[1] + 29 * p[2] + 128) >> 8;
-                rs[0] += sm * v;
-                rd[0] += dv * v;
-            } else {
 #pragma unroll
-                for (int c = 0; c < CH; c++) { rs[c] += sm * p[c]; rd[c] += dv * p[c]; }
+            for (int c = 0; c < CH; c++) {
+                const int val = (int)((t >> (8 * c)) & 0xFFu);
+                rs[c] += sm * val;
+                rd[c] += dv * val;
             }
         }
         const int smi = KS == 3 ? sm3[i] : sm5[i];
@@ -699,12 +735,15 @@ __global__ __launch_bounds__(256) void k_gradient(const uint8_t* img0, const uin
     }
     const size_t o = ((size_t)Y * pw + X) * C2;
     if (!F32) {
-        uint16_t* out = (uint16_t*)G + o;
+        uint16_t vals[C2];
 #pragma unroll
         for (int c = 0; c < CH; c++) {
-            out[c] = (uint16_t)(gx[c] + (int)BIAS);
-            out[CH + c] = (uint16_t)(gy[c] + (int)BIAS);
+            vals[c] = (uint16_t)(gx[c] + (int)BIAS);
+            vals[CH + c] = (uint16_t)(gy[c] + (int)BIAS);
         }
+        uint32_t* out = (uint32_t*)((uint16_t*)G + o);   // C2 even: pixels are dword aligned
+#pragma unroll
+        for (int q = 0; q < C2 / 2; q++) out[q] = (uint32_t)vals[2 * q] | ((uint32_t)vals[2 * q + 1] << 16);
     } else {
         float* out = (float*)G + o;
 #pragma unroll
@@ -774,7 +813,7 @@ hipError_t launch_pyr_down(const uint8_t* src0, const uint8_t* src1, long long s
                            uint8_t* dst0, uint8_t* dst1, long long dst_zs, int npairs, hipStream_t s)
 {
     const int w2 = (w + 1) / 2, h2 = (h + 1) / 2;
-    dim3 grid((w2 + 63) / 64, (h2 + 3) / 4, 2 * npairs);
+    dim3 grid((w2 + PY_TW - 1) / PY_TW, (h2 + PY_TH - 1) / PY_TH, 2 * npairs);
     hipLaunchKernelGGL(k_pyr, grid, dim3(256), 0, s, src0, src1, src_zs, pitch, w, h, dst0, dst1, dst_zs);
     return hipGetLastError();
 }
@@ -783,7 +822,7 @@ hipError_t launch_gradient(const uint8_t* img0, const uint8_t* img1, long long s
                            void* G0, void* G1, long long dst_zs, int npairs, int gray, int ksize, int f32,
                            hipStream_t s)
 {
-    dim3 grid((w + 2 * PAD + 63) / 64, (h + 2 * PAD + 3) / 4, 2 * npairs);
+    dim3 grid((w + 2 * PAD + GR_TW - 1) / GR_TW, (h + 2 * PAD + GR_TH - 1) / GR_TH, 2 * npairs);
 #define PGM_GRAD(KS, GR, F)                                                                       \
     if (ksize == KS && !!gray == GR && !!f32 == F) {                                               \
         hipLaunchKernelGGL((k_gradient<KS, GR, F>), grid, dim3(256), 0, s, img0, img1, src_zs, pitch, w, \
