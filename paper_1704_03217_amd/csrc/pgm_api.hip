@@ -29,6 +29,7 @@ struct Layout {
     size_t cnt[4] = {0, 0, 0, 0};
     long long cnt_cap[4] = {0, 0, 0, 0};
     size_t blockcnt = 0;
+    size_t cntpart = 0;
     // the random-number table is shared by all pairs of a batch; everything else is per pair
     // (offsets above are relative to the pair's slice, except rnd / rnd_init)
     size_t shared_bytes = 0, pair_bytes = 0;
@@ -160,6 +161,8 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
     }
     for (int k = 0; k < 4; k++) Y.cnt[k] = take(cur, (size_t)Y.cnt_cap[k] * 4 + 4);
     Y.blockcnt = take(cur, (size_t)((Y.lnx[0] * Y.lny[0] + 255) / 256) * 4);
+    // partial evaluation sums of the count reduction: COUNT_SLICES x KINDS per pair
+    Y.cntpart = take(cur, (size_t)COUNT_SLICES * CountArgs::KINDS * sizeof(unsigned long long));
     Y.pair_bytes = (cur + 255) & ~(size_t)255;
     Y.total = Y.shared_bytes + Y.pair_bytes;
 }
@@ -561,7 +564,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         ca.zs = zs;
         ca.user = nev;
         ca.prof = c->prof ? c->prof_evals : nullptr;
-        PGM_HIP(c, launch_count(ca, s));
+        PGM_HIP(c, launch_count(ca, (unsigned long long*)(pw0 + Y.cntpart), s));
     }
 
     c->have_last = true;

@@ -154,6 +154,9 @@ hipError_t launch_up(const TransArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);
 hipError_t launch_output(const OutArgs& a, hipStream_t s);
 hipError_t launch_compact(const OutArgs& a, hipStream_t s);
-hipError_t launch_count(const CountArgs& a, hipStream_t s);
+// part: pair 0's array of COUNT_SLICES * CountArgs::KINDS partial sums; pair z's array is at
+// the same offset of its own workspace slice (z * zs bytes further)
+constexpr int COUNT_SLICES = 16;
+hipError_t launch_count(const CountArgs& a, unsigned long long* part, hipStream_t s);
 
 }  // namespace pgm

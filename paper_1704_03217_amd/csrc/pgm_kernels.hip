@@ -110,6 +110,7 @@ __device__ __forceinline__ double group_sum(double v)
 // Integer gradients, biased u16, two per dword; C2 channels per pixel (C2 even).
 // v_sad_u16 adds |a.lo16 - b.lo16| + |a.hi16 - b.hi16| (unsigned halves) to its accumulator,
 // so one instruction covers two gradient values of a packed dword.
+// Rows past the patch side (P < PMAX) read row P - 1 again and add nothing.
 template <int C2, int PMAX, bool FIXED>
 struct IntRow {
     static constexpr int W3 = C2 / 2;   // dwords per pixel
@@ -120,18 +121,20 @@ struct IntRow {
     __device__ __forceinline__ void load(const uint32_t* base, ptrdiff_t pitch, int P)
     {
 #pragma unroll
-        for (int y = 0; y < PMAX; y++)
+        for (int y = 0; y < PMAX; y++) {
+            const int yy = (FIXED || y < P) ? y : P - 1;
 #pragma unroll
-            for (int w = 0; w < W3; w++) a[y][w] = (FIXED || y < P) ? base[y * pitch + w] : 0u;
+            for (int w = 0; w < W3; w++) a[y][w] = base[yy * pitch + w];
+        }
     }
-    __device__ __forceinline__ uint32_t sad(const uint32_t* base, ptrdiff_t pitch, int P) const
+    __device__ __forceinline__ uint32_t sad(const IntRow& B, int P) const
     {
         uint32_t acc = 0;
 #pragma unroll
         for (int y = 0; y < PMAX; y++)
             if (FIXED || y < P)
 #pragma unroll
-                for (int w = 0; w < W3; w++) acc = __builtin_amdgcn_sad_u16(a[y][w], base[y * pitch + w], acc);
+                for (int w = 0; w < W3; w++) acc = __builtin_amdgcn_sad_u16(a[y][w], B.a[y][w], acc);
         return acc;
     }
     static __device__ __forceinline__ const uint32_t* at(const void* G, const Geo& g, int x, int y)
@@ -149,23 +152,25 @@ struct IntRow {
 template <int C2, int PMAX, bool FIXED>
 struct F32Row {
     using Acc = double;
-    double a[PMAX][C2];
+    float a[PMAX][C2];
 
     __device__ __forceinline__ void load(const float* base, ptrdiff_t pitch, int P)
     {
 #pragma unroll
-        for (int y = 0; y < PMAX; y++)
+        for (int y = 0; y < PMAX; y++) {
+            const int yy = (FIXED || y < P) ? y : P - 1;
 #pragma unroll
-            for (int c = 0; c < C2; c++) a[y][c] = (FIXED || y < P) ? (double)base[y * pitch + c] : 0.0;
+            for (int c = 0; c < C2; c++) a[y][c] = base[yy * pitch + c];
+        }
     }
-    __device__ __forceinline__ double sad(const float* base, ptrdiff_t pitch, int P) const
+    __device__ __forceinline__ double sad(const F32Row& B, int P) const
     {
         double acc = 0.0;
 #pragma unroll
         for (int y = 0; y < PMAX; y++)
             if (FIXED || y < P)
 #pragma unroll
-                for (int c = 0; c < C2; c++) acc += fabs((double)base[y * pitch + c] - a[y][c]);
+                for (int c = 0; c < C2; c++) acc += fabs((double)B.a[y][c] - (double)a[y][c]);
         return acc;
     }
     static __device__ __forceinline__ const float* at(const void* G, const Geo& g, int x, int y)
@@ -185,16 +190,42 @@ using RowT = typename std::conditional<F32, F32Row<C2, PMAX, FIXED>, IntRow<C2, 
 
 // Patch distance of Eq. 3 (absolute differences) between the patch held by the group and
 // the patch of the other image at (qx, qy); every lane of the group gets the result. Lanes
-// past the patch side read a valid column and add nothing.
+// past the patch side read a valid column and add nothing. All rows of the candidate are
+// requested before the first one is used (the scheduling barrier keeps the compiler from
+// trading the loads in flight for registers), so a candidate costs one memory round trip.
 template <class Row, int LPS>
 __device__ __forceinline__ uint32_t patch_cost(const Row& A, const void* Gb, const Geo& g, int P,
                                                int r, int qx, int qy)
 {
     const int half = P >> 1;
     const int rc = r < P ? r : P - 1;
-    typename Row::Acc part = A.sad(Row::at(Gb, g, qx - half + rc, qy - half), Row::pitch(g), P);
+    Row B;
+    B.load(Row::at(Gb, g, qx - half + rc, qy - half), Row::pitch(g), P);
+    __builtin_amdgcn_sched_barrier(0);
+    typename Row::Acc part = A.sad(B, P);
     if (r >= P) part = typename Row::Acc(0);
     return Row::template finish<LPS>(part);
+}
+
+// Two patch distances with the reads of both candidates in flight together.
+template <class Row, int LPS>
+__device__ __forceinline__ void patch_cost2(const Row& A, const void* Gb, const Geo& g, int P, int r, int q0x,
+                                            int q0y, int q1x, int q1y, uint32_t& e0, uint32_t& e1)
+{
+    const int half = P >> 1;
+    const int rc = r < P ? r : P - 1;
+    Row B0, B1;
+    B0.load(Row::at(Gb, g, q0x - half + rc, q0y - half), Row::pitch(g), P);
+    B1.load(Row::at(Gb, g, q1x - half + rc, q1y - half), Row::pitch(g), P);
+    __builtin_amdgcn_sched_barrier(0);
+    typename Row::Acc p0 = A.sad(B0, P);
+    typename Row::Acc p1 = A.sad(B1, P);
+    if (r >= P) {
+        p0 = typename Row::Acc(0);
+        p1 = typename Row::Acc(0);
+    }
+    e0 = Row::template finish<LPS>(p0);
+    e1 = Row::template finish<LPS>(p1);
 }
 
 template <class Row>
@@ -291,9 +322,14 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         const int P = D.P;
         Row A;
         load_own(A, D.Ga, g, P, r, px, py);
-        uint32_t cur = D.f.disp[s];
-        uint32_t cd = D.f.dist[s];
-        bool init = cur != UNINIT, changed = false;
+        const uint32_t cur0 = D.f.disp[s];
+        const uint32_t cd0 = D.f.dist[s];
+        const bool init0 = cur0 != UNINIT;
+        // Eq. 5 offsets of the first two random candidates (nI >= 1), fetched with the field;
+        // the neighbours' fields are read from clamped indices and masked, so that every read
+        // of this phase is in flight at once
+        const short2* R = D.rnd + ((size_t)a.t * (size_t)(g.nx * g.ny) + s) * a.nI;
+        short2 o0 = R[0], o1 = R[a.nI > 1 ? 1 : 0];
 
         // Eq. 4: Omega = {F(p), F(p - Dx) + Dx, F(p - Dy) + Dy} with the FlowFields order
         // (1,0),(0,1) -> (-1,0),(0,-1) -> (-1,0),(0,1) -> (1,0),(0,-1); members whose
@@ -301,30 +337,78 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         const int k = a.t & 3;
         const int sx = (k == 0 || k == 3) ? 1 : -1;
         const int sy = (k == 0 || k == 2) ? 1 : -1;
+        uint32_t c[2], nv[2];
+        bool ok[2];
 #pragma unroll
         for (int m = 0; m < 2; m++) {
             const int ni = m == 0 ? i - sx : i;
             const int nj = m == 0 ? j : j - sy;
-            if (ni < 0 || nj < 0 || ni >= g.nx || nj >= g.ny) continue;
-            const uint32_t nd = D.f.disp[nj * g.nx + ni];
-            if (nd == UNINIT) continue;
-            const uint32_t cand = target(px, py, d_x(nd), d_y(nd), g);
-            if (init && cand == cur) continue;
-            const uint32_t e = patch_cost<Row, LPS>(A, D.Gb, g, P, r, px + d_x(cand), py + d_y(cand));
-            nev++;
-            if (!init || e < cd) { cur = cand; cd = e; init = true; changed = true; }
+            ok[m] = ni >= 0 && nj >= 0 && ni < g.nx && nj < g.ny;
+            nv[m] = D.f.disp[clampi(nj, 0, g.ny - 1) * g.nx + clampi(ni, 0, g.nx - 1)];
         }
-        // Eq. 5: Psi = {F(p)} + {F(p) + floor(R_i W / 2^i)}, around the propagated match
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int m = 0; m < 2; m++) {
+            ok[m] = ok[m] && nv[m] != UNINIT;
+            const uint32_t t = target(px, py, d_x(nv[m]), d_y(nv[m]), g);
+            c[m] = ok[m] ? t : cur0;
+        }
+        // Both members are priced together. A member equal to F(p) costs the stored distance
+        // and one equal to the other member costs what that one costs, so only new patches
+        // are read; the decisions below replay the paper's one-at-a-time order exactly.
+        const bool need0 = ok[0] && !(init0 && c[0] == cur0);
+        const bool need1 = ok[1] && !(init0 && c[1] == cur0) && !(ok[0] && c[1] == c[0]);
+        uint32_t e[2] = {cd0, cd0};
+        if (need0 || need1) {
+            const uint32_t qa = need0 ? c[0] : c[1], qb = need1 ? c[1] : c[0];
+            uint32_t ea, eb;
+            patch_cost2<Row, LPS>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb), ea, eb);
+            if (need0) e[0] = ea;
+            if (need1) e[1] = eb;
+        }
+        if (ok[1] && !need1 && !(init0 && c[1] == cur0)) e[1] = e[0];
+        uint32_t cur = cur0, cd = cd0;
+        bool init = init0, changed = false;
+#pragma unroll
+        for (int m = 0; m < 2; m++) {
+            if (!ok[m] || (init && c[m] == cur)) continue;
+            nev++;
+            if (!init || e[m] < cd) { cur = c[m]; cd = e[m]; init = true; changed = true; }
+        }
+
+        // Eq. 5: Psi = {F(p)} + {F(p) + floor(R_i W / 2^i)}, all around the propagated match,
+        // priced two at a time in the same way and decided in order
         if (init) {
-            const short2* R = D.rnd + ((size_t)a.t * (size_t)(g.nx * g.ny) + s) * a.nI;
             const int cx = d_x(cur), cy = d_y(cur);
-            for (int ii = 0; ii < a.nI; ii++) {
-                const short2 o = R[ii];
-                const uint32_t cand = target(px, py, cx + o.x, cy + o.y, g);
-                if (cand == cur) continue;
-                const uint32_t e = patch_cost<Row, LPS>(A, D.Gb, g, P, r, px + d_x(cand), py + d_y(cand));
-                nev++;
-                if (e < cd) { cur = cand; cd = e; changed = true; }
+            const uint32_t curp = cur, cdp = cd;
+            for (int ii = 0; ii < a.nI; ii += 2) {
+                if (ii > 0) {
+                    o0 = R[ii];
+                    if (ii + 1 < a.nI) o1 = R[ii + 1];
+                }
+                const bool two = ii + 1 < a.nI;
+                const uint32_t r0 = target(px, py, cx + o0.x, cy + o0.y, g);
+                const uint32_t r1 = two ? target(px, py, cx + o1.x, cy + o1.y, g) : curp;
+                const bool n0 = r0 != curp;
+                const bool n1 = r1 != curp && r1 != r0;
+                uint32_t f0 = cdp, f1 = cdp;
+                if (n0 || n1) {
+                    const uint32_t qa = n0 ? r0 : r1, qb = n1 ? r1 : r0;
+                    uint32_t ea, eb;
+                    patch_cost2<Row, LPS>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb),
+                                          ea, eb);
+                    if (n0) f0 = ea;
+                    if (n1) f1 = eb;
+                }
+                if (two && !n1 && r1 != curp) f1 = f0;
+                if (r0 != cur) {
+                    nev++;
+                    if (f0 < cd) { cur = r0; cd = f0; changed = true; }
+                }
+                if (two && r1 != cur) {
+                    nev++;
+                    if (f1 < cd) { cur = r1; cd = f1; changed = true; }
+                }
             }
         }
         if (changed && r == 0) {
@@ -586,29 +670,47 @@ __global__ __launch_bounds__(256) void k_compact(OutArgs a)
         a.n_out[blockIdx.z] = (int32_t)(prefix + wtot[0] + wtot[1] + wtot[2] + wtot[3]);
 }
 
-// Add up the count tables of a pair: per kernel kind (for profiling) and in total (for the
-// caller's counter). Blocks take strided slices; one atomic per block and kind.
-__global__ __launch_bounds__(256) void k_count(CountArgs a)
+// Add up the count tables: k_count_part sums slice x of pair y's tables per kernel kind into
+// pair y's partial array at [x * KINDS + kind] (each pair's array sits at the same offset of
+// its own workspace slice); k_count_sum adds the parts per kind (profiling) and in total (the
+// caller's counter).
+__global__ __launch_bounds__(256) void k_count_part(CountArgs a, unsigned long long* part)
+{
+    __shared__ unsigned long long ws[4];
+    const uint32_t z = blockIdx.y;
+    for (int k = 0; k < CountArgs::KINDS; k++) {
+        const uint32_t* t = zoff(a.table[k], (size_t)z * (size_t)a.zs);
+        unsigned long long v = 0;
+        for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.n[k]; i += (long long)gridDim.x * 256)
+            v += t[i];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            zoff(part, (size_t)z * (size_t)a.zs)[blockIdx.x * CountArgs::KINDS + k] = ws[0] + ws[1] + ws[2] + ws[3];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_count_sum(CountArgs a, const unsigned long long* part, int slices)
 {
     __shared__ unsigned long long ws[4];
     unsigned long long total = 0;
     for (int k = 0; k < CountArgs::KINDS; k++) {
         unsigned long long v = 0;
-        for (int z = 0; z < a.npairs; z++) {
-            const uint32_t* t = zoff(a.table[k], (size_t)z * (size_t)a.zs);
-            for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.n[k]; i += (long long)gridDim.x * 256)
-                v += t[i];
-        }
+        for (int i = threadIdx.x; i < slices * a.npairs; i += 256)
+            v += zoff(part, (size_t)(i / slices) * (size_t)a.zs)[(i % slices) * CountArgs::KINDS + k];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
         if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
         __syncthreads();
         const unsigned long long sum = ws[0] + ws[1] + ws[2] + ws[3];
         __syncthreads();
-        if (threadIdx.x == 0 && a.prof && sum) atomicAdd(a.prof + a.kind[k], sum);
+        if (threadIdx.x == 0 && a.prof) a.prof[a.kind[k]] += sum;
         total += sum;
     }
-    if (threadIdx.x == 0 && a.user && total) atomicAdd(a.user, total);
+    if (threadIdx.x == 0 && a.user) atomicAdd(a.user, total);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -788,12 +890,23 @@ __global__ __launch_bounds__(256) void k_rng(RngArgs a)
         const int nB = (S.nI + 1) >> 1;
         const long long cnt = 2LL * S.n * S.iters * nB;
         if (item >= cnt) { item -= cnt; continue; }
-        const int b = (int)(item % nB);
-        long long rest = item / nB;
-        const int s = (int)(rest % S.n);
-        rest /= S.n;
-        const int t = (int)(rest % S.iters);
-        const int dir = (int)(rest / S.iters);
+        int b, s, t, dir;
+        if (cnt <= 0x7FFFFFFFLL) {   // 32-bit index arithmetic (64-bit division is slow)
+            uint32_t it = (uint32_t)item;
+            b = (int)(it % (uint32_t)nB);
+            it /= (uint32_t)nB;
+            s = (int)(it % (uint32_t)S.n);
+            it /= (uint32_t)S.n;
+            t = (int)(it % (uint32_t)S.iters);
+            dir = (int)(it / (uint32_t)S.iters);
+        } else {
+            b = (int)(item % nB);
+            long long rest = item / nB;
+            s = (int)(rest % S.n);
+            rest /= S.n;
+            t = (int)(rest % S.iters);
+            dir = (int)(rest / S.iters);
+        }
         const uint32_t w1 = (uint32_t)t | ((uint32_t)S.level << 8) | ((uint32_t)dir << 16) | (1u << 24);
         const uint4 u = philox4x32_10(make_uint4((uint32_t)s, w1, (uint32_t)b, (uint32_t)S.stage), a.key0, a.key1);
         short2* out = a.table + S.base + (((long long)dir * S.iters + t) * S.n + s) * S.nI;
@@ -909,12 +1022,15 @@ hipError_t launch_compact(const OutArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_count(const CountArgs& a, hipStream_t s)
+hipError_t launch_count(const CountArgs& a, unsigned long long* part, hipStream_t s)
 {
     long long n = 0;
     for (int k = 0; k < CountArgs::KINDS; k++) n = n > a.n[k] ? n : a.n[k];
-    const int blocks = (int)std::min<long long>(64, std::max<long long>(1, (n + 2047) / 2048));
-    hipLaunchKernelGGL(k_count, dim3(blocks), dim3(256), 0, s, a);
+    const int slices = (int)std::min<long long>(COUNT_SLICES, std::max<long long>(1, (n + 2047) / 2048));
+    hipLaunchKernelGGL(k_count_part, dim3(slices, a.npairs), dim3(256), 0, s, a, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_count_sum, dim3(1), dim3(256), 0, s, a, (const unsigned long long*)part, slices);
     return hipGetLastError();
 }
 
