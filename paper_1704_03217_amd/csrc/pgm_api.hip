@@ -292,6 +292,7 @@ pgm_status pgm_create(int32_t device, uint64_t workspace_bytes, void** out_ctx)
     if (e == hipSuccess) e = hipMalloc((void**)&c->prof_evals, PGM_K_KINDS * sizeof(unsigned long long));
     if (e != hipSuccess) {
         if (c->ws) (void)hipFree(c->ws);
+        if (c->prof_evals) (void)hipFree(c->prof_evals);
         std::string msg = std::string("workspace allocation failed: ") + hipGetErrorString(e);
         delete c;
         return fail(nullptr, e == hipErrorOutOfMemory ? PGM_ENOMEM : PGM_EDEVICE, msg);
@@ -375,32 +376,13 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         return t;
     };
 
-    // image pyramids and gradient pyramids of both images (Sec. III-D, III-A)
-    const uint8_t* lvl[2] = {img1, img2};
-    int pitch = pitch_bytes;
-    long long src_zs = image_stride_bytes;
-    for (int l = 0; l < Y.L; l++) {
-        if (l > 0) {
-            uint8_t* d0 = pw0 + Y.pyr[0][l];
-            uint8_t* d1 = pw0 + Y.pyr[1][l];
-            PGM_HIP(c, timed(PGM_K_PYRAMID, [&] {
-                           return launch_pyr_down(lvl[0], lvl[1], src_zs, pitch, Y.lw[l - 1], Y.lh[l - 1], d0, d1, zs,
-                                                  npairs, s);
-                       }));
-            lvl[0] = d0; lvl[1] = d1;
-            pitch = Y.lw[l] * 3;
-            src_zs = zs;
-        }
-        PGM_HIP(c, timed(PGM_K_GRADIENT, [&] {
-                       return launch_gradient(lvl[0], lvl[1], src_zs, pitch, Y.lw[l], Y.lh[l], pw0 + Y.grad[0][l],
-                                              pw0 + Y.grad[1][l], zs, npairs, p->color == PGM_GRAY, p->sobel_ksize,
-                                              Y.f32, s);
-                   }));
-    }
-
-    // every random number, shared by the pairs (they depend only on the parameters)
-    RngArgs ra;
-    memset(&ra, 0, sizeof ra);
+    // The image stage. One launch draws every random number (shared by the pairs: they depend
+    // only on the parameters), builds the level-0 gradient images and the first pyramid level;
+    // then the further pyramid levels, then the gradient images of levels 1.. in one launch
+    // (Sec. III-D, III-A).
+    PrepArgs pa;
+    memset(&pa, 0, sizeof pa);
+    RngArgs& ra = pa.rng;
     ra.nstages = Y.nst;
     for (int k = 0; k < Y.nst; k++) {
         const int l = Y.st_level[k];
@@ -421,7 +403,49 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     ra.top_level = m;
     ra.key0 = (uint32_t)p->rng_seed;
     ra.key1 = (uint32_t)(p->rng_seed >> 32);
-    PGM_HIP(c, timed(PGM_K_RNG, [&] { return launch_rng(ra, s); }));
+
+    auto grad_level = [&](GradArgs& ga, int l, const uint8_t* s0, const uint8_t* s1, long long szs, int pitch) {
+        GradLevel& L = ga.lv[ga.n++];
+        L.src[0] = s0;
+        L.src[1] = s1;
+        L.src_zs = szs;
+        L.pitch = pitch;
+        L.w = Y.lw[l];
+        L.h = Y.lh[l];
+        L.G[0] = pw0 + Y.grad[0][l];
+        L.G[1] = pw0 + Y.grad[1][l];
+    };
+    auto pyr_level = [&](PyrArgs& pr, int l, const uint8_t* s0, const uint8_t* s1, long long szs, int pitch) {
+        pr.src[0] = s0;
+        pr.src[1] = s1;
+        pr.src_zs = szs;
+        pr.pitch = pitch;
+        pr.w = Y.lw[l - 1];
+        pr.h = Y.lh[l - 1];
+        pr.dst[0] = pw0 + Y.pyr[0][l];
+        pr.dst[1] = pw0 + Y.pyr[1][l];
+        pr.dst_zs = zs;
+    };
+    const bool gray = p->color == PGM_GRAY;
+    pa.grad.dst_zs = zs;
+    grad_level(pa.grad, 0, img1, img2, image_stride_bytes, pitch_bytes);
+    pa.grad.n = 1;
+    pa.with_pyr = Y.L > 1;
+    if (pa.with_pyr) pyr_level(pa.pyr, 1, img1, img2, image_stride_bytes, pitch_bytes);
+    PGM_HIP(c, timed(PGM_K_PREP, [&] { return launch_prep(pa, npairs, gray, p->sobel_ksize, Y.f32, s); }));
+    GradArgs gl;
+    memset(&gl, 0, sizeof gl);
+    gl.dst_zs = zs;
+    for (int l = 1; l < Y.L; l++) {
+        if (l > 1) {
+            PyrArgs pr;
+            memset(&pr, 0, sizeof pr);
+            pyr_level(pr, l, pw0 + Y.pyr[0][l - 1], pw0 + Y.pyr[1][l - 1], zs, Y.lw[l - 1] * 3);
+            PGM_HIP(c, timed(PGM_K_PYRAMID, [&] { return launch_pyr(pr, npairs, s); }));
+        }
+        grad_level(gl, l, pw0 + Y.pyr[0][l], pw0 + Y.pyr[1][l], zs, Y.lw[l] * 3);
+    }
+    if (gl.n) PGM_HIP(c, timed(PGM_K_GRADIENT, [&] { return launch_gradient(gl, npairs, gray, p->sobel_ksize, Y.f32, s); }));
 
     auto geo = [&](int l) {
         Geo g;

@@ -141,12 +141,39 @@ inline int sweep_blocks(int nx, int ny, int P) { return match_blocks(ny * ((nx +
 // Launch wrappers (pgm_kernels.hip). Each returns hipSuccess or the launch error.
 // Per-image pointers are those of pair 0; pair z's source is src_zs bytes further and its
 // destination dst_zs bytes further.
-hipError_t launch_pyr_down(const uint8_t* src0, const uint8_t* src1, long long src_zs, int pitch, int w, int h,
-                           uint8_t* dst0, uint8_t* dst1, long long dst_zs, int npairs, hipStream_t s);
-hipError_t launch_gradient(const uint8_t* img0, const uint8_t* img1, long long src_zs, int pitch, int w, int h,
-                           void* G0, void* G1, long long dst_zs, int npairs, int gray, int ksize, int f32,
-                           hipStream_t s);
-hipError_t launch_rng(const RngArgs& a, hipStream_t s);
+// one pyramid level (tx, tiles filled in by the launchers)
+struct PyrArgs {
+    const uint8_t* src[2];   // pair 0's source images (the finer level)
+    long long src_zs;        // bytes between pairs' source images
+    int pitch, w, h;         // source pitch (bytes) and size
+    uint8_t* dst[2];         // pair 0's destination images (packed rows of (w + 1) / 2 pixels)
+    long long dst_zs;
+    int tx, tiles;
+};
+// gradient images of one or more levels (tx, tiles and base filled in by the launchers)
+struct GradLevel {
+    const uint8_t* src[2];   // pair 0's source images
+    long long src_zs;        // bytes between pairs' source images
+    int pitch, w, h;
+    void* G[2];              // pair 0's padded gradient images
+    int tx, tiles, base;
+};
+struct GradArgs {
+    GradLevel lv[PGM_MAX_LEVELS];
+    int n;
+    long long dst_zs;
+};
+// the first launch of a call: random numbers, level-0 gradients and (with_pyr) pyramid level 1
+struct PrepArgs {
+    RngArgs rng;
+    GradArgs grad;           // level 0 in lv[0]
+    PyrArgs pyr;
+    int with_pyr;
+    int rng_blocks, grad_blocks;   // filled in by the launcher
+};
+hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int f32, hipStream_t s);
+hipError_t launch_pyr(PyrArgs a, int npairs, hipStream_t s);
+hipError_t launch_gradient(GradArgs a, int npairs, int gray, int ksize, int f32, hipStream_t s);
 hipError_t launch_init(const InitArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_sweep(const SweepArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_down(const TransArgs& a, int C2, int f32, hipStream_t s);

@@ -495,13 +495,15 @@ __global__ __launch_bounds__(256) void k_down(TransArgs a)
         const int i = s % g.nx, j = s / g.nx;
         const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
         const int ps = grid_near(py >> 1, a.gs.ny, a.gs) * a.gs.nx + grid_near(px >> 1, a.gs.nx, a.gs);
-        const bool par_inl = (S.flags[ps] & ST_INL) != 0;
+        // the parent's state and this seed's patch are read together
+        Row A;
+        load_own(A, D.Ga, g, D.P, r, px, py);
+        const uint8_t pf = S.flags[ps];
+        const uint32_t pd = S.disp[ps];
+        const bool par_inl = (pf & ST_INL) != 0;
         uint32_t disp = UNINIT, dist = NO_DIST;
         if (par_inl) {
-            const uint32_t pd = S.disp[ps];
             disp = target(px, py, 2 * d_x(pd), 2 * d_y(pd), g);
-            Row A;
-            load_own(A, D.Ga, g, D.P, r, px, py);
             dist = patch_cost<Row, LPS>(A, D.Gb, g, D.P, r, px + d_x(disp), py + d_y(disp));
             nev++;
         }
@@ -717,45 +719,63 @@ __global__ __launch_bounds__(256) void k_count_sum(CountArgs a, const unsigned l
 // image pyramid (Sec. III-D): 5x5 binomial, decimation by 2, reflect-101 borders
 // ---------------------------------------------------------------------------------------
 
-// A work-group computes 64 x 4 output pixels from a staged (2*64+3) x (2*4+3) block of source
-// pixels (reflect-101 applied at load time, one dword per RGB pixel).
-constexpr int PY_TW = 64, PY_TH = 4, PY_SU = 2 * PY_TW + 3, PY_SV = 2 * PY_TH + 3;
+__device__ __forceinline__ int mirror_fast(int i, int n) { return (unsigned)i < (unsigned)n ? i : mirror(i, n); }
 
-__global__ __launch_bounds__(256) void k_pyr(const uint8_t* src0, const uint8_t* src1, long long src_zs, int pitch,
-                                             int w, int h, uint8_t* dst0, uint8_t* dst1, long long dst_zs)
+// packed R | G << 8 | B << 16 of pixel (x, y)
+__device__ __forceinline__ uint32_t rgb_at(const uint8_t* img, int pitch, int x, int y)
 {
-    __shared__ uint32_t tile[PY_SV][PY_SU];
-    const int w2 = (w + 1) >> 1, h2 = (h + 1) >> 1;
-    const int X0 = blockIdx.x * PY_TW, Y0 = blockIdx.y * PY_TH;
-    const size_t pair = blockIdx.z >> 1;
-    const uint8_t* src = ((blockIdx.z & 1) ? src1 : src0) + pair * (size_t)src_zs;
-    uint8_t* dst = ((blockIdx.z & 1) ? dst1 : dst0) + pair * (size_t)dst_zs;
+    const uint8_t* p = img + (size_t)y * pitch + 3 * (size_t)x;
+    return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+}
+
+// A work-group computes 64 x 4 output pixels: it stages the (2*64+3) x (2*4+3) source pixels
+// (reflect-101 applied at load time), filters every staged row at the even columns, then the
+// columns; the integer result is the 5x5 sum of the same products.
+constexpr int PY_TW = 64, PY_TH = 4, PY_SU = 2 * PY_TW + 3, PY_SV = 2 * PY_TH + 3;
+constexpr int PY_LDS = PY_SV * PY_SU + PY_SV * PY_TW * 3;   // dwords
+
+__device__ __forceinline__ void pyr_tile(const PyrArgs& a, int t, int z, uint32_t* lds)
+{
+    uint32_t* S = lds;                        // [PY_SV][PY_SU] staged pixels
+    int* H = (int*)(lds + PY_SV * PY_SU);     // [PY_SV][PY_TW][3] row-filtered values
+    const int w = a.w, h = a.h, w2 = (w + 1) >> 1, h2 = (h + 1) >> 1;
+    const int X0 = (t % a.tx) * PY_TW, Y0 = (t / a.tx) * PY_TH;
+    const size_t pair = (size_t)(z >> 1);
+    const uint8_t* src = a.src[z & 1] + pair * (size_t)a.src_zs;
+    uint8_t* dst = a.dst[z & 1] + pair * (size_t)a.dst_zs;
     const int xlo = 2 * X0 - 2, ylo = 2 * Y0 - 2;
     for (int e = threadIdx.x; e < PY_SU * PY_SV; e += 256) {
         const int v = e / PY_SU, u = e - v * PY_SU;
-        const uint8_t* p = src + (size_t)mirror(ylo + v, h) * pitch + 3 * (size_t)mirror(xlo + u, w);
-        tile[v][u] = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+        S[e] = rgb_at(src, a.pitch, mirror_fast(xlo + u, w), mirror_fast(ylo + v, h));
     }
     __syncthreads();
-    const int x = X0 + (threadIdx.x & (PY_TW - 1));
-    const int y = Y0 + (threadIdx.x / PY_TW);
-    if (x >= w2 || y >= h2) return;
     const int tap[5] = {1, 4, 6, 4, 1};
+    for (int e = threadIdx.x; e < PY_SV * PY_TW; e += 256) {
+        const int v = e / PY_TW, u = e - v * PY_TW;
+        const uint32_t* row = S + v * PY_SU + 2 * u;
+        int acc0 = 0, acc1 = 0, acc2 = 0;
+#pragma unroll
+        for (int j = 0; j < 5; j++) {
+            const uint32_t q = row[j];
+            acc0 += tap[j] * (int)(q & 0xFFu);
+            acc1 += tap[j] * (int)((q >> 8) & 0xFFu);
+            acc2 += tap[j] * (int)((q >> 16) & 0xFFu);
+        }
+        H[3 * e] = acc0;
+        H[3 * e + 1] = acc1;
+        H[3 * e + 2] = acc2;
+    }
+    __syncthreads();
+    const int x = X0 + (threadIdx.x & (PY_TW - 1)), y = Y0 + (threadIdx.x / PY_TW);
+    if (x >= w2 || y >= h2) return;
+    const int u = x - X0, v0 = 2 * (y - Y0);
     int acc[3] = {0, 0, 0};
-    const int u0 = 2 * (x - X0), v0 = 2 * (y - Y0);
 #pragma unroll
     for (int i = 0; i < 5; i++) {
-        int racc[3] = {0, 0, 0};
-#pragma unroll
-        for (int jj = 0; jj < 5; jj++) {
-            const uint32_t t = tile[v0 + i][u0 + jj];
-            racc[0] += tap[jj] * (int)(t & 0xFFu);
-            racc[1] += tap[jj] * (int)((t >> 8) & 0xFFu);
-            racc[2] += tap[jj] * (int)((t >> 16) & 0xFFu);
-        }
-        acc[0] += tap[i] * racc[0];
-        acc[1] += tap[i] * racc[1];
-        acc[2] += tap[i] * racc[2];
+        const int* q = H + 3 * ((v0 + i) * PY_TW + u);
+        acc[0] += tap[i] * q[0];
+        acc[1] += tap[i] * q[1];
+        acc[2] += tap[i] * q[2];
     }
     uint8_t* o = dst + ((size_t)y * w2 + x) * 3;
     o[0] = (uint8_t)((acc[0] + 128) >> 8);
@@ -767,97 +787,112 @@ __global__ __launch_bounds__(256) void k_pyr(const uint8_t* src0, const uint8_t*
 // gradient image (Sec. III-A, Eq. 1-2) written with a replicated PAD border
 // ---------------------------------------------------------------------------------------
 
-// A work-group computes 64 x 4 pixels of the padded gradient image. It first stages the source
-// pixels its 5x5 windows read -- border rules (clamp for the padding, reflect-101 for the
-// filter) applied once at load time -- in LDS, one dword per pixel (R | G << 8 | B << 16, or the
-// integer luma), then every thread forms its Sobel sums from LDS.
-constexpr int GR_TW = 64, GR_TH = 4;
+// A work-group computes 64 x 8 pixels of the padded gradient image. It stages the source
+// pixels (one dword per pixel: R | G << 8 | B << 16, or the integer luma) that the windows of
+// its pixels read -- the padding maps to the nearest image pixel, the filter reflects (101) --
+// applies the smoothing and derivative taps along the staged rows, then across them: the
+// Sobel sums are separable, so the integer results equal the full KS x KS sums.
+constexpr int GR_TW = 64, GR_TH = 8, GR_SU = GR_TW + 4, GR_SV = GR_TH + 4;   // kernel radius <= 2
+constexpr int GR_LDS = GR_SV * GR_SU + GR_SV * GR_TW * 6;                    // dwords
 
 template <int KS, bool GRAY, bool F32>
-__global__ __launch_bounds__(256) void k_gradient(const uint8_t* img0, const uint8_t* img1, long long src_zs,
-                                                  int pitch, int w, int h, void* G0, void* G1, long long dst_zs)
+__device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, int t, int z, uint32_t* lds)
 {
     constexpr int CH = GRAY ? 1 : 3;
     constexpr int C2 = 2 * CH;
     constexpr int K = KS / 2;
-    constexpr int NUX = GR_TW + 2 * K, NVX = GR_TH + 2 * K;
-    __shared__ uint32_t tile[NVX][NUX];
+    uint32_t* S = lds;                          // [NV][GR_SU] staged pixels
+    int* H = (int*)(lds + GR_SV * GR_SU);       // [NV][GR_TW][C2]: row smoothing, row derivative
+    const int w = L.w, h = L.h;
     const int pw = w + 2 * PAD, ph = h + 2 * PAD;
-    const int X0 = blockIdx.x * GR_TW, Y0 = blockIdx.y * GR_TH;
-    const size_t pair = blockIdx.z >> 1;
-    const uint8_t* img = ((blockIdx.z & 1) ? img1 : img0) + pair * (size_t)src_zs;
-    void* G = zoff((blockIdx.z & 1) ? G1 : G0, pair * (size_t)dst_zs);
-    // source columns / rows the tile needs: clamp of the padded coordinates, widened by K
-    const int xlo = clampi(X0 - PAD, 0, w - 1) - K;
-    const int xhi = clampi(min(X0 + GR_TW - 1, pw - 1) - PAD, 0, w - 1) + K;
-    const int ylo = clampi(Y0 - PAD, 0, h - 1) - K;
-    const int yhi = clampi(min(Y0 + GR_TH - 1, ph - 1) - PAD, 0, h - 1) + K;
-    const int NU = xhi - xlo + 1, NV = yhi - ylo + 1;
+    const int X0 = (t % L.tx) * GR_TW, Y0 = (t / L.tx) * GR_TH;
+    const size_t pair = (size_t)(z >> 1);
+    const uint8_t* img = L.src[z & 1] + pair * (size_t)L.src_zs;
+    void* G = zoff(L.G[z & 1], pair * (size_t)dst_zs);
+    // the image columns and rows the tile's pixels map to
+    const int cx0 = clampi(X0 - PAD, 0, w - 1), cx1 = clampi(min(X0 + GR_TW - 1, pw - 1) - PAD, 0, w - 1);
+    const int cy0 = clampi(Y0 - PAD, 0, h - 1), cy1 = clampi(min(Y0 + GR_TH - 1, ph - 1) - PAD, 0, h - 1);
+    const int NC = cx1 - cx0 + 1, NR = cy1 - cy0 + 1;
+    const int NU = NC + 2 * K, NV = NR + 2 * K;
     for (int e = threadIdx.x; e < NU * NV; e += 256) {
         const int v = e / NU, u = e - v * NU;
-        const uint8_t* p = img + (size_t)mirror(ylo + v, h) * pitch + 3 * (size_t)mirror(xlo + u, w);
+        const int x = mirror_fast(cx0 - K + u, w), y = mirror_fast(cy0 - K + v, h);
         uint32_t val;
-        if (GRAY) val = (uint32_t)((77 * p[0] + 150 * p[1] + 29 * p[2] + 128) >> 8);
-        else val = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
-        tile[v][u] = val;
+        if (GRAY) {
+            const uint8_t* p = img + (size_t)y * L.pitch + 3 * (size_t)x;
+            val = (uint32_t)((77 * p[0] + 150 * p[1] + 29 * p[2] + 128) >> 8);
+        } else {
+            val = rgb_at(img, L.pitch, x, y);
+        }
+        S[v * GR_SU + u] = val;
     }
     __syncthreads();
-    const int X = X0 + (threadIdx.x & (GR_TW - 1));
-    const int Y = Y0 + (threadIdx.x / GR_TW);
-    if (X >= pw || Y >= ph) return;
-    const int u0 = clampi(X - PAD, 0, w - 1) - K - xlo;
-    const int v0 = clampi(Y - PAD, 0, h - 1) - K - ylo;
     // smoothing and derivative taps of the size-KS Sobel operator
     const int sm3[3] = {1, 2, 1}, dv3[3] = {-1, 0, 1};
     const int sm5[5] = {1, 4, 6, 4, 1}, dv5[5] = {-1, -2, 0, 2, 1};
-    int gx[CH], gy[CH];
-#pragma unroll
-    for (int c = 0; c < CH; c++) { gx[c] = 0; gy[c] = 0; }
-#pragma unroll
-    for (int i = 0; i < KS; i++) {
+    for (int e = threadIdx.x; e < NV * NC; e += 256) {
+        const int v = e / NC, u = e - v * NC;
+        const uint32_t* row = S + v * GR_SU + u;
         int rs[CH], rd[CH];
 #pragma unroll
         for (int c = 0; c < CH; c++) { rs[c] = 0; rd[c] = 0; }
 #pragma unroll
-        for (int jj = 0; jj < KS; jj++) {
-            const uint32_t t = tile[v0 + i][u0 + jj];
-            const int sm = KS == 3 ? sm3[jj] : sm5[jj];
-            const int dv = KS == 3 ? dv3[jj] : dv5[jj];
+        for (int j = 0; j < KS; j++) {
+            const uint32_t q = row[j];
+            const int sm = KS == 3 ? sm3[j] : sm5[j];
+            const int dv = KS == 3 ? dv3[j] : dv5[j];
 #pragma unroll
             for (int c = 0; c < CH; c++) {
-                const int val = (int)((t >> (8 * c)) & 0xFFu);
+                const int val = (int)((q >> (8 * c)) & 0xFFu);
                 rs[c] += sm * val;
                 rd[c] += dv * val;
             }
         }
-        const int smi = KS == 3 ? sm3[i] : sm5[i];
-        const int dvi = KS == 3 ? dv3[i] : dv5[i];
+        int* o = H + (v * GR_TW + u) * C2;
 #pragma unroll
-        for (int c = 0; c < CH; c++) { gx[c] += smi * rd[c]; gy[c] += dvi * rs[c]; }
+        for (int c = 0; c < CH; c++) { o[c] = rs[c]; o[CH + c] = rd[c]; }
     }
-    const size_t o = ((size_t)Y * pw + X) * C2;
-    if (!F32) {
-        uint16_t vals[C2];
+    __syncthreads();
+    for (int e = threadIdx.x; e < GR_TW * GR_TH; e += 256) {
+        const int X = X0 + (e & (GR_TW - 1)), Y = Y0 + e / GR_TW;
+        if (X >= pw || Y >= ph) continue;
+        const int u = clampi(X - PAD, 0, w - 1) - cx0;
+        const int v = clampi(Y - PAD, 0, h - 1) - cy0;
+        int gx[CH], gy[CH];
 #pragma unroll
-        for (int c = 0; c < CH; c++) {
-            vals[c] = (uint16_t)(gx[c] + (int)BIAS);
-            vals[CH + c] = (uint16_t)(gy[c] + (int)BIAS);
+        for (int c = 0; c < CH; c++) { gx[c] = 0; gy[c] = 0; }
+#pragma unroll
+        for (int i = 0; i < KS; i++) {
+            const int* q = H + ((v + i) * GR_TW + u) * C2;
+            const int smi = KS == 3 ? sm3[i] : sm5[i];
+            const int dvi = KS == 3 ? dv3[i] : dv5[i];
+#pragma unroll
+            for (int c = 0; c < CH; c++) { gx[c] += smi * q[CH + c]; gy[c] += dvi * q[c]; }
         }
-        uint32_t* out = (uint32_t*)((uint16_t*)G + o);   // C2 even: pixels are dword aligned
+        const size_t o = ((size_t)Y * pw + X) * C2;
+        if (!F32) {
+            uint16_t vals[C2];
 #pragma unroll
-        for (int q = 0; q < C2 / 2; q++) out[q] = (uint32_t)vals[2 * q] | ((uint32_t)vals[2 * q + 1] << 16);
-    } else {
-        float* out = (float*)G + o;
-#pragma unroll
-        for (int c = 0; c < CH; c++) {
-            float ux = 0.0f, uy = 0.0f;
-            if (gx[c] != 0 || gy[c] != 0) {
-                const double n = sqrt((double)gx[c] * gx[c] + (double)gy[c] * gy[c]);
-                ux = (float)((double)gx[c] / n);
-                uy = (float)((double)gy[c] / n);
+            for (int c = 0; c < CH; c++) {
+                vals[c] = (uint16_t)(gx[c] + (int)BIAS);
+                vals[CH + c] = (uint16_t)(gy[c] + (int)BIAS);
             }
-            out[c] = ux;
-            out[CH + c] = uy;
+            uint32_t* out = (uint32_t*)((uint16_t*)G + o);   // C2 even: pixels are dword aligned
+#pragma unroll
+            for (int q = 0; q < C2 / 2; q++) out[q] = (uint32_t)vals[2 * q] | ((uint32_t)vals[2 * q + 1] << 16);
+        } else {
+            float* out = (float*)G + o;
+#pragma unroll
+            for (int c = 0; c < CH; c++) {
+                float ux = 0.0f, uy = 0.0f;
+                if (gx[c] != 0 || gy[c] != 0) {
+                    const double n = sqrt((double)gx[c] * gx[c] + (double)gy[c] * gy[c]);
+                    ux = (float)((double)gx[c] / n);
+                    uy = (float)((double)gy[c] / n);
+                }
+                out[c] = ux;
+                out[CH + c] = uy;
+            }
         }
     }
 }
@@ -873,9 +908,8 @@ __device__ __forceinline__ int search_off(uint32_t u, int W, int i)
     return (int)(A >> (32 + i));
 }
 
-__global__ __launch_bounds__(256) void k_rng(RngArgs a)
+__device__ __forceinline__ void rng_item(const RngArgs& a, long long item)
 {
-    long long item = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (item < 2LL * a.n_top) {
         const int dir = (int)(item / a.n_top), s = (int)(item % a.n_top);
         const uint4 u = philox4x32_10(
@@ -919,42 +953,116 @@ __global__ __launch_bounds__(256) void k_rng(RngArgs a)
 }
 
 // ---------------------------------------------------------------------------------------
+// kernels of the image stage. k_prep starts a call with three independent jobs in one launch
+// (work-group ranges): the random numbers, the level-0 gradient images and the first pyramid
+// level; k_pyr builds the further pyramid levels and k_gradient their gradient images (all
+// levels in one launch: blockIdx.x runs over the tiles of each level in turn).
+// ---------------------------------------------------------------------------------------
+
+constexpr int PREP_LDS = GR_LDS > PY_LDS ? GR_LDS : PY_LDS;
+
+template <int KS, bool GRAY, bool F32>
+__global__ __launch_bounds__(256) void k_prep(PrepArgs a)
+{
+    __shared__ uint32_t lds[PREP_LDS];
+    int b = blockIdx.x;
+    if (b < a.rng_blocks) {
+        rng_item(a.rng, (long long)b * 256 + threadIdx.x);
+        return;
+    }
+    b -= a.rng_blocks;
+    if (b < a.grad_blocks) {
+        grad_tile<KS, GRAY, F32>(a.grad.lv[0], a.grad.dst_zs, b % a.grad.lv[0].tiles, b / a.grad.lv[0].tiles, lds);
+        return;
+    }
+    b -= a.grad_blocks;
+    pyr_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
+}
+
+__global__ __launch_bounds__(256) void k_pyr(PyrArgs a)
+{
+    __shared__ uint32_t lds[PY_LDS];
+    pyr_tile(a, blockIdx.x, blockIdx.y, lds);
+}
+
+template <int KS, bool GRAY, bool F32>
+__global__ __launch_bounds__(256) void k_gradient(GradArgs a)
+{
+    __shared__ uint32_t lds[GR_LDS];
+    int lv = 0;
+    while (lv + 1 < a.n && (int)blockIdx.x >= a.lv[lv + 1].base) lv++;
+    grad_tile<KS, GRAY, F32>(a.lv[lv], a.dst_zs, (int)blockIdx.x - a.lv[lv].base, blockIdx.y, lds);
+}
+
+// ---------------------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------------------
 
-hipError_t launch_pyr_down(const uint8_t* src0, const uint8_t* src1, long long src_zs, int pitch, int w, int h,
-                           uint8_t* dst0, uint8_t* dst1, long long dst_zs, int npairs, hipStream_t s)
+static void plan_pyr(PyrArgs& a)
 {
-    const int w2 = (w + 1) / 2, h2 = (h + 1) / 2;
-    dim3 grid((w2 + PY_TW - 1) / PY_TW, (h2 + PY_TH - 1) / PY_TH, 2 * npairs);
-    hipLaunchKernelGGL(k_pyr, grid, dim3(256), 0, s, src0, src1, src_zs, pitch, w, h, dst0, dst1, dst_zs);
+    a.tx = ((a.w + 1) / 2 + PY_TW - 1) / PY_TW;
+    a.tiles = a.tx * (((a.h + 1) / 2 + PY_TH - 1) / PY_TH);
+}
+
+static int plan_grad(GradArgs& a)
+{
+    int total = 0;
+    for (int k = 0; k < a.n; k++) {
+        GradLevel& L = a.lv[k];
+        L.tx = (L.w + 2 * PAD + GR_TW - 1) / GR_TW;
+        L.tiles = L.tx * ((L.h + 2 * PAD + GR_TH - 1) / GR_TH);
+        L.base = total;
+        total += L.tiles;
+    }
+    return total;
+}
+
+hipError_t launch_pyr(PyrArgs a, int npairs, hipStream_t s)
+{
+    plan_pyr(a);
+    hipLaunchKernelGGL(k_pyr, dim3(a.tiles, 2 * npairs), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_gradient(const uint8_t* img0, const uint8_t* img1, long long src_zs, int pitch, int w, int h,
-                           void* G0, void* G1, long long dst_zs, int npairs, int gray, int ksize, int f32,
-                           hipStream_t s)
+#define PGM_IMG_VARIANTS(M) M(3, false, false) M(3, false, true) M(3, true, false) M(3, true, true) \
+    M(5, false, false) M(5, false, true) M(5, true, false) M(5, true, true)
+
+hipError_t launch_gradient(GradArgs a, int npairs, int gray, int ksize, int f32, hipStream_t s)
 {
-    dim3 grid((w + 2 * PAD + GR_TW - 1) / GR_TW, (h + 2 * PAD + GR_TH - 1) / GR_TH, 2 * npairs);
+    const int total = plan_grad(a);
+    if (total == 0) return hipSuccess;
+    dim3 grid(total, 2 * npairs);
 #define PGM_GRAD(KS, GR, F)                                                                       \
     if (ksize == KS && !!gray == GR && !!f32 == F) {                                               \
-        hipLaunchKernelGGL((k_gradient<KS, GR, F>), grid, dim3(256), 0, s, img0, img1, src_zs, pitch, w, \
-                           h, G0, G1, dst_zs);                                                     \
+        hipLaunchKernelGGL((k_gradient<KS, GR, F>), grid, dim3(256), 0, s, a);                     \
         return hipGetLastError();                                                                  \
     }
-    PGM_GRAD(3, false, false) PGM_GRAD(3, false, true) PGM_GRAD(3, true, false) PGM_GRAD(3, true, true)
-    PGM_GRAD(5, false, false) PGM_GRAD(5, false, true) PGM_GRAD(5, true, false) PGM_GRAD(5, true, true)
+    PGM_IMG_VARIANTS(PGM_GRAD)
 #undef PGM_GRAD
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_rng(const RngArgs& a, hipStream_t s)
+hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int f32, hipStream_t s)
 {
-    const long long items = 2LL * a.n_top + a.total_items;
-    if (items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rng, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
+    const long long items = 2LL * a.rng.n_top + a.rng.total_items;
+    if ((items + 255) / 256 > 0x40000000LL) return hipErrorInvalidValue;
+    a.rng_blocks = (int)((items + 255) / 256);
+    a.grad.n = 1;
+    a.grad_blocks = plan_grad(a.grad) * 2 * npairs;
+    if (a.with_pyr) plan_pyr(a.pyr);
+    const long long blocks = (long long)a.rng_blocks + a.grad_blocks + (a.with_pyr ? (long long)a.pyr.tiles * 2 * npairs : 0);
+    if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+#define PGM_PREP(KS, GR, F)                                                                       \
+    if (ksize == KS && !!gray == GR && !!f32 == F) {                                               \
+        hipLaunchKernelGGL((k_prep<KS, GR, F>), dim3((unsigned)blocks), dim3(256), 0, s, a);       \
+        return hipGetLastError();                                                                  \
+    }
+    PGM_IMG_VARIANTS(PGM_PREP)
+#undef PGM_PREP
+    return hipErrorInvalidValue;
 }
+
+#undef PGM_IMG_VARIANTS
 
 // Kernel variants: patch side exactly 8 or 16 (fully unrolled rows), or any side up to 8 /
 // up to 16 with masked rows; 6 or 2 gradient channels; integer or float features.
