@@ -162,10 +162,12 @@ PGM_API pgm_status pgm_dump_pyramid(void* ctx, int32_t level, int32_t image, uin
  * the number of launches, their summed duration in milliseconds and their summed distance
  * evaluations since the last clear. Kinds (PGM_K_PREP: the first launch of a call, which
  * draws the random numbers and builds the level-0 gradients and pyramid level 1;
- * PGM_K_PYRAMID: pyramid levels 2 and up; PGM_K_GRADIENT: gradients of levels 1 and up): */
+ * PGM_K_PYRAMID: pyramid levels 2 and up; PGM_K_GRADIENT: gradients of levels 1 and up;
+ * PGM_K_LEVEL: all sweeps of a level small enough for one work-group's LDS, whose distance
+ * evaluations count under PGM_K_SWEEP): */
 enum { PGM_K_PYRAMID = 0, PGM_K_GRADIENT = 1, PGM_K_PREP = 2, PGM_K_INIT = 3, PGM_K_DOWN = 4,
        PGM_K_UP = 5, PGM_K_SWEEP = 6, PGM_K_CHECK = 7, PGM_K_OUTPUT = 8, PGM_K_COMPACT = 9,
-       PGM_K_KINDS = 10 };
+       PGM_K_LEVEL = 10, PGM_K_KINDS = 11 };
 PGM_API pgm_status pgm_profile(void* ctx, int32_t enable);
 PGM_API pgm_status pgm_profile_read(void* ctx, int32_t kind, int64_t* host_launches,
                                     double* host_total_ms, uint64_t* host_evals);

@@ -181,10 +181,23 @@ void fill_sizes(const Layout& Y, pgm_sizes* s)
     s->workspace_pair_bytes = Y.pair_bytes;
 }
 
+// LDS layout of a whole-level sweep launch at level l, if it fits in lds_max bytes
+bool level_layout(const Layout& Y, int l, size_t lds_max, LevelLayout& o)
+{
+    const size_t n = (size_t)Y.lnx[l] * Y.lny[l];
+    const size_t graw = (size_t)(Y.lw[l] + 2 * PAD) * (Y.lh[l] + 2 * PAD) * Y.C2 * Y.esize;
+    o.gstride = (graw + 15) & ~(size_t)15;
+    o.disp = 2 * o.gstride;
+    o.dist = o.disp + n * 4;
+    o.total = (o.dist + n * 4 + 15) & ~(size_t)15;
+    return o.total + 64 <= lds_max;   // room for the kernel's static LDS
+}
+
 }  // namespace
 
 struct pgm_ctx_s {
     int device = 0;
+    size_t lds_max = 0;            // LDS bytes a work-group may use on this device
     uint8_t* ws = nullptr;
     size_t ws_bytes = 0;
     std::string err;
@@ -290,6 +303,11 @@ pgm_status pgm_create(int32_t device, uint64_t workspace_bytes, void** out_ctx)
     e = hipSetDevice(device);
     if (e == hipSuccess) e = hipMalloc((void**)&c->ws, c->ws_bytes);
     if (e == hipSuccess) e = hipMalloc((void**)&c->prof_evals, PGM_K_KINDS * sizeof(unsigned long long));
+    if (e == hipSuccess) {
+        int v = 0;
+        e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+        c->lds_max = v > 0 ? (size_t)v : 0;
+    }
     if (e != hipSuccess) {
         if (c->ws) (void)hipFree(c->ws);
         if (c->prof_evals) (void)hipFree(c->prof_evals);
@@ -523,8 +541,23 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
                 }
             }
         }
+        // Step 1 of a small level in one work-group per pair and direction, from LDS
+        LevelArgs la;
+        memset(&la, 0, sizeof la);
+        const bool in_lds = shared && p->iters[l] > 0 && level_layout(Y, l, c->lds_max, la.lay);
+        if (in_lds) {
+            for (int q = 0; q < 2; q++) la.d[q] = dirargs(q, l, k);
+            la.g = g;
+            la.b = batch(2);
+            la.iters = p->iters[l];
+            la.nI = Y.st_nI[k];
+            la.cnt = ctable(CNT_SWEEP, 2);
+            la.gbytes = la.lay.gstride;
+            la.gorig = ((size_t)PAD * (Y.lw[l] + 2 * PAD) + PAD) * Y.C2 * Y.esize;
+            PGM_HIP(c, timed(PGM_K_LEVEL, [&] { return launch_level(la, Y.C2, Y.f32, s); }));
+        }
         // Step 1: iterations of propagation and limited random search, red then black
-        for (int t = 0; t < p->iters[l]; t++)
+        for (int t = 0; t < (in_lds ? 0 : p->iters[l]); t++)
             for (int colour = 0; colour < 2; colour++)
                 for (int pass = 0; pass < (shared ? 1 : 2); pass++) {
                     const int nd = shared ? 2 : 1;

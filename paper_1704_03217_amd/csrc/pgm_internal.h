@@ -89,6 +89,21 @@ struct CheckArgs {
     int fwd_bwd, tau2, rec_valid;
 };
 
+// LDS layout of a whole-level sweep launch (byte offsets; gstride: bytes per gradient image)
+struct LevelLayout {
+    size_t gstride, disp, dist, total;
+};
+struct LevelArgs {
+    DirArgs d[2];          // both directions, pair 0 (in HBM)
+    Geo g;
+    Batch b;
+    int iters, nI;
+    uint32_t* cnt;         // two sweep-count slots (one per direction) per pair, pair 0 (or null)
+    size_t gbytes;         // bytes of one padded gradient image (a multiple of 16)
+    size_t gorig;          // byte offset of pixel (0, 0) inside it
+    LevelLayout lay;
+};
+
 struct OutArgs {
     Field f;               // level-0 field of one direction, pair 0
     Geo g;
@@ -179,6 +194,8 @@ hipError_t launch_sweep(const SweepArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_down(const TransArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_up(const TransArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);
+// every sweep of a small level, one work-group per pair and direction
+hipError_t launch_level(const LevelArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_output(const OutArgs& a, hipStream_t s);
 hipError_t launch_compact(const OutArgs& a, hipStream_t s);
 // part: pair 0's array of COUNT_SLICES * CountArgs::KINDS partial sums; pair z's array is at

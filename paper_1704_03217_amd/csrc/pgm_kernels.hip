@@ -299,6 +299,114 @@ __device__ __forceinline__ void count_evals(uint32_t* cnt, int slot, uint32_t ne
 // Step 1 (Sec. III-B): one colour of one propagation + limited random search iteration
 // ---------------------------------------------------------------------------------------
 
+// One seed's half-sweep step (Step 1): propagation (Eq. 4) then limited random search
+// (Eq. 5) for seed (i, j) of field D at iteration t; returns the distance evaluations made.
+// The group's lanes all call it for the same seed; lane 0 writes the result.
+template <class Row, int LPS>
+__device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, int i, int j, int t, int nI, int r)
+{
+    uint32_t nev = 0;
+    const int s = j * g.nx + i;
+    const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
+    const int P = D.P;
+    Row A;
+    load_own(A, D.Ga, g, P, r, px, py);
+    const uint32_t cur0 = D.f.disp[s];
+    const uint32_t cd0 = D.f.dist[s];
+    const bool init0 = cur0 != UNINIT;
+    // Eq. 5 offsets of the first two random candidates (nI >= 1), fetched with the field;
+    // the neighbours' fields are read from clamped indices and masked, so that every read
+    // of this phase is in flight at once
+    const short2* R = D.rnd + ((size_t)t * (size_t)(g.nx * g.ny) + s) * nI;
+    short2 o0 = R[0], o1 = R[nI > 1 ? 1 : 0];
+
+    // Eq. 4: Omega = {F(p), F(p - Dx) + Dx, F(p - Dy) + Dy} with the FlowFields order
+    // (1,0),(0,1) -> (-1,0),(0,-1) -> (-1,0),(0,1) -> (1,0),(0,-1); members whose
+    // neighbour is uninitialised are ignored.
+    const int k = t & 3;
+    const int sx = (k == 0 || k == 3) ? 1 : -1;
+    const int sy = (k == 0 || k == 2) ? 1 : -1;
+    uint32_t c[2], nv[2];
+    bool ok[2];
+#pragma unroll
+    for (int m = 0; m < 2; m++) {
+        const int ni = m == 0 ? i - sx : i;
+        const int nj = m == 0 ? j : j - sy;
+        ok[m] = ni >= 0 && nj >= 0 && ni < g.nx && nj < g.ny;
+        nv[m] = D.f.disp[clampi(nj, 0, g.ny - 1) * g.nx + clampi(ni, 0, g.nx - 1)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = 0; m < 2; m++) {
+        ok[m] = ok[m] && nv[m] != UNINIT;
+        const uint32_t tg = target(px, py, d_x(nv[m]), d_y(nv[m]), g);
+        c[m] = ok[m] ? tg : cur0;
+    }
+    // Both members are priced together. A member equal to F(p) costs the stored distance
+    // and one equal to the other member costs what that one costs, so only new patches
+    // are read; the decisions below replay the paper's one-at-a-time order exactly.
+    const bool need0 = ok[0] && !(init0 && c[0] == cur0);
+    const bool need1 = ok[1] && !(init0 && c[1] == cur0) && !(ok[0] && c[1] == c[0]);
+    uint32_t e[2] = {cd0, cd0};
+    if (need0 || need1) {
+        const uint32_t qa = need0 ? c[0] : c[1], qb = need1 ? c[1] : c[0];
+        uint32_t ea, eb;
+        patch_cost2<Row, LPS>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb), ea, eb);
+        if (need0) e[0] = ea;
+        if (need1) e[1] = eb;
+    }
+    if (ok[1] && !need1 && !(init0 && c[1] == cur0)) e[1] = e[0];
+    uint32_t cur = cur0, cd = cd0;
+    bool init = init0, changed = false;
+#pragma unroll
+    for (int m = 0; m < 2; m++) {
+        if (!ok[m] || (init && c[m] == cur)) continue;
+        nev++;
+        if (!init || e[m] < cd) { cur = c[m]; cd = e[m]; init = true; changed = true; }
+    }
+
+    // Eq. 5: Psi = {F(p)} + {F(p) + floor(R_i W / 2^i)}, all around the propagated match,
+    // priced two at a time in the same way and decided in order
+    if (init) {
+        const int cx = d_x(cur), cy = d_y(cur);
+        const uint32_t curp = cur, cdp = cd;
+        for (int ii = 0; ii < nI; ii += 2) {
+            if (ii > 0) {
+                o0 = R[ii];
+                if (ii + 1 < nI) o1 = R[ii + 1];
+            }
+            const bool two = ii + 1 < nI;
+            const uint32_t r0 = target(px, py, cx + o0.x, cy + o0.y, g);
+            const uint32_t r1 = two ? target(px, py, cx + o1.x, cy + o1.y, g) : curp;
+            const bool n0 = r0 != curp;
+            const bool n1 = r1 != curp && r1 != r0;
+            uint32_t f0 = cdp, f1 = cdp;
+            if (n0 || n1) {
+                const uint32_t qa = n0 ? r0 : r1, qb = n1 ? r1 : r0;
+                uint32_t ea, eb;
+                patch_cost2<Row, LPS>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb),
+                                      ea, eb);
+                if (n0) f0 = ea;
+                if (n1) f1 = eb;
+            }
+            if (two && !n1 && r1 != curp) f1 = f0;
+            if (r0 != cur) {
+                nev++;
+                if (f0 < cd) { cur = r0; cd = f0; changed = true; }
+            }
+            if (two && r1 != cur) {
+                nev++;
+                if (f1 < cd) { cur = r1; cd = f1; changed = true; }
+            }
+        }
+    }
+    if (changed && r == 0) {
+        D.f.disp[s] = cur;
+        D.f.dist[s] = cd;
+    }
+    return nev;
+}
+
 template <int C2, int PMAX, bool FIXED, bool F32>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 {
@@ -316,106 +424,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     const int j = gid / hx;
     const int i = 2 * (gid - j * hx) + ((a.colour + j) & 1);
     uint32_t nev = 0;
-    if (j < g.ny && i < g.nx) {
-        const int s = j * g.nx + i;
-        const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
-        const int P = D.P;
-        Row A;
-        load_own(A, D.Ga, g, P, r, px, py);
-        const uint32_t cur0 = D.f.disp[s];
-        const uint32_t cd0 = D.f.dist[s];
-        const bool init0 = cur0 != UNINIT;
-        // Eq. 5 offsets of the first two random candidates (nI >= 1), fetched with the field;
-        // the neighbours' fields are read from clamped indices and masked, so that every read
-        // of this phase is in flight at once
-        const short2* R = D.rnd + ((size_t)a.t * (size_t)(g.nx * g.ny) + s) * a.nI;
-        short2 o0 = R[0], o1 = R[a.nI > 1 ? 1 : 0];
-
-        // Eq. 4: Omega = {F(p), F(p - Dx) + Dx, F(p - Dy) + Dy} with the FlowFields order
-        // (1,0),(0,1) -> (-1,0),(0,-1) -> (-1,0),(0,1) -> (1,0),(0,-1); members whose
-        // neighbour is uninitialised are ignored.
-        const int k = a.t & 3;
-        const int sx = (k == 0 || k == 3) ? 1 : -1;
-        const int sy = (k == 0 || k == 2) ? 1 : -1;
-        uint32_t c[2], nv[2];
-        bool ok[2];
-#pragma unroll
-        for (int m = 0; m < 2; m++) {
-            const int ni = m == 0 ? i - sx : i;
-            const int nj = m == 0 ? j : j - sy;
-            ok[m] = ni >= 0 && nj >= 0 && ni < g.nx && nj < g.ny;
-            nv[m] = D.f.disp[clampi(nj, 0, g.ny - 1) * g.nx + clampi(ni, 0, g.nx - 1)];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int m = 0; m < 2; m++) {
-            ok[m] = ok[m] && nv[m] != UNINIT;
-            const uint32_t t = target(px, py, d_x(nv[m]), d_y(nv[m]), g);
-            c[m] = ok[m] ? t : cur0;
-        }
-        // Both members are priced together. A member equal to F(p) costs the stored distance
-        // and one equal to the other member costs what that one costs, so only new patches
-        // are read; the decisions below replay the paper's one-at-a-time order exactly.
-        const bool need0 = ok[0] && !(init0 && c[0] == cur0);
-        const bool need1 = ok[1] && !(init0 && c[1] == cur0) && !(ok[0] && c[1] == c[0]);
-        uint32_t e[2] = {cd0, cd0};
-        if (need0 || need1) {
-            const uint32_t qa = need0 ? c[0] : c[1], qb = need1 ? c[1] : c[0];
-            uint32_t ea, eb;
-            patch_cost2<Row, LPS>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb), ea, eb);
-            if (need0) e[0] = ea;
-            if (need1) e[1] = eb;
-        }
-        if (ok[1] && !need1 && !(init0 && c[1] == cur0)) e[1] = e[0];
-        uint32_t cur = cur0, cd = cd0;
-        bool init = init0, changed = false;
-#pragma unroll
-        for (int m = 0; m < 2; m++) {
-            if (!ok[m] || (init && c[m] == cur)) continue;
-            nev++;
-            if (!init || e[m] < cd) { cur = c[m]; cd = e[m]; init = true; changed = true; }
-        }
-
-        // Eq. 5: Psi = {F(p)} + {F(p) + floor(R_i W / 2^i)}, all around the propagated match,
-        // priced two at a time in the same way and decided in order
-        if (init) {
-            const int cx = d_x(cur), cy = d_y(cur);
-            const uint32_t curp = cur, cdp = cd;
-            for (int ii = 0; ii < a.nI; ii += 2) {
-                if (ii > 0) {
-                    o0 = R[ii];
-                    if (ii + 1 < a.nI) o1 = R[ii + 1];
-                }
-                const bool two = ii + 1 < a.nI;
-                const uint32_t r0 = target(px, py, cx + o0.x, cy + o0.y, g);
-                const uint32_t r1 = two ? target(px, py, cx + o1.x, cy + o1.y, g) : curp;
-                const bool n0 = r0 != curp;
-                const bool n1 = r1 != curp && r1 != r0;
-                uint32_t f0 = cdp, f1 = cdp;
-                if (n0 || n1) {
-                    const uint32_t qa = n0 ? r0 : r1, qb = n1 ? r1 : r0;
-                    uint32_t ea, eb;
-                    patch_cost2<Row, LPS>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb),
-                                          ea, eb);
-                    if (n0) f0 = ea;
-                    if (n1) f1 = eb;
-                }
-                if (two && !n1 && r1 != curp) f1 = f0;
-                if (r0 != cur) {
-                    nev++;
-                    if (f0 < cd) { cur = r0; cd = f0; changed = true; }
-                }
-                if (two && r1 != cur) {
-                    nev++;
-                    if (f1 < cd) { cur = r1; cd = f1; changed = true; }
-                }
-            }
-        }
-        if (changed && r == 0) {
-            D.f.disp[s] = cur;
-            D.f.dist[s] = cd;
-        }
-    }
+    if (j < g.ny && i < g.nx) nev = sweep_seed<Row, LPS>(D, g, i, j, a.t, a.nI, r);
     count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, r == 0);
 }
 
@@ -582,6 +591,27 @@ __global__ __launch_bounds__(256) void k_up(TransArgs a)
 // Step 2-3: forward-backward consistency check and the record update of Eq. 7
 // ---------------------------------------------------------------------------------------
 
+// Steps 2-3 for seed s of field F against the opposite field O
+__device__ __forceinline__ void check_seed(const Field& F, const Field& O, const Geo& g, int s, int fwd_bwd, int tau2,
+                                           int rec_valid)
+{
+    const uint32_t d = F.disp[s];
+    bool ok = d != UNINIT;
+    if (ok && fwd_bwd) {
+        const int i = s % g.nx, j = s / g.nx;
+        const int qx = grid_pos(i, g.w, g) + d_x(d), qy = grid_pos(j, g.h, g) + d_y(d);
+        const uint32_t od = O.disp[grid_near(qy, g.ny, g) * g.nx + grid_near(qx, g.nx, g)];
+        if (od == UNINIT) ok = false;
+        else {
+            const int ex = d_x(d) + d_x(od), ey = d_y(d) + d_y(od);
+            ok = ex * ex + ey * ey <= tau2;
+        }
+    }
+    const uint8_t fl = F.flags[s];
+    const bool inl = rec_valid ? (ok && (fl & ST_REC)) : ok;
+    F.flags[s] = (uint8_t)((fl & ST_REC) | (inl ? ST_INL : 0));
+}
+
 __global__ __launch_bounds__(256) void k_check(CheckArgs a)
 {
     const Geo& g = a.g;
@@ -590,21 +620,84 @@ __global__ __launch_bounds__(256) void k_check(CheckArgs a)
     const size_t zo = (size_t)blockIdx.z * (size_t)a.b.zs;
     const Field F = pair_field(a.f[blockIdx.y], zo);
     const Field O = pair_field(a.f[1 - blockIdx.y], zo);
-    const uint32_t d = F.disp[s];
-    bool ok = d != UNINIT;
-    if (ok && a.fwd_bwd) {
-        const int i = s % g.nx, j = s / g.nx;
-        const int qx = grid_pos(i, g.w, g) + d_x(d), qy = grid_pos(j, g.h, g) + d_y(d);
-        const uint32_t od = O.disp[grid_near(qy, g.ny, g) * g.nx + grid_near(qx, g.nx, g)];
-        if (od == UNINIT) ok = false;
-        else {
-            const int ex = d_x(d) + d_x(od), ey = d_y(d) + d_y(od);
-            ok = ex * ex + ey * ey <= a.tau2;
+    check_seed(F, O, g, s, a.fwd_bwd, a.tau2, a.rec_valid);
+}
+
+// ---------------------------------------------------------------------------------------
+// Step 1 of a small level in one work-group per pair and direction: both gradient images and
+// the field are copied into LDS, every half-sweep runs between work-group barriers and the
+// field goes back to HBM (Steps 2-3 follow in k_check). The seeds and their decisions are
+// those of k_sweep; only the memory they live in differs.
+// ---------------------------------------------------------------------------------------
+
+template <int PMAX, bool F32>
+struct LevelShape {
+    // the sweep's registers per lane bound the work-group size
+    static constexpr int threads = !F32 ? (PMAX == 8 ? 1024 : 512) : (PMAX == 8 ? 512 : 256);
+};
+
+template <int C2, int PMAX, bool FIXED, bool F32>
+__global__ __launch_bounds__((LevelShape<PMAX, F32>::threads)) void k_level(LevelArgs a)
+{
+    using Row = RowT<C2, PMAX, FIXED, F32>;
+    constexpr int LPS = PMAX;
+    constexpr int NT = LevelShape<PMAX, F32>::threads;
+    constexpr int NG = NT / LPS;
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint32_t evsum;
+    const Geo& g = a.g;
+    const int n = g.nx * g.ny;
+    const int dir = blockIdx.x & 1;
+    const size_t zo = (size_t)(blockIdx.x >> 1) * (size_t)a.b.zs;
+    const DirArgs H = pair_dir(a.d[dir], zo);
+    const LevelLayout& Y = a.lay;
+    uint8_t* GA = lds;
+    uint8_t* GB = lds + Y.gstride;
+    uint32_t* disp = (uint32_t*)(lds + Y.disp);
+    uint32_t* dist = (uint32_t*)(lds + Y.dist);
+    // copy in: both padded gradient images (16-byte pieces) and the field
+    {
+        const uint4* sa = (const uint4*)((const uint8_t*)H.Ga - a.gorig);
+        const uint4* sb = (const uint4*)((const uint8_t*)H.Gb - a.gorig);
+        const int nq = (int)(a.gbytes / 16);   // gbytes is rounded up to 16 inside the 256-aligned image
+        for (int q = threadIdx.x; q < nq; q += NT) {
+            ((uint4*)GA)[q] = sa[q];
+            ((uint4*)GB)[q] = sb[q];
+        }
+        for (int q = threadIdx.x; q < n; q += NT) {
+            disp[q] = H.f.disp[q];
+            dist[q] = H.f.dist[q];
+        }
+        if (threadIdx.x == 0) evsum = 0;
+    }
+    __syncthreads();
+    DirArgs L = H;
+    L.Ga = GA + a.gorig;
+    L.Gb = GB + a.gorig;
+    L.f.disp = disp;
+    L.f.dist = dist;
+    L.f.flags = nullptr;   // not used by Step 1
+    const int r = threadIdx.x % LPS;
+    const int hx = (g.nx + 1) >> 1;
+    const int per = hx * g.ny;
+    uint32_t nev = 0;
+    for (int t = 0; t < a.iters; t++) {
+        for (int colour = 0; colour < 2; colour++) {
+            for (int q = threadIdx.x / LPS; q < per; q += NG) {
+                const int j = q / hx;
+                const int i = 2 * (q - j * hx) + ((colour + j) & 1);
+                if (i < g.nx) nev += sweep_seed<Row, LPS>(L, g, i, j, t, a.nI, r);
+            }
+            __syncthreads();
         }
     }
-    const uint8_t fl = F.flags[s];
-    const bool inl = a.rec_valid ? (ok && (fl & ST_REC)) : ok;
-    F.flags[s] = (uint8_t)((fl & ST_REC) | (inl ? ST_INL : 0));
+    if (r == 0 && nev) atomicAdd(&evsum, nev);
+    for (int q = threadIdx.x; q < n; q += NT) {
+        H.f.disp[q] = disp[q];
+        H.f.dist[q] = dist[q];
+    }
+    __syncthreads();
+    if (a.cnt && threadIdx.x == 0) zoff(a.cnt, zo)[dir] = evsum;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1108,6 +1201,30 @@ hipError_t launch_up(const TransArgs& a, int C2, int f32, hipStream_t s)
 
 #undef PGM_V
 #undef PGM_DISPATCH
+
+template <int C2, int PM, bool FX, bool F>
+static hipError_t launch_level_v(const LevelArgs& a, hipStream_t s)
+{
+    const void* fn = (const void*)k_level<C2, PM, FX, F>;
+    const size_t bytes = a.lay.total;
+    if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipLaunchKernelGGL((k_level<C2, PM, FX, F>), dim3(2 * a.b.npairs), dim3(LevelShape<PM, F>::threads), bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_level(const LevelArgs& a, int C2, int f32, hipStream_t s)
+{
+    const int P = a.d[0].P;
+    const int pmax = P <= 8 ? 8 : 16;
+    const bool fixed = P == pmax;
+#define PGM_LV(C2_, PM_, FX_)                                                                    \
+    if (C2 == C2_ && pmax == PM_ && fixed == FX_)                                                \
+        return f32 ? launch_level_v<C2_, PM_, FX_, true>(a, s) : launch_level_v<C2_, PM_, FX_, false>(a, s);
+    PGM_LV(6, 8, true) PGM_LV(6, 8, false) PGM_LV(6, 16, true) PGM_LV(6, 16, false)
+    PGM_LV(2, 8, true) PGM_LV(2, 8, false) PGM_LV(2, 16, true) PGM_LV(2, 16, false)
+#undef PGM_LV
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_check(const CheckArgs& a, hipStream_t s)
 {
