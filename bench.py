@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--batch", type=int, default=32, help="pairs per step of the batched pass (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device (a known-size kernel for HBM counter scaling)")
     return ap.parse_args()
 
 
@@ -102,6 +104,14 @@ def main():
     print(f"[bench] generating {args.pairs} synthetic 1024x436 pairs", file=sys.stderr, flush=True)
     pairs = [synth.config_pair(2, i) for i in range(args.pairs)]
     imgs = [(torch.from_numpy(p.img1).to(dev), torch.from_numpy(p.img2).to(dev)) for p in pairs]
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {nbytes} bytes done", file=sys.stderr, flush=True)
+        del src, dst
     m = pgm.Matcher(0, 256 << 20)
     outs = [m.outputs(params, w, h, bwd=True, compact=True, count_evals=True) for _ in imgs]
     stream = torch.cuda.current_stream(dev).cuda_stream
