@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -44,6 +46,10 @@ def parse():
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--batch", type=int, default=32, help="pairs per step of the batched pass (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--groups-pairs", type=int, default=64, help="pairs of the uneven-size batch (0 = skip)")
+    ap.add_argument("--groups-steps", type=int, default=10)
+    ap.add_argument("--served", type=int, default=240, help="requests per served run (0 = skip)")
+    ap.add_argument("--served-pool", type=int, default=24, help="distinct generated request pairs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a known-size kernel for HBM counter scaling)")
     return ap.parse_args()
@@ -84,6 +90,121 @@ def sweep_roofline(pgm, ctx, steps, run, torch):
     return roof, kernels
 
 
+def _gen(args):
+    import synth
+    config, index, size = args
+    return synth.config_pair(config, index, size)
+
+
+def generate(jobs):
+    """Seeded synthetic pairs, generated in worker processes."""
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=min(8, max(1, len(jobs)))) as ex:
+        return list(ex.map(_gen, jobs))
+
+
+def sized_params(pgm, w):
+    """Configuration-2 matching parameters with |d| <= ceil(w / 5) (uneven and served pairs)."""
+    p = pgm.pgm_default_params(pgm.PRESET_CONFIG2)
+    p.max_disp = -(-w // 5)
+    return p
+
+
+def run_groups(pgm, torch, dev, args, stream, pre):
+    """64 pairs of uneven sizes, grouped by size into one pgm_match_groups call per step
+    (captured into one HIP graph and replayed)."""
+    sizes, pairs = pre["groups"]
+    by = {}
+    for sz, pr in zip(sizes, pairs):
+        by.setdefault(tuple(sz), []).append(pr)
+    need = 0
+    for (w, h), prs in by.items():
+        q = pgm.pgm_query(sized_params(pgm, w), w, h)
+        need += (q.workspace_shared_bytes + len(prs) * q.workspace_pair_bytes + 255) // 256 * 256
+    m = pgm.Matcher(0, need + (1 << 20))
+    items, keep = [], []
+    for (w, h), prs in sorted(by.items()):
+        p = sized_params(pgm, w)
+        a = torch.from_numpy(np.stack([q.img1 for q in prs])).to(dev)
+        b = torch.from_numpy(np.stack([q.img2 for q in prs])).to(dev)
+        o = m.outputs_batch(p, w, h, len(prs), count_evals=False)
+        items.append((p, a, b, o))
+    nev = torch.zeros(1, dtype=torch.int64, device=dev)
+    # eager reference, then graph replays (the first one captures)
+    m.match_groups_into(items, n_evals=nev, stream=stream)
+    torch.cuda.synchronize()
+    evals_per_step = int(nev.item())
+    ref = [o["fwd"].clone() for *_, o in items]
+    for k in range(2):
+        m.match_groups_into(items, use_graph=True, stream=stream)
+    torch.cuda.synchronize()
+    same = all(torch.equal(o["fwd"], r) for (*_, o), r in zip(items, ref))
+    print(f"[bench] uneven batch: timing {args.groups_steps} graph launches", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.groups_steps):
+        m.match_groups_into(items, use_graph=True, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n = args.groups_pairs * args.groups_steps
+    m.close()
+    return {"value": round(n / (t1 - t0), 3), "unit": "pairs/s", "pairs_per_step": args.groups_pairs,
+            "steps": args.groups_steps, "ms_per_step": round(1000.0 * (t1 - t0) / args.groups_steps, 4),
+            "sizes": {f"{w}x{h}": len(v) for (w, h), v in sorted(by.items())},
+            "dist_evals_per_s": round(evals_per_step * args.groups_steps / (t1 - t0), 1),
+            "graph_equals_eager": same,
+            "workload": "64 pairs, sizes uniform over 320x240, 640x480, 1024x436, 1242x375 (rectangle-layer "
+                        "generator, |d| <= w/5), config-2 matching with max_disp = ceil(w/5); grouped by size, "
+                        "groups concurrent on 4 streams, one HIP graph launch per step"}
+
+
+def run_served(pgm, torch, dev, args, pre):
+    """Poisson request streams through the request server: capacity (all requests at once),
+    then arrivals at 50% and 80% of it; latency from arrival to observed completion."""
+    sizes, pool = pre["served"]
+    imgs = [(torch.from_numpy(q.img1).to(dev), torch.from_numpy(q.img2).to(dev)) for q in pool]
+    prm = [sized_params(pgm, w) for (w, h) in sizes]
+    rng = np.random.default_rng(5001)
+    order = rng.integers(0, len(pool), args.served)
+    need = max((pgm.pgm_query(prm[k], w, h).workspace_bytes + 255) // 256 * 256 for k, (w, h) in enumerate(sizes))
+    srv = pgm.Server(0, 16 * need, 4)
+
+    def run(arrivals):
+        lat = np.zeros(len(arrivals))
+        subm, done = 0, 0
+        t0 = time.perf_counter()
+        while done < len(arrivals):
+            now = time.perf_counter() - t0
+            while subm < len(arrivals) and arrivals[subm] <= now:
+                k = int(order[subm])
+                srv.submit(prm[k], imgs[k][0], imgs[k][1], tag=subm)
+                subm += 1
+            for tag, _ in srv.poll():
+                lat[tag] = (time.perf_counter() - t0) - arrivals[tag]
+                done += 1
+        return lat, time.perf_counter() - t0
+
+    run(np.zeros(min(16, args.served)))    # warm-up
+    lat, span = run(np.zeros(args.served))
+    capacity = args.served / span
+    out = {"unit": "ms", "capacity_pairs_per_s": round(capacity, 2), "requests": args.served,
+           "streams": 4, "pool_bytes": 16 * need, "distinct_pairs": len(pool),
+           "workload": "Poisson arrivals; sizes log-uniform in area over [320x240, 2048x1024], aspect "
+                       "U[1.3, 3.3] (rectangle-layer generator, |d| <= w/5); config-2 matching with "
+                       "max_disp = ceil(w/5); requests drawn from the distinct generated pairs"}
+    for frac in (0.5, 0.8):
+        qps = frac * capacity
+        arr = np.cumsum(rng.exponential(1.0 / qps, args.served))
+        arr -= arr[0]
+        print(f"[bench] served at {qps:.0f} pairs/s", file=sys.stderr, flush=True)
+        lat, span = run(arr)
+        out[f"at_{int(frac * 100)}pct"] = {"qps": round(qps, 2), "p50_ms": round(1000 * float(np.percentile(lat, 50)), 3),
+                                           "p99_ms": round(1000 * float(np.percentile(lat, 99)), 3),
+                                           "pairs_per_s": round(args.served / span, 2)}
+    srv.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -97,12 +218,31 @@ def main():
     import paper_1704_03217_amd as pgm
     import synth
 
+    # every synthetic pair is generated (in worker processes) before the GPU is first touched
+    print(f"[bench] generating {args.pairs} synthetic 1024x436 pairs", file=sys.stderr, flush=True)
+    pre = {}
+    jobs = [(2, i, None) for i in range(args.pairs)]
+    if args.groups_pairs > 0:
+        gsizes = [tuple(sz) for sz in synth.batch_sizes(4000, args.groups_pairs)]
+        jobs += [(4, k, sz) for k, sz in enumerate(gsizes)]
+        print(f"[bench] generating {len(gsizes)} uneven-size pairs", file=sys.stderr, flush=True)
+    if args.served > 0:
+        ssizes = [tuple(sz) for sz in synth.served_sizes(5000, args.served_pool)]
+        jobs += [(5, k, sz) for k, sz in enumerate(ssizes)]
+        print(f"[bench] generating {len(ssizes)} served-size pairs", file=sys.stderr, flush=True)
+    made = generate(jobs)
+    pairs = made[: args.pairs]
+    rest = made[args.pairs:]
+    if args.groups_pairs > 0:
+        pre["groups"] = (gsizes, rest[: len(gsizes)])
+        rest = rest[len(gsizes):]
+    if args.served > 0:
+        pre["served"] = (ssizes, rest)
+
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     params = pgm.pgm_default_params(pgm.PRESET_CONFIG2)
     w, h = 1024, 436
-    print(f"[bench] generating {args.pairs} synthetic 1024x436 pairs", file=sys.stderr, flush=True)
-    pairs = [synth.config_pair(2, i) for i in range(args.pairs)]
     imgs = [(torch.from_numpy(p.img1).to(dev), torch.from_numpy(p.img2).to(dev)) for p in pairs]
     if args.copy_calibration > 0:
         nbytes = args.copy_calibration << 20
@@ -180,6 +320,9 @@ def main():
                    "roofline": broof, "kernels": bkern}
         mb.close()
 
+    groups = run_groups(pgm, torch, dev, args, stream, pre) if args.groups_pairs > 0 else None
+    served = run_served(pgm, torch, dev, args, pre) if args.served > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -219,7 +362,9 @@ def main():
         "n_inliers_pair0": n_inl,
         "roofline": roofline,
         "kernels": kernels,
-        "batched": batched,
+        "batched": groups,
+        "batched_uniform": batched,
+        "served": served,
         "cpu_baseline": cpu,
     }
     m.close()

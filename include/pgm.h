@@ -144,6 +144,58 @@ PGM_API pgm_status pgm_match_batch(void* ctx, const pgm_params* p, int32_t n_pai
                                    int32_t* out_n_inliers, pgm_match_t* out_compact, uint64_t* out_n_evals,
                                    void* stream);
 
+/* One group of a pgm_match_groups call: n_pairs pairs of one size and one parameter set, laid
+ * out as for pgm_match_batch (pair k at img1/img2 + k * image_stride_bytes, outputs at
+ * out_* + k * nx * ny and out_n_inliers[k]). All pointers are device pointers except params. */
+typedef struct {
+    const pgm_params* params;
+    int32_t n_pairs, w, h, pitch_bytes;
+    int64_t image_stride_bytes;
+    const uint8_t* img1;
+    const uint8_t* img2;
+    pgm_match_t* out_fwd;
+    pgm_match_t* out_bwd;        /* or NULL */
+    int32_t* out_n_inliers;      /* or NULL */
+    pgm_match_t* out_compact;    /* or NULL */
+} pgm_group;
+
+/* Match several groups of pairs whose sizes and parameters differ between groups. The groups
+ * run concurrently on the context's internal streams (each exactly as pgm_match_batch runs
+ * it, so every pair's results equal pgm_match on that pair alone), forked from and joined
+ * back into `stream`. Group g uses the workspace after the parts of groups 0..g-1, each part
+ * workspace_shared_bytes + n_pairs * workspace_pair_bytes rounded up to 256 bytes; the call
+ * returns PGM_ENOMEM, before any device work, when the parts do not fit. out_n_evals (device
+ * or NULL) receives the total evaluation count. With use_graph = 1 the call's launches are
+ * captured into one HIP graph that later calls with identical arguments (pointers and
+ * parameter values) replay with a single launch; any other call re-captures it. use_graph
+ * is ignored while profiling is on. The dump entry points then show group n_groups-1, pair 0. */
+PGM_API pgm_status pgm_match_groups(void* ctx, int32_t n_groups, const pgm_group* groups,
+                                    uint64_t* out_n_evals, int32_t use_graph, void* stream);
+
+/* Request server: pairs of any size and parameters arrive one at a time and are matched
+ * concurrently. A server owns a device memory pool of pool_bytes and n_streams HIP streams
+ * (1..16). pgm_server_submit queues a request (the pgm_match arguments plus a caller tag) and
+ * starts queued requests, oldest first, while the head's workspace (pgm_query's
+ * workspace_bytes rounded up to 256) fits in the pool; a started request runs as pgm_match
+ * on the least loaded stream, so its results equal pgm_match on that pair alone.
+ * pgm_server_poll reports finished requests: it writes up to max_tags tags to host_tags and
+ * returns their number (or a negative pgm_status), frees their memory and starts queued
+ * requests. The caller keeps a request's images and outputs alive until its tag is reported.
+ * pgm_server_drain waits until nothing is queued or running (the finished tags stay for
+ * pgm_server_poll). Argument errors are reported by pgm_server_submit synchronously, and
+ * PGM_ENOMEM when the request alone exceeds the pool. One host thread per server. */
+PGM_API pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_streams, void** out_server);
+PGM_API pgm_status pgm_server_submit(void* server, const pgm_params* p, const uint8_t* img1,
+                                     const uint8_t* img2, int32_t w, int32_t h, int32_t pitch_bytes,
+                                     pgm_match_t* out_fwd, pgm_match_t* out_bwd, int32_t* out_n_inliers,
+                                     pgm_match_t* out_compact, uint64_t* out_n_evals, uint64_t tag);
+PGM_API int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t max_tags);
+PGM_API pgm_status pgm_server_pending(void* server, int32_t* host_queued, int32_t* host_running,
+                                      int32_t* host_finished);
+PGM_API pgm_status pgm_server_drain(void* server);
+PGM_API const char* pgm_server_last_error(void* server);
+PGM_API void pgm_server_destroy(void* server);
+
 /* Debug copies of the last pgm_match's intermediate state into host memory; each waits for
  * the last call's stream to finish.
  *  pgm_dump_level:    level_nx*level_ny records of 4 int32 {dx, dy, dist, flags} of field

@@ -52,11 +52,24 @@ class pgm_sizes(C.Structure):
     ]
 
 
+class pgm_group(C.Structure):
+    _fields_ = [
+        ("params", C.POINTER(pgm_params)),
+        ("n_pairs", C.c_int32), ("w", C.c_int32), ("h", C.c_int32), ("pitch_bytes", C.c_int32),
+        ("image_stride_bytes", C.c_int64),
+        ("img1", C.c_void_p), ("img2", C.c_void_p),
+        ("out_fwd", C.c_void_p), ("out_bwd", C.c_void_p),
+        ("out_n_inliers", C.c_void_p), ("out_compact", C.c_void_p),
+    ]
+
+
 MATCH_DTYPE = np.dtype([("x1", "<i4"), ("y1", "<i4"), ("x2", "<i4"), ("y2", "<i4"),
                         ("dist", "<i4"), ("flags", "<u4")])
 MATCH_BYTES = 24
 
-EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_match_batch", "pgm_dump_level",
+EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_match_batch", "pgm_match_groups",
+           "pgm_server_create", "pgm_server_submit", "pgm_server_poll", "pgm_server_pending",
+           "pgm_server_drain", "pgm_server_last_error", "pgm_server_destroy", "pgm_dump_level",
            "pgm_dump_gradient", "pgm_dump_pyramid", "pgm_profile", "pgm_profile_read",
            "pgm_last_error", "pgm_destroy")
 
@@ -95,6 +108,23 @@ def lib():
         L.pgm_match_batch.argtypes = [V, C.POINTER(pgm_params), C.c_int32, V, V, C.c_int32, C.c_int32,
                                       C.c_int32, C.c_int64, V, V, V, V, V, V]
         L.pgm_match_batch.restype = C.c_int32
+        L.pgm_match_groups.argtypes = [V, C.c_int32, C.POINTER(pgm_group), V, C.c_int32, V]
+        L.pgm_match_groups.restype = C.c_int32
+        L.pgm_server_create.argtypes = [C.c_int32, C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]
+        L.pgm_server_create.restype = C.c_int32
+        L.pgm_server_submit.argtypes = [V, C.POINTER(pgm_params), V, V, C.c_int32, C.c_int32, C.c_int32,
+                                        V, V, V, V, V, C.c_uint64]
+        L.pgm_server_submit.restype = C.c_int32
+        L.pgm_server_poll.argtypes = [V, C.POINTER(C.c_uint64), C.c_int32]
+        L.pgm_server_poll.restype = C.c_int32
+        L.pgm_server_pending.argtypes = [V, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.pgm_server_pending.restype = C.c_int32
+        L.pgm_server_drain.argtypes = [V]
+        L.pgm_server_drain.restype = C.c_int32
+        L.pgm_server_last_error.argtypes = [V]
+        L.pgm_server_last_error.restype = C.c_char_p
+        L.pgm_server_destroy.argtypes = [V]
+        L.pgm_server_destroy.restype = None
         L.pgm_dump_level.argtypes = [V, C.c_int32, C.c_int32, V]
         L.pgm_dump_level.restype = C.c_int32
         L.pgm_dump_gradient.argtypes = [V, C.c_int32, C.c_int32, V]
@@ -179,6 +209,54 @@ def pgm_match_batch(ctx, p, n_pairs: int, img1: int, img2: int, w: int, h: int, 
     return _check(lib().pgm_match_batch(ctx, C.byref(_as_params(p)), n_pairs, img1, img2, w, h, pitch_bytes,
                                         image_stride_bytes, out_fwd, out_bwd, out_n_inliers, out_compact,
                                         out_n_evals, stream), ctx)
+
+
+def pgm_match_groups(ctx, groups, out_n_evals: int | None = None, use_graph: bool = False,
+                     stream: int | None = None):
+    """groups: a sequence of pgm_group (their params pointers must stay alive for the call)."""
+    arr = (pgm_group * len(groups))(*groups)
+    return _check(lib().pgm_match_groups(ctx, len(groups), arr, out_n_evals, 1 if use_graph else 0, stream), ctx)
+
+
+def _check_server(status, server):
+    if status < 0:
+        msg = lib().pgm_server_last_error(server)
+        raise PGMError(status, msg.decode() if msg else "")
+    return status
+
+
+def pgm_server_create(device: int, pool_bytes: int, n_streams: int):
+    h = C.c_void_p()
+    _check_server(lib().pgm_server_create(device, pool_bytes, n_streams, C.byref(h)), None)
+    return h
+
+
+def pgm_server_submit(server, p, img1: int, img2: int, w: int, h: int, pitch_bytes: int, out_fwd: int,
+                      out_bwd: int | None, out_n_inliers: int | None, out_compact: int | None,
+                      out_n_evals: int | None, tag: int):
+    return _check_server(lib().pgm_server_submit(server, C.byref(_as_params(p)), img1, img2, w, h, pitch_bytes,
+                                                 out_fwd, out_bwd, out_n_inliers, out_compact, out_n_evals,
+                                                 tag), server)
+
+
+def pgm_server_poll(server, max_tags: int = 256) -> list:
+    buf = (C.c_uint64 * max(1, max_tags))()
+    n = _check_server(lib().pgm_server_poll(server, buf, max_tags), server)
+    return list(buf[:n])
+
+
+def pgm_server_pending(server):
+    q, r, f = C.c_int32(), C.c_int32(), C.c_int32()
+    _check_server(lib().pgm_server_pending(server, C.byref(q), C.byref(r), C.byref(f)), server)
+    return q.value, r.value, f.value
+
+
+def pgm_server_drain(server) -> None:
+    _check_server(lib().pgm_server_drain(server), server)
+
+
+def pgm_server_destroy(server) -> None:
+    lib().pgm_server_destroy(server)
 
 
 def pgm_dump_level(ctx, level: int, dir: int, n: int) -> np.ndarray:
@@ -316,6 +394,28 @@ class Matcher:
         o = self.outputs_batch(p, w, h, B, bwd, compact, count_evals)
         return self.match_batch_into(p, img1, img2, o)
 
+    def match_groups_into(self, items, n_evals=None, use_graph=False, stream=None):
+        """items: a list of (params, img1, img2, outputs) with (B, h, w, 3) uint8 CUDA image
+        tensors and outputs from outputs_batch; all groups run in one pgm_match_groups call."""
+        torch = self.torch
+        ptr = lambda t: None if t is None else t.data_ptr()
+        keep, groups = [], []
+        for p, img1, img2, o in items:
+            assert img1.is_cuda and img1.dtype == torch.uint8 and img1.dim() == 4 and img1.shape[3] == 3
+            assert img2.shape == img1.shape and img1.stride() == img2.stride()
+            assert img1.stride(3) == 1 and img1.stride(2) == 3
+            B, h, w = img1.shape[:3]
+            assert B == o["n_pairs"]
+            pp = _as_params(p)
+            keep.append(pp)
+            groups.append(pgm_group(C.pointer(pp), B, w, h, img1.stride(1), img1.stride(0), img1.data_ptr(),
+                                    img2.data_ptr(), o["fwd"].data_ptr(), ptr(o["bwd"]), ptr(o["n_inliers"]),
+                                    ptr(o["compact"])))
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        pgm_match_groups(self.ctx, groups, ptr(n_evals), use_graph, stream)
+        return items
+
     @staticmethod
     def to_numpy(t, count=None):
         a = t.cpu().numpy().view(MATCH_DTYPE) if t is not None else None
@@ -332,3 +432,67 @@ class Matcher:
     def dump_pyramid(self, level, image):
         s = self.last_sizes
         return pgm_dump_pyramid(self.ctx, level, image, s.level_w[level], s.level_h[level])
+
+
+class Server:
+    """A libpgm request server with torch-allocated outputs. submit() takes (h, w, 3) uint8
+    CUDA image tensors and returns the tag; poll() returns the tags of finished requests.
+    The server keeps references to each request's tensors until its tag has been reported."""
+
+    def __init__(self, device: int = 0, pool_bytes: int = 1 << 30, n_streams: int = 4):
+        import torch  # device memory only
+        self.torch = torch
+        self.device = device
+        self.h = pgm_server_create(device, pool_bytes, n_streams)
+        self.live = {}
+        self.next_tag = 0
+
+    def close(self):
+        if self.h:
+            pgm_server_destroy(self.h)
+            self.h = None
+            self.live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, p, img1, img2, bwd=True, compact=True, count_evals=False, tag=None):
+        torch = self.torch
+        assert img1.is_cuda and img1.dtype == torch.uint8 and img1.dim() == 3 and img1.shape[2] == 3
+        assert img2.shape == img1.shape and img1.stride() == img2.stride() and img1.stride(1) == 3
+        h, w = img1.shape[:2]
+        s = pgm_query(p, w, h)
+        n = s.nx * s.ny
+        dev = torch.device("cuda", self.device)
+        o = dict(sizes=s, n=n, img1=img1, img2=img2)
+        o["fwd"] = torch.empty(n * 6, dtype=torch.int32, device=dev)
+        o["bwd"] = torch.empty(n * 6, dtype=torch.int32, device=dev) if bwd else None
+        o["n_inliers"] = torch.zeros(1, dtype=torch.int32, device=dev) if compact else None
+        o["compact"] = torch.empty(n * 6, dtype=torch.int32, device=dev) if compact else None
+        o["n_evals"] = torch.zeros(1, dtype=torch.int64, device=dev) if count_evals else None
+        if tag is None:
+            tag = self.next_tag
+            self.next_tag += 1
+        ptr = lambda t: None if t is None else t.data_ptr()
+        self.live[tag] = o
+        try:
+            pgm_server_submit(self.h, p, img1.data_ptr(), img2.data_ptr(), w, h, img1.stride(0),
+                              o["fwd"].data_ptr(), ptr(o["bwd"]), ptr(o["n_inliers"]), ptr(o["compact"]),
+                              ptr(o["n_evals"]), tag)
+        except Exception:
+            del self.live[tag]
+            raise
+        return tag
+
+    def poll(self, max_tags: int = 256):
+        """[(tag, outputs)] of the requests finished since the last poll."""
+        return [(t, self.live.pop(t)) for t in pgm_server_poll(self.h, max_tags)]
+
+    def pending(self):
+        return pgm_server_pending(self.h)
+
+    def drain(self):
+        pgm_server_drain(self.h)

@@ -2,6 +2,8 @@
 // level schedule of Sec. III-D and the kernel launches of one pair.
 #include <string.h>
 
+#include <deque>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -203,6 +205,7 @@ struct pgm_ctx_s {
     std::string err;
     // the last pgm_match, for the dump entry points
     bool have_last = false;
+    uint8_t* last_ws = nullptr;                   // workspace region of the last batch
     Layout last;
     pgm_params last_p;
     hipStream_t last_stream = nullptr;
@@ -216,6 +219,15 @@ struct pgm_ctx_s {
     size_t next_event = 0;
     struct Rec { int kind; hipEvent_t a, b; };
     std::vector<Rec> recs;
+    // pgm_match_groups: internal streams (default priority), fork/join events, and the graph
+    // of the last captured call with the bytes of its arguments
+    static constexpr int NSTREAMS = 4;
+    hipStream_t gs[NSTREAMS] = {};
+    hipStream_t cap = nullptr;
+    hipEvent_t fork = nullptr, join[NSTREAMS] = {};
+    hipGraphExec_t gexec = nullptr;
+    std::string gkey;
+    long long nlaunch = 0;                        // kernel launches issued (capture check)
 };
 
 static std::string g_create_error;
@@ -307,6 +319,10 @@ pgm_status pgm_create(int32_t device, uint64_t workspace_bytes, void** out_ctx)
         int v = 0;
         e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
         c->lds_max = v > 0 ? (size_t)v : 0;
+        // (HIP may not need the attribute for dynamic LDS up to the device limit; a refusal
+        // is left to the launch to report)
+        if (e == hipSuccess && c->lds_max > 65536 && level_allow_lds(c->lds_max - 64) != hipSuccess)
+            (void)hipGetLastError();
     }
     if (e != hipSuccess) {
         if (c->ws) (void)hipFree(c->ws);
@@ -328,6 +344,13 @@ void pgm_destroy(void* ctx)
     if (c->ws) (void)hipFree(c->ws);
     if (c->prof_evals) (void)hipFree(c->prof_evals);
     for (hipEvent_t ev : c->events) (void)hipEventDestroy(ev);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    for (int i = 0; i < pgm_ctx_s::NSTREAMS; i++) {
+        if (c->gs[i]) (void)hipStreamDestroy(c->gs[i]);
+        if (c->join[i]) (void)hipEventDestroy(c->join[i]);
+    }
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    if (c->fork) (void)hipEventDestroy(c->fork);
     delete c;
 }
 
@@ -337,11 +360,10 @@ const char* pgm_last_error(void* ctx)
     return c ? c->err.c_str() : g_create_error.c_str();
 }
 
-static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, const uint8_t* img1,
-                             const uint8_t* img2, int32_t w, int32_t h, int32_t pitch_bytes,
-                             int64_t image_stride_bytes, pgm_match_t* out_fwd, pgm_match_t* out_bwd,
-                             int32_t* out_n_inliers, pgm_match_t* out_compact, uint64_t* out_n_evals,
-                             hipStream_t s)
+// Checks of one batch's arguments; fills the layout.
+static pgm_status check_batch(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, const uint8_t* img1,
+                              const uint8_t* img2, int32_t w, int32_t h, int32_t pitch_bytes,
+                              int64_t image_stride_bytes, const pgm_match_t* out_fwd, Layout& Y)
 {
     if (const char* why = validate(p, w, h)) return fail(c, PGM_EINVAL, why);
     if (npairs < 1) return fail(c, PGM_EINVAL, "n_pairs must be at least 1");
@@ -349,15 +371,27 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     if (pitch_bytes < 3 * w) return fail(c, PGM_EINVAL, "pitch_bytes must be at least 3 * w");
     if (npairs > 1 && image_stride_bytes < (int64_t)pitch_bytes * h)
         return fail(c, PGM_EINVAL, "image_stride_bytes must be at least pitch_bytes * h");
-    Layout Y;
     plan(p, w, h, Y);
+    return PGM_OK;
+}
+
+// The whole method for a batch of pairs, with the workspace region [wsb, wsb + wsn).
+static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, const uint8_t* img1,
+                             const uint8_t* img2, int32_t w, int32_t h, int32_t pitch_bytes,
+                             int64_t image_stride_bytes, pgm_match_t* out_fwd, pgm_match_t* out_bwd,
+                             int32_t* out_n_inliers, pgm_match_t* out_compact, uint64_t* out_n_evals,
+                             hipStream_t s, uint8_t* wsb, size_t wsn)
+{
+    Layout Y;
+    if (pgm_status st = check_batch(c, p, npairs, img1, img2, w, h, pitch_bytes, image_stride_bytes, out_fwd, Y))
+        return st;
     const size_t need = Y.shared_bytes + (size_t)npairs * Y.pair_bytes;
-    if (need > c->ws_bytes)
-        return fail(c, PGM_ENOMEM, "workspace of " + std::to_string(c->ws_bytes) + " bytes is smaller than the " +
+    if (need > wsn)
+        return fail(c, PGM_ENOMEM, "workspace of " + std::to_string(wsn) + " bytes is smaller than the " +
                                        std::to_string(need) + " bytes this batch needs");
     PGM_HIP(c, hipSetDevice(c->device));
-    uint8_t* ws = c->ws;                          // shared slice
-    uint8_t* pw0 = c->ws + Y.shared_bytes;        // pair 0's slice
+    uint8_t* ws = wsb;                            // shared slice
+    uint8_t* pw0 = wsb + Y.shared_bytes;          // pair 0's slice
     const long long zs = (long long)Y.pair_bytes;
     unsigned long long* nev = (unsigned long long*)out_n_evals;
     // with profiling on, every launch is bracketed by two events on the caller's stream
@@ -372,6 +406,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         return hipSuccess;
     };
     auto timed = [&](int kind, auto&& launch) -> hipError_t {
+        c->nlaunch++;
         if (!c->prof) return launch();
         pgm_ctx_s::Rec r;
         r.kind = kind;
@@ -621,10 +656,12 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         ca.zs = zs;
         ca.user = nev;
         ca.prof = c->prof ? c->prof_evals : nullptr;
+        c->nlaunch += 2;
         PGM_HIP(c, launch_count(ca, (unsigned long long*)(pw0 + Y.cntpart), s));
     }
 
     c->have_last = true;
+    c->last_ws = wsb;
     c->last = Y;
     c->last_p = *p;
     c->last_stream = s;
@@ -643,7 +680,7 @@ pgm_status pgm_match(void* ctx, const pgm_params* p, const uint8_t* img1, const 
     pgm_ctx_s* c = (pgm_ctx_s*)ctx;
     if (!c) return PGM_EINVAL;
     return match_impl(c, p, 1, img1, img2, w, h, pitch_bytes, 0, out_fwd, out_bwd, out_n_inliers, out_compact,
-                      out_n_evals, (hipStream_t)stream);
+                      out_n_evals, (hipStream_t)stream, c->ws, c->ws_bytes);
 }
 
 pgm_status pgm_match_batch(void* ctx, const pgm_params* p, int32_t n_pairs, const uint8_t* img1,
@@ -655,7 +692,345 @@ pgm_status pgm_match_batch(void* ctx, const pgm_params* p, int32_t n_pairs, cons
     pgm_ctx_s* c = (pgm_ctx_s*)ctx;
     if (!c) return PGM_EINVAL;
     return match_impl(c, p, n_pairs, img1, img2, w, h, pitch_bytes, image_stride_bytes, out_fwd, out_bwd,
-                      out_n_inliers, out_compact, out_n_evals, (hipStream_t)stream);
+                      out_n_inliers, out_compact, out_n_evals, (hipStream_t)stream, c->ws, c->ws_bytes);
+}
+
+static pgm_status groups_eager(pgm_ctx_s* c, int32_t n_groups, const pgm_group* gr, const size_t* off,
+                               uint64_t* out_n_evals, hipStream_t s)
+{
+    const int ns = n_groups < pgm_ctx_s::NSTREAMS ? n_groups : pgm_ctx_s::NSTREAMS;
+    PGM_HIP(c, hipEventRecord(c->fork, s));
+    for (int i = 0; i < ns; i++) PGM_HIP(c, hipStreamWaitEvent(c->gs[i], c->fork, 0));
+    for (int g = 0; g < n_groups; g++) {
+        const pgm_group& G = gr[g];
+        const size_t end = g + 1 < n_groups ? off[g + 1] : c->ws_bytes;
+        if (pgm_status st = match_impl(c, G.params, G.n_pairs, G.img1, G.img2, G.w, G.h, G.pitch_bytes,
+                                       G.image_stride_bytes, G.out_fwd, G.out_bwd, G.out_n_inliers, G.out_compact,
+                                       out_n_evals, c->gs[g % ns], c->ws + off[g], end - off[g]))
+            return st;
+    }
+    for (int i = 0; i < ns; i++) {
+        PGM_HIP(c, hipEventRecord(c->join[i], c->gs[i]));
+        PGM_HIP(c, hipStreamWaitEvent(s, c->join[i], 0));
+    }
+    return PGM_OK;
+}
+
+pgm_status pgm_match_groups(void* ctx, int32_t n_groups, const pgm_group* groups, uint64_t* out_n_evals,
+                            int32_t use_graph, void* stream)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    if (!c) return PGM_EINVAL;
+    if (n_groups < 1 || !groups) return fail(c, PGM_EINVAL, "n_groups must be at least 1 and groups not null");
+    if (use_graph != 0 && use_graph != 1) return fail(c, PGM_EINVAL, "use_graph must be 0 or 1");
+    // every group's checks first, then the workspace split (no device work before both pass)
+    std::vector<size_t> off(n_groups);
+    size_t cur = 0;
+    for (int g = 0; g < n_groups; g++) {
+        const pgm_group& G = groups[g];
+        if (!G.params) return fail(c, PGM_EINVAL, "group " + std::to_string(g) + ": params is null");
+        Layout Y;
+        if (pgm_status st = check_batch(c, G.params, G.n_pairs, G.img1, G.img2, G.w, G.h, G.pitch_bytes,
+                                        G.image_stride_bytes, G.out_fwd, Y))
+            return fail(c, st, "group " + std::to_string(g) + ": " + c->err);
+        off[g] = cur;
+        cur += (Y.shared_bytes + (size_t)G.n_pairs * Y.pair_bytes + 255) & ~(size_t)255;
+    }
+    if (cur > c->ws_bytes)
+        return fail(c, PGM_ENOMEM, "workspace of " + std::to_string(c->ws_bytes) + " bytes is smaller than the " +
+                                       std::to_string(cur) + " bytes these groups need");
+    PGM_HIP(c, hipSetDevice(c->device));
+    if (!c->fork) {
+        for (int i = 0; i < pgm_ctx_s::NSTREAMS; i++) {
+            PGM_HIP(c, hipStreamCreateWithFlags(&c->gs[i], hipStreamNonBlocking));
+            PGM_HIP(c, hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming));
+        }
+        PGM_HIP(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+        PGM_HIP(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!use_graph || c->prof) return groups_eager(c, n_groups, groups, off.data(), out_n_evals, s);
+
+    // the graph is reused while every argument (parameter values included) is the same
+    std::string key((const char*)&out_n_evals, sizeof out_n_evals);
+    for (int g = 0; g < n_groups; g++) {
+        key.append((const char*)&groups[g], sizeof(pgm_group));
+        key.append((const char*)groups[g].params, sizeof(pgm_params));
+    }
+    if (!c->gexec || key != c->gkey) {
+        if (c->gexec) {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+            c->gkey.clear();
+        }
+        PGM_HIP(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+        const long long launches0 = c->nlaunch;
+        pgm_status st = groups_eager(c, n_groups, groups, off.data(), out_n_evals, c->cap);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap, &graph);
+        if (st != PGM_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(c, PGM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        // every launch must have become a kernel node of the graph
+        size_t nn = 0;
+        e = hipGraphGetNodes(graph, nullptr, &nn);
+        std::vector<hipGraphNode_t> nodes(nn);
+        if (e == hipSuccess && nn) e = hipGraphGetNodes(graph, nodes.data(), &nn);
+        long long kernels = 0;
+        for (size_t i = 0; e == hipSuccess && i < nn; i++) {
+            hipGraphNodeType t;
+            e = hipGraphNodeGetType(nodes[i], &t);
+            if (e == hipSuccess && t == hipGraphNodeTypeKernel) kernels++;
+        }
+        if (e != hipSuccess || kernels != c->nlaunch - launches0) {
+            (void)hipGraphDestroy(graph);
+            return fail(c, PGM_EDEVICE, "graph capture recorded " + std::to_string(kernels) + " kernel nodes of " +
+                                            std::to_string(nn) + " for " + std::to_string(c->nlaunch - launches0) +
+                                            " launches" + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : ""));
+        }
+        e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            c->gexec = nullptr;
+            return fail(c, PGM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        c->gkey = key;
+    }
+    PGM_HIP(c, hipGraphLaunch(c->gexec, s));
+    c->last_stream = s;
+    return PGM_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Request server: continuous admission of single pairs of any size (see pgm.h)
+// ---------------------------------------------------------------------------------------
+
+struct pgm_server_s {
+    pgm_ctx_s* c = nullptr;                       // its workspace is the memory pool
+    std::map<size_t, size_t> free_;               // free pool blocks: offset -> bytes
+    std::vector<hipStream_t> streams;
+    std::vector<int> load;                        // requests in flight per stream
+    std::vector<hipEvent_t> spare;                // completion events not in use
+    struct Req {
+        pgm_params p;
+        const uint8_t* img1;
+        const uint8_t* img2;
+        int32_t w, h, pitch;
+        pgm_match_t* out_fwd;
+        pgm_match_t* out_bwd;
+        int32_t* out_n_inliers;
+        pgm_match_t* out_compact;
+        uint64_t* out_n_evals;
+        uint64_t tag;
+        size_t need, off;
+        int stream;
+        hipEvent_t done;
+    };
+    std::deque<Req> queued;
+    std::vector<Req> running;
+    std::deque<uint64_t> finished;
+
+    bool alloc(size_t need, size_t& off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < need) continue;
+            off = it->first;
+            const size_t rest = it->second - need;
+            free_.erase(it);
+            if (rest) free_[off + need] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+// start queued requests, oldest first, while the head fits in the pool
+static pgm_status server_admit(pgm_server_s* S)
+{
+    pgm_ctx_s* c = S->c;
+    while (!S->queued.empty()) {
+        pgm_server_s::Req r = S->queued.front();
+        if (!S->alloc(r.need, r.off)) break;
+        int k = 0;
+        for (int i = 1; i < (int)S->streams.size(); i++)
+            if (S->load[i] < S->load[k]) k = i;
+        r.stream = k;
+        if (S->spare.empty()) {
+            hipEvent_t ev;
+            hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                S->release(r.off, r.need);
+                return fail(c, PGM_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
+            }
+            S->spare.push_back(ev);
+        }
+        r.done = S->spare.back();
+        pgm_status st = match_impl(c, &r.p, 1, r.img1, r.img2, r.w, r.h, r.pitch, 0, r.out_fwd, r.out_bwd,
+                                   r.out_n_inliers, r.out_compact, r.out_n_evals, S->streams[k], c->ws + r.off,
+                                   r.need);
+        if (st != PGM_OK) {
+            S->release(r.off, r.need);
+            return st;
+        }
+        hipError_t e = hipEventRecord(r.done, S->streams[k]);
+        if (e != hipSuccess) return fail(c, PGM_EDEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
+        S->spare.pop_back();
+        S->load[k]++;
+        S->running.push_back(r);
+        S->queued.pop_front();
+    }
+    return PGM_OK;
+}
+
+// move finished requests to the finished list (wait for them all when `wait`)
+static pgm_status server_reap(pgm_server_s* S, bool wait)
+{
+    pgm_ctx_s* c = S->c;
+    for (size_t i = 0; i < S->running.size();) {
+        pgm_server_s::Req& r = S->running[i];
+        hipError_t e = wait ? hipEventSynchronize(r.done) : hipEventQuery(r.done);
+        if (e == hipErrorNotReady) {
+            i++;
+            continue;
+        }
+        if (e != hipSuccess) return fail(c, PGM_EDEVICE, std::string("request: ") + hipGetErrorString(e));
+        S->release(r.off, r.need);
+        S->spare.push_back(r.done);
+        S->load[r.stream]--;
+        S->finished.push_back(r.tag);
+        S->running.erase(S->running.begin() + i);
+    }
+    return PGM_OK;
+}
+
+pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_streams, void** out_server)
+{
+    if (!out_server) return fail(nullptr, PGM_EINVAL, "out_server is null");
+    *out_server = nullptr;
+    if (n_streams < 1 || n_streams > 16) return fail(nullptr, PGM_EINVAL, "n_streams must be in 1..16");
+    void* ctx = nullptr;
+    pgm_status st = pgm_create(device, pool_bytes, &ctx);
+    if (st != PGM_OK) return st;
+    pgm_server_s* S = new pgm_server_s();
+    S->c = (pgm_ctx_s*)ctx;
+    S->free_[0] = S->c->ws_bytes & ~(size_t)255;
+    for (int i = 0; i < n_streams; i++) {
+        hipStream_t q;
+        hipError_t e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            for (hipStream_t x : S->streams) (void)hipStreamDestroy(x);
+            pgm_destroy(ctx);
+            delete S;
+            return fail(nullptr, PGM_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
+        S->streams.push_back(q);
+        S->load.push_back(0);
+    }
+    *out_server = S;
+    return PGM_OK;
+}
+
+pgm_status pgm_server_submit(void* server, const pgm_params* p, const uint8_t* img1, const uint8_t* img2,
+                             int32_t w, int32_t h, int32_t pitch_bytes, pgm_match_t* out_fwd,
+                             pgm_match_t* out_bwd, int32_t* out_n_inliers, pgm_match_t* out_compact,
+                             uint64_t* out_n_evals, uint64_t tag)
+{
+    pgm_server_s* S = (pgm_server_s*)server;
+    if (!S) return PGM_EINVAL;
+    pgm_ctx_s* c = S->c;
+    Layout Y;
+    if (pgm_status st = check_batch(c, p, 1, img1, img2, w, h, pitch_bytes, 0, out_fwd, Y)) return st;
+    pgm_server_s::Req r;
+    r.p = *p;
+    r.img1 = img1; r.img2 = img2;
+    r.w = w; r.h = h; r.pitch = pitch_bytes;
+    r.out_fwd = out_fwd; r.out_bwd = out_bwd; r.out_n_inliers = out_n_inliers; r.out_compact = out_compact;
+    r.out_n_evals = out_n_evals;
+    r.tag = tag;
+    r.need = (Y.shared_bytes + Y.pair_bytes + 255) & ~(size_t)255;
+    r.off = 0;
+    r.stream = 0;
+    r.done = nullptr;
+    if (r.need > (c->ws_bytes & ~(size_t)255))
+        return fail(c, PGM_ENOMEM, "request needs " + std::to_string(r.need) + " bytes, more than the pool");
+    PGM_HIP(c, hipSetDevice(c->device));
+    S->queued.push_back(r);
+    if (pgm_status st = server_reap(S, false)) return st;
+    return server_admit(S);
+}
+
+int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t max_tags)
+{
+    pgm_server_s* S = (pgm_server_s*)server;
+    if (!S || max_tags < 0 || (max_tags > 0 && !host_tags)) return PGM_EINVAL;
+    if (hipSetDevice(S->c->device) != hipSuccess) return fail(S->c, PGM_EDEVICE, "hipSetDevice failed");
+    if (pgm_status st = server_reap(S, false)) return st;
+    if (pgm_status st = server_admit(S)) return st;
+    int32_t n = 0;
+    while (n < max_tags && !S->finished.empty()) {
+        host_tags[n++] = S->finished.front();
+        S->finished.pop_front();
+    }
+    return n;
+}
+
+pgm_status pgm_server_pending(void* server, int32_t* queued, int32_t* running, int32_t* finished)
+{
+    pgm_server_s* S = (pgm_server_s*)server;
+    if (!S) return PGM_EINVAL;
+    if (queued) *queued = (int32_t)S->queued.size();
+    if (running) *running = (int32_t)S->running.size();
+    if (finished) *finished = (int32_t)S->finished.size();
+    return PGM_OK;
+}
+
+pgm_status pgm_server_drain(void* server)
+{
+    pgm_server_s* S = (pgm_server_s*)server;
+    if (!S) return PGM_EINVAL;
+    PGM_HIP(S->c, hipSetDevice(S->c->device));
+    while (!S->queued.empty() || !S->running.empty()) {
+        if (pgm_status st = server_reap(S, true)) return st;
+        if (pgm_status st = server_admit(S)) return st;
+    }
+    return PGM_OK;
+}
+
+const char* pgm_server_last_error(void* server)
+{
+    pgm_server_s* S = (pgm_server_s*)server;
+    return S ? S->c->err.c_str() : g_create_error.c_str();
+}
+
+void pgm_server_destroy(void* server)
+{
+    pgm_server_s* S = (pgm_server_s*)server;
+    if (!S) return;
+    (void)hipSetDevice(S->c->device);
+    for (hipStream_t q : S->streams) (void)hipStreamSynchronize(q);
+    for (auto& r : S->running) (void)hipEventDestroy(r.done);
+    for (hipEvent_t ev : S->spare) (void)hipEventDestroy(ev);
+    for (hipStream_t q : S->streams) (void)hipStreamDestroy(q);
+    pgm_destroy(S->c);
+    delete S;
 }
 
 static pgm_status dump_prep(pgm_ctx_s* c, int level)
@@ -680,9 +1055,9 @@ pgm_status pgm_dump_level(void* ctx, int32_t level, int32_t dir, int32_t* host_o
     uint32_t* disp = (uint32_t*)&buf[0];
     uint32_t* dist = disp + n;
     uint8_t* flags = (uint8_t*)(dist + n);
-    PGM_HIP(c, hipMemcpy(disp, c->ws + Y.shared_bytes + Y.disp[dir][level], n * 4, hipMemcpyDeviceToHost));
-    PGM_HIP(c, hipMemcpy(dist, c->ws + Y.shared_bytes + Y.dist[dir][level], n * 4, hipMemcpyDeviceToHost));
-    PGM_HIP(c, hipMemcpy(flags, c->ws + Y.shared_bytes + Y.flags[dir][level], n, hipMemcpyDeviceToHost));
+    PGM_HIP(c, hipMemcpy(disp, c->last_ws + Y.shared_bytes + Y.disp[dir][level], n * 4, hipMemcpyDeviceToHost));
+    PGM_HIP(c, hipMemcpy(dist, c->last_ws + Y.shared_bytes + Y.dist[dir][level], n * 4, hipMemcpyDeviceToHost));
+    PGM_HIP(c, hipMemcpy(flags, c->last_ws + Y.shared_bytes + Y.flags[dir][level], n, hipMemcpyDeviceToHost));
     for (size_t s = 0; s < n; s++) {
         const bool init = disp[s] != UNINIT;
         host_out[4 * s + 0] = init ? (int32_t)(int16_t)(disp[s] & 0xFFFF) : 0;
@@ -704,7 +1079,7 @@ pgm_status pgm_dump_gradient(void* ctx, int32_t level, int32_t image, void* host
     const int w = Y.lw[level], h = Y.lh[level], pw = w + 2 * PAD;
     const size_t row = (size_t)w * Y.C2 * Y.esize;
     for (int y = 0; y < h; y++) {
-        const uint8_t* src = c->ws + Y.shared_bytes + Y.grad[image][level] + (((size_t)(y + PAD) * pw + PAD) * Y.C2) * Y.esize;
+        const uint8_t* src = c->last_ws + Y.shared_bytes + Y.grad[image][level] + (((size_t)(y + PAD) * pw + PAD) * Y.C2) * Y.esize;
         PGM_HIP(c, hipMemcpy((uint8_t*)host_out + y * row, src, row, hipMemcpyDeviceToHost));
     }
     if (!Y.f32) {
@@ -726,7 +1101,7 @@ pgm_status pgm_dump_pyramid(void* ctx, int32_t level, int32_t image, uint8_t* ho
         PGM_HIP(c, hipMemcpy2D(host_out, (size_t)w * 3, c->last_img[image], c->last_pitch, (size_t)w * 3, h,
                                hipMemcpyDeviceToHost));
     } else {
-        PGM_HIP(c, hipMemcpy(host_out, c->ws + Y.shared_bytes + Y.pyr[image][level], (size_t)w * h * 3, hipMemcpyDeviceToHost));
+        PGM_HIP(c, hipMemcpy(host_out, c->last_ws + Y.shared_bytes + Y.pyr[image][level], (size_t)w * h * 3, hipMemcpyDeviceToHost));
     }
     return PGM_OK;
 }

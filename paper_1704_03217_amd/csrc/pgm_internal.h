@@ -196,6 +196,8 @@ hipError_t launch_up(const TransArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);
 // every sweep of a small level, one work-group per pair and direction
 hipError_t launch_level(const LevelArgs& a, int C2, int f32, hipStream_t s);
+// let every whole-level kernel use up to `bytes` of dynamic LDS (once per context)
+hipError_t level_allow_lds(size_t bytes);
 hipError_t launch_output(const OutArgs& a, hipStream_t s);
 hipError_t launch_compact(const OutArgs& a, hipStream_t s);
 // part: pair 0's array of COUNT_SLICES * CountArgs::KINDS partial sums; pair z's array is at

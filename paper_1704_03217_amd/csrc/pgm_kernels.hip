@@ -1205,11 +1205,25 @@ hipError_t launch_up(const TransArgs& a, int C2, int f32, hipStream_t s)
 template <int C2, int PM, bool FX, bool F>
 static hipError_t launch_level_v(const LevelArgs& a, hipStream_t s)
 {
-    const void* fn = (const void*)k_level<C2, PM, FX, F>;
     const size_t bytes = a.lay.total;
-    if (bytes > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     hipLaunchKernelGGL((k_level<C2, PM, FX, F>), dim3(2 * a.b.npairs), dim3(LevelShape<PM, F>::threads), bytes, s, a);
     return hipGetLastError();
+}
+
+hipError_t level_allow_lds(size_t bytes)
+{
+    hipError_t first = hipSuccess;
+    auto allow = [&](const void* fn) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess && first == hipSuccess) first = e;
+    };
+#define PGM_LA(C2_, PM_, FX_)                                                                    \
+    allow((const void*)k_level<C2_, PM_, FX_, false>);                                           \
+    allow((const void*)k_level<C2_, PM_, FX_, true>);
+    PGM_LA(6, 8, true) PGM_LA(6, 8, false) PGM_LA(6, 16, true) PGM_LA(6, 16, false)
+    PGM_LA(2, 8, true) PGM_LA(2, 8, false) PGM_LA(2, 16, true) PGM_LA(2, 16, false)
+#undef PGM_LA
+    return first;
 }
 
 hipError_t launch_level(const LevelArgs& a, int C2, int f32, hipStream_t s)

@@ -39,9 +39,10 @@ def test_struct_layout_matches_header():
 #include <stddef.h>
 #include "pgm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(pgm_params), offsetof(pgm_params, iters),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pgm_params), offsetof(pgm_params, iters),
          offsetof(pgm_params, rng_seed), sizeof(pgm_match_t), sizeof(pgm_sizes),
-         offsetof(pgm_sizes, workspace_bytes), offsetof(pgm_sizes, workspace_pair_bytes));
+         offsetof(pgm_sizes, workspace_bytes), offsetof(pgm_sizes, workspace_pair_bytes),
+         sizeof(pgm_group), offsetof(pgm_group, image_stride_bytes), offsetof(pgm_group, out_compact));
   return 0;
 }
 """
@@ -53,7 +54,8 @@ int main(void) {
         got = [int(v) for v in subprocess.check_output([exe]).split()]
     exp = [C.sizeof(pgm.pgm_params), pgm.pgm_params.iters.offset, pgm.pgm_params.rng_seed.offset,
            pgm.MATCH_BYTES, C.sizeof(pgm.pgm_sizes), pgm.pgm_sizes.workspace_bytes.offset,
-           pgm.pgm_sizes.workspace_pair_bytes.offset]
+           pgm.pgm_sizes.workspace_pair_bytes.offset, C.sizeof(pgm.pgm_group),
+           pgm.pgm_group.image_stride_bytes.offset, pgm.pgm_group.out_compact.offset]
     assert got == exp
     assert pgm.MATCH_DTYPE.itemsize == pgm.MATCH_BYTES
 
@@ -121,6 +123,14 @@ def test_null_arguments_rejected_without_device_work():
     assert L.pgm_match(None, C.byref(p), None, None, 10, 10, 30, None, None, None, None, None, None) == pgm.PGM_EINVAL
     assert L.pgm_match_batch(None, C.byref(p), 2, None, None, 10, 10, 30, 300, None, None, None, None, None,
                              None) == pgm.PGM_EINVAL
+    assert L.pgm_match_groups(None, 1, None, None, 0, None) == pgm.PGM_EINVAL
+    assert L.pgm_server_create(0, 1 << 20, 0, C.byref(C.c_void_p())) == pgm.PGM_EINVAL
+    assert L.pgm_server_create(0, 1 << 20, 1, None) == pgm.PGM_EINVAL
+    assert L.pgm_server_submit(None, C.byref(p), None, None, 10, 10, 30, None, None, None, None, None, 0) \
+        == pgm.PGM_EINVAL
+    assert L.pgm_server_poll(None, None, 0) == pgm.PGM_EINVAL
+    assert L.pgm_server_drain(None) == pgm.PGM_EINVAL
+    L.pgm_server_destroy(None)
     assert L.pgm_dump_level(None, 0, 0, None) == pgm.PGM_EINVAL
     L.pgm_destroy(None)
 
