@@ -33,6 +33,7 @@ class Params(C.Structure):
         ("radius", C.c_int32), ("max_disp", C.c_int32), ("sobel_ksize", C.c_int32),
         ("feature", C.c_int32), ("color", C.c_int32), ("fwd_bwd", C.c_int32),
         ("consistency_px", C.c_int32), ("init_mode", C.c_int32), ("refine_rounds", C.c_int32),
+        ("min_region_px", C.c_int32), ("region_link_px", C.c_int32),
         ("rng_seed", C.c_uint64),
     ]
 
@@ -83,6 +84,8 @@ def lib():
         L.pgmo_grid_nearest.argtypes = [C.c_int, C.c_int, C.c_int]
         L.pgmo_geometry.argtypes = [C.POINTER(Params), C.c_int, C.c_int, P, P, P, P]
         L.pgmo_top_radius.argtypes = [C.POINTER(Params), C.c_int, C.c_int]
+        L.pgmo_remove_small_regions.argtypes = [P, P, P] + [C.c_int] * 5
+        L.pgmo_remove_small_regions.restype = None
         L.pgmo_match.argtypes = [C.POINTER(Params), P, P, C.c_int, C.c_int, C.c_int, C.c_int,
                                  P, P, P, P, P, P]
         _lib = L
@@ -105,6 +108,17 @@ def make_params(d: dict) -> Params:
 
 
 # ---- building blocks ----
+
+def remove_small_regions(dx: np.ndarray, dy: np.ndarray, inl: np.ndarray, stride: int, min_px: int,
+                         link_px: int) -> np.ndarray:
+    """Small-region removal on an (ny, nx) grid field; returns the new inlier mask."""
+    dx = np.ascontiguousarray(dx, np.int32)
+    dy = np.ascontiguousarray(dy, np.int32)
+    out = np.ascontiguousarray(inl, np.uint8).copy()
+    ny, nx = out.shape
+    lib().pgmo_remove_small_regions(_p(dx), _p(dy), _p(out), nx, ny, stride, min_px, link_px)
+    return out.astype(bool)
+
 
 def reflect101(i: int, n: int) -> int:
     return lib().pgmo_reflect101(i, n)

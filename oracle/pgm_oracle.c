@@ -530,6 +530,51 @@ static void check_and_update(field_t* fw, field_t* bw, int fwd_bwd, int tau)
     }
 }
 
+/* Small-region removal (Sec. III-E, after FlowFields): segment the field, then drop the
+ * regions whose area is too small. READING: only inliers take part; the segments are the
+ * connected components of the 4-neighbour graph on the seed grid whose edges join inliers
+ * with displacements closer than link_px (Euclidean, integer comparison of squares); a
+ * region's area counts stride^2 pixels per seed; it is applied once, to the forward field at
+ * full resolution after its consistency check, before the output. Breadth-first search. */
+void pgmo_remove_small_regions(const int32_t* dx, const int32_t* dy, uint8_t* inl, int nx, int ny,
+                               int stride, int min_px, int link_px)
+{
+    const int n = nx * ny;
+    int* comp = malloc((size_t)n * sizeof(int));
+    int* queue = malloc((size_t)n * sizeof(int));
+    int* size = malloc((size_t)n * sizeof(int));
+    for (int s = 0; s < n; s++) comp[s] = -1;
+    const long T2 = (long)link_px * link_px;
+    int ncomp = 0;
+    for (int s0 = 0; s0 < n; s0++) {
+        if (!inl[s0] || comp[s0] >= 0) continue;
+        int head = 0, tail = 0;
+        queue[tail++] = s0;
+        comp[s0] = ncomp;
+        while (head < tail) {
+            int s = queue[head++];
+            int i = s % nx, j = s / nx;
+            const int ni[4] = {i - 1, i + 1, i, i};
+            const int nj[4] = {j, j, j - 1, j + 1};
+            for (int k = 0; k < 4; k++) {
+                if (ni[k] < 0 || nj[k] < 0 || ni[k] >= nx || nj[k] >= ny) continue;
+                int t = nj[k] * nx + ni[k];
+                if (!inl[t] || comp[t] >= 0) continue;
+                long ex = (long)dx[s] - dx[t], ey = (long)dy[s] - dy[t];
+                if (ex * ex + ey * ey >= T2) continue;
+                comp[t] = ncomp;
+                queue[tail++] = t;
+            }
+        }
+        size[ncomp++] = tail;
+    }
+    for (int s = 0; s < n; s++)
+        if (inl[s] && (long)size[comp[s]] * stride * stride < (long)min_px) inl[s] = 0;
+    free(comp);
+    free(queue);
+    free(size);
+}
+
 static int32_t dist_bits(const field_t* f, int s)
 {
     if (!f->init[s]) return 0x7FFFFFFF;
@@ -603,6 +648,7 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
     if (p->init_mode != PGMO_INIT_RANDOM && p->init_mode != PGMO_INIT_EXHAUSTIVE) return -1;
     if (w > 16384 || h > 16384) return -1;
     if (p->refine_rounds > 0 && p->levels < 2) return -1;
+    if (p->min_region_px < 0 || (p->min_region_px > 0 && p->region_link_px < 1)) return -1;
     if (pitch < 3 * w) return -1;
     for (int l = 0; l < p->levels; l++) if (p->iters[l] < 0 || p->iters[l] > 255) return -1;
     int L = p->levels;
@@ -697,6 +743,11 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
             for (int d = 0; d < 2; d++) iterate(&run, &F[d][l], t, l, d, sidx, W, schedule);
         /* Step 2 and 3 */
         check_and_update(&F[0][l], &F[1][l], p->fwd_bwd, p->consistency_px);
+    }
+    if (p->min_region_px > 0) {
+        field_t* f = &F[0][0];
+        pgmo_remove_small_regions(f->dx, f->dy, f->inl, f->nx, f->ny, f->stride, p->min_region_px,
+                                  p->region_link_px);
     }
 
     if (trace) {

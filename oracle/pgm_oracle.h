@@ -11,8 +11,8 @@
  * 2*C channels per pixel in the order [Gx_0..Gx_{C-1}, Gy_0..Gy_{C-1}] (Sec. III-A, Eq. 2).
  *
  * Parity status: the gradient image, pyramid, patch distance, Philox generator, random-search
- * offsets, exhaustive initialisation, propagation/search on small cases, the consistency check
- * and the level transitions are pinned by independent tests. The scan-order schedule
+ * offsets, exhaustive initialisation, propagation/search on small cases, the consistency check,
+ * the level transitions and the small-region removal are pinned by independent tests. The scan-order schedule
  * (PGMO_SCAN) is parity unpinned beyond invariants: the paper prints no worked example.
  */
 #ifndef PGM_ORACLE_H
@@ -50,6 +50,8 @@ typedef struct {
     int32_t consistency_px;            /* tau: consistent iff |d_f + d_b|^2 <= tau^2         */
     int32_t init_mode;                 /* PGMO_INIT_*                                        */
     int32_t refine_rounds;             /* N of Sec. III-D (refinement between m and m-1)     */
+    int32_t min_region_px;             /* small-region removal (Sec. III-E): 0 = off         */
+    int32_t region_link_px;            /* neighbours link when |d_a - d_b| < this            */
     uint64_t rng_seed;                 /* key of the counter-based generator                 */
 } pgmo_params;
 
@@ -87,6 +89,13 @@ int pgmo_grid_nearest(int x, int nseeds, int stride);
 int pgmo_geometry(const pgmo_params* p, int w, int h, int32_t* lw, int32_t* lh, int32_t* lnx, int32_t* lny);
 /* search radius of the initial (coarsest) level */
 int pgmo_top_radius(const pgmo_params* p, int w, int h);
+
+/* Small-region removal (Sec. III-E) on one grid field: inlier seeds are segmented into
+ * regions -- two 4-neighbouring inliers belong together when their displacements differ by
+ * less than link_px (Euclidean) -- and the inliers of every region whose area (seeds x
+ * stride^2 pixels) is below min_px become outliers. inl (0/1) is updated in place. */
+void pgmo_remove_small_regions(const int32_t* dx, const int32_t* dy, uint8_t* inl, int nx, int ny,
+                               int stride, int min_px, int link_px);
 
 /* Step 1 alone (propagation + limited random search, Eq. 4-5) on one field, for tests:
  * iterations t0 .. t0+n_iter-1 with search radius W. Ga / Gb are the features of this and

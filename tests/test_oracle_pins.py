@@ -557,3 +557,96 @@ def test_invalid_parameters_rejected():
                 dict(sobel_ksize=7), dict(radius=0), dict(feature=5), dict(iters=[300, 4, 4])):
         with pytest.raises(ValueError):
             oracle.match(base_params(**bad), img, img)
+
+
+# ---- small-region removal (Sec. III-E) ----
+
+def _regions_by_csgraph(dx, dy, inl, stride, min_px, link_px):
+    """Expected result from scipy's connected components of the linked-inlier graph."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    ny, nx = inl.shape
+    idx = np.arange(nx * ny).reshape(ny, nx)
+    rows, cols = [], []
+    for a_sl, b_sl in (((slice(None), slice(0, nx - 1)), (slice(None), slice(1, nx))),
+                       ((slice(0, ny - 1), slice(None)), (slice(1, ny), slice(None)))):
+        ok = inl[a_sl] & inl[b_sl]
+        d2 = (dx[a_sl].astype(np.int64) - dx[b_sl]) ** 2 + (dy[a_sl].astype(np.int64) - dy[b_sl]) ** 2
+        ok &= d2 < link_px * link_px
+        rows.append(idx[a_sl][ok]); cols.append(idx[b_sl][ok])
+    r = np.concatenate(rows); c = np.concatenate(cols)
+    g = coo_matrix((np.ones(len(r)), (r, c)), shape=(nx * ny, nx * ny))
+    _, lab = connected_components(g, directed=False)
+    lab = lab.reshape(ny, nx)
+    sizes = np.bincount(lab[inl], minlength=lab.max() + 1)
+    keep = inl.copy()
+    keep[inl] = sizes[lab[inl]] * stride * stride >= min_px
+    return keep
+
+
+@pytest.mark.parametrize("seed,stride,min_px,link", [(0, 1, 9, 12), (1, 3, 27, 3), (2, 2, 12, 2), (3, 1, 30, 5)])
+def test_region_removal_matches_scipy_components(oracle_lib, seed, stride, min_px, link):
+    rng = np.random.default_rng(seed)
+    ny, nx = 23, 31
+    dx = rng.integers(-6, 7, (ny, nx)).astype(np.int32)
+    dy = rng.integers(-6, 7, (ny, nx)).astype(np.int32)
+    inl = rng.random((ny, nx)) < 0.7
+    got = oracle.remove_small_regions(dx, dy, inl, stride, min_px, link)
+    want = _regions_by_csgraph(dx, dy, inl, stride, min_px, link)
+    assert np.array_equal(got, want)
+    assert not np.any(got & ~inl)          # never creates inliers
+
+
+def test_region_removal_piecewise_constant_matches_ndimage_label(oracle_lib):
+    """Regions of constant displacement, neighbours of different regions far apart: the
+    segments are exactly the 4-connected components of each constant region."""
+    from scipy import ndimage
+    rng = np.random.default_rng(7)
+    ny, nx = 40, 50
+    lab = rng.integers(0, 6, (ny // 4, nx // 5)).repeat(4, 0).repeat(5, 1)
+    lab[rng.random((ny, nx)) < 0.05] = 6 + rng.integers(0, 4)    # speckle
+    dx = (lab * 30).astype(np.int32)
+    dy = (-lab * 20).astype(np.int32)
+    inl = rng.random((ny, nx)) < 0.9
+    want = np.zeros_like(inl)
+    for v in np.unique(lab):
+        comp, n = ndimage.label((lab == v) & inl)   # 4-connectivity
+        sizes = np.bincount(comp.ravel())
+        want |= (comp > 0) & (sizes[comp] >= 9)
+    got = oracle.remove_small_regions(dx, dy, inl, 1, 9, 12)
+    assert np.array_equal(got, want)
+
+
+def test_region_removal_special_cases(oracle_lib):
+    ny, nx = 9, 11
+    z = np.zeros((ny, nx), np.int32)
+    inl = np.zeros((ny, nx), bool)
+    inl[::2, ::2] = True                      # isolated single inliers
+    assert not oracle.remove_small_regions(z, z, inl, 1, 9, 12).any()       # 1 px < 9
+    assert np.array_equal(oracle.remove_small_regions(z, z, inl, 3, 9, 12), inl)   # 9 px each
+    full = np.ones((ny, nx), bool)
+    assert oracle.remove_small_regions(z, z, full, 1, 9, 12).all()          # one big region
+    # two seeds linked only when their displacements differ by less than link
+    inl2 = np.zeros((ny, nx), bool); inl2[4, 4:6] = True
+    dxs = z.copy(); dxs[4, 5] = 3
+    assert oracle.remove_small_regions(dxs, z, inl2, 3, 18, 4).sum() == 2   # |3| < 4: 18 px kept
+    assert oracle.remove_small_regions(dxs, z, inl2, 3, 18, 3).sum() == 0   # |3| = 3: split
+
+
+def test_region_removal_in_the_pipeline_only_clears_forward_inliers(oracle_lib):
+    pr = synth.config_pair(1, 0)
+    p0 = base_params(seed_stride=1, levels=2, iters=[2, 2], rng_seed=77)
+    a = oracle.match(p0, pr.img1, pr.img2, trace=False)
+    b = oracle.match(dict(p0, min_region_px=9, region_link_px=12), pr.img1, pr.img2, trace=False)
+    for k in ("x1", "y1", "x2", "y2", "dist"):
+        assert np.array_equal(a["fwd"][k], b["fwd"][k])
+    assert np.array_equal(a["bwd"], b["bwd"])
+    ia = (a["fwd"]["flags"] & 2) != 0
+    ib = (b["fwd"]["flags"] & 2) != 0
+    assert not np.any(ib & ~ia) and ib.sum() < ia.sum()
+    assert b["n_inliers"] == ib.sum()
+    ny, nx = pr.img1.shape[0], pr.img1.shape[1]
+    want = oracle.remove_small_regions((a["fwd"]["x2"] - a["fwd"]["x1"]).reshape(ny, nx),
+                                       (a["fwd"]["y2"] - a["fwd"]["y1"]).reshape(ny, nx),
+                                       ia.reshape(ny, nx), 1, 9, 12)
+    assert np.array_equal(ib.reshape(ny, nx), want)
