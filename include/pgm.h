@@ -74,6 +74,11 @@ typedef struct {
     int32_t consistency_px;          /* tau: consistent iff |d_fwd + d_bwd|^2 <= tau^2      */
     int32_t init_mode;               /* PGM_INIT_*                                           */
     int32_t refine_rounds;           /* N of Sec. III-D: round trips between m and m-1       */
+    int32_t min_region_px;           /* small-region removal (Sec. III-E): forward inliers   */
+                                     /* in regions of fewer pixels (seeds x stride^2) become */
+                                     /* outliers; 0 = off (the paper uses 9)                 */
+    int32_t region_link_px;          /* 4-neighbouring inliers share a region when their     */
+                                     /* displacements differ by less than this (1..65535)   */
     uint64_t rng_seed;               /* key of the counter-based random generator            */
 } pgm_params;
 
@@ -216,10 +221,10 @@ PGM_API pgm_status pgm_dump_pyramid(void* ctx, int32_t level, int32_t image, uin
  * draws the random numbers and builds the level-0 gradients and pyramid level 1;
  * PGM_K_PYRAMID: pyramid levels 2 and up; PGM_K_GRADIENT: gradients of levels 1 and up;
  * PGM_K_LEVEL: all sweeps of a level small enough for one work-group's LDS, whose distance
- * evaluations count under PGM_K_SWEEP): */
+ * evaluations count under PGM_K_SWEEP; PGM_K_REGION: small-region removal): */
 enum { PGM_K_PYRAMID = 0, PGM_K_GRADIENT = 1, PGM_K_PREP = 2, PGM_K_INIT = 3, PGM_K_DOWN = 4,
        PGM_K_UP = 5, PGM_K_SWEEP = 6, PGM_K_CHECK = 7, PGM_K_OUTPUT = 8, PGM_K_COMPACT = 9,
-       PGM_K_LEVEL = 10, PGM_K_KINDS = 11 };
+       PGM_K_LEVEL = 10, PGM_K_REGION = 11, PGM_K_KINDS = 12 };
 PGM_API pgm_status pgm_profile(void* ctx, int32_t enable);
 PGM_API pgm_status pgm_profile_read(void* ctx, int32_t kind, int64_t* host_launches,
                                     double* host_total_ms, uint64_t* host_evals);

@@ -36,6 +36,7 @@ class pgm_params(C.Structure):
         ("radius", C.c_int32), ("max_disp", C.c_int32), ("sobel_ksize", C.c_int32),
         ("feature", C.c_int32), ("color", C.c_int32), ("fwd_bwd", C.c_int32),
         ("consistency_px", C.c_int32), ("init_mode", C.c_int32), ("refine_rounds", C.c_int32),
+        ("min_region_px", C.c_int32), ("region_link_px", C.c_int32),
         ("rng_seed", C.c_uint64),
     ]
 
@@ -74,8 +75,10 @@ EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_ma
            "pgm_last_error", "pgm_destroy")
 
 # kernel kinds of pgm_profile_read
-K_PYRAMID, K_GRADIENT, K_PREP, K_INIT, K_DOWN, K_UP, K_SWEEP, K_CHECK, K_OUTPUT, K_COMPACT, K_LEVEL = range(11)
-KIND_NAMES = ("pyramid", "gradient", "prep", "init", "down", "up", "sweep", "check", "output", "compact", "level")
+K_PYRAMID, K_GRADIENT, K_PREP, K_INIT, K_DOWN, K_UP, K_SWEEP, K_CHECK, K_OUTPUT, K_COMPACT, K_LEVEL, K_REGION = \
+    range(12)
+KIND_NAMES = ("pyramid", "gradient", "prep", "init", "down", "up", "sweep", "check", "output", "compact", "level",
+              "region")
 
 
 class PGMError(RuntimeError):

@@ -32,6 +32,7 @@ struct Layout {
     long long cnt_cap[4] = {0, 0, 0, 0};
     size_t blockcnt = 0;
     size_t cntpart = 0;
+    size_t cclabel = 0, ccsize = 0;
     // the random-number table is shared by all pairs of a batch; everything else is per pair
     // (offsets above are relative to the pair's slice, except rnd / rnd_init)
     size_t shared_bytes = 0, pair_bytes = 0;
@@ -92,6 +93,9 @@ const char* validate(const pgm_params* p, int w, int h)
     if (p->init_mode != PGM_INIT_RANDOM && p->init_mode != PGM_INIT_EXHAUSTIVE) return "unknown init_mode";
     if (p->refine_rounds < 0 || p->refine_rounds > 16) return "refine_rounds must be within 0..16";
     if (p->refine_rounds > 0 && p->levels < 2) return "refinement needs at least two levels";
+    if (p->min_region_px < 0) return "min_region_px must not be negative";
+    if (p->min_region_px > 0 && (p->region_link_px < 1 || p->region_link_px > 65535))
+        return "region_link_px must be within 1..65535";
     return nullptr;
 }
 
@@ -165,6 +169,9 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
     Y.blockcnt = take(cur, (size_t)((Y.lnx[0] * Y.lny[0] + 255) / 256) * 4);
     // partial evaluation sums of the count reduction: COUNT_SLICES x KINDS per pair
     Y.cntpart = take(cur, (size_t)COUNT_SLICES * CountArgs::KINDS * sizeof(unsigned long long));
+    // region labels and sizes on the level-0 grid (small-region removal)
+    Y.cclabel = take(cur, (size_t)Y.lnx[0] * Y.lny[0] * 4);
+    Y.ccsize = take(cur, (size_t)Y.lnx[0] * Y.lny[0] * 4);
     Y.pair_bytes = (cur + 255) & ~(size_t)255;
     Y.total = Y.shared_bytes + Y.pair_bytes;
 }
@@ -265,6 +272,8 @@ pgm_status pgm_default_params(pgm_params* p, int32_t preset)
     p->consistency_px = 1;
     p->init_mode = PGM_INIT_RANDOM;
     p->refine_rounds = 0;
+    p->min_region_px = 0;
+    p->region_link_px = 12;
     switch (preset) {
     case PGM_PRESET_PAPER:   // Sec. IV: W=2, S=5, L=3, N=2, 6 / 4 iterations; r = 7 / 5
         p->seed_stride = 1;
@@ -273,6 +282,7 @@ pgm_status pgm_default_params(pgm_params* p, int32_t preset)
         p->iters[0] = 6;
         p->max_disp = 0;
         p->refine_rounds = 2;
+        p->min_region_px = 9;    // Sec. III-E: regions below 9 pixels are removed
         p->rng_seed = 0;
         return PGM_OK;
     case PGM_PRESET_CONFIG1:
@@ -619,6 +629,20 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         ca.rec_valid = enter == ENTER_DOWN_FO || enter == ENTER_UP_FO;
         rec_valid[l] = ca.rec_valid;
         PGM_HIP(c, timed(PGM_K_CHECK, [&] { return launch_check(ca, s); }));
+    }
+
+    // small-region removal on the forward field at full resolution (Sec. III-E)
+    if (p->min_region_px > 0) {
+        RegionArgs ra2;
+        ra2.f = field(0, 0);
+        ra2.g = geo(0);
+        ra2.b = batch(1);
+        ra2.label = (int32_t*)(pw0 + Y.cclabel);
+        ra2.size = (int32_t*)(pw0 + Y.ccsize);
+        ra2.min_px = p->min_region_px;
+        ra2.link2 = (long long)p->region_link_px * p->region_link_px;
+        c->nlaunch += 3;   // four launches, one counted by timed()
+        PGM_HIP(c, timed(PGM_K_REGION, [&] { return launch_regions(ra2, s); }));
     }
 
     // level-0 matches on the grid (Sec. III-G)

@@ -194,6 +194,18 @@ hipError_t launch_sweep(const SweepArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_down(const TransArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_up(const TransArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);
+// small-region removal on the level-0 forward field: four launches (labels, unions, region
+// sizes, flags)
+struct RegionArgs {
+    Field f;               // level-0 forward field, pair 0
+    Geo g;
+    Batch b;
+    int32_t* label;        // nx*ny per pair, pair 0
+    int32_t* size;         // nx*ny per pair, pair 0
+    int min_px;
+    long long link2;       // region_link_px^2
+};
+hipError_t launch_regions(const RegionArgs& a, hipStream_t s);
 // every sweep of a small level, one work-group per pair and direction
 hipError_t launch_level(const LevelArgs& a, int C2, int f32, hipStream_t s);
 // let every whole-level kernel use up to `bytes` of dynamic LDS (once per context)

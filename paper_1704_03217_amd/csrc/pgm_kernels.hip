@@ -701,6 +701,103 @@ __global__ __launch_bounds__((LevelShape<PMAX, F32>::threads)) void k_level(Leve
 }
 
 // ---------------------------------------------------------------------------------------
+// small-region removal (Sec. III-E): the inliers of the level-0 forward field are segmented
+// into 4-connected regions of close displacements by union-find on a label array (a root is
+// its own label, a label never exceeds its index and only decreases, joins are atomicMin on
+// roots), then the inliers of regions smaller than min_px pixels lose their inlier flag. The
+// resulting flags do not depend on the order of the joins.
+// ---------------------------------------------------------------------------------------
+
+// Root of x. Labels strictly decrease along the walk, so it ends within n steps; the bound
+// also holds while other threads lower labels.
+__device__ __forceinline__ int cc_find(const int32_t* L, int x, int n)
+{
+    for (int k = 0; k < n; k++) {
+        const int y = __atomic_load_n(&L[x], __ATOMIC_RELAXED);
+        if (y == x) break;
+        x = y;
+    }
+    return x;
+}
+
+// Join the regions of a and b: hook the larger root under the smaller. When another thread
+// moved the larger root first, retry from its new parent; every retry lowers that root, so
+// the loop ends within n rounds (the bound keeps it finite whatever happens).
+__device__ __forceinline__ void cc_union(int32_t* L, int a, int b, int n)
+{
+    for (int k = 0; k <= n; k++) {
+        a = cc_find(L, a, n);
+        b = cc_find(L, b, n);
+        if (a == b) return;
+        if (a < b) { const int t = a; a = b; b = t; }
+        const int old = atomicMin(&L[a], b);
+        if (old == a) return;
+        a = old;
+    }
+}
+
+__device__ __forceinline__ bool cc_linked(const Field& f, int s, int t, long long link2)
+{
+    const uint32_t a = f.disp[s], b = f.disp[t];
+    const long long ex = d_x(a) - d_x(b), ey = d_y(a) - d_y(b);
+    return ex * ex + ey * ey < link2;
+}
+
+__global__ __launch_bounds__(256) void k_cc_init(RegionArgs a)
+{
+    const int n = a.g.nx * a.g.ny;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const size_t zo = (size_t)blockIdx.z * (size_t)a.b.zs;
+    zoff(a.label, zo)[s] = s;
+    zoff(a.size, zo)[s] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_cc_union(RegionArgs a)
+{
+    const Geo& g = a.g;
+    const int n = g.nx * g.ny;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const size_t zo = (size_t)blockIdx.z * (size_t)a.b.zs;
+    const Field f = pair_field(a.f, zo);
+    int32_t* L = zoff(a.label, zo);
+    if (!(f.flags[s] & ST_INL)) return;
+    const int i = s % g.nx, j = s / g.nx;
+    if (i + 1 < g.nx && (f.flags[s + 1] & ST_INL) && cc_linked(f, s, s + 1, a.link2)) cc_union(L, s, s + 1, n);
+    if (j + 1 < g.ny && (f.flags[s + g.nx] & ST_INL) && cc_linked(f, s, s + g.nx, a.link2))
+        cc_union(L, s, s + g.nx, n);
+}
+
+__global__ __launch_bounds__(256) void k_cc_size(RegionArgs a)
+{
+    const int n = a.g.nx * a.g.ny;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const size_t zo = (size_t)blockIdx.z * (size_t)a.b.zs;
+    const Field f = pair_field(a.f, zo);
+    if (!(f.flags[s] & ST_INL)) return;
+    int32_t* L = zoff(a.label, zo);
+    const int r = cc_find(L, s, n);
+    L[s] = r;   // a root stays a root now that every join is done
+    atomicAdd(zoff(a.size, zo) + r, 1);
+}
+
+__global__ __launch_bounds__(256) void k_cc_apply(RegionArgs a)
+{
+    const int n = a.g.nx * a.g.ny;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const size_t zo = (size_t)blockIdx.z * (size_t)a.b.zs;
+    const Field f = pair_field(a.f, zo);
+    const uint8_t fl = f.flags[s];
+    if (!(fl & ST_INL)) return;
+    const int r = zoff(a.label, zo)[s];
+    const long long area = (long long)zoff(a.size, zo)[r] * a.g.stride * a.g.stride;
+    if (area < a.min_px) f.flags[s] = (uint8_t)(fl & ~ST_INL);
+}
+
+// ---------------------------------------------------------------------------------------
 // output on the level-0 grid and the compaction of forward inliers (Sec. III-G)
 // ---------------------------------------------------------------------------------------
 
@@ -1244,6 +1341,17 @@ hipError_t launch_check(const CheckArgs& a, hipStream_t s)
 {
     const int n = a.g.nx * a.g.ny;
     hipLaunchKernelGGL(k_check, dim3((n + 255) / 256, 2, a.b.npairs), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_regions(const RegionArgs& a, hipStream_t s)
+{
+    const int n = a.g.nx * a.g.ny;
+    const dim3 grid((n + 255) / 256, 1, a.b.npairs);
+    hipLaunchKernelGGL(k_cc_init, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_cc_union, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_cc_size, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_cc_apply, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -73,6 +73,7 @@ def test_paper_preset():
     assert d["iters"] == [6, 4, 4]
     assert (d["patch_fwd"], d["patch_bwd"]) == (15, 11)
     assert d["seed_stride"] == 1
+    assert (d["min_region_px"], d["region_link_px"]) == (9, 12)   # Sec. III-E
 
 
 @pytest.mark.parametrize("w,h,L,stride", [(1024, 436, 5, 3), (1242, 375, 5, 3), (256, 192, 3, 3),
@@ -99,7 +100,9 @@ def test_query_workspace_of_config2_is_modest():
                                  dict(patch_bwd=17), dict(iters=[256, 1, 1]), dict(radius=0),
                                  dict(sobel_ksize=7), dict(feature=2), dict(color=3), dict(fwd_bwd=2),
                                  dict(consistency_px=-1), dict(init_mode=2), dict(refine_rounds=17),
-                                 dict(levels=1, iters=[1], refine_rounds=1), dict(max_disp=-1)])
+                                 dict(levels=1, iters=[1], refine_rounds=1), dict(max_disp=-1),
+                                 dict(min_region_px=-1), dict(min_region_px=9, region_link_px=0),
+                                 dict(min_region_px=9, region_link_px=65536)])
 def test_query_rejects_invalid_parameters(bad):
     with pytest.raises(pgm.PGMError) as e:
         pgm.pgm_query(base_params(**bad), 64, 64)

@@ -37,7 +37,7 @@ def run_batch(m, params, pairs):
     return fwd, bwd, comp, nin, int(o["n_evals"].item())
 
 
-@pytest.mark.parametrize("case", ["config1_x3", "patch5_11_gray_x4", "refine_x2", "direction_x2"])
+@pytest.mark.parametrize("case", ["config1_x3", "patch5_11_gray_x4", "refine_x2", "direction_x2", "regions_x3"])
 def test_batch_equals_oracle_per_pair(matcher, case):
     if case == "config1_x3":
         pairs = [synth.config_pair(1, i) for i in range(3)]
@@ -48,6 +48,9 @@ def test_batch_equals_oracle_per_pair(matcher, case):
     elif case == "refine_x2":
         pairs = [synth.config_pair(1, i) for i in range(2)]
         params = base_params(refine_rounds=2, rng_seed=32)
+    elif case == "regions_x3":
+        pairs = [synth.config_pair(1, i) for i in range(3)]
+        params = base_params(min_region_px=45, region_link_px=1, rng_seed=34)
     else:
         pairs = [synth.config_pair(1, i) for i in range(2)]
         params = base_params(feature=1, rng_seed=33)

@@ -115,6 +115,10 @@ CASES = {
     "wide_16384x12": (lambda: synth.rect_pair(9, 12, 16384, n_rect=2, dmax=20), base_params(levels=2, iters=[2, 2], max_disp=20, seed_stride=5)),
     "translation": (lambda: synth.translate_pair(3, 72, 96, 10, -6), base_params(levels=2, iters=[8, 8], max_disp=16)),
     "identical": (lambda: (lambda p: synth.Pair(p.img1, p.img1, p.flow, p.valid))(synth.config_pair(1)), base_params(rng_seed=3)),
+    # small-region removal (Sec. III-E): the paper's 9 px / 12 px on a dense field, and a
+    # stride-3 grid where regions under 9 seeds of equal displacement go
+    "regions_dense": (lambda: synth.rect_pair(21, 72, 96, dmax=8), base_params(seed_stride=1, levels=2, iters=[3, 3], max_disp=8, min_region_px=9, region_link_px=12, rng_seed=16)),
+    "regions_stride3": (lambda: synth.config_pair(1), base_params(min_region_px=81, region_link_px=1, rng_seed=17)),
 }
 
 
