@@ -84,6 +84,8 @@ def lib():
         L.pgmo_grid_nearest.argtypes = [C.c_int, C.c_int, C.c_int]
         L.pgmo_geometry.argtypes = [C.POINTER(Params), C.c_int, C.c_int, P, P, P, P]
         L.pgmo_top_radius.argtypes = [C.POINTER(Params), C.c_int, C.c_int]
+        L.pgmo_sign.argtypes = [P, C.c_int]
+        L.pgmo_sign.restype = None
         L.pgmo_remove_small_regions.argtypes = [P, P, P] + [C.c_int] * 5
         L.pgmo_remove_small_regions.restype = None
         L.pgmo_match.argtypes = [C.POINTER(Params), P, P, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -108,6 +110,13 @@ def make_params(d: dict) -> Params:
 
 
 # ---- building blocks ----
+
+def sign(G: np.ndarray) -> np.ndarray:
+    """Literal "G./|G|" of Sec. III-F: the sign of every gradient component (int16)."""
+    out = np.ascontiguousarray(G, np.int16).copy()
+    lib().pgmo_sign(_p(out), out.size)
+    return out
+
 
 def remove_small_regions(dx: np.ndarray, dy: np.ndarray, inl: np.ndarray, stride: int, min_px: int,
                          link_px: int) -> np.ndarray:

@@ -149,6 +149,13 @@ int64_t pgmo_dist_i16(const int16_t* Ga, const int16_t* Gb, int w, int h, int C2
     return s;
 }
 
+/* Sec. III-F, "G./|G|" read literally: the element-wise division of G by |G| leaves the
+ * sign of every gradient component; a zero component stays zero (0/0 taken as 0). */
+void pgmo_sign(int16_t* G, int n)
+{
+    for (int k = 0; k < n; k++) G[k] = (int16_t)(G[k] > 0 ? 1 : (G[k] < 0 ? -1 : 0));
+}
+
 /* The float features are unit-vector components: zero or of magnitude >= 2^-14 (the
  * gradient is at most 12240 for S <= 5), hence multiples of 2^-37 in [-1, 1]. Their
  * differences and the sum of up to 16*16*6 of them are therefore exact in double, so this
@@ -280,7 +287,7 @@ typedef struct {
 static double cost(run_t* r, const field_t* f, int xa, int ya, int xb, int yb)
 {
     r->evals++;
-    if (f->feature == PGMO_FEAT_INT16)
+    if (f->feature != PGMO_FEAT_F32_DIR)
         return (double)pgmo_dist_i16(f->Gi_self, f->Gi_other, f->w, f->h, f->C2, f->P, xa, ya, xb, yb);
     return (double)pgmo_dist_f32(f->Gf_self, f->Gf_other, f->w, f->h, f->C2, f->P, xa, ya, xb, yb);
 }
@@ -578,7 +585,7 @@ void pgmo_remove_small_regions(const int32_t* dx, const int32_t* dy, uint8_t* in
 static int32_t dist_bits(const field_t* f, int s)
 {
     if (!f->init[s]) return 0x7FFFFFFF;
-    if (f->feature == PGMO_FEAT_INT16) return (int32_t)f->dist[s];
+    if (f->feature != PGMO_FEAT_F32_DIR) return (int32_t)f->dist[s];
     float v = (float)f->dist[s];
     int32_t b;
     memcpy(&b, &v, 4);
@@ -608,13 +615,13 @@ int pgmo_sweep(const pgmo_params* p, int level, int dir, int stage, int W, const
     f.w = w; f.h = h; f.stride = p->seed_stride;
     f.nx = pgmo_grid_count(w, f.stride); f.ny = pgmo_grid_count(h, f.stride); f.n = f.nx * f.ny;
     f.C2 = 2 * ch; f.P = P; f.feature = p->feature;
-    if (p->feature == PGMO_FEAT_INT16) { f.Gi_self = Ga; f.Gi_other = Gb; }
+    if (p->feature != PGMO_FEAT_F32_DIR) { f.Gi_self = Ga; f.Gi_other = Gb; }
     else { f.Gf_self = Ga; f.Gf_other = Gb; }
     f.dx = dx; f.dy = dy; f.init = init;
     f.dist = malloc((size_t)f.n * sizeof(double));
     f.rec = calloc((size_t)f.n, 1); f.inl = calloc((size_t)f.n, 1);
     for (int s = 0; s < f.n; s++) {
-        if (p->feature == PGMO_FEAT_INT16) f.dist[s] = (double)dist[s];
+        if (p->feature != PGMO_FEAT_F32_DIR) f.dist[s] = (double)dist[s];
         else { float v; memcpy(&v, &dist[s], 4); f.dist[s] = (double)v; }
     }
     run_t run;
@@ -644,7 +651,7 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
     if (p->sobel_ksize != 3 && p->sobel_ksize != 5) return -1;
     if (p->patch_fwd < 1 || p->patch_fwd > 16 || p->patch_bwd < 1 || p->patch_bwd > 16) return -1;
     if (p->radius < 1 || p->consistency_px < 0 || p->refine_rounds < 0 || p->refine_rounds > 16) return -1;
-    if (p->feature != PGMO_FEAT_INT16 && p->feature != PGMO_FEAT_F32_DIR) return -1;
+    if (p->feature != PGMO_FEAT_INT16 && p->feature != PGMO_FEAT_F32_DIR && p->feature != PGMO_FEAT_SIGN) return -1;
     if (p->init_mode != PGMO_INIT_RANDOM && p->init_mode != PGMO_INIT_EXHAUSTIVE) return -1;
     if (w > 16384 || h > 16384) return -1;
     if (p->refine_rounds > 0 && p->levels < 2) return -1;
@@ -684,6 +691,7 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
                 free(gy);
             }
             Gf[im][l] = NULL;
+            if (p->feature == PGMO_FEAT_SIGN) pgmo_sign(Gi[im][l], (int)(npx * C2));
             if (p->feature == PGMO_FEAT_F32_DIR) {
                 Gf[im][l] = malloc(npx * C2 * sizeof(float));
                 pgmo_direction(Gi[im][l], (int)npx, ch, Gf[im][l]);

@@ -26,7 +26,7 @@ extern "C" {
 
 #define PGMO_MAX_LEVELS 8
 
-enum { PGMO_FEAT_INT16 = 0, PGMO_FEAT_F32_DIR = 1 };
+enum { PGMO_FEAT_INT16 = 0, PGMO_FEAT_F32_DIR = 1, PGMO_FEAT_SIGN = 2 };
 enum { PGMO_RGB = 0, PGMO_GRAY = 1 };
 enum { PGMO_INIT_RANDOM = 0, PGMO_INIT_EXHAUSTIVE = 1 };
 enum { PGMO_SYNC = 0, PGMO_SCAN = 1 };
@@ -69,6 +69,9 @@ void pgmo_gray(const uint8_t* rgb, int w, int h, int pitch, uint8_t* y);
 void pgmo_gradient_image(const uint8_t* img, int w, int h, int pitch, int ch, int ksize, int16_t* G);
 /* direction-only gradient image (Sec. III-F): per channel (Gx,Gy)/|(Gx,Gy)|, 0 -> (0,0) */
 void pgmo_direction(const int16_t* G, int npix, int ch, float* U);
+/* literal reading of "G./|G|" (Sec. III-F): every element divided by its own absolute
+ * value, i.e. its sign in {-1, 0, 1} (0 stays 0); in place on npix*C2 values */
+void pgmo_sign(int16_t* G, int n);
 /* patch distance (Eq. 3, absolute-difference reading) between the patch of Ga at (xa,ya)
  * and the patch of Gb at (xb,yb); C2 = channels per pixel (2*ch); P = patch side */
 int64_t pgmo_dist_i16(const int16_t* Ga, const int16_t* Gb, int w, int h, int C2, int P,

@@ -650,3 +650,39 @@ def test_region_removal_in_the_pipeline_only_clears_forward_inliers(oracle_lib):
                                        (a["fwd"]["y2"] - a["fwd"]["y1"]).reshape(ny, nx),
                                        ia.reshape(ny, nx), 1, 9, 12)
     assert np.array_equal(ib.reshape(ny, nx), want)
+
+
+# ---- literal-sign direction variant (Sec. III-F, "G./|G|" element-wise) ----
+
+def test_sign_feature_is_numpy_sign(oracle_lib):
+    rng = np.random.default_rng(5)
+    G = rng.integers(-30000, 30000, 5000).astype(np.int16)
+    G[::7] = 0
+    assert np.array_equal(oracle.sign(G), np.sign(G).astype(np.int16))
+
+
+def test_sign_feature_distance_counts_sign_disagreements(oracle_lib):
+    """On sign features the patch distance is the sum of |s_a - s_b|: 2 for opposite signs,
+    1 where exactly one side is zero (checked by brute force on a gradient image)."""
+    pair = synth.config_pair(1)
+    G1 = oracle.sign(oracle.gradient_image(pair.img1, 5))
+    G2 = oracle.sign(oracle.gradient_image(pair.img2, 5))
+    h, w, C2 = G1.shape
+    for (xa, ya, xb, yb) in [(40, 30, 43, 28), (0, 0, 5, 1), (w - 1, h - 1, w - 3, h - 2)]:
+        a = G1[np.clip(ya + np.arange(-4, 4), 0, h - 1)][:, np.clip(xa + np.arange(-4, 4), 0, w - 1)]
+        b = G2[np.clip(yb + np.arange(-4, 4), 0, h - 1)][:, np.clip(xb + np.arange(-4, 4), 0, w - 1)]
+        want = int((a.astype(int) != b).sum() + ((a.astype(int) * b) < 0).sum())
+        assert oracle.dist(G1, G2, 8, xa, ya, xb, yb) == want
+
+
+@pytest.mark.parametrize("dx,dy", [(6, -2), (-4, 4)])
+def test_sign_feature_recovers_translation(oracle_lib, dx, dy):
+    h, w = 72, 96
+    pair = synth.translate_pair(31 + dx, h, w, dx, dy)
+    p = base_params(levels=2, iters=[8, 8], max_disp=16, feature=2, rng_seed=5)
+    r = oracle.match(p, pair.img1, pair.img2)
+    st = r["levels"][0][0]
+    fin = _interior(_seed_pts(w, h, 3), w, h, (dx, dy), 8)
+    assert len(fin) > 100
+    ok = sum((st[s, 0], st[s, 1], st[s, 2]) == (dx, dy, 0) for s in fin)
+    assert ok >= 0.98 * len(fin)     # sign patches can tie; almost every seed is exact
