@@ -46,7 +46,9 @@ enum {
 };
 
 enum { PGM_FEAT_INT16 = 0,     /* full gradient image, int16 (PGM-C / PGM-G, Sec. III-F)      */
-       PGM_FEAT_F32_DIR = 1 }; /* direction-only unit gradients, float (PGM-CD / PGM-GD)      */
+       PGM_FEAT_F32_DIR = 1,   /* direction-only unit gradients, float (PGM-CD / PGM-GD)      */
+       PGM_FEAT_SIGN = 2 };    /* direction-only, "G./|G|" read element-wise: the sign of     */
+                               /* every gradient component in {-1, 0, 1} (integer distance)   */
 enum { PGM_RGB = 0, PGM_GRAY = 1 };                    /* 6- or 2-channel gradient image       */
 enum { PGM_INIT_RANDOM = 0, PGM_INIT_EXHAUSTIVE = 1 }; /* initial field at the coarsest level  */
 
@@ -200,6 +202,16 @@ PGM_API pgm_status pgm_server_pending(void* server, int32_t* host_queued, int32_
 PGM_API pgm_status pgm_server_drain(void* server);
 PGM_API const char* pgm_server_last_error(void* server);
 PGM_API void pgm_server_destroy(void* server);
+
+/* Matches as text for an external sparse-to-dense interpolator (Sec. III-G hands the
+ * grid matches to EpicFlow, whose match files hold one "x1 y1 x2 y2" line per match). Host
+ * only: formats the n matches at host_matches (copied from a pgm_match output), all of them
+ * or only those flagged PGM_FLAG_INLIER, as decimal lines "x1 y1 x2 y2\n" into host_buf
+ * (capacity cap bytes, not NUL-terminated) and stores the bytes needed in *host_len (always,
+ * so a call with host_buf NULL sizes the buffer). PGM_ENOMEM, with *host_len set, when cap
+ * is too small; nothing is written then. */
+PGM_API pgm_status pgm_format_matches(const pgm_match_t* host_matches, int64_t n, int32_t inliers_only,
+                                      char* host_buf, uint64_t cap, uint64_t* host_len);
 
 /* Debug copies of the last pgm_match's intermediate state into host memory; each waits for
  * the last call's stream to finish.

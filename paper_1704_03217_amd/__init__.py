@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libpgm.so")
 
 MAX_LEVELS = 8
 PGM_OK, PGM_EINVAL, PGM_ENOMEM, PGM_EDEVICE, PGM_EUNSUPPORTED = 0, -1, -2, -3, -5
-FEAT_INT16, FEAT_F32_DIR = 0, 1
+FEAT_INT16, FEAT_F32_DIR, FEAT_SIGN = 0, 1, 2
 RGB, GRAY = 0, 1
 INIT_RANDOM, INIT_EXHAUSTIVE = 0, 1
 FLAG_INIT, FLAG_INLIER, FLAG_RECORD = 1, 2, 4
@@ -70,7 +70,8 @@ MATCH_BYTES = 24
 
 EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_match_batch", "pgm_match_groups",
            "pgm_server_create", "pgm_server_submit", "pgm_server_poll", "pgm_server_pending",
-           "pgm_server_drain", "pgm_server_last_error", "pgm_server_destroy", "pgm_dump_level",
+           "pgm_server_drain", "pgm_server_last_error", "pgm_server_destroy", "pgm_format_matches",
+           "pgm_dump_level",
            "pgm_dump_gradient", "pgm_dump_pyramid", "pgm_profile", "pgm_profile_read",
            "pgm_last_error", "pgm_destroy")
 
@@ -128,6 +129,8 @@ def lib():
         L.pgm_server_last_error.restype = C.c_char_p
         L.pgm_server_destroy.argtypes = [V]
         L.pgm_server_destroy.restype = None
+        L.pgm_format_matches.argtypes = [V, C.c_int64, C.c_int32, V, C.c_uint64, C.POINTER(C.c_uint64)]
+        L.pgm_format_matches.restype = C.c_int32
         L.pgm_dump_level.argtypes = [V, C.c_int32, C.c_int32, V]
         L.pgm_dump_level.restype = C.c_int32
         L.pgm_dump_gradient.argtypes = [V, C.c_int32, C.c_int32, V]
@@ -260,6 +263,29 @@ def pgm_server_drain(server) -> None:
 
 def pgm_server_destroy(server) -> None:
     lib().pgm_server_destroy(server)
+
+
+def pgm_format_matches(matches: np.ndarray, inliers_only: bool = True) -> str:
+    """EpicFlow-style "x1 y1 x2 y2" lines of host matches (a MATCH_DTYPE array)."""
+    m = np.ascontiguousarray(matches).view(MATCH_DTYPE)
+    n = C.c_uint64()
+    ptr = m.ctypes.data if m.size else None
+    st = lib().pgm_format_matches(ptr, m.size, 1 if inliers_only else 0, None, 0, C.byref(n))
+    if st != PGM_OK:
+        raise PGMError(st, "invalid arguments")
+    buf = C.create_string_buffer(max(1, n.value))
+    st = lib().pgm_format_matches(ptr, m.size, 1 if inliers_only else 0, buf, n.value, C.byref(n))
+    if st != PGM_OK:
+        raise PGMError(st, "formatting failed")
+    return buf.raw[: n.value].decode()
+
+
+def write_epicflow_matches(path: str, matches: np.ndarray, inliers_only: bool = True) -> int:
+    """Write the matches to a text file for an external interpolator; returns the line count."""
+    text = pgm_format_matches(matches, inliers_only)
+    with open(path, "w") as f:
+        f.write(text)
+    return text.count("\n")
 
 
 def pgm_dump_level(ctx, level: int, dir: int, n: int) -> np.ndarray:

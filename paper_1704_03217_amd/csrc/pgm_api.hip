@@ -1,5 +1,6 @@
 // C ABI of libpgm (declared in include/pgm.h): parameter validation, workspace layout, the
 // level schedule of Sec. III-D and the kernel launches of one pair.
+#include <stdio.h>
 #include <string.h>
 
 #include <deque>
@@ -86,7 +87,8 @@ const char* validate(const pgm_params* p, int w, int h)
     if (p->radius < 1 || p->radius > 16384) return "radius must be within 1..16384";
     if (p->max_disp < 0 || p->max_disp > 65535) return "max_disp must be within 0..65535";
     if (p->sobel_ksize != 3 && p->sobel_ksize != 5) return "sobel_ksize must be 3 or 5";
-    if (p->feature != PGM_FEAT_INT16 && p->feature != PGM_FEAT_F32_DIR) return "unknown feature";
+    if (p->feature != PGM_FEAT_INT16 && p->feature != PGM_FEAT_F32_DIR && p->feature != PGM_FEAT_SIGN)
+        return "unknown feature";
     if (p->color != PGM_RGB && p->color != PGM_GRAY) return "unknown color";
     if (p->fwd_bwd != 0 && p->fwd_bwd != 1) return "fwd_bwd must be 0 or 1";
     if (p->consistency_px < 0 || p->consistency_px > 46340) return "consistency_px must be within 0..46340";
@@ -495,7 +497,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     pa.grad.n = 1;
     pa.with_pyr = Y.L > 1;
     if (pa.with_pyr) pyr_level(pa.pyr, 1, img1, img2, image_stride_bytes, pitch_bytes);
-    PGM_HIP(c, timed(PGM_K_PREP, [&] { return launch_prep(pa, npairs, gray, p->sobel_ksize, Y.f32, s); }));
+    PGM_HIP(c, timed(PGM_K_PREP, [&] { return launch_prep(pa, npairs, gray, p->sobel_ksize, p->feature, s); }));
     GradArgs gl;
     memset(&gl, 0, sizeof gl);
     gl.dst_zs = zs;
@@ -508,7 +510,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         }
         grad_level(gl, l, pw0 + Y.pyr[0][l], pw0 + Y.pyr[1][l], zs, Y.lw[l] * 3);
     }
-    if (gl.n) PGM_HIP(c, timed(PGM_K_GRADIENT, [&] { return launch_gradient(gl, npairs, gray, p->sobel_ksize, Y.f32, s); }));
+    if (gl.n) PGM_HIP(c, timed(PGM_K_GRADIENT, [&] { return launch_gradient(gl, npairs, gray, p->sobel_ksize, p->feature, s); }));
 
     auto geo = [&](int l) {
         Geo g;
@@ -1055,6 +1057,26 @@ void pgm_server_destroy(void* server)
     for (hipStream_t q : S->streams) (void)hipStreamDestroy(q);
     pgm_destroy(S->c);
     delete S;
+}
+
+pgm_status pgm_format_matches(const pgm_match_t* host_matches, int64_t n, int32_t inliers_only, char* host_buf,
+                              uint64_t cap, uint64_t* host_len)
+{
+    if (!host_len || n < 0 || (n > 0 && !host_matches) || (inliers_only != 0 && inliers_only != 1))
+        return PGM_EINVAL;
+    std::string out;
+    char line[64];
+    for (int64_t k = 0; k < n; k++) {
+        const pgm_match_t& m = host_matches[k];
+        if (inliers_only && !(m.flags & PGM_FLAG_INLIER)) continue;
+        const int len = snprintf(line, sizeof line, "%d %d %d %d\n", m.x1, m.y1, m.x2, m.y2);
+        out.append(line, (size_t)len);
+    }
+    *host_len = out.size();
+    if (!host_buf) return PGM_OK;
+    if (out.size() > cap) return PGM_ENOMEM;
+    memcpy(host_buf, out.data(), out.size());
+    return PGM_OK;
 }
 
 static pgm_status dump_prep(pgm_ctx_s* c, int level)

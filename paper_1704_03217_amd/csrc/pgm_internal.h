@@ -186,9 +186,10 @@ struct PrepArgs {
     int with_pyr;
     int rng_blocks, grad_blocks;   // filled in by the launcher
 };
-hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int f32, hipStream_t s);
+// feat: PGM_FEAT_* (0 integer gradients, 1 direction-only float, 2 literal signs)
+hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hipStream_t s);
 hipError_t launch_pyr(PyrArgs a, int npairs, hipStream_t s);
-hipError_t launch_gradient(GradArgs a, int npairs, int gray, int ksize, int f32, hipStream_t s);
+hipError_t launch_gradient(GradArgs a, int npairs, int gray, int ksize, int feat, hipStream_t s);
 hipError_t launch_init(const InitArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_sweep(const SweepArgs& a, int C2, int f32, hipStream_t s);
 hipError_t launch_down(const TransArgs& a, int C2, int f32, hipStream_t s);

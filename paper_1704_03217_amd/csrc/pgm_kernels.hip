@@ -985,9 +985,11 @@ __device__ __forceinline__ void pyr_tile(const PyrArgs& a, int t, int z, uint32_
 constexpr int GR_TW = 64, GR_TH = 8, GR_SU = GR_TW + 4, GR_SV = GR_TH + 4;   // kernel radius <= 2
 constexpr int GR_LDS = GR_SV * GR_SU + GR_SV * GR_TW * 6;                    // dwords
 
-template <int KS, bool GRAY, bool F32>
+// FEAT: 0 integer gradients, 1 direction-only unit vectors (float), 2 literal signs
+template <int KS, bool GRAY, int FEAT>
 __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, int t, int z, uint32_t* lds)
 {
+    constexpr bool F32 = FEAT == 1;
     constexpr int CH = GRAY ? 1 : 3;
     constexpr int C2 = 2 * CH;
     constexpr int K = KS / 2;
@@ -1064,6 +1066,10 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
             uint16_t vals[C2];
 #pragma unroll
             for (int c = 0; c < CH; c++) {
+                if (FEAT == 2) {   // Sec. III-F read element-wise: G./|G| is the sign, 0 stays 0
+                    gx[c] = (gx[c] > 0) - (gx[c] < 0);
+                    gy[c] = (gy[c] > 0) - (gy[c] < 0);
+                }
                 vals[c] = (uint16_t)(gx[c] + (int)BIAS);
                 vals[CH + c] = (uint16_t)(gy[c] + (int)BIAS);
             }
@@ -1151,7 +1157,7 @@ __device__ __forceinline__ void rng_item(const RngArgs& a, long long item)
 
 constexpr int PREP_LDS = GR_LDS > PY_LDS ? GR_LDS : PY_LDS;
 
-template <int KS, bool GRAY, bool F32>
+template <int KS, bool GRAY, int FEAT>
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
 {
     __shared__ uint32_t lds[PREP_LDS];
@@ -1162,7 +1168,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
     }
     b -= a.rng_blocks;
     if (b < a.grad_blocks) {
-        grad_tile<KS, GRAY, F32>(a.grad.lv[0], a.grad.dst_zs, b % a.grad.lv[0].tiles, b / a.grad.lv[0].tiles, lds);
+        grad_tile<KS, GRAY, FEAT>(a.grad.lv[0], a.grad.dst_zs, b % a.grad.lv[0].tiles, b / a.grad.lv[0].tiles, lds);
         return;
     }
     b -= a.grad_blocks;
@@ -1175,13 +1181,13 @@ __global__ __launch_bounds__(256) void k_pyr(PyrArgs a)
     pyr_tile(a, blockIdx.x, blockIdx.y, lds);
 }
 
-template <int KS, bool GRAY, bool F32>
+template <int KS, bool GRAY, int FEAT>
 __global__ __launch_bounds__(256) void k_gradient(GradArgs a)
 {
     __shared__ uint32_t lds[GR_LDS];
     int lv = 0;
     while (lv + 1 < a.n && (int)blockIdx.x >= a.lv[lv + 1].base) lv++;
-    grad_tile<KS, GRAY, F32>(a.lv[lv], a.dst_zs, (int)blockIdx.x - a.lv[lv].base, blockIdx.y, lds);
+    grad_tile<KS, GRAY, FEAT>(a.lv[lv], a.dst_zs, (int)blockIdx.x - a.lv[lv].base, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1214,16 +1220,17 @@ hipError_t launch_pyr(PyrArgs a, int npairs, hipStream_t s)
     return hipGetLastError();
 }
 
-#define PGM_IMG_VARIANTS(M) M(3, false, false) M(3, false, true) M(3, true, false) M(3, true, true) \
-    M(5, false, false) M(5, false, true) M(5, true, false) M(5, true, true)
+#define PGM_IMG_VARIANTS(M)                                                                    \
+    M(3, false, 0) M(3, false, 1) M(3, false, 2) M(3, true, 0) M(3, true, 1) M(3, true, 2)       \
+    M(5, false, 0) M(5, false, 1) M(5, false, 2) M(5, true, 0) M(5, true, 1) M(5, true, 2)
 
-hipError_t launch_gradient(GradArgs a, int npairs, int gray, int ksize, int f32, hipStream_t s)
+hipError_t launch_gradient(GradArgs a, int npairs, int gray, int ksize, int feat, hipStream_t s)
 {
     const int total = plan_grad(a);
     if (total == 0) return hipSuccess;
     dim3 grid(total, 2 * npairs);
 #define PGM_GRAD(KS, GR, F)                                                                       \
-    if (ksize == KS && !!gray == GR && !!f32 == F) {                                               \
+    if (ksize == KS && !!gray == GR && feat == F) {                                                \
         hipLaunchKernelGGL((k_gradient<KS, GR, F>), grid, dim3(256), 0, s, a);                     \
         return hipGetLastError();                                                                  \
     }
@@ -1232,7 +1239,7 @@ hipError_t launch_gradient(GradArgs a, int npairs, int gray, int ksize, int f32,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int f32, hipStream_t s)
+hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hipStream_t s)
 {
     const long long items = 2LL * a.rng.n_top + a.rng.total_items;
     if ((items + 255) / 256 > 0x40000000LL) return hipErrorInvalidValue;
@@ -1243,7 +1250,7 @@ hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int f32, hip
     const long long blocks = (long long)a.rng_blocks + a.grad_blocks + (a.with_pyr ? (long long)a.pyr.tiles * 2 * npairs : 0);
     if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
 #define PGM_PREP(KS, GR, F)                                                                       \
-    if (ksize == KS && !!gray == GR && !!f32 == F) {                                               \
+    if (ksize == KS && !!gray == GR && feat == F) {                                                \
         hipLaunchKernelGGL((k_prep<KS, GR, F>), dim3((unsigned)blocks), dim3(256), 0, s, a);       \
         return hipGetLastError();                                                                  \
     }

@@ -98,7 +98,7 @@ def test_query_workspace_of_config2_is_modest():
 
 @pytest.mark.parametrize("bad", [dict(levels=0), dict(levels=9), dict(seed_stride=0), dict(patch_fwd=0),
                                  dict(patch_bwd=17), dict(iters=[256, 1, 1]), dict(radius=0),
-                                 dict(sobel_ksize=7), dict(feature=2), dict(color=3), dict(fwd_bwd=2),
+                                 dict(sobel_ksize=7), dict(feature=3), dict(color=3), dict(fwd_bwd=2),
                                  dict(consistency_px=-1), dict(init_mode=2), dict(refine_rounds=17),
                                  dict(levels=1, iters=[1], refine_rounds=1), dict(max_disp=-1),
                                  dict(min_region_px=-1), dict(min_region_px=9, region_link_px=0),
@@ -143,3 +143,28 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pgm, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         pgm.lib()
+
+
+def test_format_matches_epicflow_lines(tmp_path):
+    """Host-only formatting of grid matches as "x1 y1 x2 y2" lines, all or inliers only."""
+    rng = np.random.default_rng(3)
+    m = np.zeros(50, pgm.MATCH_DTYPE)
+    for k in ("x1", "y1", "x2", "y2"):
+        m[k] = rng.integers(-5, 2000, 50)
+    m["dist"] = rng.integers(0, 10**6, 50)
+    m["flags"] = rng.integers(0, 8, 50)
+    text_all = pgm.pgm_format_matches(m, inliers_only=False)
+    assert text_all == "".join(f"{a} {b} {c} {d}\n" for a, b, c, d in zip(m["x1"], m["y1"], m["x2"], m["y2"]))
+    inl = m[(m["flags"] & pgm.FLAG_INLIER) != 0]
+    path = tmp_path / "matches.txt"
+    n = pgm.write_epicflow_matches(str(path), m)
+    assert n == len(inl)
+    back = np.loadtxt(path, dtype=np.int64, ndmin=2)
+    assert np.array_equal(back, np.stack([inl["x1"], inl["y1"], inl["x2"], inl["y2"]], 1))
+    assert pgm.pgm_format_matches(m[:0]) == ""
+    L = pgm.lib()
+    small = C.create_string_buffer(4)
+    need = C.c_uint64()
+    assert L.pgm_format_matches(m.ctypes.data, 50, 0, small, 4, C.byref(need)) == pgm.PGM_ENOMEM
+    assert need.value == len(text_all)
+    assert L.pgm_format_matches(None, 5, 0, None, 0, C.byref(need)) == pgm.PGM_EINVAL

@@ -87,6 +87,8 @@ def check_features(m, params, img1, img2, name):
             G = oracle.gradient_image(src, params["sobel_ksize"])
             if f32:
                 G = oracle.direction(G)
+            elif params["feature"] == 2:
+                G = oracle.sign(G)
             got = m.dump_gradient(l, k, 2 * ch, f32)
             a, b = (got.view(np.uint32), G.view(np.uint32)) if f32 else (got, G)
             if not np.array_equal(a, b):
@@ -117,6 +119,9 @@ CASES = {
     "identical": (lambda: (lambda p: synth.Pair(p.img1, p.img1, p.flow, p.valid))(synth.config_pair(1)), base_params(rng_seed=3)),
     # small-region removal (Sec. III-E): the paper's 9 px / 12 px on a dense field, and a
     # stride-3 grid where regions under 9 seeds of equal displacement go
+    # "G./|G|" read element-wise (literal signs, Sec. III-F), colour and gray
+    "sign_feature": (lambda: synth.config_pair(1), base_params(feature=2, rng_seed=18)),
+    "sign_feature_gray_dense": (lambda: synth.rect_pair(22, 48, 64, dmax=6), base_params(feature=2, color=1, seed_stride=1, max_disp=6, rng_seed=19)),
     "regions_dense": (lambda: synth.rect_pair(21, 72, 96, dmax=8), base_params(seed_stride=1, levels=2, iters=[3, 3], max_disp=8, min_region_px=9, region_link_px=12, rng_seed=16)),
     "regions_stride3": (lambda: synth.config_pair(1), base_params(min_region_px=81, region_link_px=1, rng_seed=17)),
 }
