@@ -52,10 +52,67 @@ def parse():
     ap.add_argument("--served-pool", type=int, default=24, help="distinct generated request pairs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a known-size kernel for HBM counter scaling)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU work: turn the counter_collection.csv files of a FETCH_SIZE and a WRITE_SIZE "
+                         "rocprofv3 run of the plain pass (with --copy-calibration) into TRAFFIC_FILE")
+    ap.add_argument("--copy-mib", type=int, default=256, help="size of the calibration copy in those runs")
     return ap.parse_args()
 
 
-def sweep_roofline(pgm, ctx, steps, run, torch):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_hbm_traffic_1024x436.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1704_03217_amd", "csrc", "pgm_kernels.hip")
+
+
+def _source_hash():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def summarize_counters(fetch_csv, write_csv, copy_mib):
+    """HBM bytes per k_sweep launch of the plain pass from two rocprofv3 --pmc runs, each
+    counter scaled by what it reads for the calibration copy of copy_mib MiB."""
+    import csv
+
+    def load(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"].startswith(counter)]
+        return [(r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])) for r in rows]
+
+    out = {}
+    for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = load(path, counter)
+        copies = [v for k, g, v in rows if "copyBuffer" in k]
+        if not copies:
+            raise SystemExit(f"no calibration copy in {path}")
+        scale = (copy_mib << 20) / (max(copies) * 1024.0)     # bytes per counted KiB
+        sweeps = [v for k, g, v in rows if "k_sweep" in k]
+        out[name] = dict(kib_per_launch=sum(sweeps) / len(sweeps), scale=scale, launches=len(sweeps),
+                         bytes_per_launch=scale * 1024.0 * sum(sweeps) / len(sweeps))
+    res = {"kernel": "k_sweep", "workload": "plain pass, one 1024x436 pair per step (bench.py --batch 0)",
+           "fetch_bytes_per_launch": round(out["fetch"]["bytes_per_launch"]),
+           "write_bytes_per_launch": round(out["write"]["bytes_per_launch"]),
+           "fetch_scale": out["fetch"]["scale"], "write_scale": out["write"]["scale"],
+           "launches": out["fetch"]["launches"], "kernel_source_sha256": _source_hash()}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
+def measured_traffic():
+    """HBM bytes per k_sweep launch from the committed counter summary, or None when it is
+    missing or was taken on another version of the kernels."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        if t.get("kernel_source_sha256") != _source_hash():
+            return None
+        return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def sweep_roofline(pgm, ctx, steps, run, torch, traffic=None):
     """Run `steps` steps with per-launch HIP events on; return (roofline of k_sweep, per-kind
     breakdown). achieved = evaluations x 192 / launches / average launch duration."""
     pgm.pgm_profile(ctx, True)
@@ -79,7 +136,7 @@ def sweep_roofline(pgm, ctx, steps, run, torch):
         ops_per_launch = sw["evals"] * float(OPS_PER_EVAL) / n_launch
         achieved = ops_per_launch / (sw["avg_launch_us"] * 1e-6) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic,
                 "kernel": "k_sweep (propagation + random search half-sweep)",
                 "op": "v_sad_u16 (two 16-bit absolute differences), 192 per 8x8x6 patch distance",
                 "avg_launch_us": round(sw["avg_launch_us"], 3),
@@ -207,6 +264,9 @@ def run_served(pgm, torch, dev, args, pre):
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, args.copy_mib)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the pairs are independent and this build runs on a single "
               "MI355X; run with --gpus 1", file=sys.stderr)
@@ -283,7 +343,7 @@ def main():
     if not args.no_profile_pass:
         print(f"[bench] profiled pass of {args.steps} steps (HIP events around every launch)", file=sys.stderr,
               flush=True)
-        roofline, kernels = sweep_roofline(pgm, m.ctx, args.steps, step, torch)
+        roofline, kernels = sweep_roofline(pgm, m.ctx, args.steps, step, torch, measured_traffic())
 
     batched = None
     if args.batch > 0:
