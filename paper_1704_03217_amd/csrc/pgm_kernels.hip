@@ -2,12 +2,12 @@
 // (Y. Li, "Pyramidal Gradient Matching for Optical Flow Estimation", arXiv:1704.03217).
 //
 // Matching kernels assign one group of LPS lanes (8 for patches up to 8 pixels, 16 up to 16)
-// to each seed of the grid: lane r holds row r of the seed's patch of the first gradient
-// image in registers for the whole launch, reads row r of a candidate patch of the second
-// image, and the patch distance is the DPP sum over the group. Candidates of one seed are
-// evaluated one after another in the order of the paper's candidate sets, so every seed's
-// decision sequence is exactly the sequential one; seeds of one colour of the red-black
-// checkerboard are independent and run in parallel.
+// to each seed of the grid: lane c holds pixel column c of every row of the seed's patch of
+// the first gradient image in registers, reads the same column of candidate patches of the
+// second image (buffer loads from HBM, plain loads from LDS), and the patch distance is the
+// DPP sum over the group. Candidates are priced two at a time, but every seed's decisions
+// replay the paper's candidate order one at a time, so they are exactly the sequential ones;
+// seeds of one colour of the red-black checkerboard are independent and run in parallel.
 #include "pgm_internal.h"
 
 namespace pgm {
@@ -137,11 +137,46 @@ struct IntRow {
                 for (int w = 0; w < W3; w++) acc = __builtin_amdgcn_sad_u16(a[y][w], B.a[y][w], acc);
         return acc;
     }
+    // The same rows of a padded gradient image in HBM through buffer loads: one VGPR holds
+    // the lane's byte offset, the row offsets are scalar (SGPR), and a read outside the
+    // image's bytes returns zero instead of touching other memory. (x, y): the lane's pixel
+    // of the first row, image coordinates >= -PAD.
+    static constexpr bool CAN_BUF = W3 == 1 || W3 == 3;
+    __device__ __forceinline__ void load_buf(const void* G, const Geo& g, int x, int y, int P)
+    {
+        constexpr uint32_t PXB = W3 * 4;
+        const uint32_t pitch_b = (uint32_t)g.pw * PXB;
+        const char* base = (const char*)G - ((size_t)PAD * g.pw + PAD) * PXB;
+        const uint32_t bytes = pitch_b * (uint32_t)(g.h + 2 * PAD);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000);
+        const uint32_t vo = ((uint32_t)(y + PAD) * (uint32_t)g.pw + (uint32_t)(x + PAD)) * PXB;
+#pragma unroll
+        for (int r = 0; r < PMAX; r++) {
+            const uint32_t so = (uint32_t)((FIXED || r < P) ? r : P - 1) * pitch_b;
+            if constexpr (W3 == 3) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, vo, so, 0);
+                a[r][0] = v[0];
+                a[r][1] = v[1];
+                a[r][2] = v[2];
+            } else if constexpr (W3 == 1) {
+                a[r][0] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0);
+            }
+        }
+    }
     static __device__ __forceinline__ const uint32_t* at(const void* G, const Geo& g, int x, int y)
     {
         return (const uint32_t*)G + ((ptrdiff_t)y * g.pw + x) * W3;
     }
     static __device__ __forceinline__ ptrdiff_t pitch(const Geo& g) { return (ptrdiff_t)g.pw * W3; }
+    // the patch whose top-left pixel is (tlx, tly): lane r reads column r (lanes past the
+    // patch side read its last column and add nothing)
+    template <bool BUF>
+    __device__ __forceinline__ void fetch(const void* G, const Geo& g, int tlx, int tly, int P, int r)
+    {
+        const int x = tlx + (r < P ? r : P - 1);
+        if constexpr (BUF && CAN_BUF) load_buf(G, g, x, tly, P);
+        else load(at(G, g, x, tly), pitch(g), P);
+    }
     template <int LPS>
     static __device__ __forceinline__ uint32_t finish(uint32_t partial) { return group_sum<LPS>(partial); }
 };
@@ -152,6 +187,7 @@ struct IntRow {
 template <int C2, int PMAX, bool FIXED>
 struct F32Row {
     using Acc = double;
+    static constexpr bool CAN_BUF = false;
     float a[PMAX][C2];
 
     __device__ __forceinline__ void load(const float* base, ptrdiff_t pitch, int P)
@@ -178,6 +214,11 @@ struct F32Row {
         return (const float*)G + ((ptrdiff_t)y * g.pw + x) * C2;
     }
     static __device__ __forceinline__ ptrdiff_t pitch(const Geo& g) { return (ptrdiff_t)g.pw * C2; }
+    template <bool BUF>
+    __device__ __forceinline__ void fetch(const void* G, const Geo& g, int tlx, int tly, int P, int r)
+    {
+        load(at(G, g, tlx + (r < P ? r : P - 1), tly), pitch(g), P);
+    }
     template <int LPS>
     static __device__ __forceinline__ uint32_t finish(double partial)
     {
@@ -193,14 +234,16 @@ using RowT = typename std::conditional<F32, F32Row<C2, PMAX, FIXED>, IntRow<C2, 
 // past the patch side read a valid column and add nothing. All rows of the candidate are
 // requested before the first one is used (the scheduling barrier keeps the compiler from
 // trading the loads in flight for registers), so a candidate costs one memory round trip.
-template <class Row, int LPS>
+// rows of the patch whose first-row pixel for this lane is (x, y): buffer loads from HBM
+// (BUF) or plain loads (LDS images, float features)
+
+template <class Row, int LPS, bool BUF>
 __device__ __forceinline__ uint32_t patch_cost(const Row& A, const void* Gb, const Geo& g, int P,
                                                int r, int qx, int qy)
 {
     const int half = P >> 1;
-    const int rc = r < P ? r : P - 1;
     Row B;
-    B.load(Row::at(Gb, g, qx - half + rc, qy - half), Row::pitch(g), P);
+    B.template fetch<BUF>(Gb, g, qx - half, qy - half, P, r);
     __builtin_amdgcn_sched_barrier(0);
     typename Row::Acc part = A.sad(B, P);
     if (r >= P) part = typename Row::Acc(0);
@@ -208,15 +251,14 @@ __device__ __forceinline__ uint32_t patch_cost(const Row& A, const void* Gb, con
 }
 
 // Two patch distances with the reads of both candidates in flight together.
-template <class Row, int LPS>
+template <class Row, int LPS, bool BUF>
 __device__ __forceinline__ void patch_cost2(const Row& A, const void* Gb, const Geo& g, int P, int r, int q0x,
                                             int q0y, int q1x, int q1y, uint32_t& e0, uint32_t& e1)
 {
     const int half = P >> 1;
-    const int rc = r < P ? r : P - 1;
     Row B0, B1;
-    B0.load(Row::at(Gb, g, q0x - half + rc, q0y - half), Row::pitch(g), P);
-    B1.load(Row::at(Gb, g, q1x - half + rc, q1y - half), Row::pitch(g), P);
+    B0.template fetch<BUF>(Gb, g, q0x - half, q0y - half, P, r);
+    B1.template fetch<BUF>(Gb, g, q1x - half, q1y - half, P, r);
     __builtin_amdgcn_sched_barrier(0);
     typename Row::Acc p0 = A.sad(B0, P);
     typename Row::Acc p1 = A.sad(B1, P);
@@ -228,12 +270,11 @@ __device__ __forceinline__ void patch_cost2(const Row& A, const void* Gb, const 
     e1 = Row::template finish<LPS>(p1);
 }
 
-template <class Row>
+template <bool BUF, class Row>
 __device__ __forceinline__ void load_own(Row& A, const void* Ga, const Geo& g, int P, int r, int px, int py)
 {
     const int half = P >> 1;
-    const int rc = r < P ? r : P - 1;
-    A.load(Row::at(Ga, g, px - half + rc, py - half), Row::pitch(g), P);
+    A.template fetch<BUF>(Ga, g, px - half, py - half, P, r);
 }
 
 // Logical block of a 1-D launch over nbx x ndir x npairs work-groups. Consecutive work-group
@@ -302,7 +343,7 @@ __device__ __forceinline__ void count_evals(uint32_t* cnt, int slot, uint32_t ne
 // One seed's half-sweep step (Step 1): propagation (Eq. 4) then limited random search
 // (Eq. 5) for seed (i, j) of field D at iteration t; returns the distance evaluations made.
 // The group's lanes all call it for the same seed; lane 0 writes the result.
-template <class Row, int LPS>
+template <class Row, int LPS, bool BUF>
 __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, int i, int j, int t, int nI, int r)
 {
     uint32_t nev = 0;
@@ -310,7 +351,7 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
     const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
     const int P = D.P;
     Row A;
-    load_own(A, D.Ga, g, P, r, px, py);
+    load_own<BUF>(A, D.Ga, g, P, r, px, py);
     const uint32_t cur0 = D.f.disp[s];
     const uint32_t cd0 = D.f.dist[s];
     const bool init0 = cur0 != UNINIT;
@@ -351,7 +392,7 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
     if (need0 || need1) {
         const uint32_t qa = need0 ? c[0] : c[1], qb = need1 ? c[1] : c[0];
         uint32_t ea, eb;
-        patch_cost2<Row, LPS>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb), ea, eb);
+        patch_cost2<Row, LPS, BUF>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb), ea, eb);
         if (need0) e[0] = ea;
         if (need1) e[1] = eb;
     }
@@ -384,7 +425,7 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
             if (n0 || n1) {
                 const uint32_t qa = n0 ? r0 : r1, qb = n1 ? r1 : r0;
                 uint32_t ea, eb;
-                patch_cost2<Row, LPS>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb),
+                patch_cost2<Row, LPS, BUF>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb),
                                       ea, eb);
                 if (n0) f0 = ea;
                 if (n1) f1 = eb;
@@ -407,6 +448,7 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
     return nev;
 }
 
+// one half-sweep (Step 1, one colour of one iteration) of every seed of the launch
 template <int C2, int PMAX, bool FIXED, bool F32>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 {
@@ -424,7 +466,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     const int j = gid / hx;
     const int i = 2 * (gid - j * hx) + ((a.colour + j) & 1);
     uint32_t nev = 0;
-    if (j < g.ny && i < g.nx) nev = sweep_seed<Row, LPS>(D, g, i, j, a.t, a.nI, r);
+    if (j < g.ny && i < g.nx) nev = sweep_seed<Row, LPS, true>(D, g, i, j, a.t, a.nI, r);
     count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, r == 0);
 }
 
@@ -452,12 +494,12 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
         const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
         const int P = D.P;
         Row A;
-        load_own(A, D.Ga, g, P, r, px, py);
+        load_own<true>(A, D.Ga, g, P, r, px, py);
         uint32_t best = UNINIT, bd = NO_DIST;
         if (!a.exhaustive) {
             const short2 o = D.rnd0[s];
             best = target(px, py, o.x, o.y, g);
-            bd = patch_cost<Row, LPS>(A, D.Gb, g, P, r, px + d_x(best), py + d_y(best));
+            bd = patch_cost<Row, LPS, true>(A, D.Gb, g, P, r, px + d_x(best), py + d_y(best));
             nev++;
         } else {
             // the window clipped to the image, in the same (dy outer, dx inner) order
@@ -465,7 +507,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
             const int x0 = max(-a.R, -px), x1 = min(a.R, g.w - 1 - px);
             for (int dy = y0; dy <= y1; dy++) {
                 for (int dx = x0; dx <= x1; dx++) {
-                    const uint32_t e = patch_cost<Row, LPS>(A, D.Gb, g, P, r, px + dx, py + dy);
+                    const uint32_t e = patch_cost<Row, LPS, true>(A, D.Gb, g, P, r, px + dx, py + dy);
                     nev++;
                     if (best == UNINIT || e < bd) { best = pack_d(dx, dy); bd = e; }
                 }
@@ -506,14 +548,14 @@ __global__ __launch_bounds__(256) void k_down(TransArgs a)
         const int ps = grid_near(py >> 1, a.gs.ny, a.gs) * a.gs.nx + grid_near(px >> 1, a.gs.nx, a.gs);
         // the parent's state and this seed's patch are read together
         Row A;
-        load_own(A, D.Ga, g, D.P, r, px, py);
+        load_own<true>(A, D.Ga, g, D.P, r, px, py);
         const uint8_t pf = S.flags[ps];
         const uint32_t pd = S.disp[ps];
         const bool par_inl = (pf & ST_INL) != 0;
         uint32_t disp = UNINIT, dist = NO_DIST;
         if (par_inl) {
             disp = target(px, py, 2 * d_x(pd), 2 * d_y(pd), g);
-            dist = patch_cost<Row, LPS>(A, D.Gb, g, D.P, r, px + d_x(disp), py + d_y(disp));
+            dist = patch_cost<Row, LPS, true>(A, D.Gb, g, D.P, r, px + d_x(disp), py + d_y(disp));
             nev++;
         }
         if (r == 0) {
@@ -574,8 +616,8 @@ __global__ __launch_bounds__(256) void k_up(TransArgs a)
         if (cnt > 0) {
             disp = target(px, py, div_round(sx, 2 * cnt), div_round(sy, 2 * cnt), g);
             Row A;
-            load_own(A, D.Ga, g, D.P, r, px, py);
-            dist = patch_cost<Row, LPS>(A, D.Gb, g, D.P, r, px + d_x(disp), py + d_y(disp));
+            load_own<true>(A, D.Ga, g, D.P, r, px, py);
+            dist = patch_cost<Row, LPS, true>(A, D.Gb, g, D.P, r, px + d_x(disp), py + d_y(disp));
             nev++;
         }
         if (r == 0) {
@@ -686,7 +728,7 @@ __global__ __launch_bounds__((LevelShape<PMAX, F32>::threads)) void k_level(Leve
             for (int q = threadIdx.x / LPS; q < per; q += NG) {
                 const int j = q / hx;
                 const int i = 2 * (q - j * hx) + ((colour + j) & 1);
-                if (i < g.nx) nev += sweep_seed<Row, LPS>(L, g, i, j, t, a.nI, r);
+                if (i < g.nx) nev += sweep_seed<Row, LPS, false>(L, g, i, j, t, a.nI, r);
             }
             __syncthreads();
         }
