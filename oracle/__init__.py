@@ -34,6 +34,7 @@ class Params(C.Structure):
         ("feature", C.c_int32), ("color", C.c_int32), ("fwd_bwd", C.c_int32),
         ("consistency_px", C.c_int32), ("init_mode", C.c_int32), ("refine_rounds", C.c_int32),
         ("min_region_px", C.c_int32), ("region_link_px", C.c_int32),
+        ("space_fwd", C.c_int32 * MAX_LEVELS), ("space_bwd", C.c_int32 * MAX_LEVELS),
         ("rng_seed", C.c_uint64),
     ]
 
@@ -84,6 +85,8 @@ def lib():
         L.pgmo_grid_nearest.argtypes = [C.c_int, C.c_int, C.c_int]
         L.pgmo_geometry.argtypes = [C.POINTER(Params), C.c_int, C.c_int, P, P, P, P]
         L.pgmo_top_radius.argtypes = [C.POINTER(Params), C.c_int, C.c_int]
+        L.pgmo_convert.argtypes = [P, C.c_int, C.c_int, P]
+        L.pgmo_convert.restype = None
         L.pgmo_sign.argtypes = [P, C.c_int]
         L.pgmo_sign.restype = None
         L.pgmo_remove_small_regions.argtypes = [P, P, P] + [C.c_int] * 5
@@ -101,15 +104,26 @@ def _p(a: np.ndarray):
 def make_params(d: dict) -> Params:
     p = Params()
     for k, v in d.items():
-        if k == "iters":
+        if k in ("iters", "space_fwd", "space_bwd"):
             arr = (list(v) + [0] * MAX_LEVELS)[:MAX_LEVELS]
-            p.iters = (C.c_int32 * MAX_LEVELS)(*arr)
+            setattr(p, k, (C.c_int32 * MAX_LEVELS)(*arr))
         else:
             setattr(p, k, v)
     return p
 
 
 # ---- building blocks ----
+
+SPACE_RGB, SPACE_YCRCB, SPACE_LAB = 0, 1, 2
+
+
+def convert(img: np.ndarray, space: int) -> np.ndarray:
+    """Colour conversion of an (h, w, 3) uint8 RGB image (Table II's spaces)."""
+    img = np.ascontiguousarray(img, np.uint8)
+    out = np.empty_like(img)
+    lib().pgmo_convert(_p(img), img.size // 3, space, _p(out))
+    return out
+
 
 def sign(G: np.ndarray) -> np.ndarray:
     """Literal "G./|G|" of Sec. III-F: the sign of every gradient component (int16)."""

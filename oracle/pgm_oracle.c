@@ -149,6 +149,76 @@ int64_t pgmo_dist_i16(const int16_t* Ga, const int16_t* Gb, int w, int h, int C2
     return s;
 }
 
+/* Colour spaces of the two gradient pyramids (Sec. III-E, Table II). READING, YCrCb: integer
+ * BT.601 full range, Y = (77 R + 150 G + 29 B + 128) >> 8, Cr = 128 + floor((R - Y) 183 / 256
+ * + 1/2), Cb = 128 + floor((B - Y) 144 / 256 + 1/2), clamped to [0, 255], stored (Y, Cr, Cb).
+ * READING, CIELab: sRGB (IEC 61966-2-1 transfer curve) to linear, the sRGB / D65 matrix to
+ * XYZ, Lab with the D65 white (0.95047, 1, 1.08883), stored as 8-bit (L* 255/100, a* + 128,
+ * b* + 128) rounded half up and clamped. The powers are computed with plain IEEE double
+ * operations only: u^2.4 = u^2 (u^2)^(1/5) and t^(1/3) by 40 Newton steps from 1 each, so the
+ * result is a fixed function of the input bits. */
+static double root_n(double a, int n)
+{
+    double y = 1.0;
+    for (int k = 0; k < 40; k++) {
+        double p = y;
+        for (int m = 2; m < n; m++) p = p * y;        /* y^(n-1) */
+        y = y - (p * y - a) / ((double)n * p);
+    }
+    return y;
+}
+
+static double srgb_linear(int c)
+{
+    double v = (double)c / 255.0;
+    if (v <= 0.04045) return v / 12.92;
+    double u = (v + 0.055) / 1.055;
+    double u2 = u * u;
+    return u2 * root_n(u2, 5);
+}
+
+static double lab_f(double t)
+{
+    const double e = (6.0 / 29.0) * (6.0 / 29.0) * (6.0 / 29.0);
+    if (t > e) return root_n(t, 3);
+    return t / (3.0 * (6.0 / 29.0) * (6.0 / 29.0)) + 4.0 / 29.0;
+}
+
+static uint8_t to_u8(double x)
+{
+    double r = floor(x + 0.5);
+    return (uint8_t)(r < 0.0 ? 0.0 : (r > 255.0 ? 255.0 : r));
+}
+
+void pgmo_convert(const uint8_t* rgb, int npx, int space, uint8_t* out)
+{
+    double lin[256];
+    if (space == PGMO_SPACE_LAB)
+        for (int c = 0; c < 256; c++) lin[c] = srgb_linear(c);
+    for (int k = 0; k < npx; k++) {
+        const int R = rgb[3 * k], G = rgb[3 * k + 1], B = rgb[3 * k + 2];
+        uint8_t* o = out + 3 * k;
+        if (space == PGMO_SPACE_YCRCB) {
+            const int Y = (77 * R + 150 * G + 29 * B + 128) >> 8;
+            const int cr = ((R - Y) * 183 + 32768 + 128), cb = ((B - Y) * 144 + 32768 + 128);
+            o[0] = (uint8_t)Y;
+            o[1] = (uint8_t)(cr < 0 ? 0 : (cr >> 8 > 255 ? 255 : cr >> 8));
+            o[2] = (uint8_t)(cb < 0 ? 0 : (cb >> 8 > 255 ? 255 : cb >> 8));
+        } else if (space == PGMO_SPACE_LAB) {
+            const double r = lin[R], g = lin[G], b = lin[B];
+            const double X = 0.4124564 * r + 0.3575761 * g + 0.1804375 * b;
+            const double Yv = 0.2126729 * r + 0.7151522 * g + 0.0721750 * b;
+            const double Z = 0.0193339 * r + 0.1191920 * g + 0.9503041 * b;
+            const double fx = lab_f(X / 0.95047), fy = lab_f(Yv), fz = lab_f(Z / 1.08883);
+            o[0] = to_u8((116.0 * fy - 16.0) * 2.55);
+            o[1] = to_u8(500.0 * (fx - fy) + 128.0);
+            o[2] = to_u8(200.0 * (fy - fz) + 128.0);
+        } else {
+            o[0] = (uint8_t)R; o[1] = (uint8_t)G; o[2] = (uint8_t)B;
+        }
+    }
+}
+
 /* Sec. III-F, "G./|G|" read literally: the element-wise division of G by |G| leaves the
  * sign of every gradient component; a zero component stays zero (0/0 taken as 0). */
 void pgmo_sign(int16_t* G, int n)
@@ -656,6 +726,10 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
     if (w > 16384 || h > 16384) return -1;
     if (p->refine_rounds > 0 && p->levels < 2) return -1;
     if (p->min_region_px < 0 || (p->min_region_px > 0 && p->region_link_px < 1)) return -1;
+    for (int l = 0; l < p->levels; l++) {
+        if (p->space_fwd[l] < 0 || p->space_fwd[l] > 2 || p->space_bwd[l] < 0 || p->space_bwd[l] > 2) return -1;
+        if (p->color == PGMO_GRAY && (p->space_fwd[l] || p->space_bwd[l])) return -1;
+    }
     if (pitch < 3 * w) return -1;
     for (int l = 0; l < p->levels; l++) if (p->iters[l] < 0 || p->iters[l] > 255) return -1;
     int L = p->levels;
@@ -668,10 +742,11 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
     run.key[1] = (uint32_t)(p->rng_seed >> 32);
     run.evals = 0;
 
-    /* image pyramids {I^l} of both images, then gradient pyramids {G^l} (Sec. III-D) */
+    /* image pyramids {I^l} of both images (RGB), then the gradient pyramids {G^l} (Sec.
+     * III-D): one per direction, each level in that direction's colour space (Table II) */
     uint8_t* pyr[2][PGMO_MAX_LEVELS];
-    int16_t* Gi[2][PGMO_MAX_LEVELS];
-    float* Gf[2][PGMO_MAX_LEVELS];
+    int16_t* Gi[2][2][PGMO_MAX_LEVELS];   /* [direction][image][level] */
+    float* Gf[2][2][PGMO_MAX_LEVELS];
     for (int im = 0; im < 2; im++) {
         const uint8_t* src = im == 0 ? img1 : img2;
         for (int l = 0; l < L; l++) {
@@ -681,20 +756,26 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
                 for (int y = 0; y < h; y++) memcpy(pyr[im][0] + (size_t)y * w * 3, src + (size_t)y * pitch, (size_t)w * 3);
             else
                 pgmo_pyr_down(pyr[im][l - 1], lw[l - 1], lh[l - 1], lw[l - 1] * 3, 3, pyr[im][l]);
-            Gi[im][l] = malloc(npx * C2 * sizeof(int16_t));
-            if (ch == 3) {
-                pgmo_gradient_image(pyr[im][l], lw[l], lh[l], lw[l] * 3, 3, p->sobel_ksize, Gi[im][l]);
-            } else {
-                uint8_t* gy = malloc(npx);
-                pgmo_gray(pyr[im][l], lw[l], lh[l], lw[l] * 3, gy);
-                pgmo_gradient_image(gy, lw[l], lh[l], lw[l], 1, p->sobel_ksize, Gi[im][l]);
-                free(gy);
-            }
-            Gf[im][l] = NULL;
-            if (p->feature == PGMO_FEAT_SIGN) pgmo_sign(Gi[im][l], (int)(npx * C2));
-            if (p->feature == PGMO_FEAT_F32_DIR) {
-                Gf[im][l] = malloc(npx * C2 * sizeof(float));
-                pgmo_direction(Gi[im][l], (int)npx, ch, Gf[im][l]);
+            for (int d = 0; d < 2; d++) {
+                const int space = d == 0 ? p->space_fwd[l] : p->space_bwd[l];
+                Gi[d][im][l] = malloc(npx * C2 * sizeof(int16_t));
+                if (ch == 3) {
+                    uint8_t* cv = malloc(npx * 3);
+                    pgmo_convert(pyr[im][l], (int)npx, space, cv);
+                    pgmo_gradient_image(cv, lw[l], lh[l], lw[l] * 3, 3, p->sobel_ksize, Gi[d][im][l]);
+                    free(cv);
+                } else {
+                    uint8_t* gy = malloc(npx);
+                    pgmo_gray(pyr[im][l], lw[l], lh[l], lw[l] * 3, gy);
+                    pgmo_gradient_image(gy, lw[l], lh[l], lw[l], 1, p->sobel_ksize, Gi[d][im][l]);
+                    free(gy);
+                }
+                Gf[d][im][l] = NULL;
+                if (p->feature == PGMO_FEAT_SIGN) pgmo_sign(Gi[d][im][l], (int)(npx * C2));
+                if (p->feature == PGMO_FEAT_F32_DIR) {
+                    Gf[d][im][l] = malloc(npx * C2 * sizeof(float));
+                    pgmo_direction(Gi[d][im][l], (int)npx, ch, Gf[d][im][l]);
+                }
             }
         }
     }
@@ -707,8 +788,8 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
             f->w = lw[l]; f->h = lh[l]; f->nx = lnx[l]; f->ny = lny[l]; f->n = lnx[l] * lny[l];
             f->stride = p->seed_stride; f->C2 = C2; f->feature = p->feature;
             f->P = d == 0 ? p->patch_fwd : p->patch_bwd;
-            f->Gi_self = Gi[d][l]; f->Gi_other = Gi[1 - d][l];
-            f->Gf_self = Gf[d][l]; f->Gf_other = Gf[1 - d][l];
+            f->Gi_self = Gi[d][d][l]; f->Gi_other = Gi[d][1 - d][l];
+            f->Gf_self = Gf[d][d][l]; f->Gf_other = Gf[d][1 - d][l];
             f->dx = calloc((size_t)f->n, sizeof(int32_t));
             f->dy = calloc((size_t)f->n, sizeof(int32_t));
             f->dist = calloc((size_t)f->n, sizeof(double));
@@ -800,6 +881,9 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
             free(f->dx); free(f->dy); free(f->dist); free(f->init); free(f->rec); free(f->inl);
         }
     for (int im = 0; im < 2; im++)
-        for (int l = 0; l < L; l++) { free(pyr[im][l]); free(Gi[im][l]); free(Gf[im][l]); }
+        for (int l = 0; l < L; l++) {
+            free(pyr[im][l]);
+            for (int d = 0; d < 2; d++) { free(Gi[d][im][l]); free(Gf[d][im][l]); }
+        }
     return 0;
 }

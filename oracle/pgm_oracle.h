@@ -28,6 +28,7 @@ extern "C" {
 
 enum { PGMO_FEAT_INT16 = 0, PGMO_FEAT_F32_DIR = 1, PGMO_FEAT_SIGN = 2 };
 enum { PGMO_RGB = 0, PGMO_GRAY = 1 };
+enum { PGMO_SPACE_RGB = 0, PGMO_SPACE_YCRCB = 1, PGMO_SPACE_LAB = 2 };
 enum { PGMO_INIT_RANDOM = 0, PGMO_INIT_EXHAUSTIVE = 1 };
 enum { PGMO_SYNC = 0, PGMO_SCAN = 1 };
 
@@ -52,6 +53,8 @@ typedef struct {
     int32_t refine_rounds;             /* N of Sec. III-D (refinement between m and m-1)     */
     int32_t min_region_px;             /* small-region removal (Sec. III-E): 0 = off         */
     int32_t region_link_px;            /* neighbours link when |d_a - d_b| < this            */
+    int32_t space_fwd[PGMO_MAX_LEVELS]; /* colour space of the forward / backward gradient   */
+    int32_t space_bwd[PGMO_MAX_LEVELS]; /* pyramid per level (Table II), PGMO_SPACE_*        */
     uint64_t rng_seed;                 /* key of the counter-based generator                 */
 } pgmo_params;
 
@@ -63,6 +66,8 @@ typedef struct { int32_t x1, y1, x2, y2, dist; uint32_t flags; } pgmo_match_t;
 int pgmo_reflect101(int i, int n);
 /* one pyramid step: 5x5 binomial, decimation by 2; dst is ceil(w/2) x ceil(h/2), packed */
 void pgmo_pyr_down(const uint8_t* src, int w, int h, int pitch, int ch, uint8_t* dst);
+/* colour conversion of npx packed RGB pixels into PGMO_SPACE_* (3 uint8 channels) */
+void pgmo_convert(const uint8_t* rgb, int npx, int space, uint8_t* out);
 /* integer luma Y = (77 R + 150 G + 29 B + 128) >> 8, packed w x h */
 void pgmo_gray(const uint8_t* rgb, int w, int h, int pitch, uint8_t* y);
 /* gradient image of Eq. 1-2: G is w*h*2*ch int16 */

@@ -686,3 +686,66 @@ def test_sign_feature_recovers_translation(oracle_lib, dx, dy):
     assert len(fin) > 100
     ok = sum((st[s, 0], st[s, 1], st[s, 2]) == (dx, dy, 0) for s in fin)
     assert ok >= 0.98 * len(fin)     # sign patches can tie; almost every seed is exact
+
+
+# ---- colour spaces of the two gradient pyramids (Sec. III-E, Table II) ----
+
+def _all_colours(n, seed):
+    rng = np.random.default_rng(seed)
+    c = rng.integers(0, 256, (n, 1, 3)).astype(np.uint8)
+    extremes = np.array([[0, 0, 0], [255, 255, 255], [255, 0, 0], [0, 255, 0], [0, 0, 255],
+                         [255, 255, 0], [0, 255, 255], [255, 0, 255]], np.uint8)[:, None, :]
+    return np.concatenate([extremes, c])
+
+
+def test_ycrcb_close_to_bt601_and_exact_on_greys(oracle_lib):
+    c = _all_colours(200000, 1)
+    out = oracle.convert(c, oracle.SPACE_YCRCB).astype(float)
+    R, G, B = (c[..., k].astype(float) for k in range(3))
+    Y = 0.299 * R + 0.587 * G + 0.114 * B
+    ref = np.stack([Y, 128 + 0.713 * (R - Y), 128 + 0.564 * (B - Y)], -1).clip(0, 255)
+    assert np.abs(out - ref).max() <= 2.0          # the integer approximation's error bound
+    g = np.repeat(np.arange(256, dtype=np.uint8)[:, None, None], 3, axis=2)
+    og = oracle.convert(g, oracle.SPACE_YCRCB)
+    assert np.array_equal(og[..., 0, 0], np.arange(256)) and (og[..., 1:] == 128).all()
+
+
+def test_lab_matches_the_standard_formula(oracle_lib):
+    """The fixed-iteration powers agree with numpy's power / cbrt after rounding to 8 bits;
+    white, black and greys land on their closed forms."""
+    c = _all_colours(200000, 2)
+    out = oracle.convert(c, oracle.SPACE_LAB).astype(int)
+    v = c.astype(float) / 255.0
+    lin = np.where(v <= 0.04045, v / 12.92, ((v + 0.055) / 1.055) ** 2.4)
+    M = np.array([[0.4124564, 0.3575761, 0.1804375], [0.2126729, 0.7151522, 0.0721750],
+                  [0.0193339, 0.1191920, 0.9503041]])
+    XYZ = lin @ M.T / np.array([0.95047, 1.0, 1.08883])
+    e = (6 / 29) ** 3
+    f = np.where(XYZ > e, np.cbrt(XYZ), XYZ / (3 * (6 / 29) ** 2) + 4 / 29)
+    L = 116 * f[..., 1] - 16
+    ref = np.stack([L * 2.55, 500 * (f[..., 0] - f[..., 1]) + 128, 200 * (f[..., 1] - f[..., 2]) + 128], -1)
+    ref = np.clip(np.floor(ref + 0.5), 0, 255).astype(int)
+    diff = np.abs(out - ref)
+    assert diff.max() <= 1 and (diff == 0).mean() > 0.99999
+    assert oracle.convert(np.array([[[255, 255, 255]]], np.uint8), oracle.SPACE_LAB).tolist() == [[[255, 128, 128]]]
+    assert oracle.convert(np.array([[[0, 0, 0]]], np.uint8), oracle.SPACE_LAB).tolist() == [[[0, 128, 128]]]
+    g = np.repeat(np.arange(256, dtype=np.uint8)[:, None, None], 3, axis=2)
+    og = oracle.convert(g, oracle.SPACE_LAB).astype(int)
+    assert (np.abs(og[..., 1:] - 128) <= 1).all() and (np.diff(og[:, 0, 0]) >= 0).all()
+
+
+def test_colour_spaces_in_the_pipeline(oracle_lib):
+    """Table II's spaces change the features of each direction: identical pairs still give
+    zero flow, and with every level in RGB the result equals the plain run."""
+    pr = synth.config_pair(1, 0)
+    p0 = base_params(rng_seed=61)
+    paper = dict(p0, space_fwd=[0, 2, 1], space_bwd=[2, 1, 0])
+    plain = oracle.match(p0, pr.img1, pr.img2, trace=False)
+    same = oracle.match(dict(p0, space_fwd=[0, 0, 0], space_bwd=[0, 0, 0]), pr.img1, pr.img2, trace=False)
+    assert np.array_equal(plain["fwd"], same["fwd"]) and np.array_equal(plain["bwd"], same["bwd"])
+    r = oracle.match(paper, pr.img1, pr.img1, trace=False)
+    init = (r["fwd"]["flags"] & 1) != 0
+    assert np.all(r["fwd"]["x2"][init] == r["fwd"]["x1"][init])
+    assert np.all(r["fwd"]["dist"][init] == 0)
+    d = oracle.match(paper, pr.img1, pr.img2, trace=False)
+    assert not np.array_equal(d["bwd"], plain["bwd"])      # the backward field sees other features
