@@ -155,12 +155,12 @@ int64_t pgmo_dist_i16(const int16_t* Ga, const int16_t* Gb, int w, int h, int C2
  * READING, CIELab: sRGB (IEC 61966-2-1 transfer curve) to linear, the sRGB / D65 matrix to
  * XYZ, Lab with the D65 white (0.95047, 1, 1.08883), stored as 8-bit (L* 255/100, a* + 128,
  * b* + 128) rounded half up and clamped. The powers are computed with plain IEEE double
- * operations only: u^2.4 = u^2 (u^2)^(1/5) and t^(1/3) by 40 Newton steps from 1 each, so the
- * result is a fixed function of the input bits. */
-static double root_n(double a, int n)
+ * operations only: u^2.4 = u^2 (u^2)^(1/5) by 40 Newton steps from 1 and t^(1/3) by 20, so
+ * the result is a fixed function of the input bits. */
+static double root_n(double a, int n, int steps)
 {
     double y = 1.0;
-    for (int k = 0; k < 40; k++) {
+    for (int k = 0; k < steps; k++) {
         double p = y;
         for (int m = 2; m < n; m++) p = p * y;        /* y^(n-1) */
         y = y - (p * y - a) / ((double)n * p);
@@ -174,13 +174,13 @@ static double srgb_linear(int c)
     if (v <= 0.04045) return v / 12.92;
     double u = (v + 0.055) / 1.055;
     double u2 = u * u;
-    return u2 * root_n(u2, 5);
+    return u2 * root_n(u2, 5, 40);
 }
 
 static double lab_f(double t)
 {
     const double e = (6.0 / 29.0) * (6.0 / 29.0) * (6.0 / 29.0);
-    if (t > e) return root_n(t, 3);
+    if (t > e) return root_n(t, 3, 20);
     return t / (3.0 * (6.0 / 29.0) * (6.0 / 29.0)) + 4.0 / 29.0;
 }
 
