@@ -50,6 +50,10 @@ enum { PGM_FEAT_INT16 = 0,     /* full gradient image, int16 (PGM-C / PGM-G, Sec
        PGM_FEAT_SIGN = 2 };    /* direction-only, "G./|G|" read element-wise: the sign of     */
                                /* every gradient component in {-1, 0, 1} (integer distance)   */
 enum { PGM_RGB = 0, PGM_GRAY = 1 };                    /* 6- or 2-channel gradient image       */
+enum { PGM_SPACE_RGB = 0,    /* colour spaces of the gradient pyramids (Sec. III-E, Table II)  */
+       PGM_SPACE_YCRCB = 1,  /* integer BT.601: Y = (77R + 150G + 29B + 128) >> 8, Cr and Cb  */
+                             /* 128 + round((R - Y) 183 / 256), 128 + round((B - Y) 144 / 256) */
+       PGM_SPACE_LAB = 2 };  /* 8-bit CIELab (sRGB curve, D65): L* 255/100, a* + 128, b* + 128 */
 enum { PGM_INIT_RANDOM = 0, PGM_INIT_EXHAUSTIVE = 1 }; /* initial field at the coarsest level  */
 
 #define PGM_MAX_LEVELS 8
@@ -81,6 +85,8 @@ typedef struct {
                                      /* outliers; 0 = off (the paper uses 9)                 */
     int32_t region_link_px;          /* 4-neighbouring inliers share a region when their     */
                                      /* displacements differ by less than this (1..65535)   */
+    int32_t space_fwd[PGM_MAX_LEVELS]; /* PGM_SPACE_* of the forward / backward gradient    */
+    int32_t space_bwd[PGM_MAX_LEVELS]; /* pyramid per level (PGM_RGB only; 0 = RGB)         */
     uint64_t rng_seed;               /* key of the counter-based random generator            */
 } pgm_params;
 
@@ -217,8 +223,10 @@ PGM_API pgm_status pgm_format_matches(const pgm_match_t* host_matches, int64_t n
  * the last call's stream to finish.
  *  pgm_dump_level:    level_nx*level_ny records of 4 int32 {dx, dy, dist, flags} of field
  *                     `dir` (0 forward, 1 backward) after the level's last update.
- *  pgm_dump_gradient: level_w*level_h*2C values of image `image` (0 or 1) at `level`, int16
- *                     (PGM_FEAT_INT16) or float, channel order [Gx_0..Gx_C-1, Gy_0..Gy_C-1].
+ *  pgm_dump_gradient: level_w*level_h*2C values of image `image` at `level`, int16 (integer
+ *                     features) or float, channel order [Gx_0..Gx_C-1, Gy_0..Gy_C-1]; images
+ *                     0 and 1 in the forward pyramid's colour space, 2 and 3 (images 1 and 2)
+ *                     in the backward one's.
  *  pgm_dump_pyramid:  level_w*level_h*3 uint8 of image `image` at `level`. */
 PGM_API pgm_status pgm_dump_level(void* ctx, int32_t level, int32_t dir, int32_t* host_out);
 PGM_API pgm_status pgm_dump_gradient(void* ctx, int32_t level, int32_t image, void* host_out);

@@ -23,6 +23,7 @@ MAX_LEVELS = 8
 PGM_OK, PGM_EINVAL, PGM_ENOMEM, PGM_EDEVICE, PGM_EUNSUPPORTED = 0, -1, -2, -3, -5
 FEAT_INT16, FEAT_F32_DIR, FEAT_SIGN = 0, 1, 2
 RGB, GRAY = 0, 1
+SPACE_RGB, SPACE_YCRCB, SPACE_LAB = 0, 1, 2
 INIT_RANDOM, INIT_EXHAUSTIVE = 0, 1
 FLAG_INIT, FLAG_INLIER, FLAG_RECORD = 1, 2, 4
 PRESET_PAPER, PRESET_CONFIG1, PRESET_CONFIG2, PRESET_CONFIG3 = 0, 1, 2, 3
@@ -37,6 +38,7 @@ class pgm_params(C.Structure):
         ("feature", C.c_int32), ("color", C.c_int32), ("fwd_bwd", C.c_int32),
         ("consistency_px", C.c_int32), ("init_mode", C.c_int32), ("refine_rounds", C.c_int32),
         ("min_region_px", C.c_int32), ("region_link_px", C.c_int32),
+        ("space_fwd", C.c_int32 * MAX_LEVELS), ("space_bwd", C.c_int32 * MAX_LEVELS),
         ("rng_seed", C.c_uint64),
     ]
 
@@ -156,9 +158,9 @@ def params(d: dict | None = None, preset: int | None = None, **kw) -> pgm_params
     if preset is not None:
         _check(lib().pgm_default_params(C.byref(p), preset), None)
     for k, v in dict(d or {}, **kw).items():
-        if k == "iters":
+        if k in ("iters", "space_fwd", "space_bwd"):
             vals = (list(v) + [0] * MAX_LEVELS)[:MAX_LEVELS]
-            p.iters = (C.c_int32 * MAX_LEVELS)(*vals)
+            setattr(p, k, (C.c_int32 * MAX_LEVELS)(*vals))
         else:
             setattr(p, k, v)
     return p
@@ -167,6 +169,8 @@ def params(d: dict | None = None, preset: int | None = None, **kw) -> pgm_params
 def params_dict(p: pgm_params) -> dict:
     d = {name: getattr(p, name) for name, _ in pgm_params._fields_}
     d["iters"] = list(p.iters)[: p.levels]
+    d["space_fwd"] = list(p.space_fwd)[: p.levels]
+    d["space_bwd"] = list(p.space_bwd)[: p.levels]
     return d
 
 

@@ -18,7 +18,7 @@ struct Layout {
     int L = 0, ch = 3, C2 = 6, esize = 2, f32 = 0;
     int lw[PGM_MAX_LEVELS], lh[PGM_MAX_LEVELS], lnx[PGM_MAX_LEVELS], lny[PGM_MAX_LEVELS];
     size_t pyr[2][PGM_MAX_LEVELS];                       // level >= 1 RGB images
-    size_t grad[2][PGM_MAX_LEVELS];                      // padded gradient images
+    size_t grad[4][PGM_MAX_LEVELS];                      // padded gradient images (4 slots)
     size_t disp[2][PGM_MAX_LEVELS], dist[2][PGM_MAX_LEVELS], flags[2][PGM_MAX_LEVELS];
     size_t rnd = 0, rnd_init = 0;
     // stages of the schedule
@@ -95,6 +95,13 @@ const char* validate(const pgm_params* p, int w, int h)
     if (p->init_mode != PGM_INIT_RANDOM && p->init_mode != PGM_INIT_EXHAUSTIVE) return "unknown init_mode";
     if (p->refine_rounds < 0 || p->refine_rounds > 16) return "refine_rounds must be within 0..16";
     if (p->refine_rounds > 0 && p->levels < 2) return "refinement needs at least two levels";
+    for (int l = 0; l < p->levels; l++) {
+        if (p->space_fwd[l] < PGM_SPACE_RGB || p->space_fwd[l] > PGM_SPACE_LAB || p->space_bwd[l] < PGM_SPACE_RGB ||
+            p->space_bwd[l] > PGM_SPACE_LAB)
+            return "unknown colour space";
+        if (p->color == PGM_GRAY && (p->space_fwd[l] != PGM_SPACE_RGB || p->space_bwd[l] != PGM_SPACE_RGB))
+            return "colour spaces need color = PGM_RGB";
+    }
     if (p->min_region_px < 0) return "min_region_px must not be negative";
     if (p->min_region_px > 0 && (p->region_link_px < 1 || p->region_link_px > 65535))
         return "region_link_px must be within 1..65535";
@@ -146,11 +153,18 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
 
     // per-pair slice
     cur = 0;
+    // gradient images: slots 0, 1 = images 1, 2 in the forward pyramid's colour space, slots
+    // 2, 3 = images 1, 2 in the backward one's (the same memory when the spaces agree)
     for (int im = 0; im < 2; im++)
         for (int l = 0; l < Y.L; l++) {
             Y.pyr[im][l] = l ? take(cur, (size_t)Y.lw[l] * Y.lh[l] * 3) : 0;
             Y.grad[im][l] = take(cur, (size_t)(Y.lw[l] + 2 * PAD) * (Y.lh[l] + 2 * PAD) * Y.C2 * Y.esize);
         }
+    for (int l = 0; l < Y.L; l++)
+        for (int im = 0; im < 2; im++)
+            Y.grad[2 + im][l] = p->space_fwd[l] == p->space_bwd[l]
+                                    ? Y.grad[im][l]
+                                    : take(cur, (size_t)(Y.lw[l] + 2 * PAD) * (Y.lh[l] + 2 * PAD) * Y.C2 * Y.esize);
     for (int d = 0; d < 2; d++)
         for (int l = 0; l < Y.L; l++) {
             size_t n = (size_t)Y.lnx[l] * Y.lny[l];
@@ -278,6 +292,13 @@ pgm_status pgm_default_params(pgm_params* p, int32_t preset)
     p->region_link_px = 12;
     switch (preset) {
     case PGM_PRESET_PAPER:   // Sec. IV: W=2, S=5, L=3, N=2, 6 / 4 iterations; r = 7 / 5
+        // Table II: forward pyramid RGB, CIELab, YCrCb; backward CIELab, YCrCb, RGB
+        p->space_fwd[0] = PGM_SPACE_RGB;
+        p->space_fwd[1] = PGM_SPACE_LAB;
+        p->space_fwd[2] = PGM_SPACE_YCRCB;
+        p->space_bwd[0] = PGM_SPACE_LAB;
+        p->space_bwd[1] = PGM_SPACE_YCRCB;
+        p->space_bwd[2] = PGM_SPACE_RGB;
         p->seed_stride = 1;
         p->patch_fwd = 15;
         p->patch_bwd = 11;
@@ -469,16 +490,21 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     ra.key0 = (uint32_t)p->rng_seed;
     ra.key1 = (uint32_t)(p->rng_seed >> 32);
 
+    // one entry per colour space the level needs (two when the pyramids differ there)
     auto grad_level = [&](GradArgs& ga, int l, const uint8_t* s0, const uint8_t* s1, long long szs, int pitch) {
-        GradLevel& L = ga.lv[ga.n++];
-        L.src[0] = s0;
-        L.src[1] = s1;
-        L.src_zs = szs;
-        L.pitch = pitch;
-        L.w = Y.lw[l];
-        L.h = Y.lh[l];
-        L.G[0] = pw0 + Y.grad[0][l];
-        L.G[1] = pw0 + Y.grad[1][l];
+        for (int half = 0; half < 2; half++) {
+            if (half == 1 && p->space_fwd[l] == p->space_bwd[l]) break;
+            GradLevel& L = ga.lv[ga.n++];
+            L.src[0] = s0;
+            L.src[1] = s1;
+            L.src_zs = szs;
+            L.pitch = pitch;
+            L.w = Y.lw[l];
+            L.h = Y.lh[l];
+            L.G[0] = pw0 + Y.grad[2 * half][l];
+            L.G[1] = pw0 + Y.grad[2 * half + 1][l];
+            L.space = half ? p->space_bwd[l] : p->space_fwd[l];
+        }
     };
     auto pyr_level = [&](PyrArgs& pr, int l, const uint8_t* s0, const uint8_t* s1, long long szs, int pitch) {
         pr.src[0] = s0;
@@ -494,7 +520,6 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     const bool gray = p->color == PGM_GRAY;
     pa.grad.dst_zs = zs;
     grad_level(pa.grad, 0, img1, img2, image_stride_bytes, pitch_bytes);
-    pa.grad.n = 1;
     pa.with_pyr = Y.L > 1;
     if (pa.with_pyr) pyr_level(pa.pyr, 1, img1, img2, image_stride_bytes, pitch_bytes);
     PGM_HIP(c, timed(PGM_K_PREP, [&] { return launch_prep(pa, npairs, gray, p->sobel_ksize, p->feature, s); }));
@@ -526,13 +551,15 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         f.flags = pw0 + Y.flags[d][l];
         return f;
     };
-    auto gorigin = [&](int im, int l) {
-        return (const void*)(pw0 + Y.grad[im][l] + ((size_t)PAD * (Y.lw[l] + 2 * PAD) + PAD) * Y.C2 * Y.esize);
+    auto gorigin = [&](int slot, int l) {
+        return (const void*)(pw0 + Y.grad[slot][l] + ((size_t)PAD * (Y.lw[l] + 2 * PAD) + PAD) * Y.C2 * Y.esize);
     };
     auto dirargs = [&](int d, int l, int k) {
         DirArgs a;
-        a.Ga = gorigin(d, l);
-        a.Gb = gorigin(1 - d, l);
+        // forward: image 1 against image 2 in the forward space; backward: image 2 against
+        // image 1 in the backward space
+        a.Ga = d == 0 ? gorigin(0, l) : gorigin(3, l);
+        a.Gb = d == 0 ? gorigin(1, l) : gorigin(2, l);
         a.f = field(d, l);
         a.rnd = (const short2*)(ws + Y.rnd) + Y.st_base[k] + (long long)d * p->iters[l] * Y.lnx[l] * Y.lny[l] * Y.st_nI[k];
         a.rnd0 = (const short2*)(ws + Y.rnd_init) + (size_t)d * Y.lnx[m] * Y.lny[m];
@@ -1120,7 +1147,7 @@ pgm_status pgm_dump_gradient(void* ctx, int32_t level, int32_t image, void* host
     pgm_ctx_s* c = (pgm_ctx_s*)ctx;
     pgm_status st = dump_prep(c, level);
     if (st != PGM_OK) return st;
-    if ((image != 0 && image != 1) || !host_out) return fail(c, PGM_EINVAL, "bad image or null output");
+    if (image < 0 || image > 3 || !host_out) return fail(c, PGM_EINVAL, "bad image or null output");
     const Layout& Y = c->last;
     const int w = Y.lw[level], h = Y.lh[level], pw = w + 2 * PAD;
     const size_t row = (size_t)w * Y.C2 * Y.esize;

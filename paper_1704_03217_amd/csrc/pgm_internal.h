@@ -171,20 +171,21 @@ struct GradLevel {
     long long src_zs;        // bytes between pairs' source images
     int pitch, w, h;
     void* G[2];              // pair 0's padded gradient images
+    int space;               // PGM_SPACE_* the pixels are converted into first
     int tx, tiles, base;
 };
 struct GradArgs {
-    GradLevel lv[PGM_MAX_LEVELS];
+    GradLevel lv[2 * PGM_MAX_LEVELS];
     int n;
     long long dst_zs;
 };
 // the first launch of a call: random numbers, level-0 gradients and (with_pyr) pyramid level 1
 struct PrepArgs {
     RngArgs rng;
-    GradArgs grad;           // level 0 in lv[0]
+    GradArgs grad;           // level 0 (one entry per colour space)
     PyrArgs pyr;
     int with_pyr;
-    int rng_blocks, grad_blocks;   // filled in by the launcher
+    int rng_blocks, grad_blocks, grad_tiles;   // filled in by the launcher
 };
 // feat: PGM_FEAT_* (0 integer gradients, 1 direction-only float, 2 literal signs)
 hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hipStream_t s);

@@ -1019,6 +1019,68 @@ __device__ __forceinline__ void pyr_tile(const PyrArgs& a, int t, int z, uint32_
 // gradient image (Sec. III-A, Eq. 1-2) written with a replicated PAD border
 // ---------------------------------------------------------------------------------------
 
+// Colour spaces of the gradient pyramids (Sec. III-E, Table II): integer BT.601 YCrCb, and
+// 8-bit CIELab (sRGB transfer curve, D65) from plain IEEE double operations in a fixed order
+// (u^2.4 = u^2 (u^2)^(1/5) by 40 Newton steps, t^(1/3) by 20), so that each value is a fixed
+// function of the pixel; contraction into fused multiply-adds is off for that reason.
+__device__ __forceinline__ uint32_t to_ycrcb(uint32_t rgb)
+{
+    const int R = rgb & 0xFF, G = (rgb >> 8) & 0xFF, B = (rgb >> 16) & 0xFF;
+    const int Y = (77 * R + 150 * G + 29 * B + 128) >> 8;
+    const int cr = (R - Y) * 183 + 32768 + 128, cb = (B - Y) * 144 + 32768 + 128;
+    const int Cr = cr < 0 ? 0 : min(cr >> 8, 255), Cb = cb < 0 ? 0 : min(cb >> 8, 255);
+    return (uint32_t)Y | ((uint32_t)Cr << 8) | ((uint32_t)Cb << 16);
+}
+
+__device__ double root_newton(double a, int n, int steps)
+{
+#pragma clang fp contract(off)
+    double y = 1.0;
+    for (int k = 0; k < steps; k++) {
+        double p = y;
+        for (int m = 2; m < n; m++) p = p * y;
+        y = y - (p * y - a) / ((double)n * p);
+    }
+    return y;
+}
+
+__device__ double srgb_linear(int c)
+{
+#pragma clang fp contract(off)
+    const double v = (double)c / 255.0;
+    if (v <= 0.04045) return v / 12.92;
+    const double u = (v + 0.055) / 1.055;
+    const double u2 = u * u;
+    return u2 * root_newton(u2, 5, 40);
+}
+
+__device__ double lab_f(double t)
+{
+#pragma clang fp contract(off)
+    const double e = (6.0 / 29.0) * (6.0 / 29.0) * (6.0 / 29.0);
+    if (t > e) return root_newton(t, 3, 20);
+    return t / (3.0 * (6.0 / 29.0) * (6.0 / 29.0)) + 4.0 / 29.0;
+}
+
+__device__ __forceinline__ uint32_t lab_u8(double x)
+{
+    const double r = floor(x + 0.5);
+    return (uint32_t)(r < 0.0 ? 0.0 : (r > 255.0 ? 255.0 : r));
+}
+
+// lin: the block's table of srgb_linear(0..255)
+__device__ uint32_t to_lab(uint32_t rgb, const double* lin)
+{
+#pragma clang fp contract(off)
+    const double r = lin[rgb & 0xFF], g = lin[(rgb >> 8) & 0xFF], b = lin[(rgb >> 16) & 0xFF];
+    const double X = 0.4124564 * r + 0.3575761 * g + 0.1804375 * b;
+    const double Yv = 0.2126729 * r + 0.7151522 * g + 0.0721750 * b;
+    const double Z = 0.0193339 * r + 0.1191920 * g + 0.9503041 * b;
+    const double fx = lab_f(X / 0.95047), fy = lab_f(Yv), fz = lab_f(Z / 1.08883);
+    return lab_u8((116.0 * fy - 16.0) * 2.55) | (lab_u8(500.0 * (fx - fy) + 128.0) << 8) |
+           (lab_u8(200.0 * (fy - fz) + 128.0) << 16);
+}
+
 // A work-group computes 64 x 8 pixels of the padded gradient image. It stages the source
 // pixels (one dword per pixel: R | G << 8 | B << 16, or the integer luma) that the windows of
 // its pixels read -- the padding maps to the nearest image pixel, the filter reflects (101) --
@@ -1029,7 +1091,8 @@ constexpr int GR_LDS = GR_SV * GR_SU + GR_SV * GR_TW * 6;                    // 
 
 // FEAT: 0 integer gradients, 1 direction-only unit vectors (float), 2 literal signs
 template <int KS, bool GRAY, int FEAT>
-__device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, int t, int z, uint32_t* lds)
+__device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, int t, int z, uint32_t* lds,
+                                          double* lin)
 {
     constexpr bool F32 = FEAT == 1;
     constexpr int CH = GRAY ? 1 : 3;
@@ -1048,6 +1111,10 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
     const int cy0 = clampi(Y0 - PAD, 0, h - 1), cy1 = clampi(min(Y0 + GR_TH - 1, ph - 1) - PAD, 0, h - 1);
     const int NC = cx1 - cx0 + 1, NR = cy1 - cy0 + 1;
     const int NU = NC + 2 * K, NV = NR + 2 * K;
+    if (!GRAY && L.space == PGM_SPACE_LAB) {   // uniform over the work-group
+        lin[threadIdx.x] = srgb_linear((int)threadIdx.x);
+        __syncthreads();
+    }
     for (int e = threadIdx.x; e < NU * NV; e += 256) {
         const int v = e / NU, u = e - v * NU;
         const int x = mirror_fast(cx0 - K + u, w), y = mirror_fast(cy0 - K + v, h);
@@ -1057,6 +1124,8 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
             val = (uint32_t)((77 * p[0] + 150 * p[1] + 29 * p[2] + 128) >> 8);
         } else {
             val = rgb_at(img, L.pitch, x, y);
+            if (L.space == PGM_SPACE_YCRCB) val = to_ycrcb(val);
+            else if (L.space == PGM_SPACE_LAB) val = to_lab(val, lin);
         }
         S[v * GR_SU + u] = val;
     }
@@ -1203,14 +1272,18 @@ template <int KS, bool GRAY, int FEAT>
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
 {
     __shared__ uint32_t lds[PREP_LDS];
+    __shared__ double lin[256];
     int b = blockIdx.x;
     if (b < a.rng_blocks) {
         rng_item(a.rng, (long long)b * 256 + threadIdx.x);
         return;
     }
     b -= a.rng_blocks;
-    if (b < a.grad_blocks) {
-        grad_tile<KS, GRAY, FEAT>(a.grad.lv[0], a.grad.dst_zs, b % a.grad.lv[0].tiles, b / a.grad.lv[0].tiles, lds);
+    if (b < a.grad_blocks) {   // level 0 in each colour space it needs
+        const int z = b / a.grad_tiles, tt = b - z * a.grad_tiles;
+        int e = 0;
+        while (e + 1 < a.grad.n && tt >= a.grad.lv[e + 1].base) e++;
+        grad_tile<KS, GRAY, FEAT>(a.grad.lv[e], a.grad.dst_zs, tt - a.grad.lv[e].base, z, lds, lin);
         return;
     }
     b -= a.grad_blocks;
@@ -1227,9 +1300,10 @@ template <int KS, bool GRAY, int FEAT>
 __global__ __launch_bounds__(256) void k_gradient(GradArgs a)
 {
     __shared__ uint32_t lds[GR_LDS];
+    __shared__ double lin[256];
     int lv = 0;
     while (lv + 1 < a.n && (int)blockIdx.x >= a.lv[lv + 1].base) lv++;
-    grad_tile<KS, GRAY, FEAT>(a.lv[lv], a.dst_zs, (int)blockIdx.x - a.lv[lv].base, blockIdx.y, lds);
+    grad_tile<KS, GRAY, FEAT>(a.lv[lv], a.dst_zs, (int)blockIdx.x - a.lv[lv].base, blockIdx.y, lds, lin);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1286,8 +1360,8 @@ hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hi
     const long long items = 2LL * a.rng.n_top + a.rng.total_items;
     if ((items + 255) / 256 > 0x40000000LL) return hipErrorInvalidValue;
     a.rng_blocks = (int)((items + 255) / 256);
-    a.grad.n = 1;
-    a.grad_blocks = plan_grad(a.grad) * 2 * npairs;
+    a.grad_tiles = plan_grad(a.grad);
+    a.grad_blocks = a.grad_tiles * 2 * npairs;
     if (a.with_pyr) plan_pyr(a.pyr);
     const long long blocks = (long long)a.rng_blocks + a.grad_blocks + (a.with_pyr ? (long long)a.pyr.tiles * 2 * npairs : 0);
     if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;

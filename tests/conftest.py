@@ -20,6 +20,8 @@ def base_params(**kw):
     p.update(kw)
     if len(p["iters"]) < p["levels"]:
         p["iters"] = list(p["iters"]) + [p["iters"][-1]] * (p["levels"] - len(p["iters"]))
+    for k in ("space_fwd", "space_bwd"):
+        p[k] = (list(p.get(k, [])) + [0] * p["levels"])[: p["levels"]]
     return p
 
 

@@ -74,6 +74,8 @@ def test_paper_preset():
     assert (d["patch_fwd"], d["patch_bwd"]) == (15, 11)
     assert d["seed_stride"] == 1
     assert (d["min_region_px"], d["region_link_px"]) == (9, 12)   # Sec. III-E
+    assert d["space_fwd"] == [pgm.SPACE_RGB, pgm.SPACE_LAB, pgm.SPACE_YCRCB]   # Table II
+    assert d["space_bwd"] == [pgm.SPACE_LAB, pgm.SPACE_YCRCB, pgm.SPACE_RGB]
 
 
 @pytest.mark.parametrize("w,h,L,stride", [(1024, 436, 5, 3), (1242, 375, 5, 3), (256, 192, 3, 3),
@@ -102,7 +104,8 @@ def test_query_workspace_of_config2_is_modest():
                                  dict(consistency_px=-1), dict(init_mode=2), dict(refine_rounds=17),
                                  dict(levels=1, iters=[1], refine_rounds=1), dict(max_disp=-1),
                                  dict(min_region_px=-1), dict(min_region_px=9, region_link_px=0),
-                                 dict(min_region_px=9, region_link_px=65536)])
+                                 dict(min_region_px=9, region_link_px=65536), dict(space_fwd=[3, 0, 0]),
+                                 dict(space_bwd=[0, -1, 0]), dict(color=1, space_fwd=[1, 0, 0])])
 def test_query_rejects_invalid_parameters(bad):
     with pytest.raises(pgm.PGMError) as e:
         pgm.pgm_query(base_params(**bad), 64, 64)

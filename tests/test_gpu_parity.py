@@ -70,10 +70,13 @@ def compare(m, params, img1, img2, name, levels=True, features=True):
 
 
 def check_features(m, params, img1, img2, name):
-    """Pyramid (Sec. III-D) and gradient image (Eq. 1-2) of every level, bit-exact."""
+    """Pyramid (Sec. III-D) and gradient image (Eq. 1-2) of every level, bit-exact, in the
+    colour space of each direction's pyramid (Table II)."""
     L = params["levels"]
     f32 = params["feature"] == 1
     ch = 1 if params["color"] == 1 else 3
+    sf = params.get("space_fwd", [0] * L)
+    sb = params.get("space_bwd", [0] * L)
     ims = [np.ascontiguousarray(img1), np.ascontiguousarray(img2)]
     problems = []
     for l in range(L):
@@ -83,17 +86,20 @@ def check_features(m, params, img1, img2, name):
             gp = m.dump_pyramid(l, k)
             if not np.array_equal(gp, ims[k]):
                 problems.append(f"pyramid level {l} image {k}: {(gp != ims[k]).sum()} values differ")
-            src = oracle.gray(ims[k]) if ch == 1 else ims[k]
+        for slot in range(4):
+            k = slot % 2
+            space = sf[l] if slot < 2 else sb[l]
+            src = oracle.gray(ims[k]) if ch == 1 else oracle.convert(ims[k], space)
             G = oracle.gradient_image(src, params["sobel_ksize"])
             if f32:
                 G = oracle.direction(G)
             elif params["feature"] == 2:
                 G = oracle.sign(G)
-            got = m.dump_gradient(l, k, 2 * ch, f32)
+            got = m.dump_gradient(l, slot, 2 * ch, f32)
             a, b = (got.view(np.uint32), G.view(np.uint32)) if f32 else (got, G)
             if not np.array_equal(a, b):
                 bad = np.argwhere(a != b)
-                problems.append(f"gradient level {l} image {k}: {len(bad)} values differ, first {bad[:3].tolist()} "
+                problems.append(f"gradient level {l} slot {slot}: {len(bad)} values differ, first {bad[:3].tolist()} "
                                 f"gpu {[got[tuple(i)] for i in bad[:3]]} oracle {[G[tuple(i)] for i in bad[:3]]}")
     assert not problems, f"{name}: " + " | ".join(problems)
 
@@ -122,6 +128,11 @@ CASES = {
     # "G./|G|" read element-wise (literal signs, Sec. III-F), colour and gray
     "sign_feature": (lambda: synth.config_pair(1), base_params(feature=2, rng_seed=18)),
     "sign_feature_gray_dense": (lambda: synth.rect_pair(22, 48, 64, dmax=6), base_params(feature=2, color=1, seed_stride=1, max_disp=6, rng_seed=19)),
+    # the colour spaces of Table II (forward RGB, CIELab, YCrCb; backward CIELab, YCrCb, RGB),
+    # the same with direction features, and one space shared by both pyramids
+    "spaces_table2": (lambda: synth.config_pair(1), base_params(space_fwd=[0, 2, 1], space_bwd=[2, 1, 0], rng_seed=20)),
+    "spaces_table2_direction": (lambda: synth.config_pair(1), base_params(feature=1, space_fwd=[0, 2, 1], space_bwd=[2, 1, 0], rng_seed=21)),
+    "spaces_shared_lab": (lambda: synth.rect_pair(23, 96, 128, dmax=10), base_params(levels=2, iters=[3, 3], max_disp=10, space_fwd=[2, 2], space_bwd=[2, 2], rng_seed=22)),
     "regions_dense": (lambda: synth.rect_pair(21, 72, 96, dmax=8), base_params(seed_stride=1, levels=2, iters=[3, 3], max_disp=8, min_region_px=9, region_link_px=12, rng_seed=16)),
     "regions_stride3": (lambda: synth.config_pair(1), base_params(min_region_px=81, region_link_px=1, rng_seed=17)),
 }
