@@ -35,6 +35,7 @@ class Params(C.Structure):
         ("consistency_px", C.c_int32), ("init_mode", C.c_int32), ("refine_rounds", C.c_int32),
         ("min_region_px", C.c_int32), ("region_link_px", C.c_int32),
         ("space_fwd", C.c_int32 * MAX_LEVELS), ("space_bwd", C.c_int32 * MAX_LEVELS),
+        ("metric", C.c_int32),
         ("rng_seed", C.c_uint64),
     ]
 
@@ -75,6 +76,8 @@ def lib():
         L.pgmo_direction.argtypes = [P, C.c_int, C.c_int, P]
         L.pgmo_dist_i16.argtypes = [P, P] + [C.c_int] * 8
         L.pgmo_dist_i16.restype = C.c_int64
+        L.pgmo_ssd_i16.argtypes = [P, P] + [C.c_int] * 8
+        L.pgmo_ssd_i16.restype = C.c_int64
         L.pgmo_dist_f32.argtypes = [P, P] + [C.c_int] * 8
         L.pgmo_dist_f32.restype = C.c_float
         L.pgmo_philox4x32_10.argtypes = [P, P, P]
@@ -189,6 +192,13 @@ def dist(Ga: np.ndarray, Gb: np.ndarray, P: int, xa: int, ya: int, xb: int, yb: 
         return lib().pgmo_dist_i16(_p(Ga), _p(Gb), w, h, C2, P, xa, ya, xb, yb)
     Ga = np.ascontiguousarray(Ga, np.float32); Gb = np.ascontiguousarray(Gb, np.float32)
     return lib().pgmo_dist_f32(_p(Ga), _p(Gb), w, h, C2, P, xa, ya, xb, yb)
+
+
+def ssd(Ga: np.ndarray, Gb: np.ndarray, P: int, xa: int, ya: int, xb: int, yb: int) -> int:
+    """Eq. 3 as printed (squared differences) on integer features, exact."""
+    h, w, C2 = Ga.shape
+    Ga = np.ascontiguousarray(Ga, np.int16); Gb = np.ascontiguousarray(Gb, np.int16)
+    return lib().pgmo_ssd_i16(_p(Ga), _p(Gb), w, h, C2, P, xa, ya, xb, yb)
 
 
 def philox(ctr, key) -> np.ndarray:

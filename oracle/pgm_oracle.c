@@ -130,9 +130,9 @@ void pgmo_direction(const int16_t* G, int npix, int ch, float* U)
 
 /* ------------------------------------------------------------------------------------- */
 /* Patch distance (Sec. III-B, Eq. 3).                                                    */
-/* READING: absolute differences summed over the patch and channels (the paper squares    */
-/* them); patch offsets [-floor(P/2), ceil(P/2)-1] so that even sides work; pixels        */
-/* outside the image take the nearest edge pixel.                                         */
+/* READING: absolute differences summed over the patch and channels by default (the paper */
+/* squares them: PGMO_METRIC_SSD); patch offsets [-floor(P/2), ceil(P/2)-1] so that even */
+/* sides work; pixels outside the image take the nearest edge pixel.                      */
 /* ------------------------------------------------------------------------------------- */
 
 int64_t pgmo_dist_i16(const int16_t* Ga, const int16_t* Gb, int w, int h, int C2, int P,
@@ -224,6 +224,25 @@ void pgmo_convert(const uint8_t* rgb, int npx, int space, uint8_t* out)
 void pgmo_sign(int16_t* G, int n)
 {
     for (int k = 0; k < n; k++) G[k] = (int16_t)(G[k] > 0 ? 1 : (G[k] < 0 ? -1 : 0));
+}
+
+/* Eq. 3 read literally (the squared metric, PGMO_METRIC_SSD): the squared differences of
+ * integer features summed exactly in 64 bits (at most 16*16*6 terms of 48960^2 < 2^42). */
+int64_t pgmo_ssd_i16(const int16_t* Ga, const int16_t* Gb, int w, int h, int C2, int P,
+                     int xa, int ya, int xb, int yb)
+{
+    int lo = -(P / 2), hi = (P + 1) / 2 - 1;
+    int64_t s = 0;
+    for (int oy = lo; oy <= hi; oy++)
+        for (int ox = lo; ox <= hi; ox++) {
+            size_t ia = ((size_t)clampi(ya + oy, 0, h - 1) * w + clampi(xa + ox, 0, w - 1)) * C2;
+            size_t ib = ((size_t)clampi(yb + oy, 0, h - 1) * w + clampi(xb + ox, 0, w - 1)) * C2;
+            for (int c = 0; c < C2; c++) {
+                int64_t d = (int64_t)Ga[ia + c] - (int64_t)Gb[ib + c];
+                s += d * d;
+            }
+        }
+    return s;
 }
 
 /* The float features are unit-vector components: zero or of magnitude >= 2^-14 (the
@@ -340,7 +359,7 @@ int pgmo_top_radius(const pgmo_params* p, int w, int h)
 
 typedef struct {
     int w, h, nx, ny, n, stride;
-    int C2, P, feature;
+    int C2, P, feature, metric;
     const int16_t *Gi_self, *Gi_other;   /* integer features of this field's two images */
     const float *Gf_self, *Gf_other;     /* float features (direction-only variant)     */
     int32_t *dx, *dy;                    /* displacement F(p) - p                       */
@@ -357,6 +376,8 @@ typedef struct {
 static double cost(run_t* r, const field_t* f, int xa, int ya, int xb, int yb)
 {
     r->evals++;
+    if (f->feature != PGMO_FEAT_F32_DIR && f->metric == PGMO_METRIC_SSD)   /* exact: < 2^53 */
+        return (double)pgmo_ssd_i16(f->Gi_self, f->Gi_other, f->w, f->h, f->C2, f->P, xa, ya, xb, yb);
     if (f->feature != PGMO_FEAT_F32_DIR)
         return (double)pgmo_dist_i16(f->Gi_self, f->Gi_other, f->w, f->h, f->C2, f->P, xa, ya, xb, yb);
     return (double)pgmo_dist_f32(f->Gf_self, f->Gf_other, f->w, f->h, f->C2, f->P, xa, ya, xb, yb);
@@ -655,7 +676,7 @@ void pgmo_remove_small_regions(const int32_t* dx, const int32_t* dy, uint8_t* in
 static int32_t dist_bits(const field_t* f, int s)
 {
     if (!f->init[s]) return 0x7FFFFFFF;
-    if (f->feature != PGMO_FEAT_F32_DIR) return (int32_t)f->dist[s];
+    if (f->feature != PGMO_FEAT_F32_DIR) return (int32_t)(f->dist[s] < 2147483646.0 ? f->dist[s] : 2147483646.0);
     float v = (float)f->dist[s];
     int32_t b;
     memcpy(&b, &v, 4);
@@ -684,7 +705,8 @@ int pgmo_sweep(const pgmo_params* p, int level, int dir, int stage, int W, const
     memset(&f, 0, sizeof f);
     f.w = w; f.h = h; f.stride = p->seed_stride;
     f.nx = pgmo_grid_count(w, f.stride); f.ny = pgmo_grid_count(h, f.stride); f.n = f.nx * f.ny;
-    f.C2 = 2 * ch; f.P = P; f.feature = p->feature;
+    f.C2 = 2 * ch; f.P = P; f.feature = p->feature; f.metric = p->metric;
+    if (p->metric == PGMO_METRIC_SSD) return -1;   /* a 32-bit distance state cannot hold it */
     if (p->feature != PGMO_FEAT_F32_DIR) { f.Gi_self = Ga; f.Gi_other = Gb; }
     else { f.Gf_self = Ga; f.Gf_other = Gb; }
     f.dx = dx; f.dy = dy; f.init = init;
@@ -726,6 +748,8 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
     if (w > 16384 || h > 16384) return -1;
     if (p->refine_rounds > 0 && p->levels < 2) return -1;
     if (p->min_region_px < 0 || (p->min_region_px > 0 && p->region_link_px < 1)) return -1;
+    if (p->metric != PGMO_METRIC_SAD && p->metric != PGMO_METRIC_SSD) return -1;
+    if (p->metric == PGMO_METRIC_SSD && p->feature == PGMO_FEAT_F32_DIR) return -1;
     for (int l = 0; l < p->levels; l++) {
         if (p->space_fwd[l] < 0 || p->space_fwd[l] > 2 || p->space_bwd[l] < 0 || p->space_bwd[l] > 2) return -1;
         if (p->color == PGMO_GRAY && (p->space_fwd[l] || p->space_bwd[l])) return -1;
@@ -786,7 +810,7 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
         for (int l = 0; l < L; l++) {
             field_t* f = &F[d][l];
             f->w = lw[l]; f->h = lh[l]; f->nx = lnx[l]; f->ny = lny[l]; f->n = lnx[l] * lny[l];
-            f->stride = p->seed_stride; f->C2 = C2; f->feature = p->feature;
+            f->stride = p->seed_stride; f->C2 = C2; f->feature = p->feature; f->metric = p->metric;
             f->P = d == 0 ? p->patch_fwd : p->patch_bwd;
             f->Gi_self = Gi[d][d][l]; f->Gi_other = Gi[d][1 - d][l];
             f->Gf_self = Gf[d][d][l]; f->Gf_other = Gf[d][1 - d][l];

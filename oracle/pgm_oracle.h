@@ -29,6 +29,7 @@ extern "C" {
 enum { PGMO_FEAT_INT16 = 0, PGMO_FEAT_F32_DIR = 1, PGMO_FEAT_SIGN = 2 };
 enum { PGMO_RGB = 0, PGMO_GRAY = 1 };
 enum { PGMO_SPACE_RGB = 0, PGMO_SPACE_YCRCB = 1, PGMO_SPACE_LAB = 2 };
+enum { PGMO_METRIC_SAD = 0, PGMO_METRIC_SSD = 1 };
 enum { PGMO_INIT_RANDOM = 0, PGMO_INIT_EXHAUSTIVE = 1 };
 enum { PGMO_SYNC = 0, PGMO_SCAN = 1 };
 
@@ -55,6 +56,7 @@ typedef struct {
     int32_t region_link_px;            /* neighbours link when |d_a - d_b| < this            */
     int32_t space_fwd[PGMO_MAX_LEVELS]; /* colour space of the forward / backward gradient   */
     int32_t space_bwd[PGMO_MAX_LEVELS]; /* pyramid per level (Table II), PGMO_SPACE_*        */
+    int32_t metric;                    /* PGMO_METRIC_*: Eq. 3 summed absolutely or squared */
     uint64_t rng_seed;                 /* key of the counter-based generator                 */
 } pgmo_params;
 
@@ -83,6 +85,9 @@ int64_t pgmo_dist_i16(const int16_t* Ga, const int16_t* Gb, int w, int h, int C2
                       int xa, int ya, int xb, int yb);
 float pgmo_dist_f32(const float* Ua, const float* Ub, int w, int h, int C2, int P,
                     int xa, int ya, int xb, int yb);
+/* Eq. 3 as printed: sum of squared differences of integer features, exact in 64 bits */
+int64_t pgmo_ssd_i16(const int16_t* Ga, const int16_t* Gb, int w, int h, int C2, int P,
+                     int xa, int ya, int xb, int yb);
 /* Philox4x32 with 10 rounds (Salmon et al., SC'11) */
 void pgmo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* offset floor(R W / 2^i) of Eq. 5 for R = (2u+1)/2^32 - 1 */
@@ -119,6 +124,8 @@ int pgmo_sweep(const pgmo_params* p, int level, int dir, int stage, int W, const
  * trace (nullable): for dir 0 then 1, for level 0..L-1, n_l seeds x {dx, dy, dist, flags}
  *   int32, the state after that level's last consistency update;
  * n_evals (nullable): number of patch-distance evaluations.
+ * A match's dist is the patch distance, the bits of a float for the float features, and for
+ * the squared metric the 64-bit sum clamped to 0x7FFFFFFE (the decisions use the exact sum).
  * Returns 0, or -1 on invalid parameters. */
 int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, int w, int h,
                int pitch, int schedule, pgmo_match_t* out_fwd, pgmo_match_t* out_bwd,

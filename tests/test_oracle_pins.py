@@ -749,3 +749,40 @@ def test_colour_spaces_in_the_pipeline(oracle_lib):
     assert np.all(r["fwd"]["dist"][init] == 0)
     d = oracle.match(paper, pr.img1, pr.img2, trace=False)
     assert not np.array_equal(d["bwd"], plain["bwd"])      # the backward field sees other features
+
+
+# ---- Eq. 3 as printed: the squared metric ----
+
+@pytest.mark.parametrize("P", [1, 5, 8, 16])
+def test_ssd_matches_numpy_brute_force(oracle_lib, P):
+    rng = np.random.default_rng(P)
+    h, w = 23, 29
+    Ga = rng.integers(-24480, 24481, (h, w, 6)).astype(np.int16)
+    Gb = rng.integers(-24480, 24481, (h, w, 6)).astype(np.int16)
+    lo, hi = -(P // 2), (P + 1) // 2 - 1
+    for (xa, ya, xb, yb) in [(10, 10, 12, 9), (0, 0, w - 1, h - 1), (3, h - 2, 1, 2)]:
+        ys_a = np.clip(ya + np.arange(lo, hi + 1), 0, h - 1); xs_a = np.clip(xa + np.arange(lo, hi + 1), 0, w - 1)
+        ys_b = np.clip(yb + np.arange(lo, hi + 1), 0, h - 1); xs_b = np.clip(xb + np.arange(lo, hi + 1), 0, w - 1)
+        a = Ga[ys_a][:, xs_a].astype(np.int64); b = Gb[ys_b][:, xs_b].astype(np.int64)
+        assert oracle.ssd(Ga, Gb, P, xa, ya, xb, yb) == int(((a - b) ** 2).sum())
+
+
+def test_ssd_exact_beyond_32_bits(oracle_lib):
+    h, w = 20, 20
+    Ga = np.full((h, w, 6), 24480, np.int16)
+    Gb = np.full((h, w, 6), -24480, np.int16)
+    assert oracle.ssd(Ga, Gb, 16, 10, 10, 10, 10) == 16 * 16 * 6 * 48960 ** 2   # ~3.7e12
+
+
+def test_ssd_pipeline_translation_and_output_clamp(oracle_lib):
+    h, w = 72, 96
+    pair = synth.translate_pair(41, h, w, 6, -4)
+    p = base_params(levels=2, iters=[8, 8], max_disp=16, metric=1, rng_seed=7)
+    r = oracle.match(p, pair.img1, pair.img2)
+    st = r["levels"][0][0]
+    fin = _interior(_seed_pts(w, h, 3), w, h, (6, -4), 8)
+    assert len(fin) > 100
+    for s in fin:
+        assert (st[s, 0], st[s, 1], st[s, 2]) == (6, -4, 0)
+    init = (r["fwd"]["flags"] & 1) != 0
+    assert r["fwd"]["dist"][init].max() <= 0x7FFFFFFE            # clamped output
