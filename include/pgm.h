@@ -55,6 +55,9 @@ enum { PGM_SPACE_RGB = 0,    /* colour spaces of the gradient pyramids (Sec. III
                              /* 128 + round((R - Y) 183 / 256), 128 + round((B - Y) 144 / 256) */
        PGM_SPACE_LAB = 2 };  /* 8-bit CIELab (sRGB curve, D65): L* 255/100, a* + 128, b* + 128 */
 enum { PGM_INIT_RANDOM = 0, PGM_INIT_EXHAUSTIVE = 1 }; /* initial field at the coarsest level  */
+enum { PGM_METRIC_SAD = 0,   /* patch distance: sum of absolute feature differences          */
+       PGM_METRIC_SSD = 1 }; /* sum of squared differences (Eq. 3 as printed), integer       */
+                             /* features only, exact in 64 bits                              */
 
 #define PGM_MAX_LEVELS 8
 
@@ -87,13 +90,14 @@ typedef struct {
                                      /* displacements differ by less than this (1..65535)   */
     int32_t space_fwd[PGM_MAX_LEVELS]; /* PGM_SPACE_* of the forward / backward gradient    */
     int32_t space_bwd[PGM_MAX_LEVELS]; /* pyramid per level (PGM_RGB only; 0 = RGB)         */
+    int32_t metric;                  /* PGM_METRIC_*                                         */
     uint64_t rng_seed;               /* key of the counter-based random generator            */
 } pgm_params;
 
 /* One match on the level-0 seed grid: seed (x1, y1) in the first image of the pair and its
- * match (x2, y2) in the second. dist is the patch distance (int32 sum of absolute gradient
- * differences, or the bits of a float for PGM_FEAT_F32_DIR); 0x7FFFFFFF and (x2, y2) =
- * (x1, y1) where the field is uninitialised. flags: PGM_FLAG_*. 24 bytes. */
+ * match (x2, y2) in the second. dist is the patch distance (the integer sum of the metric,
+ * clamped to 0x7FFFFFFE, or the bits of a float for PGM_FEAT_F32_DIR); 0x7FFFFFFF and
+ * (x2, y2) = (x1, y1) where the field is uninitialised. flags: PGM_FLAG_*. 24 bytes. */
 typedef struct { int32_t x1, y1, x2, y2, dist; uint32_t flags; } pgm_match_t;
 
 /* Sizes for an image size and parameter set. */

@@ -25,6 +25,7 @@ FEAT_INT16, FEAT_F32_DIR, FEAT_SIGN = 0, 1, 2
 RGB, GRAY = 0, 1
 SPACE_RGB, SPACE_YCRCB, SPACE_LAB = 0, 1, 2
 INIT_RANDOM, INIT_EXHAUSTIVE = 0, 1
+METRIC_SAD, METRIC_SSD = 0, 1
 FLAG_INIT, FLAG_INLIER, FLAG_RECORD = 1, 2, 4
 PRESET_PAPER, PRESET_CONFIG1, PRESET_CONFIG2, PRESET_CONFIG3 = 0, 1, 2, 3
 
@@ -39,7 +40,7 @@ class pgm_params(C.Structure):
         ("consistency_px", C.c_int32), ("init_mode", C.c_int32), ("refine_rounds", C.c_int32),
         ("min_region_px", C.c_int32), ("region_link_px", C.c_int32),
         ("space_fwd", C.c_int32 * MAX_LEVELS), ("space_bwd", C.c_int32 * MAX_LEVELS),
-        ("rng_seed", C.c_uint64),
+        ("metric", C.c_int32), ("rng_seed", C.c_uint64),
     ]
 
 

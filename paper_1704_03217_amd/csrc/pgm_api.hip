@@ -16,6 +16,7 @@ namespace {
 
 struct Layout {
     int L = 0, ch = 3, C2 = 6, esize = 2, f32 = 0;
+    int kind = 0, dsize = 4;   // matching kernel family; bytes per stored distance
     int lw[PGM_MAX_LEVELS], lh[PGM_MAX_LEVELS], lnx[PGM_MAX_LEVELS], lny[PGM_MAX_LEVELS];
     size_t pyr[2][PGM_MAX_LEVELS];                       // level >= 1 RGB images
     size_t grad[4][PGM_MAX_LEVELS];                      // padded gradient images (4 slots)
@@ -102,6 +103,9 @@ const char* validate(const pgm_params* p, int w, int h)
         if (p->color == PGM_GRAY && (p->space_fwd[l] != PGM_SPACE_RGB || p->space_bwd[l] != PGM_SPACE_RGB))
             return "colour spaces need color = PGM_RGB";
     }
+    if (p->metric != PGM_METRIC_SAD && p->metric != PGM_METRIC_SSD) return "unknown metric";
+    if (p->metric == PGM_METRIC_SSD && p->feature == PGM_FEAT_F32_DIR)
+        return "the squared metric needs integer features";
     if (p->min_region_px < 0) return "min_region_px must not be negative";
     if (p->min_region_px > 0 && (p->region_link_px < 1 || p->region_link_px > 65535))
         return "region_link_px must be within 1..65535";
@@ -115,6 +119,8 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
     Y.ch = p->color == PGM_GRAY ? 1 : 3;
     Y.C2 = 2 * Y.ch;
     Y.f32 = p->feature == PGM_FEAT_F32_DIR;
+    Y.kind = Y.f32 ? 1 : (p->metric == PGM_METRIC_SSD ? 2 : 0);
+    Y.dsize = Y.kind == 2 ? 8 : 4;
     Y.esize = Y.f32 ? 4 : 2;
     int cw = w, chh = h;
     for (int l = 0; l < Y.L; l++) {
@@ -169,7 +175,7 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
         for (int l = 0; l < Y.L; l++) {
             size_t n = (size_t)Y.lnx[l] * Y.lny[l];
             Y.disp[d][l] = take(cur, n * 4);
-            Y.dist[d][l] = take(cur, n * 4);
+            Y.dist[d][l] = take(cur, n * Y.dsize);
             Y.flags[d][l] = take(cur, n);
         }
     for (int k = 0; k < Y.nst; k++) {
@@ -214,7 +220,7 @@ bool level_layout(const Layout& Y, int l, size_t lds_max, LevelLayout& o)
     o.gstride = (graw + 15) & ~(size_t)15;
     o.disp = 2 * o.gstride;
     o.dist = o.disp + n * 4;
-    o.total = (o.dist + n * 4 + 15) & ~(size_t)15;
+    o.total = (o.dist + n * Y.dsize + 15) & ~(size_t)15;
     return o.total + 64 <= lds_max;   // room for the kernel's static LDS
 }
 
@@ -547,7 +553,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     auto field = [&](int d, int l) {
         Field f;
         f.disp = (uint32_t*)(pw0 + Y.disp[d][l]);
-        f.dist = (uint32_t*)(pw0 + Y.dist[d][l]);
+        f.dist = pw0 + Y.dist[d][l];
         f.flags = pw0 + Y.flags[d][l];
         return f;
     };
@@ -592,7 +598,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
                 a.exhaustive = p->init_mode == PGM_INIT_EXHAUSTIVE;
                 a.R = Y.R_top;
                 a.cnt = ctable(CNT_INIT, (long long)nd * match_blocks(g.nx * g.ny, a.d[0].P));
-                PGM_HIP(c, timed(PGM_K_INIT, [&] { return launch_init(a, Y.C2, Y.f32, s); }));
+                PGM_HIP(c, timed(PGM_K_INIT, [&] { return launch_init(a, Y.C2, Y.kind, s); }));
             } else {
                 TransArgs a;
                 memset(&a, 0, sizeof a);
@@ -608,10 +614,10 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
                 const long long nb = (long long)nd * match_blocks(g.nx * g.ny, a.d[0].P);
                 if (enter == ENTER_UP_FO) {
                     a.cnt = ctable(CNT_UP, nb);
-                    PGM_HIP(c, timed(PGM_K_UP, [&] { return launch_up(a, Y.C2, Y.f32, s); }));
+                    PGM_HIP(c, timed(PGM_K_UP, [&] { return launch_up(a, Y.C2, Y.kind, s); }));
                 } else {
                     a.cnt = ctable(CNT_DOWN, nb);
-                    PGM_HIP(c, timed(PGM_K_DOWN, [&] { return launch_down(a, Y.C2, Y.f32, s); }));
+                    PGM_HIP(c, timed(PGM_K_DOWN, [&] { return launch_down(a, Y.C2, Y.kind, s); }));
                 }
             }
         }
@@ -628,7 +634,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
             la.cnt = ctable(CNT_SWEEP, 2);
             la.gbytes = la.lay.gstride;
             la.gorig = ((size_t)PAD * (Y.lw[l] + 2 * PAD) + PAD) * Y.C2 * Y.esize;
-            PGM_HIP(c, timed(PGM_K_LEVEL, [&] { return launch_level(la, Y.C2, Y.f32, s); }));
+            PGM_HIP(c, timed(PGM_K_LEVEL, [&] { return launch_level(la, Y.C2, Y.kind, s); }));
         }
         // Step 1: iterations of propagation and limited random search, red then black
         for (int t = 0; t < (in_lds ? 0 : p->iters[l]); t++)
@@ -645,7 +651,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
                     a.colour = colour;
                     a.nI = Y.st_nI[k];
                     a.cnt = ctable(CNT_SWEEP, (long long)nd * sweep_blocks(g.nx, g.ny, a.d[0].P));
-                    PGM_HIP(c, timed(PGM_K_SWEEP, [&] { return launch_sweep(a, Y.C2, Y.f32, s); }));
+                    PGM_HIP(c, timed(PGM_K_SWEEP, [&] { return launch_sweep(a, Y.C2, Y.kind, s); }));
                 }
         // Step 2-3
         CheckArgs ca;
@@ -682,6 +688,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     oa.b = batch(1);
     oa.f = field(0, 0);
     oa.out = out_fwd;
+    oa.dist8 = Y.dsize == 8;
     oa.blockcnt = compact ? (uint32_t*)(pw0 + Y.blockcnt) : nullptr;
     PGM_HIP(c, timed(PGM_K_OUTPUT, [&] { return launch_output(oa, s); }));
     if (out_bwd) {
@@ -1124,18 +1131,27 @@ pgm_status pgm_dump_level(void* ctx, int32_t level, int32_t dir, int32_t* host_o
     if ((dir != 0 && dir != 1) || !host_out) return fail(c, PGM_EINVAL, "bad dir or null output");
     const Layout& Y = c->last;
     const size_t n = (size_t)Y.lnx[level] * Y.lny[level];
-    std::string buf(n * 9, '\0');
+    std::vector<uint64_t> dist(n);
+    std::string buf(n * 5, '\0');
     uint32_t* disp = (uint32_t*)&buf[0];
-    uint32_t* dist = disp + n;
-    uint8_t* flags = (uint8_t*)(dist + n);
+    uint8_t* flags = (uint8_t*)(disp + n);
     PGM_HIP(c, hipMemcpy(disp, c->last_ws + Y.shared_bytes + Y.disp[dir][level], n * 4, hipMemcpyDeviceToHost));
-    PGM_HIP(c, hipMemcpy(dist, c->last_ws + Y.shared_bytes + Y.dist[dir][level], n * 4, hipMemcpyDeviceToHost));
+    if (Y.dsize == 8) {
+        PGM_HIP(c, hipMemcpy(dist.data(), c->last_ws + Y.shared_bytes + Y.dist[dir][level], n * 8,
+                             hipMemcpyDeviceToHost));
+    } else {
+        std::vector<uint32_t> d32(n);
+        PGM_HIP(c, hipMemcpy(d32.data(), c->last_ws + Y.shared_bytes + Y.dist[dir][level], n * 4,
+                             hipMemcpyDeviceToHost));
+        for (size_t s = 0; s < n; s++) dist[s] = d32[s];
+    }
     PGM_HIP(c, hipMemcpy(flags, c->last_ws + Y.shared_bytes + Y.flags[dir][level], n, hipMemcpyDeviceToHost));
     for (size_t s = 0; s < n; s++) {
         const bool init = disp[s] != UNINIT;
         host_out[4 * s + 0] = init ? (int32_t)(int16_t)(disp[s] & 0xFFFF) : 0;
         host_out[4 * s + 1] = init ? (int32_t)(int16_t)(disp[s] >> 16) : 0;
-        host_out[4 * s + 2] = init ? (int32_t)dist[s] : (int32_t)NO_DIST;
+        // squared distances above the int32 range report its largest value below NO_DIST
+        host_out[4 * s + 2] = init ? (int32_t)(dist[s] < 0x7FFFFFFEull ? dist[s] : 0x7FFFFFFEull) : (int32_t)NO_DIST;
         host_out[4 * s + 3] = (int32_t)((init ? PGM_FLAG_INIT : 0u) | ((flags[s] & ST_INL) ? PGM_FLAG_INLIER : 0u) |
                                         ((flags[s] & ST_REC) ? PGM_FLAG_RECORD : 0u));
     }

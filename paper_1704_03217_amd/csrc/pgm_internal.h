@@ -16,7 +16,7 @@ constexpr int PAD = 8;
 // Packed displacement (dx in the low, dy in the high 16 bits); this value marks an
 // uninitialised seed (|d| never reaches 32768 since images are at most 16384 wide).
 constexpr uint32_t UNINIT = 0x80008000u;
-constexpr uint32_t NO_DIST = 0x7FFFFFFFu;
+constexpr uint64_t NO_DIST = 0x7FFFFFFFull;
 // Integer gradients are stored biased to unsigned 16 bit (g + 32768) for v_sad_u16.
 constexpr uint32_t BIAS = 32768u;
 // Per-seed state flags in the workspace.
@@ -28,7 +28,8 @@ constexpr int MAX_STAGES = 1 + 2 * 16 + PGM_MAX_LEVELS;
 // One correspondence field (one direction at one level) in device memory.
 struct Field {
     uint32_t* disp;   // packed (dx, dy) or UNINIT
-    uint32_t* dist;   // int32 distance, or float bits (non-negative floats order as uints)
+    void* dist;       // patch distance: uint32 (absolute-difference sum, or float bits, as
+                      // non-negative floats order as unsigned integers) or uint64 (squared sum)
     uint8_t* flags;   // ST_*
 };
 
@@ -114,6 +115,7 @@ struct OutArgs {
     const pgm_match_t* dense;
     pgm_match_t* compact;  // pair z writes compact + z * nx * ny (or null)
     int32_t* n_out;        // pair z writes n_out[z] (or null)
+    int dist8;             // the field's distances are uint64
 };
 
 struct RngStage {
@@ -191,10 +193,10 @@ struct PrepArgs {
 hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hipStream_t s);
 hipError_t launch_pyr(PyrArgs a, int npairs, hipStream_t s);
 hipError_t launch_gradient(GradArgs a, int npairs, int gray, int ksize, int feat, hipStream_t s);
-hipError_t launch_init(const InitArgs& a, int C2, int f32, hipStream_t s);
-hipError_t launch_sweep(const SweepArgs& a, int C2, int f32, hipStream_t s);
-hipError_t launch_down(const TransArgs& a, int C2, int f32, hipStream_t s);
-hipError_t launch_up(const TransArgs& a, int C2, int f32, hipStream_t s);
+hipError_t launch_init(const InitArgs& a, int C2, int kind, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs& a, int C2, int kind, hipStream_t s);
+hipError_t launch_down(const TransArgs& a, int C2, int kind, hipStream_t s);
+hipError_t launch_up(const TransArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);
 // small-region removal on the level-0 forward field: four launches (labels, unions, region
 // sizes, flags)
@@ -209,7 +211,7 @@ struct RegionArgs {
 };
 hipError_t launch_regions(const RegionArgs& a, hipStream_t s);
 // every sweep of a small level, one work-group per pair and direction
-hipError_t launch_level(const LevelArgs& a, int C2, int f32, hipStream_t s);
+hipError_t launch_level(const LevelArgs& a, int C2, int kind, hipStream_t s);
 // let every whole-level kernel use up to `bytes` of dynamic LDS (once per context)
 hipError_t level_allow_lds(size_t bytes);
 hipError_t launch_output(const OutArgs& a, hipStream_t s);

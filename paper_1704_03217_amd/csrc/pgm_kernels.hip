@@ -179,6 +179,7 @@ struct IntRow {
     }
     template <int LPS>
     static __device__ __forceinline__ uint32_t finish(uint32_t partial) { return group_sum<LPS>(partial); }
+    using Dist = uint32_t;
 };
 
 // Direction-only float features. The components are unit-vector coordinates (zero or of
@@ -187,6 +188,7 @@ struct IntRow {
 template <int C2, int PMAX, bool FIXED>
 struct F32Row {
     using Acc = double;
+    using Dist = uint32_t;
     static constexpr bool CAN_BUF = false;
     float a[PMAX][C2];
 
@@ -226,10 +228,42 @@ struct F32Row {
     }
 };
 
-template <int C2, int PMAX, bool FIXED, bool F32>
-using RowT = typename std::conditional<F32, F32Row<C2, PMAX, FIXED>, IntRow<C2, PMAX, FIXED>>::type;
+// Eq. 3 as printed: squared differences of the same packed integer features, summed exactly
+// (a lane's part < 2^38, a group's < 2^42: exact in the double used for the DPP sum).
+template <int C2, int PMAX, bool FIXED>
+struct SsdRow : IntRow<C2, PMAX, FIXED> {
+    using Acc = uint64_t;
+    using Dist = uint64_t;
+    __device__ __forceinline__ uint64_t sad(const SsdRow& B, int P) const
+    {
+        uint64_t acc = 0;
+#pragma unroll
+        for (int y = 0; y < PMAX; y++)
+            if (FIXED || y < P)
+#pragma unroll
+                for (int w = 0; w < IntRow<C2, PMAX, FIXED>::W3; w++) {
+                    const uint32_t a = this->a[y][w], b = B.a[y][w];
+                    const uint32_t d0 = (uint32_t)abs((int)(a & 0xFFFFu) - (int)(b & 0xFFFFu));
+                    const uint32_t d1 = (uint32_t)abs((int)(a >> 16) - (int)(b >> 16));
+                    acc += (uint64_t)(d0 * d0) + (uint64_t)(d1 * d1);
+                }
+        return acc;
+    }
+    template <int LPS>
+    static __device__ __forceinline__ uint64_t finish(uint64_t partial)
+    {
+        return (uint64_t)group_sum<LPS>((double)partial);
+    }
+};
 
-// Patch distance of Eq. 3 (absolute differences) between the patch held by the group and
+// KIND: 0 integer features with absolute differences, 1 float direction features, 2 integer
+// features with squared differences
+template <int C2, int PMAX, bool FIXED, int KIND>
+using RowT = typename std::conditional<
+    KIND == 1, F32Row<C2, PMAX, FIXED>,
+    typename std::conditional<KIND == 2, SsdRow<C2, PMAX, FIXED>, IntRow<C2, PMAX, FIXED>>::type>::type;
+
+// Patch distance of Eq. 3 (absolute or squared differences) between the patch held by the group and
 // the patch of the other image at (qx, qy); every lane of the group gets the result. Lanes
 // past the patch side read a valid column and add nothing. All rows of the candidate are
 // requested before the first one is used (the scheduling barrier keeps the compiler from
@@ -238,7 +272,7 @@ using RowT = typename std::conditional<F32, F32Row<C2, PMAX, FIXED>, IntRow<C2, 
 // (BUF) or plain loads (LDS images, float features)
 
 template <class Row, int LPS, bool BUF>
-__device__ __forceinline__ uint32_t patch_cost(const Row& A, const void* Gb, const Geo& g, int P,
+__device__ __forceinline__ typename Row::Dist patch_cost(const Row& A, const void* Gb, const Geo& g, int P,
                                                int r, int qx, int qy)
 {
     const int half = P >> 1;
@@ -253,7 +287,8 @@ __device__ __forceinline__ uint32_t patch_cost(const Row& A, const void* Gb, con
 // Two patch distances with the reads of both candidates in flight together.
 template <class Row, int LPS, bool BUF>
 __device__ __forceinline__ void patch_cost2(const Row& A, const void* Gb, const Geo& g, int P, int r, int q0x,
-                                            int q0y, int q1x, int q1y, uint32_t& e0, uint32_t& e1)
+                                            int q0y, int q1x, int q1y, typename Row::Dist& e0,
+                                            typename Row::Dist& e1)
 {
     const int half = P >> 1;
     Row B0, B1;
@@ -352,8 +387,10 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
     const int P = D.P;
     Row A;
     load_own<BUF>(A, D.Ga, g, P, r, px, py);
+    using Dist = typename Row::Dist;
+    Dist* const dist = (Dist*)D.f.dist;
     const uint32_t cur0 = D.f.disp[s];
-    const uint32_t cd0 = D.f.dist[s];
+    const Dist cd0 = dist[s];
     const bool init0 = cur0 != UNINIT;
     // Eq. 5 offsets of the first two random candidates (nI >= 1), fetched with the field;
     // the neighbours' fields are read from clamped indices and masked, so that every read
@@ -388,16 +425,17 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
     // are read; the decisions below replay the paper's one-at-a-time order exactly.
     const bool need0 = ok[0] && !(init0 && c[0] == cur0);
     const bool need1 = ok[1] && !(init0 && c[1] == cur0) && !(ok[0] && c[1] == c[0]);
-    uint32_t e[2] = {cd0, cd0};
+    Dist e[2] = {cd0, cd0};
     if (need0 || need1) {
         const uint32_t qa = need0 ? c[0] : c[1], qb = need1 ? c[1] : c[0];
-        uint32_t ea, eb;
+        Dist ea, eb;
         patch_cost2<Row, LPS, BUF>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb), ea, eb);
         if (need0) e[0] = ea;
         if (need1) e[1] = eb;
     }
     if (ok[1] && !need1 && !(init0 && c[1] == cur0)) e[1] = e[0];
-    uint32_t cur = cur0, cd = cd0;
+    uint32_t cur = cur0;
+    Dist cd = cd0;
     bool init = init0, changed = false;
 #pragma unroll
     for (int m = 0; m < 2; m++) {
@@ -410,7 +448,8 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
     // priced two at a time in the same way and decided in order
     if (init) {
         const int cx = d_x(cur), cy = d_y(cur);
-        const uint32_t curp = cur, cdp = cd;
+        const uint32_t curp = cur;
+        const Dist cdp = cd;
         for (int ii = 0; ii < nI; ii += 2) {
             if (ii > 0) {
                 o0 = R[ii];
@@ -421,10 +460,10 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
             const uint32_t r1 = two ? target(px, py, cx + o1.x, cy + o1.y, g) : curp;
             const bool n0 = r0 != curp;
             const bool n1 = r1 != curp && r1 != r0;
-            uint32_t f0 = cdp, f1 = cdp;
+            Dist f0 = cdp, f1 = cdp;
             if (n0 || n1) {
                 const uint32_t qa = n0 ? r0 : r1, qb = n1 ? r1 : r0;
-                uint32_t ea, eb;
+                Dist ea, eb;
                 patch_cost2<Row, LPS, BUF>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb),
                                       ea, eb);
                 if (n0) f0 = ea;
@@ -443,16 +482,16 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
     }
     if (changed && r == 0) {
         D.f.disp[s] = cur;
-        D.f.dist[s] = cd;
+        dist[s] = cd;
     }
     return nev;
 }
 
 // one half-sweep (Step 1, one colour of one iteration) of every seed of the launch
-template <int C2, int PMAX, bool FIXED, bool F32>
+template <int C2, int PMAX, bool FIXED, int KIND>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 {
-    using Row = RowT<C2, PMAX, FIXED, F32>;
+    using Row = RowT<C2, PMAX, FIXED, KIND>;
     constexpr int LPS = PMAX;
     constexpr int GPB = 256 / LPS;
     const Geo& g = a.g;
@@ -475,10 +514,10 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 // the exact best displacement in that window (dy outer, dx inner, strictly smaller wins)
 // ---------------------------------------------------------------------------------------
 
-template <int C2, int PMAX, bool FIXED, bool F32>
+template <int C2, int PMAX, bool FIXED, int KIND>
 __global__ __launch_bounds__(256) void k_init(InitArgs a)
 {
-    using Row = RowT<C2, PMAX, FIXED, F32>;
+    using Row = RowT<C2, PMAX, FIXED, KIND>;
     constexpr int LPS = PMAX;
     constexpr int GPB = 256 / LPS;
     const Geo& g = a.g;
@@ -495,7 +534,9 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
         const int P = D.P;
         Row A;
         load_own<true>(A, D.Ga, g, P, r, px, py);
-        uint32_t best = UNINIT, bd = NO_DIST;
+        using Dist = typename Row::Dist;
+        uint32_t best = UNINIT;
+        Dist bd = NO_DIST;
         if (!a.exhaustive) {
             const short2 o = D.rnd0[s];
             best = target(px, py, o.x, o.y, g);
@@ -507,7 +548,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
             const int x0 = max(-a.R, -px), x1 = min(a.R, g.w - 1 - px);
             for (int dy = y0; dy <= y1; dy++) {
                 for (int dx = x0; dx <= x1; dx++) {
-                    const uint32_t e = patch_cost<Row, LPS, true>(A, D.Gb, g, P, r, px + dx, py + dy);
+                    const Dist e = patch_cost<Row, LPS, true>(A, D.Gb, g, P, r, px + dx, py + dy);
                     nev++;
                     if (best == UNINIT || e < bd) { best = pack_d(dx, dy); bd = e; }
                 }
@@ -515,7 +556,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
         }
         if (r == 0) {
             D.f.disp[s] = best;
-            D.f.dist[s] = bd;
+            ((Dist*)D.f.dist)[s] = bd;
             D.f.flags[s] = 0;
         }
     }
@@ -527,10 +568,10 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
 // displacement of the nearest parent seed to (x/2, y/2) if that parent is an inlier
 // ---------------------------------------------------------------------------------------
 
-template <int C2, int PMAX, bool FIXED, bool F32>
+template <int C2, int PMAX, bool FIXED, int KIND>
 __global__ __launch_bounds__(256) void k_down(TransArgs a)
 {
-    using Row = RowT<C2, PMAX, FIXED, F32>;
+    using Row = RowT<C2, PMAX, FIXED, KIND>;
     constexpr int LPS = PMAX;
     constexpr int GPB = 256 / LPS;
     const Geo& g = a.g;
@@ -552,7 +593,8 @@ __global__ __launch_bounds__(256) void k_down(TransArgs a)
         const uint8_t pf = S.flags[ps];
         const uint32_t pd = S.disp[ps];
         const bool par_inl = (pf & ST_INL) != 0;
-        uint32_t disp = UNINIT, dist = NO_DIST;
+        uint32_t disp = UNINIT;
+        typename Row::Dist dist = NO_DIST;
         if (par_inl) {
             disp = target(px, py, 2 * d_x(pd), 2 * d_y(pd), g);
             dist = patch_cost<Row, LPS, true>(A, D.Gb, g, D.P, r, px + d_x(disp), py + d_y(disp));
@@ -560,7 +602,7 @@ __global__ __launch_bounds__(256) void k_down(TransArgs a)
         }
         if (r == 0) {
             D.f.disp[s] = disp;
-            D.f.dist[s] = dist;
+            ((typename Row::Dist*)D.f.dist)[s] = dist;
             D.f.flags[s] = (a.carry_record && par_inl) ? ST_REC : 0;
         }
     }
@@ -579,10 +621,10 @@ __device__ __forceinline__ int div_round(int num, int den)   // den > 0
     return num < 0 ? -q : q;
 }
 
-template <int C2, int PMAX, bool FIXED, bool F32>
+template <int C2, int PMAX, bool FIXED, int KIND>
 __global__ __launch_bounds__(256) void k_up(TransArgs a)
 {
-    using Row = RowT<C2, PMAX, FIXED, F32>;
+    using Row = RowT<C2, PMAX, FIXED, KIND>;
     constexpr int LPS = PMAX;
     constexpr int GPB = 256 / LPS;
     const Geo& g = a.g;     // coarse level being entered
@@ -612,7 +654,8 @@ __global__ __launch_bounds__(256) void k_up(TransArgs a)
                 sx += d_x(d); sy += d_y(d); cnt++;
             }
         }
-        uint32_t disp = UNINIT, dist = NO_DIST;
+        uint32_t disp = UNINIT;
+        typename Row::Dist dist = NO_DIST;
         if (cnt > 0) {
             disp = target(px, py, div_round(sx, 2 * cnt), div_round(sy, 2 * cnt), g);
             Row A;
@@ -622,7 +665,7 @@ __global__ __launch_bounds__(256) void k_up(TransArgs a)
         }
         if (r == 0) {
             D.f.disp[s] = disp;
-            D.f.dist[s] = dist;
+            ((typename Row::Dist*)D.f.dist)[s] = dist;
             D.f.flags[s] = cnt > 0 ? ST_REC : 0;
         }
     }
@@ -678,12 +721,12 @@ struct LevelShape {
     static constexpr int threads = !F32 ? (PMAX == 8 ? 1024 : 512) : (PMAX == 8 ? 512 : 256);
 };
 
-template <int C2, int PMAX, bool FIXED, bool F32>
-__global__ __launch_bounds__((LevelShape<PMAX, F32>::threads)) void k_level(LevelArgs a)
+template <int C2, int PMAX, bool FIXED, int KIND>
+__global__ __launch_bounds__((LevelShape<PMAX, KIND == 1>::threads)) void k_level(LevelArgs a)
 {
-    using Row = RowT<C2, PMAX, FIXED, F32>;
+    using Row = RowT<C2, PMAX, FIXED, KIND>;
     constexpr int LPS = PMAX;
-    constexpr int NT = LevelShape<PMAX, F32>::threads;
+    constexpr int NT = LevelShape<PMAX, KIND == 1>::threads;
     constexpr int NG = NT / LPS;
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t evsum;
@@ -696,7 +739,9 @@ __global__ __launch_bounds__((LevelShape<PMAX, F32>::threads)) void k_level(Leve
     uint8_t* GA = lds;
     uint8_t* GB = lds + Y.gstride;
     uint32_t* disp = (uint32_t*)(lds + Y.disp);
-    uint32_t* dist = (uint32_t*)(lds + Y.dist);
+    using Dist = typename Row::Dist;
+    Dist* dist = (Dist*)(lds + Y.dist);
+    Dist* const hdist = (Dist*)H.f.dist;
     // copy in: both padded gradient images (16-byte pieces) and the field
     {
         const uint4* sa = (const uint4*)((const uint8_t*)H.Ga - a.gorig);
@@ -708,7 +753,7 @@ __global__ __launch_bounds__((LevelShape<PMAX, F32>::threads)) void k_level(Leve
         }
         for (int q = threadIdx.x; q < n; q += NT) {
             disp[q] = H.f.disp[q];
-            dist[q] = H.f.dist[q];
+            dist[q] = hdist[q];
         }
         if (threadIdx.x == 0) evsum = 0;
     }
@@ -736,7 +781,7 @@ __global__ __launch_bounds__((LevelShape<PMAX, F32>::threads)) void k_level(Leve
     if (r == 0 && nev) atomicAdd(&evsum, nev);
     for (int q = threadIdx.x; q < n; q += NT) {
         H.f.disp[q] = disp[q];
-        H.f.dist[q] = dist[q];
+        hdist[q] = dist[q];
     }
     __syncthreads();
     if (a.cnt && threadIdx.x == 0) zoff(a.cnt, zo)[dir] = evsum;
@@ -862,7 +907,9 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a)
         const bool init = d != UNINIT;
         m.x2 = m.x1 + (init ? d_x(d) : 0);
         m.y2 = m.y1 + (init ? d_y(d) : 0);
-        m.dist = init ? (int32_t)f.dist[s] : (int32_t)NO_DIST;
+        // the squared metric's 64-bit sum is reported clamped to 31 bits (decisions used it whole)
+        const uint64_t fd = a.dist8 ? ((const uint64_t*)f.dist)[s] : ((const uint32_t*)f.dist)[s];
+        m.dist = init ? (int32_t)(fd < 0x7FFFFFFEull ? fd : 0x7FFFFFFEull) : (int32_t)NO_DIST;
         m.flags = (init ? PGM_FLAG_INIT : 0u) | ((fl & ST_INL) ? PGM_FLAG_INLIER : 0u) |
                   ((fl & ST_REC) ? PGM_FLAG_RECORD : 0u);
         out[s] = m;
@@ -1394,27 +1441,28 @@ hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hi
 
 #define PGM_V(KERNEL, C2_, PM_, FX_)                                                             \
     if (C2 == C2_ && pmax == PM_ && fixed == FX_) {                                              \
-        if (f32) hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, true>), grid, dim3(256), 0, s, a);    \
-        else hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, false>), grid, dim3(256), 0, s, a);       \
+        if (kind == 1) hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, 1>), grid, dim3(256), 0, s, a); \
+        else if (kind == 2) hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, 2>), grid, dim3(256), 0, s, a); \
+        else hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, 0>), grid, dim3(256), 0, s, a);           \
         return hipGetLastError();                                                                \
     }
 
-hipError_t launch_sweep(const SweepArgs& a, int C2, int f32, hipStream_t s)
+hipError_t launch_sweep(const SweepArgs& a, int C2, int kind, hipStream_t s)
 {
     PGM_DISPATCH(k_sweep, a, a.g.ny * ((a.g.nx + 1) / 2));
 }
 
-hipError_t launch_init(const InitArgs& a, int C2, int f32, hipStream_t s)
+hipError_t launch_init(const InitArgs& a, int C2, int kind, hipStream_t s)
 {
     PGM_DISPATCH(k_init, a, a.g.nx * a.g.ny);
 }
 
-hipError_t launch_down(const TransArgs& a, int C2, int f32, hipStream_t s)
+hipError_t launch_down(const TransArgs& a, int C2, int kind, hipStream_t s)
 {
     PGM_DISPATCH(k_down, a, a.g.nx * a.g.ny);
 }
 
-hipError_t launch_up(const TransArgs& a, int C2, int f32, hipStream_t s)
+hipError_t launch_up(const TransArgs& a, int C2, int kind, hipStream_t s)
 {
     PGM_DISPATCH(k_up, a, a.g.nx * a.g.ny);
 }
@@ -1422,11 +1470,12 @@ hipError_t launch_up(const TransArgs& a, int C2, int f32, hipStream_t s)
 #undef PGM_V
 #undef PGM_DISPATCH
 
-template <int C2, int PM, bool FX, bool F>
+template <int C2, int PM, bool FX, int K>
 static hipError_t launch_level_v(const LevelArgs& a, hipStream_t s)
 {
     const size_t bytes = a.lay.total;
-    hipLaunchKernelGGL((k_level<C2, PM, FX, F>), dim3(2 * a.b.npairs), dim3(LevelShape<PM, F>::threads), bytes, s, a);
+    hipLaunchKernelGGL((k_level<C2, PM, FX, K>), dim3(2 * a.b.npairs), dim3(LevelShape<PM, K == 1>::threads), bytes,
+                       s, a);
     return hipGetLastError();
 }
 
@@ -1438,22 +1487,24 @@ hipError_t level_allow_lds(size_t bytes)
         if (e != hipSuccess && first == hipSuccess) first = e;
     };
 #define PGM_LA(C2_, PM_, FX_)                                                                    \
-    allow((const void*)k_level<C2_, PM_, FX_, false>);                                           \
-    allow((const void*)k_level<C2_, PM_, FX_, true>);
+    allow((const void*)k_level<C2_, PM_, FX_, 0>);                                               \
+    allow((const void*)k_level<C2_, PM_, FX_, 1>);                                               \
+    allow((const void*)k_level<C2_, PM_, FX_, 2>);
     PGM_LA(6, 8, true) PGM_LA(6, 8, false) PGM_LA(6, 16, true) PGM_LA(6, 16, false)
     PGM_LA(2, 8, true) PGM_LA(2, 8, false) PGM_LA(2, 16, true) PGM_LA(2, 16, false)
 #undef PGM_LA
     return first;
 }
 
-hipError_t launch_level(const LevelArgs& a, int C2, int f32, hipStream_t s)
+hipError_t launch_level(const LevelArgs& a, int C2, int kind, hipStream_t s)
 {
     const int P = a.d[0].P;
     const int pmax = P <= 8 ? 8 : 16;
     const bool fixed = P == pmax;
 #define PGM_LV(C2_, PM_, FX_)                                                                    \
     if (C2 == C2_ && pmax == PM_ && fixed == FX_)                                                \
-        return f32 ? launch_level_v<C2_, PM_, FX_, true>(a, s) : launch_level_v<C2_, PM_, FX_, false>(a, s);
+        return kind == 1 ? launch_level_v<C2_, PM_, FX_, 1>(a, s)                                  \
+               : kind == 2 ? launch_level_v<C2_, PM_, FX_, 2>(a, s) : launch_level_v<C2_, PM_, FX_, 0>(a, s);
     PGM_LV(6, 8, true) PGM_LV(6, 8, false) PGM_LV(6, 16, true) PGM_LV(6, 16, false)
     PGM_LV(2, 8, true) PGM_LV(2, 8, false) PGM_LV(2, 16, true) PGM_LV(2, 16, false)
 #undef PGM_LV

@@ -105,7 +105,8 @@ def test_query_workspace_of_config2_is_modest():
                                  dict(levels=1, iters=[1], refine_rounds=1), dict(max_disp=-1),
                                  dict(min_region_px=-1), dict(min_region_px=9, region_link_px=0),
                                  dict(min_region_px=9, region_link_px=65536), dict(space_fwd=[3, 0, 0]),
-                                 dict(space_bwd=[0, -1, 0]), dict(color=1, space_fwd=[1, 0, 0])])
+                                 dict(space_bwd=[0, -1, 0]), dict(color=1, space_fwd=[1, 0, 0]),
+                                 dict(metric=2), dict(metric=-1), dict(metric=1, feature=1)])
 def test_query_rejects_invalid_parameters(bad):
     with pytest.raises(pgm.PGMError) as e:
         pgm.pgm_query(base_params(**bad), 64, 64)

@@ -135,6 +135,12 @@ CASES = {
     "spaces_shared_lab": (lambda: synth.rect_pair(23, 96, 128, dmax=10), base_params(levels=2, iters=[3, 3], max_disp=10, space_fwd=[2, 2], space_bwd=[2, 2], rng_seed=22)),
     "regions_dense": (lambda: synth.rect_pair(21, 72, 96, dmax=8), base_params(seed_stride=1, levels=2, iters=[3, 3], max_disp=8, min_region_px=9, region_link_px=12, rng_seed=16)),
     "regions_stride3": (lambda: synth.config_pair(1), base_params(min_region_px=81, region_link_px=1, rng_seed=17)),
+    # Eq. 3 as printed: squared differences, 64-bit sums (colour, 16-wide patches, signs,
+    # gray dense with the exhaustive start)
+    "ssd": (lambda: synth.config_pair(1), base_params(metric=1, rng_seed=23)),
+    "ssd_patch16_s3": (lambda: synth.config_pair(1), base_params(metric=1, patch_fwd=16, patch_bwd=13, sobel_ksize=3, rng_seed=24)),
+    "ssd_sign": (lambda: synth.config_pair(1), base_params(metric=1, feature=2, rng_seed=25)),
+    "ssd_gray_dense_exhaustive": (lambda: synth.rect_pair(24, 40, 56, dmax=5), base_params(metric=1, color=1, seed_stride=1, levels=2, iters=[3, 3], init_mode=1, max_disp=6, rng_seed=26)),
 }
 
 
