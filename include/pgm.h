@@ -236,16 +236,19 @@ PGM_API pgm_status pgm_dump_level(void* ctx, int32_t level, int32_t dir, int32_t
 PGM_API pgm_status pgm_dump_gradient(void* ctx, int32_t level, int32_t image, void* host_out);
 PGM_API pgm_status pgm_dump_pyramid(void* ctx, int32_t level, int32_t image, uint8_t* host_out);
 
-/* Per-kernel timing for measurement. While enabled, pgm_match records HIP events around
- * every kernel launch on the caller's stream and counts the distance evaluations of each
- * kernel kind. pgm_profile(ctx, 1) enables and clears the totals, pgm_profile(ctx, 0)
+/* Per-kernel timing for measurement. While enabled, pgm_match records HIP events on the
+ * caller's stream around every run of consecutive launches of one kernel kind (no event
+ * between the kernels of a run; its time includes the gaps between them) and counts the
+ * distance evaluations of each kernel kind. pgm_profile(ctx, 1) enables and clears the totals, pgm_profile(ctx, 0)
  * disables. pgm_profile_read waits for the last call's stream and returns, for one kind,
  * the number of launches, their summed duration in milliseconds and their summed distance
  * evaluations since the last clear. Kinds (PGM_K_PREP: the first launch of a call, which
  * draws the random numbers and builds the level-0 gradients and pyramid level 1;
  * PGM_K_PYRAMID: pyramid levels 2 and up; PGM_K_GRADIENT: gradients of levels 1 and up;
  * PGM_K_LEVEL: all sweeps of a level small enough for one work-group's LDS, whose distance
- * evaluations count under PGM_K_SWEEP; PGM_K_REGION: small-region removal): */
+ * evaluations count under PGM_K_SWEEP; PGM_K_OUTPUT: the
+ * matches of both directions and the compaction, so nothing is recorded under PGM_K_COMPACT;
+ * PGM_K_REGION: small-region removal): */
 enum { PGM_K_PYRAMID = 0, PGM_K_GRADIENT = 1, PGM_K_PREP = 2, PGM_K_INIT = 3, PGM_K_DOWN = 4,
        PGM_K_UP = 5, PGM_K_SWEEP = 6, PGM_K_CHECK = 7, PGM_K_OUTPUT = 8, PGM_K_COMPACT = 9,
        PGM_K_LEVEL = 10, PGM_K_REGION = 11, PGM_K_KINDS = 12 };

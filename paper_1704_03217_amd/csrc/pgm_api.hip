@@ -32,7 +32,6 @@ struct Layout {
     // (init, down, up, sweep), and the per-block inlier counts of the level-0 output
     size_t cnt[4] = {0, 0, 0, 0};
     long long cnt_cap[4] = {0, 0, 0, 0};
-    size_t blockcnt = 0;
     size_t cntpart = 0;
     size_t cclabel = 0, ccsize = 0;
     // the random-number table is shared by all pairs of a batch; everything else is per pair
@@ -54,6 +53,8 @@ long long dir_blocks(const pgm_params* p, int groups)
 }
 
 enum { ENTER_INIT = 0, ENTER_DOWN_F = 1, ENTER_DOWN_FO = 2, ENTER_UP_FO = 3 };
+// largest level (seeds x pairs) entered by one fused launch
+constexpr long long FUSE_MAX_SEEDS = 8192;
 
 size_t take(size_t& cur, size_t bytes)
 {
@@ -182,13 +183,14 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
         const int l = Y.st_level[k];
         const int kind = Y.st_enter[k] == ENTER_INIT ? CNT_INIT : Y.st_enter[k] == ENTER_UP_FO ? CNT_UP : CNT_DOWN;
         Y.cnt_cap[kind] += dir_blocks(p, Y.lnx[l] * Y.lny[l]);
+        if (kind == CNT_DOWN && l + 1 < Y.L)   // room for a launch that enters the level whole
+            Y.cnt_cap[kind] += 2LL * enter_blocks(Y.lnx[l], Y.lny[l], p->patch_fwd, Y.lnx[l + 1] * Y.lny[l + 1]);
         auto sb = [&](int P) { return (long long)sweep_blocks(Y.lnx[l], Y.lny[l], P); };
         const long long per_sweep = variant(p->patch_fwd) == variant(p->patch_bwd) ? 2 * sb(p->patch_fwd)
                                                                                    : sb(p->patch_fwd) + sb(p->patch_bwd);
         Y.cnt_cap[CNT_SWEEP] += 2LL * p->iters[l] * per_sweep;
     }
     for (int k = 0; k < 4; k++) Y.cnt[k] = take(cur, (size_t)Y.cnt_cap[k] * 4 + 4);
-    Y.blockcnt = take(cur, (size_t)((Y.lnx[0] * Y.lny[0] + 255) / 256) * 4);
     // partial evaluation sums of the count reduction: COUNT_SLICES x KINDS per pair
     Y.cntpart = take(cur, (size_t)COUNT_SLICES * CountArgs::KINDS * sizeof(unsigned long long));
     // region labels and sizes on the level-0 grid (small-region removal)
@@ -213,14 +215,15 @@ void fill_sizes(const Layout& Y, pgm_sizes* s)
 }
 
 // LDS layout of a whole-level sweep launch at level l, if it fits in lds_max bytes
-bool level_layout(const Layout& Y, int l, size_t lds_max, LevelLayout& o)
+bool level_layout(const Layout& Y, int l, int iters, int nI, size_t lds_max, LevelLayout& o)
 {
     const size_t n = (size_t)Y.lnx[l] * Y.lny[l];
     const size_t graw = (size_t)(Y.lw[l] + 2 * PAD) * (Y.lh[l] + 2 * PAD) * Y.C2 * Y.esize;
     o.gstride = (graw + 15) & ~(size_t)15;
     o.disp = 2 * o.gstride;
     o.dist = o.disp + n * 4;
-    o.total = (o.dist + n * Y.dsize + 15) & ~(size_t)15;
+    o.rnd = (o.dist + n * Y.dsize + 15) & ~(size_t)15;
+    o.total = (o.rnd + (size_t)iters * n * nI * sizeof(short2) + 15) & ~(size_t)15;
     return o.total + 64 <= lds_max;   // room for the kernel's static LDS
 }
 
@@ -246,8 +249,9 @@ struct pgm_ctx_s {
     unsigned long long* prof_evals = nullptr;     // PGM_K_KINDS device counters
     std::vector<hipEvent_t> events;               // pool, reused after each clear
     size_t next_event = 0;
-    struct Rec { int kind; hipEvent_t a, b; };
+    struct Rec { int kind; int n; hipEvent_t a, b; };   // n consecutive launches of one kind
     std::vector<Rec> recs;
+    bool run_open = false;   // recs.back() still waits for its end event
     // pgm_match_groups: internal streams (default priority), fork/join events, and the graph
     // of the last captured call with the bytes of its arguments
     static constexpr int NSTREAMS = 4;
@@ -444,17 +448,38 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         *ev = c->events[c->next_event++];
         return hipSuccess;
     };
+    // Profiling times runs of consecutive launches of one kind between two events, so that no
+    // event packet sits between the kernels of a run (a run's time includes the gaps between
+    // its kernels). A run left open by a failed call is dropped.
+    if (c->run_open) {
+        c->recs.pop_back();
+        c->run_open = false;
+    }
+    auto close_run = [&]() -> hipError_t {
+        if (!c->run_open) return hipSuccess;
+        c->run_open = false;
+        return hipEventRecord(c->recs.back().b, s);
+    };
     auto timed = [&](int kind, auto&& launch) -> hipError_t {
         c->nlaunch++;
         if (!c->prof) return launch();
+        if (c->run_open && c->recs.back().kind == kind) {
+            hipError_t e = launch();
+            if (e == hipSuccess) c->recs.back().n++;
+            return e;
+        }
+        hipError_t e = close_run();
         pgm_ctx_s::Rec r;
         r.kind = kind;
-        hipError_t e = event(&r.a);
+        r.n = 1;
+        if (e == hipSuccess) e = event(&r.a);
         if (e == hipSuccess) e = event(&r.b);
         if (e == hipSuccess) e = hipEventRecord(r.a, s);
         if (e == hipSuccess) e = launch();
-        if (e == hipSuccess) e = hipEventRecord(r.b, s);
-        if (e == hipSuccess) c->recs.push_back(r);
+        if (e == hipSuccess) {
+            c->recs.push_back(r);
+            c->run_open = true;
+        }
         return e;
     };
     // evaluation counts: each matching launch stores one count per work-group into its kind's
@@ -486,7 +511,6 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         ra.st[k].stage = k;
         ra.st[k].base = Y.st_base[k];
     }
-    ra.total_items = Y.rnd_items;
     ra.table = (short2*)(ws + Y.rnd);
     ra.init = (short2*)(ws + Y.rnd_init);
     const int m = Y.L - 1;
@@ -581,12 +605,52 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         return b;
     };
 
+    // Stages whose level is entered from the coarser one by a single launch (the coarser
+    // level's check, the transition and the first half-sweep): small levels, where the
+    // separate launches cost mostly their latency (the fused launch needs more registers per
+    // lane, which costs more than it saves once a level fills the chip); both directions
+    // share the kernels, patch sides are at most 8 (six-channel float features excepted:
+    // their three candidate patches do not fit the registers) and the level is swept with
+    // per-half-sweep launches.
+    const bool can_fuse = shared && std::max(p->patch_fwd, p->patch_bwd) <= 8 && !(Y.kind == 1 && Y.C2 == 6);
+    auto lds_level = [&](int k, LevelLayout& lay) {
+        const int l = Y.st_level[k];
+        return shared && p->iters[l] > 0 && level_layout(Y, l, p->iters[l], Y.st_nI[k], c->lds_max, lay);
+    };
+    auto fused = [&](int k) {
+        if (k <= 0 || k >= Y.nst) return false;
+        const int e = Y.st_enter[k];
+        LevelLayout lay;
+        const int l = Y.st_level[k];
+        return (e == ENTER_DOWN_F || e == ENTER_DOWN_FO) && can_fuse && p->iters[l] > 0 &&
+               (long long)Y.lnx[l] * Y.lny[l] * npairs <= FUSE_MAX_SEEDS && !lds_level(k, lay);
+    };
     int rec_valid[PGM_MAX_LEVELS] = {0};
+    int check_rec_valid = 0;   // rec_valid of the check deferred into the next stage's launch
     for (int k = 0; k < Y.nst; k++) {
         const int l = Y.st_level[k];
         const Geo g = geo(l);
         const int enter = Y.st_enter[k];
-        for (int pass = 0; pass < (shared ? 1 : 2); pass++) {
+        const bool fuse = fused(k);
+        if (fuse) {
+            EnterArgs ea;
+            memset(&ea, 0, sizeof ea);
+            for (int q = 0; q < 2; q++) {
+                ea.d[q] = dirargs(q, l, k);
+                ea.src[q] = field(q, l + 1);
+            }
+            ea.g = g;
+            ea.gs = geo(l + 1);
+            ea.b = batch(2);
+            ea.carry_record = enter != ENTER_DOWN_F;
+            ea.fwd_bwd = p->fwd_bwd;
+            ea.tau2 = p->consistency_px * p->consistency_px;
+            ea.rec_valid = check_rec_valid;
+            ea.nI = Y.st_nI[k];
+            ea.cnt = ctable(CNT_DOWN, 2LL * enter_blocks(g.nx, g.ny, ea.d[0].P, ea.gs.nx * ea.gs.ny));
+            PGM_HIP(c, timed(PGM_K_DOWN, [&] { return launch_enter(ea, Y.C2, Y.kind, s); }));
+        }
+        for (int pass = 0; pass < (fuse ? 0 : shared ? 1 : 2); pass++) {
             const int nd = shared ? 2 : 1;
             const int d0 = shared ? 0 : pass;
             if (enter == ENTER_INIT) {
@@ -624,7 +688,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         // Step 1 of a small level in one work-group per pair and direction, from LDS
         LevelArgs la;
         memset(&la, 0, sizeof la);
-        const bool in_lds = shared && p->iters[l] > 0 && level_layout(Y, l, c->lds_max, la.lay);
+        const bool in_lds = lds_level(k, la.lay);
         if (in_lds) {
             for (int q = 0; q < 2; q++) la.d[q] = dirargs(q, l, k);
             la.g = g;
@@ -638,7 +702,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         }
         // Step 1: iterations of propagation and limited random search, red then black
         for (int t = 0; t < (in_lds ? 0 : p->iters[l]); t++)
-            for (int colour = 0; colour < 2; colour++)
+            for (int colour = (fuse && t == 0) ? 1 : 0; colour < 2; colour++)
                 for (int pass = 0; pass < (shared ? 1 : 2); pass++) {
                     const int nd = shared ? 2 : 1;
                     const int d0 = shared ? 0 : pass;
@@ -663,7 +727,8 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         ca.tau2 = p->consistency_px * p->consistency_px;
         ca.rec_valid = enter == ENTER_DOWN_FO || enter == ENTER_UP_FO;
         rec_valid[l] = ca.rec_valid;
-        PGM_HIP(c, timed(PGM_K_CHECK, [&] { return launch_check(ca, s); }));
+        check_rec_valid = ca.rec_valid;
+        if (!fused(k + 1)) PGM_HIP(c, timed(PGM_K_CHECK, [&] { return launch_check(ca, s); }));
     }
 
     // small-region removal on the forward field at full resolution (Sec. III-E)
@@ -680,30 +745,20 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         PGM_HIP(c, timed(PGM_K_REGION, [&] { return launch_regions(ra2, s); }));
     }
 
-    // level-0 matches on the grid (Sec. III-G)
-    const bool compact = out_compact || out_n_inliers;
+    // level-0 matches on the grid and the compacted forward inliers (Sec. III-G)
     OutArgs oa;
     memset(&oa, 0, sizeof oa);
     oa.g = geo(0);
-    oa.b = batch(1);
-    oa.f = field(0, 0);
-    oa.out = out_fwd;
+    oa.b = batch(out_bwd ? 2 : 1);
+    oa.f[0] = field(0, 0);
+    oa.f[1] = field(1, 0);
+    oa.out[0] = out_fwd;
+    oa.out[1] = out_bwd;
+    oa.compact = out_compact;
+    oa.n_out = out_n_inliers;
     oa.dist8 = Y.dsize == 8;
-    oa.blockcnt = compact ? (uint32_t*)(pw0 + Y.blockcnt) : nullptr;
     PGM_HIP(c, timed(PGM_K_OUTPUT, [&] { return launch_output(oa, s); }));
-    if (out_bwd) {
-        OutArgs ob = oa;
-        ob.f = field(1, 0);
-        ob.out = out_bwd;
-        ob.blockcnt = nullptr;
-        PGM_HIP(c, timed(PGM_K_OUTPUT, [&] { return launch_output(ob, s); }));
-    }
-    if (compact) {
-        oa.dense = out_fwd;
-        oa.compact = out_compact;
-        oa.n_out = out_n_inliers;
-        PGM_HIP(c, timed(PGM_K_COMPACT, [&] { return launch_compact(oa, s); }));
-    }
+    PGM_HIP(c, close_run());
     if (counting) {
         CountArgs ca;
         const int kinds[4] = {PGM_K_INIT, PGM_K_DOWN, PGM_K_UP, PGM_K_SWEEP};
@@ -1204,6 +1259,7 @@ pgm_status pgm_profile(void* ctx, int32_t enable)
         PGM_HIP(c, hipDeviceSynchronize());
         PGM_HIP(c, hipMemset(c->prof_evals, 0, PGM_K_KINDS * sizeof(unsigned long long)));
         c->recs.clear();
+        c->run_open = false;
         c->next_event = 0;
     }
     c->prof = enable != 0;
@@ -1224,7 +1280,7 @@ pgm_status pgm_profile_read(void* ctx, int32_t kind, int64_t* host_launches, dou
         float t = 0.0f;
         PGM_HIP(c, hipEventElapsedTime(&t, r.a, r.b));
         ms += t;
-        n++;
+        n += r.n;
     }
     unsigned long long ev[PGM_K_KINDS];
     PGM_HIP(c, hipMemcpy(ev, c->prof_evals, sizeof ev, hipMemcpyDeviceToHost));

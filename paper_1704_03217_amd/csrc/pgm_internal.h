@@ -83,6 +83,20 @@ struct TransArgs {         // level-down (to the finer level) or level-up (to th
     uint32_t* cnt;
 };
 
+// Entering a finer level in one launch: the coarser level's check (Steps 2-3), the
+// transition (Steps 4-5) and the first half-sweep of Step 1 at the finer level.
+struct EnterArgs {
+    DirArgs d[2];          // the finer level being entered (both directions), pair 0
+    Field src[2];          // the coarser level (both directions), pair 0
+    Geo g, gs;             // geometry of the finer and of the coarser level
+    Batch b;
+    int carry_record;      // a child's record takes its parent's inlier flag (Eq. 8)
+    int fwd_bwd, tau2, rec_valid;   // the coarser level's check
+    int nI;                // random-search candidates of the half-sweep
+    int nb_col, nb_chk;    // work-groups per direction and pair: per colour, for the check
+    uint32_t* cnt;         // per-block evaluation counts, pair 0 (or null)
+};
+
 struct CheckArgs {
     Field f[2];
     Geo g;
@@ -90,9 +104,10 @@ struct CheckArgs {
     int fwd_bwd, tau2, rec_valid;
 };
 
-// LDS layout of a whole-level sweep launch (byte offsets; gstride: bytes per gradient image)
+// LDS layout of a whole-level sweep launch (byte offsets; gstride: bytes per gradient image;
+// rnd: the level's random-search offsets of one direction)
 struct LevelLayout {
-    size_t gstride, disp, dist, total;
+    size_t gstride, disp, dist, rnd, total;
 };
 struct LevelArgs {
     DirArgs d[2];          // both directions, pair 0 (in HBM)
@@ -106,13 +121,11 @@ struct LevelArgs {
 };
 
 struct OutArgs {
-    Field f;               // level-0 field of one direction, pair 0
+    Field f[2];            // level-0 fields (forward, backward), pair 0
+    pgm_match_t* out[2];   // pair z writes out[d] + z * nx * ny (out[1] used when ndir == 2)
     Geo g;
-    Batch b;
-    pgm_match_t* out;      // pair z writes out + z * nx * ny
-    uint32_t* blockcnt;    // per-block inlier counts, pair 0 (or null)
-    // compaction
-    const pgm_match_t* dense;
+    Batch b;               // b.ndir: 1 = forward only, 2 = both
+    // compaction of the forward inliers (both null: none)
     pgm_match_t* compact;  // pair z writes compact + z * nx * ny (or null)
     int32_t* n_out;        // pair z writes n_out[z] (or null)
     int dist8;             // the field's distances are uint64
@@ -121,16 +134,17 @@ struct OutArgs {
 struct RngStage {
     int n, iters, nI, W, level, stage;
     long long base;        // first short2 of the stage in the table
+    int bpt, b0;           // work-groups per (direction, iteration) and the stage's first one
 };
 
 struct RngArgs {
     RngStage st[MAX_STAGES];
     int nstages;
-    long long total_items; // sum over stages of 2 * n * iters * ceil(nI / 2)
     short2* table;
     short2* init;          // 2 * n_top initial displacements
     int n_top, R_top, top_level;
     uint32_t key0, key1;
+    int init_blocks;       // work-groups of the initial displacements (filled in by the launcher)
 };
 
 struct CountArgs {
@@ -198,6 +212,12 @@ hipError_t launch_sweep(const SweepArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_down(const TransArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_up(const TransArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);
+hipError_t launch_enter(EnterArgs a, int C2, int kind, hipStream_t s);
+// work-groups of one k_enter launch per direction and pair
+inline int enter_blocks(int nx, int ny, int P, int n_coarse)
+{
+    return 2 * sweep_blocks(nx, ny, P) + (n_coarse + 255) / 256;
+}
 // small-region removal on the level-0 forward field: four launches (labels, unions, region
 // sizes, flags)
 struct RegionArgs {
@@ -215,7 +235,6 @@ hipError_t launch_level(const LevelArgs& a, int C2, int kind, hipStream_t s);
 // let every whole-level kernel use up to `bytes` of dynamic LDS (once per context)
 hipError_t level_allow_lds(size_t bytes);
 hipError_t launch_output(const OutArgs& a, hipStream_t s);
-hipError_t launch_compact(const OutArgs& a, hipStream_t s);
 // part: pair 0's array of COUNT_SLICES * CountArgs::KINDS partial sums; pair z's array is at
 // the same offset of its own workspace slice (z * zs bytes further)
 constexpr int COUNT_SLICES = 16;

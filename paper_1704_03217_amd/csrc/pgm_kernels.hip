@@ -305,6 +305,30 @@ __device__ __forceinline__ void patch_cost2(const Row& A, const void* Gb, const 
     e1 = Row::template finish<LPS>(p1);
 }
 
+// Three patch distances with the reads of all three candidates in flight together.
+template <class Row, int LPS, bool BUF>
+__device__ __forceinline__ void patch_cost3(const Row& A, const void* Gb, const Geo& g, int P, int r, const int qx[3],
+                                            const int qy[3], typename Row::Dist e[3])
+{
+    const int half = P >> 1;
+    Row B0, B1, B2;
+    B0.template fetch<BUF>(Gb, g, qx[0] - half, qy[0] - half, P, r);
+    B1.template fetch<BUF>(Gb, g, qx[1] - half, qy[1] - half, P, r);
+    B2.template fetch<BUF>(Gb, g, qx[2] - half, qy[2] - half, P, r);
+    __builtin_amdgcn_sched_barrier(0);
+    typename Row::Acc p0 = A.sad(B0, P);
+    typename Row::Acc p1 = A.sad(B1, P);
+    typename Row::Acc p2 = A.sad(B2, P);
+    if (r >= P) {
+        p0 = typename Row::Acc(0);
+        p1 = typename Row::Acc(0);
+        p2 = typename Row::Acc(0);
+    }
+    e[0] = Row::template finish<LPS>(p0);
+    e[1] = Row::template finish<LPS>(p1);
+    e[2] = Row::template finish<LPS>(p2);
+}
+
 template <bool BUF, class Row>
 __device__ __forceinline__ void load_own(Row& A, const void* Ga, const Geo& g, int P, int r, int px, int py)
 {
@@ -375,6 +399,73 @@ __device__ __forceinline__ void count_evals(uint32_t* cnt, int slot, uint32_t ne
 // Step 1 (Sec. III-B): one colour of one propagation + limited random search iteration
 // ---------------------------------------------------------------------------------------
 
+// Step 1 after the propagation members are priced: the decisions of Eq. 4 in order, then the
+// limited random search of Eq. 5 around the result (Psi = {F(p)} + {F(p) + floor(R_i W / 2^i)},
+// priced two at a time and decided in order). Returns the evaluations counted; lane 0 writes
+// the seed if it changed (or always, with store).
+template <class Row, int LPS, bool BUF>
+__device__ __forceinline__ uint32_t decide_and_search(const Row& A, const DirArgs& D, const Geo& g, int s, int px,
+                                                      int py, int r, const short2* R, int nI, short2 o0, short2 o1,
+                                                      uint32_t cur0, typename Row::Dist cd0, const uint32_t c[2],
+                                                      const bool ok[2], const typename Row::Dist e[2], bool store)
+{
+    using Dist = typename Row::Dist;
+    const int P = D.P;
+    const bool init0 = cur0 != UNINIT;
+    uint32_t nev = 0;
+    uint32_t cur = cur0;
+    Dist cd = cd0;
+    bool init = init0, changed = false;
+#pragma unroll
+    for (int m = 0; m < 2; m++) {
+        if (!ok[m] || (init && c[m] == cur)) continue;
+        nev++;
+        if (!init || e[m] < cd) { cur = c[m]; cd = e[m]; init = true; changed = true; }
+    }
+
+    // Eq. 5: Psi = {F(p)} + {F(p) + floor(R_i W / 2^i)}, all around the propagated match,
+    // priced two at a time in the same way and decided in order
+    if (init) {
+        const int cx = d_x(cur), cy = d_y(cur);
+        const uint32_t curp = cur;
+        const Dist cdp = cd;
+        for (int ii = 0; ii < nI; ii += 2) {
+            if (ii > 0) {
+                o0 = R[ii];
+                if (ii + 1 < nI) o1 = R[ii + 1];
+            }
+            const bool two = ii + 1 < nI;
+            const uint32_t r0 = target(px, py, cx + o0.x, cy + o0.y, g);
+            const uint32_t r1 = two ? target(px, py, cx + o1.x, cy + o1.y, g) : curp;
+            const bool n0 = r0 != curp;
+            const bool n1 = r1 != curp && r1 != r0;
+            Dist f0 = cdp, f1 = cdp;
+            if (n0 || n1) {
+                const uint32_t qa = n0 ? r0 : r1, qb = n1 ? r1 : r0;
+                Dist ea, eb;
+                patch_cost2<Row, LPS, BUF>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb),
+                                      ea, eb);
+                if (n0) f0 = ea;
+                if (n1) f1 = eb;
+            }
+            if (two && !n1 && r1 != curp) f1 = f0;
+            if (r0 != cur) {
+                nev++;
+                if (f0 < cd) { cur = r0; cd = f0; changed = true; }
+            }
+            if (two && r1 != cur) {
+                nev++;
+                if (f1 < cd) { cur = r1; cd = f1; changed = true; }
+            }
+        }
+    }
+    if ((changed || store) && r == 0) {
+        D.f.disp[s] = cur;
+        ((Dist*)D.f.dist)[s] = cd;
+    }
+    return nev;
+}
+
 // One seed's half-sweep step (Step 1): propagation (Eq. 4) then limited random search
 // (Eq. 5) for seed (i, j) of field D at iteration t; returns the distance evaluations made.
 // The group's lanes all call it for the same seed; lane 0 writes the result.
@@ -434,57 +525,7 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
         if (need1) e[1] = eb;
     }
     if (ok[1] && !need1 && !(init0 && c[1] == cur0)) e[1] = e[0];
-    uint32_t cur = cur0;
-    Dist cd = cd0;
-    bool init = init0, changed = false;
-#pragma unroll
-    for (int m = 0; m < 2; m++) {
-        if (!ok[m] || (init && c[m] == cur)) continue;
-        nev++;
-        if (!init || e[m] < cd) { cur = c[m]; cd = e[m]; init = true; changed = true; }
-    }
-
-    // Eq. 5: Psi = {F(p)} + {F(p) + floor(R_i W / 2^i)}, all around the propagated match,
-    // priced two at a time in the same way and decided in order
-    if (init) {
-        const int cx = d_x(cur), cy = d_y(cur);
-        const uint32_t curp = cur;
-        const Dist cdp = cd;
-        for (int ii = 0; ii < nI; ii += 2) {
-            if (ii > 0) {
-                o0 = R[ii];
-                if (ii + 1 < nI) o1 = R[ii + 1];
-            }
-            const bool two = ii + 1 < nI;
-            const uint32_t r0 = target(px, py, cx + o0.x, cy + o0.y, g);
-            const uint32_t r1 = two ? target(px, py, cx + o1.x, cy + o1.y, g) : curp;
-            const bool n0 = r0 != curp;
-            const bool n1 = r1 != curp && r1 != r0;
-            Dist f0 = cdp, f1 = cdp;
-            if (n0 || n1) {
-                const uint32_t qa = n0 ? r0 : r1, qb = n1 ? r1 : r0;
-                Dist ea, eb;
-                patch_cost2<Row, LPS, BUF>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb),
-                                      ea, eb);
-                if (n0) f0 = ea;
-                if (n1) f1 = eb;
-            }
-            if (two && !n1 && r1 != curp) f1 = f0;
-            if (r0 != cur) {
-                nev++;
-                if (f0 < cd) { cur = r0; cd = f0; changed = true; }
-            }
-            if (two && r1 != cur) {
-                nev++;
-                if (f1 < cd) { cur = r1; cd = f1; changed = true; }
-            }
-        }
-    }
-    if (changed && r == 0) {
-        D.f.disp[s] = cur;
-        dist[s] = cd;
-    }
-    return nev;
+    return nev + decide_and_search<Row, LPS, BUF>(A, D, g, s, px, py, r, R, nI, o0, o1, cur0, cd0, c, ok, e, false);
 }
 
 // one half-sweep (Step 1, one colour of one iteration) of every seed of the launch
@@ -510,7 +551,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 }
 
 // ---------------------------------------------------------------------------------------
-// initial field at the coarsest level: random displacement in [-R, R]^2 (drawn by k_rng) or
+// initial field at the coarsest level: random displacement in [-R, R]^2 (drawn in k_prep) or
 // the exact best displacement in that window (dy outer, dx inner, strictly smaller wins)
 // ---------------------------------------------------------------------------------------
 
@@ -676,24 +717,39 @@ __global__ __launch_bounds__(256) void k_up(TransArgs a)
 // Step 2-3: forward-backward consistency check and the record update of Eq. 7
 // ---------------------------------------------------------------------------------------
 
-// Steps 2-3 for seed s of field F against the opposite field O
-__device__ __forceinline__ void check_seed(const Field& F, const Field& O, const Geo& g, int s, int fwd_bwd, int tau2,
-                                           int rec_valid)
+// Steps 2-3 (Sec. III-C, Eq. 7) for seed s of field F, whose displacement is d and flags fl,
+// against the opposite field O: the backward match consulted is the one at the opposite seed
+// nearest to p + d; consistent iff the two displacements cancel within tau. Returns whether
+// the seed is an inlier after the record update. (The opposite displacement is read only
+// when it is needed.)
+__device__ __forceinline__ int check_partner(const Geo& g, int s, uint32_t d)
 {
-    const uint32_t d = F.disp[s];
+    const int i = s % g.nx, j = s / g.nx;
+    const int qx = grid_pos(i, g.w, g) + d_x(d), qy = grid_pos(j, g.h, g) + d_y(d);
+    return grid_near(qy, g.ny, g) * g.nx + grid_near(qx, g.nx, g);
+}
+__device__ __forceinline__ bool check_inlier(const Field& O, const Geo& g, int s, uint32_t d, uint8_t fl, int fwd_bwd,
+                                             int tau2, int rec_valid)
+{
     bool ok = d != UNINIT;
     if (ok && fwd_bwd) {
-        const int i = s % g.nx, j = s / g.nx;
-        const int qx = grid_pos(i, g.w, g) + d_x(d), qy = grid_pos(j, g.h, g) + d_y(d);
-        const uint32_t od = O.disp[grid_near(qy, g.ny, g) * g.nx + grid_near(qx, g.nx, g)];
+        const uint32_t od = O.disp[check_partner(g, s, d)];
         if (od == UNINIT) ok = false;
         else {
             const int ex = d_x(d) + d_x(od), ey = d_y(d) + d_y(od);
             ok = ex * ex + ey * ey <= tau2;
         }
     }
+    return rec_valid ? (ok && (fl & ST_REC)) : ok;
+}
+
+// Steps 2-3 for seed s of field F against the opposite field O, written to its flags
+__device__ __forceinline__ void check_seed(const Field& F, const Field& O, const Geo& g, int s, int fwd_bwd, int tau2,
+                                           int rec_valid)
+{
+    const uint32_t d = F.disp[s];
     const uint8_t fl = F.flags[s];
-    const bool inl = rec_valid ? (ok && (fl & ST_REC)) : ok;
+    const bool inl = check_inlier(O, g, s, d, fl, fwd_bwd, tau2, rec_valid);
     F.flags[s] = (uint8_t)((fl & ST_REC) | (inl ? ST_INL : 0));
 }
 
@@ -709,11 +765,150 @@ __global__ __launch_bounds__(256) void k_check(CheckArgs a)
 }
 
 // ---------------------------------------------------------------------------------------
+// Entering a finer level in one launch. The results equal those of the coarser level's check
+// (Steps 2-3), the transition of Eq. 6 and 8 (Steps 4-5) and the first half-sweep of Step 1
+// launched one after the other. Per direction and pair the work-groups cover: the seeds of
+// the first colour, each of which derives its own start and the starts of the two neighbours
+// it propagates from (t = 0) from their parents' checks and then takes its step; the seeds of
+// the second colour, which take their start; and the coarser seeds, whose check is written
+// to their flags. A start depends only on the parent's state, so no seed waits for another.
+// ---------------------------------------------------------------------------------------
+
+template <class Row, int LPS>
+__device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs& D, const Field& S, const Field& O,
+                                               int i, int j, bool first, int r)
+{
+    using Dist = typename Row::Dist;
+    const Geo& g = a.g;
+    const Geo& gs = a.gs;
+    const int s = j * g.nx + i;
+    const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
+    const int P = D.P;
+    Row A;
+    load_own<true>(A, D.Ga, g, P, r, px, py);
+    // m = 0: this seed; m = 1, 2: the neighbours (i - 1, j) and (i, j - 1) that the step at
+    // t = 0 propagates from (the first of the Delta orders of Eq. 4)
+    int qx[3], qy[3], ps[3];
+    bool on[3];
+    uint32_t pd[3];
+    uint8_t pf[3];
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+        const int ni = m == 1 ? i - 1 : i, nj = m == 2 ? j - 1 : j;
+        on[m] = m == 0 || (first && ni >= 0 && nj >= 0);
+        qx[m] = grid_pos(max(ni, 0), g.w, g);
+        qy[m] = grid_pos(max(nj, 0), g.h, g);
+        ps[m] = grid_near(qy[m] >> 1, gs.ny, gs) * gs.nx + grid_near(qx[m] >> 1, gs.nx, gs);
+        pd[m] = S.disp[ps[m]];
+        pf[m] = S.flags[ps[m]];
+    }
+    const short2* R = D.rnd + (size_t)s * a.nI;   // offsets of the step at t = 0
+    const short2 o0 = R[0], o1 = R[a.nI > 1 ? 1 : 0];
+    __builtin_amdgcn_sched_barrier(0);
+    // the parents' checks (Steps 2-3 at the coarser level) and the starts of Eq. 6
+    uint32_t st[3];
+    bool inl[3];
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+        inl[m] = on[m] && check_inlier(O, gs, ps[m], pd[m], pf[m], a.fwd_bwd, a.tau2, a.rec_valid);
+        st[m] = inl[m] ? target(qx[m], qy[m], 2 * d_x(pd[m]), 2 * d_y(pd[m]), g) : UNINIT;
+    }
+    const uint32_t cur0 = st[0];
+    const bool init0 = cur0 != UNINIT;
+    if (r == 0) D.f.flags[s] = (a.carry_record && inl[0]) ? ST_REC : 0;
+    uint32_t nev = init0 ? 1u : 0u;
+    if (!first) {
+        Dist d0 = NO_DIST;
+        if (init0) d0 = patch_cost<Row, LPS, true>(A, D.Gb, g, P, r, px + d_x(cur0), py + d_y(cur0));
+        if (r == 0) {
+            D.f.disp[s] = cur0;
+            ((Dist*)D.f.dist)[s] = d0;
+        }
+        return nev;
+    }
+    // the step at t = 0, as in sweep_seed, from the starts just derived: this seed's start and
+    // the new propagation members are priced in one round trip
+    uint32_t c[2];
+    bool ok[2];
+#pragma unroll
+    for (int m = 0; m < 2; m++) {
+        ok[m] = st[m + 1] != UNINIT;
+        c[m] = ok[m] ? target(px, py, d_x(st[m + 1]), d_y(st[m + 1]), g) : cur0;
+    }
+    const bool need0 = ok[0] && !(init0 && c[0] == cur0);
+    const bool need1 = ok[1] && !(init0 && c[1] == cur0) && !(ok[0] && c[1] == c[0]);
+    Dist cd0 = NO_DIST;
+    Dist e[2];
+    if (init0 || need0 || need1) {
+        const uint32_t q0 = init0 ? cur0 : (need0 ? c[0] : c[1]);
+        const uint32_t qa = need0 ? c[0] : (need1 ? c[1] : q0), qb = need1 ? c[1] : qa;
+        int tx[3] = {px + d_x(q0), px + d_x(qa), px + d_x(qb)};
+        int ty[3] = {py + d_y(q0), py + d_y(qa), py + d_y(qb)};
+        Dist pe[3];
+        patch_cost3<Row, LPS, true>(A, D.Gb, g, P, r, tx, ty, pe);
+        if (init0) cd0 = pe[0];
+        e[0] = need0 ? pe[1] : cd0;
+        e[1] = need1 ? pe[2] : cd0;
+    } else {
+        e[0] = cd0;
+        e[1] = cd0;
+    }
+    if (ok[1] && !need1 && !(init0 && c[1] == cur0)) e[1] = e[0];
+    return nev + decide_and_search<Row, LPS, true>(A, D, g, s, px, py, r, R, a.nI, o0, o1, cur0, cd0, c, ok, e, true);
+}
+
+template <int C2, int PMAX, bool FIXED, int KIND>
+__global__ __launch_bounds__(256) void k_enter(EnterArgs a)
+{
+    using Row = RowT<C2, PMAX, FIXED, KIND>;
+    constexpr int LPS = PMAX;
+    constexpr int GPB = 256 / LPS;
+    const int nbx = 2 * a.nb_col + a.nb_chk;
+    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
+    const Field S = pair_field(a.src[lb.dir], zo);       // the coarser field of this direction
+    const Field O = pair_field(a.src[1 - lb.dir], zo);   // and of the opposite direction
+    uint32_t nev = 0;
+    bool leader = false;
+    if (lb.x >= 2 * a.nb_col) {
+        // the coarser level's check, one seed per thread
+        const int ps = (lb.x - 2 * a.nb_col) * 256 + threadIdx.x;
+        if (ps < a.gs.nx * a.gs.ny) check_seed(S, O, a.gs, ps, a.fwd_bwd, a.tau2, a.rec_valid);
+    } else {
+        const DirArgs D = pair_dir(a.d[lb.dir], zo);
+        const int colour = lb.x >= a.nb_col ? 1 : 0;
+        const int r = threadIdx.x % LPS;
+        const int gid = (lb.x - colour * a.nb_col) * GPB + threadIdx.x / LPS;
+        const int hx = (a.g.nx + 1) >> 1;
+        const int j = gid / hx;
+        const int i = 2 * (gid - j * hx) + ((colour + j) & 1);
+        leader = r == 0;
+        if (j < a.g.ny && i < a.g.nx) nev = enter_seed<Row, LPS>(a, D, S, O, i, j, colour == 0, r);
+    }
+    count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, leader);
+}
+
+// ---------------------------------------------------------------------------------------
 // Step 1 of a small level in one work-group per pair and direction: both gradient images and
 // the field are copied into LDS, every half-sweep runs between work-group barriers and the
 // field goes back to HBM (Steps 2-3 follow in k_check). The seeds and their decisions are
 // those of k_sweep; only the memory they live in differs.
 // ---------------------------------------------------------------------------------------
+
+// dst[q] = src[q] for q < n by the NT threads of the work-group, U loads in flight per thread
+template <int NT, int U, class T>
+__device__ __forceinline__ void copy_in(T* dst, const T* src, int n)
+{
+    for (int q0 = threadIdx.x; q0 < n; q0 += U * NT) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (q0 + u * NT < n) v[u] = src[q0 + u * NT];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (q0 + u * NT < n) dst[q0 + u * NT] = v[u];
+    }
+}
 
 template <int PMAX, bool F32>
 struct LevelShape {
@@ -742,19 +937,16 @@ __global__ __launch_bounds__((LevelShape<PMAX, KIND == 1>::threads)) void k_leve
     using Dist = typename Row::Dist;
     Dist* dist = (Dist*)(lds + Y.dist);
     Dist* const hdist = (Dist*)H.f.dist;
-    // copy in: both padded gradient images (16-byte pieces) and the field
+    short2* rnd = (short2*)(lds + Y.rnd);
+    // copy in: both padded gradient images (16-byte pieces), the field and the level's
+    // random-search offsets, several loads in flight per thread
     {
-        const uint4* sa = (const uint4*)((const uint8_t*)H.Ga - a.gorig);
-        const uint4* sb = (const uint4*)((const uint8_t*)H.Gb - a.gorig);
         const int nq = (int)(a.gbytes / 16);   // gbytes is rounded up to 16 inside the 256-aligned image
-        for (int q = threadIdx.x; q < nq; q += NT) {
-            ((uint4*)GA)[q] = sa[q];
-            ((uint4*)GB)[q] = sb[q];
-        }
-        for (int q = threadIdx.x; q < n; q += NT) {
-            disp[q] = H.f.disp[q];
-            dist[q] = hdist[q];
-        }
+        copy_in<NT, 4>((uint4*)GA, (const uint4*)((const uint8_t*)H.Ga - a.gorig), nq);
+        copy_in<NT, 4>((uint4*)GB, (const uint4*)((const uint8_t*)H.Gb - a.gorig), nq);
+        copy_in<NT, 2>(disp, (const uint32_t*)H.f.disp, n);
+        copy_in<NT, 2>(dist, (const Dist*)hdist, n);
+        copy_in<NT, 4>(rnd, H.rnd, a.iters * n * a.nI);
         if (threadIdx.x == 0) evsum = 0;
     }
     __syncthreads();
@@ -763,6 +955,7 @@ __global__ __launch_bounds__((LevelShape<PMAX, KIND == 1>::threads)) void k_leve
     L.Gb = GB + a.gorig;
     L.f.disp = disp;
     L.f.dist = dist;
+    L.rnd = rnd;
     L.f.flags = nullptr;   // not used by Step 1
     const int r = threadIdx.x % LPS;
     const int hx = (g.nx + 1) >> 1;
@@ -888,20 +1081,26 @@ __global__ __launch_bounds__(256) void k_cc_apply(RegionArgs a)
 // output on the level-0 grid and the compaction of forward inliers (Sec. III-G)
 // ---------------------------------------------------------------------------------------
 
+// Block x of direction y writes the matches of seeds [256 x, 256 x + 256). With compaction,
+// a forward block also places its inliers, in seed order, after those of the blocks before
+// it: it counts them from the flags itself (no pass between blocks) and ranks its own with
+// wave ballots; the last block writes the total.
 __global__ __launch_bounds__(256) void k_output(OutArgs a)
 {
+    __shared__ uint32_t part[4], wtot[4];
     const Geo& g = a.g;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = g.nx * g.ny;
+    const int dir = blockIdx.y;
     const size_t zo = (size_t)blockIdx.z * (size_t)a.b.zs;
-    const Field f = pair_field(a.f, zo);
-    pgm_match_t* out = a.out + (size_t)blockIdx.z * n;
+    const Field f = pair_field(a.f[dir], zo);
+    pgm_match_t* out = a.out[dir] + (size_t)blockIdx.z * n;
     bool inl = false;
+    pgm_match_t m;
     if (s < n) {
         const int i = s % g.nx, j = s / g.nx;
         const uint32_t d = f.disp[s];
         const uint8_t fl = f.flags[s];
-        pgm_match_t m;
         m.x1 = grid_pos(i, g.w, g);
         m.y1 = grid_pos(j, g.h, g);
         const bool init = d != UNINIT;
@@ -915,30 +1114,18 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a)
         out[s] = m;
         inl = (fl & ST_INL) != 0;
     }
-    if (a.blockcnt) {   // uniform over the launch
-        const int c = __syncthreads_count(inl);
-        if (threadIdx.x == 0) zoff(a.blockcnt, zo)[blockIdx.x] = (uint32_t)c;
-    }
-}
-
-// Stable compaction of the forward inliers: block b owns the same 256 seeds as block b of
-// k_output, starts at the sum of the inlier counts of the blocks before it and ranks its
-// inliers with wave ballots.
-__global__ __launch_bounds__(256) void k_compact(OutArgs a)
-{
-    __shared__ uint32_t part[4], wtot[4];
-    const int n = a.g.nx * a.g.ny;
-    const size_t zo = (size_t)blockIdx.z * (size_t)a.b.zs;
-    const uint32_t* blockcnt = zoff(a.blockcnt, zo);
-    const pgm_match_t* dense = a.dense + (size_t)blockIdx.z * n;
-    pgm_match_t* out = a.compact ? a.compact + (size_t)blockIdx.z * n : nullptr;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (dir != 0 || (!a.compact && !a.n_out)) return;   // uniform over the block
+    // inliers before this block: the flags of its 256 x seeds, 16 per load (256-aligned array)
+    const uint4* fl4 = (const uint4*)f.flags;
     uint32_t v = 0;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) v += blockcnt[b];
+    for (int q = threadIdx.x; q < (int)blockIdx.x * 16; q += 256) {
+        const uint4 w = fl4[q];
+        v += __popc(w.x & 0x02020202u) + __popc(w.y & 0x02020202u) + __popc(w.z & 0x02020202u) +
+             __popc(w.w & 0x02020202u);
+    }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    const bool inl = s < n && (dense[s].flags & PGM_FLAG_INLIER);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long mask = __ballot(inl);
     if (lane == 0) { part[wv] = v; wtot[wv] = (uint32_t)__popcll(mask); }
     __syncthreads();
@@ -946,7 +1133,7 @@ __global__ __launch_bounds__(256) void k_compact(OutArgs a)
     uint32_t before = 0;
     for (int k = 0; k < wv; k++) before += wtot[k];
     const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-    if (inl && out) out[prefix + before + rank] = dense[s];
+    if (inl && a.compact) a.compact[(size_t)blockIdx.z * n + prefix + before + rank] = m;
     if (a.n_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
         a.n_out[blockIdx.z] = (int32_t)(prefix + wtot[0] + wtot[1] + wtot[2] + wtot[3]);
 }
@@ -1023,9 +1210,21 @@ __device__ __forceinline__ void pyr_tile(const PyrArgs& a, int t, int z, uint32_
     const uint8_t* src = a.src[z & 1] + pair * (size_t)a.src_zs;
     uint8_t* dst = a.dst[z & 1] + pair * (size_t)a.dst_zs;
     const int xlo = 2 * X0 - 2, ylo = 2 * Y0 - 2;
-    for (int e = threadIdx.x; e < PY_SU * PY_SV; e += 256) {
-        const int v = e / PY_SU, u = e - v * PY_SU;
-        S[e] = rgb_at(src, a.pitch, mirror_fast(xlo + u, w), mirror_fast(ylo + v, h));
+    constexpr int SPT = (PY_SU * PY_SV + 255) / 256;   // loads in flight per thread
+    uint32_t raw[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; k++) {
+        const int e = threadIdx.x + 256 * k;
+        raw[k] = 0;
+        if (e < PY_SU * PY_SV) {
+            const int v = e / PY_SU, u = e - v * PY_SU;
+            raw[k] = rgb_at(src, a.pitch, mirror_fast(xlo + u, w), mirror_fast(ylo + v, h));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < SPT; k++) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < PY_SU * PY_SV) S[e] = raw[k];
     }
     __syncthreads();
     const int tap[5] = {1, 4, 6, 4, 1};
@@ -1146,7 +1345,8 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
     constexpr int C2 = 2 * CH;
     constexpr int K = KS / 2;
     uint32_t* S = lds;                          // [NV][GR_SU] staged pixels
-    int* H = (int*)(lds + GR_SV * GR_SU);       // [NV][GR_TW][C2]: row smoothing, row derivative
+    int* H = (int*)(lds + GR_SV * GR_SU);       // [C2][GR_SV][GR_TW]: row smoothing, row derivative
+                                                // (planes: consecutive lanes, consecutive banks)
     const int w = L.w, h = L.h;
     const int pw = w + 2 * PAD, ph = h + 2 * PAD;
     const int X0 = (t % L.tx) * GR_TW, Y0 = (t / L.tx) * GR_TH;
@@ -1162,19 +1362,32 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
         lin[threadIdx.x] = srgb_linear((int)threadIdx.x);
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < NU * NV; e += 256) {
-        const int v = e / NU, u = e - v * NU;
-        const int x = mirror_fast(cx0 - K + u, w), y = mirror_fast(cy0 - K + v, h);
-        uint32_t val;
-        if (GRAY) {
-            const uint8_t* p = img + (size_t)y * L.pitch + 3 * (size_t)x;
-            val = (uint32_t)((77 * p[0] + 150 * p[1] + 29 * p[2] + 128) >> 8);
-        } else {
-            val = rgb_at(img, L.pitch, x, y);
-            if (L.space == PGM_SPACE_YCRCB) val = to_ycrcb(val);
-            else if (L.space == PGM_SPACE_LAB) val = to_lab(val, lin);
+    // every load of the staging is issued before the first conversion
+    constexpr int SPT = (GR_SU * GR_SV + 255) / 256;
+    uint32_t raw[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; k++) {
+        const int e = threadIdx.x + 256 * k;
+        raw[k] = 0;
+        if (e < NU * NV) {
+            const int v = e / NU, u = e - v * NU;
+            raw[k] = rgb_at(img, L.pitch, mirror_fast(cx0 - K + u, w), mirror_fast(cy0 - K + v, h));
         }
-        S[v * GR_SU + u] = val;
+    }
+#pragma unroll
+    for (int k = 0; k < SPT; k++) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < NU * NV) {
+            const int v = e / NU, u = e - v * NU;
+            uint32_t val = raw[k];
+            if (GRAY) {
+                val = (77 * (val & 0xFFu) + 150 * ((val >> 8) & 0xFFu) + 29 * ((val >> 16) & 0xFFu) + 128) >> 8;
+            } else {
+                if (L.space == PGM_SPACE_YCRCB) val = to_ycrcb(val);
+                else if (L.space == PGM_SPACE_LAB) val = to_lab(val, lin);
+            }
+            S[v * GR_SU + u] = val;
+        }
     }
     __syncthreads();
     // smoothing and derivative taps of the size-KS Sobel operator
@@ -1198,9 +1411,12 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
                 rd[c] += dv * val;
             }
         }
-        int* o = H + (v * GR_TW + u) * C2;
+        int* o = H + v * GR_TW + u;
 #pragma unroll
-        for (int c = 0; c < CH; c++) { o[c] = rs[c]; o[CH + c] = rd[c]; }
+        for (int c = 0; c < CH; c++) {
+            o[c * (GR_SV * GR_TW)] = rs[c];
+            o[(CH + c) * (GR_SV * GR_TW)] = rd[c];
+        }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < GR_TW * GR_TH; e += 256) {
@@ -1213,11 +1429,14 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
         for (int c = 0; c < CH; c++) { gx[c] = 0; gy[c] = 0; }
 #pragma unroll
         for (int i = 0; i < KS; i++) {
-            const int* q = H + ((v + i) * GR_TW + u) * C2;
+            const int* q = H + (v + i) * GR_TW + u;
             const int smi = KS == 3 ? sm3[i] : sm5[i];
             const int dvi = KS == 3 ? dv3[i] : dv5[i];
 #pragma unroll
-            for (int c = 0; c < CH; c++) { gx[c] += smi * q[CH + c]; gy[c] += dvi * q[c]; }
+            for (int c = 0; c < CH; c++) {
+                gx[c] += smi * q[(CH + c) * (GR_SV * GR_TW)];
+                gy[c] += dvi * q[c * (GR_SV * GR_TW)];
+            }
         }
         const size_t o = ((size_t)Y * pw + X) * C2;
         if (!F32) {
@@ -1262,47 +1481,37 @@ __device__ __forceinline__ int search_off(uint32_t u, int W, int i)
     return (int)(A >> (32 + i));
 }
 
-__device__ __forceinline__ void rng_item(const RngArgs& a, long long item)
+// Work-group b of the random numbers: the initial displacements first, then per stage one
+// range per (direction, iteration) in which thread x draws every search offset of seed
+// 256 c + x (one Philox block per two offsets).
+__device__ __forceinline__ void rng_block(const RngArgs& a, int b)
 {
-    if (item < 2LL * a.n_top) {
-        const int dir = (int)(item / a.n_top), s = (int)(item % a.n_top);
+    if (b < a.init_blocks) {
+        const int item = b * 256 + (int)threadIdx.x;
+        if (item >= 2 * a.n_top) return;
+        const int dir = item / a.n_top, s = item - dir * a.n_top;
         const uint4 u = philox4x32_10(
             make_uint4((uint32_t)s, ((uint32_t)a.top_level << 8) | ((uint32_t)dir << 16), 0u, 0u), a.key0, a.key1);
         const uint32_t span = 2u * (uint32_t)a.R_top + 1u;
         a.init[item] = make_short2((short)((int)__umulhi(u.x, span) - a.R_top), (short)((int)__umulhi(u.y, span) - a.R_top));
         return;
     }
-    item -= 2LL * a.n_top;
-    for (int k = 0; k < a.nstages; k++) {
-        const RngStage& S = a.st[k];
-        const int nB = (S.nI + 1) >> 1;
-        const long long cnt = 2LL * S.n * S.iters * nB;
-        if (item >= cnt) { item -= cnt; continue; }
-        int b, s, t, dir;
-        if (cnt <= 0x7FFFFFFFLL) {   // 32-bit index arithmetic (64-bit division is slow)
-            uint32_t it = (uint32_t)item;
-            b = (int)(it % (uint32_t)nB);
-            it /= (uint32_t)nB;
-            s = (int)(it % (uint32_t)S.n);
-            it /= (uint32_t)S.n;
-            t = (int)(it % (uint32_t)S.iters);
-            dir = (int)(it / (uint32_t)S.iters);
-        } else {
-            b = (int)(item % nB);
-            long long rest = item / nB;
-            s = (int)(rest % S.n);
-            rest /= S.n;
-            t = (int)(rest % S.iters);
-            dir = (int)(rest / S.iters);
-        }
-        const uint32_t w1 = (uint32_t)t | ((uint32_t)S.level << 8) | ((uint32_t)dir << 16) | (1u << 24);
-        const uint4 u = philox4x32_10(make_uint4((uint32_t)s, w1, (uint32_t)b, (uint32_t)S.stage), a.key0, a.key1);
-        short2* out = a.table + S.base + (((long long)dir * S.iters + t) * S.n + s) * S.nI;
-        const int i0 = 2 * b;
+    b -= a.init_blocks;
+    int k = 0;
+    while (k + 1 < a.nstages && b >= a.st[k + 1].b0) k++;
+    const RngStage& S = a.st[k];
+    const int local = b - S.b0;
+    const int q = local / S.bpt, chunk = local - q * S.bpt;
+    const int dir = q / S.iters, t = q - dir * S.iters;
+    const int s = chunk * 256 + (int)threadIdx.x;
+    if (s >= S.n) return;
+    const uint32_t w1 = (uint32_t)t | ((uint32_t)S.level << 8) | ((uint32_t)dir << 16) | (1u << 24);
+    short2* out = a.table + S.base + (((long long)dir * S.iters + t) * S.n + s) * S.nI;
+    for (int i0 = 0; i0 < S.nI; i0 += 2) {
+        const uint4 u = philox4x32_10(make_uint4((uint32_t)s, w1, (uint32_t)(i0 >> 1), (uint32_t)S.stage), a.key0, a.key1);
         out[i0] = make_short2((short)search_off(u.x, S.W, i0), (short)search_off(u.y, S.W, i0));
         if (i0 + 1 < S.nI)
             out[i0 + 1] = make_short2((short)search_off(u.z, S.W, i0 + 1), (short)search_off(u.w, S.W, i0 + 1));
-        return;
     }
 }
 
@@ -1322,7 +1531,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
     __shared__ double lin[256];
     int b = blockIdx.x;
     if (b < a.rng_blocks) {
-        rng_item(a.rng, (long long)b * 256 + threadIdx.x);
+        rng_block(a.rng, b);
         return;
     }
     b -= a.rng_blocks;
@@ -1404,9 +1613,16 @@ hipError_t launch_gradient(GradArgs a, int npairs, int gray, int ksize, int feat
 
 hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hipStream_t s)
 {
-    const long long items = 2LL * a.rng.n_top + a.rng.total_items;
-    if ((items + 255) / 256 > 0x40000000LL) return hipErrorInvalidValue;
-    a.rng_blocks = (int)((items + 255) / 256);
+    RngArgs& r = a.rng;
+    r.init_blocks = (int)((2LL * r.n_top + 255) / 256);
+    long long nb = 0;
+    for (int k = 0; k < r.nstages; k++) {
+        r.st[k].bpt = (r.st[k].n + 255) / 256;
+        r.st[k].b0 = (int)nb;
+        nb += 2LL * r.st[k].iters * r.st[k].bpt;
+        if (nb > 0x40000000LL) return hipErrorInvalidValue;
+    }
+    a.rng_blocks = r.init_blocks + (int)nb;
     a.grad_tiles = plan_grad(a.grad);
     a.grad_blocks = a.grad_tiles * 2 * npairs;
     if (a.with_pyr) plan_pyr(a.pyr);
@@ -1465,6 +1681,21 @@ hipError_t launch_down(const TransArgs& a, int C2, int kind, hipStream_t s)
 hipError_t launch_up(const TransArgs& a, int C2, int kind, hipStream_t s)
 {
     PGM_DISPATCH(k_up, a, a.g.nx * a.g.ny);
+}
+
+hipError_t launch_enter(EnterArgs a, int C2, int kind, hipStream_t s)
+{
+    const int P = a.d[0].P;
+    a.nb_col = sweep_blocks(a.g.nx, a.g.ny, P);
+    a.nb_chk = (a.gs.nx * a.gs.ny + 255) / 256;
+    const int pmax = P <= 8 ? 8 : 16;
+    const bool fixed = P == pmax;
+    const long long nb = (long long)(2 * a.nb_col + a.nb_chk) * a.b.ndir * a.b.npairs;
+    if (nb > 0x7FFFFFFFLL || a.b.ndir != 2) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nb);
+    // patch sides up to 8 only: three candidate patches of 16 rows do not fit the registers
+    PGM_V(k_enter, 6, 8, true) PGM_V(k_enter, 6, 8, false) PGM_V(k_enter, 2, 8, true) PGM_V(k_enter, 2, 8, false)
+    return hipErrorInvalidValue;
 }
 
 #undef PGM_V
@@ -1532,14 +1763,7 @@ hipError_t launch_regions(const RegionArgs& a, hipStream_t s)
 hipError_t launch_output(const OutArgs& a, hipStream_t s)
 {
     const int n = a.g.nx * a.g.ny;
-    hipLaunchKernelGGL(k_output, dim3((n + 255) / 256, 1, a.b.npairs), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_compact(const OutArgs& a, hipStream_t s)
-{
-    const int n = a.g.nx * a.g.ny;
-    hipLaunchKernelGGL(k_compact, dim3((n + 255) / 256, 1, a.b.npairs), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_output, dim3((n + 255) / 256, a.b.ndir, a.b.npairs), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
