@@ -231,6 +231,9 @@ bool level_layout(const Layout& Y, int l, int iters, int nI, size_t lds_max, Lev
 
 struct pgm_ctx_s {
     int device = 0;
+    // the pairs of a call share the GPU with other work (concurrent groups, the server's
+    // requests): small levels then run in one work-group per pair and direction
+    bool concurrent = false;
     size_t lds_max = 0;            // LDS bytes a work-group may use on this device
     uint8_t* ws = nullptr;
     size_t ws_bytes = 0;
@@ -613,9 +616,13 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     // their three candidate patches do not fit the registers) and the level is swept with
     // per-half-sweep launches.
     const bool can_fuse = shared && std::max(p->patch_fwd, p->patch_bwd) <= 8 && !(Y.kind == 1 && Y.C2 == 6);
+    // A small level runs in one work-group per pair and direction (k_level) where several
+    // pairs share the GPU; a lone pair's small level runs faster as half-sweep launches
+    // across the chip.
     auto lds_level = [&](int k, LevelLayout& lay) {
         const int l = Y.st_level[k];
-        return shared && p->iters[l] > 0 && level_layout(Y, l, p->iters[l], Y.st_nI[k], c->lds_max, lay);
+        return shared && p->iters[l] > 0 && (npairs >= 2 || c->concurrent) &&
+               level_layout(Y, l, p->iters[l], Y.st_nI[k], c->lds_max, lay);
     };
     auto fused = [&](int k) {
         if (k <= 0 || k >= Y.nst) return false;
@@ -819,10 +826,12 @@ static pgm_status groups_eager(pgm_ctx_s* c, int32_t n_groups, const pgm_group* 
     for (int g = 0; g < n_groups; g++) {
         const pgm_group& G = gr[g];
         const size_t end = g + 1 < n_groups ? off[g + 1] : c->ws_bytes;
-        if (pgm_status st = match_impl(c, G.params, G.n_pairs, G.img1, G.img2, G.w, G.h, G.pitch_bytes,
-                                       G.image_stride_bytes, G.out_fwd, G.out_bwd, G.out_n_inliers, G.out_compact,
-                                       out_n_evals, c->gs[g % ns], c->ws + off[g], end - off[g]))
-            return st;
+        c->concurrent = n_groups > 1;
+        const pgm_status st = match_impl(c, G.params, G.n_pairs, G.img1, G.img2, G.w, G.h, G.pitch_bytes,
+                                         G.image_stride_bytes, G.out_fwd, G.out_bwd, G.out_n_inliers, G.out_compact,
+                                         out_n_evals, c->gs[g % ns], c->ws + off[g], end - off[g]);
+        c->concurrent = false;
+        if (st) return st;
     }
     for (int i = 0; i < ns; i++) {
         PGM_HIP(c, hipEventRecord(c->join[i], c->gs[i]));
@@ -1046,6 +1055,7 @@ pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_stre
     if (st != PGM_OK) return st;
     pgm_server_s* S = new pgm_server_s();
     S->c = (pgm_ctx_s*)ctx;
+    S->c->concurrent = true;
     S->free_[0] = S->c->ws_bytes & ~(size_t)255;
     for (int i = 0; i < n_streams; i++) {
         hipStream_t q;
