@@ -12,6 +12,9 @@
 
 namespace pgm {
 
+// two 16-bit lanes of one register (packed integer arithmetic)
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
 // ---------------------------------------------------------------------------------------
 // small device helpers
 // ---------------------------------------------------------------------------------------
@@ -1362,23 +1365,23 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
         lin[threadIdx.x] = srgb_linear((int)threadIdx.x);
         __syncthreads();
     }
-    // every load of the staging is issued before the first conversion
+    // Staging: a fixed GR_SV x GR_SU block (columns and rows past the needed NU x NV repeat the
+    // last needed one), every load issued before the first conversion.
     constexpr int SPT = (GR_SU * GR_SV + 255) / 256;
     uint32_t raw[SPT];
 #pragma unroll
     for (int k = 0; k < SPT; k++) {
         const int e = threadIdx.x + 256 * k;
         raw[k] = 0;
-        if (e < NU * NV) {
-            const int v = e / NU, u = e - v * NU;
-            raw[k] = rgb_at(img, L.pitch, mirror_fast(cx0 - K + u, w), mirror_fast(cy0 - K + v, h));
+        if (e < GR_SU * GR_SV) {
+            const int v = e / GR_SU, u = e - v * GR_SU;
+            raw[k] = rgb_at(img, L.pitch, mirror_fast(cx0 - K + min(u, NU - 1), w), mirror_fast(cy0 - K + min(v, NV - 1), h));
         }
     }
 #pragma unroll
     for (int k = 0; k < SPT; k++) {
         const int e = threadIdx.x + 256 * k;
-        if (e < NU * NV) {
-            const int v = e / NU, u = e - v * NU;
+        if (e < GR_SU * GR_SV) {
             uint32_t val = raw[k];
             if (GRAY) {
                 val = (77 * (val & 0xFFu) + 150 * ((val >> 8) & 0xFFu) + 29 * ((val >> 16) & 0xFFu) + 128) >> 8;
@@ -1386,57 +1389,63 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
                 if (L.space == PGM_SPACE_YCRCB) val = to_ycrcb(val);
                 else if (L.space == PGM_SPACE_LAB) val = to_lab(val, lin);
             }
-            S[v * GR_SU + u] = val;
+            S[e] = val;
         }
     }
     __syncthreads();
-    // smoothing and derivative taps of the size-KS Sobel operator
-    const int sm3[3] = {1, 2, 1}, dv3[3] = {-1, 0, 1};
-    const int sm5[5] = {1, 4, 6, 4, 1}, dv5[5] = {-1, -2, 0, 2, 1};
-    for (int e = threadIdx.x; e < NV * NC; e += 256) {
-        const int v = e / NC, u = e - v * NC;
-        const uint32_t* row = S + v * GR_SU + u;
-        int rs[CH], rd[CH];
+    // Sobel taps of size KS: smoothing and derivative. Every partial sum fits in 16 bits (row
+    // smoothing <= 16 * 255, row derivative <= 6 * 255, columns <= 6 * 4080), so each pair of
+    // sums runs in the two halves of one register (packed 16-bit multiply-adds).
+    const short sm3[3] = {1, 2, 1}, dv3[3] = {-1, 0, 1};
+    const short sm5[5] = {1, 4, 6, 4, 1}, dv5[5] = {-1, -2, 0, 2, 1};
+    // Row pass over the fixed block: plane c holds (smoothing, derivative) of channel c.
+    uint32_t* H2 = (uint32_t*)H;   // [CH][GR_SV][GR_TW] packed pairs
+    constexpr int RPT = GR_SV * GR_TW / 256;
+    static_assert(GR_SV * GR_TW % 256 == 0, "row pass: whole entries per thread");
 #pragma unroll
-        for (int c = 0; c < CH; c++) { rs[c] = 0; rd[c] = 0; }
+    for (int k = 0; k < RPT; k++) {
+        const int e = threadIdx.x + 256 * k;
+        const int v = e / GR_TW, u = e - v * GR_TW;
+        const uint32_t* row = S + v * GR_SU + u;
+        s16x2 acc[CH];
+#pragma unroll
+        for (int c = 0; c < CH; c++) acc[c] = s16x2{0, 0};
 #pragma unroll
         for (int j = 0; j < KS; j++) {
             const uint32_t q = row[j];
-            const int sm = KS == 3 ? sm3[j] : sm5[j];
-            const int dv = KS == 3 ? dv3[j] : dv5[j];
+            const s16x2 wt = s16x2{KS == 3 ? sm3[j] : sm5[j], KS == 3 ? dv3[j] : dv5[j]};
 #pragma unroll
             for (int c = 0; c < CH; c++) {
-                const int val = (int)((q >> (8 * c)) & 0xFFu);
-                rs[c] += sm * val;
-                rd[c] += dv * val;
+                const short val = (short)((q >> (8 * c)) & 0xFFu);
+                acc[c] += wt * s16x2{val, val};
             }
         }
-        int* o = H + v * GR_TW + u;
 #pragma unroll
-        for (int c = 0; c < CH; c++) {
-            o[c * (GR_SV * GR_TW)] = rs[c];
-            o[(CH + c) * (GR_SV * GR_TW)] = rd[c];
-        }
+        for (int c = 0; c < CH; c++) H2[(c * GR_SV + v) * GR_TW + u] = __builtin_bit_cast(uint32_t, acc[c]);
     }
     __syncthreads();
+    // Column pass: (sum of derivative weights x smoothing, sum of smoothing weights x
+    // derivative) = (gy, gx) per channel.
     for (int e = threadIdx.x; e < GR_TW * GR_TH; e += 256) {
         const int X = X0 + (e & (GR_TW - 1)), Y = Y0 + e / GR_TW;
         if (X >= pw || Y >= ph) continue;
         const int u = clampi(X - PAD, 0, w - 1) - cx0;
         const int v = clampi(Y - PAD, 0, h - 1) - cy0;
-        int gx[CH], gy[CH];
+        s16x2 acc[CH];
 #pragma unroll
-        for (int c = 0; c < CH; c++) { gx[c] = 0; gy[c] = 0; }
+        for (int c = 0; c < CH; c++) acc[c] = s16x2{0, 0};
 #pragma unroll
         for (int i = 0; i < KS; i++) {
-            const int* q = H + (v + i) * GR_TW + u;
-            const int smi = KS == 3 ? sm3[i] : sm5[i];
-            const int dvi = KS == 3 ? dv3[i] : dv5[i];
+            const s16x2 wt = s16x2{KS == 3 ? dv3[i] : dv5[i], KS == 3 ? sm3[i] : sm5[i]};
 #pragma unroll
-            for (int c = 0; c < CH; c++) {
-                gx[c] += smi * q[(CH + c) * (GR_SV * GR_TW)];
-                gy[c] += dvi * q[c * (GR_SV * GR_TW)];
-            }
+            for (int c = 0; c < CH; c++)
+                acc[c] += wt * __builtin_bit_cast(s16x2, H2[(c * GR_SV + v + i) * GR_TW + u]);
+        }
+        int gx[CH], gy[CH];
+#pragma unroll
+        for (int c = 0; c < CH; c++) {
+            gy[c] = acc[c].x;
+            gx[c] = acc[c].y;
         }
         const size_t o = ((size_t)Y * pw + X) * C2;
         if (!F32) {
