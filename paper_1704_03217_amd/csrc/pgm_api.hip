@@ -26,10 +26,9 @@ struct Layout {
     int nst = 0;
     int st_level[MAX_STAGES], st_enter[MAX_STAGES], st_W[MAX_STAGES], st_nI[MAX_STAGES];
     long long st_base[MAX_STAGES];                       // short2 offset of the stage's offsets
-    long long rnd_items = 0;                             // Philox calls for the search offsets
     int R_top = 0;
     // per-block evaluation counts of the matching launches, one table per kernel kind
-    // (init, down, up, sweep), and the per-block inlier counts of the level-0 output
+    // (init, down, up, sweep)
     size_t cnt[4] = {0, 0, 0, 0};
     long long cnt_cap[4] = {0, 0, 0, 0};
     size_t cntpart = 0;
@@ -151,7 +150,6 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
         Y.st_base[k] = base;
         const long long n = (long long)Y.lnx[l] * Y.lny[l];
         base += 2LL * p->iters[l] * n * Y.st_nI[k];
-        Y.rnd_items += 2LL * n * p->iters[l] * ((Y.st_nI[k] + 1) / 2);
     }
     size_t cur = 0;
     Y.rnd = take(cur, (size_t)base * sizeof(short2) + 4);
