@@ -551,21 +551,31 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     const bool gray = p->color == PGM_GRAY;
     pa.grad.dst_zs = zs;
     grad_level(pa.grad, 0, img1, img2, image_stride_bytes, pitch_bytes);
+    // pyramid levels two at a time where two remain (one pass computes both)
+    auto second_level = [&](PyrArgs& pr, int l) {
+        if (l + 1 >= Y.L) return;
+        pr.two = 1;
+        pr.dst2[0] = pw0 + Y.pyr[0][l + 1];
+        pr.dst2[1] = pw0 + Y.pyr[1][l + 1];
+    };
     pa.with_pyr = Y.L > 1;
-    if (pa.with_pyr) pyr_level(pa.pyr, 1, img1, img2, image_stride_bytes, pitch_bytes);
+    if (pa.with_pyr) {
+        pyr_level(pa.pyr, 1, img1, img2, image_stride_bytes, pitch_bytes);
+        second_level(pa.pyr, 1);
+    }
     PGM_HIP(c, timed(PGM_K_PREP, [&] { return launch_prep(pa, npairs, gray, p->sobel_ksize, p->feature, s); }));
+    for (int l = pa.pyr.two ? 3 : 2; l < Y.L;) {
+        PyrArgs pr;
+        memset(&pr, 0, sizeof pr);
+        pyr_level(pr, l, pw0 + Y.pyr[0][l - 1], pw0 + Y.pyr[1][l - 1], zs, Y.lw[l - 1] * 3);
+        second_level(pr, l);
+        PGM_HIP(c, timed(PGM_K_PYRAMID, [&] { return launch_pyr(pr, npairs, s); }));
+        l += pr.two ? 2 : 1;
+    }
     GradArgs gl;
     memset(&gl, 0, sizeof gl);
     gl.dst_zs = zs;
-    for (int l = 1; l < Y.L; l++) {
-        if (l > 1) {
-            PyrArgs pr;
-            memset(&pr, 0, sizeof pr);
-            pyr_level(pr, l, pw0 + Y.pyr[0][l - 1], pw0 + Y.pyr[1][l - 1], zs, Y.lw[l - 1] * 3);
-            PGM_HIP(c, timed(PGM_K_PYRAMID, [&] { return launch_pyr(pr, npairs, s); }));
-        }
-        grad_level(gl, l, pw0 + Y.pyr[0][l], pw0 + Y.pyr[1][l], zs, Y.lw[l] * 3);
-    }
+    for (int l = 1; l < Y.L; l++) grad_level(gl, l, pw0 + Y.pyr[0][l], pw0 + Y.pyr[1][l], zs, Y.lw[l] * 3);
     if (gl.n) PGM_HIP(c, timed(PGM_K_GRADIENT, [&] { return launch_gradient(gl, npairs, gray, p->sobel_ksize, p->feature, s); }));
 
     auto geo = [&](int l) {
@@ -614,12 +624,13 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     // their three candidate patches do not fit the registers) and the level is swept with
     // per-half-sweep launches.
     const bool can_fuse = shared && std::max(p->patch_fwd, p->patch_bwd) <= 8 && !(Y.kind == 1 && Y.C2 == 6);
-    // A small level runs in one work-group per pair and direction (k_level) where several
-    // pairs share the GPU; a lone pair's small level runs faster as half-sweep launches
-    // across the chip.
+    // A small level runs in one work-group per pair and direction (k_level) where other work
+    // shares the GPU (concurrent groups, the server) or the batch has 16 pairs or more;
+    // otherwise it runs faster as half-sweep launches across the chip (measured: one pair
+    // 65 -> 55 us at 64x28, 8 pairs slightly faster, 32 pairs slightly slower).
     auto lds_level = [&](int k, LevelLayout& lay) {
         const int l = Y.st_level[k];
-        return shared && p->iters[l] > 0 && (npairs >= 2 || c->concurrent) &&
+        return shared && p->iters[l] > 0 && (npairs >= 16 || c->concurrent) &&
                level_layout(Y, l, p->iters[l], Y.st_nI[k], c->lds_max, lay);
     };
     auto fused = [&](int k) {

@@ -178,7 +178,9 @@ struct PyrArgs {
     long long src_zs;        // bytes between pairs' source images
     int pitch, w, h;         // source pitch (bytes) and size
     uint8_t* dst[2];         // pair 0's destination images (packed rows of (w + 1) / 2 pixels)
-    long long dst_zs;
+    long long dst_zs;        // bytes between pairs' destination images (both levels)
+    int two;                 // also the level after it, from the same pass
+    uint8_t* dst2[2];        // pair 0's images of that level (two)
     int tx, tiles;
 };
 // gradient images of one or more levels (tx, tiles and base filled in by the launchers)

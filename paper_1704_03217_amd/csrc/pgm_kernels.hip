@@ -1264,6 +1264,121 @@ __device__ __forceinline__ void pyr_tile(const PyrArgs& a, int t, int z, uint32_
     o[2] = (uint8_t)((acc[2] + 128) >> 8);
 }
 
+// Two pyramid levels in one pass. A work-group computes P2_TW x P2_TH pixels of level l+2 and
+// the 2 P2_TW x 2 P2_TH pixels of level l+1 above them: it stages the level-l pixels under the
+// level-(l+1) pixels that its level-(l+2) pixels read (the reflections at the borders fall
+// inside that block), computes those level-(l+1) pixels as pyr_tile does, writes the ones it
+// owns, then filters them into level l+2. Each value is the integer of two separate passes.
+// Sums run two channels to a register: R and G in the low and high halves (every partial sum
+// stays below 2^16), B alone.
+constexpr int P2_TW = 32, P2_TH = 2;
+constexpr int P2_C1 = 2 * P2_TW + 3, P2_R1 = 2 * P2_TH + 3;   // level-(l+1) block
+constexpr int P2_SU = 2 * P2_C1 + 3, P2_SV = 2 * P2_R1 + 3;   // level-l block
+constexpr int P2_LDS = P2_SV * P2_SU + 2 * P2_SV * P2_C1 + P2_R1 * P2_C1 + 2 * P2_R1 * P2_TW;   // dwords
+
+__device__ __forceinline__ uint32_t rg_pair(uint32_t q) { return (q & 0xFFu) | ((q & 0xFF00u) << 8); }
+
+__device__ __forceinline__ void pyr2_tile(const PyrArgs& a, int t, int z, uint32_t* lds)
+{
+    uint32_t* S0 = lds;                        // [P2_SV][P2_SU] staged level-l pixels
+    uint32_t* H0 = S0 + P2_SV * P2_SU;         // [P2_SV][P2_C1][2] row sums (RG, B)
+    uint32_t* V1 = H0 + 2 * P2_SV * P2_C1;     // [P2_R1][P2_C1] level-(l+1) pixels
+    uint32_t* H1 = V1 + P2_R1 * P2_C1;         // [P2_R1][P2_TW][2] row sums of level l+1
+    const int w0 = a.w, h0 = a.h, w1 = (w0 + 1) >> 1, h1 = (h0 + 1) >> 1, w2 = (w1 + 1) >> 1, h2 = (h1 + 1) >> 1;
+    const int X0 = (t % a.tx) * P2_TW, Y0 = (t / a.tx) * P2_TH;
+    const size_t pair = (size_t)(z >> 1);
+    const uint8_t* src = a.src[z & 1] + pair * (size_t)a.src_zs;
+    uint8_t* dst1 = a.dst[z & 1] + pair * (size_t)a.dst_zs;
+    uint8_t* dst2 = a.dst2[z & 1] + pair * (size_t)a.dst_zs;
+    const int cx0 = max(0, 2 * X0 - 2), cx1 = min(w1 - 1, 2 * X0 + 2 * P2_TW);
+    const int cy0 = max(0, 2 * Y0 - 2), cy1 = min(h1 - 1, 2 * Y0 + 2 * P2_TH);
+    const int NU = 2 * (cx1 - cx0 + 1) + 3, NV = 2 * (cy1 - cy0 + 1) + 3;
+    const int xlo = 2 * cx0 - 2, ylo = 2 * cy0 - 2;
+    constexpr int SPT = (P2_SU * P2_SV + 255) / 256;
+    uint32_t raw[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; k++) {
+        const int e = threadIdx.x + 256 * k;
+        raw[k] = 0;
+        if (e < P2_SU * P2_SV) {
+            const int v = e / P2_SU, u = e - v * P2_SU;
+            raw[k] = rgb_at(src, a.pitch, mirror_fast(xlo + min(u, NU - 1), w0), mirror_fast(ylo + min(v, NV - 1), h0));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < SPT; k++) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < P2_SU * P2_SV) S0[e] = raw[k];
+    }
+    __syncthreads();
+    const uint32_t tap[5] = {1, 4, 6, 4, 1};
+    for (int e = threadIdx.x; e < P2_SV * P2_C1; e += 256) {
+        const int v = e / P2_C1, k = e - v * P2_C1;
+        const uint32_t* row = S0 + v * P2_SU + 2 * k;
+        uint32_t rg = 0, b = 0;
+#pragma unroll
+        for (int j = 0; j < 5; j++) {
+            const uint32_t q = row[j];
+            rg += tap[j] * rg_pair(q);
+            b += tap[j] * ((q >> 16) & 0xFFu);
+        }
+        H0[2 * e] = rg;
+        H0[2 * e + 1] = b;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < P2_R1 * P2_C1; e += 256) {
+        const int r = e / P2_C1, k = e - r * P2_C1;
+        uint32_t rg = 0, b = 0;
+#pragma unroll
+        for (int i = 0; i < 5; i++) {
+            const uint32_t* q = H0 + 2 * ((2 * r + i) * P2_C1 + k);
+            rg += tap[i] * q[0];
+            b += tap[i] * q[1];
+        }
+        const uint32_t R = ((rg & 0xFFFFu) + 128) >> 8, G = ((rg >> 16) + 128) >> 8, B = (b + 128) >> 8;
+        V1[e] = R | (G << 8) | (B << 16);
+        const int c = cx0 + k, y = cy0 + r;
+        if (c >= 2 * X0 && c < 2 * X0 + 2 * P2_TW && c <= cx1 && y >= 2 * Y0 && y < 2 * Y0 + 2 * P2_TH && y <= cy1) {
+            uint8_t* o = dst1 + ((size_t)y * w1 + c) * 3;
+            o[0] = (uint8_t)R;
+            o[1] = (uint8_t)G;
+            o[2] = (uint8_t)B;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < P2_R1 * P2_TW; e += 256) {
+        const int r = e / P2_TW, k = e - r * P2_TW;
+        const int X2 = X0 + k;
+        uint32_t rg = 0, b = 0;
+        if (r <= cy1 - cy0 && X2 < w2) {
+#pragma unroll
+            for (int j = 0; j < 5; j++) {
+                const uint32_t q = V1[r * P2_C1 + mirror_fast(2 * X2 - 2 + j, w1) - cx0];
+                rg += tap[j] * rg_pair(q);
+                b += tap[j] * ((q >> 16) & 0xFFu);
+            }
+        }
+        H1[2 * e] = rg;
+        H1[2 * e + 1] = b;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < P2_TW * P2_TH; e += 256) {
+        const int X2 = X0 + e % P2_TW, Y2 = Y0 + e / P2_TW;
+        if (X2 >= w2 || Y2 >= h2) continue;
+        uint32_t rg = 0, b = 0;
+#pragma unroll
+        for (int i = 0; i < 5; i++) {
+            const uint32_t* q = H1 + 2 * ((mirror_fast(2 * Y2 - 2 + i, h1) - cy0) * P2_TW + e % P2_TW);
+            rg += tap[i] * q[0];
+            b += tap[i] * q[1];
+        }
+        uint8_t* o = dst2 + ((size_t)Y2 * w2 + X2) * 3;
+        o[0] = (uint8_t)(((rg & 0xFFFFu) + 128) >> 8);
+        o[1] = (uint8_t)(((rg >> 16) + 128) >> 8);
+        o[2] = (uint8_t)((b + 128) >> 8);
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // gradient image (Sec. III-A, Eq. 1-2) written with a replicated PAD border
 // ---------------------------------------------------------------------------------------
@@ -1531,7 +1646,7 @@ __device__ __forceinline__ void rng_block(const RngArgs& a, int b)
 // levels in one launch: blockIdx.x runs over the tiles of each level in turn).
 // ---------------------------------------------------------------------------------------
 
-constexpr int PREP_LDS = GR_LDS > PY_LDS ? GR_LDS : PY_LDS;
+constexpr int PREP_LDS = GR_LDS > PY_LDS ? (GR_LDS > P2_LDS ? GR_LDS : P2_LDS) : (PY_LDS > P2_LDS ? PY_LDS : P2_LDS);
 
 template <int KS, bool GRAY, int FEAT>
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
@@ -1552,13 +1667,15 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
         return;
     }
     b -= a.grad_blocks;
-    pyr_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
+    if (a.pyr.two) pyr2_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
+    else pyr_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
 }
 
 __global__ __launch_bounds__(256) void k_pyr(PyrArgs a)
 {
-    __shared__ uint32_t lds[PY_LDS];
-    pyr_tile(a, blockIdx.x, blockIdx.y, lds);
+    __shared__ uint32_t lds[PY_LDS > P2_LDS ? PY_LDS : P2_LDS];
+    if (a.two) pyr2_tile(a, blockIdx.x, blockIdx.y, lds);
+    else pyr_tile(a, blockIdx.x, blockIdx.y, lds);
 }
 
 template <int KS, bool GRAY, int FEAT>
@@ -1577,8 +1694,14 @@ __global__ __launch_bounds__(256) void k_gradient(GradArgs a)
 
 static void plan_pyr(PyrArgs& a)
 {
-    a.tx = ((a.w + 1) / 2 + PY_TW - 1) / PY_TW;
-    a.tiles = a.tx * (((a.h + 1) / 2 + PY_TH - 1) / PY_TH);
+    const int w1 = (a.w + 1) / 2, h1 = (a.h + 1) / 2;
+    if (a.two) {   // tiles over the second level
+        a.tx = ((w1 + 1) / 2 + P2_TW - 1) / P2_TW;
+        a.tiles = a.tx * (((h1 + 1) / 2 + P2_TH - 1) / P2_TH);
+    } else {
+        a.tx = (w1 + PY_TW - 1) / PY_TW;
+        a.tiles = a.tx * ((h1 + PY_TH - 1) / PY_TH);
+    }
 }
 
 static int plan_grad(GradArgs& a)
