@@ -616,14 +616,6 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         return b;
     };
 
-    // Stages whose level is entered from the coarser one by a single launch (the coarser
-    // level's check, the transition and the first half-sweep): small levels, where the
-    // separate launches cost mostly their latency (the fused launch needs more registers per
-    // lane, which costs more than it saves once a level fills the chip); both directions
-    // share the kernels, patch sides are at most 8 (six-channel float features excepted:
-    // their three candidate patches do not fit the registers) and the level is swept with
-    // per-half-sweep launches.
-    const bool can_fuse = shared && std::max(p->patch_fwd, p->patch_bwd) <= 8 && !(Y.kind == 1 && Y.C2 == 6);
     // A small level runs in one work-group per pair and direction (k_level) where other work
     // shares the GPU (concurrent groups, the server) or the batch has 16 pairs or more;
     // otherwise it runs faster as half-sweep launches across the chip (measured: one pair
@@ -633,13 +625,23 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         return shared && p->iters[l] > 0 && (npairs >= 16 || c->concurrent) &&
                level_layout(Y, l, p->iters[l], Y.st_nI[k], c->lds_max, lay);
     };
-    auto fused = [&](int k) {
-        if (k <= 0 || k >= Y.nst) return false;
+    // Stages whose level is entered from the coarser one in one launch together with the
+    // coarser level's check: the transition alone (2; batches under 16 pairs), or also the
+    // first half-sweep (1) for small levels, where the separate launches cost mostly their
+    // latency (the half-sweep needs more registers per lane, which costs more than it saves
+    // once a level fills the chip). Both directions share the kernels, and patch sides are
+    // at most 8 (six-channel float features excepted: their three candidate patches do not
+    // fit the registers).
+    const bool can_fuse = shared && std::max(p->patch_fwd, p->patch_bwd) <= 8 && !(Y.kind == 1 && Y.C2 == 6);
+    auto fused = [&](int k) -> int {
+        if (k <= 0 || k >= Y.nst || !can_fuse) return 0;
         const int e = Y.st_enter[k];
-        LevelLayout lay;
+        if (e != ENTER_DOWN_F && e != ENTER_DOWN_FO) return 0;
         const int l = Y.st_level[k];
-        return (e == ENTER_DOWN_F || e == ENTER_DOWN_FO) && can_fuse && p->iters[l] > 0 &&
-               (long long)Y.lnx[l] * Y.lny[l] * npairs <= FUSE_MAX_SEEDS && !lds_level(k, lay);
+        LevelLayout lay;
+        if (p->iters[l] > 0 && (long long)Y.lnx[l] * Y.lny[l] * npairs <= FUSE_MAX_SEEDS && !lds_level(k, lay))
+            return 1;
+        return npairs < 16 ? 2 : 0;   // large batches: the separate check is cheaper per pair
     };
     int rec_valid[PGM_MAX_LEVELS] = {0};
     int check_rec_valid = 0;   // rec_valid of the check deferred into the next stage's launch
@@ -647,7 +649,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         const int l = Y.st_level[k];
         const Geo g = geo(l);
         const int enter = Y.st_enter[k];
-        const bool fuse = fused(k);
+        const int fuse = fused(k);
         if (fuse) {
             EnterArgs ea;
             memset(&ea, 0, sizeof ea);
@@ -664,7 +666,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
             ea.rec_valid = check_rec_valid;
             ea.nI = Y.st_nI[k];
             ea.cnt = ctable(CNT_DOWN, 2LL * enter_blocks(g.nx, g.ny, ea.d[0].P, ea.gs.nx * ea.gs.ny));
-            PGM_HIP(c, timed(PGM_K_DOWN, [&] { return launch_enter(ea, Y.C2, Y.kind, s); }));
+            PGM_HIP(c, timed(PGM_K_DOWN, [&] { return launch_enter(ea, Y.C2, Y.kind, fuse == 1, s); }));
         }
         for (int pass = 0; pass < (fuse ? 0 : shared ? 1 : 2); pass++) {
             const int nd = shared ? 2 : 1;
@@ -718,7 +720,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         }
         // Step 1: iterations of propagation and limited random search, red then black
         for (int t = 0; t < (in_lds ? 0 : p->iters[l]); t++)
-            for (int colour = (fuse && t == 0) ? 1 : 0; colour < 2; colour++)
+            for (int colour = (fuse == 1 && t == 0) ? 1 : 0; colour < 2; colour++)
                 for (int pass = 0; pass < (shared ? 1 : 2); pass++) {
                     const int nd = shared ? 2 : 1;
                     const int d0 = shared ? 0 : pass;

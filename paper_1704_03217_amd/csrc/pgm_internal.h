@@ -214,7 +214,8 @@ hipError_t launch_sweep(const SweepArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_down(const TransArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_up(const TransArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);
-hipError_t launch_enter(EnterArgs a, int C2, int kind, hipStream_t s);
+// sweep: the first half-sweep too (k_enter), else the check and the transition (k_enter_start)
+hipError_t launch_enter(EnterArgs a, int C2, int kind, bool sweep, hipStream_t s);
 // work-groups of one k_enter launch per direction and pair
 inline int enter_blocks(int nx, int ny, int P, int n_coarse)
 {

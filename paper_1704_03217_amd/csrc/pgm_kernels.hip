@@ -777,10 +777,12 @@ __global__ __launch_bounds__(256) void k_check(CheckArgs a)
 // to their flags. A start depends only on the parent's state, so no seed waits for another.
 // ---------------------------------------------------------------------------------------
 
-template <class Row, int LPS>
+template <class Row, int LPS, bool SWEEP>
 __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs& D, const Field& S, const Field& O,
                                                int i, int j, bool first, int r)
 {
+    constexpr int M = SWEEP ? 3 : 1;   // parents read: this seed's, and its two neighbours' for the step
+    first = SWEEP && first;
     using Dist = typename Row::Dist;
     const Geo& g = a.g;
     const Geo& gs = a.gs;
@@ -792,11 +794,11 @@ __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs
     // m = 0: this seed; m = 1, 2: the neighbours (i - 1, j) and (i, j - 1) that the step at
     // t = 0 propagates from (the first of the Delta orders of Eq. 4)
     int qx[3], qy[3], ps[3];
-    bool on[3];
+    bool on[3] = {false, false, false};
     uint32_t pd[3];
     uint8_t pf[3];
 #pragma unroll
-    for (int m = 0; m < 3; m++) {
+    for (int m = 0; m < M; m++) {
         const int ni = m == 1 ? i - 1 : i, nj = m == 2 ? j - 1 : j;
         on[m] = m == 0 || (first && ni >= 0 && nj >= 0);
         qx[m] = grid_pos(max(ni, 0), g.w, g);
@@ -809,10 +811,10 @@ __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs
     const short2 o0 = R[0], o1 = R[a.nI > 1 ? 1 : 0];
     __builtin_amdgcn_sched_barrier(0);
     // the parents' checks (Steps 2-3 at the coarser level) and the starts of Eq. 6
-    uint32_t st[3];
-    bool inl[3];
+    uint32_t st[3] = {UNINIT, UNINIT, UNINIT};
+    bool inl[3] = {false, false, false};
 #pragma unroll
-    for (int m = 0; m < 3; m++) {
+    for (int m = 0; m < M; m++) {
         inl[m] = on[m] && check_inlier(O, gs, ps[m], pd[m], pf[m], a.fwd_bwd, a.tau2, a.rec_valid);
         st[m] = inl[m] ? target(qx[m], qy[m], 2 * d_x(pd[m]), 2 * d_y(pd[m]), g) : UNINIT;
     }
@@ -820,7 +822,7 @@ __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs
     const bool init0 = cur0 != UNINIT;
     if (r == 0) D.f.flags[s] = (a.carry_record && inl[0]) ? ST_REC : 0;
     uint32_t nev = init0 ? 1u : 0u;
-    if (!first) {
+    if (!SWEEP || !first) {
         Dist d0 = NO_DIST;
         if (init0) d0 = patch_cost<Row, LPS, true>(A, D.Gb, g, P, r, px + d_x(cur0), py + d_y(cur0));
         if (r == 0) {
@@ -860,8 +862,8 @@ __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs
     return nev + decide_and_search<Row, LPS, true>(A, D, g, s, px, py, r, R, a.nI, o0, o1, cur0, cd0, c, ok, e, true);
 }
 
-template <int C2, int PMAX, bool FIXED, int KIND>
-__global__ __launch_bounds__(256) void k_enter(EnterArgs a)
+template <int C2, int PMAX, bool FIXED, int KIND, bool SWEEP>
+__device__ __forceinline__ void enter_body(const EnterArgs& a)
 {
     using Row = RowT<C2, PMAX, FIXED, KIND>;
     constexpr int LPS = PMAX;
@@ -886,9 +888,23 @@ __global__ __launch_bounds__(256) void k_enter(EnterArgs a)
         const int j = gid / hx;
         const int i = 2 * (gid - j * hx) + ((colour + j) & 1);
         leader = r == 0;
-        if (j < a.g.ny && i < a.g.nx) nev = enter_seed<Row, LPS>(a, D, S, O, i, j, colour == 0, r);
+        if (j < a.g.ny && i < a.g.nx) nev = enter_seed<Row, LPS, SWEEP>(a, D, S, O, i, j, colour == 0, r);
     }
     count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, leader);
+}
+
+// the coarser level's check, the transition and the first half-sweep
+template <int C2, int PMAX, bool FIXED, int KIND>
+__global__ __launch_bounds__(256) void k_enter(EnterArgs a)
+{
+    enter_body<C2, PMAX, FIXED, KIND, true>(a);
+}
+
+// the coarser level's check and the transition (both colours take their start only)
+template <int C2, int PMAX, bool FIXED, int KIND>
+__global__ __launch_bounds__(256) void k_enter_start(EnterArgs a)
+{
+    enter_body<C2, PMAX, FIXED, KIND, false>(a);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1815,7 +1831,7 @@ hipError_t launch_up(const TransArgs& a, int C2, int kind, hipStream_t s)
     PGM_DISPATCH(k_up, a, a.g.nx * a.g.ny);
 }
 
-hipError_t launch_enter(EnterArgs a, int C2, int kind, hipStream_t s)
+hipError_t launch_enter(EnterArgs a, int C2, int kind, bool sweep, hipStream_t s)
 {
     const int P = a.d[0].P;
     a.nb_col = sweep_blocks(a.g.nx, a.g.ny, P);
@@ -1826,7 +1842,12 @@ hipError_t launch_enter(EnterArgs a, int C2, int kind, hipStream_t s)
     if (nb > 0x7FFFFFFFLL || a.b.ndir != 2) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb);
     // patch sides up to 8 only: three candidate patches of 16 rows do not fit the registers
-    PGM_V(k_enter, 6, 8, true) PGM_V(k_enter, 6, 8, false) PGM_V(k_enter, 2, 8, true) PGM_V(k_enter, 2, 8, false)
+    if (sweep) {
+        PGM_V(k_enter, 6, 8, true) PGM_V(k_enter, 6, 8, false) PGM_V(k_enter, 2, 8, true) PGM_V(k_enter, 2, 8, false)
+    } else {
+        PGM_V(k_enter_start, 6, 8, true) PGM_V(k_enter_start, 6, 8, false) PGM_V(k_enter_start, 2, 8, true)
+        PGM_V(k_enter_start, 2, 8, false)
+    }
     return hipErrorInvalidValue;
 }
 
