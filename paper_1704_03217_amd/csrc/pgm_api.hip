@@ -183,6 +183,7 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
         Y.cnt_cap[kind] += dir_blocks(p, Y.lnx[l] * Y.lny[l]);
         if (kind == CNT_DOWN && l + 1 < Y.L)   // room for a launch that enters the level whole
             Y.cnt_cap[kind] += 2LL * enter_blocks(Y.lnx[l], Y.lny[l], p->patch_fwd, Y.lnx[l + 1] * Y.lny[l + 1]);
+        if (kind == CNT_INIT) Y.cnt_cap[kind] += 2LL * enter_blocks(Y.lnx[l], Y.lny[l], p->patch_fwd, 0);
         auto sb = [&](int P) { return (long long)sweep_blocks(Y.lnx[l], Y.lny[l], P); };
         const long long per_sweep = variant(p->patch_fwd) == variant(p->patch_bwd) ? 2 * sb(p->patch_fwd)
                                                                                    : sb(p->patch_fwd) + sb(p->patch_bwd);
@@ -633,14 +634,18 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     // at most 8 (six-channel float features excepted: their three candidate patches do not
     // fit the registers).
     const bool can_fuse = shared && std::max(p->patch_fwd, p->patch_bwd) <= 8 && !(Y.kind == 1 && Y.C2 == 6);
+    // The initial level of a random start is entered the same way (3): its starts and its
+    // first half-sweep in one launch.
     auto fused = [&](int k) -> int {
-        if (k <= 0 || k >= Y.nst || !can_fuse) return 0;
+        if (k < 0 || k >= Y.nst || !can_fuse) return 0;
         const int e = Y.st_enter[k];
-        if (e != ENTER_DOWN_F && e != ENTER_DOWN_FO) return 0;
         const int l = Y.st_level[k];
         LevelLayout lay;
-        if (p->iters[l] > 0 && (long long)Y.lnx[l] * Y.lny[l] * npairs <= FUSE_MAX_SEEDS && !lds_level(k, lay))
-            return 1;
+        const bool small =
+            p->iters[l] > 0 && (long long)Y.lnx[l] * Y.lny[l] * npairs <= FUSE_MAX_SEEDS && !lds_level(k, lay);
+        if (e == ENTER_INIT) return p->init_mode == PGM_INIT_RANDOM && small ? 3 : 0;
+        if (k == 0 || (e != ENTER_DOWN_F && e != ENTER_DOWN_FO)) return 0;
+        if (small) return 1;
         return npairs < 16 ? 2 : 0;   // large batches: the separate check is cheaper per pair
     };
     int rec_valid[PGM_MAX_LEVELS] = {0};
@@ -651,22 +656,25 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         const int enter = Y.st_enter[k];
         const int fuse = fused(k);
         if (fuse) {
+            const bool init = fuse == 3;
             EnterArgs ea;
             memset(&ea, 0, sizeof ea);
             for (int q = 0; q < 2; q++) {
                 ea.d[q] = dirargs(q, l, k);
-                ea.src[q] = field(q, l + 1);
+                if (!init) ea.src[q] = field(q, l + 1);
             }
             ea.g = g;
-            ea.gs = geo(l + 1);
+            ea.gs = init ? g : geo(l + 1);
             ea.b = batch(2);
-            ea.carry_record = enter != ENTER_DOWN_F;
+            ea.carry_record = enter != ENTER_DOWN_F && !init;
             ea.fwd_bwd = p->fwd_bwd;
             ea.tau2 = p->consistency_px * p->consistency_px;
             ea.rec_valid = check_rec_valid;
             ea.nI = Y.st_nI[k];
-            ea.cnt = ctable(CNT_DOWN, 2LL * enter_blocks(g.nx, g.ny, ea.d[0].P, ea.gs.nx * ea.gs.ny));
-            PGM_HIP(c, timed(PGM_K_DOWN, [&] { return launch_enter(ea, Y.C2, Y.kind, fuse == 1, s); }));
+            const int mode = init ? ENTER_LAUNCH_INIT : fuse == 1 ? ENTER_LAUNCH_SWEEP : ENTER_LAUNCH_START;
+            ea.cnt = ctable(init ? CNT_INIT : CNT_DOWN,
+                            2LL * enter_blocks(g.nx, g.ny, ea.d[0].P, init ? 0 : ea.gs.nx * ea.gs.ny));
+            PGM_HIP(c, timed(init ? PGM_K_INIT : PGM_K_DOWN, [&] { return launch_enter(ea, Y.C2, Y.kind, mode, s); }));
         }
         for (int pass = 0; pass < (fuse ? 0 : shared ? 1 : 2); pass++) {
             const int nd = shared ? 2 : 1;
@@ -720,7 +728,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         }
         // Step 1: iterations of propagation and limited random search, red then black
         for (int t = 0; t < (in_lds ? 0 : p->iters[l]); t++)
-            for (int colour = (fuse == 1 && t == 0) ? 1 : 0; colour < 2; colour++)
+            for (int colour = ((fuse == 1 || fuse == 3) && t == 0) ? 1 : 0; colour < 2; colour++)
                 for (int pass = 0; pass < (shared ? 1 : 2); pass++) {
                     const int nd = shared ? 2 : 1;
                     const int d0 = shared ? 0 : pass;

@@ -214,8 +214,11 @@ hipError_t launch_sweep(const SweepArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_down(const TransArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_up(const TransArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);
-// sweep: the first half-sweep too (k_enter), else the check and the transition (k_enter_start)
-hipError_t launch_enter(EnterArgs a, int C2, int kind, bool sweep, hipStream_t s);
+// ENTER_LAUNCH_START: the check and the transition (k_enter_start); ENTER_LAUNCH_SWEEP: and the
+// first half-sweep (k_enter); ENTER_LAUNCH_INIT: the initial level's random starts and its
+// first half-sweep (k_enter_init; no coarser level)
+enum { ENTER_LAUNCH_START = 0, ENTER_LAUNCH_SWEEP = 1, ENTER_LAUNCH_INIT = 2 };
+hipError_t launch_enter(EnterArgs a, int C2, int kind, int mode, hipStream_t s);
 // work-groups of one k_enter launch per direction and pair
 inline int enter_blocks(int nx, int ny, int P, int n_coarse)
 {

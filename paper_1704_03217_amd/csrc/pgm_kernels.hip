@@ -777,11 +777,12 @@ __global__ __launch_bounds__(256) void k_check(CheckArgs a)
 // to their flags. A start depends only on the parent's state, so no seed waits for another.
 // ---------------------------------------------------------------------------------------
 
-template <class Row, int LPS, bool SWEEP>
+// INIT: the initial level instead, whose starts are the seeds' random displacements
+template <class Row, int LPS, bool SWEEP, bool INIT>
 __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs& D, const Field& S, const Field& O,
                                                int i, int j, bool first, int r)
 {
-    constexpr int M = SWEEP ? 3 : 1;   // parents read: this seed's, and its two neighbours' for the step
+    constexpr int M = SWEEP ? 3 : 1;   // starts needed: this seed's, and its two neighbours' for the step
     first = SWEEP && first;
     using Dist = typename Row::Dist;
     const Geo& g = a.g;
@@ -797,15 +798,20 @@ __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs
     bool on[3] = {false, false, false};
     uint32_t pd[3];
     uint8_t pf[3];
+    short2 o_init[3];
 #pragma unroll
     for (int m = 0; m < M; m++) {
         const int ni = m == 1 ? i - 1 : i, nj = m == 2 ? j - 1 : j;
         on[m] = m == 0 || (first && ni >= 0 && nj >= 0);
         qx[m] = grid_pos(max(ni, 0), g.w, g);
         qy[m] = grid_pos(max(nj, 0), g.h, g);
-        ps[m] = grid_near(qy[m] >> 1, gs.ny, gs) * gs.nx + grid_near(qx[m] >> 1, gs.nx, gs);
-        pd[m] = S.disp[ps[m]];
-        pf[m] = S.flags[ps[m]];
+        if constexpr (INIT) {
+            o_init[m] = D.rnd0[max(nj, 0) * g.nx + max(ni, 0)];
+        } else {
+            ps[m] = grid_near(qy[m] >> 1, gs.ny, gs) * gs.nx + grid_near(qx[m] >> 1, gs.nx, gs);
+            pd[m] = S.disp[ps[m]];
+            pf[m] = S.flags[ps[m]];
+        }
     }
     const short2* R = D.rnd + (size_t)s * a.nI;   // offsets of the step at t = 0
     const short2 o0 = R[0], o1 = R[a.nI > 1 ? 1 : 0];
@@ -815,8 +821,13 @@ __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs
     bool inl[3] = {false, false, false};
 #pragma unroll
     for (int m = 0; m < M; m++) {
-        inl[m] = on[m] && check_inlier(O, gs, ps[m], pd[m], pf[m], a.fwd_bwd, a.tau2, a.rec_valid);
-        st[m] = inl[m] ? target(qx[m], qy[m], 2 * d_x(pd[m]), 2 * d_y(pd[m]), g) : UNINIT;
+        if constexpr (INIT) {   // the random start of the initial field, clamped into the image
+            inl[m] = false;
+            st[m] = on[m] ? target(qx[m], qy[m], o_init[m].x, o_init[m].y, g) : UNINIT;
+        } else {
+            inl[m] = on[m] && check_inlier(O, gs, ps[m], pd[m], pf[m], a.fwd_bwd, a.tau2, a.rec_valid);
+            st[m] = inl[m] ? target(qx[m], qy[m], 2 * d_x(pd[m]), 2 * d_y(pd[m]), g) : UNINIT;
+        }
     }
     const uint32_t cur0 = st[0];
     const bool init0 = cur0 != UNINIT;
@@ -862,7 +873,7 @@ __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs
     return nev + decide_and_search<Row, LPS, true>(A, D, g, s, px, py, r, R, a.nI, o0, o1, cur0, cd0, c, ok, e, true);
 }
 
-template <int C2, int PMAX, bool FIXED, int KIND, bool SWEEP>
+template <int C2, int PMAX, bool FIXED, int KIND, bool SWEEP, bool INIT>
 __device__ __forceinline__ void enter_body(const EnterArgs& a)
 {
     using Row = RowT<C2, PMAX, FIXED, KIND>;
@@ -888,7 +899,7 @@ __device__ __forceinline__ void enter_body(const EnterArgs& a)
         const int j = gid / hx;
         const int i = 2 * (gid - j * hx) + ((colour + j) & 1);
         leader = r == 0;
-        if (j < a.g.ny && i < a.g.nx) nev = enter_seed<Row, LPS, SWEEP>(a, D, S, O, i, j, colour == 0, r);
+        if (j < a.g.ny && i < a.g.nx) nev = enter_seed<Row, LPS, SWEEP, INIT>(a, D, S, O, i, j, colour == 0, r);
     }
     count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, leader);
 }
@@ -897,14 +908,21 @@ __device__ __forceinline__ void enter_body(const EnterArgs& a)
 template <int C2, int PMAX, bool FIXED, int KIND>
 __global__ __launch_bounds__(256) void k_enter(EnterArgs a)
 {
-    enter_body<C2, PMAX, FIXED, KIND, true>(a);
+    enter_body<C2, PMAX, FIXED, KIND, true, false>(a);
 }
 
 // the coarser level's check and the transition (both colours take their start only)
 template <int C2, int PMAX, bool FIXED, int KIND>
 __global__ __launch_bounds__(256) void k_enter_start(EnterArgs a)
 {
-    enter_body<C2, PMAX, FIXED, KIND, false>(a);
+    enter_body<C2, PMAX, FIXED, KIND, false, false>(a);
+}
+
+// the initial level's random starts (Sec. III-B, III-D) and its first half-sweep
+template <int C2, int PMAX, bool FIXED, int KIND>
+__global__ __launch_bounds__(256) void k_enter_init(EnterArgs a)
+{
+    enter_body<C2, PMAX, FIXED, KIND, true, true>(a);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1831,19 +1849,22 @@ hipError_t launch_up(const TransArgs& a, int C2, int kind, hipStream_t s)
     PGM_DISPATCH(k_up, a, a.g.nx * a.g.ny);
 }
 
-hipError_t launch_enter(EnterArgs a, int C2, int kind, bool sweep, hipStream_t s)
+hipError_t launch_enter(EnterArgs a, int C2, int kind, int mode, hipStream_t s)
 {
     const int P = a.d[0].P;
     a.nb_col = sweep_blocks(a.g.nx, a.g.ny, P);
-    a.nb_chk = (a.gs.nx * a.gs.ny + 255) / 256;
+    a.nb_chk = mode == ENTER_LAUNCH_INIT ? 0 : (a.gs.nx * a.gs.ny + 255) / 256;
     const int pmax = P <= 8 ? 8 : 16;
     const bool fixed = P == pmax;
     const long long nb = (long long)(2 * a.nb_col + a.nb_chk) * a.b.ndir * a.b.npairs;
     if (nb > 0x7FFFFFFFLL || a.b.ndir != 2) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb);
     // patch sides up to 8 only: three candidate patches of 16 rows do not fit the registers
-    if (sweep) {
+    if (mode == ENTER_LAUNCH_SWEEP) {
         PGM_V(k_enter, 6, 8, true) PGM_V(k_enter, 6, 8, false) PGM_V(k_enter, 2, 8, true) PGM_V(k_enter, 2, 8, false)
+    } else if (mode == ENTER_LAUNCH_INIT) {
+        PGM_V(k_enter_init, 6, 8, true) PGM_V(k_enter_init, 6, 8, false) PGM_V(k_enter_init, 2, 8, true)
+        PGM_V(k_enter_init, 2, 8, false)
     } else {
         PGM_V(k_enter_start, 6, 8, true) PGM_V(k_enter_start, 6, 8, false) PGM_V(k_enter_start, 2, 8, true)
         PGM_V(k_enter_start, 2, 8, false)
