@@ -347,7 +347,7 @@ def main():
 
     roofline, kernels = None, {}
     if not args.no_profile_pass:
-        print(f"[bench] profiled pass of {args.steps} steps (HIP events around every launch)", file=sys.stderr,
+        print(f"[bench] profiled pass of {args.steps} steps (HIP events around each run of launches of one kind)", file=sys.stderr,
               flush=True)
         roofline, kernels = sweep_roofline(pgm, m.ctx, args.steps, step, torch, measured_traffic())
 
