@@ -4,13 +4,15 @@
 One step = one whole pass of the method (pyramids, gradient images, random numbers,
 coarse-to-fine PatchMatch with the forward-backward check at every level, level-0 output and
 compaction) over one synthetic 1024x436 RGB pair already resident in HBM, issued as plain
-per-pair launches on one stream (`value`). A second pass runs the same method on B pairs per
-step through pgm_match_batch (`batched`). Prints one JSON line.
+per-pair launches on one stream (`value`). Further passes run the same method on B identical-size
+pairs per step through pgm_match_batch (`batched_uniform`), on 64 pairs of four sizes grouped
+into one pgm_match_groups graph launch (`batched`), and through the request server with
+Poisson arrivals (`served`, p50/p99 latency). Prints one JSON line.
 
 Measurement: the timed region is bracketed by torch.cuda.synchronize(). The dominant kernel
 (the propagation + random-search half-sweep) is then timed live with HIP events around each
-of its launches over a second pass of the same steps, which gives its average launch time and
-its distance evaluations; its roofline is VALU-bound at one v_sad_u16 per lane per clock.
+run of its launches over a second pass of the same steps, which gives its average launch time
+and its distance evaluations; its roofline is VALU-bound at one v_sad_u16 per lane per clock.
 The CPU baseline is the oracle (single thread, synchronous schedule) on a bounded sample.
 """
 from __future__ import annotations
