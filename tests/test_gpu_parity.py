@@ -141,6 +141,10 @@ CASES = {
     "ssd_patch16_s3": (lambda: synth.config_pair(1), base_params(metric=1, patch_fwd=16, patch_bwd=13, sobel_ksize=3, rng_seed=24)),
     "ssd_sign": (lambda: synth.config_pair(1), base_params(metric=1, feature=2, rng_seed=25)),
     "ssd_gray_dense_exhaustive": (lambda: synth.rect_pair(24, 40, 56, dmax=5), base_params(metric=1, color=1, seed_stride=1, levels=2, iters=[3, 3], init_mode=1, max_disp=6, rng_seed=26)),
+    # one random-search candidate at the initial level (R_top = 1), and a level without
+    # iterations between two with them (entered, checked and left without a sweep)
+    "init_radius1": (lambda: synth.rect_pair(25, 60, 80, dmax=2), base_params(levels=2, iters=[3, 3], max_disp=2, rng_seed=27)),
+    "level_without_iterations": (lambda: synth.rect_pair(26, 90, 120, dmax=8), base_params(levels=3, iters=[3, 0, 2], max_disp=8, rng_seed=28)),
 }
 
 
