@@ -7,7 +7,8 @@ compaction) over one synthetic 1024x436 RGB pair already resident in HBM, issued
 per-pair launches on one stream (`value`). Further passes run the same method on B identical-size
 pairs per step through pgm_match_batch (`batched_uniform`), on 64 pairs of four sizes grouped
 into one pgm_match_groups graph launch (`batched`), and through the request server with
-Poisson arrivals (`served`, p50/p99 latency). Prints one JSON line.
+Poisson arrivals (`served`, p50/p99 latency); for context, the paper's own parameters (dense
+field, patches 15/11) on the same pairs (`paper_preset`). Prints one JSON line.
 
 Measurement: the timed region is bracketed by torch.cuda.synchronize(). The dominant kernel
 (the propagation + random-search half-sweep) is then timed live with HIP events around each
@@ -52,6 +53,7 @@ def parse():
     ap.add_argument("--groups-steps", type=int, default=10)
     ap.add_argument("--served", type=int, default=240, help="requests per served run (0 = skip)")
     ap.add_argument("--served-pool", type=int, default=24, help="distinct generated request pairs")
+    ap.add_argument("--paper-steps", type=int, default=20, help="steps of the paper-preset pass (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a known-size kernel for HBM counter scaling)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -215,6 +217,34 @@ def run_groups(pgm, torch, dev, args, stream, pre):
             "workload": "64 pairs, sizes uniform over 320x240, 640x480, 1024x436, 1242x375 (rectangle-layer "
                         "generator, |d| <= w/5), config-2 matching with max_disp = ceil(w/5); grouped by size, "
                         "groups concurrent on 4 streams, one HIP graph launch per step"}
+
+
+def run_paper_preset(pgm, torch, m, imgs, stream, steps):
+    """Context: the paper's own parameters (dense stride-1 field, patches 15/11, Table II colour
+    spaces, small-region removal) on the same resident 1024x436 pairs, one pair per call."""
+    p = pgm.pgm_default_params(pgm.PRESET_PAPER)
+    w, h = 1024, 436
+    outs = [m.outputs(p, w, h, bwd=True, compact=True, count_evals=False) for _ in imgs]
+    counted = m.outputs(p, w, h, bwd=True, compact=True, count_evals=True)
+    m.match_into(p, imgs[0][0], imgs[0][1], counted, stream=stream)
+    torch.cuda.synchronize()
+    evals = int(counted["n_evals"].item())
+    for k in range(2):
+        a, b = imgs[k % len(imgs)]
+        m.match_into(p, a, b, outs[k % len(outs)], stream=stream)
+    print(f"[bench] paper preset: timing {steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        a, b = imgs[k % len(imgs)]
+        m.match_into(p, a, b, outs[k % len(outs)], stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return {"value": round(steps / (t1 - t0), 3), "unit": "pairs/s", "steps": steps,
+            "ms_per_pair": round(1000.0 * (t1 - t0) / steps, 4), "dist_evals_per_pair": evals,
+            "dist_evals_per_s": round(evals * steps / (t1 - t0), 1),
+            "workload": "paper preset on 1024x436: dense stride-1 field, patches 15 (forward) / 11 "
+                        "(backward), L=3, Table II colour spaces, small-region removal (9 px)"}
 
 
 def run_served(pgm, torch, dev, args, pre):
@@ -392,6 +422,7 @@ def main():
 
     groups = run_groups(pgm, torch, dev, args, stream, pre) if args.groups_pairs > 0 else None
     served = run_served(pgm, torch, dev, args, pre) if args.served > 0 else None
+    paper = run_paper_preset(pgm, torch, m, imgs, stream, args.paper_steps) if args.paper_steps > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -435,6 +466,7 @@ def main():
         "batched": groups,
         "batched_uniform": batched,
         "served": served,
+        "paper_preset": paper,
         "cpu_baseline": cpu,
     }
     m.close()
