@@ -1026,13 +1026,18 @@ __global__ __launch_bounds__((LevelShape<PMAX, KIND == 1>::threads)) void k_leve
 // ---------------------------------------------------------------------------------------
 
 // Root of x. Labels strictly decrease along the walk, so it ends within n steps; the bound
-// also holds while other threads lower labels.
-__device__ __forceinline__ int cc_find(const int32_t* L, int x, int n)
+// also holds while other threads lower labels. On the way every visited label is lowered to
+// its grandparent (an ancestor, so the regions do not change; atomicMin never raises a label
+// another thread has just lowered), which keeps the walks short.
+__device__ __forceinline__ int cc_find(int32_t* L, int x, int n)
 {
-    for (int k = 0; k < n; k++) {
-        const int y = __atomic_load_n(&L[x], __ATOMIC_RELAXED);
-        if (y == x) break;
+    int y = __atomic_load_n(&L[x], __ATOMIC_RELAXED);
+    for (int k = 0; k < n && y != x; k++) {
+        const int z = __atomic_load_n(&L[y], __ATOMIC_RELAXED);
+        if (z == y) return y;
+        atomicMin(&L[x], z);
         x = y;
+        y = z;
     }
     return x;
 }
@@ -1086,18 +1091,32 @@ __global__ __launch_bounds__(256) void k_cc_union(RegionArgs a)
         cc_union(L, s, s + g.nx, n);
 }
 
+// Region sizes: each inlier finds its root; the lanes of a wave that share a root add their
+// count with one atomic (neighbouring seeds mostly share one region).
 __global__ __launch_bounds__(256) void k_cc_size(RegionArgs a)
 {
     const int n = a.g.nx * a.g.ny;
     const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= n) return;
     const size_t zo = (size_t)blockIdx.z * (size_t)a.b.zs;
     const Field f = pair_field(a.f, zo);
-    if (!(f.flags[s] & ST_INL)) return;
     int32_t* L = zoff(a.label, zo);
-    const int r = cc_find(L, s, n);
-    L[s] = r;   // a root stays a root now that every join is done
-    atomicAdd(zoff(a.size, zo) + r, 1);
+    int32_t* size = zoff(a.size, zo);
+    bool pending = s < n && (f.flags[s] & ST_INL);
+    int r = -1;
+    if (pending) {
+        r = cc_find(L, s, n);
+        L[s] = r;   // a root stays a root now that every join is done
+    }
+    const int lane = threadIdx.x & 63;
+    unsigned long long left = __ballot(pending);
+    while (left) {   // one round per distinct root among the wave's lanes
+        const int leader = __ffsll((long long)left) - 1;
+        const int rl = __shfl(r, leader, 64);
+        const unsigned long long same = __ballot(pending && r == rl);
+        if (lane == leader) atomicAdd(size + rl, (int)__popcll(same));
+        if (pending && r == rl) pending = false;
+        left &= ~same;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_cc_apply(RegionArgs a)
