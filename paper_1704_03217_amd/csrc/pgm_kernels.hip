@@ -116,6 +116,7 @@ __device__ __forceinline__ double group_sum(double v)
 // Rows past the patch side (P < PMAX) read row P - 1 again and add nothing.
 template <int C2, int PMAX, bool FIXED>
 struct IntRow {
+    static constexpr int ROWS = PMAX;
     static constexpr int W3 = C2 / 2;   // dwords per pixel
     using Acc = uint32_t;
     uint32_t a[PMAX][W3];
@@ -190,6 +191,7 @@ struct IntRow {
 // the rounded float result does not depend on the order of summation.
 template <int C2, int PMAX, bool FIXED>
 struct F32Row {
+    static constexpr int ROWS = PMAX;
     using Acc = double;
     using Dist = uint32_t;
     static constexpr bool CAN_BUF = false;
@@ -293,6 +295,11 @@ __device__ __forceinline__ void patch_cost2(const Row& A, const void* Gb, const 
                                             int q0y, int q1x, int q1y, typename Row::Dist& e0,
                                             typename Row::Dist& e1)
 {
+    if constexpr (Row::ROWS == 16) {   // 16-row patches: one at a time (registers for occupancy)
+        e0 = patch_cost<Row, LPS, BUF>(A, Gb, g, P, r, q0x, q0y);
+        e1 = patch_cost<Row, LPS, BUF>(A, Gb, g, P, r, q1x, q1y);
+        return;
+    }
     const int half = P >> 1;
     Row B0, B1;
     B0.template fetch<BUF>(Gb, g, q0x - half, q0y - half, P, r);
