@@ -89,7 +89,10 @@ def summarize_counters(fetch_csv, write_csv, copy_mib):
         if not copies:
             raise SystemExit(f"no calibration copy in {path}")
         scale = (copy_mib << 20) / (max(copies) * 1024.0)     # bytes per counted KiB
-        sweeps = [v for k, g, v in rows if "k_sweep" in k]
+        # the half-sweep variant of the configuration-2 parameters (8x8 patches, integer SAD)
+        sweeps = [v for k, g, v in rows if "k_sweep<6, 8, true, 0" in k]
+        if not sweeps:
+            raise SystemExit(f"no k_sweep<6, 8, true, 0> dispatches in {path}")
         out[name] = dict(kib_per_launch=sum(sweeps) / len(sweeps), scale=scale, launches=len(sweeps),
                          bytes_per_launch=scale * 1024.0 * sum(sweeps) / len(sweeps))
     res = {"kernel": "k_sweep", "workload": "plain pass, one 1024x436 pair per step (bench.py --batch 0)",
