@@ -145,6 +145,8 @@ CASES = {
     # iterations between two with them (entered, checked and left without a sweep)
     "init_radius1": (lambda: synth.rect_pair(25, 60, 80, dmax=2), base_params(levels=2, iters=[3, 3], max_disp=2, rng_seed=27)),
     "level_without_iterations": (lambda: synth.rect_pair(26, 90, 120, dmax=8), base_params(levels=3, iters=[3, 0, 2], max_disp=8, rng_seed=28)),
+    # the deepest pyramid (8 levels: 300x260 down to 3x3)
+    "levels8": (lambda: synth.rect_pair(27, 260, 300, dmax=12), base_params(levels=8, iters=[2] * 8, max_disp=12, rng_seed=29)),
 }
 
 
