@@ -256,6 +256,18 @@ PGM_API pgm_status pgm_profile(void* ctx, int32_t enable);
 PGM_API pgm_status pgm_profile_read(void* ctx, int32_t kind, int64_t* host_launches,
                                     double* host_total_ms, uint64_t* host_evals);
 
+/* Launch schedule of later calls on ctx. The library picks, per level, among schedules that
+ * give identical results: a small level's half-sweeps in one work-group per pair and direction
+ * from LDS or as separate launches, and a level's entry (the coarser level's check, the
+ * transition, the first half-sweep) in one launch or in several. flags 0 (the default) lets it
+ * choose by size and concurrency; the bits force a choice wherever it applies, for tests of
+ * schedule invariance and for measurements. PGM_EINVAL for unknown bits or a contradiction. */
+enum { PGM_SCHED_AUTO = 0,
+       PGM_SCHED_LEVEL_LDS = 1,      /* small levels in one work-group from LDS wherever they fit */
+       PGM_SCHED_LEVEL_LAUNCHES = 2, /* small levels as half-sweep launches                       */
+       PGM_SCHED_SEPARATE = 4 };     /* every check, transition and half-sweep its own launch     */
+PGM_API pgm_status pgm_schedule(void* ctx, int32_t flags);
+
 /* Text of the last error of ctx (or of the last failed pgm_create when ctx is NULL). */
 PGM_API const char* pgm_last_error(void* ctx);
 

@@ -75,7 +75,7 @@ EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_ma
            "pgm_server_create", "pgm_server_submit", "pgm_server_poll", "pgm_server_pending",
            "pgm_server_drain", "pgm_server_last_error", "pgm_server_destroy", "pgm_format_matches",
            "pgm_dump_level",
-           "pgm_dump_gradient", "pgm_dump_pyramid", "pgm_profile", "pgm_profile_read",
+           "pgm_dump_gradient", "pgm_dump_pyramid", "pgm_schedule", "pgm_profile", "pgm_profile_read",
            "pgm_last_error", "pgm_destroy")
 
 # kernel kinds of pgm_profile_read
@@ -140,6 +140,8 @@ def lib():
         L.pgm_dump_gradient.restype = C.c_int32
         L.pgm_dump_pyramid.argtypes = [V, C.c_int32, C.c_int32, V]
         L.pgm_dump_pyramid.restype = C.c_int32
+        L.pgm_schedule.argtypes = [V, C.c_int32]
+        L.pgm_schedule.restype = C.c_int32
         L.pgm_profile.argtypes = [V, C.c_int32]
         L.pgm_profile.restype = C.c_int32
         L.pgm_profile_read.argtypes = [V, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
@@ -309,6 +311,13 @@ def pgm_dump_pyramid(ctx, level: int, image: int, w: int, h: int) -> np.ndarray:
     out = np.zeros((h, w, 3), np.uint8)
     _check(lib().pgm_dump_pyramid(ctx, level, image, out.ctypes.data), ctx)
     return out
+
+
+SCHED_AUTO, SCHED_LEVEL_LDS, SCHED_LEVEL_LAUNCHES, SCHED_SEPARATE = 0, 1, 2, 4
+
+
+def pgm_schedule(ctx, flags: int) -> None:
+    _check(lib().pgm_schedule(ctx, flags), ctx)
 
 
 def pgm_profile(ctx, enable: bool) -> None:

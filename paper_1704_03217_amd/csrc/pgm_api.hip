@@ -233,6 +233,7 @@ struct pgm_ctx_s {
     // the pairs of a call share the GPU with other work (concurrent groups, the server's
     // requests): small levels then run in one work-group per pair and direction
     bool concurrent = false;
+    int sched = PGM_SCHED_AUTO;   // pgm_schedule
     size_t lds_max = 0;            // LDS bytes a work-group may use on this device
     uint8_t* ws = nullptr;
     size_t ws_bytes = 0;
@@ -623,8 +624,9 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     // 65 -> 55 us at 64x28, 8 pairs slightly faster, 32 pairs slightly slower).
     auto lds_level = [&](int k, LevelLayout& lay) {
         const int l = Y.st_level[k];
-        return shared && p->iters[l] > 0 && (npairs >= 16 || c->concurrent) &&
-               level_layout(Y, l, p->iters[l], Y.st_nI[k], c->lds_max, lay);
+        const bool want = (c->sched & PGM_SCHED_LEVEL_LDS) ||
+                          (!(c->sched & PGM_SCHED_LEVEL_LAUNCHES) && (npairs >= 16 || c->concurrent));
+        return shared && p->iters[l] > 0 && want && level_layout(Y, l, p->iters[l], Y.st_nI[k], c->lds_max, lay);
     };
     // Stages whose level is entered from the coarser one in one launch together with the
     // coarser level's check: the transition alone (2; batches under 16 pairs), or also the
@@ -633,7 +635,8 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     // once a level fills the chip). Both directions share the kernels, and patch sides are
     // at most 8 (six-channel float features excepted: their three candidate patches do not
     // fit the registers).
-    const bool can_fuse = shared && std::max(p->patch_fwd, p->patch_bwd) <= 8 && !(Y.kind == 1 && Y.C2 == 6);
+    const bool can_fuse = shared && std::max(p->patch_fwd, p->patch_bwd) <= 8 && !(Y.kind == 1 && Y.C2 == 6) &&
+                          !(c->sched & PGM_SCHED_SEPARATE);
     // The initial level of a random start is entered the same way (3): its starts and its
     // first half-sweep in one launch.
     auto fused = [&](int k) -> int {
@@ -1276,6 +1279,19 @@ pgm_status pgm_dump_pyramid(void* ctx, int32_t level, int32_t image, uint8_t* ho
     } else {
         PGM_HIP(c, hipMemcpy(host_out, c->last_ws + Y.shared_bytes + Y.pyr[image][level], (size_t)w * h * 3, hipMemcpyDeviceToHost));
     }
+    return PGM_OK;
+}
+
+pgm_status pgm_schedule(void* ctx, int32_t flags)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    if (!c) return PGM_EINVAL;
+    const int known = PGM_SCHED_LEVEL_LDS | PGM_SCHED_LEVEL_LAUNCHES | PGM_SCHED_SEPARATE;
+    if (flags & ~known) return fail(c, PGM_EINVAL, "unknown schedule bits");
+    if ((flags & PGM_SCHED_LEVEL_LDS) && (flags & PGM_SCHED_LEVEL_LAUNCHES))
+        return fail(c, PGM_EINVAL, "small levels cannot be both in LDS and launches");
+    c->sched = flags;
+    c->gkey.clear();   // a captured graph holds the old schedule
     return PGM_OK;
 }
 

@@ -172,3 +172,7 @@ def test_format_matches_epicflow_lines(tmp_path):
     assert L.pgm_format_matches(m.ctypes.data, 50, 0, small, 4, C.byref(need)) == pgm.PGM_ENOMEM
     assert need.value == len(text_all)
     assert L.pgm_format_matches(None, 5, 0, None, 0, C.byref(need)) == pgm.PGM_EINVAL
+
+
+def test_schedule_needs_a_context():
+    assert pgm.lib().pgm_schedule(None, 0) == pgm.PGM_EINVAL
