@@ -268,6 +268,19 @@ enum { PGM_SCHED_AUTO = 0,
        PGM_SCHED_SEPARATE = 4 };     /* every check, transition and half-sweep its own launch     */
 PGM_API pgm_status pgm_schedule(void* ctx, int32_t flags);
 
+/* Autotune the launch schedule for one workload: runs pgm_match_batch on the given pairs and
+ * outputs (same layout and rules as pgm_match_batch; the outputs hold the matches afterwards)
+ * once untimed and `repeats` times timed (1..1000) under each schedule pgm_schedule can force
+ * (AUTO, LEVEL_LDS, LEVEL_LAUNCHES, SEPARATE and the two combinations with SEPARATE), keeps the
+ * fastest for later calls on ctx and writes its flags to *host_flags (host, may be NULL).
+ * Synchronous: waits for `stream`. Every schedule gives the same results, so tuning changes
+ * only speed. PGM_EINVAL while profiling is on. */
+PGM_API pgm_status pgm_tune(void* ctx, const pgm_params* p, int32_t n_pairs, const uint8_t* img1,
+                            const uint8_t* img2, int32_t w, int32_t h, int32_t pitch_bytes,
+                            int64_t image_stride_bytes, pgm_match_t* out_fwd, pgm_match_t* out_bwd,
+                            int32_t* out_n_inliers, pgm_match_t* out_compact, int32_t repeats, void* stream,
+                            int32_t* host_flags);
+
 /* Text of the last error of ctx (or of the last failed pgm_create when ctx is NULL). */
 PGM_API const char* pgm_last_error(void* ctx);
 

@@ -75,7 +75,7 @@ EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_ma
            "pgm_server_create", "pgm_server_submit", "pgm_server_poll", "pgm_server_pending",
            "pgm_server_drain", "pgm_server_last_error", "pgm_server_destroy", "pgm_format_matches",
            "pgm_dump_level",
-           "pgm_dump_gradient", "pgm_dump_pyramid", "pgm_schedule", "pgm_profile", "pgm_profile_read",
+           "pgm_dump_gradient", "pgm_dump_pyramid", "pgm_schedule", "pgm_tune", "pgm_profile", "pgm_profile_read",
            "pgm_last_error", "pgm_destroy")
 
 # kernel kinds of pgm_profile_read
@@ -142,6 +142,9 @@ def lib():
         L.pgm_dump_pyramid.restype = C.c_int32
         L.pgm_schedule.argtypes = [V, C.c_int32]
         L.pgm_schedule.restype = C.c_int32
+        L.pgm_tune.argtypes = [V, C.POINTER(pgm_params), C.c_int32, V, V, C.c_int32, C.c_int32, C.c_int32,
+                               C.c_int64, V, V, V, V, C.c_int32, V, C.POINTER(C.c_int32)]
+        L.pgm_tune.restype = C.c_int32
         L.pgm_profile.argtypes = [V, C.c_int32]
         L.pgm_profile.restype = C.c_int32
         L.pgm_profile_read.argtypes = [V, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
@@ -320,6 +323,16 @@ def pgm_schedule(ctx, flags: int) -> None:
     _check(lib().pgm_schedule(ctx, flags), ctx)
 
 
+def pgm_tune(ctx, p, n_pairs: int, img1: int, img2: int, w: int, h: int, pitch_bytes: int, image_stride_bytes: int,
+             out_fwd: int, out_bwd: int | None = None, out_n_inliers: int | None = None,
+             out_compact: int | None = None, repeats: int = 3, stream: int | None = None) -> int:
+    """All pointer arguments are integer device addresses (or None); returns the chosen flags."""
+    flags = C.c_int32(0)
+    _check(lib().pgm_tune(ctx, C.byref(_as_params(p)), n_pairs, img1, img2, w, h, pitch_bytes, image_stride_bytes,
+                          out_fwd, out_bwd, out_n_inliers, out_compact, repeats, stream, C.byref(flags)), ctx)
+    return flags.value
+
+
 def pgm_profile(ctx, enable: bool) -> None:
     _check(lib().pgm_profile(ctx, 1 if enable else 0), ctx)
 
@@ -431,6 +444,24 @@ class Matcher:
                         ptr(o["compact"]), ptr(o["n_evals"]), stream)
         self.last_sizes = o["sizes"]
         return o
+
+    def tune(self, p, img1, img2, o, repeats=3, stream=None):
+        """Pick the fastest launch schedule for this workload (pgm_tune) and keep it for later
+        calls; img1, img2 and o as for match_batch_into (o holds the matches afterwards; its
+        evaluation counter is not written). Returns the chosen SCHED_* flags."""
+        torch = self.torch
+        assert img1.is_cuda and img1.dtype == torch.uint8 and img1.dim() == 4 and img1.shape[3] == 3
+        assert img2.shape == img1.shape and img2.dtype == torch.uint8
+        assert img1.stride()[1:] == img2.stride()[1:] and img1.stride(0) == img2.stride(0)
+        assert img1.stride(3) == 1 and img1.stride(2) == 3
+        B, h, w = img1.shape[:3]
+        assert B == o["n_pairs"]
+        ptr = lambda t: None if t is None else t.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.last_sizes = o["sizes"]
+        return pgm_tune(self.ctx, p, B, img1.data_ptr(), img2.data_ptr(), w, h, img1.stride(1), img1.stride(0),
+                        o["fwd"].data_ptr(), ptr(o["bwd"]), ptr(o["n_inliers"]), ptr(o["compact"]), repeats, stream)
 
     def match_batch(self, p, img1, img2, bwd=True, compact=True, count_evals=True):
         B, h, w = img1.shape[:3]

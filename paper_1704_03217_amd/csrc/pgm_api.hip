@@ -839,6 +839,60 @@ pgm_status pgm_match_batch(void* ctx, const pgm_params* p, int32_t n_pairs, cons
                       out_n_inliers, out_compact, out_n_evals, (hipStream_t)stream, c->ws, c->ws_bytes);
 }
 
+pgm_status pgm_tune(void* ctx, const pgm_params* p, int32_t n_pairs, const uint8_t* img1, const uint8_t* img2,
+                    int32_t w, int32_t h, int32_t pitch_bytes, int64_t image_stride_bytes, pgm_match_t* out_fwd,
+                    pgm_match_t* out_bwd, int32_t* out_n_inliers, pgm_match_t* out_compact, int32_t repeats,
+                    void* stream, int32_t* host_flags)
+{
+    pgm_ctx_s* c = (pgm_ctx_s*)ctx;
+    if (!c) return PGM_EINVAL;
+    if (repeats < 1 || repeats > 1000) return fail(c, PGM_EINVAL, "repeats must be within 1..1000");
+    if (c->prof) return fail(c, PGM_EINVAL, "tuning times the calls itself: turn profiling off first");
+    const hipStream_t s = (hipStream_t)stream;
+    PGM_HIP(c, hipSetDevice(c->device));
+    static const int cand[] = {PGM_SCHED_AUTO,
+                               PGM_SCHED_LEVEL_LDS,
+                               PGM_SCHED_LEVEL_LAUNCHES,
+                               PGM_SCHED_SEPARATE,
+                               PGM_SCHED_LEVEL_LDS | PGM_SCHED_SEPARATE,
+                               PGM_SCHED_LEVEL_LAUNCHES | PGM_SCHED_SEPARATE};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PGM_HIP(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, PGM_EDEVICE, "hipEventCreate failed");
+    }
+    const int saved = c->sched;
+    int best = PGM_SCHED_AUTO;
+    float best_ms = 0.0f;
+    pgm_status st = PGM_OK;
+    for (int f : cand) {
+        c->sched = f;
+        // one untimed call, then the timed ones
+        for (int k = 0; k <= repeats && st == PGM_OK; k++) {
+            if (k == 1 && hipEventRecord(e0, s) != hipSuccess) st = fail(c, PGM_EDEVICE, "hipEventRecord failed");
+            if (st == PGM_OK)
+                st = match_impl(c, p, n_pairs, img1, img2, w, h, pitch_bytes, image_stride_bytes, out_fwd, out_bwd,
+                                out_n_inliers, out_compact, nullptr, s, c->ws, c->ws_bytes);
+        }
+        float ms = 0.0f;
+        if (st == PGM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = fail(c, PGM_EDEVICE, "timing the candidate schedule failed");
+        if (st != PGM_OK) break;
+        if (f == cand[0] || ms < best_ms) {
+            best = f;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->sched = st == PGM_OK ? best : saved;
+    c->gkey.clear();
+    if (st == PGM_OK && host_flags) *host_flags = best;
+    return st;
+}
+
 static pgm_status groups_eager(pgm_ctx_s* c, int32_t n_groups, const pgm_group* gr, const size_t* off,
                                uint64_t* out_n_evals, hipStream_t s)
 {

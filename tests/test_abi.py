@@ -176,3 +176,13 @@ def test_format_matches_epicflow_lines(tmp_path):
 
 def test_schedule_needs_a_context():
     assert pgm.lib().pgm_schedule(None, 0) == pgm.PGM_EINVAL
+
+
+def test_tune_rejects_bad_arguments_without_device_work():
+    L = pgm.lib()
+    p = pgm.pgm_default_params(pgm.PRESET_CONFIG1)
+    f = C.c_int32(-1)
+    # no context
+    assert L.pgm_tune(None, C.byref(p), 1, None, None, 64, 64, 192, 0, None, None, None, None, 1, None,
+                      C.byref(f)) == pgm.PGM_EINVAL
+    assert f.value == -1

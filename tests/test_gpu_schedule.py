@@ -78,3 +78,23 @@ def test_every_schedule_gives_the_same_batch(matcher):
             assert nin[k] == r["n_inliers"] and np.array_equal(comp[k, : nin[k]], r["compact"]), (sched, k)
         assert nev == sum(r["n_evals"] for r in ref), sched
     pgm.pgm_schedule(matcher.ctx, pgm.SCHED_AUTO)
+
+
+def test_tune_picks_a_schedule_and_keeps_the_oracle_result(matcher):
+    torch = matcher.torch
+    prs = [synth.config_pair(1, 60 + k) for k in range(2)]
+    p = CONFIG_PARAMS[1]
+    a = torch.from_numpy(np.stack([q.img1 for q in prs])).cuda()
+    b = torch.from_numpy(np.stack([q.img2 for q in prs])).cuda()
+    ref = [oracle.match(p, q.img1, q.img2, trace=False) for q in prs]
+    print("[gpu schedule] tune two config-1 pairs", file=sys.stderr, flush=True)
+    o = matcher.outputs_batch(p, 256, 192, len(prs))
+    flags = matcher.tune(p, a, b, o, repeats=2)
+    assert flags in SCHEDULES
+    for out in (o, matcher.match_batch_into(p, a, b, matcher.outputs_batch(p, 256, 192, len(prs)))):
+        torch.cuda.synchronize()
+        fwd, bwd, comp, nin, _ = outputs(matcher, out, len(prs))
+        for k, r in enumerate(ref):
+            assert np.array_equal(fwd[k], r["fwd"]) and np.array_equal(bwd[k], r["bwd"]), (flags, k)
+            assert nin[k] == r["n_inliers"] and np.array_equal(comp[k, : nin[k]], r["compact"]), (flags, k)
+    pgm.pgm_schedule(matcher.ctx, pgm.SCHED_AUTO)
