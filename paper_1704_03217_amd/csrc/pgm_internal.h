@@ -158,11 +158,18 @@ struct CountArgs {
     unsigned long long* prof;            // PGM_K_KINDS profiling counters (or null)
 };
 
-// Work-groups of a matching kernel: 256 threads, one seed per 8 lanes (patch side <= 8) or
-// per 16 lanes (side <= 16).
+// Threads per work-group of the matching kernels (k_sweep, k_init, k_down, k_up and the
+// k_enter family): one wave. A launch's waves then spread over as many CUs and L1 caches as
+// there are waves, up to the whole chip; the seeds' dependent memory round trips, not the
+// arithmetic, bound these kernels, and four-wave work-groups left most CUs idle on small
+// levels and balanced worse on large ones.
+constexpr int MATCH_TPB = 64;
+
+// Work-groups of a matching kernel: one seed per 8 lanes (patch side <= 8) or per 16 lanes
+// (side <= 16).
 inline int match_blocks(int groups, int P)
 {
-    const int gpb = 256 / (P <= 8 ? 8 : 16);
+    const int gpb = MATCH_TPB / (P <= 8 ? 8 : 16);
     return (groups + gpb - 1) / gpb;
 }
 
@@ -222,7 +229,7 @@ hipError_t launch_enter(EnterArgs a, int C2, int kind, int mode, hipStream_t s);
 // work-groups of one k_enter launch per direction and pair
 inline int enter_blocks(int nx, int ny, int P, int n_coarse)
 {
-    return 2 * sweep_blocks(nx, ny, P) + (n_coarse + 255) / 256;
+    return 2 * sweep_blocks(nx, ny, P) + (n_coarse + MATCH_TPB - 1) / MATCH_TPB;
 }
 // small-region removal on the level-0 forward field: four launches (labels, unions, region
 // sizes, flags)

@@ -396,13 +396,17 @@ __device__ __forceinline__ DirArgs pair_dir(const DirArgs& d, size_t off)
 __device__ __forceinline__ void count_evals(uint32_t* cnt, int slot, uint32_t nev, bool leader)
 {
     if (!cnt) return;   // uniform over the launch
-    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t wsum[4];   // work-groups of 64 to 256 threads
     uint32_t v = leader ? nev : 0u;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) cnt[slot] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); k++) t += wsum[k];
+        cnt[slot] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -540,11 +544,11 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
 
 // one half-sweep (Step 1, one colour of one iteration) of every seed of the launch
 template <int C2, int PMAX, bool FIXED, int KIND>
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
+__global__ __launch_bounds__(MATCH_TPB) void k_sweep(SweepArgs a)
 {
     using Row = RowT<C2, PMAX, FIXED, KIND>;
     constexpr int LPS = PMAX;
-    constexpr int GPB = 256 / LPS;
+    constexpr int GPB = MATCH_TPB / LPS;
     const Geo& g = a.g;
     const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
     const LBlock lb = logical_block(nbx, a.b.ndir);
@@ -566,11 +570,11 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 // ---------------------------------------------------------------------------------------
 
 template <int C2, int PMAX, bool FIXED, int KIND>
-__global__ __launch_bounds__(256) void k_init(InitArgs a)
+__global__ __launch_bounds__(MATCH_TPB) void k_init(InitArgs a)
 {
     using Row = RowT<C2, PMAX, FIXED, KIND>;
     constexpr int LPS = PMAX;
-    constexpr int GPB = 256 / LPS;
+    constexpr int GPB = MATCH_TPB / LPS;
     const Geo& g = a.g;
     const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
     const LBlock lb = logical_block(nbx, a.b.ndir);
@@ -620,11 +624,11 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
 // ---------------------------------------------------------------------------------------
 
 template <int C2, int PMAX, bool FIXED, int KIND>
-__global__ __launch_bounds__(256) void k_down(TransArgs a)
+__global__ __launch_bounds__(MATCH_TPB) void k_down(TransArgs a)
 {
     using Row = RowT<C2, PMAX, FIXED, KIND>;
     constexpr int LPS = PMAX;
-    constexpr int GPB = 256 / LPS;
+    constexpr int GPB = MATCH_TPB / LPS;
     const Geo& g = a.g;
     const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
     const LBlock lb = logical_block(nbx, a.b.ndir);
@@ -673,11 +677,11 @@ __device__ __forceinline__ int div_round(int num, int den)   // den > 0
 }
 
 template <int C2, int PMAX, bool FIXED, int KIND>
-__global__ __launch_bounds__(256) void k_up(TransArgs a)
+__global__ __launch_bounds__(MATCH_TPB) void k_up(TransArgs a)
 {
     using Row = RowT<C2, PMAX, FIXED, KIND>;
     constexpr int LPS = PMAX;
-    constexpr int GPB = 256 / LPS;
+    constexpr int GPB = MATCH_TPB / LPS;
     const Geo& g = a.g;     // coarse level being entered
     const Geo& f = a.gs;    // finer source level
     const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
@@ -885,7 +889,7 @@ __device__ __forceinline__ void enter_body(const EnterArgs& a)
 {
     using Row = RowT<C2, PMAX, FIXED, KIND>;
     constexpr int LPS = PMAX;
-    constexpr int GPB = 256 / LPS;
+    constexpr int GPB = MATCH_TPB / LPS;
     const int nbx = 2 * a.nb_col + a.nb_chk;
     const LBlock lb = logical_block(nbx, a.b.ndir);
     const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
@@ -895,7 +899,7 @@ __device__ __forceinline__ void enter_body(const EnterArgs& a)
     bool leader = false;
     if (lb.x >= 2 * a.nb_col) {
         // the coarser level's check, one seed per thread
-        const int ps = (lb.x - 2 * a.nb_col) * 256 + threadIdx.x;
+        const int ps = (lb.x - 2 * a.nb_col) * MATCH_TPB + threadIdx.x;
         if (ps < a.gs.nx * a.gs.ny) check_seed(S, O, a.gs, ps, a.fwd_bwd, a.tau2, a.rec_valid);
     } else {
         const DirArgs D = pair_dir(a.d[lb.dir], zo);
@@ -913,21 +917,21 @@ __device__ __forceinline__ void enter_body(const EnterArgs& a)
 
 // the coarser level's check, the transition and the first half-sweep
 template <int C2, int PMAX, bool FIXED, int KIND>
-__global__ __launch_bounds__(256) void k_enter(EnterArgs a)
+__global__ __launch_bounds__(MATCH_TPB) void k_enter(EnterArgs a)
 {
     enter_body<C2, PMAX, FIXED, KIND, true, false>(a);
 }
 
 // the coarser level's check and the transition (both colours take their start only)
 template <int C2, int PMAX, bool FIXED, int KIND>
-__global__ __launch_bounds__(256) void k_enter_start(EnterArgs a)
+__global__ __launch_bounds__(MATCH_TPB) void k_enter_start(EnterArgs a)
 {
     enter_body<C2, PMAX, FIXED, KIND, false, false>(a);
 }
 
 // the initial level's random starts (Sec. III-B, III-D) and its first half-sweep
 template <int C2, int PMAX, bool FIXED, int KIND>
-__global__ __launch_bounds__(256) void k_enter_init(EnterArgs a)
+__global__ __launch_bounds__(MATCH_TPB) void k_enter_init(EnterArgs a)
 {
     enter_body<C2, PMAX, FIXED, KIND, true, true>(a);
 }
@@ -1849,9 +1853,9 @@ hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hi
 
 #define PGM_V(KERNEL, C2_, PM_, FX_)                                                             \
     if (C2 == C2_ && pmax == PM_ && fixed == FX_) {                                              \
-        if (kind == 1) hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, 1>), grid, dim3(256), 0, s, a); \
-        else if (kind == 2) hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, 2>), grid, dim3(256), 0, s, a); \
-        else hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, 0>), grid, dim3(256), 0, s, a);           \
+        if (kind == 1) hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, 1>), grid, dim3(MATCH_TPB), 0, s, a); \
+        else if (kind == 2) hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, 2>), grid, dim3(MATCH_TPB), 0, s, a); \
+        else hipLaunchKernelGGL((KERNEL<C2_, PM_, FX_, 0>), grid, dim3(MATCH_TPB), 0, s, a);           \
         return hipGetLastError();                                                                \
     }
 
@@ -1879,7 +1883,7 @@ hipError_t launch_enter(EnterArgs a, int C2, int kind, int mode, hipStream_t s)
 {
     const int P = a.d[0].P;
     a.nb_col = sweep_blocks(a.g.nx, a.g.ny, P);
-    a.nb_chk = mode == ENTER_LAUNCH_INIT ? 0 : (a.gs.nx * a.gs.ny + 255) / 256;
+    a.nb_chk = mode == ENTER_LAUNCH_INIT ? 0 : (a.gs.nx * a.gs.ny + MATCH_TPB - 1) / MATCH_TPB;
     const int pmax = P <= 8 ? 8 : 16;
     const bool fixed = P == pmax;
     const long long nb = (long long)(2 * a.nb_col + a.nb_chk) * a.b.ndir * a.b.npairs;
