@@ -210,7 +210,7 @@ struct PrepArgs {
     GradArgs grad;           // level 0 (one entry per colour space)
     PyrArgs pyr;
     int with_pyr;
-    int rng_blocks, grad_blocks, grad_tiles;   // filled in by the launcher
+    int rng_blocks, grad_blocks, grad_tiles, pyr_blocks;   // filled in by the launcher
 };
 // feat: PGM_FEAT_* (0 integer gradients, 1 direction-only float, 2 literal signs)
 hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hipStream_t s);

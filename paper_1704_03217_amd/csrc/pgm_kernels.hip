@@ -1662,6 +1662,10 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
 // random numbers of a whole pair: initial displacements and every random-search offset
 // ---------------------------------------------------------------------------------------
 
+// seeds per thread of a random-search work-group: few, short work-groups, so that they do not
+// hold k_prep's LDS slots that the image tiles need
+constexpr int RNG_SPT = 8;
+
 __device__ __forceinline__ int search_off(uint32_t u, int W, int i)
 {
     // floor(R W / 2^i) with R = (2u + 1) / 2^32 - 1, in exact integer arithmetic
@@ -1670,8 +1674,8 @@ __device__ __forceinline__ int search_off(uint32_t u, int W, int i)
 }
 
 // Work-group b of the random numbers: the initial displacements first, then per stage one
-// range per (direction, iteration) in which thread x draws every search offset of seed
-// 256 c + x (one Philox block per two offsets).
+// range per (direction, iteration) in which thread x of chunk c draws every search offset of
+// seeds 256 (RNG_SPT c + m) + x, m < RNG_SPT (one Philox block per two offsets).
 __device__ __forceinline__ void rng_block(const RngArgs& a, int b)
 {
     if (b < a.init_blocks) {
@@ -1691,23 +1695,27 @@ __device__ __forceinline__ void rng_block(const RngArgs& a, int b)
     const int local = b - S.b0;
     const int q = local / S.bpt, chunk = local - q * S.bpt;
     const int dir = q / S.iters, t = q - dir * S.iters;
-    const int s = chunk * 256 + (int)threadIdx.x;
-    if (s >= S.n) return;
     const uint32_t w1 = (uint32_t)t | ((uint32_t)S.level << 8) | ((uint32_t)dir << 16) | (1u << 24);
-    short2* out = a.table + S.base + (((long long)dir * S.iters + t) * S.n + s) * S.nI;
-    for (int i0 = 0; i0 < S.nI; i0 += 2) {
-        const uint4 u = philox4x32_10(make_uint4((uint32_t)s, w1, (uint32_t)(i0 >> 1), (uint32_t)S.stage), a.key0, a.key1);
-        out[i0] = make_short2((short)search_off(u.x, S.W, i0), (short)search_off(u.y, S.W, i0));
-        if (i0 + 1 < S.nI)
-            out[i0 + 1] = make_short2((short)search_off(u.z, S.W, i0 + 1), (short)search_off(u.w, S.W, i0 + 1));
+    for (int m = 0; m < RNG_SPT; m++) {
+        const int s = (chunk * RNG_SPT + m) * 256 + (int)threadIdx.x;
+        if (s >= S.n) return;
+        short2* out = a.table + S.base + (((long long)dir * S.iters + t) * S.n + s) * S.nI;
+        for (int i0 = 0; i0 < S.nI; i0 += 2) {
+            const uint4 u = philox4x32_10(make_uint4((uint32_t)s, w1, (uint32_t)(i0 >> 1), (uint32_t)S.stage), a.key0, a.key1);
+            out[i0] = make_short2((short)search_off(u.x, S.W, i0), (short)search_off(u.y, S.W, i0));
+            if (i0 + 1 < S.nI)
+                out[i0 + 1] = make_short2((short)search_off(u.z, S.W, i0 + 1), (short)search_off(u.w, S.W, i0 + 1));
+        }
     }
 }
 
 // ---------------------------------------------------------------------------------------
 // kernels of the image stage. k_prep starts a call with three independent jobs in one launch
-// (work-group ranges): the random numbers, the level-0 gradient images and the first pyramid
-// level; k_pyr builds the further pyramid levels and k_gradient their gradient images (all
-// levels in one launch: blockIdx.x runs over the tiles of each level in turn).
+// (work-group ranges): the level-0 gradient images, the first pyramid levels and the random
+// numbers (dispatched in that order: the tiles' longer work-groups first, the short random
+// ones filling in behind them); k_pyr builds the further pyramid levels and k_gradient their
+// gradient images (all levels in one launch: blockIdx.x runs over the tiles of each level in
+// turn).
 // ---------------------------------------------------------------------------------------
 
 constexpr int PREP_LDS = GR_LDS > PY_LDS ? (GR_LDS > P2_LDS ? GR_LDS : P2_LDS) : (PY_LDS > P2_LDS ? PY_LDS : P2_LDS);
@@ -1718,11 +1726,6 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
     __shared__ uint32_t lds[PREP_LDS];
     __shared__ double lin[256];
     int b = blockIdx.x;
-    if (b < a.rng_blocks) {
-        rng_block(a.rng, b);
-        return;
-    }
-    b -= a.rng_blocks;
     if (b < a.grad_blocks) {   // level 0 in each colour space it needs
         const int z = b / a.grad_tiles, tt = b - z * a.grad_tiles;
         int e = 0;
@@ -1731,8 +1734,12 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
         return;
     }
     b -= a.grad_blocks;
-    if (a.pyr.two) pyr2_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
-    else pyr_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
+    if (b < a.pyr_blocks) {
+        if (a.pyr.two) pyr2_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
+        else pyr_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
+        return;
+    }
+    rng_block(a.rng, b - a.pyr_blocks);
 }
 
 __global__ __launch_bounds__(256) void k_pyr(PyrArgs a)
@@ -1813,7 +1820,7 @@ hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hi
     r.init_blocks = (int)((2LL * r.n_top + 255) / 256);
     long long nb = 0;
     for (int k = 0; k < r.nstages; k++) {
-        r.st[k].bpt = (r.st[k].n + 255) / 256;
+        r.st[k].bpt = (r.st[k].n + 256 * RNG_SPT - 1) / (256 * RNG_SPT);
         r.st[k].b0 = (int)nb;
         nb += 2LL * r.st[k].iters * r.st[k].bpt;
         if (nb > 0x40000000LL) return hipErrorInvalidValue;
@@ -1821,8 +1828,12 @@ hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hi
     a.rng_blocks = r.init_blocks + (int)nb;
     a.grad_tiles = plan_grad(a.grad);
     a.grad_blocks = a.grad_tiles * 2 * npairs;
-    if (a.with_pyr) plan_pyr(a.pyr);
-    const long long blocks = (long long)a.rng_blocks + a.grad_blocks + (a.with_pyr ? (long long)a.pyr.tiles * 2 * npairs : 0);
+    a.pyr_blocks = 0;
+    if (a.with_pyr) {
+        plan_pyr(a.pyr);
+        a.pyr_blocks = a.pyr.tiles * 2 * npairs;
+    }
+    const long long blocks = (long long)a.rng_blocks + a.grad_blocks + a.pyr_blocks;
     if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
 #define PGM_PREP(KS, GR, F)                                                                       \
     if (ksize == KS && !!gray == GR && feat == F) {                                                \
