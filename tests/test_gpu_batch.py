@@ -91,3 +91,60 @@ def test_batch_too_large_is_enomem(matcher):
         assert ok["n_inliers"].shape[0] == 2
     finally:
         small.close()
+
+
+def _check_pairs(params, pairs, fwd, bwd, comp, nin, nev, tag):
+    total = 0
+    for k, pr in enumerate(pairs):
+        r = oracle.match(params, pr.img1, pr.img2, trace=False)
+        assert np.array_equal(fwd[k], r["fwd"]), f"{tag}: pair {k} fwd"
+        assert np.array_equal(bwd[k], r["bwd"]), f"{tag}: pair {k} bwd"
+        assert nin[k] == r["n_inliers"], f"{tag}: pair {k} inliers"
+        assert np.array_equal(comp[k, : nin[k]], r["compact"]), f"{tag}: pair {k} compact"
+        total += r["n_evals"]
+    assert nev == total, tag
+
+
+def test_batch_padded_pitch_and_image_stride(matcher):
+    """Pairs cut out of larger frames: rows longer than the image and a gap between images."""
+    torch = matcher.torch
+    pairs = [synth.config_pair(1, 20 + i) for i in range(3)]
+    params = CONFIG_PARAMS[1]
+    h, w = pairs[0].img1.shape[:2]
+    print("[gpu batch] padded pitch and image stride", file=sys.stderr, flush=True)
+    big = [np.full((3, h + 3, w + 5, 3), 77, np.uint8) for _ in range(2)]
+    for k, pr in enumerate(pairs):
+        big[0][k, :h, :w] = pr.img1
+        big[1][k, :h, :w] = pr.img2
+    a = torch.from_numpy(big[0]).cuda()[:, :h, :w]
+    b = torch.from_numpy(big[1]).cuda()[:, :h, :w]
+    assert a.stride(1) == (w + 5) * 3 and a.stride(0) == (h + 3) * (w + 5) * 3
+    o = matcher.match_batch(params, a, b)
+    torch.cuda.synchronize()
+    n = o["n"]
+    fwd = matcher.to_numpy(o["fwd"]).reshape(len(pairs), n)
+    bwd = matcher.to_numpy(o["bwd"]).reshape(len(pairs), n)
+    comp = matcher.to_numpy(o["compact"]).reshape(len(pairs), n)
+    _check_pairs(params, pairs, fwd, bwd, comp, o["n_inliers"].cpu().numpy(), int(o["n_evals"].item()), "padded")
+
+
+@pytest.mark.parametrize("name,params", [
+    ("direction_patch11_9", base_params(feature=1, patch_fwd=11, patch_bwd=9, max_disp=6, rng_seed=41)),
+    ("gray_patch13", base_params(color=1, patch_fwd=13, patch_bwd=13, max_disp=6, rng_seed=42)),
+    ("ssd_patch8", base_params(metric=1, max_disp=6, rng_seed=43)),
+    ("sign_patch16", base_params(feature=2, patch_fwd=16, patch_bwd=16, max_disp=6, rng_seed=44)),
+])
+def test_batch16_small_levels_in_lds(matcher, name, params):
+    """Sixteen small pairs: at 16 pairs or more every level that fits in LDS runs in one
+    work-group per pair and direction, here with 16-lane patches, gray, float direction
+    features, signs and squared differences."""
+    pairs = [synth.rect_pair(60 + i, 48, 64, n_rect=2, dmax=6) for i in range(16)]
+    print(f"[gpu batch] batch16 {name}", file=sys.stderr, flush=True)
+    pgm.pgm_profile(matcher.ctx, True)
+    try:
+        fwd, bwd, comp, nin, nev = run_batch(matcher, params, pairs)
+        launches, _, _ = pgm.pgm_profile_read(matcher.ctx, pgm.K_LEVEL)
+    finally:
+        pgm.pgm_profile(matcher.ctx, False)
+    assert launches > 0, "no level ran in LDS"
+    _check_pairs(params, pairs, fwd, bwd, comp, nin, nev, name)
