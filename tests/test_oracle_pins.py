@@ -373,15 +373,18 @@ def _interior(pts, w, h, d, margin):
     return out
 
 
-@pytest.mark.parametrize("dx,dy,L,init_mode", [(5, -3, 1, 1), (-7, 2, 1, 0), (10, -6, 2, 0),
-                                                (12, 8, 3, 0), (0, 0, 2, 0), (0, 0, 1, 1)])
-def test_translation_recovered_exactly(dx, dy, L, init_mode):
+@pytest.mark.parametrize("dx,dy,L,init_mode,N", [(5, -3, 1, 1, 0), (-7, 2, 1, 0, 0), (10, -6, 2, 0, 0),
+                                                  (12, 8, 3, 0, 0), (0, 0, 2, 0, 0), (0, 0, 1, 1, 0),
+                                                  (12, 8, 3, 0, 2), (-8, 4, 3, 1, 1), (4, -6, 2, 0, 3)])
+def test_translation_recovered_exactly(dx, dy, L, init_mode, N):
     """An integer translation is recovered exactly at interior seeds (distance 0, inlier) and
     the backward field is its negative. Below the top level the translation must be divisible
-    by 2^level for the coarser images to be exact translations too."""
+    by 2^level for the coarser images to be exact translations too. With N refinement rounds
+    (Sec. III-D) the result must be the same (the lift itself is pinned separately: a uniform
+    translation heals a wrong lift at the finer levels)."""
     h, w = 72, 96
     pair = synth.translate_pair(11 + dx, h, w, dx, dy)
-    p = base_params(levels=L, iters=[8] * L, max_disp=16, init_mode=init_mode, rng_seed=3)
+    p = base_params(levels=L, iters=[8] * L, max_disp=16, init_mode=init_mode, refine_rounds=N, rng_seed=3)
     r = oracle.match(p, pair.img1, pair.img2)
     pts = _seed_pts(w, h, 3)
     margin = 4 + 3 + 1
@@ -394,6 +397,31 @@ def test_translation_recovered_exactly(dx, dy, L, init_mode):
         assert st_f[s, 3] & oracle.F_INLIER
     for s in bin_:
         assert (st_b[s, 0], st_b[s, 1], st_b[s, 2]) == (-dx, -dy, 0)
+
+
+def test_refinement_lift_halves_the_mean_of_inlier_children():
+    """Refinement (Sec. III-D, Eq. 6 toward the coarser level): with the coarsest level never
+    iterated, its final field is the lift of the finer level's inliers. Under a translation d
+    divisible by 4, the exhaustive start finds d/4 at level 2, level 1 holds d/2 and keeps it
+    (distance 0 cannot be beaten), so the lift must give d/4 back at every interior seed that
+    has an inlier child; without the halving it would give d/2."""
+    h, w, dx, dy = 144, 192, 8, -4
+    pair = synth.translate_pair(31, h, w, dx, dy)
+    p = base_params(levels=3, iters=[4, 4, 0], max_disp=16, init_mode=1, refine_rounds=1, rng_seed=5)
+    r = oracle.match(p, pair.img1, pair.img2)
+    lw, lh, nx, ny = r["geometry"][2]
+    st = r["levels"][0][2]
+    checked = 0
+    for j in range(ny):
+        for i in range(nx):
+            x, y = oracle.grid_pos(i, lw, 3), oracle.grid_pos(j, lh, 3)
+            if not (6 <= x < lw - 6 and 6 <= y < lh - 6):
+                continue
+            s = j * nx + i
+            if st[s, 3] & oracle.F_INIT:
+                assert (st[s, 0], st[s, 1]) == (dx // 4, dy // 4), (i, j, st[s].tolist())
+                checked += 1
+    assert checked >= 40
 
 
 def _nearest_idx(x, n, stride):
