@@ -104,6 +104,17 @@ def check_features(m, params, img1, img2, name):
     assert not problems, f"{name}: " + " | ".join(problems)
 
 
+def tie_pair(kind, h=40, w=56):
+    """Degenerate inputs whose candidate costs tie: flat images (all gradients zero) and
+    vertical stripes of period 4."""
+    if kind == "flat":
+        img = np.full((h, w, 3), 100, np.uint8)
+    else:
+        col = np.array([30, 90, 200, 140], np.uint8)[np.arange(w) % 4]
+        img = np.repeat(np.repeat(col[None, :, None], h, axis=0), 3, axis=2)
+    return synth.Pair(img, img.copy(), np.zeros((h, w, 2), np.float32), np.ones((h, w), bool))
+
+
 CASES = {
     "config1": (lambda: synth.config_pair(1), CONFIG_PARAMS[1]),
     "config1_s3_patch5_11": (lambda: synth.config_pair(1), base_params(sobel_ksize=3, patch_fwd=5, patch_bwd=11, rng_seed=7)),
@@ -145,6 +156,12 @@ CASES = {
     # iterations between two with them (entered, checked and left without a sweep)
     "init_radius1": (lambda: synth.rect_pair(25, 60, 80, dmax=2), base_params(levels=2, iters=[3, 3], max_disp=2, rng_seed=27)),
     "level_without_iterations": (lambda: synth.rect_pair(26, 90, 120, dmax=8), base_params(levels=3, iters=[3, 0, 2], max_disp=8, rng_seed=28)),
+    # ties everywhere: flat images (zero gradients) and periodic stripes, with the exhaustive
+    # start (first minimum in scan order) and with random starts and the full pyramid
+    "flat_exhaustive": (lambda: tie_pair("flat"), base_params(levels=2, iters=[2, 2], init_mode=1, max_disp=6, rng_seed=35)),
+    "flat_random": (lambda: tie_pair("flat"), base_params(levels=3, iters=[3, 3, 3], max_disp=8, rng_seed=36)),
+    "stripes_exhaustive": (lambda: tie_pair("stripes"), base_params(levels=2, iters=[2, 2], init_mode=1, max_disp=6, patch_fwd=5, patch_bwd=5, rng_seed=37)),
+    "stripes_random": (lambda: tie_pair("stripes"), base_params(levels=3, iters=[3, 3, 3], max_disp=8, rng_seed=38)),
     # the deepest pyramid (8 levels: 300x260 down to 3x3)
     "levels8": (lambda: synth.rect_pair(27, 260, 300, dmax=12), base_params(levels=8, iters=[2] * 8, max_disp=12, rng_seed=29)),
 }

@@ -310,9 +310,23 @@ def _seed_pts(w, h, stride):
     return [(oracle.grid_pos(i, w, stride), oracle.grid_pos(j, h, stride)) for j in range(ny) for i in range(nx)]
 
 
-@pytest.mark.parametrize("seed,P", [(1, 8), (2, 5), (3, 1)])
+def _tie_pair(kind):
+    """Image pairs whose window costs tie: flat images (every candidate costs 0) and vertical
+    stripes of period 4 (candidates tie along every column shift by 4 and every row shift)."""
+    h, w = 20, 24
+    if kind == "flat":
+        img = np.full((h, w, 3), 100, np.uint8)
+    else:
+        col = np.array([30, 90, 200, 140], np.uint8)[np.arange(w) % 4]
+        img = np.repeat(np.repeat(col[None, :, None], h, axis=0), 3, axis=2)
+    return synth.Pair(img, img.copy(), np.zeros((h, w, 2), np.float32), np.ones((h, w), bool))
+
+
+@pytest.mark.parametrize("seed,P", [(1, 8), (2, 5), (3, 1), ("flat", 8), ("stripes", 5)])
 def test_exhaustive_init_is_brute_force_argmin(seed, P):
-    pair = synth.rect_pair(seed, 20, 24, n_rect=2, dmax=4)
+    """The exhaustive start is the window's argmin, scanning dy outer and dx inner and keeping
+    the first minimum (strictly smaller wins), which the tie cases pin."""
+    pair = synth.rect_pair(seed, 20, 24, n_rect=2, dmax=4) if isinstance(seed, int) else _tie_pair(seed)
     p = base_params(levels=1, iters=[0], init_mode=1, max_disp=0, patch_fwd=P, patch_bwd=P)
     r = oracle.match(p, pair.img1, pair.img2)
     G1, G2 = _features(pair.img1), _features(pair.img2)
@@ -475,6 +489,30 @@ def test_consistency_and_record_invariants(tau):
                 np.testing.assert_array_equal(rec, par_inl)
             if tau >= 10**6:
                 np.testing.assert_array_equal(inl, init & binit & (rec if carried else True))
+
+
+@pytest.mark.parametrize("cfg_index,levels", [(0, 4), (1, 5)])
+def test_outlier_record_is_monotone(cfg_index, levels):
+    """Sec. III-C/D: a seed judged an outlier stays one at the following levels, so wherever the
+    record is carried (the levels below m-1), a seed can only be an inlier if the coarser seed
+    it descends from was one; the data must also contain consistent-looking seeds that the
+    record turns into outliers, or the pin would test nothing."""
+    pair = synth.config_pair(1, cfg_index)
+    p = base_params(levels=levels, iters=[3] * levels, max_disp=20, rng_seed=11 + cfg_index)
+    r = oracle.match(p, pair.img1, pair.img2)
+    blocked = 0
+    for l in range(levels - 2):                   # levels carrying the record: below m - 1
+        lw, lh, nx, ny = _geom(r, l)
+        pw, ph, pnx, pny = _geom(r, l + 1)
+        px = np.tile([oracle.grid_pos(i, lw, 3) for i in range(nx)], ny)
+        py = np.repeat([oracle.grid_pos(j, lh, 3) for j in range(ny)], nx)
+        parent = _nearest_idx(py // 2, pny, 3) * pnx + _nearest_idx(px // 2, pnx, 3)
+        for d in range(2):
+            child_in = (r["levels"][d][l][:, 3] & oracle.F_INLIER) > 0
+            par_in = (r["levels"][d][l + 1][parent, 3] & oracle.F_INLIER) > 0
+            assert not (child_in & ~par_in).any(), (l, d, int((child_in & ~par_in).sum()))
+            blocked += int((~par_in & ((r["levels"][d][l][:, 3] & oracle.F_INIT) > 0)).sum())
+    assert blocked > 0
 
 
 def test_level_down_transition():
