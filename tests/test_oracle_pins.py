@@ -413,6 +413,36 @@ def test_translation_recovered_exactly(dx, dy, L, init_mode, N):
         assert (st_b[s, 0], st_b[s, 1], st_b[s, 2]) == (-dx, -dy, 0)
 
 
+def test_ties_keep_the_current_match():
+    """Sec. III-B reading: a candidate replaces the match only if strictly better. On flat
+    images every patch distance is 0, so propagation and random search only meet ties and the
+    iterated field must equal the random start."""
+    pair = _tie_pair("flat")
+    base = dict(levels=1, max_disp=6, fwd_bwd=0, rng_seed=21)
+    r0 = oracle.match(base_params(iters=[0], **base), pair.img1, pair.img2)
+    r3 = oracle.match(base_params(iters=[3], **base), pair.img1, pair.img2)
+    for d in range(2):
+        a, b = r0["levels"][d][0], r3["levels"][d][0]
+        np.testing.assert_array_equal(a[:, :3], b[:, :3])
+    assert r3["n_evals"] > r0["n_evals"]        # the ties were evaluated, not skipped
+
+
+def test_exact_cancellation_is_consistent_at_tau_zero():
+    """The check accepts displacements that cancel within tau pixels, tau included (the reading
+    of Sec. III-C/E): at tau = 0 a pure translation, whose forward and backward fields cancel
+    exactly, must leave its interior seeds inliers at every level."""
+    h, w, dx, dy = 72, 96, 8, -4
+    pair = synth.translate_pair(17, h, w, dx, dy)
+    p = base_params(levels=2, iters=[8, 8], max_disp=16, consistency_px=0, rng_seed=4)
+    r = oracle.match(p, pair.img1, pair.img2)
+    pts = _seed_pts(w, h, 3)
+    fin = _interior(pts, w, h, (dx, dy), 4 + 3 + 1)
+    assert len(fin) > 100
+    st = r["levels"][0][0]
+    for s in fin:
+        assert (st[s, 0], st[s, 1]) == (dx, dy) and st[s, 3] & oracle.F_INLIER, (s, st[s].tolist())
+
+
 def test_refinement_lift_halves_the_mean_of_inlier_children():
     """Refinement (Sec. III-D, Eq. 6 toward the coarser level): with the coarsest level never
     iterated, its final field is the lift of the finer level's inliers. Under a translation d
