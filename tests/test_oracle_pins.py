@@ -245,6 +245,22 @@ def test_search_offset_is_exact_floor():
     assert {oracle.search_offset(u, 2, 1) for u in (0, 2**31)} == {-1, 0}
 
 
+@pytest.mark.parametrize("W,expected", [(1, 150.0), (2, 337.5), (13, 775.0)])
+def test_random_search_takes_floor_log2_W_plus_one_candidates(W, expected):
+    """Eq. 5: the limited random search tries i = 0 .. floor(log2 W), one candidate each. A
+    lone seed (no neighbours to propagate from) on flat gradients (every cost ties, so the
+    match never moves) evaluates every candidate whose offset is not (0, 0); over 200
+    iterations the count is near 200 * sum_i (1 - P(offset_i = 0)^2), which one candidate
+    more or fewer would move by more than 18%."""
+    h, w = 41, 41
+    G = np.zeros((h, w, 6), np.int16)
+    p = base_params(levels=1, seed_stride=w, max_disp=0, rng_seed=97)
+    st = dict(dx=[0], dy=[0], dist=[0], init=[1])
+    out, nev = oracle.sweep(p, G, G, st, W=W, t0=0, n_iter=200)
+    assert (out["dx"][0], out["dy"][0]) == (0, 0)
+    assert abs(nev - expected) <= 0.1 * expected, (W, nev, expected)
+
+
 def test_init_offset_is_exact_and_uniform():
     for R in (0, 1, 5, 13, 16, 300):
         for u in [0, 2**32 - 1] + [int(v) for v in RNG.integers(0, 2**32, 200, dtype=np.int64)]:
