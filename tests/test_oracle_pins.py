@@ -541,8 +541,8 @@ def test_consistency_and_record_invariants(tau):
 def test_outlier_record_is_monotone(cfg_index, levels):
     """Sec. III-C/D: a seed judged an outlier stays one at the following levels, so wherever the
     record is carried (the levels below m-1), a seed can only be an inlier if the coarser seed
-    it descends from was one; the data must also contain consistent-looking seeds that the
-    record turns into outliers, or the pin would test nothing."""
+    it descends from was one; the data must also contain seeds under outlier parents, or the
+    pin would test nothing. Level m-1 receives the field without the record."""
     pair = synth.config_pair(1, cfg_index)
     p = base_params(levels=levels, iters=[3] * levels, max_disp=20, rng_seed=11 + cfg_index)
     r = oracle.match(p, pair.img1, pair.img2)
@@ -559,6 +559,20 @@ def test_outlier_record_is_monotone(cfg_index, levels):
             assert not (child_in & ~par_in).any(), (l, d, int((child_in & ~par_in).sum()))
             blocked += int((~par_in & ((r["levels"][d][l][:, 3] & oracle.F_INIT) > 0)).sum())
     assert blocked > 0
+    # the field enters level m-1 without the record of level m (the one link of Sec. III-D that
+    # carries the field only), so there some inliers descend from outliers
+    l = levels - 2
+    lw, lh, nx, ny = _geom(r, l)
+    pw, ph, pnx, pny = _geom(r, l + 1)
+    px = np.tile([oracle.grid_pos(i, lw, 3) for i in range(nx)], ny)
+    py = np.repeat([oracle.grid_pos(j, lh, 3) for j in range(ny)], nx)
+    parent = _nearest_idx(py // 2, pny, 3) * pnx + _nearest_idx(px // 2, pnx, 3)
+    freed = 0
+    for d in range(2):
+        child_in = (r["levels"][d][l][:, 3] & oracle.F_INLIER) > 0
+        par_in = (r["levels"][d][l + 1][parent, 3] & oracle.F_INLIER) > 0
+        freed += int((child_in & ~par_in).sum())
+    assert freed > 0
 
 
 def test_level_down_transition():
