@@ -1338,7 +1338,10 @@ __device__ __forceinline__ void pyr_tile(const PyrArgs& a, int t, int z, uint32_
 constexpr int P2_TW = 32, P2_TH = 2;
 constexpr int P2_C1 = 2 * P2_TW + 3, P2_R1 = 2 * P2_TH + 3;   // level-(l+1) block
 constexpr int P2_SU = 2 * P2_C1 + 3, P2_SV = 2 * P2_R1 + 3;   // level-l block
-constexpr int P2_LDS = P2_SV * P2_SU + 2 * P2_SV * P2_C1 + P2_R1 * P2_C1 + 2 * P2_R1 * P2_TW;   // dwords
+// the level-(l+1) block reuses the staged block's space and its row sums the first row sums'
+// space (each is written after a barrier that ends the last read of what it replaces)
+constexpr int P2_LDS = P2_SV * P2_SU + 2 * P2_SV * P2_C1;   // dwords
+static_assert(P2_R1 * P2_C1 <= P2_SV * P2_SU && 2 * P2_R1 * P2_TW <= 2 * P2_SV * P2_C1, "pyramid tile aliasing");
 
 __device__ __forceinline__ uint32_t rg_pair(uint32_t q) { return (q & 0xFFu) | ((q & 0xFF00u) << 8); }
 
@@ -1346,8 +1349,8 @@ __device__ __forceinline__ void pyr2_tile(const PyrArgs& a, int t, int z, uint32
 {
     uint32_t* S0 = lds;                        // [P2_SV][P2_SU] staged level-l pixels
     uint32_t* H0 = S0 + P2_SV * P2_SU;         // [P2_SV][P2_C1][2] row sums (RG, B)
-    uint32_t* V1 = H0 + 2 * P2_SV * P2_C1;     // [P2_R1][P2_C1] level-(l+1) pixels
-    uint32_t* H1 = V1 + P2_R1 * P2_C1;         // [P2_R1][P2_TW][2] row sums of level l+1
+    uint32_t* V1 = S0;                         // [P2_R1][P2_C1] level-(l+1) pixels (S0 is dead)
+    uint32_t* H1 = H0;                         // [P2_R1][P2_TW][2] row sums of level l+1 (H0 is dead)
     const int w0 = a.w, h0 = a.h, w1 = (w0 + 1) >> 1, h1 = (h0 + 1) >> 1, w2 = (w1 + 1) >> 1, h2 = (h1 + 1) >> 1;
     const int X0 = (t % a.tx) * P2_TW, Y0 = (t / a.tx) * P2_TH;
     const size_t pair = (size_t)(z >> 1);
@@ -1509,15 +1512,18 @@ __device__ uint32_t to_lab(uint32_t rgb, const double* lin)
            (lab_u8(200.0 * (fy - fz) + 128.0) << 16);
 }
 
-// A work-group computes a 64 x 16 tile of the padded gradient image (64 x 8 was 1.4% slower on
-// 32-pair batches, 64 x 32 slower everywhere). It stages the source pixels (one dword per
+// A work-group computes a 64 x 12 tile of the padded gradient image (64 x 8 was slower on
+// 32-pair batches, 64 x 32 everywhere; 64 x 12 keeps k_prep's LDS at 8 work-groups per CU). It stages the source pixels (one dword per
 // pixel: R | G << 8 | B << 16, or the integer luma) that the windows of its pixels read -- the
 // padding maps to the nearest image pixel, the filter reflects (101) -- applies the smoothing
 // and derivative taps along the staged rows, then across them: the Sobel sums are separable,
-// so the integer results equal the full KS x KS sums. Its LDS holds the staged pixels and one
-// packed (smoothing, derivative) plane per colour channel.
-constexpr int GR_TW = 64, GR_TH = 16, GR_SU = GR_TW + 4, GR_SV = GR_TH + 4;   // kernel radius <= 2
+// so the integer results equal the full KS x KS sums. Its LDS holds the staged pixels, one
+// packed (smoothing, derivative) plane per colour channel and, after them, the sRGB
+// linearisation table of the CIELab conversion (GR_LIN dwords, 256 doubles).
+constexpr int GR_TW = 64, GR_TH = 12, GR_SU = GR_TW + 4, GR_SV = GR_TH + 4;   // kernel radius <= 2
 constexpr int GR_LDS = GR_SV * GR_SU + GR_SV * GR_TW * 3;                     // dwords
+constexpr int GR_LIN = 2 * 256;
+static_assert(GR_LDS % 2 == 0, "the linearisation table is 8-byte aligned");
 
 // FEAT: 0 integer gradients, 1 direction-only unit vectors (float), 2 literal signs
 template <int KS, bool GRAY, int FEAT>
@@ -1713,35 +1719,36 @@ __device__ __forceinline__ void rng_block(const RngArgs& a, int b)
 
 // ---------------------------------------------------------------------------------------
 // kernels of the image stage. k_prep starts a call with three independent jobs in one launch
-// (work-group ranges): the level-0 gradient images, the first pyramid levels and the random
-// numbers (dispatched in that order: the tiles' longer work-groups first, the short random
-// ones filling in behind them); k_pyr builds the further pyramid levels and k_gradient their
+// (work-group ranges): the first pyramid levels, the level-0 gradient images and the random
+// numbers (dispatched in that order: the longest work-groups first, the random ones, which
+// need no LDS, filling in behind them); k_pyr builds the further pyramid levels and k_gradient their
 // gradient images (all levels in one launch: blockIdx.x runs over the tiles of each level in
 // turn).
 // ---------------------------------------------------------------------------------------
 
-constexpr int PREP_LDS = GR_LDS > PY_LDS ? (GR_LDS > P2_LDS ? GR_LDS : P2_LDS) : (PY_LDS > P2_LDS ? PY_LDS : P2_LDS);
+constexpr int PREP_LDS = (GR_LDS + GR_LIN) > PY_LDS ? ((GR_LDS + GR_LIN) > P2_LDS ? GR_LDS + GR_LIN : P2_LDS)
+                                                    : (PY_LDS > P2_LDS ? PY_LDS : P2_LDS);
 
 template <int KS, bool GRAY, int FEAT>
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
 {
-    __shared__ uint32_t lds[PREP_LDS];
-    __shared__ double lin[256];
+    __shared__ __align__(16) uint32_t lds[PREP_LDS];
     int b = blockIdx.x;
-    if (b < a.grad_blocks) {   // level 0 in each colour space it needs
-        const int z = b / a.grad_tiles, tt = b - z * a.grad_tiles;
-        int e = 0;
-        while (e + 1 < a.grad.n && tt >= a.grad.lv[e + 1].base) e++;
-        grad_tile<KS, GRAY, FEAT>(a.grad.lv[e], a.grad.dst_zs, tt - a.grad.lv[e].base, z, lds, lin);
-        return;
-    }
-    b -= a.grad_blocks;
     if (b < a.pyr_blocks) {
         if (a.pyr.two) pyr2_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
         else pyr_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
         return;
     }
-    rng_block(a.rng, b - a.pyr_blocks);
+    b -= a.pyr_blocks;
+    if (b < a.grad_blocks) {   // level 0 in each colour space it needs
+        const int z = b / a.grad_tiles, tt = b - z * a.grad_tiles;
+        int e = 0;
+        while (e + 1 < a.grad.n && tt >= a.grad.lv[e + 1].base) e++;
+        grad_tile<KS, GRAY, FEAT>(a.grad.lv[e], a.grad.dst_zs, tt - a.grad.lv[e].base, z, lds,
+                                  (double*)(lds + GR_LDS));
+        return;
+    }
+    rng_block(a.rng, b - a.grad_blocks);
 }
 
 __global__ __launch_bounds__(256) void k_pyr(PyrArgs a)
@@ -1754,11 +1761,11 @@ __global__ __launch_bounds__(256) void k_pyr(PyrArgs a)
 template <int KS, bool GRAY, int FEAT>
 __global__ __launch_bounds__(256) void k_gradient(GradArgs a)
 {
-    __shared__ uint32_t lds[GR_LDS];
-    __shared__ double lin[256];
+    __shared__ __align__(16) uint32_t lds[GR_LDS + GR_LIN];
     int lv = 0;
     while (lv + 1 < a.n && (int)blockIdx.x >= a.lv[lv + 1].base) lv++;
-    grad_tile<KS, GRAY, FEAT>(a.lv[lv], a.dst_zs, (int)blockIdx.x - a.lv[lv].base, blockIdx.y, lds, lin);
+    grad_tile<KS, GRAY, FEAT>(a.lv[lv], a.dst_zs, (int)blockIdx.x - a.lv[lv].base, blockIdx.y, lds,
+                              (double*)(lds + GR_LDS));
 }
 
 // ---------------------------------------------------------------------------------------
