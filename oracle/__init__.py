@@ -146,6 +146,20 @@ def remove_small_regions(dx: np.ndarray, dy: np.ndarray, inl: np.ndarray, stride
     return out.astype(bool)
 
 
+def lift(fw: int, fh: int, cw: int, ch: int, stride: int, dx, dy, inl):
+    """The lift toward the coarser level (Sec. III-D) of a finer field given as (nx*ny,) arrays;
+    returns the coarse (dx, dy, init) arrays."""
+    fdx = np.ascontiguousarray(dx, np.int32); fdy = np.ascontiguousarray(dy, np.int32)
+    finl = np.ascontiguousarray(inl, np.uint8)
+    n = grid_count(cw, stride) * grid_count(ch, stride)
+    cdx = np.zeros(n, np.int32); cdy = np.zeros(n, np.int32); cinit = np.zeros(n, np.uint8)
+    L = lib()
+    L.pgmo_lift.argtypes = [C.c_int] * 5 + [C.c_void_p] * 6
+    if L.pgmo_lift(fw, fh, cw, ch, stride, _p(fdx), _p(fdy), _p(finl), _p(cdx), _p(cdy), _p(cinit)) != 0:
+        raise ValueError("oracle rejected the lift sizes")
+    return cdx, cdy, cinit
+
+
 def reflect101(i: int, n: int) -> int:
     return lib().pgmo_reflect101(i, n)
 

@@ -911,3 +911,33 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
         }
     return 0;
 }
+
+/* Test entry for the lift of Sec. III-D toward the coarser level (Eq. 6 with k = j+1, the
+ * step of propagate_up) applied to a given finer field: displacements and inlier flags of a
+ * fw x fh grid (spacing `stride`) in, the coarse cw x ch grid's displacements and
+ * initialised flags out. The coarse distances are taken on zero features; the lifted
+ * displacements do not depend on them. */
+int pgmo_lift(int fw, int fh, int cw, int ch, int stride, const int32_t* fdx, const int32_t* fdy,
+              const uint8_t* finl, int32_t* cdx, int32_t* cdy, uint8_t* cinit)
+{
+    if (fw < 1 || fh < 1 || cw < 1 || ch < 1 || stride < 1) return -1;
+    field_t fine, crs;
+    memset(&fine, 0, sizeof fine);
+    memset(&crs, 0, sizeof crs);
+    fine.w = fw; fine.h = fh; fine.stride = stride;
+    fine.nx = pgmo_grid_count(fw, stride); fine.ny = pgmo_grid_count(fh, stride); fine.n = fine.nx * fine.ny;
+    fine.dx = (int32_t*)fdx; fine.dy = (int32_t*)fdy; fine.inl = (uint8_t*)finl;
+    crs.w = cw; crs.h = ch; crs.stride = stride;
+    crs.nx = pgmo_grid_count(cw, stride); crs.ny = pgmo_grid_count(ch, stride); crs.n = crs.nx * crs.ny;
+    crs.C2 = 6; crs.P = 1;
+    int16_t* zero = calloc((size_t)cw * ch * 6, sizeof(int16_t));
+    crs.Gi_self = zero; crs.Gi_other = zero;
+    crs.dx = cdx; crs.dy = cdy; crs.init = cinit;
+    crs.dist = malloc((size_t)crs.n * sizeof(double));
+    crs.rec = malloc((size_t)crs.n); crs.inl = malloc((size_t)crs.n);
+    run_t run;
+    memset(&run, 0, sizeof run);
+    propagate_up(&run, &fine, &crs);
+    free(zero); free(crs.dist); free(crs.rec); free(crs.inl);
+    return 0;
+}

@@ -107,6 +107,10 @@ int pgmo_top_radius(const pgmo_params* p, int w, int h);
  * regions -- two 4-neighbouring inliers belong together when their displacements differ by
  * less than link_px (Euclidean) -- and the inliers of every region whose area (seeds x
  * stride^2 pixels) is below min_px become outliers. inl (0/1) is updated in place. */
+/* Test entry: the lift toward the coarser level (Sec. III-D, Eq. 6 with k = j+1) of a given
+ * finer field (fw x fh grid, spacing stride) onto a cw x ch grid; 0, or -1 for bad sizes. */
+int pgmo_lift(int fw, int fh, int cw, int ch, int stride, const int32_t* fdx, const int32_t* fdy,
+              const uint8_t* finl, int32_t* cdx, int32_t* cdy, uint8_t* cinit);
 void pgmo_remove_small_regions(const int32_t* dx, const int32_t* dy, uint8_t* inl, int nx, int ny,
                                int stride, int min_px, int link_px);
 

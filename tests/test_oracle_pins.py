@@ -459,6 +459,28 @@ def test_exact_cancellation_is_consistent_at_tau_zero():
         assert (st[s, 0], st[s, 1]) == (dx, dy) and st[s, 3] & oracle.F_INLIER, (s, st[s].tolist())
 
 
+def test_lift_rounds_the_halved_mean_of_inlier_children():
+    """The lift toward the coarser level (Sec. III-D, Eq. 6 with k = j+1) on a hand-made field:
+    a 12x12 grid (stride 3, seeds at 1, 4, 7, 10) under a 6x6 one (seeds at 1, 4), so every
+    coarse seed has the 2x2 finer seeds nearest to twice its position as children. The coarse
+    displacement is the mean of the inlier children's displacements halved, rounded to the
+    nearest integer with halves away from zero (reading), and a coarse seed without inlier
+    children stays uninitialised."""
+    fdx = np.zeros(16, np.int32); fdy = np.zeros(16, np.int32); inl = np.zeros(16, np.uint8)
+    def put(children, dxs, dys, flags):
+        for c, x, y, f in zip(children, dxs, dys, flags):
+            fdx[c], fdy[c], inl[c] = x, y, f
+    put([0, 1, 4, 5], [4, 6, 4, 6], [-2, -2, -2, -4], [1, 1, 1, 1])     # dx 20/8 = 2.5, dy -10/8
+    put([2, 3, 6, 7], [-4, -5, 100, 100], [5, 6, 100, 100], [1, 1, 0, 0])  # -9/4, 11/4; outliers ignored
+    put([8, 9, 12, 13], [2, 2, 2, 2], [2, 2, 2, 2], [0, 0, 0, 0])        # no inlier child
+    put([10, 11, 14, 15], [0, 0, 0, 2], [-4, -6, -4, -6], [1, 1, 1, 1])   # 2/8, -20/8 = -2.5
+    cdx, cdy, cinit = oracle.lift(12, 12, 6, 6, 3, fdx, fdy, inl)
+    assert cinit.tolist() == [1, 1, 0, 1]
+    assert (cdx[0], cdy[0]) == (3, -1)
+    assert (cdx[1], cdy[1]) == (-2, 3)
+    assert (cdx[3], cdy[3]) == (0, -3)
+
+
 def test_refinement_lift_halves_the_mean_of_inlier_children():
     """Refinement (Sec. III-D, Eq. 6 toward the coarser level): with the coarsest level never
     iterated, its final field is the lift of the finer level's inliers. Under a translation d
