@@ -64,6 +64,17 @@ def test_gray_keeps_gray_inputs():
     np.testing.assert_array_equal(oracle.gray(img)[0], v)
 
 
+def test_gray_is_bt601_luma():
+    """PGM-G's gray image (Sec. III-F, reading: integer BT.601 luma) stays within 1 of the
+    real-valued 0.299 R + 0.587 G + 0.114 B on random colours and on the three primaries."""
+    img = RNG.integers(0, 256, (16, 24, 3), dtype=np.uint8)
+    img[0, 0], img[0, 1], img[0, 2] = (255, 0, 0), (0, 255, 0), (0, 0, 255)
+    real = img.astype(np.float64) @ np.array([0.299, 0.587, 0.114])
+    got = oracle.gray(img).astype(np.float64)
+    assert np.abs(got - real).max() <= 1.0
+    assert (got[0, 0], got[0, 1], got[0, 2]) == (77, 149, 29)
+
+
 @pytest.mark.parametrize("shape", [(12, 17, 3), (8, 9, 1), (25, 6, 3)])
 def test_gradient_s3_is_scipy_sobel(shape):
     img = RNG.integers(0, 256, shape, dtype=np.uint8)
