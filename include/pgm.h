@@ -42,6 +42,8 @@ enum {
     PGM_EINVAL = -1,       /* invalid argument (bad sizes, parameters or null pointers)   */
     PGM_ENOMEM = -2,       /* the context's workspace is smaller than pgm_query's figure  */
     PGM_EDEVICE = -3,      /* a HIP runtime error (message in pgm_last_error)             */
+    PGM_EBUSY = -4,        /* try again later: a server's request queue is full (poll to  */
+                           /* take finished requests, then submit again)                  */
     PGM_EUNSUPPORTED = -5  /* valid but not supported by this build                       */
 };
 
@@ -55,6 +57,10 @@ enum { PGM_SPACE_RGB = 0,    /* colour spaces of the gradient pyramids (Sec. III
                              /* 128 + round((R - Y) 183 / 256), 128 + round((B - Y) 144 / 256) */
        PGM_SPACE_LAB = 2 };  /* 8-bit CIELab (sRGB curve, D65): L* 255/100, a* + 128, b* + 128 */
 enum { PGM_INIT_RANDOM = 0, PGM_INIT_EXHAUSTIVE = 1 }; /* initial field at the coarsest level  */
+enum { PGM_RS_FLOOR = 0,      /* limited random search (Sec. III-B, Eq. 5): the i-th offset   */
+                             /* floor(R_i W / 2^i), R_i uniform in (-1, 1)                  */
+       PGM_RS_SYMMETRIC = 1 };  /* the i-th offset uniform over the integers of [-w_i, w_i],  */
+                                /* w_i = floor(W / 2^i)                                       */
 enum { PGM_METRIC_SAD = 0,   /* patch distance: sum of absolute feature differences          */
        PGM_METRIC_SSD = 1 }; /* sum of squared differences (Eq. 3 as printed), integer       */
                              /* features only, exact in 64 bits                              */
@@ -75,7 +81,8 @@ typedef struct {
     int32_t iters[PGM_MAX_LEVELS];   /* propagation-search iterations per level (0 = full)   */
     int32_t radius;                  /* W of Eq. 5 below the initial field, >= 1             */
     int32_t max_disp;                /* |d| bound at full resolution for the initial field;  */
-                                     /* 0 = the whole image                                  */
+                                     /* 0 = the whole image; -k (k in 1..1024) = ceil(w / k) */
+                                     /* for a w-wide pair (pairs of many sizes)              */
     int32_t sobel_ksize;             /* S of Eq. 1: 3 or 5                                   */
     int32_t feature;                 /* PGM_FEAT_*                                           */
     int32_t color;                   /* PGM_RGB or PGM_GRAY                                  */
@@ -91,6 +98,7 @@ typedef struct {
     int32_t space_fwd[PGM_MAX_LEVELS]; /* PGM_SPACE_* of the forward / backward gradient    */
     int32_t space_bwd[PGM_MAX_LEVELS]; /* pyramid per level (PGM_RGB only; 0 = RGB)         */
     int32_t metric;                  /* PGM_METRIC_*                                         */
+    int32_t rs_mode;                 /* PGM_RS_*: offsets of the limited random search       */
     uint64_t rng_seed;               /* key of the counter-based random generator            */
 } pgm_params;
 
@@ -117,7 +125,10 @@ enum {
     PGM_PRESET_PAPER = 0,    /* Sec. IV parameters on a dense field (stride 1, P 15 / 11)    */
     PGM_PRESET_CONFIG1 = 1,  /* 256x192 pairs: L=3, stride 3, 8x8, 4 iterations, |d|<=20    */
     PGM_PRESET_CONFIG2 = 2,  /* 1024x436 pairs: L=5, stride 3, 8x8, 6 iterations, |d|<=200  */
-    PGM_PRESET_CONFIG3 = 3   /* 1242x375 pairs, direction-only float features, |d|<=250     */
+    PGM_PRESET_CONFIG3 = 3,  /* 1242x375 pairs, direction-only float features, |d|<=250     */
+    PGM_PRESET_CONFIG4 = 4,  /* batches of pairs of many sizes: configuration 2's matching  */
+                             /* with |d| <= ceil(w / 5) per pair (max_disp = -5)            */
+    PGM_PRESET_CONFIG5 = 5   /* served pairs of any size: as configuration 4                */
 };
 
 /* Fill *p with a preset. Host only. PGM_EINVAL for an unknown preset or p == NULL. */
@@ -191,22 +202,31 @@ PGM_API pgm_status pgm_match_groups(void* ctx, int32_t n_groups, const pgm_group
 
 /* Request server: pairs of any size and parameters arrive one at a time and are matched
  * concurrently. A server owns a device memory pool of pool_bytes and n_streams HIP streams
- * (1..16). pgm_server_submit queues a request (the pgm_match arguments plus a caller tag) and
- * starts queued requests, oldest first, while the head's workspace (pgm_query's
- * workspace_bytes rounded up to 256) fits in the pool; a started request runs as pgm_match
- * on the least loaded stream, so its results equal pgm_match on that pair alone.
- * pgm_server_poll reports finished requests: it writes up to max_tags tags to host_tags and
- * returns their number (or a negative pgm_status), frees their memory and starts queued
- * requests. The caller keeps a request's images and outputs alive until its tag is reported.
- * pgm_server_drain waits until nothing is queued or running (the finished tags stay for
- * pgm_server_poll). Argument errors are reported by pgm_server_submit synchronously, and
- * PGM_ENOMEM when the request alone exceeds the pool. One host thread per server. */
-PGM_API pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_streams, void** out_server);
+ * (1..16); at most max_queued requests wait for memory (0 = 4096).
+ * pgm_server_submit queues a request (the pgm_match arguments plus a caller tag) and starts
+ * queued requests, oldest first, while the head's workspace (pgm_query's workspace_bytes
+ * rounded up to 256) fits in the pool; a started request runs as pgm_match on the least
+ * loaded stream, so its results equal pgm_match on that pair alone. Its launches are ordered
+ * after the work the caller had issued on `stream` (hipStream_t or NULL) when it submitted,
+ * so inputs and zero-filled outputs produced there are seen. PGM_EBUSY when max_queued
+ * requests are already waiting (nothing is queued: poll, then submit again).
+ * pgm_server_poll reports finished requests: it writes up to max_tags tags to host_tags and,
+ * when host_status is not NULL, each request's status (PGM_OK, or the error that stopped its
+ * launches: its outputs are then undefined), returns their number (or a negative
+ * pgm_status), frees their memory and starts queued requests. A request whose launches failed
+ * keeps its memory until its stream has passed them. The caller keeps a request's images and
+ * outputs alive until its tag is reported. pgm_server_drain waits until nothing is queued or
+ * running (the finished tags stay for pgm_server_poll). Argument errors are reported by
+ * pgm_server_submit synchronously, and PGM_ENOMEM when the request alone exceeds the pool.
+ * One host thread per server. */
+PGM_API pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_streams, int32_t max_queued,
+                                     void** out_server);
 PGM_API pgm_status pgm_server_submit(void* server, const pgm_params* p, const uint8_t* img1,
                                      const uint8_t* img2, int32_t w, int32_t h, int32_t pitch_bytes,
                                      pgm_match_t* out_fwd, pgm_match_t* out_bwd, int32_t* out_n_inliers,
-                                     pgm_match_t* out_compact, uint64_t* out_n_evals, uint64_t tag);
-PGM_API int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t max_tags);
+                                     pgm_match_t* out_compact, uint64_t* out_n_evals, uint64_t tag,
+                                     void* stream);
+PGM_API int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t* host_status, int32_t max_tags);
 PGM_API pgm_status pgm_server_pending(void* server, int32_t* host_queued, int32_t* host_running,
                                       int32_t* host_finished);
 PGM_API pgm_status pgm_server_drain(void* server);

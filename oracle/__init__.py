@@ -23,6 +23,7 @@ F_INIT, F_INLIER, F_RECORD = 1, 2, 4
 FEAT_INT16, FEAT_F32_DIR = 0, 1
 RGB, GRAY = 0, 1
 INIT_RANDOM, INIT_EXHAUSTIVE = 0, 1
+RS_FLOOR, RS_SYMMETRIC = 0, 1
 
 
 class Params(C.Structure):
@@ -35,7 +36,7 @@ class Params(C.Structure):
         ("consistency_px", C.c_int32), ("init_mode", C.c_int32), ("refine_rounds", C.c_int32),
         ("min_region_px", C.c_int32), ("region_link_px", C.c_int32),
         ("space_fwd", C.c_int32 * MAX_LEVELS), ("space_bwd", C.c_int32 * MAX_LEVELS),
-        ("metric", C.c_int32),
+        ("metric", C.c_int32), ("rs_mode", C.c_int32),
         ("rng_seed", C.c_uint64),
     ]
 
@@ -83,6 +84,7 @@ def lib():
         L.pgmo_philox4x32_10.argtypes = [P, P, P]
         L.pgmo_search_offset.argtypes = [C.c_uint32, C.c_int, C.c_int]
         L.pgmo_init_offset.argtypes = [C.c_uint32, C.c_int]
+        L.pgmo_search_offset_sym.argtypes = [C.c_uint32, C.c_int, C.c_int]
         L.pgmo_grid_count.argtypes = [C.c_int, C.c_int]
         L.pgmo_grid_pos.argtypes = [C.c_int, C.c_int, C.c_int]
         L.pgmo_grid_nearest.argtypes = [C.c_int, C.c_int, C.c_int]
@@ -225,6 +227,10 @@ def philox(ctr, key) -> np.ndarray:
 
 def search_offset(u: int, W: int, i: int) -> int:
     return lib().pgmo_search_offset(u, W, i)
+
+
+def search_offset_sym(u: int, W: int, i: int) -> int:
+    return lib().pgmo_search_offset_sym(u, W, i)
 
 
 def init_offset(u: int, R: int) -> int:

@@ -297,6 +297,15 @@ int pgmo_search_offset(uint32_t u, int W, int i)
     return (int)floor(R * (double)W / ldexp(1.0, i));
 }
 
+/* Eq. 5 read symmetrically (an option): the i-th offset uniform over the integers of
+ * [-w_i, w_i] with w_i = floor(W / 2^i), the radius Eq. 5 halves per step. The same exact
+ * floor as the initial displacements below, with R = w_i. */
+int pgmo_search_offset_sym(uint32_t u, int W, int i)
+{
+    int wi = W >> i;
+    return (int)floor((double)u / 4294967296.0 * (double)(2 * wi + 1)) - wi;
+}
+
 /* Random initial displacement component, uniform over the integers of [-R, R]. */
 int pgmo_init_offset(uint32_t u, int R)
 {
@@ -348,9 +357,12 @@ int pgmo_top_radius(const pgmo_params* p, int w, int h)
 {
     int tw = w, th = h;
     for (int l = 1; l < p->levels; l++) { tw = (tw + 1) / 2; th = (th + 1) / 2; }
-    if (p->max_disp <= 0) return tw > th ? tw : th;
+    if (p->max_disp == 0) return tw > th ? tw : th;
+    /* READING (batched and served pairs of many sizes): a negative bound -k scales with the
+     * image, ceil(w / k) pixels at full resolution */
+    int bound = p->max_disp > 0 ? p->max_disp : (w + (-p->max_disp) - 1) / (-p->max_disp);
     int scale = 1 << (p->levels - 1);
-    return (p->max_disp + scale - 1) / scale;
+    return (bound + scale - 1) / scale;
 }
 
 /* ------------------------------------------------------------------------------------- */
@@ -371,6 +383,7 @@ typedef struct {
 typedef struct {
     uint32_t key[2];
     uint64_t evals;
+    int rs_sym;                          /* offsets of Eq. 5 read symmetrically         */
 } run_t;
 
 static double cost(run_t* r, const field_t* f, int xa, int ya, int xb, int yb)
@@ -446,8 +459,9 @@ static void improve_seed(run_t* r, field_t* f, int i, int j, int t, int level, i
     uint32_t u[4];
     for (int ii = 0; ii < nI; ii++) {
         if ((ii & 1) == 0) draws(r, (uint32_t)s, word1, (uint32_t)(ii >> 1), (uint32_t)stage, u);
-        int ox = pgmo_search_offset(u[2 * (ii & 1)], W, ii);
-        int oy = pgmo_search_offset(u[2 * (ii & 1) + 1], W, ii);
+        uint32_t ux = u[2 * (ii & 1)], uy = u[2 * (ii & 1) + 1];
+        int ox = r->rs_sym ? pgmo_search_offset_sym(ux, W, ii) : pgmo_search_offset(ux, W, ii);
+        int oy = r->rs_sym ? pgmo_search_offset_sym(uy, W, ii) : pgmo_search_offset(uy, W, ii);
         int cx = cx0 + ox, cy = cy0 + oy;
         clamp_target(f, px, py, &cx, &cy);
         offer(r, f, s, px, py, cx, cy);
@@ -589,8 +603,9 @@ static void propagate_up(run_t* r, const field_t* fine, field_t* crs)
 }
 
 /* Step 2 and 3: forward-backward consistency check C^l (Sec. III-C/E) and the outlier
- * record update of Eq. 7, read with "inlier" as the true value so that the AND matches the
- * text's "an outlier when either is yes". READING: the backward match consulted for seed p
+ * record update of Eq. 7 (Sec. III-D), read with the record holding "inlier": new = record
+ * AND consistent, i.e. a seed is an outlier as soon as the record or the check marks it as
+ * one. READING: the backward match consulted for seed p
  * is the one at the backward seed nearest to p + F(p); consistent iff the two
  * displacements cancel within tau pixels (squared Euclidean norm). */
 static void check_and_update(field_t* fw, field_t* bw, int fwd_bwd, int tau)
@@ -698,6 +713,7 @@ int pgmo_sweep(const pgmo_params* p, int level, int dir, int stage, int W, const
                int32_t* dy, int32_t* dist, uint8_t* init, uint64_t* n_evals)
 {
     if (w < 1 || h < 1 || p->seed_stride < 1 || W < 1 || t0 < 0 || n_iter < 0 || t0 + n_iter > 256) return -1;
+    if (p->rs_mode != PGMO_RS_FLOOR && p->rs_mode != PGMO_RS_SYMMETRIC) return -1;
     int ch = p->color == PGMO_GRAY ? 1 : 3;
     int P = dir == 0 ? p->patch_fwd : p->patch_bwd;
     if (P < 1 || P > 16) return -1;
@@ -718,6 +734,7 @@ int pgmo_sweep(const pgmo_params* p, int level, int dir, int stage, int W, const
     }
     run_t run;
     run.key[0] = (uint32_t)p->rng_seed; run.key[1] = (uint32_t)(p->rng_seed >> 32); run.evals = 0;
+    run.rs_sym = p->rs_mode == PGMO_RS_SYMMETRIC;
     for (int t = t0; t < t0 + n_iter; t++) iterate(&run, &f, t, level, dir, stage, W, schedule);
     for (int s = 0; s < f.n; s++) dist[s] = dist_bits(&f, s);
     if (n_evals) *n_evals = run.evals;
@@ -750,6 +767,8 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
     if (p->min_region_px < 0 || (p->min_region_px > 0 && p->region_link_px < 1)) return -1;
     if (p->metric != PGMO_METRIC_SAD && p->metric != PGMO_METRIC_SSD) return -1;
     if (p->metric == PGMO_METRIC_SSD && p->feature == PGMO_FEAT_F32_DIR) return -1;
+    if (p->rs_mode != PGMO_RS_FLOOR && p->rs_mode != PGMO_RS_SYMMETRIC) return -1;
+    if (p->max_disp < -1024) return -1;
     for (int l = 0; l < p->levels; l++) {
         if (p->space_fwd[l] < 0 || p->space_fwd[l] > 2 || p->space_bwd[l] < 0 || p->space_bwd[l] > 2) return -1;
         if (p->color == PGMO_GRAY && (p->space_fwd[l] || p->space_bwd[l])) return -1;
@@ -765,6 +784,7 @@ int pgmo_match(const pgmo_params* p, const uint8_t* img1, const uint8_t* img2, i
     run.key[0] = (uint32_t)p->rng_seed;
     run.key[1] = (uint32_t)(p->rng_seed >> 32);
     run.evals = 0;
+    run.rs_sym = p->rs_mode == PGMO_RS_SYMMETRIC;
 
     /* image pyramids {I^l} of both images (RGB), then the gradient pyramids {G^l} (Sec.
      * III-D): one per direction, each level in that direction's colour space (Table II) */

@@ -32,6 +32,7 @@ enum { PGMO_SPACE_RGB = 0, PGMO_SPACE_YCRCB = 1, PGMO_SPACE_LAB = 2 };
 enum { PGMO_METRIC_SAD = 0, PGMO_METRIC_SSD = 1 };
 enum { PGMO_INIT_RANDOM = 0, PGMO_INIT_EXHAUSTIVE = 1 };
 enum { PGMO_SYNC = 0, PGMO_SCAN = 1 };
+enum { PGMO_RS_FLOOR = 0, PGMO_RS_SYMMETRIC = 1 };
 
 /* per-seed flags reported by the oracle */
 #define PGMO_F_INIT   1u   /* the correspondence field is initialised at this seed      */
@@ -44,7 +45,8 @@ typedef struct {
     int32_t patch_fwd, patch_bwd;      /* patch side for the forward / backward field        */
     int32_t iters[PGMO_MAX_LEVELS];    /* propagation-search iterations per level, 0 = full  */
     int32_t radius;                    /* W of Eq. 5 below the initial level                 */
-    int32_t max_disp;                  /* bound on |d| at full resolution, 0 = image size    */
+    int32_t max_disp;                  /* bound on |d| at full resolution, 0 = image size;   */
+                                       /* negative -k: ceil(w / k) for a w-wide image        */
     int32_t sobel_ksize;               /* S of Eq. 1: 3 or 5                                 */
     int32_t feature;                   /* PGMO_FEAT_*                                        */
     int32_t color;                     /* PGMO_RGB (C = 3) or PGMO_GRAY (C = 1)              */
@@ -57,6 +59,7 @@ typedef struct {
     int32_t space_fwd[PGMO_MAX_LEVELS]; /* colour space of the forward / backward gradient   */
     int32_t space_bwd[PGMO_MAX_LEVELS]; /* pyramid per level (Table II), PGMO_SPACE_*        */
     int32_t metric;                    /* PGMO_METRIC_*: Eq. 3 summed absolutely or squared */
+    int32_t rs_mode;                   /* PGMO_RS_*: offsets of the limited random search    */
     uint64_t rng_seed;                 /* key of the counter-based generator                 */
 } pgmo_params;
 
@@ -92,6 +95,9 @@ int64_t pgmo_ssd_i16(const int16_t* Ga, const int16_t* Gb, int w, int h, int C2,
 void pgmo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* offset floor(R W / 2^i) of Eq. 5 for R = (2u+1)/2^32 - 1 */
 int pgmo_search_offset(uint32_t u, int W, int i);
+/* offset of Eq. 5 read as a uniform integer in [-w_i, w_i], w_i = floor(W / 2^i):
+ * floor(u (2 w_i + 1) / 2^32) - w_i (PGMO_RS_SYMMETRIC) */
+int pgmo_search_offset_sym(uint32_t u, int W, int i);
 /* uniform integer in [-R, R] from a 32-bit draw: floor(u (2R+1) / 2^32) - R */
 int pgmo_init_offset(uint32_t u, int R);
 /* seeds along an axis of n pixels */

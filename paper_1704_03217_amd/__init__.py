@@ -20,14 +20,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpgm.so")
 
 MAX_LEVELS = 8
-PGM_OK, PGM_EINVAL, PGM_ENOMEM, PGM_EDEVICE, PGM_EUNSUPPORTED = 0, -1, -2, -3, -5
+PGM_OK, PGM_EINVAL, PGM_ENOMEM, PGM_EDEVICE, PGM_EBUSY, PGM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FEAT_INT16, FEAT_F32_DIR, FEAT_SIGN = 0, 1, 2
 RGB, GRAY = 0, 1
 SPACE_RGB, SPACE_YCRCB, SPACE_LAB = 0, 1, 2
 INIT_RANDOM, INIT_EXHAUSTIVE = 0, 1
 METRIC_SAD, METRIC_SSD = 0, 1
+RS_FLOOR, RS_SYMMETRIC = 0, 1
 FLAG_INIT, FLAG_INLIER, FLAG_RECORD = 1, 2, 4
-PRESET_PAPER, PRESET_CONFIG1, PRESET_CONFIG2, PRESET_CONFIG3 = 0, 1, 2, 3
+PRESET_PAPER, PRESET_CONFIG1, PRESET_CONFIG2, PRESET_CONFIG3, PRESET_CONFIG4, PRESET_CONFIG5 = 0, 1, 2, 3, 4, 5
 
 
 class pgm_params(C.Structure):
@@ -40,7 +41,7 @@ class pgm_params(C.Structure):
         ("consistency_px", C.c_int32), ("init_mode", C.c_int32), ("refine_rounds", C.c_int32),
         ("min_region_px", C.c_int32), ("region_link_px", C.c_int32),
         ("space_fwd", C.c_int32 * MAX_LEVELS), ("space_bwd", C.c_int32 * MAX_LEVELS),
-        ("metric", C.c_int32), ("rng_seed", C.c_uint64),
+        ("metric", C.c_int32), ("rs_mode", C.c_int32), ("rng_seed", C.c_uint64),
     ]
 
 
@@ -117,12 +118,12 @@ def lib():
         L.pgm_match_batch.restype = C.c_int32
         L.pgm_match_groups.argtypes = [V, C.c_int32, C.POINTER(pgm_group), V, C.c_int32, V]
         L.pgm_match_groups.restype = C.c_int32
-        L.pgm_server_create.argtypes = [C.c_int32, C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]
+        L.pgm_server_create.argtypes = [C.c_int32, C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]
         L.pgm_server_create.restype = C.c_int32
         L.pgm_server_submit.argtypes = [V, C.POINTER(pgm_params), V, V, C.c_int32, C.c_int32, C.c_int32,
-                                        V, V, V, V, V, C.c_uint64]
+                                        V, V, V, V, V, C.c_uint64, V]
         L.pgm_server_submit.restype = C.c_int32
-        L.pgm_server_poll.argtypes = [V, C.POINTER(C.c_uint64), C.c_int32]
+        L.pgm_server_poll.argtypes = [V, C.POINTER(C.c_uint64), C.POINTER(C.c_int32), C.c_int32]
         L.pgm_server_poll.restype = C.c_int32
         L.pgm_server_pending.argtypes = [V, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.pgm_server_pending.restype = C.c_int32
@@ -241,30 +242,37 @@ def _check_server(status, server):
     return status
 
 
-def pgm_server_create(device: int, pool_bytes: int, n_streams: int):
+def pgm_server_create(device: int, pool_bytes: int, n_streams: int, max_queued: int = 0):
     h = C.c_void_p()
-    _check_server(lib().pgm_server_create(device, pool_bytes, n_streams, C.byref(h)), None)
+    _check_server(lib().pgm_server_create(device, pool_bytes, n_streams, max_queued, C.byref(h)), None)
     return h
 
 
 def pgm_server_submit(server, p, img1: int, img2: int, w: int, h: int, pitch_bytes: int, out_fwd: int,
                       out_bwd: int | None, out_n_inliers: int | None, out_compact: int | None,
-                      out_n_evals: int | None, tag: int):
+                      out_n_evals: int | None, tag: int, stream: int | None = None):
     return _check_server(lib().pgm_server_submit(server, C.byref(_as_params(p)), img1, img2, w, h, pitch_bytes,
                                                  out_fwd, out_bwd, out_n_inliers, out_compact, out_n_evals,
-                                                 tag), server)
+                                                 tag, stream), server)
 
 
 def pgm_server_poll(server, max_tags: int = 256) -> list:
+    """[(tag, status)] of the requests finished since the last poll."""
     buf = (C.c_uint64 * max(1, max_tags))()
-    n = _check_server(lib().pgm_server_poll(server, buf, max_tags), server)
-    return list(buf[:n])
+    st = (C.c_int32 * max(1, max_tags))()
+    n = _check_server(lib().pgm_server_poll(server, buf, st, max_tags), server)
+    return [(buf[k], st[k]) for k in range(n)]
 
 
 def pgm_server_pending(server):
     q, r, f = C.c_int32(), C.c_int32(), C.c_int32()
     _check_server(lib().pgm_server_pending(server, C.byref(q), C.byref(r), C.byref(f)), server)
     return q.value, r.value, f.value
+
+
+def pgm_server_last_error_text(server) -> str:
+    m = lib().pgm_server_last_error(server)
+    return m.decode() if m else ""
 
 
 def pgm_server_drain(server) -> None:
@@ -513,11 +521,11 @@ class Server:
     CUDA image tensors and returns the tag; poll() returns the tags of finished requests.
     The server keeps references to each request's tensors until its tag has been reported."""
 
-    def __init__(self, device: int = 0, pool_bytes: int = 1 << 30, n_streams: int = 4):
-        import torch  # device memory only
+    def __init__(self, device: int = 0, pool_bytes: int = 1 << 30, n_streams: int = 4, max_queued: int = 0):
+        import torch  # device memory and streams only
         self.torch = torch
         self.device = device
-        self.h = pgm_server_create(device, pool_bytes, n_streams)
+        self.h = pgm_server_create(device, pool_bytes, n_streams, max_queued)
         self.live = {}
         self.next_tag = 0
 
@@ -552,18 +560,27 @@ class Server:
             self.next_tag += 1
         ptr = lambda t: None if t is None else t.data_ptr()
         self.live[tag] = o
+        # the request runs after the work torch has queued so far (inputs, zero-filled counters)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
         try:
             pgm_server_submit(self.h, p, img1.data_ptr(), img2.data_ptr(), w, h, img1.stride(0),
                               o["fwd"].data_ptr(), ptr(o["bwd"]), ptr(o["n_inliers"]), ptr(o["compact"]),
-                              ptr(o["n_evals"]), tag)
+                              ptr(o["n_evals"]), tag, stream)
         except Exception:
             del self.live[tag]
             raise
         return tag
 
     def poll(self, max_tags: int = 256):
-        """[(tag, outputs)] of the requests finished since the last poll."""
-        return [(t, self.live.pop(t)) for t in pgm_server_poll(self.h, max_tags)]
+        """[(tag, outputs)] of the requests finished since the last poll; a request whose
+        launches failed raises PGMError with its status (its tag is then dropped)."""
+        out = []
+        for t, st in pgm_server_poll(self.h, max_tags):
+            o = self.live.pop(t)
+            if st != PGM_OK:
+                raise PGMError(st, f"request {t} failed: " + pgm_server_last_error_text(self.h))
+            out.append((t, o))
+        return out
 
     def pending(self):
         return pgm_server_pending(self.h)

@@ -86,7 +86,8 @@ const char* validate(const pgm_params* p, int w, int h)
     for (int l = 0; l < p->levels; l++)
         if (p->iters[l] < 0 || p->iters[l] > 255) return "iterations must be within 0..255";
     if (p->radius < 1 || p->radius > 16384) return "radius must be within 1..16384";
-    if (p->max_disp < 0 || p->max_disp > 65535) return "max_disp must be within 0..65535";
+    if (p->max_disp < -1024 || p->max_disp > 65535) return "max_disp must be within -1024..65535";
+    if (p->rs_mode != PGM_RS_FLOOR && p->rs_mode != PGM_RS_SYMMETRIC) return "unknown rs_mode";
     if (p->sobel_ksize != 3 && p->sobel_ksize != 5) return "sobel_ksize must be 3 or 5";
     if (p->feature != PGM_FEAT_INT16 && p->feature != PGM_FEAT_F32_DIR && p->feature != PGM_FEAT_SIGN)
         return "unknown feature";
@@ -130,8 +131,11 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
         cw = (cw + 1) / 2; chh = (chh + 1) / 2;
     }
     const int m = Y.L - 1;
-    if (p->max_disp <= 0) Y.R_top = Y.lw[m] > Y.lh[m] ? Y.lw[m] : Y.lh[m];
-    else Y.R_top = (p->max_disp + (1 << m) - 1) >> m;
+    if (p->max_disp == 0) Y.R_top = Y.lw[m] > Y.lh[m] ? Y.lw[m] : Y.lh[m];
+    else {   // a negative bound -k scales with the pair: ceil(w / k) pixels at full resolution
+        const int bound = p->max_disp > 0 ? p->max_disp : (w + (-p->max_disp) - 1) / (-p->max_disp);
+        Y.R_top = (bound + (1 << m) - 1) >> m;
+    }
 
     // Sec. III-D: initial field at m, N refinement round trips between m and m-1 carrying
     // field and record, the field alone from m to m-1, then field and record to level 0.
@@ -220,7 +224,7 @@ bool level_layout(const Layout& Y, int l, int iters, int nI, size_t lds_max, Lev
     const size_t graw = (size_t)(Y.lw[l] + 2 * PAD) * (Y.lh[l] + 2 * PAD) * Y.C2 * Y.esize;
     o.gstride = (graw + 15) & ~(size_t)15;
     o.disp = 2 * o.gstride;
-    o.dist = o.disp + n * 4;
+    o.dist = (o.disp + n * 4 + 15) & ~(size_t)15;   // 8-byte distances need 8-byte alignment
     o.rnd = (o.dist + n * Y.dsize + 15) & ~(size_t)15;
     o.total = (o.rnd + (size_t)iters * n * nI * sizeof(short2) + 15) & ~(size_t)15;
     return o.total + 64 <= lds_max;   // room for the kernel's static LDS
@@ -326,11 +330,13 @@ pgm_status pgm_default_params(pgm_params* p, int32_t preset)
         return PGM_OK;
     case PGM_PRESET_CONFIG2:
     case PGM_PRESET_CONFIG3:
+    case PGM_PRESET_CONFIG4:
+    case PGM_PRESET_CONFIG5:
         p->levels = 5;
         for (int l = 0; l < PGM_MAX_LEVELS; l++) p->iters[l] = 6;
-        p->max_disp = preset == PGM_PRESET_CONFIG2 ? 200 : 250;
-        p->feature = preset == PGM_PRESET_CONFIG2 ? PGM_FEAT_INT16 : PGM_FEAT_F32_DIR;
-        p->rng_seed = preset == PGM_PRESET_CONFIG2 ? 2000 : 3000;
+        p->max_disp = preset == PGM_PRESET_CONFIG2 ? 200 : preset == PGM_PRESET_CONFIG3 ? 250 : -5;
+        p->feature = preset == PGM_PRESET_CONFIG3 ? PGM_FEAT_F32_DIR : PGM_FEAT_INT16;
+        p->rng_seed = 1000ull * (uint64_t)preset;
         return PGM_OK;
     default:
         return PGM_EINVAL;
@@ -519,6 +525,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     const int m = Y.L - 1;
     ra.n_top = p->init_mode == PGM_INIT_RANDOM ? Y.lnx[m] * Y.lny[m] : 0;
     ra.R_top = Y.R_top;
+    ra.rs_sym = p->rs_mode == PGM_RS_SYMMETRIC;
     ra.top_level = m;
     ra.key0 = (uint32_t)p->rng_seed;
     ra.key1 = (uint32_t)(p->rng_seed >> 32);
@@ -1012,7 +1019,8 @@ struct pgm_server_s {
     std::map<size_t, size_t> free_;               // free pool blocks: offset -> bytes
     std::vector<hipStream_t> streams;
     std::vector<int> load;                        // requests in flight per stream
-    std::vector<hipEvent_t> spare;                // completion events not in use
+    std::vector<hipEvent_t> spare;                // events not in use (completion and submission)
+    int max_queued = 0;                           // submissions beyond this return PGM_EBUSY
     struct Req {
         pgm_params p;
         const uint8_t* img1;
@@ -1026,11 +1034,26 @@ struct pgm_server_s {
         uint64_t tag;
         size_t need, off;
         int stream;
-        hipEvent_t done;
+        hipEvent_t ready;   // recorded on the caller's stream at submission
+        hipEvent_t done;    // recorded on the server stream after the request's launches
+        pgm_status status;  // PGM_OK, or the error that stopped the request's launches
     };
     std::deque<Req> queued;
     std::vector<Req> running;
-    std::deque<uint64_t> finished;
+    std::deque<std::pair<uint64_t, pgm_status>> finished;
+
+    hipError_t take_event(hipEvent_t* ev)
+    {
+        if (spare.empty()) {
+            hipEvent_t e;
+            hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+            if (err != hipSuccess) return err;
+            spare.push_back(e);
+        }
+        *ev = spare.back();
+        spare.pop_back();
+        return hipSuccess;
+    }
 
     bool alloc(size_t need, size_t& off)
     {
@@ -1062,7 +1085,11 @@ struct pgm_server_s {
     }
 };
 
-// start queued requests, oldest first, while the head fits in the pool
+// start queued requests, oldest first, while the head fits in the pool. A request's launches
+// wait for its submission event (the caller's stream at submit time). A request whose launches
+// fail part-way is still tracked until its stream passes its completion event, so that its
+// memory is not handed out while launches may still use it; it is then reported with its
+// error status.
 static pgm_status server_admit(pgm_server_s* S)
 {
     pgm_ctx_s* c = S->c;
@@ -1073,29 +1100,31 @@ static pgm_status server_admit(pgm_server_s* S)
         for (int i = 1; i < (int)S->streams.size(); i++)
             if (S->load[i] < S->load[k]) k = i;
         r.stream = k;
-        if (S->spare.empty()) {
-            hipEvent_t ev;
-            hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-            if (e != hipSuccess) {
-                S->release(r.off, r.need);
-                return fail(c, PGM_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
-            }
-            S->spare.push_back(ev);
-        }
-        r.done = S->spare.back();
-        pgm_status st = match_impl(c, &r.p, 1, r.img1, r.img2, r.w, r.h, r.pitch, 0, r.out_fwd, r.out_bwd,
-                                   r.out_n_inliers, r.out_compact, r.out_n_evals, S->streams[k], c->ws + r.off,
-                                   r.need);
-        if (st != PGM_OK) {
+        hipError_t e = S->take_event(&r.done);
+        if (e != hipSuccess) {
             S->release(r.off, r.need);
-            return st;
+            return fail(c, PGM_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
         }
-        hipError_t e = hipEventRecord(r.done, S->streams[k]);
-        if (e != hipSuccess) return fail(c, PGM_EDEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
-        S->spare.pop_back();
+        S->queued.pop_front();
+        e = hipStreamWaitEvent(S->streams[k], r.ready, 0);
+        r.status = e == hipSuccess ? PGM_OK : fail(c, PGM_EDEVICE, std::string("hipStreamWaitEvent: ") +
+                                                                       hipGetErrorString(e));
+        if (r.status == PGM_OK)
+            r.status = match_impl(c, &r.p, 1, r.img1, r.img2, r.w, r.h, r.pitch, 0, r.out_fwd, r.out_bwd,
+                                  r.out_n_inliers, r.out_compact, r.out_n_evals, S->streams[k], c->ws + r.off,
+                                  r.need);
+        e = hipEventRecord(r.done, S->streams[k]);
+        if (e != hipSuccess) {
+            // without a completion event, wait for the stream before the memory is reused
+            (void)hipStreamSynchronize(S->streams[k]);
+            S->release(r.off, r.need);
+            S->spare.push_back(r.done);
+            S->spare.push_back(r.ready);
+            S->finished.emplace_back(r.tag, r.status != PGM_OK ? r.status : PGM_EDEVICE);
+            return fail(c, PGM_EDEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
+        }
         S->load[k]++;
         S->running.push_back(r);
-        S->queued.pop_front();
     }
     return PGM_OK;
 }
@@ -1114,24 +1143,28 @@ static pgm_status server_reap(pgm_server_s* S, bool wait)
         if (e != hipSuccess) return fail(c, PGM_EDEVICE, std::string("request: ") + hipGetErrorString(e));
         S->release(r.off, r.need);
         S->spare.push_back(r.done);
+        S->spare.push_back(r.ready);
         S->load[r.stream]--;
-        S->finished.push_back(r.tag);
+        S->finished.emplace_back(r.tag, r.status);
         S->running.erase(S->running.begin() + i);
     }
     return PGM_OK;
 }
 
-pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_streams, void** out_server)
+pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_streams, int32_t max_queued,
+                             void** out_server)
 {
     if (!out_server) return fail(nullptr, PGM_EINVAL, "out_server is null");
     *out_server = nullptr;
     if (n_streams < 1 || n_streams > 16) return fail(nullptr, PGM_EINVAL, "n_streams must be in 1..16");
+    if (max_queued < 0) return fail(nullptr, PGM_EINVAL, "max_queued must not be negative");
     void* ctx = nullptr;
     pgm_status st = pgm_create(device, pool_bytes, &ctx);
     if (st != PGM_OK) return st;
     pgm_server_s* S = new pgm_server_s();
     S->c = (pgm_ctx_s*)ctx;
     S->c->concurrent = true;
+    S->max_queued = max_queued ? max_queued : 4096;
     S->free_[0] = S->c->ws_bytes & ~(size_t)255;
     for (int i = 0; i < n_streams; i++) {
         hipStream_t q;
@@ -1152,7 +1185,7 @@ pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_stre
 pgm_status pgm_server_submit(void* server, const pgm_params* p, const uint8_t* img1, const uint8_t* img2,
                              int32_t w, int32_t h, int32_t pitch_bytes, pgm_match_t* out_fwd,
                              pgm_match_t* out_bwd, int32_t* out_n_inliers, pgm_match_t* out_compact,
-                             uint64_t* out_n_evals, uint64_t tag)
+                             uint64_t* out_n_evals, uint64_t tag, void* stream)
 {
     pgm_server_s* S = (pgm_server_s*)server;
     if (!S) return PGM_EINVAL;
@@ -1170,15 +1203,25 @@ pgm_status pgm_server_submit(void* server, const pgm_params* p, const uint8_t* i
     r.off = 0;
     r.stream = 0;
     r.done = nullptr;
+    r.status = PGM_OK;
     if (r.need > (c->ws_bytes & ~(size_t)255))
         return fail(c, PGM_ENOMEM, "request needs " + std::to_string(r.need) + " bytes, more than the pool");
     PGM_HIP(c, hipSetDevice(c->device));
-    S->queued.push_back(r);
     if (pgm_status st = server_reap(S, false)) return st;
+    if ((int)S->queued.size() >= S->max_queued)
+        return fail(c, PGM_EBUSY, "the request queue is full (" + std::to_string(S->max_queued) + " requests)");
+    // the request's launches are ordered after the caller's work on `stream` so far
+    PGM_HIP(c, S->take_event(&r.ready));
+    hipError_t e = hipEventRecord(r.ready, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        S->spare.push_back(r.ready);
+        return fail(c, PGM_EDEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
+    }
+    S->queued.push_back(r);
     return server_admit(S);
 }
 
-int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t max_tags)
+int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t* host_status, int32_t max_tags)
 {
     pgm_server_s* S = (pgm_server_s*)server;
     if (!S || max_tags < 0 || (max_tags > 0 && !host_tags)) return PGM_EINVAL;
@@ -1187,7 +1230,9 @@ int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t max_tags)
     if (pgm_status st = server_admit(S)) return st;
     int32_t n = 0;
     while (n < max_tags && !S->finished.empty()) {
-        host_tags[n++] = S->finished.front();
+        host_tags[n] = S->finished.front().first;
+        if (host_status) host_status[n] = S->finished.front().second;
+        n++;
         S->finished.pop_front();
     }
     return n;
@@ -1227,7 +1272,11 @@ void pgm_server_destroy(void* server)
     if (!S) return;
     (void)hipSetDevice(S->c->device);
     for (hipStream_t q : S->streams) (void)hipStreamSynchronize(q);
-    for (auto& r : S->running) (void)hipEventDestroy(r.done);
+    for (auto& r : S->running) {
+        (void)hipEventDestroy(r.done);
+        (void)hipEventDestroy(r.ready);
+    }
+    for (auto& r : S->queued) (void)hipEventDestroy(r.ready);
     for (hipEvent_t ev : S->spare) (void)hipEventDestroy(ev);
     for (hipStream_t q : S->streams) (void)hipStreamDestroy(q);
     pgm_destroy(S->c);

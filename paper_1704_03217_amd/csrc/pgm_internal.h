@@ -143,6 +143,7 @@ struct RngArgs {
     short2* table;
     short2* init;          // 2 * n_top initial displacements
     int n_top, R_top, top_level;
+    int rs_sym;            // PGM_RS_SYMMETRIC: search offsets uniform in [-(W >> i), W >> i]
     uint32_t key0, key1;
     int init_blocks;       // work-groups of the initial displacements (filled in by the launcher)
 };

@@ -1674,8 +1674,12 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
 // hold k_prep's LDS slots that the image tiles need
 constexpr int RNG_SPT = 8;
 
-__device__ __forceinline__ int search_off(uint32_t u, int W, int i)
+__device__ __forceinline__ int search_off(uint32_t u, int W, int i, int sym)
 {
+    if (sym) {   // uniform over the integers of [-w_i, w_i], w_i = floor(W / 2^i)
+        const int wi = W >> i;
+        return (int)__umulhi(u, 2u * (uint32_t)wi + 1u) - wi;
+    }
     // floor(R W / 2^i) with R = (2u + 1) / 2^32 - 1, in exact integer arithmetic
     const long long A = (long long)(2ull * u + 1ull) * W - ((long long)W << 32);
     return (int)(A >> (32 + i));
@@ -1710,9 +1714,10 @@ __device__ __forceinline__ void rng_block(const RngArgs& a, int b)
         short2* out = a.table + S.base + (((long long)dir * S.iters + t) * S.n + s) * S.nI;
         for (int i0 = 0; i0 < S.nI; i0 += 2) {
             const uint4 u = philox4x32_10(make_uint4((uint32_t)s, w1, (uint32_t)(i0 >> 1), (uint32_t)S.stage), a.key0, a.key1);
-            out[i0] = make_short2((short)search_off(u.x, S.W, i0), (short)search_off(u.y, S.W, i0));
+            out[i0] = make_short2((short)search_off(u.x, S.W, i0, a.rs_sym), (short)search_off(u.y, S.W, i0, a.rs_sym));
             if (i0 + 1 < S.nI)
-                out[i0 + 1] = make_short2((short)search_off(u.z, S.W, i0 + 1), (short)search_off(u.w, S.W, i0 + 1));
+                out[i0 + 1] = make_short2((short)search_off(u.z, S.W, i0 + 1, a.rs_sym),
+                                          (short)search_off(u.w, S.W, i0 + 1, a.rs_sym));
         }
     }
 }

@@ -16,7 +16,7 @@ def base_params(**kw):
     """Matching parameters as a plain dict (field names of the C structs)."""
     p = dict(levels=3, seed_stride=3, patch_fwd=8, patch_bwd=8, iters=[4, 4, 4], radius=2,
              max_disp=20, sobel_ksize=5, feature=0, color=0, fwd_bwd=1, consistency_px=1,
-             init_mode=0, refine_rounds=0, min_region_px=0, region_link_px=12, metric=0, rng_seed=1)
+             init_mode=0, refine_rounds=0, min_region_px=0, region_link_px=12, metric=0, rs_mode=0, rng_seed=1)
     p.update(kw)
     if len(p["iters"]) < p["levels"]:
         p["iters"] = list(p["iters"]) + [p["iters"][-1]] * (p["levels"] - len(p["iters"]))

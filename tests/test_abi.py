@@ -102,11 +102,11 @@ def test_query_workspace_of_config2_is_modest():
                                  dict(patch_bwd=17), dict(iters=[256, 1, 1]), dict(radius=0),
                                  dict(sobel_ksize=7), dict(feature=3), dict(color=3), dict(fwd_bwd=2),
                                  dict(consistency_px=-1), dict(init_mode=2), dict(refine_rounds=17),
-                                 dict(levels=1, iters=[1], refine_rounds=1), dict(max_disp=-1),
+                                 dict(levels=1, iters=[1], refine_rounds=1), dict(max_disp=-1025),
                                  dict(min_region_px=-1), dict(min_region_px=9, region_link_px=0),
                                  dict(min_region_px=9, region_link_px=65536), dict(space_fwd=[3, 0, 0]),
                                  dict(space_bwd=[0, -1, 0]), dict(color=1, space_fwd=[1, 0, 0]),
-                                 dict(metric=2), dict(metric=-1), dict(metric=1, feature=1)])
+                                 dict(metric=2), dict(metric=-1), dict(metric=1, feature=1), dict(rs_mode=2)])
 def test_query_rejects_invalid_parameters(bad):
     with pytest.raises(pgm.PGMError) as e:
         pgm.pgm_query(base_params(**bad), 64, 64)
@@ -131,11 +131,12 @@ def test_null_arguments_rejected_without_device_work():
     assert L.pgm_match_batch(None, C.byref(p), 2, None, None, 10, 10, 30, 300, None, None, None, None, None,
                              None) == pgm.PGM_EINVAL
     assert L.pgm_match_groups(None, 1, None, None, 0, None) == pgm.PGM_EINVAL
-    assert L.pgm_server_create(0, 1 << 20, 0, C.byref(C.c_void_p())) == pgm.PGM_EINVAL
-    assert L.pgm_server_create(0, 1 << 20, 1, None) == pgm.PGM_EINVAL
-    assert L.pgm_server_submit(None, C.byref(p), None, None, 10, 10, 30, None, None, None, None, None, 0) \
-        == pgm.PGM_EINVAL
-    assert L.pgm_server_poll(None, None, 0) == pgm.PGM_EINVAL
+    assert L.pgm_server_create(0, 1 << 20, 0, 0, C.byref(C.c_void_p())) == pgm.PGM_EINVAL
+    assert L.pgm_server_create(0, 1 << 20, 1, -1, C.byref(C.c_void_p())) == pgm.PGM_EINVAL
+    assert L.pgm_server_create(0, 1 << 20, 1, 0, None) == pgm.PGM_EINVAL
+    assert L.pgm_server_submit(None, C.byref(p), None, None, 10, 10, 30, None, None, None, None, None, 0,
+                               None) == pgm.PGM_EINVAL
+    assert L.pgm_server_poll(None, None, None, 0) == pgm.PGM_EINVAL
     assert L.pgm_server_drain(None) == pgm.PGM_EINVAL
     L.pgm_server_destroy(None)
     assert L.pgm_dump_level(None, 0, 0, None) == pgm.PGM_EINVAL
@@ -186,3 +187,45 @@ def test_tune_rejects_bad_arguments_without_device_work():
     assert L.pgm_tune(None, C.byref(p), 1, None, None, 64, 64, 192, 0, None, None, None, None, 1, None,
                       C.byref(f)) == pgm.PGM_EINVAL
     assert f.value == -1
+
+
+@pytest.mark.parametrize("preset", [pgm.PRESET_CONFIG4, pgm.PRESET_CONFIG5])
+def test_batch_and_served_presets(preset):
+    """Configurations 4 and 5: configuration 2's matching with |d| <= ceil(w / 5) per pair."""
+    d = pgm.params_dict(pgm.pgm_default_params(preset))
+    exp = dict(CONFIG_PARAMS[2], max_disp=-5, rng_seed=1000 * preset)
+    assert d == exp
+
+
+@pytest.mark.parametrize("w,h", [(320, 240), (640, 480), (1024, 436), (1242, 375), (2048, 834), (333, 241)])
+def test_scaled_max_disp_sets_the_top_radius_as_the_oracle(w, h):
+    """max_disp = -k bounds |d| by ceil(w / k): the top radius equals the oracle's and that of
+    the explicit bound ceil(w / 5)."""
+    p = pgm.pgm_default_params(pgm.PRESET_CONFIG4)
+    d = pgm.params_dict(p)
+    explicit = dict(d, max_disp=-(-w // 5))
+    assert oracle.top_radius(d, w, h) == oracle.top_radius(explicit, w, h)
+    m = d["levels"] - 1
+    assert oracle.top_radius(d, w, h) == -(-(-(-w // 5)) // (1 << m))
+    # the library's workspace (random-number table sized by the top radius) agrees too
+    q1 = pgm.pgm_query(p, w, h)
+    q2 = pgm.pgm_query(pgm.params(explicit), w, h)
+    assert q1.workspace_bytes == q2.workspace_bytes
+
+
+def test_rs_mode_and_max_disp_are_validated():
+    ok = base_params()
+    pgm.pgm_query(ok, 256, 192)
+    pgm.pgm_query(dict(ok, rs_mode=pgm.RS_SYMMETRIC), 256, 192)
+    pgm.pgm_query(dict(ok, max_disp=-1024), 256, 192)
+    for bad in (dict(ok, rs_mode=2), dict(ok, rs_mode=-1), dict(ok, max_disp=-1025)):
+        with pytest.raises(pgm.PGMError) as e:
+            pgm.pgm_query(bad, 256, 192)
+        assert e.value.status == pgm.PGM_EINVAL
+
+
+def test_status_codes_match_header():
+    src = open(HEADER).read()
+    for name in ("PGM_OK", "PGM_EINVAL", "PGM_ENOMEM", "PGM_EDEVICE", "PGM_EBUSY", "PGM_EUNSUPPORTED"):
+        v = int(re.search(rf"\b{name}\s*=\s*(-?\d+)", src).group(1))
+        assert getattr(pgm, name) == v, name

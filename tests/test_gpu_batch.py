@@ -128,17 +128,20 @@ def test_batch_padded_pitch_and_image_stride(matcher):
     _check_pairs(params, pairs, fwd, bwd, comp, o["n_inliers"].cpu().numpy(), int(o["n_evals"].item()), "padded")
 
 
-@pytest.mark.parametrize("name,params", [
-    ("direction_patch11_9", base_params(feature=1, patch_fwd=11, patch_bwd=9, max_disp=6, rng_seed=41)),
-    ("gray_patch13", base_params(color=1, patch_fwd=13, patch_bwd=13, max_disp=6, rng_seed=42)),
-    ("ssd_patch8", base_params(metric=1, max_disp=6, rng_seed=43)),
-    ("sign_patch16", base_params(feature=2, patch_fwd=16, patch_bwd=16, max_disp=6, rng_seed=44)),
+@pytest.mark.parametrize("name,params,hw", [
+    ("direction_patch11_9", base_params(feature=1, patch_fwd=11, patch_bwd=9, max_disp=6, rng_seed=41), (48, 64)),
+    ("gray_patch13", base_params(color=1, patch_fwd=13, patch_bwd=13, max_disp=6, rng_seed=42), (48, 64)),
+    ("ssd_patch8", base_params(metric=1, max_disp=6, rng_seed=43), (48, 64)),
+    # odd seed counts at every level (247, 63, 15): the 8-byte distances of the squared metric
+    # sit after an odd number of 4-byte displacements in LDS
+    ("ssd_patch8_odd_grids", base_params(metric=1, max_disp=6, rng_seed=45), (40, 56)),
+    ("sign_patch16", base_params(feature=2, patch_fwd=16, patch_bwd=16, max_disp=6, rng_seed=44), (48, 64)),
 ])
-def test_batch16_small_levels_in_lds(matcher, name, params):
+def test_batch16_small_levels_in_lds(matcher, name, params, hw):
     """Sixteen small pairs: at 16 pairs or more every level that fits in LDS runs in one
     work-group per pair and direction, here with 16-lane patches, gray, float direction
     features, signs and squared differences."""
-    pairs = [synth.rect_pair(60 + i, 48, 64, n_rect=2, dmax=6) for i in range(16)]
+    pairs = [synth.rect_pair(60 + i, hw[0], hw[1], n_rect=2, dmax=6) for i in range(16)]
     print(f"[gpu batch] batch16 {name}", file=sys.stderr, flush=True)
     pgm.pgm_profile(matcher.ctx, True)
     try:

@@ -162,6 +162,12 @@ CASES = {
     "flat_random": (lambda: tie_pair("flat"), base_params(levels=3, iters=[3, 3, 3], max_disp=8, rng_seed=36)),
     "stripes_exhaustive": (lambda: tie_pair("stripes"), base_params(levels=2, iters=[2, 2], init_mode=1, max_disp=6, patch_fwd=5, patch_bwd=5, rng_seed=37)),
     "stripes_random": (lambda: tie_pair("stripes"), base_params(levels=3, iters=[3, 3, 3], max_disp=8, rng_seed=38)),
+    # the symmetric reading of the random-search offsets (uniform in [-w_i, w_i]), with a
+    # large top radius and the refinement
+    "rs_symmetric": (lambda: synth.config_pair(1), base_params(rs_mode=1, rng_seed=46)),
+    "rs_symmetric_refine_ssd": (lambda: synth.rect_pair(28, 120, 160, dmax=16), base_params(rs_mode=1, metric=1, refine_rounds=1, max_disp=16, rng_seed=47)),
+    # the batched/served presets' scaled bound (max_disp = -5: ceil(w / 5))
+    "scaled_max_disp": (lambda: synth.rect_pair(29, 120, 200, dmax=40), base_params(levels=4, iters=[3] * 4, max_disp=-5, rng_seed=48)),
     # the deepest pyramid (8 levels: 300x260 down to 3x3)
     "levels8": (lambda: synth.rect_pair(27, 260, 300, dmax=12), base_params(levels=8, iters=[2] * 8, max_disp=12, rng_seed=29)),
 }
@@ -178,6 +184,16 @@ def test_config2_full_size_bit_exact(matcher):
     pair = synth.config_pair(2)
     g, r = compare(matcher, CONFIG_PARAMS[2], pair.img1, pair.img2, "config2")
     assert g["fwd"].shape[0] == 49445
+
+
+def test_paper_preset_at_benchmark_size(matcher):
+    """The paper's own parameters as the benchmark runs them: a dense stride-1 field of
+    446,464 seeds per direction at 1024x436, patches 15 / 11, refinement N = 2, the colour
+    spaces of Table II and small-region removal (Sec. III-E) at full resolution."""
+    pair = synth.config_pair(2)
+    p = pgm.params_dict(pgm.pgm_default_params(pgm.PRESET_PAPER))
+    g, r = compare(matcher, p, pair.img1, pair.img2, "paper_preset_1024x436")
+    assert g["fwd"].shape[0] == 1024 * 436
 
 
 def test_config3_direction_full_size(matcher):

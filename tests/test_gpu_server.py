@@ -95,3 +95,105 @@ def test_server_rejects_request_larger_than_pool():
         assert srv.pending() == (0, 0, 0)
     finally:
         srv.close()
+
+
+# sizes the benchmark's served stream reaches (log-uniform area up to 2048x1024)
+LARGE_SIZES = [(2048, 834), (1024, 436), (640, 480), (1500, 700), (320, 240)]
+
+
+def test_server_large_served_sizes_equal_oracle():
+    """Requests as large as the served benchmark's (a 2048-wide pair among them), with the
+    served preset (configuration 2's matching, |d| <= ceil(w / 5)), each bit-exact with the
+    oracle on that pair alone."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("[gpu server] large served sizes", file=sys.stderr, flush=True)
+    reqs = []
+    for k, (w, h) in enumerate(LARGE_SIZES):
+        pr = synth.config_pair(5, 80 + k, (w, h))
+        p = pgm.params_dict(pgm.pgm_default_params(pgm.PRESET_CONFIG5))
+        p["rng_seed"] = 5100 + k
+        reqs.append((p, pr, torch.from_numpy(pr.img1).cuda(), torch.from_numpy(pr.img2).cuda()))
+    need = sum((pgm.pgm_query(p, pr.img1.shape[1], pr.img1.shape[0]).workspace_bytes + 255) // 256 * 256
+               for p, pr, _, _ in reqs)
+    srv = pgm.Server(0, need // 2, 4)     # the pool holds about half of them at once
+    try:
+        done, max_queued = run_all(srv, reqs, torch, timeout_s=120.0)
+        assert max_queued > 0
+        check(done, reqs)
+    finally:
+        srv.close()
+
+
+def test_server_waits_for_the_callers_stream():
+    """Images written by torch on the current stream just before submit (behind a long
+    kernel) are the ones matched: the request's launches wait for the caller's stream."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("[gpu server] ordering after the caller's stream", file=sys.stderr, flush=True)
+    src = requests(torch)
+    srv = pgm.Server(0, 256 << 20, 4)
+    try:
+        reqs, tags = [], {}
+        for k, (p, pr, a, b) in enumerate(src):
+            img1 = torch.zeros_like(a)
+            img2 = torch.zeros_like(b)
+            torch.cuda._sleep(20_000_000)       # ~10 ms of GPU time on the current stream
+            img1.copy_(a)
+            img2.copy_(b)
+            reqs.append((p, pr, img1, img2))
+            tags[srv.submit(p, img1, img2)] = k
+        done = {}
+        t0 = time.time()
+        while len(done) < len(reqs):
+            for tag, o in srv.poll():
+                done[tags[tag]] = o
+            assert time.time() - t0 < 60.0
+        torch.cuda.synchronize()
+        check(done, reqs)
+    finally:
+        srv.close()
+
+
+def test_server_full_queue_is_ebusy():
+    """With max_queued = 1 and a pool for one request, a third request submitted while the
+    first waits for the caller's stream and the second waits for memory is refused with
+    PGM_EBUSY (nothing queued); after the queue drains it is accepted, and all three results
+    equal the oracle's."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("[gpu server] full queue", file=sys.stderr, flush=True)
+    reqs = requests(torch)[:3]
+    need = max((pgm.pgm_query(p, pr.img1.shape[1], pr.img1.shape[0]).workspace_bytes + 255) // 256 * 256
+               for p, pr, _, _ in reqs)
+    srv = pgm.Server(0, need, 2, max_queued=1)
+    try:
+        tags = {}
+        torch.cuda._sleep(200_000_000)          # holds the first request's start (~0.1 s)
+        p, _, a, b = reqs[0]
+        tags[srv.submit(p, a, b)] = 0
+        p, _, a, b = reqs[1]
+        tags[srv.submit(p, a, b)] = 1
+        assert srv.pending()[0] == 1            # the second waits for memory
+        p, _, a, b = reqs[2]
+        with pytest.raises(pgm.PGMError) as e:
+            srv.submit(p, a, b)
+        assert e.value.status == pgm.PGM_EBUSY
+        assert srv.pending()[0] == 1
+        done, t0 = {}, time.time()
+        while len(done) < 2:
+            for tag, o in srv.poll():
+                done[tags[tag]] = o
+            assert time.time() - t0 < 60.0
+        tags[srv.submit(p, a, b)] = 2
+        while len(done) < 3:
+            for tag, o in srv.poll():
+                done[tags[tag]] = o
+            assert time.time() - t0 < 60.0
+        torch.cuda.synchronize()
+        check(done, reqs)
+    finally:
+        srv.close()

@@ -713,7 +713,8 @@ def test_direction_variant_runs_and_matches_translation():
 def test_invalid_parameters_rejected():
     img = np.zeros((20, 20, 3), np.uint8)
     for bad in (dict(levels=0), dict(levels=9), dict(seed_stride=0), dict(patch_fwd=17),
-                dict(sobel_ksize=7), dict(radius=0), dict(feature=5), dict(iters=[300, 4, 4])):
+                dict(sobel_ksize=7), dict(radius=0), dict(feature=5), dict(iters=[300, 4, 4]),
+                dict(rs_mode=2), dict(max_disp=-1025)):
         with pytest.raises(ValueError):
             oracle.match(base_params(**bad), img, img)
 
@@ -945,3 +946,131 @@ def test_ssd_pipeline_translation_and_output_clamp(oracle_lib):
         assert (st[s, 0], st[s, 1], st[s, 2]) == (6, -4, 0)
     init = (r["fwd"]["flags"] & 1) != 0
     assert r["fwd"]["dist"][init].max() <= 0x7FFFFFFE            # clamped output
+
+
+# --------------------------------------------------------------------------------------
+# limited random search read symmetrically (an option of Eq. 5, Sec. III-B)
+# --------------------------------------------------------------------------------------
+
+def test_search_offset_sym_is_exact_with_full_range_and_uniform():
+    """PGM_RS_SYMMETRIC: the i-th offset is floor(u (2 w_i + 1) / 2^32) - w_i with
+    w_i = floor(W / 2^i): exact against rational arithmetic, exactly the integers of
+    [-w_i, w_i] (both ends reached, nothing outside), and uniform (chi-square)."""
+    us = [0, 1, 2**31 - 1, 2**31, 2**32 - 2, 2**32 - 1]
+    us += [int(v) for v in RNG.integers(0, 2**32, 300, dtype=np.int64)]
+    for W in (1, 2, 3, 5, 13, 16, 100, 1023):
+        nI = int(math.floor(math.log2(W))) + 1
+        for i in range(nI):
+            wi = W // 2**i
+            for u in us:
+                exp = math.floor(Fraction(u, 2**32) * (2 * wi + 1)) - wi
+                assert oracle.search_offset_sym(u, W, i) == exp, (u, W, i)
+            # the ends: the smallest draw gives -w_i, the largest +w_i
+            assert oracle.search_offset_sym(0, W, i) == -wi
+            assert oracle.search_offset_sym(2**32 - 1, W, i) == wi
+            # every integer of the range has a draw: the first u of each cell
+            for v in range(-wi, wi + 1):
+                u = -(-((v + wi) * 2**32) // (2 * wi + 1))
+                assert oracle.search_offset_sym(u, W, i) == v
+                if u > 0:
+                    assert oracle.search_offset_sym(u - 1, W, i) == v - 1
+    W = 13
+    words = np.concatenate([oracle.philox([i, 3, 0, 0], [77, 1]) for i in range(3000)])
+    for i in range(4):
+        wi = W >> i
+        vals = np.array([oracle.search_offset_sym(int(u), W, i) for u in words])
+        cnt = np.bincount(vals + wi, minlength=2 * wi + 1)
+        exp = len(vals) / (2 * wi + 1)
+        chi2 = ((cnt - exp) ** 2 / exp).sum()
+        dof = 2 * wi
+        assert chi2 < dof + 6 * math.sqrt(2 * dof), (i, chi2)
+
+
+def test_symmetric_search_candidate_count_on_flat_gradients():
+    """A lone seed on flat gradients (every cost ties, so the match never moves) evaluates
+    exactly the candidates whose offset is not (0, 0): with the symmetric reading at W = 2 the
+    expected count per iteration is (1 - 1/25) + (1 - 1/9) = 1.849 (i = 0 over [-2, 2]^2,
+    i = 1 over [-1, 1]^2), against 1.6875 for the floor reading. The count is also recomputed
+    exactly from the draws (Philox and the offset function, both pinned above)."""
+    h, w = 41, 41
+    G = np.zeros((h, w, 6), np.int16)
+    n_iter = 250
+    for rs_mode, per_iter in ((oracle.RS_SYMMETRIC, 1.849), (oracle.RS_FLOOR, 1.6875)):
+        p = base_params(levels=1, seed_stride=w, max_disp=0, rng_seed=97, rs_mode=rs_mode)
+        st = dict(dx=[0], dy=[0], dist=[0], init=[1])
+        out, nev = oracle.sweep(p, G, G, st, W=2, t0=0, n_iter=n_iter)
+        assert (out["dx"][0], out["dy"][0]) == (0, 0)
+        assert abs(nev - per_iter * n_iter) <= 0.04 * per_iter * n_iter, (rs_mode, nev)
+        off = oracle.search_offset_sym if rs_mode == oracle.RS_SYMMETRIC else oracle.search_offset
+        exact = 0
+        for t in range(n_iter):
+            u = oracle.philox([0, t | (1 << 24), 0, 0], [97, 0])
+            for i in range(2):
+                exact += (off(int(u[2 * i]), 2, i), off(int(u[2 * i + 1]), 2, i)) != (0, 0)
+        assert nev == exact
+
+
+def test_symmetric_search_recovers_translation():
+    pair = synth.translate_pair(5, 96, 128, 7, -4)
+    p = base_params(levels=3, iters=[4, 4, 4], max_disp=12, rs_mode=oracle.RS_SYMMETRIC, rng_seed=31)
+    f = oracle.match(p, pair.img1, pair.img2, trace=False)["fwd"]
+    inner = (f["x1"] > 16) & (f["x1"] < 128 - 16) & (f["y1"] > 16) & (f["y1"] < 96 - 16)
+    assert ((f["x2"] - f["x1"])[inner] == 7).all() and ((f["y2"] - f["y1"])[inner] == -4).all()
+    assert (f["dist"][inner] == 0).all()
+
+
+# --------------------------------------------------------------------------------------
+# the sequential scan schedule (the paper's PatchMatch order, Sec. III-B)
+# --------------------------------------------------------------------------------------
+
+def test_scan_hand_worked_search_feeds_the_next_seed():
+    """A hand-worked raster pass (t = 0: Delta_x = (1,0), Delta_y = (0,1), x and y ascending).
+    Image 2 is image 1 moved one pixel right (left edge replicated, flat right margin), so
+    d* = (1, 0) costs exactly 0 at every seed and nothing costs less. Only seed (0, 0) starts
+    initialised, at (0, 0); the generator key is chosen so that its first random-search offset
+    at t = 0 is (1, 0). In the sequential schedule seed (0, 0) finds d* by its search, and every
+    later seed takes d* from an already updated neighbour before its own search (Eq. 4 then
+    Eq. 5 per seed, in place): after one pass every seed holds d* at distance 0. The evaluation
+    count is worked out from the draws: seed (0, 0) two (its two search candidates), every
+    other seed one for the adopted neighbour plus one per search candidate that differs from
+    d* after clamping.
+    A scan in the wrong direction, a propagation pass before the search pass, or the
+    synchronous schedule leaves most seeds uninitialised or away from d*. Which loop is outer
+    cannot change the result: the draws are indexed by seed and iteration, and both nestings
+    visit both propagation sources of a seed before the seed, so no pin can tell them apart."""
+    h, w = 30, 48
+    img = synth.texture(np.random.default_rng(3), h, w)
+    G1 = _features(img).astype(np.int16)
+    G1[:, 40:] = 0                               # flat right margin
+    G2 = np.concatenate([G1[:, :1], G1[:, :-1]], axis=1)
+    nx, ny = oracle.grid_count(w, 3), oracle.grid_count(h, 3)
+    P = 8
+    # a key whose first offset of seed 0 at t = 0 is (1, 0) (floor reading, W = 2)
+    key = next(k for k in range(1, 5000)
+               if (oracle.search_offset(int(oracle.philox([0, 1 << 24, 0, 0], [k, 0])[0]), 2, 0),
+                   oracle.search_offset(int(oracle.philox([0, 1 << 24, 0, 0], [k, 0])[1]), 2, 0)) == (1, 0))
+    p = base_params(levels=1, rng_seed=key)
+    n = nx * ny
+    st = dict(dx=np.zeros(n), dy=np.zeros(n), dist=np.zeros(n), init=np.zeros(n))
+    st["init"][0] = 1
+    st["dist"][0] = oracle.dist(G1, G2, P, 1, 1, 1, 1)
+    assert st["dist"][0] > 0
+    out, nev = oracle.sweep(p, G1, G2, st, W=2, t0=0, n_iter=1, schedule=oracle.SCAN)
+    assert (out["init"] == 1).all()
+    assert (out["dx"] == 1).all() and (out["dy"] == 0).all() and (out["dist"] == 0).all()
+    # the evaluation count from the draws
+    exp = 2
+    for s in range(1, n):
+        i, j = s % nx, s // nx
+        px, py = oracle.grid_pos(i, w, 3), oracle.grid_pos(j, h, 3)
+        u = oracle.philox([s, 1 << 24, 0, 0], [key, 0])
+        exp += 1
+        for c in range(2):
+            ox, oy = oracle.search_offset(int(u[2 * c]), 2, c), oracle.search_offset(int(u[2 * c + 1]), 2, c)
+            tx = min(max(px + 1 + ox, 0), w - 1) - px
+            ty = min(max(py + oy, 0), h - 1) - py
+            exp += (tx, ty) != (1, 0)
+    assert nev == exp
+    # the synchronous schedule spreads d* only to the two neighbours of seed (0, 0)
+    sync, _ = oracle.sweep(p, G1, G2, st, W=2, t0=0, n_iter=1, schedule=oracle.SYNC)
+    assert set(np.nonzero(sync["init"])[0]) == {0, 1, nx}
