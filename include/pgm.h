@@ -172,6 +172,23 @@ PGM_API pgm_status pgm_match_batch(void* ctx, const pgm_params* p, int32_t n_pai
                                    int32_t* out_n_inliers, pgm_match_t* out_compact, uint64_t* out_n_evals,
                                    void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): pgm_match without a context. The workspace is a
+ * fixed device array of PGM_STATIC_SCRATCH_BYTES inside the library, one per GPU, set up on
+ * the first call on each device (with that device current) and held until the process ends;
+ * the call itself allocates nothing. It runs on the current HIP device, with the arguments,
+ * outputs and stream of pgm_match. PGM_ENOMEM, before any device work, when the pair's
+ * workspace (pgm_query's workspace_bytes) exceeds the array: 64 MiB holds a 1024x436 or a
+ * 1242x375 pair with the configuration presets, not the dense paper preset at that size.
+ * Every call on one GPU uses the same array: calls that overlap on a GPU (different streams
+ * or host threads without ordering between them) race and give undefined results. The dump
+ * entry points do not see these calls; pgm_last_error(NULL) describes the last failure. */
+#define PGM_STATIC_SCRATCH_BYTES (64ull << 20)
+PGM_API pgm_status pgm_match_static(const pgm_params* p, const uint8_t* img1, const uint8_t* img2, int32_t w,
+                                    int32_t h, int32_t pitch_bytes, pgm_match_t* out_fwd, pgm_match_t* out_bwd,
+                                    int32_t* out_n_inliers, pgm_match_t* out_compact, uint64_t* out_n_evals,
+                                    void* stream);
+
 /* One group of a pgm_match_groups call: n_pairs pairs of one size and one parameter set, laid
  * out as for pgm_match_batch (pair k at img1/img2 + k * image_stride_bytes, outputs at
  * out_* + k * nx * ny and out_n_inliers[k]). All pointers are device pointers except params. */

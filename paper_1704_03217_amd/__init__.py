@@ -72,7 +72,8 @@ MATCH_DTYPE = np.dtype([("x1", "<i4"), ("y1", "<i4"), ("x2", "<i4"), ("y2", "<i4
                         ("dist", "<i4"), ("flags", "<u4")])
 MATCH_BYTES = 24
 
-EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_match_batch", "pgm_match_groups",
+EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_match_static", "pgm_match_batch",
+           "pgm_match_groups",
            "pgm_server_create", "pgm_server_submit", "pgm_server_poll", "pgm_server_pending",
            "pgm_server_drain", "pgm_server_last_error", "pgm_server_destroy", "pgm_format_matches",
            "pgm_dump_level",
@@ -113,6 +114,9 @@ def lib():
         L.pgm_match.argtypes = [V, C.POINTER(pgm_params), V, V, C.c_int32, C.c_int32, C.c_int32,
                                 V, V, V, V, V, V]
         L.pgm_match.restype = C.c_int32
+        L.pgm_match_static.argtypes = [C.POINTER(pgm_params), V, V, C.c_int32, C.c_int32, C.c_int32,
+                                       V, V, V, V, V, V]
+        L.pgm_match_static.restype = C.c_int32
         L.pgm_match_batch.argtypes = [V, C.POINTER(pgm_params), C.c_int32, V, V, C.c_int32, C.c_int32,
                                       C.c_int32, C.c_int64, V, V, V, V, V, V]
         L.pgm_match_batch.restype = C.c_int32
@@ -216,6 +220,17 @@ def pgm_match(ctx, p, img1: int, img2: int, w: int, h: int, pitch_bytes: int, ou
     """All pointer arguments are integer device addresses (or None)."""
     return _check(lib().pgm_match(ctx, C.byref(_as_params(p)), img1, img2, w, h, pitch_bytes, out_fwd,
                                   out_bwd, out_n_inliers, out_compact, out_n_evals, stream), ctx)
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def pgm_match_static(p, img1: int, img2: int, w: int, h: int, pitch_bytes: int, out_fwd: int,
+                     out_bwd: int | None = None, out_n_inliers: int | None = None,
+                     out_compact: int | None = None, out_n_evals: int | None = None, stream: int | None = None):
+    """pgm_match without a context (no device allocation); on the current HIP device."""
+    return _check(lib().pgm_match_static(C.byref(_as_params(p)), img1, img2, w, h, pitch_bytes, out_fwd,
+                                         out_bwd, out_n_inliers, out_compact, out_n_evals, stream), None)
 
 
 def pgm_match_batch(ctx, p, n_pairs: int, img1: int, img2: int, w: int, h: int, pitch_bytes: int,

@@ -5,6 +5,7 @@
 
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -844,6 +845,73 @@ pgm_status pgm_match_batch(void* ctx, const pgm_params* p, int32_t n_pairs, cons
     if (!c) return PGM_EINVAL;
     return match_impl(c, p, n_pairs, img1, img2, w, h, pitch_bytes, image_stride_bytes, out_fwd, out_bwd,
                       out_n_inliers, out_compact, out_n_evals, (hipStream_t)stream, c->ws, c->ws_bytes);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// pgm_match_static: pgm_match for callers that cannot allocate device memory. Its workspace
+// is this fixed device array (one copy per GPU, held until the process ends); host code uses
+// only the address hipGetSymbolAddress reports for the current device, never the array's
+// name. Every call on one GPU shares the array.
+// ---------------------------------------------------------------------------------------
+
+static __device__ __align__(256) uint8_t scratch[PGM_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+pgm_ctx_s g_static_ctx[STATIC_MAX_DEVICES];     // host state per device (no workspace of its own)
+uint8_t* g_scratch_ptr[STATIC_MAX_DEVICES];     // device address of `scratch` on each device
+bool g_static_ready[STATIC_MAX_DEVICES];
+}  // namespace
+
+extern "C" {
+
+pgm_status pgm_match_static(const pgm_params* p, const uint8_t* img1, const uint8_t* img2, int32_t w, int32_t h,
+                            int32_t pitch_bytes, pgm_match_t* out_fwd, pgm_match_t* out_bwd,
+                            int32_t* out_n_inliers, pgm_match_t* out_compact, uint64_t* out_n_evals,
+                            void* stream)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0)
+        return fail(nullptr, PGM_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev >= STATIC_MAX_DEVICES) return fail(nullptr, PGM_EUNSUPPORTED, "device index beyond 63");
+    pgm_ctx_s* c = &g_static_ctx[dev];
+    {
+        // set-up once per device, with that device current: the array's device address and
+        // the LDS limit of the whole-level kernels
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (!g_static_ready[dev]) {
+            void* ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(nullptr, PGM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            int v = 0;
+            e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+            if (e != hipSuccess)
+                return fail(nullptr, PGM_EDEVICE, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(e));
+            c->device = dev;
+            c->lds_max = v > 0 ? (size_t)v : 0;
+            if (c->lds_max > 65536 && level_allow_lds(c->lds_max - 64) != hipSuccess) (void)hipGetLastError();
+            g_scratch_ptr[dev] = (uint8_t*)ptr;
+            g_static_ready[dev] = true;
+        }
+    }
+    Layout Y;
+    if (pgm_status st = check_batch(c, p, 1, img1, img2, w, h, pitch_bytes, 0, out_fwd, Y))
+        return fail(nullptr, st, c->err);
+    if (Y.total > (size_t)PGM_STATIC_SCRATCH_BYTES)
+        return fail(nullptr, PGM_ENOMEM, "this pair needs " + std::to_string(Y.total) +
+                                             " bytes of workspace, more than the " +
+                                             std::to_string((unsigned long long)PGM_STATIC_SCRATCH_BYTES) +
+                                             " bytes of pgm_match_static's fixed array");
+    pgm_status st = match_impl(c, p, 1, img1, img2, w, h, pitch_bytes, 0, out_fwd, out_bwd, out_n_inliers,
+                               out_compact, out_n_evals, (hipStream_t)stream, g_scratch_ptr[dev],
+                               (size_t)PGM_STATIC_SCRATCH_BYTES);
+    if (st != PGM_OK) return fail(nullptr, st, c->err);
+    return PGM_OK;
 }
 
 pgm_status pgm_tune(void* ctx, const pgm_params* p, int32_t n_pairs, const uint8_t* img1, const uint8_t* img2,
