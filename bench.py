@@ -54,6 +54,13 @@ def parse():
     ap.add_argument("--served", type=int, default=240, help="requests per served run (0 = skip)")
     ap.add_argument("--served-pool", type=int, default=24, help="distinct generated request pairs")
     ap.add_argument("--paper-steps", type=int, default=20, help="steps of the paper-preset pass (0 = skip)")
+    ap.add_argument("--config-steps", type=int, default=100,
+                    help="steps of the 256x192 and 1242x375 plain passes (0 = skip)")
+    ap.add_argument("--served-pool-mib", type=int, default=2048, help="HBM budget of the request server's pool")
+    ap.add_argument("--cpu-all-seconds", type=float, default=8.0,
+                    help="wall time of the all-core oracle throughput run (0 = skip)")
+    ap.add_argument("--cpu-scan-seconds", type=float, default=6.0,
+                    help="CPU time of the oracle's sequential-scan timing (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a known-size kernel for HBM counter scaling)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -119,9 +126,12 @@ def measured_traffic():
         return None
 
 
-def sweep_roofline(pgm, ctx, steps, run, torch, traffic=None):
+def sweep_roofline(pgm, ctx, steps, run, torch, traffic=None, ops_per_eval=None, peak=None, unit="TOP/s",
+                   op="v_sad_u16 (two 16-bit absolute differences), 192 per 8x8x6 patch distance", bound="alu"):
     """Run `steps` steps with per-launch HIP events on; return (roofline of k_sweep, per-kind
-    breakdown). achieved = evaluations x 192 / launches / average launch duration."""
+    breakdown). achieved = evaluations x ops_per_eval / launches / average launch duration."""
+    ops_per_eval = OPS_PER_EVAL if ops_per_eval is None else ops_per_eval
+    peak = VALU_PEAK_TOPS if peak is None else peak
     pgm.pgm_profile(ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -140,12 +150,12 @@ def sweep_roofline(pgm, ctx, steps, run, torch, traffic=None):
     roof = None
     if sw:
         n_launch = sw["launches_per_step"] * steps
-        ops_per_launch = sw["evals"] * float(OPS_PER_EVAL) / n_launch
+        ops_per_launch = sw["evals"] * float(ops_per_eval) / n_launch
         achieved = ops_per_launch / (sw["avg_launch_us"] * 1e-6) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic,
+        roof = {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 2),
+                "unit": unit, "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": "k_sweep (propagation + random search half-sweep)",
-                "op": "v_sad_u16 (two 16-bit absolute differences), 192 per 8x8x6 patch distance",
+                "op": op,
                 "avg_launch_us": round(sw["avg_launch_us"], 3),
                 "ops_per_launch": round(ops_per_launch),
                 "profiled_ms_per_step": round(1000.0 * (t1 - t0) / steps, 4)}
@@ -251,17 +261,19 @@ def run_paper_preset(pgm, torch, m, imgs, stream, steps):
 
 
 def run_served(pgm, torch, dev, args, pre):
-    """Poisson request streams through the request server: capacity (all requests at once),
-    then arrivals at 50% and 80% of it; latency from arrival to observed completion."""
+    """Poisson request streams through the request server, whose queued requests of one shape
+    share launch sequences (continuous batching), and through plain per-pair launches (each
+    request alone, in arrival order, on one stream) for the same requests at the same arrival
+    times: capacity (all requests at once), then arrivals at 50% and 80% of the batching
+    server's capacity; latency from arrival to observed completion."""
     sizes, pool = pre["served"]
     imgs = [(torch.from_numpy(q.img1).to(dev), torch.from_numpy(q.img2).to(dev)) for q in pool]
     prm = [sized_params(pgm, w) for (w, h) in sizes]
     rng = np.random.default_rng(5001)
     order = rng.integers(0, len(pool), args.served)
-    need = max((pgm.pgm_query(prm[k], w, h).workspace_bytes + 255) // 256 * 256 for k, (w, h) in enumerate(sizes))
-    srv = pgm.Server(0, 16 * need, 4)
+    budget = args.served_pool_mib << 20
 
-    def run(arrivals):
+    def run(srv, arrivals):
         lat = np.zeros(len(arrivals))
         subm, done = 0, 0
         t0 = time.perf_counter()
@@ -276,25 +288,111 @@ def run_served(pgm, torch, dev, args, pre):
                 done += 1
         return lat, time.perf_counter() - t0
 
-    run(np.zeros(min(16, args.served)))    # warm-up
-    lat, span = run(np.zeros(args.served))
-    capacity = args.served / span
-    out = {"unit": "ms", "capacity_pairs_per_s": round(capacity, 2), "requests": args.served,
-           "streams": 4, "pool_bytes": 16 * need, "distinct_pairs": len(pool),
-           "workload": "Poisson arrivals; sizes log-uniform in area over [320x240, 2048x1024], aspect "
-                       "U[1.3, 3.3] (rectangle-layer generator, |d| <= w/5); config-2 matching with "
-                       "max_disp = ceil(w/5); requests drawn from the distinct generated pairs"}
+    servers = {"batched": pgm.Server(0, budget, 4), "plain": pgm.Server(0, budget, 1, max_batch=1)}
+    res = {}
+    for name, srv in servers.items():
+        run(srv, np.zeros(min(16, args.served)))    # warm-up
+        s0 = srv.stats()
+        lat, span = run(srv, np.zeros(args.served))
+        s1 = srv.stats()
+        res[name] = {"capacity_pairs_per_s": round(args.served / span, 2),
+                     "launch_sequences": s1[0] - s0[0], "requests": s1[1] - s0[1]}
+    capacity = res["batched"]["capacity_pairs_per_s"]
+    arrivals = {}
     for frac in (0.5, 0.8):
         qps = frac * capacity
         arr = np.cumsum(rng.exponential(1.0 / qps, args.served))
-        arr -= arr[0]
-        print(f"[bench] served at {qps:.0f} pairs/s", file=sys.stderr, flush=True)
-        lat, span = run(arr)
-        out[f"at_{int(frac * 100)}pct"] = {"qps": round(qps, 2), "p50_ms": round(1000 * float(np.percentile(lat, 50)), 3),
-                                           "p99_ms": round(1000 * float(np.percentile(lat, 99)), 3),
-                                           "pairs_per_s": round(args.served / span, 2)}
-    srv.close()
+        arrivals[frac] = (qps, arr - arr[0])
+    for name, srv in servers.items():
+        for frac, (qps, arr) in arrivals.items():
+            print(f"[bench] served ({name}) at {qps:.0f} pairs/s", file=sys.stderr, flush=True)
+            s0 = srv.stats()
+            lat, span = run(srv, arr)
+            s1 = srv.stats()
+            res[name][f"at_{int(frac * 100)}pct"] = {
+                "qps": round(qps, 2), "p50_ms": round(1000 * float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(1000 * float(np.percentile(lat, 99)), 3),
+                "pairs_per_s": round(args.served / span, 2),
+                "mean_requests_per_launch_sequence": round((s1[1] - s0[1]) / max(1, s1[0] - s0[0]), 3)}
+        srv.close()
+    out = {"unit": "ms", "capacity_pairs_per_s": capacity, "requests": args.served, "pool_bytes": budget,
+           "distinct_pairs": len(pool), "batched_server": res["batched"], "plain_per_pair": res["plain"],
+           "workload": "Poisson arrivals; sizes log-uniform in area over [320x240, 2048x1024], aspect "
+                       "U[1.3, 3.3] (rectangle-layer generator, |d| <= w/5); config-2 matching with "
+                       "max_disp = ceil(w/5); requests drawn from the distinct generated pairs; batched_server: "
+                       "4 streams, requests of one shape share launch sequences (at most 16, at most 8 "
+                       "sequences in flight); plain_per_pair: pgm_match per request in arrival order on one "
+                       "stream; pool = the stated HBM budget"}
+    for frac in (0.5, 0.8):
+        out[f"at_{int(frac * 100)}pct"] = res["batched"][f"at_{int(frac * 100)}pct"]
     return out
+
+
+def run_config_pass(pgm, torch, dev, config, preset, steps, ops_per_eval, peak, unit, op, bound):
+    """Plain passes of another workload (one pair per call): pairs/s, evaluations/s and the
+    half-sweep's roofline fraction."""
+    import synth
+    pairs = [synth.config_pair(config, i) for i in range(2)]
+    params = pgm.pgm_default_params(preset)
+    h, w = pairs[0].img1.shape[:2]
+    imgs = [(torch.from_numpy(p.img1).to(dev), torch.from_numpy(p.img2).to(dev)) for p in pairs]
+    m = pgm.Matcher(0, pgm.pgm_query(params, w, h).workspace_bytes + (1 << 20))
+    outs = [m.outputs(params, w, h, count_evals=False) for _ in imgs]
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def step(k):
+        m.match_into(params, *imgs[k % 2], outs[k % 2], stream=stream)
+
+    for k in range(10):
+        step(k)
+    torch.cuda.synchronize()
+    print(f"[bench] config {config} ({w}x{h}): timing {steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    counted = [m.outputs(params, w, h, count_evals=True) for _ in imgs]
+    for k in range(2):
+        m.match_into(params, *imgs[k], counted[k], stream=stream)
+    torch.cuda.synchronize()
+    per_pair = [int(o["n_evals"].item()) for o in counted]
+    evals = sum(per_pair[k % 2] for k in range(steps))
+    roof, _ = sweep_roofline(pgm, m.ctx, steps, step, torch, None, ops_per_eval, peak, unit, op, bound)
+    m.close()
+    return {"value": round(steps / (t1 - t0), 3), "unit": "pairs/s", "steps": steps,
+            "ms_per_step": round(1000.0 * (t1 - t0) / steps, 4), "dist_evals_per_pair": evals / steps,
+            "dist_evals_per_s": round(evals / (t1 - t0), 1), "roofline": roof}
+
+
+def _oracle_worker(args):
+    """One process of the all-core oracle run: runs until `seconds` of wall time are spent."""
+    params_d, pair_ids, seconds, schedule = args
+    import oracle
+    import synth
+    pairs = [synth.config_pair(2, i) for i in pair_ids]
+    t0 = time.perf_counter()
+    runs = 0
+    while time.perf_counter() - t0 < seconds:
+        p = pairs[runs % len(pairs)]
+        oracle.match(params_d, p.img1, p.img2, schedule=schedule, trace=False)
+        runs += 1
+    return runs, time.perf_counter() - t0
+
+
+def cpu_all_cores(params_d, seconds):
+    """Throughput of independent oracle processes, one per host core (different pairs)."""
+    import multiprocessing as mp
+    import oracle
+    n = os.cpu_count() or 1
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(n) as pool:
+        res = pool.map(_oracle_worker, [(params_d, [k % 2], seconds, oracle.SYNC) for k in range(n)])
+    runs = sum(r for r, _ in res)
+    wall = max(t for _, t in res)
+    return {"value": round(runs / wall, 4), "unit": "pairs/s", "cores": n, "processes": n, "runs": runs,
+            "sample": f"{n} independent single-threaded oracle processes (synchronous schedule), each "
+                      f"looping over a 1024x436 config-2 pair for {seconds:.0f} s of wall time"}
 
 
 def main():
@@ -396,6 +494,9 @@ def main():
         Bm = torch.stack([imgs[k % len(imgs)][1] for k in range(B)]).contiguous()
         ob = mb.outputs_batch(params, w, h, B, count_evals=False)
 
+        # the launch schedule for this workload, picked by the library's tuner (untimed)
+        sched = mb.tune(params, A, Bm, ob, repeats=2, stream=stream)
+
         def bstep(k):
             mb.match_batch_into(params, A, Bm, ob, stream=stream)
 
@@ -420,9 +521,28 @@ def main():
         batched = {"value": round(B * args.batch_steps / (b1 - b0), 3), "unit": "pairs/s", "global_batch": B,
                    "steps": args.batch_steps, "ms_per_step": round(1000.0 * (b1 - b0) / args.batch_steps, 4),
                    "dist_evals_per_s": round(bev / (b1 - b0), 1), "pair0_equals_plain": same,
+                   "schedule_flags": sched,
                    "roofline": broof, "kernels": bkern}
         mb.close()
 
+    configs = {}
+    if args.config_steps > 0:
+        configs["config1_256x192"] = run_config_pass(pgm, torch, dev, 1, pgm.PRESET_CONFIG1, args.config_steps,
+                                                     OPS_PER_EVAL, VALU_PEAK_TOPS, "TOP/s",
+                                                     "v_sad_u16 (two 16-bit absolute differences), 192 per 8x8x6 "
+                                                     "patch distance", "alu")
+        configs["config1_256x192"]["workload"] = (
+            "plain, one 256x192 pair per step: 4 textured rectangles with integer motion |d| <= 20; L=3, stride 3, "
+            "8x8 patch, 4 iterations, int16 gradients with int32 SAD, fwd+bwd tau=1")
+        # float direction features: each patch element is a subtraction and an addition in
+        # double precision (exact, see the kernels), 2 x 384 fp64 operations per distance
+        configs["config3_1242x375"] = run_config_pass(pgm, torch, dev, 3, pgm.PRESET_CONFIG3, args.config_steps,
+                                                      2 * 8 * 8 * 6, 78.6, "TFLOP/s",
+                                                      "fp64 subtract + add per element of the unit-vector features, "
+                                                      "768 per 8x8x6 patch distance", "alu")
+        configs["config3_1242x375"]["workload"] = (
+            "plain, one 1242x375 pair per step: ground plane with perspective flow, far background, 3 boxes, "
+            "|d| <= 250; direction-only float features (unit gradient vectors), L=5, stride 3, 8x8, 6 iterations")
     groups = run_groups(pgm, torch, dev, args, stream, pre) if args.groups_pairs > 0 else None
     served = run_served(pgm, torch, dev, args, pre) if args.served > 0 else None
     paper = run_paper_preset(pgm, torch, m, imgs, stream, args.paper_steps) if args.paper_steps > 0 else None
@@ -443,6 +563,19 @@ def main():
                "sample": f"{runs} oracle runs (single-threaded C, synchronous schedule) over {len(pairs)} "
                          f"1024x436 config-2 pairs, {spent:.1f} s",
                "cpu": _cpu_name(), "host_cores": os.cpu_count()}
+        if args.cpu_scan_seconds > 0:
+            runs, spent = 0, 0.0
+            while spent < args.cpu_scan_seconds and runs < 64:
+                p = pairs[runs % len(pairs)]
+                c0 = time.perf_counter()
+                oracle.match(params_d, p.img1, p.img2, schedule=oracle.SCAN, trace=False)
+                spent += time.perf_counter() - c0
+                runs += 1
+            cpu["scan_schedule"] = {"value": round(runs / spent, 4), "unit": "pairs/s", "cores": 1,
+                                    "sample": f"{runs} runs of the paper's sequential raster order, {spent:.1f} s"}
+        if args.cpu_all_seconds > 0:
+            print("[bench] oracle on every host core", file=sys.stderr, flush=True)
+            cpu["all_cores"] = cpu_all_cores(params_d, args.cpu_all_seconds)
 
     out = {
         "metric": METRIC,
@@ -468,6 +601,7 @@ def main():
         "kernels": kernels,
         "batched": groups,
         "batched_uniform": batched,
+        "configs": configs,
         "served": served,
         "paper_preset": paper,
         "cpu_baseline": cpu,

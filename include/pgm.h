@@ -219,31 +219,40 @@ PGM_API pgm_status pgm_match_groups(void* ctx, int32_t n_groups, const pgm_group
 
 /* Request server: pairs of any size and parameters arrive one at a time and are matched
  * concurrently. A server owns a device memory pool of pool_bytes and n_streams HIP streams
- * (1..16); at most max_queued requests wait for memory (0 = 4096).
+ * (1..16); at most max_queued requests wait for memory (0 = 4096), and up to max_batch
+ * requests (1..16, 0 = 16) may share one launch sequence.
  * pgm_server_submit queues a request (the pgm_match arguments plus a caller tag) and starts
- * queued requests, oldest first, while the head's workspace (pgm_query's workspace_bytes
- * rounded up to 256) fits in the pool; a started request runs as pgm_match on the least
- * loaded stream, so its results equal pgm_match on that pair alone. Its launches are ordered
- * after the work the caller had issued on `stream` (hipStream_t or NULL) when it submitted,
- * so inputs and zero-filled outputs produced there are seen. PGM_EBUSY when max_queued
- * requests are already waiting (nothing is queued: poll, then submit again).
+ * queued requests, oldest first, while fewer than n_streams launch sequences are in flight
+ * (pgm_server_poll and pgm_server_drain: fewer than 2 * n_streams) and the head's workspace
+ * (pgm_query's workspace_bytes rounded up to 256) fits in the pool; under load requests
+ * gather in the queue meanwhile. The head starts together with the later queued
+ * requests of the same width, height, pitch and parameters that ask for the same outputs
+ * (at most max_batch, as many as the free memory holds): they run as one batch whose kernels
+ * cover every pair (each pair's buffers from a pointer table), so per-pair launch costs are
+ * paid once, on the least loaded stream. Every request's results equal pgm_match on that pair
+ * alone. A request's launches are ordered after the work the caller had issued on `stream`
+ * (hipStream_t or NULL) when it submitted, so inputs and zero-filled outputs produced there
+ * are seen. PGM_EBUSY when max_queued requests are already waiting (nothing is queued:
+ * poll, then submit again).
  * pgm_server_poll reports finished requests: it writes up to max_tags tags to host_tags and,
  * when host_status is not NULL, each request's status (PGM_OK, or the error that stopped its
  * launches: its outputs are then undefined), returns their number (or a negative
  * pgm_status), frees their memory and starts queued requests. A request whose launches failed
  * keeps its memory until its stream has passed them. The caller keeps a request's images and
  * outputs alive until its tag is reported. pgm_server_drain waits until nothing is queued or
- * running (the finished tags stay for pgm_server_poll). Argument errors are reported by
+ * running (the finished tags stay for pgm_server_poll). pgm_server_stats reports the launch
+ * sequences and the requests started so far. Argument errors are reported by
  * pgm_server_submit synchronously, and PGM_ENOMEM when the request alone exceeds the pool.
  * One host thread per server. */
 PGM_API pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_streams, int32_t max_queued,
-                                     void** out_server);
+                                     int32_t max_batch, void** out_server);
 PGM_API pgm_status pgm_server_submit(void* server, const pgm_params* p, const uint8_t* img1,
                                      const uint8_t* img2, int32_t w, int32_t h, int32_t pitch_bytes,
                                      pgm_match_t* out_fwd, pgm_match_t* out_bwd, int32_t* out_n_inliers,
                                      pgm_match_t* out_compact, uint64_t* out_n_evals, uint64_t tag,
                                      void* stream);
 PGM_API int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t* host_status, int32_t max_tags);
+PGM_API pgm_status pgm_server_stats(void* server, int64_t* host_sequences, int64_t* host_started);
 PGM_API pgm_status pgm_server_pending(void* server, int32_t* host_queued, int32_t* host_running,
                                       int32_t* host_finished);
 PGM_API pgm_status pgm_server_drain(void* server);

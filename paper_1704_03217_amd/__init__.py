@@ -74,7 +74,7 @@ MATCH_BYTES = 24
 
 EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_match_static", "pgm_match_batch",
            "pgm_match_groups",
-           "pgm_server_create", "pgm_server_submit", "pgm_server_poll", "pgm_server_pending",
+           "pgm_server_create", "pgm_server_submit", "pgm_server_poll", "pgm_server_stats", "pgm_server_pending",
            "pgm_server_drain", "pgm_server_last_error", "pgm_server_destroy", "pgm_format_matches",
            "pgm_dump_level",
            "pgm_dump_gradient", "pgm_dump_pyramid", "pgm_schedule", "pgm_tune", "pgm_profile", "pgm_profile_read",
@@ -122,13 +122,16 @@ def lib():
         L.pgm_match_batch.restype = C.c_int32
         L.pgm_match_groups.argtypes = [V, C.c_int32, C.POINTER(pgm_group), V, C.c_int32, V]
         L.pgm_match_groups.restype = C.c_int32
-        L.pgm_server_create.argtypes = [C.c_int32, C.c_uint64, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]
+        L.pgm_server_create.argtypes = [C.c_int32, C.c_uint64, C.c_int32, C.c_int32, C.c_int32,
+                                        C.POINTER(C.c_void_p)]
         L.pgm_server_create.restype = C.c_int32
         L.pgm_server_submit.argtypes = [V, C.POINTER(pgm_params), V, V, C.c_int32, C.c_int32, C.c_int32,
                                         V, V, V, V, V, C.c_uint64, V]
         L.pgm_server_submit.restype = C.c_int32
         L.pgm_server_poll.argtypes = [V, C.POINTER(C.c_uint64), C.POINTER(C.c_int32), C.c_int32]
         L.pgm_server_poll.restype = C.c_int32
+        L.pgm_server_stats.argtypes = [V, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.pgm_server_stats.restype = C.c_int32
         L.pgm_server_pending.argtypes = [V, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.pgm_server_pending.restype = C.c_int32
         L.pgm_server_drain.argtypes = [V]
@@ -257,9 +260,9 @@ def _check_server(status, server):
     return status
 
 
-def pgm_server_create(device: int, pool_bytes: int, n_streams: int, max_queued: int = 0):
+def pgm_server_create(device: int, pool_bytes: int, n_streams: int, max_queued: int = 0, max_batch: int = 0):
     h = C.c_void_p()
-    _check_server(lib().pgm_server_create(device, pool_bytes, n_streams, max_queued, C.byref(h)), None)
+    _check_server(lib().pgm_server_create(device, pool_bytes, n_streams, max_queued, max_batch, C.byref(h)), None)
     return h
 
 
@@ -277,6 +280,13 @@ def pgm_server_poll(server, max_tags: int = 256) -> list:
     st = (C.c_int32 * max(1, max_tags))()
     n = _check_server(lib().pgm_server_poll(server, buf, st, max_tags), server)
     return [(buf[k], st[k]) for k in range(n)]
+
+
+def pgm_server_stats(server):
+    """(launch sequences, requests) started so far."""
+    a, b = C.c_int64(), C.c_int64()
+    _check_server(lib().pgm_server_stats(server, C.byref(a), C.byref(b)), server)
+    return a.value, b.value
 
 
 def pgm_server_pending(server):
@@ -536,11 +546,12 @@ class Server:
     CUDA image tensors and returns the tag; poll() returns the tags of finished requests.
     The server keeps references to each request's tensors until its tag has been reported."""
 
-    def __init__(self, device: int = 0, pool_bytes: int = 1 << 30, n_streams: int = 4, max_queued: int = 0):
+    def __init__(self, device: int = 0, pool_bytes: int = 1 << 30, n_streams: int = 4, max_queued: int = 0,
+                 max_batch: int = 0):
         import torch  # device memory and streams only
         self.torch = torch
         self.device = device
-        self.h = pgm_server_create(device, pool_bytes, n_streams, max_queued)
+        self.h = pgm_server_create(device, pool_bytes, n_streams, max_queued, max_batch)
         self.live = {}
         self.next_tag = 0
 
@@ -599,6 +610,9 @@ class Server:
 
     def pending(self):
         return pgm_server_pending(self.h)
+
+    def stats(self):
+        return pgm_server_stats(self.h)
 
     def drain(self):
         pgm_server_drain(self.h)

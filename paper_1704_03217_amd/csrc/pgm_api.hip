@@ -1,5 +1,6 @@
 // C ABI of libpgm (declared in include/pgm.h): parameter validation, workspace layout, the
 // level schedule of Sec. III-D and the kernel launches of one pair.
+#include <stddef.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -23,6 +24,7 @@ struct Layout {
     size_t grad[4][PGM_MAX_LEVELS];                      // padded gradient images (4 slots)
     size_t disp[2][PGM_MAX_LEVELS], dist[2][PGM_MAX_LEVELS], flags[2][PGM_MAX_LEVELS];
     size_t rnd = 0, rnd_init = 0;
+    size_t tab = 0;                                      // PairTab entries of a table-driven batch
     // stages of the schedule
     int nst = 0;
     int st_level[MAX_STAGES], st_enter[MAX_STAGES], st_W[MAX_STAGES], st_nI[MAX_STAGES];
@@ -159,6 +161,7 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
     size_t cur = 0;
     Y.rnd = take(cur, (size_t)base * sizeof(short2) + 4);
     Y.rnd_init = take(cur, (size_t)2 * Y.lnx[m] * Y.lny[m] * sizeof(short2));
+    Y.tab = take(cur, (size_t)TAB_MAX * sizeof(PairTab));
     Y.shared_bytes = (cur + 255) & ~(size_t)255;
 
     // per-pair slice
@@ -429,15 +432,21 @@ static pgm_status check_batch(pgm_ctx_s* c, const pgm_params* p, int32_t npairs,
 }
 
 // The whole method for a batch of pairs, with the workspace region [wsb, wsb + wsn).
+// With host_tab (npairs <= TAB_MAX entries), every pair brings its own images and outputs:
+// img1, img2 and the out_* arguments are then those of entry 0 (for the checks) and are not
+// used otherwise; out_n_evals must be null (each entry has its own counter).
 static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, const uint8_t* img1,
                              const uint8_t* img2, int32_t w, int32_t h, int32_t pitch_bytes,
                              int64_t image_stride_bytes, pgm_match_t* out_fwd, pgm_match_t* out_bwd,
                              int32_t* out_n_inliers, pgm_match_t* out_compact, uint64_t* out_n_evals,
-                             hipStream_t s, uint8_t* wsb, size_t wsn)
+                             hipStream_t s, uint8_t* wsb, size_t wsn, const PairTab* host_tab = nullptr)
 {
     Layout Y;
+    if (host_tab) image_stride_bytes = (int64_t)pitch_bytes * h;   // unused: the table has the images
     if (pgm_status st = check_batch(c, p, npairs, img1, img2, w, h, pitch_bytes, image_stride_bytes, out_fwd, Y))
         return st;
+    if (host_tab && (npairs > TAB_MAX || out_n_evals))
+        return fail(c, PGM_EINVAL, "a table-driven batch holds at most 16 pairs and counts per pair");
     const size_t need = Y.shared_bytes + (size_t)npairs * Y.pair_bytes;
     if (need > wsn)
         return fail(c, PGM_ENOMEM, "workspace of " + std::to_string(wsn) + " bytes is smaller than the " +
@@ -492,9 +501,18 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         }
         return e;
     };
+    // the per-pair buffers of a table-driven batch, written into the workspace first
+    const PairTab* dtab = nullptr;
+    bool tab_counts = false;
+    if (host_tab) {
+        dtab = (const PairTab*)(ws + Y.tab);
+        for (int k = 0; k < npairs; k++) tab_counts = tab_counts || host_tab[k].n_evals;
+        c->nlaunch++;
+        PGM_HIP(c, launch_fill_tab((PairTab*)dtab, host_tab, npairs, s));
+    }
     // evaluation counts: each matching launch stores one count per work-group into its kind's
     // table (per pair); k_count adds them up at the end
-    const bool counting = nev || c->prof;
+    const bool counting = nev || c->prof || tab_counts;
     long long cnt_off[4] = {0, 0, 0, 0};
     auto ctable = [&](int kind, long long blocks) -> uint32_t* {
         if (!counting) return nullptr;
@@ -544,6 +562,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
             L.h = Y.lh[l];
             L.G[0] = pw0 + Y.grad[2 * half][l];
             L.G[1] = pw0 + Y.grad[2 * half + 1][l];
+            L.tab = l == 0 ? dtab : nullptr;   // level 0 reads the caller's images
             L.space = half ? p->space_bwd[l] : p->space_fwd[l];
         }
     };
@@ -571,6 +590,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     pa.with_pyr = Y.L > 1;
     if (pa.with_pyr) {
         pyr_level(pa.pyr, 1, img1, img2, image_stride_bytes, pitch_bytes);
+        pa.pyr.tab = dtab;
         second_level(pa.pyr, 1);
     }
     PGM_HIP(c, timed(PGM_K_PREP, [&] { return launch_prep(pa, npairs, gray, p->sobel_ksize, p->feature, s); }));
@@ -793,6 +813,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     oa.out[1] = out_bwd;
     oa.compact = out_compact;
     oa.n_out = out_n_inliers;
+    oa.tab = dtab;
     oa.dist8 = Y.dsize == 8;
     PGM_HIP(c, timed(PGM_K_OUTPUT, [&] { return launch_output(oa, s); }));
     PGM_HIP(c, close_run());
@@ -808,6 +829,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         ca.zs = zs;
         ca.user = nev;
         ca.prof = c->prof ? c->prof_evals : nullptr;
+        ca.tab = dtab;
         c->nlaunch += 2;
         PGM_HIP(c, launch_count(ca, (unsigned long long*)(pw0 + Y.cntpart), s));
     }
@@ -1086,9 +1108,12 @@ struct pgm_server_s {
     pgm_ctx_s* c = nullptr;                       // its workspace is the memory pool
     std::map<size_t, size_t> free_;               // free pool blocks: offset -> bytes
     std::vector<hipStream_t> streams;
-    std::vector<int> load;                        // requests in flight per stream
+    std::vector<int> load;                        // launch sequences in flight per stream
     std::vector<hipEvent_t> spare;                // events not in use (completion and submission)
     int max_queued = 0;                           // submissions beyond this return PGM_EBUSY
+    int max_batch = 1;                            // requests that may share one launch sequence
+    int max_running = 2;                          // launch sequences in flight (2 per stream)
+    long long n_batches = 0, n_started = 0;       // launch sequences and requests started
     struct Req {
         pgm_params p;
         const uint8_t* img1;
@@ -1100,14 +1125,18 @@ struct pgm_server_s {
         pgm_match_t* out_compact;
         uint64_t* out_n_evals;
         uint64_t tag;
+        size_t need;        // workspace of the request alone
+        hipEvent_t ready;   // recorded on the caller's stream at submission
+    };
+    struct Run {            // one launch sequence: one request, or several of the same shape
+        std::vector<Req> reqs;
         size_t need, off;
         int stream;
-        hipEvent_t ready;   // recorded on the caller's stream at submission
-        hipEvent_t done;    // recorded on the server stream after the request's launches
-        pgm_status status;  // PGM_OK, or the error that stopped the request's launches
+        hipEvent_t done;    // recorded on the server stream after the sequence's launches
+        pgm_status status;  // PGM_OK, or the error that stopped the launches
     };
     std::deque<Req> queued;
-    std::vector<Req> running;
+    std::vector<Run> running;
     std::deque<std::pair<uint64_t, pgm_status>> finished;
 
     hipError_t take_event(hipEvent_t* ev)
@@ -1122,7 +1151,6 @@ struct pgm_server_s {
         spare.pop_back();
         return hipSuccess;
     }
-
     bool alloc(size_t need, size_t& off)
     {
         for (auto it = free_.begin(); it != free_.end(); ++it) {
@@ -1153,46 +1181,103 @@ struct pgm_server_s {
     }
 };
 
-// start queued requests, oldest first, while the head fits in the pool. A request's launches
-// wait for its submission event (the caller's stream at submit time). A request whose launches
-// fail part-way is still tracked until its stream passes its completion event, so that its
-// memory is not handed out while launches may still use it; it is then reported with its
-// error status.
-static pgm_status server_admit(pgm_server_s* S)
+// Requests share a launch sequence when they have the same size, pitch and parameters (so the
+// same random numbers) and ask for the same outputs; each pair's buffers then come from the
+// batch's pointer table, and its results equal those of pgm_match on that pair alone.
+static bool same_shape(const pgm_server_s::Req& a, const pgm_server_s::Req& b)
+{
+    return a.w == b.w && a.h == b.h && a.pitch == b.pitch && memcmp(&a.p, &b.p, sizeof a.p) == 0 &&
+           !a.out_bwd == !b.out_bwd && !a.out_n_inliers == !b.out_n_inliers && !a.out_compact == !b.out_compact &&
+           !a.out_n_evals == !b.out_n_evals;
+}
+
+// Start queued requests, oldest first, while fewer than max_running launch sequences are in
+// flight and the head fits in the pool: the head together with up to max_batch - 1 later
+// requests of its shape, as many as the free memory holds (at least the head). Submission
+// starts requests only while fewer sequences than streams are in flight, polling up to two per
+// stream: under load (the GPU busy, or the host busy issuing launches) requests gather in the
+// queue, and then start in batches whose launch costs they share. A started sequence waits for the submission events of its requests (the
+// callers' streams at submit time). A sequence whose launches fail part-way is still tracked
+// until its stream passes its completion event, so that its memory is not handed out while
+// launches may still use it; its requests are then reported with the error status.
+static pgm_status server_admit(pgm_server_s* S, int max_running)
 {
     pgm_ctx_s* c = S->c;
-    while (!S->queued.empty()) {
-        pgm_server_s::Req r = S->queued.front();
-        if (!S->alloc(r.need, r.off)) break;
-        int k = 0;
+    while (!S->queued.empty() && (int)S->running.size() < max_running) {
+        const pgm_server_s::Req& head = S->queued.front();
+        std::vector<size_t> pick(1, 0);
+        for (size_t k = 1; k < S->queued.size() && (int)pick.size() < S->max_batch; k++)
+            if (same_shape(head, S->queued[k])) pick.push_back(k);
+        Layout Y;
+        plan(&head.p, head.w, head.h, Y);
+        size_t n = pick.size(), off = 0, need = 0;
+        for (; n > 0; n--) {
+            need = n == 1 ? head.need : ((Y.shared_bytes + n * Y.pair_bytes + 255) & ~(size_t)255);
+            if (S->alloc(need, off)) break;
+        }
+        if (n == 0) break;
+        pgm_server_s::Run r;
+        r.need = need;
+        r.off = off;
+        r.status = PGM_OK;
+        for (size_t k = 0; k < n; k++) r.reqs.push_back(S->queued[pick[k]]);
+        for (size_t k = n; k-- > 0;) S->queued.erase(S->queued.begin() + (long)pick[k]);
+        int q = 0;
         for (int i = 1; i < (int)S->streams.size(); i++)
-            if (S->load[i] < S->load[k]) k = i;
-        r.stream = k;
+            if (S->load[i] < S->load[q]) q = i;
+        r.stream = q;
         hipError_t e = S->take_event(&r.done);
         if (e != hipSuccess) {
-            S->release(r.off, r.need);
+            // nothing launched: back to the head of the queue, in order
+            for (size_t k = n; k-- > 0;) S->queued.push_front(r.reqs[k]);
+            S->release(off, need);
             return fail(c, PGM_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
         }
-        S->queued.pop_front();
-        e = hipStreamWaitEvent(S->streams[k], r.ready, 0);
-        r.status = e == hipSuccess ? PGM_OK : fail(c, PGM_EDEVICE, std::string("hipStreamWaitEvent: ") +
-                                                                       hipGetErrorString(e));
-        if (r.status == PGM_OK)
-            r.status = match_impl(c, &r.p, 1, r.img1, r.img2, r.w, r.h, r.pitch, 0, r.out_fwd, r.out_bwd,
-                                  r.out_n_inliers, r.out_compact, r.out_n_evals, S->streams[k], c->ws + r.off,
-                                  r.need);
-        e = hipEventRecord(r.done, S->streams[k]);
+        const hipStream_t st = S->streams[q];
+        for (const auto& rq : r.reqs) {
+            e = hipStreamWaitEvent(st, rq.ready, 0);
+            if (e != hipSuccess && r.status == PGM_OK)
+                r.status = fail(c, PGM_EDEVICE, std::string("hipStreamWaitEvent: ") + hipGetErrorString(e));
+        }
+        const pgm_server_s::Req& h0 = r.reqs[0];
+        if (r.status == PGM_OK) {
+            if (n == 1) {
+                r.status = match_impl(c, &h0.p, 1, h0.img1, h0.img2, h0.w, h0.h, h0.pitch, 0, h0.out_fwd, h0.out_bwd,
+                                      h0.out_n_inliers, h0.out_compact, h0.out_n_evals, st, c->ws + off, need);
+            } else {
+                PairTab tab[TAB_MAX];
+                for (size_t k = 0; k < n; k++) {
+                    const pgm_server_s::Req& q2 = r.reqs[k];
+                    tab[k].img[0] = q2.img1;
+                    tab[k].img[1] = q2.img2;
+                    tab[k].out[0] = q2.out_fwd;
+                    tab[k].out[1] = q2.out_bwd;
+                    tab[k].compact = q2.out_compact;
+                    tab[k].n_in = q2.out_n_inliers;
+                    tab[k].n_evals = (unsigned long long*)q2.out_n_evals;
+                    tab[k].unused = nullptr;
+                }
+                r.status = match_impl(c, &h0.p, (int32_t)n, h0.img1, h0.img2, h0.w, h0.h, h0.pitch, 0, h0.out_fwd,
+                                      h0.out_bwd, h0.out_n_inliers, h0.out_compact, nullptr, st, c->ws + off, need,
+                                      tab);
+            }
+        }
+        S->n_batches++;
+        S->n_started += (long long)n;
+        e = hipEventRecord(r.done, st);
         if (e != hipSuccess) {
             // without a completion event, wait for the stream before the memory is reused
-            (void)hipStreamSynchronize(S->streams[k]);
-            S->release(r.off, r.need);
+            (void)hipStreamSynchronize(st);
+            S->release(off, need);
             S->spare.push_back(r.done);
-            S->spare.push_back(r.ready);
-            S->finished.emplace_back(r.tag, r.status != PGM_OK ? r.status : PGM_EDEVICE);
+            for (const auto& rq : r.reqs) {
+                S->spare.push_back(rq.ready);
+                S->finished.emplace_back(rq.tag, r.status != PGM_OK ? r.status : PGM_EDEVICE);
+            }
             return fail(c, PGM_EDEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
         }
-        S->load[k]++;
-        S->running.push_back(r);
+        S->load[q]++;
+        S->running.push_back(std::move(r));
     }
     return PGM_OK;
 }
@@ -1202,7 +1287,7 @@ static pgm_status server_reap(pgm_server_s* S, bool wait)
 {
     pgm_ctx_s* c = S->c;
     for (size_t i = 0; i < S->running.size();) {
-        pgm_server_s::Req& r = S->running[i];
+        pgm_server_s::Run& r = S->running[i];
         hipError_t e = wait ? hipEventSynchronize(r.done) : hipEventQuery(r.done);
         if (e == hipErrorNotReady) {
             i++;
@@ -1211,21 +1296,24 @@ static pgm_status server_reap(pgm_server_s* S, bool wait)
         if (e != hipSuccess) return fail(c, PGM_EDEVICE, std::string("request: ") + hipGetErrorString(e));
         S->release(r.off, r.need);
         S->spare.push_back(r.done);
-        S->spare.push_back(r.ready);
+        for (const auto& rq : r.reqs) {
+            S->spare.push_back(rq.ready);
+            S->finished.emplace_back(rq.tag, r.status);
+        }
         S->load[r.stream]--;
-        S->finished.emplace_back(r.tag, r.status);
-        S->running.erase(S->running.begin() + i);
+        S->running.erase(S->running.begin() + (long)i);
     }
     return PGM_OK;
 }
 
 pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_streams, int32_t max_queued,
-                             void** out_server)
+                             int32_t max_batch, void** out_server)
 {
     if (!out_server) return fail(nullptr, PGM_EINVAL, "out_server is null");
     *out_server = nullptr;
     if (n_streams < 1 || n_streams > 16) return fail(nullptr, PGM_EINVAL, "n_streams must be in 1..16");
     if (max_queued < 0) return fail(nullptr, PGM_EINVAL, "max_queued must not be negative");
+    if (max_batch < 0 || max_batch > TAB_MAX) return fail(nullptr, PGM_EINVAL, "max_batch must be in 0..16");
     void* ctx = nullptr;
     pgm_status st = pgm_create(device, pool_bytes, &ctx);
     if (st != PGM_OK) return st;
@@ -1233,6 +1321,8 @@ pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_stre
     S->c = (pgm_ctx_s*)ctx;
     S->c->concurrent = true;
     S->max_queued = max_queued ? max_queued : 4096;
+    S->max_batch = max_batch ? max_batch : TAB_MAX;
+    S->max_running = 2 * n_streams;
     S->free_[0] = S->c->ws_bytes & ~(size_t)255;
     for (int i = 0; i < n_streams; i++) {
         hipStream_t q;
@@ -1262,16 +1352,17 @@ pgm_status pgm_server_submit(void* server, const pgm_params* p, const uint8_t* i
     if (pgm_status st = check_batch(c, p, 1, img1, img2, w, h, pitch_bytes, 0, out_fwd, Y)) return st;
     pgm_server_s::Req r;
     r.p = *p;
+    {   // the padding before rng_seed is zeroed so that equal parameters compare equal bytewise
+        const size_t a = offsetof(pgm_params, rs_mode) + sizeof(int32_t);
+        memset((unsigned char*)&r.p + a, 0, offsetof(pgm_params, rng_seed) - a);
+    }
     r.img1 = img1; r.img2 = img2;
     r.w = w; r.h = h; r.pitch = pitch_bytes;
     r.out_fwd = out_fwd; r.out_bwd = out_bwd; r.out_n_inliers = out_n_inliers; r.out_compact = out_compact;
     r.out_n_evals = out_n_evals;
     r.tag = tag;
     r.need = (Y.shared_bytes + Y.pair_bytes + 255) & ~(size_t)255;
-    r.off = 0;
-    r.stream = 0;
-    r.done = nullptr;
-    r.status = PGM_OK;
+    r.ready = nullptr;
     if (r.need > (c->ws_bytes & ~(size_t)255))
         return fail(c, PGM_ENOMEM, "request needs " + std::to_string(r.need) + " bytes, more than the pool");
     PGM_HIP(c, hipSetDevice(c->device));
@@ -1286,7 +1377,7 @@ pgm_status pgm_server_submit(void* server, const pgm_params* p, const uint8_t* i
         return fail(c, PGM_EDEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
     }
     S->queued.push_back(r);
-    return server_admit(S);
+    return server_admit(S, (int)S->streams.size());
 }
 
 int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t* host_status, int32_t max_tags)
@@ -1295,7 +1386,7 @@ int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t* host_status,
     if (!S || max_tags < 0 || (max_tags > 0 && !host_tags)) return PGM_EINVAL;
     if (hipSetDevice(S->c->device) != hipSuccess) return fail(S->c, PGM_EDEVICE, "hipSetDevice failed");
     if (pgm_status st = server_reap(S, false)) return st;
-    if (pgm_status st = server_admit(S)) return st;
+    if (pgm_status st = server_admit(S, S->max_running)) return st;
     int32_t n = 0;
     while (n < max_tags && !S->finished.empty()) {
         host_tags[n] = S->finished.front().first;
@@ -1304,6 +1395,15 @@ int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t* host_status,
         S->finished.pop_front();
     }
     return n;
+}
+
+pgm_status pgm_server_stats(void* server, int64_t* host_sequences, int64_t* host_started)
+{
+    pgm_server_s* S = (pgm_server_s*)server;
+    if (!S) return PGM_EINVAL;
+    if (host_sequences) *host_sequences = S->n_batches;
+    if (host_started) *host_started = S->n_started;
+    return PGM_OK;
 }
 
 pgm_status pgm_server_pending(void* server, int32_t* queued, int32_t* running, int32_t* finished)
@@ -1323,7 +1423,7 @@ pgm_status pgm_server_drain(void* server)
     PGM_HIP(S->c, hipSetDevice(S->c->device));
     while (!S->queued.empty() || !S->running.empty()) {
         if (pgm_status st = server_reap(S, true)) return st;
-        if (pgm_status st = server_admit(S)) return st;
+        if (pgm_status st = server_admit(S, S->max_running)) return st;
     }
     return PGM_OK;
 }
@@ -1342,7 +1442,7 @@ void pgm_server_destroy(void* server)
     for (hipStream_t q : S->streams) (void)hipStreamSynchronize(q);
     for (auto& r : S->running) {
         (void)hipEventDestroy(r.done);
-        (void)hipEventDestroy(r.ready);
+        for (auto& rq : r.reqs) (void)hipEventDestroy(rq.ready);
     }
     for (auto& r : S->queued) (void)hipEventDestroy(r.ready);
     for (hipEvent_t ev : S->spare) (void)hipEventDestroy(ev);

@@ -25,6 +25,20 @@ constexpr uint8_t ST_INL = 2;   // outlier record after the level's update says 
 
 constexpr int MAX_STAGES = 1 + 2 * 16 + PGM_MAX_LEVELS;
 
+// Caller buffers of one pair of a batch whose pairs each bring their own images and outputs
+// (the request server's shared launches). The table lives in the batch's workspace; a kernel
+// that reads or writes caller memory takes pair z's pointers from entry z when the table is
+// set, and the uniform pair strides otherwise.
+struct PairTab {
+    const uint8_t* img[2];
+    pgm_match_t* out[2];                 // forward, backward (null when not wanted)
+    pgm_match_t* compact;
+    int32_t* n_in;
+    unsigned long long* n_evals;         // the pair's evaluation count is added here (or null)
+    const void* unused;
+};
+constexpr int TAB_MAX = 16;              // pairs of a table-driven batch
+
 // One correspondence field (one direction at one level) in device memory.
 struct Field {
     uint32_t* disp;   // packed (dx, dy) or UNINIT
@@ -128,6 +142,7 @@ struct OutArgs {
     // compaction of the forward inliers (both null: none)
     pgm_match_t* compact;  // pair z writes compact + z * nx * ny (or null)
     int32_t* n_out;        // pair z writes n_out[z] (or null)
+    const PairTab* tab;    // outputs per pair instead of the strides above (or null)
     int dist8;             // the field's distances are uint64
 };
 
@@ -157,7 +172,9 @@ struct CountArgs {
     int kind[KINDS];                     // PGM_K_* of each table
     unsigned long long* user;            // caller's counter (or null)
     unsigned long long* prof;            // PGM_K_KINDS profiling counters (or null)
+    const PairTab* tab;                  // per-pair counters instead of user (or null)
 };
+
 
 // Threads per work-group of the matching kernels (k_sweep, k_init, k_down, k_up and the
 // k_enter family): one wave. A launch's waves then spread over as many CUs and L1 caches as
@@ -189,6 +206,7 @@ struct PyrArgs {
     long long dst_zs;        // bytes between pairs' destination images (both levels)
     int two;                 // also the level after it, from the same pass
     uint8_t* dst2[2];        // pair 0's images of that level (two)
+    const PairTab* tab;      // source images per pair (or null: src + pair * src_zs)
     int tx, tiles;
 };
 // gradient images of one or more levels (tx, tiles and base filled in by the launchers)
@@ -197,6 +215,7 @@ struct GradLevel {
     long long src_zs;        // bytes between pairs' source images
     int pitch, w, h;
     void* G[2];              // pair 0's padded gradient images
+    const PairTab* tab;      // source images per pair (or null: src + pair * src_zs)
     int space;               // PGM_SPACE_* the pixels are converted into first
     int tx, tiles, base;
 };
@@ -253,5 +272,8 @@ hipError_t launch_output(const OutArgs& a, hipStream_t s);
 // the same offset of its own workspace slice (z * zs bytes further)
 constexpr int COUNT_SLICES = 16;
 hipError_t launch_count(const CountArgs& a, unsigned long long* part, hipStream_t s);
+// writes the n <= TAB_MAX entries of host into the device table dst (through the kernel's
+// arguments: nothing on the host side has to outlive the call)
+hipError_t launch_fill_tab(PairTab* dst, const PairTab* host, int n, hipStream_t s);
 
 }  // namespace pgm

@@ -3,11 +3,14 @@
 //
 // Matching kernels assign one group of LPS lanes (8 for patches up to 8 pixels, 16 up to 16)
 // to each seed of the grid: lane c holds pixel column c of every row of the seed's patch of
-// the first gradient image in registers, reads the same column of candidate patches of the
-// second image (buffer loads from HBM, plain loads from LDS), and the patch distance is the
-// DPP sum over the group. Candidates are priced two at a time, but every seed's decisions
+// the first gradient image in registers (full 8x8 integer patches read from HBM: six 16-byte
+// pieces of the patch instead), reads the same part of candidate patches of the second image
+// (buffer loads from HBM, plain loads from LDS), and the patch distance is the DPP sum over
+// the group. Candidates are priced two at a time, but every seed's decisions
 // replay the paper's candidate order one at a time, so they are exactly the sequential ones;
 // seeds of one colour of the red-black checkerboard are independent and run in parallel.
+#include <string.h>
+
 #include "pgm_internal.h"
 
 namespace pgm {
@@ -186,6 +189,41 @@ struct IntRow {
     using Dist = uint32_t;
 };
 
+// Full 8x8 patches of 6 integer channels from HBM: the 48 16-byte pieces of a patch (8 rows
+// of 96 bytes) are dealt to the group's 8 lanes, piece r + 8 m to lane r (m < 6), so a
+// candidate costs six dwordx4 loads per lane instead of eight dwordx3. The texture addresser
+// spends the same time on a load instruction whatever its width or its number of active
+// lanes (measured: ~16 clocks per wave), so the wider pieces read a patch in 25% less of it.
+// Both patches of a distance are read with the same map, so the sum is unchanged; patches in
+// LDS (BUF false) keep the column map of IntRow.
+struct IntRowQ : IntRow<6, 8, true> {
+    __device__ __forceinline__ void load_pieces(const void* G, const Geo& g, int tlx, int tly, int r)
+    {
+        const uint32_t pitch_b = (uint32_t)g.pw * 12u;
+        const char* base = (const char*)G - ((size_t)PAD * g.pw + PAD) * 12;
+        const uint32_t bytes = pitch_b * (uint32_t)(g.h + 2 * PAD);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000);
+        const uint32_t vo = ((uint32_t)(tly + PAD) * (uint32_t)g.pw + (uint32_t)(tlx + PAD)) * 12u;
+        uint32_t* f = &a[0][0];   // the 24 dwords as one array: piece m in f[4 m .. 4 m + 3]
+#pragma unroll
+        for (int m = 0; m < 6; m++) {
+            const int k = r + 8 * m;
+            const uint32_t off = (uint32_t)(k / 6) * pitch_b + (uint32_t)(k % 6) * 16u;
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, vo + off, 0, 0);
+            f[4 * m + 0] = v[0];
+            f[4 * m + 1] = v[1];
+            f[4 * m + 2] = v[2];
+            f[4 * m + 3] = v[3];
+        }
+    }
+    template <bool BUF>
+    __device__ __forceinline__ void fetch(const void* G, const Geo& g, int tlx, int tly, int P, int r)
+    {
+        if constexpr (BUF) load_pieces(G, g, tlx, tly, r);
+        else IntRow<6, 8, true>::template fetch<false>(G, g, tlx, tly, P, r);
+    }
+};
+
 // Direction-only float features. The components are unit-vector coordinates (zero or of
 // magnitude >= 2^-14), so every difference and the sum over a patch are exact in double and
 // the rounded float result does not depend on the order of summation.
@@ -266,7 +304,9 @@ struct SsdRow : IntRow<C2, PMAX, FIXED> {
 template <int C2, int PMAX, bool FIXED, int KIND>
 using RowT = typename std::conditional<
     KIND == 1, F32Row<C2, PMAX, FIXED>,
-    typename std::conditional<KIND == 2, SsdRow<C2, PMAX, FIXED>, IntRow<C2, PMAX, FIXED>>::type>::type;
+    typename std::conditional<KIND == 2, SsdRow<C2, PMAX, FIXED>,
+                              typename std::conditional<C2 == 6 && PMAX == 8 && FIXED, IntRowQ,
+                                                        IntRow<C2, PMAX, FIXED>>::type>::type>::type;
 
 // Patch distance of Eq. 3 (absolute or squared differences) between the patch held by the group and
 // the patch of the other image at (qx, qy); every lane of the group gets the result. Lanes
@@ -1161,7 +1201,10 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a)
     const int dir = blockIdx.y;
     const size_t zo = (size_t)blockIdx.z * (size_t)a.b.zs;
     const Field f = pair_field(a.f[dir], zo);
-    pgm_match_t* out = a.out[dir] + (size_t)blockIdx.z * n;
+    const PairTab* tz = a.tab ? a.tab + blockIdx.z : nullptr;
+    pgm_match_t* out = tz ? tz->out[dir] : a.out[dir] + (size_t)blockIdx.z * n;
+    pgm_match_t* compact = tz ? tz->compact : (a.compact ? a.compact + (size_t)blockIdx.z * n : nullptr);
+    int32_t* n_out = tz ? tz->n_in : (a.n_out ? a.n_out + blockIdx.z : nullptr);
     bool inl = false;
     pgm_match_t m;
     if (s < n) {
@@ -1181,7 +1224,7 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a)
         out[s] = m;
         inl = (fl & ST_INL) != 0;
     }
-    if (dir != 0 || (!a.compact && !a.n_out)) return;   // uniform over the block
+    if (dir != 0 || (!compact && !n_out)) return;   // uniform over the block
     // inliers before this block: the flags of its 256 x seeds, 16 per load (256-aligned array)
     const uint4* fl4 = (const uint4*)f.flags;
     uint32_t v = 0;
@@ -1200,15 +1243,15 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a)
     uint32_t before = 0;
     for (int k = 0; k < wv; k++) before += wtot[k];
     const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-    if (inl && a.compact) a.compact[(size_t)blockIdx.z * n + prefix + before + rank] = m;
-    if (a.n_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
-        a.n_out[blockIdx.z] = (int32_t)(prefix + wtot[0] + wtot[1] + wtot[2] + wtot[3]);
+    if (inl && compact) compact[prefix + before + rank] = m;
+    if (n_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+        *n_out = (int32_t)(prefix + wtot[0] + wtot[1] + wtot[2] + wtot[3]);
 }
 
 // Add up the count tables: k_count_part sums slice x of pair y's tables per kernel kind into
 // pair y's partial array at [x * KINDS + kind] (each pair's array sits at the same offset of
 // its own workspace slice); k_count_sum adds the parts per kind (profiling) and in total (the
-// caller's counter).
+// caller's counter), or per pair into the pairs' own counters of a table-driven batch.
 __global__ __launch_bounds__(256) void k_count_part(CountArgs a, unsigned long long* part)
 {
     __shared__ unsigned long long ws[4];
@@ -1246,6 +1289,25 @@ __global__ __launch_bounds__(256) void k_count_sum(CountArgs a, const unsigned l
         total += sum;
     }
     if (threadIdx.x == 0 && a.user) atomicAdd(a.user, total);
+    // table-driven batches: each pair's own total into its own counter
+    if (a.tab && (int)threadIdx.x < a.npairs && a.tab[threadIdx.x].n_evals) {
+        const int z = (int)threadIdx.x;
+        const unsigned long long* pz = zoff(part, (size_t)z * (size_t)a.zs);
+        unsigned long long t = 0;
+        for (int i = 0; i < slices * CountArgs::KINDS; i++) t += pz[i];
+        atomicAdd(a.tab[z].n_evals, t);
+    }
+}
+
+struct TabFill {
+    PairTab t[TAB_MAX];
+    PairTab* dst;
+    int n;
+};
+
+__global__ __launch_bounds__(64) void k_fill_tab(TabFill a)
+{
+    if ((int)threadIdx.x < a.n) a.dst[threadIdx.x] = a.t[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1274,7 +1336,7 @@ __device__ __forceinline__ void pyr_tile(const PyrArgs& a, int t, int z, uint32_
     const int w = a.w, h = a.h, w2 = (w + 1) >> 1, h2 = (h + 1) >> 1;
     const int X0 = (t % a.tx) * PY_TW, Y0 = (t / a.tx) * PY_TH;
     const size_t pair = (size_t)(z >> 1);
-    const uint8_t* src = a.src[z & 1] + pair * (size_t)a.src_zs;
+    const uint8_t* src = a.tab ? a.tab[pair].img[z & 1] : a.src[z & 1] + pair * (size_t)a.src_zs;
     uint8_t* dst = a.dst[z & 1] + pair * (size_t)a.dst_zs;
     const int xlo = 2 * X0 - 2, ylo = 2 * Y0 - 2;
     constexpr int SPT = (PY_SU * PY_SV + 255) / 256;   // loads in flight per thread
@@ -1354,7 +1416,7 @@ __device__ __forceinline__ void pyr2_tile(const PyrArgs& a, int t, int z, uint32
     const int w0 = a.w, h0 = a.h, w1 = (w0 + 1) >> 1, h1 = (h0 + 1) >> 1, w2 = (w1 + 1) >> 1, h2 = (h1 + 1) >> 1;
     const int X0 = (t % a.tx) * P2_TW, Y0 = (t / a.tx) * P2_TH;
     const size_t pair = (size_t)(z >> 1);
-    const uint8_t* src = a.src[z & 1] + pair * (size_t)a.src_zs;
+    const uint8_t* src = a.tab ? a.tab[pair].img[z & 1] : a.src[z & 1] + pair * (size_t)a.src_zs;
     uint8_t* dst1 = a.dst[z & 1] + pair * (size_t)a.dst_zs;
     uint8_t* dst2 = a.dst2[z & 1] + pair * (size_t)a.dst_zs;
     const int cx0 = max(0, 2 * X0 - 2), cx1 = min(w1 - 1, 2 * X0 + 2 * P2_TW);
@@ -1541,7 +1603,7 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
     const int pw = w + 2 * PAD, ph = h + 2 * PAD;
     const int X0 = (t % L.tx) * GR_TW, Y0 = (t / L.tx) * GR_TH;
     const size_t pair = (size_t)(z >> 1);
-    const uint8_t* img = L.src[z & 1] + pair * (size_t)L.src_zs;
+    const uint8_t* img = L.tab ? L.tab[pair].img[z & 1] : L.src[z & 1] + pair * (size_t)L.src_zs;
     void* G = zoff(L.G[z & 1], pair * (size_t)dst_zs);
     // the image columns and rows the tile's pixels map to
     const int cx0 = clampi(X0 - PAD, 0, w - 1), cx1 = clampi(min(X0 + GR_TW - 1, pw - 1) - PAD, 0, w - 1);
@@ -1993,6 +2055,18 @@ hipError_t launch_output(const OutArgs& a, hipStream_t s)
 {
     const int n = a.g.nx * a.g.ny;
     hipLaunchKernelGGL(k_output, dim3((n + 255) / 256, a.b.ndir, a.b.npairs), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_tab(PairTab* dst, const PairTab* host, int n, hipStream_t s)
+{
+    if (n < 1 || n > TAB_MAX) return hipErrorInvalidValue;
+    TabFill f;
+    memset(&f, 0, sizeof f);
+    for (int k = 0; k < n; k++) f.t[k] = host[k];
+    f.dst = dst;
+    f.n = n;
+    hipLaunchKernelGGL(k_fill_tab, dim3(1), dim3(64), 0, s, f);
     return hipGetLastError();
 }
 

@@ -131,9 +131,11 @@ def test_null_arguments_rejected_without_device_work():
     assert L.pgm_match_batch(None, C.byref(p), 2, None, None, 10, 10, 30, 300, None, None, None, None, None,
                              None) == pgm.PGM_EINVAL
     assert L.pgm_match_groups(None, 1, None, None, 0, None) == pgm.PGM_EINVAL
-    assert L.pgm_server_create(0, 1 << 20, 0, 0, C.byref(C.c_void_p())) == pgm.PGM_EINVAL
-    assert L.pgm_server_create(0, 1 << 20, 1, -1, C.byref(C.c_void_p())) == pgm.PGM_EINVAL
-    assert L.pgm_server_create(0, 1 << 20, 1, 0, None) == pgm.PGM_EINVAL
+    assert L.pgm_server_create(0, 1 << 20, 0, 0, 0, C.byref(C.c_void_p())) == pgm.PGM_EINVAL
+    assert L.pgm_server_create(0, 1 << 20, 1, -1, 0, C.byref(C.c_void_p())) == pgm.PGM_EINVAL
+    assert L.pgm_server_create(0, 1 << 20, 1, 0, 17, C.byref(C.c_void_p())) == pgm.PGM_EINVAL
+    assert L.pgm_server_create(0, 1 << 20, 1, 0, 0, None) == pgm.PGM_EINVAL
+    assert L.pgm_server_stats(None, None, None) == pgm.PGM_EINVAL
     assert L.pgm_server_submit(None, C.byref(p), None, None, 10, 10, 30, None, None, None, None, None, 0,
                                None) == pgm.PGM_EINVAL
     assert L.pgm_server_poll(None, None, None, 0) == pgm.PGM_EINVAL

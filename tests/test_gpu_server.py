@@ -43,6 +43,8 @@ def check(done, reqs):
     for k, (p, pr, _, _) in enumerate(reqs):
         o = done[k]
         r = oracle.match(p, pr.img1, pr.img2, trace=False)
+        if o["n_evals"] is not None:
+            assert int(o["n_evals"].item()) == r["n_evals"], f"request {k}: evaluations"
         fwd = o["fwd"].cpu().numpy().view(pgm.MATCH_DTYPE)
         bwd = o["bwd"].cpu().numpy().view(pgm.MATCH_DTYPE)
         assert np.array_equal(fwd, r["fwd"]) and np.array_equal(bwd, r["bwd"]), f"request {k}"
@@ -194,6 +196,44 @@ def test_server_full_queue_is_ebusy():
                 done[tags[tag]] = o
             assert time.time() - t0 < 60.0
         torch.cuda.synchronize()
+        check(done, reqs)
+    finally:
+        srv.close()
+
+
+def test_server_same_shape_requests_share_launches():
+    """Requests of three shapes (different images, one parameter set per shape) queue behind a
+    long kernel on the caller's stream; once memory frees, queued requests of the head's
+    shape start together as one batch (fewer launch sequences than requests). Every result,
+    the evaluation count included, equals the oracle's on that pair alone."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("[gpu server] same-shape requests batched", file=sys.stderr, flush=True)
+    shapes = [(320, 240), (256, 192), (330, 250)]
+    reqs = []
+    for k in range(12):
+        w, h = shapes[k % 3]
+        pr = synth.config_pair(5, 300 + k, (w, h))
+        p = base_params(max_disp=max(1, -(-w // 5)), rng_seed=5200 + k % 3)
+        reqs.append((p, pr, torch.from_numpy(pr.img1).cuda(), torch.from_numpy(pr.img2).cuda()))
+    need = max((pgm.pgm_query(p, pr.img1.shape[1], pr.img1.shape[0]).workspace_bytes + 255) // 256 * 256
+               for p, pr, _, _ in reqs)
+    srv = pgm.Server(0, 16 * need, 2)         # at most 4 launch sequences in flight
+    try:
+        tags = {}
+        torch.cuda._sleep(100_000_000)          # the first requests wait; the rest queue up
+        for k, (p, _, a, b) in enumerate(reqs):
+            tags[srv.submit(p, a, b, count_evals=True)] = k
+        assert srv.pending()[0] > 0
+        done, t0 = {}, time.time()
+        while len(done) < len(reqs):
+            for tag, o in srv.poll():
+                done[tags[tag]] = o
+            assert time.time() - t0 < 60.0
+        torch.cuda.synchronize()
+        sequences, started = srv.stats()
+        assert started == len(reqs) and sequences < len(reqs), (sequences, started)
         check(done, reqs)
     finally:
         srv.close()
