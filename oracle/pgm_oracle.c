@@ -9,8 +9,8 @@
  * READING and take one fixed interpretation (listed with the design notes of the project).
  *
  * Parity status per part: pinned by independent tests (brute force, closed forms, library
- * routines, invariants) except the sequential scan schedule, which is parity unpinned beyond
- * invariants because the paper prints no worked example.
+ * routines, invariants). The sequential scan schedule, for which the paper prints no worked
+ * example, is pinned by invariants and by a hand-worked one-pass case.
  */
 #include "pgm_oracle.h"
 
