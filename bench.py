@@ -204,6 +204,10 @@ def run_groups(pgm, torch, dev, args, stream, pre):
         o = m.outputs_batch(p, w, h, len(prs), count_evals=False)
         items.append((p, a, b, o))
     nev = torch.zeros(1, dtype=torch.int64, device=dev)
+    # the launch schedule, picked by the library's tuner on the largest group (untimed; the
+    # schedules give identical results)
+    big = max(items, key=lambda it: it[1].shape[0] * it[1].shape[1] * it[1].shape[2])
+    sched = m.tune(big[0], big[1], big[2], big[3], repeats=2, stream=stream)
     # eager reference, then graph replays (the first one captures)
     m.match_groups_into(items, n_evals=nev, stream=stream)
     torch.cuda.synchronize()
@@ -221,12 +225,16 @@ def run_groups(pgm, torch, dev, args, stream, pre):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     n = args.groups_pairs * args.groups_steps
+    roof = None
+    if not args.no_profile_pass:   # eager launches (profiling records events around them)
+        roof, _ = sweep_roofline(pgm, m.ctx, args.groups_steps, lambda k: m.match_groups_into(items, stream=stream),
+                                 torch)
     m.close()
     return {"value": round(n / (t1 - t0), 3), "unit": "pairs/s", "pairs_per_step": args.groups_pairs,
             "steps": args.groups_steps, "ms_per_step": round(1000.0 * (t1 - t0) / args.groups_steps, 4),
             "sizes": {f"{w}x{h}": len(v) for (w, h), v in sorted(by.items())},
             "dist_evals_per_s": round(evals_per_step * args.groups_steps / (t1 - t0), 1),
-            "graph_equals_eager": same,
+            "graph_equals_eager": same, "schedule_flags": sched, "roofline": roof,
             "workload": "64 pairs, sizes uniform over 320x240, 640x480, 1024x436, 1242x375 (rectangle-layer "
                         "generator, |d| <= w/5), config-2 matching with max_disp = ceil(w/5); grouped by size, "
                         "groups concurrent on 4 streams, one HIP graph launch per step"}

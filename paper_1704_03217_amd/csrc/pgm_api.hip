@@ -1367,6 +1367,7 @@ pgm_status pgm_server_submit(void* server, const pgm_params* p, const uint8_t* i
         return fail(c, PGM_ENOMEM, "request needs " + std::to_string(r.need) + " bytes, more than the pool");
     PGM_HIP(c, hipSetDevice(c->device));
     if (pgm_status st = server_reap(S, false)) return st;
+    if (pgm_status st = server_admit(S, (int)S->streams.size())) return st;   // may make room
     if ((int)S->queued.size() >= S->max_queued)
         return fail(c, PGM_EBUSY, "the request queue is full (" + std::to_string(S->max_queued) + " requests)");
     // the request's launches are ordered after the caller's work on `stream` so far
