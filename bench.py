@@ -543,9 +543,11 @@ def main():
             "plain, one 256x192 pair per step: 4 textured rectangles with integer motion |d| <= 20; L=3, stride 3, "
             "8x8 patch, 4 iterations, int16 gradients with int32 SAD, fwd+bwd tau=1")
         # float direction features: each patch element is a subtraction and an addition in
-        # double precision (exact, see the kernels), 2 x 384 fp64 operations per distance
+        # double precision (exact, see the kernels), 2 x 384 fp64 operations per distance. The
+        # fp64 vector peak of 78.6 TFLOP/s counts a fused multiply-add as two; additions retire
+        # one per lane per clock, 39.3 T per second, which is the peak used here.
         configs["config3_1242x375"] = run_config_pass(pgm, torch, dev, 3, pgm.PRESET_CONFIG3, args.config_steps,
-                                                      2 * 8 * 8 * 6, 78.6, "TFLOP/s",
+                                                      2 * 8 * 8 * 6, VALU_PEAK_TOPS, "TOP/s",
                                                       "fp64 subtract + add per element of the unit-vector features, "
                                                       "768 per 8x8x6 patch distance", "alu")
         configs["config3_1242x375"]["workload"] = (
