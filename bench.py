@@ -177,11 +177,10 @@ def generate(jobs):
         return list(ex.map(_gen, jobs))
 
 
-def sized_params(pgm, w):
-    """Configuration-2 matching parameters with |d| <= ceil(w / 5) (uneven and served pairs)."""
-    p = pgm.pgm_default_params(pgm.PRESET_CONFIG2)
-    p.max_disp = -(-w // 5)
-    return p
+def sized_params(pgm, w, preset=None):
+    """Matching parameters of the uneven batch (preset 4) or of served pairs (preset 5):
+    configuration 2's matching with |d| <= ceil(w / 5), through max_disp = -5."""
+    return pgm.pgm_default_params(pgm.PRESET_CONFIG4 if preset is None else preset)
 
 
 def run_groups(pgm, torch, dev, args, stream, pre):
@@ -236,7 +235,7 @@ def run_groups(pgm, torch, dev, args, stream, pre):
             "dist_evals_per_s": round(evals_per_step * args.groups_steps / (t1 - t0), 1),
             "graph_equals_eager": same, "schedule_flags": sched, "roofline": roof,
             "workload": "64 pairs, sizes uniform over 320x240, 640x480, 1024x436, 1242x375 (rectangle-layer "
-                        "generator, |d| <= w/5), config-2 matching with max_disp = ceil(w/5); grouped by size, "
+                        "generator, |d| <= w/5), preset 4 (config-2 matching with |d| <= ceil(w/5)); grouped by size, "
                         "groups concurrent on 4 streams, one HIP graph launch per step"}
 
 
@@ -276,7 +275,7 @@ def run_served(pgm, torch, dev, args, pre):
     server's capacity; latency from arrival to observed completion."""
     sizes, pool = pre["served"]
     imgs = [(torch.from_numpy(q.img1).to(dev), torch.from_numpy(q.img2).to(dev)) for q in pool]
-    prm = [sized_params(pgm, w) for (w, h) in sizes]
+    prm = [sized_params(pgm, w, pgm.PRESET_CONFIG5) for (w, h) in sizes]
     rng = np.random.default_rng(5001)
     order = rng.integers(0, len(pool), args.served)
     budget = args.served_pool_mib << 20
@@ -326,8 +325,8 @@ def run_served(pgm, torch, dev, args, pre):
     out = {"unit": "ms", "capacity_pairs_per_s": capacity, "requests": args.served, "pool_bytes": budget,
            "distinct_pairs": len(pool), "batched_server": res["batched"], "plain_per_pair": res["plain"],
            "workload": "Poisson arrivals; sizes log-uniform in area over [320x240, 2048x1024], aspect "
-                       "U[1.3, 3.3] (rectangle-layer generator, |d| <= w/5); config-2 matching with "
-                       "max_disp = ceil(w/5); requests drawn from the distinct generated pairs; batched_server: "
+                       "U[1.3, 3.3] (rectangle-layer generator, |d| <= w/5); preset 5 (config-2 matching with "
+                       "|d| <= ceil(w/5)); requests drawn from the distinct generated pairs; batched_server: "
                        "4 streams, requests of one shape share launch sequences (at most 16, at most 8 "
                        "sequences in flight); plain_per_pair: pgm_match per request in arrival order on one "
                        "stream; pool = the stated HBM budget"}
@@ -375,10 +374,10 @@ def run_config_pass(pgm, torch, dev, config, preset, steps, ops_per_eval, peak, 
 
 def _oracle_worker(args):
     """One process of the all-core oracle run: runs until `seconds` of wall time are spent."""
-    params_d, pair_ids, seconds, schedule = args
+    params_d, pair_ids, seconds, schedule, config = args
     import oracle
     import synth
-    pairs = [synth.config_pair(2, i) for i in pair_ids]
+    pairs = [synth.config_pair(config, i) for i in pair_ids]
     t0 = time.perf_counter()
     runs = 0
     while time.perf_counter() - t0 < seconds:
@@ -388,14 +387,14 @@ def _oracle_worker(args):
     return runs, time.perf_counter() - t0
 
 
-def cpu_all_cores(params_d, seconds):
+def cpu_all_cores(params_d, seconds, config=2):
     """Throughput of independent oracle processes, one per host core (different pairs)."""
     import multiprocessing as mp
     import oracle
     n = os.cpu_count() or 1
     ctx = mp.get_context("spawn")
     with ctx.Pool(n) as pool:
-        res = pool.map(_oracle_worker, [(params_d, [k % 2], seconds, oracle.SYNC) for k in range(n)])
+        res = pool.map(_oracle_worker, [(params_d, [k % 2], seconds, oracle.SYNC, config) for k in range(n)])
     runs = sum(r for r, _ in res)
     wall = max(t for _, t in res)
     return {"value": round(runs / wall, 4), "unit": "pairs/s", "cores": n, "processes": n, "runs": runs,

@@ -62,7 +62,18 @@ def test_missing_calibration_copy_is_an_error(tmp_path, traffic_file):
 
 
 def test_uneven_batch_parameters_bound_the_displacement_by_a_fifth_of_the_width():
+    import oracle
     import paper_1704_03217_amd as pgm
-    for w, d in ((320, 64), (640, 128), (1024, 205), (1242, 249)):
-        p = bench.sized_params(pgm, w)
-        assert p.max_disp == d and p.levels == 5 and p.seed_stride == 3
+    for preset in (None, pgm.PRESET_CONFIG5):
+        for w, h, d in ((320, 240, 64), (640, 480, 128), (1024, 436, 205), (1242, 375, 249)):
+            p = bench.sized_params(pgm, w, preset)
+            assert p.max_disp == -5 and p.levels == 5 and p.seed_stride == 3
+            explicit = dict(pgm.params_dict(p), max_disp=d)
+            assert oracle.top_radius(pgm.params_dict(p), w, h) == oracle.top_radius(explicit, w, h)
+
+
+def test_all_core_oracle_baseline_reports_its_sample():
+    import paper_1704_03217_amd as pgm
+    r = bench.cpu_all_cores(pgm.params_dict(pgm.pgm_default_params(pgm.PRESET_CONFIG1)), 0.5, config=1)
+    assert r["cores"] == r["processes"] >= 1 and r["runs"] >= r["processes"] and r["value"] > 0
+    assert "independent" in r["sample"]

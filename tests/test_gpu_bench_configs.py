@@ -3,8 +3,8 @@
 - The uniform batch: 32 resident 1024x436 pairs (two distinct pairs, alternating) in one
   pgm_match_batch call with the configuration-2 parameters; every pair must equal the oracle's
   result for its distinct pair.
-- The uneven batch: pairs of the four batch sizes with configuration-2 matching and
-  max_disp = ceil(w / 5), grouped by size into one pgm_match_groups call, run eagerly and then
+- The uneven batch: pairs of the four batch sizes with preset 4 (configuration-2 matching,
+  |d| <= ceil(w / 5)), grouped by size into one pgm_match_groups call, run eagerly and then
   replayed from its HIP graph; every pair of every run must equal the oracle.
 """
 import sys
@@ -68,8 +68,7 @@ def test_uneven_groups_bench_config_with_graph_replays(torch):
     groups, pairs, params = [], [], []
     need = 0
     for (w, h) in BATCH_SIZES:
-        p = pgm.pgm_default_params(pgm.PRESET_CONFIG2)
-        p.max_disp = -(-w // 5)
+        p = pgm.pgm_default_params(pgm.PRESET_CONFIG4)    # the benchmark's uneven-batch parameters
         q = pgm.pgm_query(p, w, h)
         need += (q.workspace_shared_bytes + per_size * q.workspace_pair_bytes + 255) // 256 * 256
         params.append(p)
