@@ -379,6 +379,24 @@ __device__ __forceinline__ void patch_cost3(const Row& A, const void* Gb, const 
     e[2] = Row::template finish<LPS>(p2);
 }
 
+// The patch distances of qa and, where `both`, of qb (qb's result is qa's otherwise), for the
+// seeds of the wave that call it: both patches' reads in flight together when some of these
+// seeds need two, one patch otherwise. A load instruction holds the texture addresser as long
+// whatever its number of active lanes, so a second patch that no seed of the wave needs is
+// not fetched.
+template <class Row, int LPS, bool BUF>
+__device__ __forceinline__ void patch_cost_some(const Row& A, const void* Gb, const Geo& g, int P, int r, int px,
+                                                int py, uint32_t qa, uint32_t qb, bool both,
+                                                typename Row::Dist& ea, typename Row::Dist& eb)
+{
+    if (__builtin_amdgcn_ballot_w64(both) != 0ull) {   // uniform over the active lanes
+        patch_cost2<Row, LPS, BUF>(A, Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb), ea, eb);
+    } else {
+        ea = patch_cost<Row, LPS, BUF>(A, Gb, g, P, r, px + d_x(qa), py + d_y(qa));
+        eb = ea;
+    }
+}
+
 template <bool BUF, class Row>
 __device__ __forceinline__ void load_own(Row& A, const void* Ga, const Geo& g, int P, int r, int px, int py)
 {
@@ -497,8 +515,7 @@ __device__ __forceinline__ uint32_t decide_and_search(const Row& A, const DirArg
             if (n0 || n1) {
                 const uint32_t qa = n0 ? r0 : r1, qb = n1 ? r1 : r0;
                 Dist ea, eb;
-                patch_cost2<Row, LPS, BUF>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb),
-                                      ea, eb);
+                patch_cost_some<Row, LPS, BUF>(A, D.Gb, g, P, r, px, py, qa, qb, n0 && n1, ea, eb);
                 if (n0) f0 = ea;
                 if (n1) f1 = eb;
             }
@@ -574,7 +591,7 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
     if (need0 || need1) {
         const uint32_t qa = need0 ? c[0] : c[1], qb = need1 ? c[1] : c[0];
         Dist ea, eb;
-        patch_cost2<Row, LPS, BUF>(A, D.Gb, g, P, r, px + d_x(qa), py + d_y(qa), px + d_x(qb), py + d_y(qb), ea, eb);
+        patch_cost_some<Row, LPS, BUF>(A, D.Gb, g, P, r, px, py, qa, qb, need0 && need1, ea, eb);
         if (need0) e[0] = ea;
         if (need1) e[1] = eb;
     }
