@@ -154,6 +154,9 @@ def sweep_roofline(pgm, ctx, steps, run, torch, traffic=None, ops_per_eval=None,
         achieved = ops_per_launch / (sw["avg_launch_us"] * 1e-6) / 1e12
         roof = {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak, 2),
                 "unit": unit, "frac": round(achieved / peak, 4), "traffic": traffic,
+                # the HBM side of the same launches, from the counted bytes (when current)
+                "hbm_GBps": (round(traffic / (sw["avg_launch_us"] * 1e-6) / 1e9, 1) if traffic else None),
+                "hbm_frac": (round(traffic / (sw["avg_launch_us"] * 1e-6) / 8.0e12, 4) if traffic else None),
                 "kernel": "k_sweep (propagation + random search half-sweep)",
                 "op": op,
                 "avg_launch_us": round(sw["avg_launch_us"], 3),
