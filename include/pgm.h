@@ -222,8 +222,8 @@ PGM_API pgm_status pgm_match_groups(void* ctx, int32_t n_groups, const pgm_group
  * (1..16); at most max_queued requests wait for memory (0 = 4096), and up to max_batch
  * requests (1..16, 0 = 16) may share one launch sequence.
  * pgm_server_submit queues a request (the pgm_match arguments plus a caller tag) and starts
- * queued requests, oldest first, while fewer than n_streams launch sequences are in flight
- * (pgm_server_poll and pgm_server_drain: fewer than 2 * n_streams) and the head's workspace
+ * queued requests, oldest first, when no launch sequence is in flight (pgm_server_poll and
+ * pgm_server_drain: while fewer than 2 * n_streams are) and the head's workspace
  * (pgm_query's workspace_bytes rounded up to 256) fits in the pool; under load requests
  * gather in the queue meanwhile. The head starts together with the later queued
  * requests of the same width, height, pitch and parameters that ask for the same outputs

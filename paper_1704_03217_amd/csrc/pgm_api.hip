@@ -1194,9 +1194,11 @@ static bool same_shape(const pgm_server_s::Req& a, const pgm_server_s::Req& b)
 // Start queued requests, oldest first, while fewer than max_running launch sequences are in
 // flight and the head fits in the pool: the head together with up to max_batch - 1 later
 // requests of its shape, as many as the free memory holds (at least the head). Submission
-// starts requests only while fewer sequences than streams are in flight, polling up to two per
-// stream: under load (the GPU busy, or the host busy issuing launches) requests gather in the
-// queue, and then start in batches whose launch costs they share. A started sequence waits for the submission events of its requests (the
+// starts a request only when no sequence is in flight, polling up to two per stream: a burst
+// of submissions or arrivals while the GPU is busy gather in the queue, and then start in
+// batches whose launch costs they share (issuing a sequence's ~40 launches costs the host
+// about as much as the GPU spends on a pair, so eager one-by-one starts at submission would
+// keep the queue from ever forming). A started sequence waits for the submission events of its requests (the
 // callers' streams at submit time). A sequence whose launches fail part-way is still tracked
 // until its stream passes its completion event, so that its memory is not handed out while
 // launches may still use it; its requests are then reported with the error status.
@@ -1367,7 +1369,7 @@ pgm_status pgm_server_submit(void* server, const pgm_params* p, const uint8_t* i
         return fail(c, PGM_ENOMEM, "request needs " + std::to_string(r.need) + " bytes, more than the pool");
     PGM_HIP(c, hipSetDevice(c->device));
     if (pgm_status st = server_reap(S, false)) return st;
-    if (pgm_status st = server_admit(S, (int)S->streams.size())) return st;   // may make room
+    if (pgm_status st = server_admit(S, 1)) return st;   // may make room
     if ((int)S->queued.size() >= S->max_queued)
         return fail(c, PGM_EBUSY, "the request queue is full (" + std::to_string(S->max_queued) + " requests)");
     // the request's launches are ordered after the caller's work on `stream` so far
@@ -1378,7 +1380,7 @@ pgm_status pgm_server_submit(void* server, const pgm_params* p, const uint8_t* i
         return fail(c, PGM_EDEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
     }
     S->queued.push_back(r);
-    return server_admit(S, (int)S->streams.size());
+    return server_admit(S, 1);
 }
 
 int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t* host_status, int32_t max_tags)
