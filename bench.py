@@ -394,7 +394,11 @@ def cpu_all_cores(params_d, seconds, config=2):
     """Throughput of independent oracle processes, one per host core (different pairs)."""
     import multiprocessing as mp
     import oracle
-    n = os.cpu_count() or 1
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    n = max(1, min(n, 16))   # the host share of one GPU
     ctx = mp.get_context("spawn")
     with ctx.Pool(n) as pool:
         res = pool.map(_oracle_worker, [(params_d, [k % 2], seconds, oracle.SYNC, config) for k in range(n)])
