@@ -132,6 +132,7 @@ CASES = {
     "ragged_17x9": (lambda: synth.rect_pair(2, 9, 17, n_rect=1, dmax=3), base_params(levels=3, iters=[3, 3, 3], max_disp=4)),
     "ragged_101x67": (lambda: synth.rect_pair(3, 67, 101, dmax=10), base_params(levels=4, iters=[2, 3, 4, 5], max_disp=12)),
     "wide_16384x12": (lambda: synth.rect_pair(9, 12, 16384, n_rect=2, dmax=20), base_params(levels=2, iters=[2, 2], max_disp=20, seed_stride=5)),
+    "tall_12x16384": (lambda: synth.rect_pair(10, 16384, 12, n_rect=2, dmax=20), base_params(levels=2, iters=[2, 2], max_disp=20, seed_stride=5)),
     "translation": (lambda: synth.translate_pair(3, 72, 96, 10, -6), base_params(levels=2, iters=[8, 8], max_disp=16)),
     "identical": (lambda: (lambda p: synth.Pair(p.img1, p.img1, p.flow, p.valid))(synth.config_pair(1)), base_params(rng_seed=3)),
     # small-region removal (Sec. III-E): the paper's 9 px / 12 px on a dense field, and a
