@@ -19,6 +19,10 @@
  *    use one context per stream / host thread.
  *  - All functions return a pgm_status; pgm_last_error() describes the last failure of a
  *    context in text.
+ *  - Logging to stderr by the environment variable PGM_LOG (read once): 1 failures, 2 also
+ *    contexts, servers and each server request (shape, requests sharing its launch sequence,
+ *    latency from submission to completion as seen by polling, pool bytes in use), 3 also
+ *    each matching call (pairs, launches); unset or 0: nothing.
  */
 #ifndef PGM_H
 #define PGM_H
@@ -241,7 +245,7 @@ PGM_API pgm_status pgm_match_groups(void* ctx, int32_t n_groups, const pgm_group
  * keeps its memory until its stream has passed them. The caller keeps a request's images and
  * outputs alive until its tag is reported. pgm_server_drain waits until nothing is queued or
  * running (the finished tags stay for pgm_server_poll). pgm_server_stats reports the launch
- * sequences and the requests started so far. Argument errors are reported by
+ * sequences and the requests started so far and the pool bytes in use. Argument errors are reported by
  * pgm_server_submit synchronously, and PGM_ENOMEM when the request alone exceeds the pool.
  * One host thread per server. */
 PGM_API pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_streams, int32_t max_queued,
@@ -252,7 +256,8 @@ PGM_API pgm_status pgm_server_submit(void* server, const pgm_params* p, const ui
                                      pgm_match_t* out_compact, uint64_t* out_n_evals, uint64_t tag,
                                      void* stream);
 PGM_API int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t* host_status, int32_t max_tags);
-PGM_API pgm_status pgm_server_stats(void* server, int64_t* host_sequences, int64_t* host_started);
+PGM_API pgm_status pgm_server_stats(void* server, int64_t* host_sequences, int64_t* host_started,
+                                    uint64_t* host_bytes_in_use);
 PGM_API pgm_status pgm_server_pending(void* server, int32_t* host_queued, int32_t* host_running,
                                       int32_t* host_finished);
 PGM_API pgm_status pgm_server_drain(void* server);

@@ -130,7 +130,7 @@ def lib():
         L.pgm_server_submit.restype = C.c_int32
         L.pgm_server_poll.argtypes = [V, C.POINTER(C.c_uint64), C.POINTER(C.c_int32), C.c_int32]
         L.pgm_server_poll.restype = C.c_int32
-        L.pgm_server_stats.argtypes = [V, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.pgm_server_stats.argtypes = [V, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]
         L.pgm_server_stats.restype = C.c_int32
         L.pgm_server_pending.argtypes = [V, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.pgm_server_pending.restype = C.c_int32
@@ -283,10 +283,10 @@ def pgm_server_poll(server, max_tags: int = 256) -> list:
 
 
 def pgm_server_stats(server):
-    """(launch sequences, requests) started so far."""
-    a, b = C.c_int64(), C.c_int64()
-    _check_server(lib().pgm_server_stats(server, C.byref(a), C.byref(b)), server)
-    return a.value, b.value
+    """(launch sequences started, requests started, pool bytes in use)."""
+    a, b, u = C.c_int64(), C.c_int64(), C.c_uint64()
+    _check_server(lib().pgm_server_stats(server, C.byref(a), C.byref(b), C.byref(u)), server)
+    return a.value, b.value, u.value
 
 
 def pgm_server_pending(server):

@@ -1,9 +1,12 @@
 // C ABI of libpgm (declared in include/pgm.h): parameter validation, workspace layout, the
 // level schedule of Sec. III-D and the kernel launches of one pair.
+#include <stdarg.h>
 #include <stddef.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <chrono>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -276,10 +279,35 @@ struct pgm_ctx_s {
 
 static std::string g_create_error;
 
+// Logging to stderr, by the level in the environment variable PGM_LOG (read once): 0 or unset
+// nothing, 1 failures, 2 also contexts, servers and every server request (its shape, the
+// requests sharing its launch sequence, its latency from submission to completion as seen by
+// polling, and the pool bytes in use), 3 also every matching call (pairs, launches).
+static int log_level()
+{
+    static const int level = [] {
+        const char* e = getenv("PGM_LOG");
+        return e ? atoi(e) : 0;
+    }();
+    return level;
+}
+
+__attribute__((format(printf, 2, 3))) static void pgm_log(int level, const char* fmt, ...)
+{
+    if (log_level() < level) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "[pgm] %s\n", buf);
+}
+
 static pgm_status fail(pgm_ctx_s* c, pgm_status st, const std::string& msg)
 {
     if (c) c->err = msg;
     else g_create_error = msg;
+    pgm_log(1, "error %d: %s", (int)st, msg.c_str());
     return st;
 }
 
@@ -388,6 +416,7 @@ pgm_status pgm_create(int32_t device, uint64_t workspace_bytes, void** out_ctx)
         return fail(nullptr, e == hipErrorOutOfMemory ? PGM_ENOMEM : PGM_EDEVICE, msg);
     }
     *out_ctx = c;
+    pgm_log(2, "context on device %d: workspace %zu bytes", device, c->ws_bytes);
     return PGM_OK;
 }
 
@@ -395,6 +424,7 @@ void pgm_destroy(void* ctx)
 {
     pgm_ctx_s* c = (pgm_ctx_s*)ctx;
     if (!c) return;
+    pgm_log(2, "context on device %d destroyed", c->device);
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     if (c->ws) (void)hipFree(c->ws);
@@ -452,6 +482,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         return fail(c, PGM_ENOMEM, "workspace of " + std::to_string(wsn) + " bytes is smaller than the " +
                                        std::to_string(need) + " bytes this batch needs");
     PGM_HIP(c, hipSetDevice(c->device));
+    const long long nlaunch0 = c->nlaunch;
     uint8_t* ws = wsb;                            // shared slice
     uint8_t* pw0 = wsb + Y.shared_bytes;          // pair 0's slice
     const long long zs = (long long)Y.pair_bytes;
@@ -834,6 +865,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         PGM_HIP(c, launch_count(ca, (unsigned long long*)(pw0 + Y.cntpart), s));
     }
 
+    pgm_log(3, "match: %d pair(s) of %dx%d, %lld launches", (int)npairs, (int)w, (int)h, c->nlaunch - nlaunch0);
     c->have_last = true;
     c->last_ws = wsb;
     c->last = Y;
@@ -1114,6 +1146,7 @@ struct pgm_server_s {
     int max_batch = 1;                            // requests that may share one launch sequence
     int max_running = 2;                          // launch sequences in flight (2 per stream)
     long long n_batches = 0, n_started = 0;       // launch sequences and requests started
+    size_t in_use = 0;                            // pool bytes held by launch sequences
     struct Req {
         pgm_params p;
         const uint8_t* img1;
@@ -1127,6 +1160,7 @@ struct pgm_server_s {
         uint64_t tag;
         size_t need;        // workspace of the request alone
         hipEvent_t ready;   // recorded on the caller's stream at submission
+        std::chrono::steady_clock::time_point t_submit;
     };
     struct Run {            // one launch sequence: one request, or several of the same shape
         std::vector<Req> reqs;
@@ -1159,12 +1193,14 @@ struct pgm_server_s {
             const size_t rest = it->second - need;
             free_.erase(it);
             if (rest) free_[off + need] = rest;
+            in_use += need;
             return true;
         }
         return false;
     }
     void release(size_t off, size_t bytes)
     {
+        in_use -= bytes;
         auto it = free_.emplace(off, bytes).first;
         auto nx = std::next(it);
         if (nx != free_.end() && it->first + it->second == nx->first) {
@@ -1266,6 +1302,8 @@ static pgm_status server_admit(pgm_server_s* S, int max_running)
         }
         S->n_batches++;
         S->n_started += (long long)n;
+        pgm_log(2, "server: started %zu request(s) of %dx%d on stream %d (tag %llu first); pool in use %zu of %zu bytes",
+                n, h0.w, h0.h, q, (unsigned long long)h0.tag, S->in_use, c->ws_bytes & ~(size_t)255);
         e = hipEventRecord(r.done, st);
         if (e != hipSuccess) {
             // without a completion event, wait for the stream before the memory is reused
@@ -1298,9 +1336,13 @@ static pgm_status server_reap(pgm_server_s* S, bool wait)
         if (e != hipSuccess) return fail(c, PGM_EDEVICE, std::string("request: ") + hipGetErrorString(e));
         S->release(r.off, r.need);
         S->spare.push_back(r.done);
+        const auto now = std::chrono::steady_clock::now();
         for (const auto& rq : r.reqs) {
             S->spare.push_back(rq.ready);
             S->finished.emplace_back(rq.tag, r.status);
+            pgm_log(2, "server: request tag %llu (%dx%d) finished, status %d, %.3f ms after submission",
+                    (unsigned long long)rq.tag, rq.w, rq.h, (int)r.status,
+                    std::chrono::duration<double, std::milli>(now - rq.t_submit).count());
         }
         S->load[r.stream]--;
         S->running.erase(S->running.begin() + (long)i);
@@ -1325,6 +1367,8 @@ pgm_status pgm_server_create(int32_t device, uint64_t pool_bytes, int32_t n_stre
     S->max_queued = max_queued ? max_queued : 4096;
     S->max_batch = max_batch ? max_batch : TAB_MAX;
     S->max_running = 2 * n_streams;
+    pgm_log(2, "server on device %d: pool %zu bytes, %d streams, queue %d, batches of up to %d", device,
+            S->c->ws_bytes, n_streams, S->max_queued, S->max_batch);
     S->free_[0] = S->c->ws_bytes & ~(size_t)255;
     for (int i = 0; i < n_streams; i++) {
         hipStream_t q;
@@ -1365,6 +1409,7 @@ pgm_status pgm_server_submit(void* server, const pgm_params* p, const uint8_t* i
     r.tag = tag;
     r.need = (Y.shared_bytes + Y.pair_bytes + 255) & ~(size_t)255;
     r.ready = nullptr;
+    r.t_submit = std::chrono::steady_clock::now();
     if (r.need > (c->ws_bytes & ~(size_t)255))
         return fail(c, PGM_ENOMEM, "request needs " + std::to_string(r.need) + " bytes, more than the pool");
     PGM_HIP(c, hipSetDevice(c->device));
@@ -1400,12 +1445,14 @@ int32_t pgm_server_poll(void* server, uint64_t* host_tags, int32_t* host_status,
     return n;
 }
 
-pgm_status pgm_server_stats(void* server, int64_t* host_sequences, int64_t* host_started)
+pgm_status pgm_server_stats(void* server, int64_t* host_sequences, int64_t* host_started,
+                            uint64_t* host_bytes_in_use)
 {
     pgm_server_s* S = (pgm_server_s*)server;
     if (!S) return PGM_EINVAL;
     if (host_sequences) *host_sequences = S->n_batches;
     if (host_started) *host_started = S->n_started;
+    if (host_bytes_in_use) *host_bytes_in_use = S->in_use;
     return PGM_OK;
 }
 

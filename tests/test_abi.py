@@ -135,7 +135,7 @@ def test_null_arguments_rejected_without_device_work():
     assert L.pgm_server_create(0, 1 << 20, 1, -1, 0, C.byref(C.c_void_p())) == pgm.PGM_EINVAL
     assert L.pgm_server_create(0, 1 << 20, 1, 0, 17, C.byref(C.c_void_p())) == pgm.PGM_EINVAL
     assert L.pgm_server_create(0, 1 << 20, 1, 0, 0, None) == pgm.PGM_EINVAL
-    assert L.pgm_server_stats(None, None, None) == pgm.PGM_EINVAL
+    assert L.pgm_server_stats(None, None, None, None) == pgm.PGM_EINVAL
     assert L.pgm_server_submit(None, C.byref(p), None, None, 10, 10, 30, None, None, None, None, None, 0,
                                None) == pgm.PGM_EINVAL
     assert L.pgm_server_poll(None, None, None, 0) == pgm.PGM_EINVAL
@@ -231,3 +231,19 @@ def test_status_codes_match_header():
     for name in ("PGM_OK", "PGM_EINVAL", "PGM_ENOMEM", "PGM_EDEVICE", "PGM_EBUSY", "PGM_EUNSUPPORTED"):
         v = int(re.search(rf"\b{name}\s*=\s*(-?\d+)", src).group(1))
         assert getattr(pgm, name) == v, name
+
+
+def test_pgm_log_reports_failures_on_stderr():
+    """PGM_LOG=1 prints failures: here pgm_create refused on a machine without a usable device
+    (or for a device index out of range)."""
+    import sys
+    code = ("import sys; sys.path.insert(0, %r); import paper_1704_03217_amd as pgm\n"
+            "try:\n    pgm.pgm_create(999, 1 << 20)\nexcept pgm.PGMError as e:\n    print('status', e.status)\n"
+            % ROOT)
+    env = dict(os.environ, PGM_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+    assert "status" in r.stdout
+    assert "[pgm] error" in r.stderr
+    env["PGM_LOG"] = "0"
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+    assert "[pgm]" not in r.stderr

@@ -232,8 +232,44 @@ def test_server_same_shape_requests_share_launches():
                 done[tags[tag]] = o
             assert time.time() - t0 < 60.0
         torch.cuda.synchronize()
-        sequences, started = srv.stats()
+        sequences, started, in_use = srv.stats()
         assert started == len(reqs) and sequences < len(reqs), (sequences, started)
+        assert in_use == 0          # every sequence finished and gave its memory back
         check(done, reqs)
     finally:
         srv.close()
+
+
+def test_server_logs_requests_with_pgm_log():
+    """PGM_LOG=2: the server logs its creation, each started launch sequence with the pool bytes
+    in use, and each finished request with its latency (in a child process, stderr captured)."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import os
+    import subprocess
+    from conftest import ROOT
+    code = f"""
+import sys, time
+sys.path.insert(0, {ROOT!r}); sys.path.insert(0, {os.path.join(ROOT, 'tests')!r})
+import torch
+import paper_1704_03217_amd as pgm
+import synth
+from conftest import base_params
+srv = pgm.Server(0, 64 << 20, 1)
+pr = synth.config_pair(5, 1, (160, 120))
+a, b = torch.from_numpy(pr.img1).cuda(), torch.from_numpy(pr.img2).cuda()
+for k in range(2):
+    srv.submit(base_params(max_disp=32), a, b)
+done, t0 = 0, time.time()
+while done < 2 and time.time() - t0 < 60:
+    done += len(srv.poll())
+print("done", done, srv.stats())
+srv.close()
+"""
+    env = dict(os.environ, PGM_LOG="2")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=180)
+    assert "done 2" in r.stdout, r.stdout + r.stderr[-2000:]
+    assert "[pgm] server on device 0" in r.stderr
+    assert r.stderr.count("server: started") >= 1 and "pool in use" in r.stderr
+    assert r.stderr.count("finished, status 0") == 2
