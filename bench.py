@@ -621,6 +621,13 @@ def main():
         "served": served,
         "paper_preset": paper,
         "cpu_baseline": cpu,
+        # the paper's own matching times (Table III), context only: other hardware, the dense
+        # per-pixel method with 15/11 patches, the MPI Sintel and KITTI 2012 training sets
+        "paper_runtimes_context": {
+            "hardware": "Intel Pentium G3240 @3.1 GHz, 4 GB, one thread (Sec. IV)",
+            "seconds_per_pair": {"PGM-C Sintel": 3.49, "PGM-C KITTI2012": 4.55, "PGM-G Sintel": 1.82,
+                                 "PGM-G KITTI2012": 2.05, "PGM-CD Sintel": 1.56, "PGM-CD KITTI2012": 1.60,
+                                 "PGM-GD Sintel": 1.08, "PGM-GD KITTI2012": 1.16}},
     }
     m.close()
     print(json.dumps(out), flush=True)
