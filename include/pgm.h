@@ -178,9 +178,10 @@ PGM_API pgm_status pgm_match_batch(void* ctx, const pgm_params* p, int32_t n_pai
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): pgm_match without a context. The workspace is a
- * fixed device array of PGM_STATIC_SCRATCH_BYTES inside the library, one per GPU, set up on
- * the first call on each device (with that device current) and held until the process ends;
- * the call itself allocates nothing. It runs on the current HIP device, with the arguments,
+ * fixed device array of PGM_STATIC_SCRATCH_BYTES inside the library, one per GPU (it occupies
+ * device memory on every GPU the library's code is loaded on, whether or not this entry point
+ * is called), whose address is looked up on the first call on each device (with that device
+ * current) and kept until the process ends; the call itself allocates nothing. It runs on the current HIP device, with the arguments,
  * outputs and stream of pgm_match. PGM_ENOMEM, before any device work, when the pair's
  * workspace (pgm_query's workspace_bytes) exceeds the array: 64 MiB holds a 1024x436 or a
  * 1242x375 pair with the configuration presets, not the dense paper preset at that size.
