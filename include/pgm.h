@@ -10,7 +10,8 @@
  * Conventions for every entry point
  *  - Image and output pointers passed to pgm_match are DEVICE pointers owned by the caller
  *    (e.g. torch tensors). Pointers named host_* are host pointers owned by the caller.
- *  - Images are interleaved RGB uint8 (HWC), `pitch_bytes` apart between rows (>= 3*w).
+ *  - Images are interleaved RGB uint8 (HWC), `pitch_bytes` apart between rows (>= 3*w); one
+ *    image spans pitch_bytes * (h - 1) + 3 * w bytes, which must stay below 2^31 (PGM_EINVAL).
  *  - A context owns one device workspace allocated once by pgm_create; pgm_match never
  *    allocates device memory and returns PGM_ENOMEM when the workspace is too small.
  *  - pgm_match is asynchronous on the caller's HIP stream (a hipStream_t passed as void*;

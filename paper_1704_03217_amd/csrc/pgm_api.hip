@@ -455,6 +455,9 @@ static pgm_status check_batch(pgm_ctx_s* c, const pgm_params* p, int32_t npairs,
     if (npairs < 1) return fail(c, PGM_EINVAL, "n_pairs must be at least 1");
     if (!img1 || !img2 || !out_fwd) return fail(c, PGM_EINVAL, "img1, img2 and out_fwd must not be null");
     if (pitch_bytes < 3 * w) return fail(c, PGM_EINVAL, "pitch_bytes must be at least 3 * w");
+    // the image kernels address an image's bytes with 32-bit offsets
+    if ((int64_t)pitch_bytes * (h - 1) + 3LL * w + 4 > INT32_MAX)
+        return fail(c, PGM_EINVAL, "an image must span less than 2^31 bytes: pitch_bytes * (h - 1) + 3 * w");
     if (npairs > 1 && image_stride_bytes < (int64_t)pitch_bytes * h)
         return fail(c, PGM_EINVAL, "image_stride_bytes must be at least pitch_bytes * h");
     plan(p, w, h, Y);

@@ -1333,196 +1333,291 @@ __global__ __launch_bounds__(64) void k_fill_tab(TabFill a)
 
 __device__ __forceinline__ int mirror_fast(int i, int n) { return (unsigned)i < (unsigned)n ? i : mirror(i, n); }
 
-// packed R | G << 8 | B << 16 of pixel (x, y)
-__device__ __forceinline__ uint32_t rgb_at(const uint8_t* img, int pitch, int x, int y)
+// [lo, hi]: the interval that holds mirror(i, n) for every i in [a, b] (a <= n - 1). Inside
+// the image the values are i itself; below 0 they rise from 0 to at most -a; past n - 1 they
+// fall from n - 1 to at least 2 (n - 1) - b; a wider reach covers the whole image.
+__device__ __forceinline__ void mirror_span(int a, int b, int n, int& lo, int& hi)
 {
-    const uint8_t* p = img + (size_t)y * pitch + 3 * (size_t)x;
-    return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+    lo = max(0, min(a, 2 * (n - 1) - b));
+    hi = min(n - 1, max(b, -a));
+}
+
+// LDS dwords per image row that stage_rgb needs for a block SU pixels wide (the row's bytes
+// with up to three before them, and one more dword that the last pixel's read may touch), and
+// that count padded to whole 64-lane loads
+template <int SU> constexpr int stage_row_min() { return (3 * SU + 6) / 4 + 1; }
+template <int SU> constexpr int stage_row_dwords() { return (stage_row_min<SU>() + 63) / 64 * 64; }
+
+// Stages the SU x SV block of pixels (mirror(x0 + min(u, nu - 1), w), mirror(y0 + min(v, nv - 1),
+// h)), u < SU, v < SV, handing each to put(v, u, R | G << 8 | B << 16). The image rows and
+// columns those pixels lie in are first copied to T (SV rows of RB dwords)
+// by whole-dword loads, each row from the 4-byte boundary at or below its first byte. The
+// loads go through a buffer descriptor that spans the image, from the 4-byte boundary at or
+// below its first byte to the end of the dword that holds its last one: no load reaches
+// outside that, and one whose offset lies past it returns 0 without a memory access, so the
+// loads need no per-lane bounds tests. The pixels are then cut out of T at their byte
+// offsets. Wave q of the four handles block rows q, q + 4, ..., so that everything that
+// depends on the row alone is wave-uniform and lanes run along the row. Ends after a barrier,
+// with what put wrote to LDS visible; T is free again from then on. The host keeps every
+// image below 2^31 bytes, so the 32-bit offsets do not wrap.
+template <int SU, int SV, int RB = stage_row_dwords<SU>(), typename Put>
+__device__ __forceinline__ void stage_rgb(const uint8_t* img, int pitch, int w, int h, int x0, int nu, int y0,
+                                          int nv, uint32_t* T, Put put)
+{
+    static_assert(RB >= stage_row_min<SU>(), "a staged row holds the pixels' bytes");
+    constexpr int RPW = (SV + 3) / 4, DPL = (RB + 63) / 64, UPL = (SU + 63) / 64;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) & 3, lane = (int)threadIdx.x & 63;
+    int c_lo, c_hi, r_lo, r_hi;
+    mirror_span(x0, x0 + min(nu, SU) - 1, w, c_lo, c_hi);
+    mirror_span(y0, y0 + min(nv, SV) - 1, h, r_lo, r_hi);
+    c_hi = min(c_hi, c_lo + SU - 1);   // the bounds above never exceed SU x SV; this keeps T's
+    r_hi = min(r_hi, r_lo + SV - 1);   // indices in range whatever the arguments
+    const uint32_t mis = (uint32_t)((uintptr_t)img & 3u);
+    const uint32_t bytes = mis + (uint32_t)(h - 1) * (uint32_t)pitch + 3u * (uint32_t)w;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)((uintptr_t)img - mis), 0, (int)((bytes + 3u) & ~3u), 0x00020000);
+    const uint32_t col0 = mis + 3u * (uint32_t)c_lo;   // offset of column c_lo in row 0
+    uint32_t raw[RPW][DPL];
+#pragma unroll
+    for (int r = 0; r < RPW; r++) {
+        const uint32_t ro = (col0 + (uint32_t)min(r_lo + wave + 4 * r, h - 1) * (uint32_t)pitch) & ~3u;
+#pragma unroll
+        for (int q = 0; q < DPL; q++)
+            raw[r][q] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(ro + 4u * (uint32_t)(lane + 64 * q)), 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; r++) {
+        const int v = wave + 4 * r;
+        if (v < SV) {
+#pragma unroll
+            for (int q = 0; q < DPL; q++)
+                if (RB % 64 == 0 || lane + 64 * q < RB) T[v * RB + lane + 64 * q] = raw[r][q];
+        }
+    }
+    // byte offset of each of the lane's columns in a T row whose first byte is 4-aligned
+    int xo[UPL];
+#pragma unroll
+    for (int q = 0; q < UPL; q++) xo[q] = 3 * (clampi(mirror_fast(x0 + min(lane + 64 * q, nu - 1), w), c_lo, c_hi) - c_lo);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RPW; r++) {
+        const int v = wave + 4 * r;
+        if (v >= SV) break;
+        const int y = clampi(mirror_fast(y0 + min(v, nv - 1), h), r_lo, r_hi);
+        const int sh = (int)((col0 + (uint32_t)y * (uint32_t)pitch) & 3u);   // the row's misalignment
+        const uint32_t* row = T + (y - r_lo) * RB;
+#pragma unroll
+        for (int q = 0; q < UPL; q++) {
+            const int u = lane + 64 * q;
+            if (u < SU) {
+                const int o = sh + xo[q];
+                const uint32_t* c = row + (o >> 2);
+                put(v, u, __builtin_amdgcn_alignbyte(c[1], c[0], (uint32_t)(o & 3)) & 0xFFFFFFu);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Binomial sums of packed pixels. A pixel R | G << 8 | B << 16 contributes (R, B) to the two
+// halves of one 32-bit sum (p & 0x00FF00FF) and G << 8 to another (p & 0xFF00). A 5-tap pass
+// sums to at most 16 * 255 and two passes to at most 256 * 255 < 2^16 per channel, so the halves
+// never carry into each other and each channel's sum is the integer of the separate passes.
+__device__ __forceinline__ void binom_add(uint32_t& rb, uint32_t& g, uint32_t tap, uint32_t p)
+{
+    rb += tap * (p & 0x00FF00FFu);
+    g += tap * (p & 0xFF00u);
+}
+
+// the rounded level value (sum + 128) >> 8 of each channel, packed again
+__device__ __forceinline__ uint32_t binom_pixel(uint32_t rb, uint32_t g)
+{
+    const uint32_t R = ((rb & 0xFFFFu) + 128u) >> 8, B = ((rb >> 16) + 128u) >> 8, G = ((g >> 8) + 128u) >> 8;
+    return R | (G << 8) | (B << 16);
+}
+
+__device__ __forceinline__ void put_rgb(uint8_t* o, uint32_t p)
+{
+    o[0] = (uint8_t)p;
+    o[1] = (uint8_t)(p >> 8);
+    o[2] = (uint8_t)(p >> 16);
+}
+
+// Horizontal 5-tap binomial at even position 2k of a staged row whose stride is even: two
+// 8-byte and one 4-byte LDS reads.
+__device__ __forceinline__ void binom_row(const uint32_t* row, int k, uint32_t& rb, uint32_t& g)
+{
+    const uint2 a = *(const uint2*)(row + 2 * k), b = *(const uint2*)(row + 2 * k + 2);
+    const uint32_t c = row[2 * k + 4];
+    rb = 0;
+    g = 0;
+    binom_add(rb, g, 1, a.x);
+    binom_add(rb, g, 4, a.y);
+    binom_add(rb, g, 6, b.x);
+    binom_add(rb, g, 4, b.y);
+    binom_add(rb, g, 1, c);
 }
 
 // A work-group computes 64 x 4 output pixels: it stages the (2*64+3) x (2*4+3) source pixels
 // (reflect-101 applied at load time), filters every staged row at the even columns, then the
-// columns; the integer result is the 5x5 sum of the same products.
+// columns; the integer result is the 5x5 sum of the same products. Wave q handles staged rows
+// q, q + 4, ... and output row q; lanes run along the rows.
 constexpr int PY_TW = 64, PY_TH = 4, PY_SU = 2 * PY_TW + 3, PY_SV = 2 * PY_TH + 3;
-constexpr int PY_LDS = PY_SV * PY_SU + PY_SV * PY_TW * 3;   // dwords
+constexpr int PY_SP = PY_SU + 1;   // even row stride of the staged pixels
+constexpr int PY_H = PY_SV * PY_TW * 2 > PY_SV * stage_row_dwords<PY_SU>() ? PY_SV * PY_TW * 2 : PY_SV * stage_row_dwords<PY_SU>();
+constexpr int PY_LDS = PY_SV * PY_SP + PY_H;   // dwords
+static_assert(PY_TW == 64 && PY_TH == 4, "one lane per output column, one wave per output row");
 
 __device__ __forceinline__ void pyr_tile(const PyrArgs& a, int t, int z, uint32_t* lds)
 {
-    uint32_t* S = lds;                        // [PY_SV][PY_SU] staged pixels
-    int* H = (int*)(lds + PY_SV * PY_SU);     // [PY_SV][PY_TW][3] row-filtered values
+    uint32_t* S = lds;                  // [PY_SV][PY_SP] staged pixels
+    uint32_t* H = lds + PY_SV * PY_SP;  // [PY_SV][PY_TW][2] row sums (staging rows before them)
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) & 3, lane = (int)threadIdx.x & 63;
     const int w = a.w, h = a.h, w2 = (w + 1) >> 1, h2 = (h + 1) >> 1;
     const int X0 = (t % a.tx) * PY_TW, Y0 = (t / a.tx) * PY_TH;
     const size_t pair = (size_t)(z >> 1);
     const uint8_t* src = a.tab ? a.tab[pair].img[z & 1] : a.src[z & 1] + pair * (size_t)a.src_zs;
     uint8_t* dst = a.dst[z & 1] + pair * (size_t)a.dst_zs;
     const int xlo = 2 * X0 - 2, ylo = 2 * Y0 - 2;
-    constexpr int SPT = (PY_SU * PY_SV + 255) / 256;   // loads in flight per thread
-    uint32_t raw[SPT];
+    stage_rgb<PY_SU, PY_SV>(src, a.pitch, w, h, xlo, PY_SU, ylo, PY_SV, H, [=](int v, int u, uint32_t p) { S[v * PY_SP + u] = p; });
 #pragma unroll
-    for (int k = 0; k < SPT; k++) {
-        const int e = threadIdx.x + 256 * k;
-        raw[k] = 0;
-        if (e < PY_SU * PY_SV) {
-            const int v = e / PY_SU, u = e - v * PY_SU;
-            raw[k] = rgb_at(src, a.pitch, mirror_fast(xlo + u, w), mirror_fast(ylo + v, h));
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < SPT; k++) {
-        const int e = threadIdx.x + 256 * k;
-        if (e < PY_SU * PY_SV) S[e] = raw[k];
+    for (int r = 0; r < (PY_SV + 3) / 4; r++) {
+        const int v = wave + 4 * r;
+        if (v >= PY_SV) break;
+        uint32_t rb, g;
+        binom_row(S + v * PY_SP, lane, rb, g);
+        *(uint2*)(H + 2 * (v * PY_TW + lane)) = make_uint2(rb, g);
     }
     __syncthreads();
-    const int tap[5] = {1, 4, 6, 4, 1};
-    for (int e = threadIdx.x; e < PY_SV * PY_TW; e += 256) {
-        const int v = e / PY_TW, u = e - v * PY_TW;
-        const uint32_t* row = S + v * PY_SU + 2 * u;
-        int acc0 = 0, acc1 = 0, acc2 = 0;
-#pragma unroll
-        for (int j = 0; j < 5; j++) {
-            const uint32_t q = row[j];
-            acc0 += tap[j] * (int)(q & 0xFFu);
-            acc1 += tap[j] * (int)((q >> 8) & 0xFFu);
-            acc2 += tap[j] * (int)((q >> 16) & 0xFFu);
-        }
-        H[3 * e] = acc0;
-        H[3 * e + 1] = acc1;
-        H[3 * e + 2] = acc2;
-    }
-    __syncthreads();
-    const int x = X0 + (threadIdx.x & (PY_TW - 1)), y = Y0 + (threadIdx.x / PY_TW);
+    const int x = X0 + lane, y = Y0 + wave;
     if (x >= w2 || y >= h2) return;
-    const int u = x - X0, v0 = 2 * (y - Y0);
-    int acc[3] = {0, 0, 0};
+    const uint32_t tap[5] = {1, 4, 6, 4, 1};
+    uint32_t rb = 0, g = 0;
 #pragma unroll
     for (int i = 0; i < 5; i++) {
-        const int* q = H + 3 * ((v0 + i) * PY_TW + u);
-        acc[0] += tap[i] * q[0];
-        acc[1] += tap[i] * q[1];
-        acc[2] += tap[i] * q[2];
+        const uint2 q = *(const uint2*)(H + 2 * ((2 * wave + i) * PY_TW + lane));
+        rb += tap[i] * q.x;
+        g += tap[i] * q.y;
     }
-    uint8_t* o = dst + ((size_t)y * w2 + x) * 3;
-    o[0] = (uint8_t)((acc[0] + 128) >> 8);
-    o[1] = (uint8_t)((acc[1] + 128) >> 8);
-    o[2] = (uint8_t)((acc[2] + 128) >> 8);
+    put_rgb(dst + ((size_t)y * w2 + x) * 3, binom_pixel(rb, g));
 }
 
-// Two pyramid levels in one pass. A work-group computes P2_TW x P2_TH pixels of level l+2 and
-// the 2 P2_TW x 2 P2_TH pixels of level l+1 above them: it stages the level-l pixels under the
-// level-(l+1) pixels that its level-(l+2) pixels read (the reflections at the borders fall
-// inside that block), computes those level-(l+1) pixels as pyr_tile does, writes the ones it
-// owns, then filters them into level l+2. Each value is the integer of two separate passes.
-// Sums run two channels to a register: R and G in the low and high halves (every partial sum
-// stays below 2^16), B alone.
-constexpr int P2_TW = 32, P2_TH = 2;
-constexpr int P2_C1 = 2 * P2_TW + 3, P2_R1 = 2 * P2_TH + 3;   // level-(l+1) block
-constexpr int P2_SU = 2 * P2_C1 + 3, P2_SV = 2 * P2_R1 + 3;   // level-l block
-// the level-(l+1) block reuses the staged block's space and its row sums the first row sums'
-// space (each is written after a barrier that ends the last read of what it replaces)
-constexpr int P2_LDS = P2_SV * P2_SU + 2 * P2_SV * P2_C1;   // dwords
-static_assert(P2_R1 * P2_C1 <= P2_SV * P2_SU && 2 * P2_R1 * P2_TW <= 2 * P2_SV * P2_C1, "pyramid tile aliasing");
+// Two pyramid levels in one pass. A work-group computes TW x TH pixels of level l+2 and the
+// 2 TW x 2 TH pixels of level l+1 above them: it stages the level-l pixels under the level-(l+1)
+// pixels that its level-(l+2) pixels read (the reflections at the borders fall inside that
+// block), computes those level-(l+1) pixels as pyr_tile does, writes the ones it owns, then
+// filters them into level l+2. Each value is the integer of two separate passes. Wave q
+// handles rows q, q + 4, ... of each stage, lanes the columns. 29 x 3 makes the level-(l+1)
+// block 61 columns wide and the staged block 125: one and two 64-lane passes, for wide levels,
+// with the LDS of the gradient tile; 32 x 2 (67 and 137 columns, a nearly empty extra pass)
+// tiles a 64-pixel-wide level with two work-groups across instead of three.
+template <int TW_, int TH_> struct P2 {
+    static constexpr int TW = TW_, TH = TH_;
+    static constexpr int RB = stage_row_min<2 * (2 * TW_ + 3) + 3>();   // staging row stride
+    static constexpr int C1 = 2 * TW + 3, R1 = 2 * TH + 3;   // level-(l+1) block
+    static constexpr int SU = 2 * C1 + 3, SV = 2 * R1 + 3;   // level-l block
+    static constexpr int SP = SU + 1;                        // even row stride of the staged pixels
+    static constexpr int CP = (C1 + 63) / 64;                // column passes over the level-(l+1) block
+    // the level-(l+1) block reuses the staged block's space and its row sums the first row
+    // sums' space (each is written after a barrier that ends the last read of what it replaces)
+    static constexpr int H = SV * C1 * 2 > SV * RB ? SV * C1 * 2 : SV * RB;
+    static constexpr int LDS = SV * SP + H;   // dwords
+    static_assert(TW <= 64 && R1 * C1 <= SV * SP && 2 * R1 * TW <= H && TH <= 4, "pyramid tile shape and aliasing");
+};
+using P2Wide = P2<29, 3>;
+using P2Narrow = P2<32, 2>;
+constexpr int P2_LDS = P2Wide::LDS > P2Narrow::LDS ? P2Wide::LDS : P2Narrow::LDS;
 
-__device__ __forceinline__ uint32_t rg_pair(uint32_t q) { return (q & 0xFFu) | ((q & 0xFF00u) << 8); }
-
+template <typename D>
 __device__ __forceinline__ void pyr2_tile(const PyrArgs& a, int t, int z, uint32_t* lds)
 {
-    uint32_t* S0 = lds;                        // [P2_SV][P2_SU] staged level-l pixels
-    uint32_t* H0 = S0 + P2_SV * P2_SU;         // [P2_SV][P2_C1][2] row sums (RG, B)
-    uint32_t* V1 = S0;                         // [P2_R1][P2_C1] level-(l+1) pixels (S0 is dead)
-    uint32_t* H1 = H0;                         // [P2_R1][P2_TW][2] row sums of level l+1 (H0 is dead)
+    constexpr int TW = D::TW;
+    constexpr int TH = D::TH, C1 = D::C1, R1 = D::R1, SU = D::SU, SV = D::SV, SP = D::SP;
+    uint32_t* S0 = lds;             // [SV][SP] staged level-l pixels
+    uint32_t* H0 = lds + SV * SP;   // [SV][C1][2] row sums (staging rows before them)
+    uint32_t* V1 = S0;              // [R1][C1] level-(l+1) pixels (S0 is dead)
+    uint32_t* H1 = H0;              // [R1][TW][2] row sums of level l+1 (H0 is dead)
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) & 3, lane = (int)threadIdx.x & 63;
     const int w0 = a.w, h0 = a.h, w1 = (w0 + 1) >> 1, h1 = (h0 + 1) >> 1, w2 = (w1 + 1) >> 1, h2 = (h1 + 1) >> 1;
-    const int X0 = (t % a.tx) * P2_TW, Y0 = (t / a.tx) * P2_TH;
+    const int X0 = (t % a.tx) * TW, Y0 = (t / a.tx) * TH;
     const size_t pair = (size_t)(z >> 1);
     const uint8_t* src = a.tab ? a.tab[pair].img[z & 1] : a.src[z & 1] + pair * (size_t)a.src_zs;
     uint8_t* dst1 = a.dst[z & 1] + pair * (size_t)a.dst_zs;
     uint8_t* dst2 = a.dst2[z & 1] + pair * (size_t)a.dst_zs;
-    const int cx0 = max(0, 2 * X0 - 2), cx1 = min(w1 - 1, 2 * X0 + 2 * P2_TW);
-    const int cy0 = max(0, 2 * Y0 - 2), cy1 = min(h1 - 1, 2 * Y0 + 2 * P2_TH);
+    const int cx0 = max(0, 2 * X0 - 2), cx1 = min(w1 - 1, 2 * X0 + 2 * TW);
+    const int cy0 = max(0, 2 * Y0 - 2), cy1 = min(h1 - 1, 2 * Y0 + 2 * TH);
     const int NU = 2 * (cx1 - cx0 + 1) + 3, NV = 2 * (cy1 - cy0 + 1) + 3;
     const int xlo = 2 * cx0 - 2, ylo = 2 * cy0 - 2;
-    constexpr int SPT = (P2_SU * P2_SV + 255) / 256;
-    uint32_t raw[SPT];
+    stage_rgb<SU, SV, D::RB>(src, a.pitch, w0, h0, xlo, NU, ylo, NV, H0, [=](int v, int u, uint32_t p) { S0[v * SP + u] = p; });
 #pragma unroll
-    for (int k = 0; k < SPT; k++) {
-        const int e = threadIdx.x + 256 * k;
-        raw[k] = 0;
-        if (e < P2_SU * P2_SV) {
-            const int v = e / P2_SU, u = e - v * P2_SU;
-            raw[k] = rgb_at(src, a.pitch, mirror_fast(xlo + min(u, NU - 1), w0), mirror_fast(ylo + min(v, NV - 1), h0));
+    for (int r = 0; r < (SV + 3) / 4; r++) {
+        const int v = wave + 4 * r;
+        if (v >= SV) break;
+#pragma unroll
+        for (int q = 0; q < D::CP; q++) {
+            const int k = lane + 64 * q;   // level-(l+1) block column
+            if (k < C1) {
+                uint32_t rb, g;
+                binom_row(S0 + v * SP, k, rb, g);
+                *(uint2*)(H0 + 2 * (v * C1 + k)) = make_uint2(rb, g);
+            }
         }
-    }
-#pragma unroll
-    for (int k = 0; k < SPT; k++) {
-        const int e = threadIdx.x + 256 * k;
-        if (e < P2_SU * P2_SV) S0[e] = raw[k];
     }
     __syncthreads();
     const uint32_t tap[5] = {1, 4, 6, 4, 1};
-    for (int e = threadIdx.x; e < P2_SV * P2_C1; e += 256) {
-        const int v = e / P2_C1, k = e - v * P2_C1;
-        const uint32_t* row = S0 + v * P2_SU + 2 * k;
-        uint32_t rg = 0, b = 0;
 #pragma unroll
-        for (int j = 0; j < 5; j++) {
-            const uint32_t q = row[j];
-            rg += tap[j] * rg_pair(q);
-            b += tap[j] * ((q >> 16) & 0xFFu);
-        }
-        H0[2 * e] = rg;
-        H0[2 * e + 1] = b;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < P2_R1 * P2_C1; e += 256) {
-        const int r = e / P2_C1, k = e - r * P2_C1;
-        uint32_t rg = 0, b = 0;
+    for (int r = 0; r < (R1 + 3) / 4; r++) {
+        const int rr = wave + 4 * r;
+        if (rr >= R1) break;
 #pragma unroll
-        for (int i = 0; i < 5; i++) {
-            const uint32_t* q = H0 + 2 * ((2 * r + i) * P2_C1 + k);
-            rg += tap[i] * q[0];
-            b += tap[i] * q[1];
-        }
-        const uint32_t R = ((rg & 0xFFFFu) + 128) >> 8, G = ((rg >> 16) + 128) >> 8, B = (b + 128) >> 8;
-        V1[e] = R | (G << 8) | (B << 16);
-        const int c = cx0 + k, y = cy0 + r;
-        if (c >= 2 * X0 && c < 2 * X0 + 2 * P2_TW && c <= cx1 && y >= 2 * Y0 && y < 2 * Y0 + 2 * P2_TH && y <= cy1) {
-            uint8_t* o = dst1 + ((size_t)y * w1 + c) * 3;
-            o[0] = (uint8_t)R;
-            o[1] = (uint8_t)G;
-            o[2] = (uint8_t)B;
-        }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < P2_R1 * P2_TW; e += 256) {
-        const int r = e / P2_TW, k = e - r * P2_TW;
-        const int X2 = X0 + k;
-        uint32_t rg = 0, b = 0;
-        if (r <= cy1 - cy0 && X2 < w2) {
+        for (int q = 0; q < D::CP; q++) {
+            const int k = lane + 64 * q;
+            if (k < C1) {
+                uint32_t rb = 0, g = 0;
 #pragma unroll
-            for (int j = 0; j < 5; j++) {
-                const uint32_t q = V1[r * P2_C1 + mirror_fast(2 * X2 - 2 + j, w1) - cx0];
-                rg += tap[j] * rg_pair(q);
-                b += tap[j] * ((q >> 16) & 0xFFu);
+                for (int i = 0; i < 5; i++) {
+                    const uint2 e = *(const uint2*)(H0 + 2 * ((2 * rr + i) * C1 + k));
+                    rb += tap[i] * e.x;
+                    g += tap[i] * e.y;
+                }
+                const uint32_t px = binom_pixel(rb, g);
+                V1[rr * C1 + k] = px;
+                const int c = cx0 + k, y = cy0 + rr;
+                if (c >= 2 * X0 && c < 2 * X0 + 2 * TW && c <= cx1 && y >= 2 * Y0 && y < 2 * Y0 + 2 * TH && y <= cy1)
+                    put_rgb(dst1 + ((size_t)y * w1 + c) * 3, px);
             }
         }
-        H1[2 * e] = rg;
-        H1[2 * e + 1] = b;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < P2_TW * P2_TH; e += 256) {
-        const int X2 = X0 + e % P2_TW, Y2 = Y0 + e / P2_TW;
-        if (X2 >= w2 || Y2 >= h2) continue;
-        uint32_t rg = 0, b = 0;
+    // level l+2: rows of the level-(l+1) block at this tile's even columns, then its columns
+    const int X2 = X0 + lane;
+    int col[5];   // the level-(l+1) block columns of the five taps (reflected at the border)
 #pragma unroll
-        for (int i = 0; i < 5; i++) {
-            const uint32_t* q = H1 + 2 * ((mirror_fast(2 * Y2 - 2 + i, h1) - cy0) * P2_TW + e % P2_TW);
-            rg += tap[i] * q[0];
-            b += tap[i] * q[1];
+    for (int j = 0; j < 5; j++) col[j] = mirror_fast(2 * X2 - 2 + j, w1) - cx0;
+#pragma unroll
+    for (int r = 0; r < (R1 + 3) / 4; r++) {
+        const int rr = wave + 4 * r;
+        if (rr >= R1) break;
+        if (lane < TW) {
+            uint32_t rb = 0, g = 0;
+            if (rr <= cy1 - cy0 && X2 < w2) {
+#pragma unroll
+                for (int j = 0; j < 5; j++) binom_add(rb, g, tap[j], V1[rr * C1 + col[j]]);
+            }
+            *(uint2*)(H1 + 2 * (rr * TW + lane)) = make_uint2(rb, g);
         }
-        uint8_t* o = dst2 + ((size_t)Y2 * w2 + X2) * 3;
-        o[0] = (uint8_t)(((rg & 0xFFFFu) + 128) >> 8);
-        o[1] = (uint8_t)(((rg >> 16) + 128) >> 8);
-        o[2] = (uint8_t)((b + 128) >> 8);
     }
+    __syncthreads();
+    const int Y2 = Y0 + wave;
+    if (wave >= TH || lane >= TW || X2 >= w2 || Y2 >= h2) return;
+    uint32_t rb = 0, g = 0;
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+        const uint2 e = *(const uint2*)(H1 + 2 * ((mirror_fast(2 * Y2 - 2 + i, h1) - cy0) * TW + lane));
+        rb += tap[i] * e.x;
+        g += tap[i] * e.y;
+    }
+    put_rgb(dst2 + ((size_t)Y2 * w2 + X2) * 3, binom_pixel(rb, g));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1592,30 +1687,41 @@ __device__ uint32_t to_lab(uint32_t rgb, const double* lin)
 }
 
 // A work-group computes a 64 x 12 tile of the padded gradient image (64 x 8 was slower on
-// 32-pair batches, 64 x 32 everywhere; 64 x 12 keeps k_prep's LDS at 8 work-groups per CU). It stages the source pixels (one dword per
-// pixel: R | G << 8 | B << 16, or the integer luma) that the windows of its pixels read -- the
-// padding maps to the nearest image pixel, the filter reflects (101) -- applies the smoothing
-// and derivative taps along the staged rows, then across them: the Sobel sums are separable,
-// so the integer results equal the full KS x KS sums. Its LDS holds the staged pixels, one
-// packed (smoothing, derivative) plane per colour channel and, after them, the sRGB
-// linearisation table of the CIELab conversion (GR_LIN dwords, 256 doubles).
+// 32-pair batches, 64 x 32 everywhere). It stages the pixels that the windows of its pixels
+// read -- the padding maps to the nearest image pixel, the filter reflects (101) -- converted to
+// the level's colour space, applies the smoothing and derivative taps along the staged rows,
+// then across them: the Sobel sums are separable, so the integer results equal the full
+// KS x KS sums. Every partial sum fits in 16 bits (row smoothing <= 16 * 255, row derivative
+// <= 6 * 255, columns <= 6 * 4080), so the sums run as packed 16-bit multiply-adds on pairs of
+// values: a staged colour pixel is kept as (R, G) and (B, B), a grey one as (Y, Y), and the row
+// sums as the planes (smooth R, smooth G), (deriv R, deriv G), (smooth B, deriv B), or (smooth
+// Y, deriv Y). Wave q of the four handles rows q, q + 4, ... of each pass, lanes the columns.
+// LDS: the staged pixels, then the row-sum planes; the staging rows and the sRGB linearisation
+// table of the CIELab conversion (256 doubles) use the planes' space before the row pass.
 constexpr int GR_TW = 64, GR_TH = 12, GR_SU = GR_TW + 4, GR_SV = GR_TH + 4;   // kernel radius <= 2
-constexpr int GR_LDS = GR_SV * GR_SU + GR_SV * GR_TW * 3;                     // dwords
-constexpr int GR_LIN = 2 * 256;
-static_assert(GR_LDS % 2 == 0, "the linearisation table is 8-byte aligned");
+constexpr int GR_LDS = GR_SV * GR_SU * 2 + GR_SV * GR_TW * 3;                 // dwords
+constexpr int GR_LIN_AT = GR_SV * GR_SU * 2 + GR_SV * stage_row_dwords<GR_SU>();
+static_assert(GR_TW == 64 && GR_SV % 4 == 0 && GR_TH % 4 == 0, "one lane per column, whole rows per wave");
+static_assert(GR_LIN_AT % 2 == 0 && GR_LIN_AT + 512 <= GR_LDS, "the linearisation table fits after the staging rows");
+
+__device__ __forceinline__ uint32_t lo_hi(uint32_t lo, uint32_t hi, uint32_t sel) { return __builtin_amdgcn_perm(hi, lo, sel); }
+__device__ __forceinline__ s16x2 as_s16x2(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(s16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 
 // FEAT: 0 integer gradients, 1 direction-only unit vectors (float), 2 literal signs
 template <int KS, bool GRAY, int FEAT>
-__device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, int t, int z, uint32_t* lds,
-                                          double* lin)
+__device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, int t, int z, uint32_t* lds)
 {
-    constexpr bool F32 = FEAT == 1;
     constexpr int CH = GRAY ? 1 : 3;
     constexpr int C2 = 2 * CH;
     constexpr int K = KS / 2;
-    uint32_t* S = lds;                          // [NV][GR_SU] staged pixels
-    int* H = (int*)(lds + GR_SV * GR_SU);       // [CH][GR_SV][GR_TW] packed (row smoothing, row
-                                                // derivative); consecutive lanes, consecutive banks
+    constexpr int SW = GRAY ? 1 : 2;   // dwords per staged pixel
+    constexpr int NP = GRAY ? 1 : 3;   // row-sum planes
+    constexpr int PL = GR_SV * GR_TW;  // dwords per plane
+    uint32_t* S = lds;                             // [GR_SV][GR_SU][SW]
+    uint32_t* H = lds + GR_SV * GR_SU * 2;         // [NP][GR_SV][GR_TW]
+    double* lin = (double*)(lds + GR_LIN_AT);
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
     const int w = L.w, h = L.h;
     const int pw = w + 2 * PAD, ph = h + 2 * PAD;
     const int X0 = (t % L.tx) * GR_TW, Y0 = (t / L.tx) * GR_TH;
@@ -1625,121 +1731,115 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
     // the image columns and rows the tile's pixels map to
     const int cx0 = clampi(X0 - PAD, 0, w - 1), cx1 = clampi(min(X0 + GR_TW - 1, pw - 1) - PAD, 0, w - 1);
     const int cy0 = clampi(Y0 - PAD, 0, h - 1), cy1 = clampi(min(Y0 + GR_TH - 1, ph - 1) - PAD, 0, h - 1);
-    const int NC = cx1 - cx0 + 1, NR = cy1 - cy0 + 1;
-    const int NU = NC + 2 * K, NV = NR + 2 * K;
-    if (!GRAY && L.space == PGM_SPACE_LAB) {   // uniform over the work-group
-        lin[threadIdx.x] = srgb_linear((int)threadIdx.x);
-        __syncthreads();
-    }
+    const int NU = cx1 - cx0 + 1 + 2 * K, NV = cy1 - cy0 + 1 + 2 * K;
+    const int space = L.space;
+    if (!GRAY && space == PGM_SPACE_LAB) lin[threadIdx.x] = srgb_linear((int)threadIdx.x);   // read after the staging barrier
     // Staging: a fixed GR_SV x GR_SU block (columns and rows past the needed NU x NV repeat the
-    // last needed one), every load issued before the first conversion.
-    constexpr int SPT = (GR_SU * GR_SV + 255) / 256;
-    uint32_t raw[SPT];
-#pragma unroll
-    for (int k = 0; k < SPT; k++) {
-        const int e = threadIdx.x + 256 * k;
-        raw[k] = 0;
-        if (e < GR_SU * GR_SV) {
-            const int v = e / GR_SU, u = e - v * GR_SU;
-            raw[k] = rgb_at(img, L.pitch, mirror_fast(cx0 - K + min(u, NU - 1), w), mirror_fast(cy0 - K + min(v, NV - 1), h));
+    // last needed one).
+    stage_rgb<GR_SU, GR_SV>(img, L.pitch, w, h, cx0 - K, NU, cy0 - K, NV, H, [=](int v, int u, uint32_t p) {
+        if (GRAY) {
+            const uint32_t y = (77 * (p & 0xFFu) + 150 * ((p >> 8) & 0xFFu) + 29 * ((p >> 16) & 0xFFu) + 128) >> 8;
+            S[v * GR_SU + u] = y | (y << 16);
+        } else {
+            if (space == PGM_SPACE_YCRCB) p = to_ycrcb(p);
+            else if (space == PGM_SPACE_LAB) p = to_lab(p, lin);
+            ((uint2*)S)[v * GR_SU + u] = make_uint2(__builtin_amdgcn_perm(0u, p, 0x0c010c00u), __builtin_amdgcn_perm(0u, p, 0x0c020c02u));
         }
-    }
-#pragma unroll
-    for (int k = 0; k < SPT; k++) {
-        const int e = threadIdx.x + 256 * k;
-        if (e < GR_SU * GR_SV) {
-            uint32_t val = raw[k];
-            if (GRAY) {
-                val = (77 * (val & 0xFFu) + 150 * ((val >> 8) & 0xFFu) + 29 * ((val >> 16) & 0xFFu) + 128) >> 8;
-            } else {
-                if (L.space == PGM_SPACE_YCRCB) val = to_ycrcb(val);
-                else if (L.space == PGM_SPACE_LAB) val = to_lab(val, lin);
-            }
-            S[e] = val;
-        }
-    }
-    __syncthreads();
-    // Sobel taps of size KS: smoothing and derivative. Every partial sum fits in 16 bits (row
-    // smoothing <= 16 * 255, row derivative <= 6 * 255, columns <= 6 * 4080), so each pair of
-    // sums runs in the two halves of one register (packed 16-bit multiply-adds).
+    });
     const short sm3[3] = {1, 2, 1}, dv3[3] = {-1, 0, 1};
     const short sm5[5] = {1, 4, 6, 4, 1}, dv5[5] = {-1, -2, 0, 2, 1};
-    // Row pass over the fixed block: plane c holds (smoothing, derivative) of channel c.
-    uint32_t* H2 = (uint32_t*)H;   // [CH][GR_SV][GR_TW] packed pairs
-    constexpr int RPT = GR_SV * GR_TW / 256;
-    static_assert(GR_SV * GR_TW % 256 == 0, "row pass: whole entries per thread");
+    // Row pass over the fixed block.
 #pragma unroll
-    for (int k = 0; k < RPT; k++) {
-        const int e = threadIdx.x + 256 * k;
-        const int v = e / GR_TW, u = e - v * GR_TW;
-        const uint32_t* row = S + v * GR_SU + u;
-        s16x2 acc[CH];
+    for (int r = 0; r < GR_SV / 4; r++) {
+        const int v = wave + 4 * r;
+        s16x2 acc[NP];
 #pragma unroll
-        for (int c = 0; c < CH; c++) acc[c] = s16x2{0, 0};
+        for (int c = 0; c < NP; c++) acc[c] = s16x2{0, 0};
 #pragma unroll
         for (int j = 0; j < KS; j++) {
-            const uint32_t q = row[j];
-            const s16x2 wt = s16x2{KS == 3 ? sm3[j] : sm5[j], KS == 3 ? dv3[j] : dv5[j]};
-#pragma unroll
-            for (int c = 0; c < CH; c++) {
-                const short val = (short)((q >> (8 * c)) & 0xFFu);
-                acc[c] += wt * s16x2{val, val};
+            const short sm = KS == 3 ? sm3[j] : sm5[j], dv = KS == 3 ? dv3[j] : dv5[j];
+            if (GRAY) {
+                acc[0] += s16x2{sm, dv} * as_s16x2(S[v * GR_SU + lane + j]);
+            } else {
+                const uint2 q = ((const uint2*)S)[v * GR_SU + lane + j];
+                acc[0] += s16x2{sm, sm} * as_s16x2(q.x);
+                acc[1] += s16x2{dv, dv} * as_s16x2(q.x);
+                acc[2] += s16x2{sm, dv} * as_s16x2(q.y);
             }
         }
 #pragma unroll
-        for (int c = 0; c < CH; c++) H2[(c * GR_SV + v) * GR_TW + u] = __builtin_bit_cast(uint32_t, acc[c]);
+        for (int c = 0; c < NP; c++) H[c * PL + v * GR_TW + lane] = as_u32(acc[c]);
     }
     __syncthreads();
     // Column pass: (sum of derivative weights x smoothing, sum of smoothing weights x
     // derivative) = (gy, gx) per channel.
-    for (int e = threadIdx.x; e < GR_TW * GR_TH; e += 256) {
-        const int X = X0 + (e & (GR_TW - 1)), Y = Y0 + e / GR_TW;
-        if (X >= pw || Y >= ph) continue;
-        const int u = clampi(X - PAD, 0, w - 1) - cx0;
-        const int v = clampi(Y - PAD, 0, h - 1) - cy0;
-        s16x2 acc[CH];
+    const int X = X0 + lane;
+    const int u = clampi(X - PAD, 0, w - 1) - cx0;
 #pragma unroll
-        for (int c = 0; c < CH; c++) acc[c] = s16x2{0, 0};
+    for (int r = 0; r < GR_TH / 4; r++) {
+        const int Y = Y0 + wave + 4 * r;
+        if (Y >= ph) break;
+        if (X >= pw) continue;
+        const int v = clampi(Y - PAD, 0, h - 1) - cy0;
+        s16x2 g[NP];   // colour: (gy R, gy G), (gx R, gx G), (gy B, gx B); grey: (gy, gx)
+#pragma unroll
+        for (int c = 0; c < NP; c++) g[c] = s16x2{0, 0};
 #pragma unroll
         for (int i = 0; i < KS; i++) {
-            const s16x2 wt = s16x2{KS == 3 ? dv3[i] : dv5[i], KS == 3 ? sm3[i] : sm5[i]};
-#pragma unroll
-            for (int c = 0; c < CH; c++)
-                acc[c] += wt * __builtin_bit_cast(s16x2, H2[(c * GR_SV + v + i) * GR_TW + u]);
-        }
-        int gx[CH], gy[CH];
-#pragma unroll
-        for (int c = 0; c < CH; c++) {
-            gy[c] = acc[c].x;
-            gx[c] = acc[c].y;
+            const short sm = KS == 3 ? sm3[i] : sm5[i], dv = KS == 3 ? dv3[i] : dv5[i];
+            const uint32_t* q = H + (v + i) * GR_TW + u;
+            if (GRAY) {
+                g[0] += s16x2{dv, sm} * as_s16x2(q[0]);
+            } else {
+                g[0] += s16x2{dv, dv} * as_s16x2(q[0]);
+                g[1] += s16x2{sm, sm} * as_s16x2(q[PL]);
+                g[2] += s16x2{dv, sm} * as_s16x2(q[2 * PL]);
+            }
         }
         const size_t o = ((size_t)Y * pw + X) * C2;
-        if (!F32) {
-            uint16_t vals[C2];
-#pragma unroll
-            for (int c = 0; c < CH; c++) {
-                if (FEAT == 2) {   // Sec. III-F read element-wise: G./|G| is the sign, 0 stays 0
-                    gx[c] = (gx[c] > 0) - (gx[c] < 0);
-                    gy[c] = (gy[c] > 0) - (gy[c] < 0);
-                }
-                vals[c] = (uint16_t)(gx[c] + (int)BIAS);
-                vals[CH + c] = (uint16_t)(gy[c] + (int)BIAS);
-            }
+        if (FEAT == 0) {
+            // biased 16-bit values in the order gx of each channel, then gy of each; adding
+            // 2^15 modulo 2^16 flips the top bit of each half
             uint32_t* out = (uint32_t*)((uint16_t*)G + o);   // C2 even: pixels are dword aligned
-#pragma unroll
-            for (int q = 0; q < C2 / 2; q++) out[q] = (uint32_t)vals[2 * q] | ((uint32_t)vals[2 * q + 1] << 16);
+            if (GRAY) {
+                out[0] = __builtin_amdgcn_alignbit(as_u32(g[0]), as_u32(g[0]), 16) ^ 0x80008000u;
+            } else {
+                out[0] = as_u32(g[1]) ^ 0x80008000u;
+                out[1] = lo_hi(as_u32(g[2]), as_u32(g[0]), 0x05040302u) ^ 0x80008000u;
+                out[2] = lo_hi(as_u32(g[0]), as_u32(g[2]), 0x05040302u) ^ 0x80008000u;
+            }
         } else {
-            float* out = (float*)G + o;
+            int gx[CH], gy[CH];
+            if (GRAY) {
+                gy[0] = g[0].x;
+                gx[0] = g[0].y;
+            } else {
+                gy[0] = g[0].x, gy[1] = g[0].y, gy[2] = g[2].x;
+                gx[0] = g[1].x, gx[1] = g[1].y, gx[2] = g[2].y;
+            }
+            if (FEAT == 2) {   // Sec. III-F read element-wise: G./|G| is the sign, 0 stays 0
+                uint16_t vals[C2];
 #pragma unroll
-            for (int c = 0; c < CH; c++) {
-                float ux = 0.0f, uy = 0.0f;
-                if (gx[c] != 0 || gy[c] != 0) {
-                    const double n = sqrt((double)gx[c] * gx[c] + (double)gy[c] * gy[c]);
-                    ux = (float)((double)gx[c] / n);
-                    uy = (float)((double)gy[c] / n);
+                for (int c = 0; c < CH; c++) {
+                    vals[c] = (uint16_t)(((gx[c] > 0) - (gx[c] < 0)) + (int)BIAS);
+                    vals[CH + c] = (uint16_t)(((gy[c] > 0) - (gy[c] < 0)) + (int)BIAS);
                 }
-                out[c] = ux;
-                out[CH + c] = uy;
+                uint32_t* out = (uint32_t*)((uint16_t*)G + o);
+#pragma unroll
+                for (int k = 0; k < C2 / 2; k++) out[k] = (uint32_t)vals[2 * k] | ((uint32_t)vals[2 * k + 1] << 16);
+            } else {
+                float* out = (float*)G + o;
+#pragma unroll
+                for (int c = 0; c < CH; c++) {
+                    float ux = 0.0f, uy = 0.0f;
+                    if (gx[c] != 0 || gy[c] != 0) {
+                        const double n = sqrt((double)gx[c] * gx[c] + (double)gy[c] * gy[c]);
+                        ux = (float)((double)gx[c] / n);
+                        uy = (float)((double)gy[c] / n);
+                    }
+                    out[c] = ux;
+                    out[CH + c] = uy;
+                }
             }
         }
     }
@@ -1810,8 +1910,7 @@ __device__ __forceinline__ void rng_block(const RngArgs& a, int b)
 // turn).
 // ---------------------------------------------------------------------------------------
 
-constexpr int PREP_LDS = (GR_LDS + GR_LIN) > PY_LDS ? ((GR_LDS + GR_LIN) > P2_LDS ? GR_LDS + GR_LIN : P2_LDS)
-                                                    : (PY_LDS > P2_LDS ? PY_LDS : P2_LDS);
+constexpr int PREP_LDS = GR_LDS > PY_LDS ? (GR_LDS > P2_LDS ? GR_LDS : P2_LDS) : (PY_LDS > P2_LDS ? PY_LDS : P2_LDS);
 
 template <int KS, bool GRAY, int FEAT>
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
@@ -1819,7 +1918,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
     __shared__ __align__(16) uint32_t lds[PREP_LDS];
     int b = blockIdx.x;
     if (b < a.pyr_blocks) {
-        if (a.pyr.two) pyr2_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
+        if (a.pyr.two) pyr2_tile<P2Wide>(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
         else pyr_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
         return;
     }
@@ -1828,8 +1927,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
         const int z = b / a.grad_tiles, tt = b - z * a.grad_tiles;
         int e = 0;
         while (e + 1 < a.grad.n && tt >= a.grad.lv[e + 1].base) e++;
-        grad_tile<KS, GRAY, FEAT>(a.grad.lv[e], a.grad.dst_zs, tt - a.grad.lv[e].base, z, lds,
-                                  (double*)(lds + GR_LDS));
+        grad_tile<KS, GRAY, FEAT>(a.grad.lv[e], a.grad.dst_zs, tt - a.grad.lv[e].base, z, lds);
         return;
     }
     rng_block(a.rng, b - a.grad_blocks);
@@ -1837,31 +1935,31 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
 
 __global__ __launch_bounds__(256) void k_pyr(PyrArgs a)
 {
-    __shared__ uint32_t lds[PY_LDS > P2_LDS ? PY_LDS : P2_LDS];
-    if (a.two) pyr2_tile(a, blockIdx.x, blockIdx.y, lds);
+    __shared__ __align__(16) uint32_t lds[PY_LDS > P2_LDS ? PY_LDS : P2_LDS];
+    if (a.two) pyr2_tile<P2Narrow>(a, blockIdx.x, blockIdx.y, lds);
     else pyr_tile(a, blockIdx.x, blockIdx.y, lds);
 }
 
 template <int KS, bool GRAY, int FEAT>
 __global__ __launch_bounds__(256) void k_gradient(GradArgs a)
 {
-    __shared__ __align__(16) uint32_t lds[GR_LDS + GR_LIN];
+    __shared__ __align__(16) uint32_t lds[GR_LDS];
     int lv = 0;
     while (lv + 1 < a.n && (int)blockIdx.x >= a.lv[lv + 1].base) lv++;
-    grad_tile<KS, GRAY, FEAT>(a.lv[lv], a.dst_zs, (int)blockIdx.x - a.lv[lv].base, blockIdx.y, lds,
-                              (double*)(lds + GR_LDS));
+    grad_tile<KS, GRAY, FEAT>(a.lv[lv], a.dst_zs, (int)blockIdx.x - a.lv[lv].base, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------------------
 
-static void plan_pyr(PyrArgs& a)
+// tw x th: the level-(l+2) tile of the kernel that runs the plan (two levels)
+static void plan_pyr(PyrArgs& a, int tw, int th)
 {
     const int w1 = (a.w + 1) / 2, h1 = (a.h + 1) / 2;
     if (a.two) {   // tiles over the second level
-        a.tx = ((w1 + 1) / 2 + P2_TW - 1) / P2_TW;
-        a.tiles = a.tx * (((h1 + 1) / 2 + P2_TH - 1) / P2_TH);
+        a.tx = ((w1 + 1) / 2 + tw - 1) / tw;
+        a.tiles = a.tx * (((h1 + 1) / 2 + th - 1) / th);
     } else {
         a.tx = (w1 + PY_TW - 1) / PY_TW;
         a.tiles = a.tx * ((h1 + PY_TH - 1) / PY_TH);
@@ -1883,7 +1981,7 @@ static int plan_grad(GradArgs& a)
 
 hipError_t launch_pyr(PyrArgs a, int npairs, hipStream_t s)
 {
-    plan_pyr(a);
+    plan_pyr(a, P2Narrow::TW, P2Narrow::TH);
     hipLaunchKernelGGL(k_pyr, dim3(a.tiles, 2 * npairs), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -1923,7 +2021,7 @@ hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hi
     a.grad_blocks = a.grad_tiles * 2 * npairs;
     a.pyr_blocks = 0;
     if (a.with_pyr) {
-        plan_pyr(a.pyr);
+        plan_pyr(a.pyr, P2Wide::TW, P2Wide::TH);
         a.pyr_blocks = a.pyr.tiles * 2 * npairs;
     }
     const long long blocks = (long long)a.rng_blocks + a.grad_blocks + a.pyr_blocks;

@@ -243,3 +243,20 @@ def test_workspace_too_small_is_enomem(matcher):
         assert e.value.status == pgm.PGM_ENOMEM
     finally:
         small.close()
+
+
+def test_image_span_of_2_31_bytes_is_einval(matcher):
+    """The image kernels address an image's bytes with 32-bit offsets, so a pitch that makes one
+    image span 2^31 bytes or more is refused before any launch (the images here are small; the
+    pitch alone is checked)."""
+    torch = matcher.torch
+    img = torch.zeros((64, 64, 3), dtype=torch.uint8, device="cuda")
+    o = matcher.outputs(base_params(), 64, 64)
+    stream = torch.cuda.current_stream().cuda_stream
+    pitch = (2**31 - 3 * 64 - 4) // 63 + 1   # 63 * pitch + 3 * 64 + 4 > 2^31 - 1
+    with pytest.raises(pgm.PGMError) as e:
+        pgm.pgm_match(matcher.ctx, base_params(), img.data_ptr(), img.data_ptr(), 64, 64, pitch,
+                      o["fwd"].data_ptr(), None, None, None, None, stream)
+    assert e.value.status == pgm.PGM_EINVAL
+    assert "2^31" in pgm.pgm_last_error(matcher.ctx)
+    torch.cuda.synchronize()
