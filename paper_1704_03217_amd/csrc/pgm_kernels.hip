@@ -1365,7 +1365,10 @@ __device__ __forceinline__ void stage_rgb(const uint8_t* img, int pitch, int w, 
                                           int nv, uint32_t* T, Put put)
 {
     static_assert(RB >= stage_row_min<SU>(), "a staged row holds the pixels' bytes");
-    constexpr int RPW = (SV + 3) / 4, DPL = (RB + 63) / 64, UPL = (SU + 63) / 64;
+    // Columns past the last whole 64 go in one flat pass over all rows when they fit 256
+    // threads, instead of a nearly idle pass per row.
+    constexpr int REM = SU % 64, FLAT = REM > 0 && REM * SV <= 256;
+    constexpr int RPW = (SV + 3) / 4, DPL = (RB + 63) / 64, UPL = FLAT ? SU / 64 : (SU + 63) / 64;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) & 3, lane = (int)threadIdx.x & 63;
     int c_lo, c_hi, r_lo, r_hi;
     mirror_span(x0, x0 + min(nu, SU) - 1, w, c_lo, c_hi);
@@ -1415,6 +1418,14 @@ __device__ __forceinline__ void stage_rgb(const uint8_t* img, int pitch, int w, 
                 put(v, u, __builtin_amdgcn_alignbyte(c[1], c[0], (uint32_t)(o & 3)) & 0xFFFFFFu);
             }
         }
+    }
+    if (FLAT && (int)threadIdx.x < REM * SV) {
+        const int v = (int)threadIdx.x / (REM > 0 ? REM : 1), u = SU - REM + ((int)threadIdx.x - v * REM);
+        const int x = clampi(mirror_fast(x0 + min(u, nu - 1), w), c_lo, c_hi);
+        const int y = clampi(mirror_fast(y0 + min(v, nv - 1), h), r_lo, r_hi);
+        const int o = (int)((col0 + (uint32_t)y * (uint32_t)pitch) & 3u) + 3 * (x - c_lo);
+        const uint32_t* c = T + (y - r_lo) * RB + (o >> 2);
+        put(v, u, __builtin_amdgcn_alignbyte(c[1], c[0], (uint32_t)(o & 3)) & 0xFFFFFFu);
     }
     __syncthreads();
 }
@@ -1773,13 +1784,15 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
     __syncthreads();
     // Column pass: (sum of derivative weights x smoothing, sum of smoothing weights x
     // derivative) = (gy, gx) per channel.
+    constexpr int PX = C2 * (FEAT == 1 ? 4 : 2);   // bytes per gradient pixel
     const int X = X0 + lane;
     const int u = clampi(X - PAD, 0, w - 1) - cx0;
+    char* const tile = (char*)G + ((size_t)Y0 * pw + X0) * PX;   // the tile's first pixel
+    const size_t row_bytes = (size_t)pw * PX;
 #pragma unroll
     for (int r = 0; r < GR_TH / 4; r++) {
         const int Y = Y0 + wave + 4 * r;
-        if (Y >= ph) break;
-        if (X >= pw) continue;
+        if (Y >= ph || X >= pw) continue;
         const int v = clampi(Y - PAD, 0, h - 1) - cy0;
         s16x2 g[NP];   // colour: (gy R, gy G), (gx R, gx G), (gy B, gx B); grey: (gy, gx)
 #pragma unroll
@@ -1796,11 +1809,11 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
                 g[2] += s16x2{dv, sm} * as_s16x2(q[2 * PL]);
             }
         }
-        const size_t o = ((size_t)Y * pw + X) * C2;
+        char* const px = tile + (wave + 4 * r) * row_bytes + (uint32_t)(lane * PX);
         if (FEAT == 0) {
             // biased 16-bit values in the order gx of each channel, then gy of each; adding
             // 2^15 modulo 2^16 flips the top bit of each half
-            uint32_t* out = (uint32_t*)((uint16_t*)G + o);   // C2 even: pixels are dword aligned
+            uint32_t* out = (uint32_t*)px;   // C2 even: pixels are dword aligned
             if (GRAY) {
                 out[0] = __builtin_amdgcn_alignbit(as_u32(g[0]), as_u32(g[0]), 16) ^ 0x80008000u;
             } else {
@@ -1824,11 +1837,11 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
                     vals[c] = (uint16_t)(((gx[c] > 0) - (gx[c] < 0)) + (int)BIAS);
                     vals[CH + c] = (uint16_t)(((gy[c] > 0) - (gy[c] < 0)) + (int)BIAS);
                 }
-                uint32_t* out = (uint32_t*)((uint16_t*)G + o);
+                uint32_t* out = (uint32_t*)px;
 #pragma unroll
                 for (int k = 0; k < C2 / 2; k++) out[k] = (uint32_t)vals[2 * k] | ((uint32_t)vals[2 * k + 1] << 16);
             } else {
-                float* out = (float*)G + o;
+                float* out = (float*)px;
 #pragma unroll
                 for (int c = 0; c < CH; c++) {
                     float ux = 0.0f, uy = 0.0f;
