@@ -1862,9 +1862,9 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
 // random numbers of a whole pair: initial displacements and every random-search offset
 // ---------------------------------------------------------------------------------------
 
-// seeds per thread of a random-search work-group: few, short work-groups, so that they do not
-// hold k_prep's LDS slots that the image tiles need
-constexpr int RNG_SPT = 8;
+// seeds per thread of a random-search work-group (each seed takes a few Philox blocks per
+// stage, direction and iteration: these are k_prep's longest work-groups)
+constexpr int RNG_SPT = 4;
 
 __device__ __forceinline__ int search_off(uint32_t u, int W, int i, int sym)
 {
@@ -1916,11 +1916,10 @@ __device__ __forceinline__ void rng_block(const RngArgs& a, int b)
 
 // ---------------------------------------------------------------------------------------
 // kernels of the image stage. k_prep starts a call with three independent jobs in one launch
-// (work-group ranges): the first pyramid levels, the level-0 gradient images and the random
-// numbers (dispatched in that order: the longest work-groups first, the random ones, which
-// need no LDS, filling in behind them); k_pyr builds the further pyramid levels and k_gradient their
-// gradient images (all levels in one launch: blockIdx.x runs over the tiles of each level in
-// turn).
+// (work-group ranges): the random numbers, the first pyramid levels and the level-0 gradient
+// images, dispatched in that order (the longest work-groups, the random ones, first); k_pyr
+// builds the further pyramid levels and k_gradient their gradient images (all levels in one
+// launch: blockIdx.x runs over the tiles of each level in turn).
 // ---------------------------------------------------------------------------------------
 
 constexpr int PREP_LDS = GR_LDS > PY_LDS ? (GR_LDS > P2_LDS ? GR_LDS : P2_LDS) : (PY_LDS > P2_LDS ? PY_LDS : P2_LDS);
@@ -1930,6 +1929,11 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
 {
     __shared__ __align__(16) uint32_t lds[PREP_LDS];
     int b = blockIdx.x;
+    if (b < a.rng_blocks) {
+        rng_block(a.rng, b);
+        return;
+    }
+    b -= a.rng_blocks;
     if (b < a.pyr_blocks) {
         if (a.pyr.two) pyr2_tile<P2Wide>(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
         else pyr_tile(a.pyr, b % a.pyr.tiles, b / a.pyr.tiles, lds);
@@ -1941,9 +1945,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a)
         int e = 0;
         while (e + 1 < a.grad.n && tt >= a.grad.lv[e + 1].base) e++;
         grad_tile<KS, GRAY, FEAT>(a.grad.lv[e], a.grad.dst_zs, tt - a.grad.lv[e].base, z, lds);
-        return;
     }
-    rng_block(a.rng, b - a.grad_blocks);
 }
 
 __global__ __launch_bounds__(256) void k_pyr(PyrArgs a)
