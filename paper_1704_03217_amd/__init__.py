@@ -81,10 +81,10 @@ EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_ma
            "pgm_last_error", "pgm_destroy")
 
 # kernel kinds of pgm_profile_read
-K_PYRAMID, K_GRADIENT, K_PREP, K_INIT, K_DOWN, K_UP, K_SWEEP, K_CHECK, K_OUTPUT, K_COMPACT, K_LEVEL, K_REGION = \
-    range(12)
+K_PYRAMID, K_GRADIENT, K_PREP, K_INIT, K_DOWN, K_UP, K_SWEEP, K_CHECK, K_OUTPUT, K_COMPACT, K_LEVEL, K_REGION, \
+    K_SWEEP_PAIR = range(13)
 KIND_NAMES = ("pyramid", "gradient", "prep", "init", "down", "up", "sweep", "check", "output", "compact", "level",
-              "region")
+              "region", "sweep_pair")
 
 
 class PGMError(RuntimeError):

@@ -26,6 +26,7 @@ struct Layout {
     size_t pyr[2][PGM_MAX_LEVELS];                       // level >= 1 RGB images
     size_t grad[4][PGM_MAX_LEVELS];                      // padded gradient images (4 slots)
     size_t disp[2][PGM_MAX_LEVELS], dist[2][PGM_MAX_LEVELS], flags[2][PGM_MAX_LEVELS];
+    size_t disp2[2][PGM_MAX_LEVELS], dist2[2][PGM_MAX_LEVELS];   // second field buffer (paired half-sweeps)
     size_t rnd = 0, rnd_init = 0;
     size_t tab = 0;                                      // PairTab entries of a table-driven batch
     // stages of the schedule
@@ -34,9 +35,9 @@ struct Layout {
     long long st_base[MAX_STAGES];                       // short2 offset of the stage's offsets
     int R_top = 0;
     // per-block evaluation counts of the matching launches, one table per kernel kind
-    // (init, down, up, sweep)
-    size_t cnt[4] = {0, 0, 0, 0};
-    long long cnt_cap[4] = {0, 0, 0, 0};
+    // (init, down, up, sweep, paired sweeps)
+    size_t cnt[5] = {0, 0, 0, 0, 0};
+    long long cnt_cap[5] = {0, 0, 0, 0, 0};
     size_t cntpart = 0;
     size_t cclabel = 0, ccsize = 0;
     // the random-number table is shared by all pairs of a batch; everything else is per pair
@@ -45,7 +46,7 @@ struct Layout {
     size_t total = 0;   // shared + one pair
 };
 
-enum { CNT_INIT = 0, CNT_DOWN = 1, CNT_UP = 2, CNT_SWEEP = 3 };
+enum { CNT_INIT = 0, CNT_DOWN = 1, CNT_UP = 2, CNT_SWEEP = 3, CNT_PAIR = 4 };
 
 // both directions share a launch when their patch sides select the same kernel variant
 int variant(int P) { return P == 8 ? 0 : P < 8 ? 1 : P == 16 ? 2 : 3; }
@@ -60,6 +61,8 @@ long long dir_blocks(const pgm_params* p, int groups)
 enum { ENTER_INIT = 0, ENTER_DOWN_F = 1, ENTER_DOWN_FO = 2, ENTER_UP_FO = 3 };
 // largest level (seeds x pairs) entered by one fused launch
 constexpr long long FUSE_MAX_SEEDS = 8192;
+// largest level (seeds x pairs) whose half-sweeps run two per launch
+constexpr long long PAIR_MAX_SEEDS = 16384;
 
 size_t take(size_t& cur, size_t bytes)
 {
@@ -187,6 +190,8 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
             Y.disp[d][l] = take(cur, n * 4);
             Y.dist[d][l] = take(cur, n * Y.dsize);
             Y.flags[d][l] = take(cur, n);
+            Y.disp2[d][l] = take(cur, n * 4);
+            Y.dist2[d][l] = take(cur, n * Y.dsize);
         }
     for (int k = 0; k < Y.nst; k++) {
         const int l = Y.st_level[k];
@@ -199,8 +204,9 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
         const long long per_sweep = variant(p->patch_fwd) == variant(p->patch_bwd) ? 2 * sb(p->patch_fwd)
                                                                                    : sb(p->patch_fwd) + sb(p->patch_bwd);
         Y.cnt_cap[CNT_SWEEP] += 2LL * p->iters[l] * per_sweep;
+        Y.cnt_cap[CNT_PAIR] += 2LL * p->iters[l] * 2 * sweep_pair_blocks(Y.lnx[l], Y.lny[l]);   // one launch per half-sweep at most
     }
-    for (int k = 0; k < 4; k++) Y.cnt[k] = take(cur, (size_t)Y.cnt_cap[k] * 4 + 4);
+    for (int k = 0; k < 5; k++) Y.cnt[k] = take(cur, (size_t)Y.cnt_cap[k] * 4 + 4);
     // partial evaluation sums of the count reduction: COUNT_SLICES x KINDS per pair
     Y.cntpart = take(cur, (size_t)COUNT_SLICES * CountArgs::KINDS * sizeof(unsigned long long));
     // region labels and sizes on the level-0 grid (small-region removal)
@@ -547,7 +553,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     // evaluation counts: each matching launch stores one count per work-group into its kind's
     // table (per pair); k_count adds them up at the end
     const bool counting = nev || c->prof || tab_counts;
-    long long cnt_off[4] = {0, 0, 0, 0};
+    long long cnt_off[5] = {0, 0, 0, 0, 0};
     auto ctable = [&](int kind, long long blocks) -> uint32_t* {
         if (!counting) return nullptr;
         uint32_t* t = (uint32_t*)(pw0 + Y.cnt[kind]) + cnt_off[kind];
@@ -654,6 +660,13 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         f.disp = (uint32_t*)(pw0 + Y.disp[d][l]);
         f.dist = pw0 + Y.dist[d][l];
         f.flags = pw0 + Y.flags[d][l];
+        return f;
+    };
+    // the second buffer of a level's field (displacements and distances; the flags are shared)
+    auto field2 = [&](int d, int l) {
+        Field f = field(d, l);
+        f.disp = (uint32_t*)(pw0 + Y.disp2[d][l]);
+        f.dist = pw0 + Y.dist2[d][l];
         return f;
     };
     auto gorigin = [&](int slot, int l) {
@@ -791,8 +804,50 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
             la.gorig = ((size_t)PAD * (Y.lw[l] + 2 * PAD) + PAD) * Y.C2 * Y.esize;
             PGM_HIP(c, timed(PGM_K_LEVEL, [&] { return launch_level(la, Y.C2, Y.kind, s); }));
         }
-        // Step 1: iterations of propagation and limited random search, red then black
+        // Step 1: iterations of propagation and limited random search, red then black. A small
+        // level's half-sweeps go two per launch (k_sweep_pair), each launch reading the field
+        // from one buffer and writing it to the other; an even number of launches ends in the
+        // level's own buffer (a pair is split into two single ones, each sweeping one colour
+        // and copying the other, where needed).
+        int hs_t[2 * 256], hs_c[2 * 256], nhs = 0;   // iterations are at most 255
         for (int t = 0; t < (in_lds ? 0 : p->iters[l]); t++)
+            for (int colour = ((fuse == 1 || fuse == 3) && t == 0) ? 1 : 0; colour < 2; colour++) {
+                hs_t[nhs] = t;
+                hs_c[nhs++] = colour;
+            }
+        const bool paired = shared && nhs >= 2 && std::max(p->patch_fwd, p->patch_bwd) <= 8 &&
+                            !(c->sched & PGM_SCHED_SEPARATE) && (long long)g.nx * g.ny * npairs <= PAIR_MAX_SEEDS;
+        if (paired) {
+            int sizes[2 * 256 + 1], nl = 0;   // half-sweeps per launch
+            for (int h = 0; h < nhs; h += 2) sizes[nl++] = nhs - h >= 2 ? 2 : 1;
+            if (nl & 1) {   // split the last pair
+                int last = nl - 1;
+                while (sizes[last] != 2) last--;
+                for (int q = nl; q > last + 1; q--) sizes[q] = sizes[q - 1];
+                sizes[last] = sizes[last + 1] = 1;
+                nl++;
+            }
+            for (int L2 = 0, h = 0; L2 < nl; L2++) {
+                SweepPairArgs a;
+                memset(&a, 0, sizeof a);
+                for (int q = 0; q < 2; q++) {
+                    a.d[q] = dirargs(q, l, k);
+                    a.d[q].f = (L2 & 1) ? field2(q, l) : field(q, l);
+                    a.out[q] = (L2 & 1) ? field(q, l) : field2(q, l);
+                }
+                a.g = g;
+                a.b = batch(2);
+                a.t1 = hs_t[h];
+                a.c1 = hs_c[h];
+                a.second = sizes[L2] == 2;
+                a.t2 = a.second ? hs_t[h + 1] : a.t1;
+                a.nI = Y.st_nI[k];
+                a.cnt = ctable(CNT_PAIR, 2LL * sweep_pair_blocks(g.nx, g.ny));
+                PGM_HIP(c, timed(PGM_K_SWEEP_PAIR, [&] { return launch_sweep_pair(a, Y.C2, Y.kind, s); }));
+                h += sizes[L2];
+            }
+        }
+        for (int t = 0; t < (in_lds || paired ? 0 : p->iters[l]); t++)
             for (int colour = ((fuse == 1 || fuse == 3) && t == 0) ? 1 : 0; colour < 2; colour++)
                 for (int pass = 0; pass < (shared ? 1 : 2); pass++) {
                     const int nd = shared ? 2 : 1;
@@ -853,8 +908,8 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     PGM_HIP(c, close_run());
     if (counting) {
         CountArgs ca;
-        const int kinds[4] = {PGM_K_INIT, PGM_K_DOWN, PGM_K_UP, PGM_K_SWEEP};
-        for (int k = 0; k < 4; k++) {
+        const int kinds[5] = {PGM_K_INIT, PGM_K_DOWN, PGM_K_UP, PGM_K_SWEEP, PGM_K_SWEEP_PAIR};
+        for (int k = 0; k < 5; k++) {
             ca.table[k] = (const uint32_t*)(pw0 + Y.cnt[k]);
             ca.n[k] = cnt_off[k];
             ca.kind[k] = kinds[k];

@@ -473,13 +473,13 @@ __device__ __forceinline__ void count_evals(uint32_t* cnt, int slot, uint32_t ne
 
 // Step 1 after the propagation members are priced: the decisions of Eq. 4 in order, then the
 // limited random search of Eq. 5 around the result (Psi = {F(p)} + {F(p) + floor(R_i W / 2^i)},
-// priced two at a time and decided in order). Returns the evaluations counted; lane 0 writes
-// the seed if it changed (or always, with store).
-template <class Row, int LPS, bool BUF>
-__device__ __forceinline__ uint32_t decide_and_search(const Row& A, const DirArgs& D, const Geo& g, int s, int px,
-                                                      int py, int r, const short2* R, int nI, short2 o0, short2 o1,
+// priced two at a time and decided in order). Returns the evaluations counted; lane 0 hands
+// the result to put(displacement, distance, changed).
+template <class Row, int LPS, bool BUF, class Put>
+__device__ __forceinline__ uint32_t decide_and_search(const Row& A, const DirArgs& D, const Geo& g, int px, int py,
+                                                      int r, const short2* R, int nI, short2 o0, short2 o1,
                                                       uint32_t cur0, typename Row::Dist cd0, const uint32_t c[2],
-                                                      const bool ok[2], const typename Row::Dist e[2], bool store)
+                                                      const bool ok[2], const typename Row::Dist e[2], Put put)
 {
     using Dist = typename Row::Dist;
     const int P = D.P;
@@ -530,36 +530,69 @@ __device__ __forceinline__ uint32_t decide_and_search(const Row& A, const DirArg
             }
         }
     }
-    if ((changed || store) && r == 0) {
-        D.f.disp[s] = cur;
-        ((Dist*)D.f.dist)[s] = cd;
-    }
+    if (r == 0) put(cur, cd, changed);
     return nev;
 }
 
-// One seed's half-sweep step (Step 1): propagation (Eq. 4) then limited random search
-// (Eq. 5) for seed (i, j) of field D at iteration t; returns the distance evaluations made.
-// The group's lanes all call it for the same seed; lane 0 writes the result.
-template <class Row, int LPS, bool BUF>
-__device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, int i, int j, int t, int nI, int r)
-{
-    uint32_t nev = 0;
-    const int s = j * g.nx + i;
-    const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
-    const int P = D.P;
-    Row A;
-    load_own<BUF>(A, D.Ga, g, P, r, px, py);
-    using Dist = typename Row::Dist;
-    Dist* const dist = (Dist*)D.f.dist;
-    const uint32_t cur0 = D.f.disp[s];
-    const Dist cd0 = dist[s];
-    const bool init0 = cur0 != UNINIT;
-    // Eq. 5 offsets of the first two random candidates (nI >= 1), fetched with the field;
-    // the neighbours' fields are read from clamped indices and masked, so that every read
-    // of this phase is in flight at once
-    const short2* R = D.rnd + ((size_t)t * (size_t)(g.nx * g.ny) + s) * nI;
-    short2 o0 = R[0], o1 = R[nI > 1 ? 1 : 0];
+// lane 0's write of a seed's result into field f: always, or only when it changed
+template <class Dist>
+struct PutSeed {
+    Field f;
+    int s;
+    bool always;
+    __device__ __forceinline__ void operator()(uint32_t cur, Dist cd, bool changed) const
+    {
+        if (changed || always) {
+            f.disp[s] = cur;
+            ((Dist*)f.dist)[s] = cd;
+        }
+    }
+};
 
+// One seed's half-sweep step (Step 1): propagation (Eq. 4) then limited random search
+// (Eq. 5) for seed (i, j) of field D at iteration t. seed_start issues the reads that need
+// nothing from other seeds (the seed's first-image patch, its own field, its first two random
+// offsets); seed_finish takes the propagation members' displacements from nbr(i', j')
+// (called for positions outside the grid too, whose value is then ignored), prices and
+// decides, and returns the distance evaluations made. The group's lanes all call both for
+// the same seed; lane 0 hands the result to put.
+template <class Row>
+struct SeedStart {
+    Row A;
+    uint32_t cur0;
+    typename Row::Dist cd0;
+    const short2* R;
+    short2 o0, o1;
+    int s, px, py;
+};
+
+template <class Row, int LPS, bool BUF>
+__device__ __forceinline__ void seed_start(SeedStart<Row>& S, const DirArgs& D, const Geo& g, int i, int j, int t,
+                                           int nI, int r)
+{
+    using Dist = typename Row::Dist;
+    S.s = j * g.nx + i;
+    S.px = grid_pos(i, g.w, g);
+    S.py = grid_pos(j, g.h, g);
+    load_own<BUF>(S.A, D.Ga, g, D.P, r, S.px, S.py);
+    S.cur0 = D.f.disp[S.s];
+    S.cd0 = ((const Dist*)D.f.dist)[S.s];
+    // Eq. 5 offsets of the first two random candidates (nI >= 1), fetched with the field
+    S.R = D.rnd + ((size_t)t * (size_t)(g.nx * g.ny) + S.s) * nI;
+    S.o0 = S.R[0];
+    S.o1 = S.R[nI > 1 ? 1 : 0];
+}
+
+template <class Row, int LPS, bool BUF, class Nbr, class Put>
+__device__ __forceinline__ uint32_t seed_finish(const SeedStart<Row>& S, const DirArgs& D, const Geo& g, int i, int j,
+                                                int t, int nI, int r, Nbr nbr, Put put)
+{
+    using Dist = typename Row::Dist;
+    const int P = D.P;
+    const int px = S.px, py = S.py;
+    const uint32_t cur0 = S.cur0;
+    const Dist cd0 = S.cd0;
+    const bool init0 = cur0 != UNINIT;
     // Eq. 4: Omega = {F(p), F(p - Dx) + Dx, F(p - Dy) + Dy} with the FlowFields order
     // (1,0),(0,1) -> (-1,0),(0,-1) -> (-1,0),(0,1) -> (1,0),(0,-1); members whose
     // neighbour is uninitialised are ignored.
@@ -573,7 +606,7 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
         const int ni = m == 0 ? i - sx : i;
         const int nj = m == 0 ? j : j - sy;
         ok[m] = ni >= 0 && nj >= 0 && ni < g.nx && nj < g.ny;
-        nv[m] = D.f.disp[clampi(nj, 0, g.ny - 1) * g.nx + clampi(ni, 0, g.nx - 1)];
+        nv[m] = nbr(ni, nj);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -591,12 +624,33 @@ __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, i
     if (need0 || need1) {
         const uint32_t qa = need0 ? c[0] : c[1], qb = need1 ? c[1] : c[0];
         Dist ea, eb;
-        patch_cost_some<Row, LPS, BUF>(A, D.Gb, g, P, r, px, py, qa, qb, need0 && need1, ea, eb);
+        patch_cost_some<Row, LPS, BUF>(S.A, D.Gb, g, P, r, px, py, qa, qb, need0 && need1, ea, eb);
         if (need0) e[0] = ea;
         if (need1) e[1] = eb;
     }
     if (ok[1] && !need1 && !(init0 && c[1] == cur0)) e[1] = e[0];
-    return nev + decide_and_search<Row, LPS, BUF>(A, D, g, s, px, py, r, R, nI, o0, o1, cur0, cd0, c, ok, e, false);
+    return decide_and_search<Row, LPS, BUF>(S.A, D, g, px, py, r, S.R, nI, S.o0, S.o1, cur0, cd0, c, ok, e, put);
+}
+
+template <class Row, int LPS, bool BUF, class Nbr, class Put>
+__device__ __forceinline__ uint32_t sweep_seed_with(const DirArgs& D, const Geo& g, int i, int j, int t, int nI, int r,
+                                                    Nbr nbr, Put put)
+{
+    SeedStart<Row> S;
+    seed_start<Row, LPS, BUF>(S, D, g, i, j, t, nI, r);
+    return seed_finish<Row, LPS, BUF>(S, D, g, i, j, t, nI, r, nbr, put);
+}
+
+// the half-sweep step in place: neighbours from the field itself (read from clamped indices
+// and masked, so that every read of the phase is in flight at once), a changed seed written back
+template <class Row, int LPS, bool BUF>
+__device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, int i, int j, int t, int nI, int r)
+{
+    const uint32_t* disp = D.f.disp;
+    return sweep_seed_with<Row, LPS, BUF>(
+        D, g, i, j, t, nI, r,
+        [=](int ni, int nj) { return disp[clampi(nj, 0, g.ny - 1) * g.nx + clampi(ni, 0, g.nx - 1)]; },
+        PutSeed<typename Row::Dist>{D.f, j * g.nx + i, false});
 }
 
 // one half-sweep (Step 1, one colour of one iteration) of every seed of the launch
@@ -618,6 +672,96 @@ __global__ __launch_bounds__(MATCH_TPB) void k_sweep(SweepArgs a)
     const int i = 2 * (gid - j * hx) + ((a.colour + j) & 1);
     uint32_t nev = 0;
     if (j < g.ny && i < g.nx) nev = sweep_seed<Row, LPS, true>(D, g, i, j, a.t, a.nI, r);
+    count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, r == 0);
+}
+
+// ---------------------------------------------------------------------------------------
+// two consecutive half-sweeps of a small level in one launch (Step 1 of Sec. III-B, twice)
+// ---------------------------------------------------------------------------------------
+
+// Work-group (x0, y0) owns a PAIR_TX x PAIR_TY tile of seeds, one 8-lane group per seed. The
+// field is read only from the input buffer, which no work-group of the launch writes, and the
+// tile is written whole to the output buffer. First pass: the tile's seeds of colour c1 at
+// iteration t1 and, when the second half-sweep runs, the seeds of that colour in the column
+// and the row just outside the tile that the second half-sweep's propagation members come
+// from (their results stay in LDS). Second pass: the tile's seeds of the other colour at
+// iteration t2, their propagation members from LDS, or copied unchanged (second = 0). Every
+// seed thus sees exactly the field that the two half-sweeps in sequence give it, and only the
+// tile's own seeds are counted.
+template <int C2, int PMAX, bool FIXED, int KIND>
+__global__ __launch_bounds__(PAIR_TPB) void k_sweep_pair(SweepPairArgs a)
+{
+    static_assert(PMAX == 8, "eight lanes per seed");
+    using Row = RowT<C2, PMAX, FIXED, KIND>;
+    using Dist = typename Row::Dist;
+    constexpr int LPS = PMAX;
+    constexpr int EX = PAIR_TX + 2;                // row length of the tile and its border in LDS
+    constexpr int HALF = PAIR_TX * PAIR_TY / 2;     // seeds of one colour in a tile
+    static_assert(PAIR_TX % 2 == 0 && PAIR_TY % 2 == 0 && HALF + PAIR_TX / 2 + PAIR_TY / 2 <= PAIR_TPB / LPS,
+                  "one pass per colour");
+    __shared__ uint32_t first[(PAIR_TY + 2) * EX];   // first-pass displacements
+    const Geo& g = a.g;
+    const int tiles_x = (g.nx + PAIR_TX - 1) / PAIR_TX;
+    const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
+    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
+    const DirArgs D = pair_dir(a.d[lb.dir], zo);
+    const Field out = pair_field(a.out[lb.dir], zo);
+    const int x0 = (lb.x % tiles_x) * PAIR_TX, y0 = (lb.x / tiles_x) * PAIR_TY;
+    const int r = threadIdx.x % LPS, grp = threadIdx.x / LPS;
+    // the second half-sweep's propagation members are (i - sx, j) and (i, j - sy)
+    const int k2 = a.t2 & 3;
+    const int sx = (k2 == 0 || k2 == 3) ? 1 : -1, sy = (k2 == 0 || k2 == 2) ? 1 : -1;
+    uint32_t nev = 0;
+    {
+        int i = -1, j = -1;
+        bool own = false;
+        if (grp < HALF) {
+            j = y0 + grp / (PAIR_TX / 2);
+            i = x0 + 2 * (grp % (PAIR_TX / 2)) + ((a.c1 + j + x0) & 1);
+            own = true;
+        } else if (a.second && grp < HALF + PAIR_TY / 2) {   // the look-back column
+            i = sx == 1 ? x0 - 1 : x0 + PAIR_TX;
+            j = y0 + 2 * (grp - HALF) + ((a.c1 + i + y0) & 1);
+        } else if (a.second && grp < HALF + PAIR_TY / 2 + PAIR_TX / 2) {   // the look-back row
+            j = sy == 1 ? y0 - 1 : y0 + PAIR_TY;
+            i = x0 + 2 * (grp - HALF - PAIR_TY / 2) + ((a.c1 + j + x0) & 1);
+        }
+        if (i >= 0 && j >= 0 && i < g.nx && j < g.ny) {
+            const uint32_t* disp = D.f.disp;
+            const int s = j * g.nx + i;
+            const int slot = (j - y0 + 1) * EX + (i - x0 + 1);
+            const uint32_t n = sweep_seed_with<Row, LPS, true>(
+                D, g, i, j, a.t1, a.nI, r,
+                [=](int ni, int nj) { return disp[clampi(nj, 0, g.ny - 1) * g.nx + clampi(ni, 0, g.nx - 1)]; },
+                [&](uint32_t cur, Dist cd, bool) {
+                    first[slot] = cur;
+                    if (own) {
+                        out.disp[s] = cur;
+                        ((Dist*)out.dist)[s] = cd;
+                    }
+                });
+            if (own) nev += n;
+        }
+    }
+    // the second pass's reads that need nothing from the first are issued before the barrier
+    const int j2 = y0 + grp / (PAIR_TX / 2);
+    const int i2 = x0 + 2 * (grp % (PAIR_TX / 2)) + ((1 - a.c1 + j2 + x0) & 1);
+    const bool second = a.second && grp < HALF && i2 < g.nx && j2 < g.ny;
+    SeedStart<Row> S2;
+    if (second) seed_start<Row, LPS, true>(S2, D, g, i2, j2, a.t2, a.nI, r);
+    __syncthreads();
+    if (second) {
+        // (ni, nj) lies in the tile or its border: seeds of colour c1 priced above (or
+        // outside the grid, where the value is ignored)
+        nev += seed_finish<Row, LPS, true>(S2, D, g, i2, j2, a.t2, a.nI, r,
+                                           [&](int ni, int nj) { return first[(nj - y0 + 1) * EX + (ni - x0 + 1)]; },
+                                           PutSeed<Dist>{out, S2.s, true});
+    } else if (!a.second && grp < HALF && i2 < g.nx && j2 < g.ny && r == 0) {
+        const int s = j2 * g.nx + i2;
+        out.disp[s] = D.f.disp[s];
+        ((Dist*)out.dist)[s] = ((const Dist*)D.f.dist)[s];
+    }
     count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, r == 0);
 }
 
@@ -938,7 +1082,8 @@ __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs
         e[1] = cd0;
     }
     if (ok[1] && !need1 && !(init0 && c[1] == cur0)) e[1] = e[0];
-    return nev + decide_and_search<Row, LPS, true>(A, D, g, s, px, py, r, R, a.nI, o0, o1, cur0, cd0, c, ok, e, true);
+    return nev + decide_and_search<Row, LPS, true>(A, D, g, px, py, r, R, a.nI, o0, o1, cur0, cd0, c, ok, e,
+                                                   PutSeed<Dist>{D.f, s, true});
 }
 
 template <int C2, int PMAX, bool FIXED, int KIND, bool SWEEP, bool INIT>
@@ -2079,6 +2224,27 @@ hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hi
 hipError_t launch_sweep(const SweepArgs& a, int C2, int kind, hipStream_t s)
 {
     PGM_DISPATCH(k_sweep, a, a.g.ny * ((a.g.nx + 1) / 2));
+}
+
+hipError_t launch_sweep_pair(const SweepPairArgs& a, int C2, int kind, hipStream_t s)
+{
+    const int P = a.d[0].P;
+    if (P > 8 || a.d[1].P > 8 || a.c1 < 0 || a.c1 > 1) return hipErrorInvalidValue;
+    const bool fixed = P == 8;
+    const long long nb = (long long)sweep_pair_blocks(a.g.nx, a.g.ny) * a.b.ndir * a.b.npairs;
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nb);
+#define PGM_PAIR(C2_, FX_)                                                                              \
+    if (C2 == C2_ && fixed == FX_) {                                                                     \
+        if (kind == 1) hipLaunchKernelGGL((k_sweep_pair<C2_, 8, FX_, 1>), grid, dim3(PAIR_TPB), 0, s, a);  \
+        else if (kind == 2) hipLaunchKernelGGL((k_sweep_pair<C2_, 8, FX_, 2>), grid, dim3(PAIR_TPB), 0, s, a); \
+        else hipLaunchKernelGGL((k_sweep_pair<C2_, 8, FX_, 0>), grid, dim3(PAIR_TPB), 0, s, a);            \
+        return hipGetLastError();                                                                        \
+    }
+    PGM_PAIR(6, true) PGM_PAIR(6, false) PGM_PAIR(2, true) PGM_PAIR(2, false)
+#undef PGM_PAIR
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_init(const InitArgs& a, int C2, int kind, hipStream_t s)
