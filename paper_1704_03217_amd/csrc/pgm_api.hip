@@ -26,7 +26,7 @@ struct Layout {
     size_t pyr[2][PGM_MAX_LEVELS];                       // level >= 1 RGB images
     size_t grad[4][PGM_MAX_LEVELS];                      // padded gradient images (4 slots)
     size_t disp[2][PGM_MAX_LEVELS], dist[2][PGM_MAX_LEVELS], flags[2][PGM_MAX_LEVELS];
-    size_t disp2[2][PGM_MAX_LEVELS], dist2[2][PGM_MAX_LEVELS];   // second field buffer (paired half-sweeps)
+    size_t disp2[2][PGM_MAX_LEVELS], dist2[2][PGM_MAX_LEVELS];   // second field buffer (k_sweep_multi)
     size_t rnd = 0, rnd_init = 0;
     size_t tab = 0;                                      // PairTab entries of a table-driven batch
     // stages of the schedule
@@ -35,7 +35,7 @@ struct Layout {
     long long st_base[MAX_STAGES];                       // short2 offset of the stage's offsets
     int R_top = 0;
     // per-block evaluation counts of the matching launches, one table per kernel kind
-    // (init, down, up, sweep, paired sweeps)
+    // (init, down, up, sweep, multi-sweep launches)
     size_t cnt[5] = {0, 0, 0, 0, 0};
     long long cnt_cap[5] = {0, 0, 0, 0, 0};
     size_t cntpart = 0;
@@ -46,7 +46,7 @@ struct Layout {
     size_t total = 0;   // shared + one pair
 };
 
-enum { CNT_INIT = 0, CNT_DOWN = 1, CNT_UP = 2, CNT_SWEEP = 3, CNT_PAIR = 4 };
+enum { CNT_INIT = 0, CNT_DOWN = 1, CNT_UP = 2, CNT_SWEEP = 3, CNT_MULTI = 4 };
 
 // both directions share a launch when their patch sides select the same kernel variant
 int variant(int P) { return P == 8 ? 0 : P < 8 ? 1 : P == 16 ? 2 : 3; }
@@ -61,8 +61,8 @@ long long dir_blocks(const pgm_params* p, int groups)
 enum { ENTER_INIT = 0, ENTER_DOWN_F = 1, ENTER_DOWN_FO = 2, ENTER_UP_FO = 3 };
 // largest level (seeds x pairs) entered by one fused launch
 constexpr long long FUSE_MAX_SEEDS = 8192;
-// largest level (seeds x pairs) whose half-sweeps run two per launch
-constexpr long long PAIR_MAX_SEEDS = 16384;
+// largest level (seeds x pairs) whose half-sweeps run several per launch
+constexpr long long MULTI_MAX_SEEDS = 8192;
 
 size_t take(size_t& cur, size_t bytes)
 {
@@ -204,7 +204,7 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
         const long long per_sweep = variant(p->patch_fwd) == variant(p->patch_bwd) ? 2 * sb(p->patch_fwd)
                                                                                    : sb(p->patch_fwd) + sb(p->patch_bwd);
         Y.cnt_cap[CNT_SWEEP] += 2LL * p->iters[l] * per_sweep;
-        Y.cnt_cap[CNT_PAIR] += 2LL * p->iters[l] * 2 * sweep_pair_blocks(Y.lnx[l], Y.lny[l]);   // one launch per half-sweep at most
+        Y.cnt_cap[CNT_MULTI] += 2LL * p->iters[l] * 2 * sweep_multi_blocks(Y.lnx[l], Y.lny[l]);   // one launch per half-sweep at most
     }
     for (int k = 0; k < 5; k++) Y.cnt[k] = take(cur, (size_t)Y.cnt_cap[k] * 4 + 4);
     // partial evaluation sums of the count reduction: COUNT_SLICES x KINDS per pair
@@ -733,12 +733,45 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         const Geo g = geo(l);
         const int enter = Y.st_enter[k];
         const int fuse = fused(k);
+        LevelArgs la;
+        memset(&la, 0, sizeof la);
+        const bool in_lds = lds_level(k, la.lay);
+        // Step 1's half-sweeps (iteration, colour), red then black. A small level's run
+        // several per launch (k_sweep_multi), each launch reading the field from one buffer
+        // and writing it whole to the other: chunks of 4, the rest as 2 or 3. With an odd
+        // number of launches the level's entry writes the second buffer, so that the last
+        // launch writes the level's own.
+        int hs_t[2 * 256], hs_c[2 * 256], nhs = 0;   // iterations are at most 255
+        for (int t = 0; t < (in_lds ? 0 : p->iters[l]); t++)
+            for (int colour = ((fuse == 1 || fuse == 3) && t == 0) ? 1 : 0; colour < 2; colour++) {
+                hs_t[nhs] = t;
+                hs_c[nhs++] = colour;
+            }
+        const bool multi = shared && nhs >= 2 && std::max(p->patch_fwd, p->patch_bwd) <= 8 &&
+                           !(c->sched & PGM_SCHED_SEPARATE) && (long long)g.nx * g.ny * npairs <= MULTI_MAX_SEEDS;
+        int chunk[2 * 256], nch = 0;
+        if (multi) {
+            for (int h = 0; h + 4 <= nhs; h += 4) chunk[nch++] = 4;
+            const int rest = nhs % 4;
+            if (rest == 1) {   // 4 + 1 as 3 + 2
+                chunk[nch - 1] = 3;
+                chunk[nch++] = 2;
+            } else if (rest) {
+                chunk[nch++] = rest;
+            }
+        }
+        const bool entry_second = multi && (nch & 1);
+        auto entry_dir = [&](int d) {
+            DirArgs a = dirargs(d, l, k);
+            if (entry_second) a.f = field2(d, l);
+            return a;
+        };
         if (fuse) {
             const bool init = fuse == 3;
             EnterArgs ea;
             memset(&ea, 0, sizeof ea);
             for (int q = 0; q < 2; q++) {
-                ea.d[q] = dirargs(q, l, k);
+                ea.d[q] = entry_dir(q);
                 if (!init) ea.src[q] = field(q, l + 1);
             }
             ea.g = g;
@@ -760,7 +793,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
             if (enter == ENTER_INIT) {
                 InitArgs a;
                 memset(&a, 0, sizeof a);
-                for (int q = 0; q < nd; q++) a.d[q] = dirargs(d0 + q, l, k);
+                for (int q = 0; q < nd; q++) a.d[q] = entry_dir(d0 + q);
                 a.g = g;
                 a.b = batch(nd);
                 a.exhaustive = p->init_mode == PGM_INIT_EXHAUSTIVE;
@@ -772,7 +805,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
                 memset(&a, 0, sizeof a);
                 const int src = enter == ENTER_UP_FO ? l - 1 : l + 1;
                 for (int q = 0; q < nd; q++) {
-                    a.d[q] = dirargs(d0 + q, l, k);
+                    a.d[q] = entry_dir(d0 + q);
                     a.src[q] = field(d0 + q, src);
                 }
                 a.g = g;
@@ -790,9 +823,6 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
             }
         }
         // Step 1 of a small level in one work-group per pair and direction, from LDS
-        LevelArgs la;
-        memset(&la, 0, sizeof la);
-        const bool in_lds = lds_level(k, la.lay);
         if (in_lds) {
             for (int q = 0; q < 2; q++) la.d[q] = dirargs(q, l, k);
             la.g = g;
@@ -804,50 +834,29 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
             la.gorig = ((size_t)PAD * (Y.lw[l] + 2 * PAD) + PAD) * Y.C2 * Y.esize;
             PGM_HIP(c, timed(PGM_K_LEVEL, [&] { return launch_level(la, Y.C2, Y.kind, s); }));
         }
-        // Step 1: iterations of propagation and limited random search, red then black. A small
-        // level's half-sweeps go two per launch (k_sweep_pair), each launch reading the field
-        // from one buffer and writing it to the other; an even number of launches ends in the
-        // level's own buffer (a pair is split into two single ones, each sweeping one colour
-        // and copying the other, where needed).
-        int hs_t[2 * 256], hs_c[2 * 256], nhs = 0;   // iterations are at most 255
-        for (int t = 0; t < (in_lds ? 0 : p->iters[l]); t++)
-            for (int colour = ((fuse == 1 || fuse == 3) && t == 0) ? 1 : 0; colour < 2; colour++) {
-                hs_t[nhs] = t;
-                hs_c[nhs++] = colour;
+        bool second = entry_second;   // which buffer holds the field
+        for (int q = 0, h = 0; q < nch; q++) {
+            SweepMultiArgs a;
+            memset(&a, 0, sizeof a);
+            for (int d = 0; d < 2; d++) {
+                a.d[d] = dirargs(d, l, k);
+                a.d[d].f = second ? field2(d, l) : field(d, l);
+                a.out[d] = second ? field(d, l) : field2(d, l);
             }
-        const bool paired = shared && nhs >= 2 && std::max(p->patch_fwd, p->patch_bwd) <= 8 &&
-                            !(c->sched & PGM_SCHED_SEPARATE) && (long long)g.nx * g.ny * npairs <= PAIR_MAX_SEEDS;
-        if (paired) {
-            int sizes[2 * 256 + 1], nl = 0;   // half-sweeps per launch
-            for (int h = 0; h < nhs; h += 2) sizes[nl++] = nhs - h >= 2 ? 2 : 1;
-            if (nl & 1) {   // split the last pair
-                int last = nl - 1;
-                while (sizes[last] != 2) last--;
-                for (int q = nl; q > last + 1; q--) sizes[q] = sizes[q - 1];
-                sizes[last] = sizes[last + 1] = 1;
-                nl++;
+            a.g = g;
+            a.b = batch(2);
+            a.nph = chunk[q];
+            for (int m = 0; m < a.nph; m++) {
+                a.t[m] = hs_t[h + m];
+                a.c[m] = hs_c[h + m];
             }
-            for (int L2 = 0, h = 0; L2 < nl; L2++) {
-                SweepPairArgs a;
-                memset(&a, 0, sizeof a);
-                for (int q = 0; q < 2; q++) {
-                    a.d[q] = dirargs(q, l, k);
-                    a.d[q].f = (L2 & 1) ? field2(q, l) : field(q, l);
-                    a.out[q] = (L2 & 1) ? field(q, l) : field2(q, l);
-                }
-                a.g = g;
-                a.b = batch(2);
-                a.t1 = hs_t[h];
-                a.c1 = hs_c[h];
-                a.second = sizes[L2] == 2;
-                a.t2 = a.second ? hs_t[h + 1] : a.t1;
-                a.nI = Y.st_nI[k];
-                a.cnt = ctable(CNT_PAIR, 2LL * sweep_pair_blocks(g.nx, g.ny));
-                PGM_HIP(c, timed(PGM_K_SWEEP_PAIR, [&] { return launch_sweep_pair(a, Y.C2, Y.kind, s); }));
-                h += sizes[L2];
-            }
+            a.nI = Y.st_nI[k];
+            a.cnt = ctable(CNT_MULTI, 2LL * sweep_multi_blocks(g.nx, g.ny));
+            PGM_HIP(c, timed(PGM_K_SWEEP_MULTI, [&] { return launch_sweep_multi(a, Y.C2, Y.kind, s); }));
+            h += chunk[q];
+            second = !second;
         }
-        for (int t = 0; t < (in_lds || paired ? 0 : p->iters[l]); t++)
+        for (int t = 0; t < (in_lds || multi ? 0 : p->iters[l]); t++)
             for (int colour = ((fuse == 1 || fuse == 3) && t == 0) ? 1 : 0; colour < 2; colour++)
                 for (int pass = 0; pass < (shared ? 1 : 2); pass++) {
                     const int nd = shared ? 2 : 1;
@@ -908,7 +917,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     PGM_HIP(c, close_run());
     if (counting) {
         CountArgs ca;
-        const int kinds[5] = {PGM_K_INIT, PGM_K_DOWN, PGM_K_UP, PGM_K_SWEEP, PGM_K_SWEEP_PAIR};
+        const int kinds[5] = {PGM_K_INIT, PGM_K_DOWN, PGM_K_UP, PGM_K_SWEEP, PGM_K_SWEEP_MULTI};
         for (int k = 0; k < 5; k++) {
             ca.table[k] = (const uint32_t*)(pw0 + Y.cnt[k]);
             ca.n[k] = cnt_off[k];

@@ -80,15 +80,15 @@ struct SweepArgs {
     uint32_t* cnt;         // per-block evaluation counts of this launch, pair 0 (or null)
 };
 
-// Two consecutive half-sweeps in one launch, the field read from one buffer (d[].f) and
-// written whole to another (out[]): the seeds of colour c1 at iteration t1, then those of the
-// other colour at iteration t2 (or, with second = 0, the other colour copied unchanged).
-struct SweepPairArgs {
+// Two to four consecutive half-sweeps of one level in one launch, the field read from one
+// buffer (d[].f) and written whole to another (out[]): half-sweep m updates the seeds of colour
+// c[m] at iteration t[m] (the colours alternate).
+struct SweepMultiArgs {
     DirArgs d[2];
     Field out[2];          // disp and dist of the output buffer of each direction, pair 0
     Geo g;
     Batch b;
-    int t1, c1, t2, second, nI;
+    int nph, t[4], c[4], nI;
     uint32_t* cnt;         // per-block evaluation counts of this launch, pair 0 (or null)
 };
 
@@ -176,7 +176,7 @@ struct RngArgs {
 };
 
 struct CountArgs {
-    static constexpr int KINDS = 5;      // init, down, up, sweep, paired sweeps
+    static constexpr int KINDS = 5;      // init, down, up, sweep, multi-sweep launches
     const uint32_t* table[KINDS];        // pair 0
     long long n[KINDS];
     int npairs;
@@ -206,14 +206,11 @@ inline int match_blocks(int groups, int P)
 // Work-groups of one half-sweep launch per direction and pair.
 inline int sweep_blocks(int nx, int ny, int P) { return match_blocks(ny * ((nx + 1) / 2), P); }
 
-// Tiles of seeds of a launch of two half-sweeps (four-wave work-groups, patch sides <= 8):
-// with its look-back column and row, a tile's first-colour seeds fill one pass of 32 seed
-// groups (24 + 4 + 3) and its second-colour seeds a second pass.
-constexpr int PAIR_TX = 6, PAIR_TY = 8, PAIR_TPB = 256;
-inline int sweep_pair_blocks(int nx, int ny)
-{
-    return ((nx + PAIR_TX - 1) / PAIR_TX) * ((ny + PAIR_TY - 1) / PAIR_TY);
-}
+// Tiles of seeds of a launch of several half-sweeps (four-wave work-groups of 32 seed groups,
+// patch sides <= 8): 4 x 6 seeds, so that the rectangle of the first of up to four half-sweeps
+// (7 x 9 seeds) holds at most 32 seeds of its colour.
+constexpr int PAIR_TPB = 256;
+inline int sweep_multi_blocks(int nx, int ny) { return ((nx + 3) / 4) * ((ny + 5) / 6); }
 
 // Launch wrappers (pgm_kernels.hip). Each returns hipSuccess or the launch error.
 // Per-image pointers are those of pair 0; pair z's source is src_zs bytes further and its
@@ -259,7 +256,7 @@ hipError_t launch_pyr(PyrArgs a, int npairs, hipStream_t s);
 hipError_t launch_gradient(GradArgs a, int npairs, int gray, int ksize, int feat, hipStream_t s);
 hipError_t launch_init(const InitArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_sweep(const SweepArgs& a, int C2, int kind, hipStream_t s);
-hipError_t launch_sweep_pair(const SweepPairArgs& a, int C2, int kind, hipStream_t s);
+hipError_t launch_sweep_multi(const SweepMultiArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_down(const TransArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_up(const TransArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);

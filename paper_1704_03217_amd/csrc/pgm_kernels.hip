@@ -676,91 +676,125 @@ __global__ __launch_bounds__(MATCH_TPB) void k_sweep(SweepArgs a)
 }
 
 // ---------------------------------------------------------------------------------------
-// two consecutive half-sweeps of a small level in one launch (Step 1 of Sec. III-B, twice)
+// consecutive half-sweeps of a small level in one launch (Step 1 of Sec. III-B, 2-4 times)
 // ---------------------------------------------------------------------------------------
 
-// Work-group (x0, y0) owns a PAIR_TX x PAIR_TY tile of seeds, one 8-lane group per seed. The
-// field is read only from the input buffer, which no work-group of the launch writes, and the
-// tile is written whole to the output buffer. First pass: the tile's seeds of colour c1 at
-// iteration t1 and, when the second half-sweep runs, the seeds of that colour in the column
-// and the row just outside the tile that the second half-sweep's propagation members come
-// from (their results stay in LDS). Second pass: the tile's seeds of the other colour at
-// iteration t2, their propagation members from LDS, or copied unchanged (second = 0). Every
-// seed thus sees exactly the field that the two half-sweeps in sequence give it, and only the
-// tile's own seeds are counted.
+// Work-group (x0, y0) owns a MULTI_TX x MULTI_TY tile of seeds, one 8-lane group per seed.
+// Half-sweep m = 0 .. nph-1 updates the seeds of colour c[m] at iteration t[m] inside a
+// rectangle R_m: R_{nph-1} is the tile, and R_m is R_{m+1} grown by one seed on the sides that
+// half-sweep m+1's propagation looks back to, so that every member it reads lies in R_m. The
+// first half-sweep reads the field from the input buffer (which no work-group of the launch
+// writes), the second its own seeds' values from there too; everything else comes from the
+// results of the earlier half-sweeps, kept in LDS per colour over R_0. Every seed thus sees
+// exactly the field that the half-sweeps in sequence give it. Only the tile's seeds are
+// counted, and they are written to the output buffer after the last half-sweep of their
+// colour, so the launch writes the whole field once.
+constexpr int MULTI_TX = 4, MULTI_TY = 6, MULTI_MAXPH = 4;
+constexpr int MULTI_W = MULTI_TX + MULTI_MAXPH - 1, MULTI_H = MULTI_TY + MULTI_MAXPH - 1;
+static_assert((MULTI_W * MULTI_H + 1) / 2 <= PAIR_TPB / 8, "every half-sweep of a tile in one pass");
+
 template <int C2, int PMAX, bool FIXED, int KIND>
-__global__ __launch_bounds__(PAIR_TPB) void k_sweep_pair(SweepPairArgs a)
+__global__ __launch_bounds__(PAIR_TPB) void k_sweep_multi(SweepMultiArgs a)
 {
     static_assert(PMAX == 8, "eight lanes per seed");
     using Row = RowT<C2, PMAX, FIXED, KIND>;
     using Dist = typename Row::Dist;
     constexpr int LPS = PMAX;
-    constexpr int EX = PAIR_TX + 2;                // row length of the tile and its border in LDS
-    constexpr int HALF = PAIR_TX * PAIR_TY / 2;     // seeds of one colour in a tile
-    static_assert(PAIR_TX % 2 == 0 && PAIR_TY % 2 == 0 && HALF + PAIR_TX / 2 + PAIR_TY / 2 <= PAIR_TPB / LPS,
-                  "one pass per colour");
-    __shared__ uint32_t first[(PAIR_TY + 2) * EX];   // first-pass displacements
+    __shared__ uint32_t ldisp[2][MULTI_W * MULTI_H];   // per colour, over R_0
+    __shared__ Dist ldist[2][MULTI_W * MULTI_H];
     const Geo& g = a.g;
-    const int tiles_x = (g.nx + PAIR_TX - 1) / PAIR_TX;
+    const int nph = a.nph;   // 2..MULTI_MAXPH, checked by the launcher
+    const int tiles_x = (g.nx + MULTI_TX - 1) / MULTI_TX;
     const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
     const LBlock lb = logical_block(nbx, a.b.ndir);
     const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
     const DirArgs D = pair_dir(a.d[lb.dir], zo);
     const Field out = pair_field(a.out[lb.dir], zo);
-    const int x0 = (lb.x % tiles_x) * PAIR_TX, y0 = (lb.x / tiles_x) * PAIR_TY;
+    const int x0 = (lb.x % tiles_x) * MULTI_TX, y0 = (lb.x / tiles_x) * MULTI_TY;
     const int r = threadIdx.x % LPS, grp = threadIdx.x / LPS;
-    // the second half-sweep's propagation members are (i - sx, j) and (i, j - sy)
-    const int k2 = a.t2 & 3;
-    const int sx = (k2 == 0 || k2 == 3) ? 1 : -1, sy = (k2 == 0 || k2 == 2) ? 1 : -1;
-    uint32_t nev = 0;
-    {
-        int i = -1, j = -1;
-        bool own = false;
-        if (grp < HALF) {
-            j = y0 + grp / (PAIR_TX / 2);
-            i = x0 + 2 * (grp % (PAIR_TX / 2)) + ((a.c1 + j + x0) & 1);
-            own = true;
-        } else if (a.second && grp < HALF + PAIR_TY / 2) {   // the look-back column
-            i = sx == 1 ? x0 - 1 : x0 + PAIR_TX;
-            j = y0 + 2 * (grp - HALF) + ((a.c1 + i + y0) & 1);
-        } else if (a.second && grp < HALF + PAIR_TY / 2 + PAIR_TX / 2) {   // the look-back row
-            j = sy == 1 ? y0 - 1 : y0 + PAIR_TY;
-            i = x0 + 2 * (grp - HALF - PAIR_TY / 2) + ((a.c1 + j + x0) & 1);
+    // the rectangles [xa, xb) x [ya, yb), from the tile outward
+    int xa[MULTI_MAXPH], xb[MULTI_MAXPH], ya[MULTI_MAXPH], yb[MULTI_MAXPH];
+    xa[MULTI_MAXPH - 1] = x0;
+    xb[MULTI_MAXPH - 1] = x0 + MULTI_TX;
+    ya[MULTI_MAXPH - 1] = y0;
+    yb[MULTI_MAXPH - 1] = y0 + MULTI_TY;
+#pragma unroll
+    for (int q = MULTI_MAXPH - 2; q >= 0; q--) {   // rectangle of half-sweep m = q - (MULTI_MAXPH - nph)
+        const int m1 = q + 1 - (MULTI_MAXPH - nph);   // the half-sweep after it
+        const int k = m1 > 0 ? a.t[m1] & 3 : 0;
+        const int sx = (k == 0 || k == 3) ? 1 : -1, sy = (k == 0 || k == 2) ? 1 : -1;
+        const bool grow = m1 > 0;
+        xa[q] = xa[q + 1] - (grow && sx == 1);
+        xb[q] = xb[q + 1] + (grow && sx == -1);
+        ya[q] = ya[q + 1] - (grow && sy == 1);
+        yb[q] = yb[q + 1] + (grow && sy == -1);
+    }
+    const int o = MULTI_MAXPH - nph;   // rectangle index of half-sweep 0
+    const int ox = xa[o], oy = ya[o];  // LDS cells are relative to R_0
+    // group grp's seed of half-sweep m: the grp-th cell of colour c[m] of R_m in row order
+    auto pick = [&](int m, int& x, int& y) {
+        const int c = a.c[m];
+        const int Xa = xa[o + m], Ya = ya[o + m], W = xb[o + m] - Xa, H = yb[o + m] - Ya;
+        x = -1;
+        y = -1;
+        if (W & 1) {   // colours alternate along the whole row-major order
+            const int q = 2 * grp + ((c + Xa + Ya) & 1);
+            if (q < W * H) {
+                x = Xa + q % W;
+                y = Ya + q / W;
+            }
+        } else if (grp < (W / 2) * H) {
+            y = Ya + grp / (W / 2);
+            x = Xa + 2 * (grp % (W / 2)) + ((c + y + Xa) & 1);
         }
-        if (i >= 0 && j >= 0 && i < g.nx && j < g.ny) {
+        return x >= 0 && y >= 0 && x < g.nx && y < g.ny;   // cells outside the grid are skipped
+    };
+    // The reads of a half-sweep that need nothing from the one before it (the seed's patch,
+    // its field, its random offsets) are issued before the barrier that ends that one; the
+    // barrier waits for LDS only, so they stay in flight across it.
+    auto start = [&](SeedStart<Row>& S, int m, int x, int y) {
+        seed_start<Row, LPS, true>(S, D, g, x, y, a.t[m], a.nI, r);
+        if (m >= 2) {   // the result of half-sweep m - 2, visible since the barrier that ended it
+            const int cell = (y - oy) * MULTI_W + (x - ox);
+            S.cur0 = ldisp[a.c[m]][cell];
+            S.cd0 = ldist[a.c[m]][cell];
+        }
+    };
+    int x, y;
+    bool have = pick(0, x, y);
+    SeedStart<Row> S;
+    if (have) start(S, 0, x, y);
+    uint32_t nev = 0;
+    for (int m = 0; m < nph; m++) {
+        const int c = a.c[m], t = a.t[m];
+        if (have) {
+            const bool own = x >= x0 && x < x0 + MULTI_TX && y >= y0 && y < y0 + MULTI_TY;
+            const bool last = m >= nph - 2;
+            const int cell = (y - oy) * MULTI_W + (x - ox);
             const uint32_t* disp = D.f.disp;
-            const int s = j * g.nx + i;
-            const int slot = (j - y0 + 1) * EX + (i - x0 + 1);
-            const uint32_t n = sweep_seed_with<Row, LPS, true>(
-                D, g, i, j, a.t1, a.nI, r,
-                [=](int ni, int nj) { return disp[clampi(nj, 0, g.ny - 1) * g.nx + clampi(ni, 0, g.nx - 1)]; },
+            const uint32_t n = seed_finish<Row, LPS, true>(
+                S, D, g, x, y, t, a.nI, r,
+                [&](int ni, int nj) {
+                    if (m == 0) return disp[clampi(nj, 0, g.ny - 1) * g.nx + clampi(ni, 0, g.nx - 1)];
+                    return ldisp[c ^ 1][(nj - oy) * MULTI_W + (ni - ox)];   // a member in R_{m-1}
+                },
                 [&](uint32_t cur, Dist cd, bool) {
-                    first[slot] = cur;
-                    if (own) {
-                        out.disp[s] = cur;
-                        ((Dist*)out.dist)[s] = cd;
+                    ldisp[c][cell] = cur;
+                    ldist[c][cell] = cd;
+                    if (own && last) {
+                        out.disp[S.s] = cur;
+                        ((Dist*)out.dist)[S.s] = cd;
                     }
                 });
             if (own) nev += n;
         }
-    }
-    // the second pass's reads that need nothing from the first are issued before the barrier
-    const int j2 = y0 + grp / (PAIR_TX / 2);
-    const int i2 = x0 + 2 * (grp % (PAIR_TX / 2)) + ((1 - a.c1 + j2 + x0) & 1);
-    const bool second = a.second && grp < HALF && i2 < g.nx && j2 < g.ny;
-    SeedStart<Row> S2;
-    if (second) seed_start<Row, LPS, true>(S2, D, g, i2, j2, a.t2, a.nI, r);
-    __syncthreads();
-    if (second) {
-        // (ni, nj) lies in the tile or its border: seeds of colour c1 priced above (or
-        // outside the grid, where the value is ignored)
-        nev += seed_finish<Row, LPS, true>(S2, D, g, i2, j2, a.t2, a.nI, r,
-                                           [&](int ni, int nj) { return first[(nj - y0 + 1) * EX + (ni - x0 + 1)]; },
-                                           PutSeed<Dist>{out, S2.s, true});
-    } else if (!a.second && grp < HALF && i2 < g.nx && j2 < g.ny && r == 0) {
-        const int s = j2 * g.nx + i2;
-        out.disp[s] = D.f.disp[s];
-        ((Dist*)out.dist)[s] = ((const Dist*)D.f.dist)[s];
+        if (m + 1 < nph) {
+            have = pick(m + 1, x, y);
+            if (have) start(S, m + 1, x, y);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     }
     count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, r == 0);
 }
@@ -2226,24 +2260,26 @@ hipError_t launch_sweep(const SweepArgs& a, int C2, int kind, hipStream_t s)
     PGM_DISPATCH(k_sweep, a, a.g.ny * ((a.g.nx + 1) / 2));
 }
 
-hipError_t launch_sweep_pair(const SweepPairArgs& a, int C2, int kind, hipStream_t s)
+hipError_t launch_sweep_multi(const SweepMultiArgs& a, int C2, int kind, hipStream_t s)
 {
     const int P = a.d[0].P;
-    if (P > 8 || a.d[1].P > 8 || a.c1 < 0 || a.c1 > 1) return hipErrorInvalidValue;
+    if (P > 8 || a.d[1].P > 8 || a.nph < 2 || a.nph > MULTI_MAXPH) return hipErrorInvalidValue;
+    for (int m = 0; m < a.nph; m++)
+        if (a.c[m] != ((a.c[0] + m) & 1) || a.t[m] < 0) return hipErrorInvalidValue;   // colours alternate
     const bool fixed = P == 8;
-    const long long nb = (long long)sweep_pair_blocks(a.g.nx, a.g.ny) * a.b.ndir * a.b.npairs;
+    const long long nb = (long long)sweep_multi_blocks(a.g.nx, a.g.ny) * a.b.ndir * a.b.npairs;
     if (nb <= 0) return hipSuccess;
     if (nb > 0x7FFFFFFFLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb);
-#define PGM_PAIR(C2_, FX_)                                                                              \
-    if (C2 == C2_ && fixed == FX_) {                                                                     \
-        if (kind == 1) hipLaunchKernelGGL((k_sweep_pair<C2_, 8, FX_, 1>), grid, dim3(PAIR_TPB), 0, s, a);  \
-        else if (kind == 2) hipLaunchKernelGGL((k_sweep_pair<C2_, 8, FX_, 2>), grid, dim3(PAIR_TPB), 0, s, a); \
-        else hipLaunchKernelGGL((k_sweep_pair<C2_, 8, FX_, 0>), grid, dim3(PAIR_TPB), 0, s, a);            \
-        return hipGetLastError();                                                                        \
+#define PGM_MULTI(C2_, FX_)                                                                              \
+    if (C2 == C2_ && fixed == FX_) {                                                                      \
+        if (kind == 1) hipLaunchKernelGGL((k_sweep_multi<C2_, 8, FX_, 1>), grid, dim3(PAIR_TPB), 0, s, a);  \
+        else if (kind == 2) hipLaunchKernelGGL((k_sweep_multi<C2_, 8, FX_, 2>), grid, dim3(PAIR_TPB), 0, s, a); \
+        else hipLaunchKernelGGL((k_sweep_multi<C2_, 8, FX_, 0>), grid, dim3(PAIR_TPB), 0, s, a);            \
+        return hipGetLastError();                                                                         \
     }
-    PGM_PAIR(6, true) PGM_PAIR(6, false) PGM_PAIR(2, true) PGM_PAIR(2, false)
-#undef PGM_PAIR
+    PGM_MULTI(6, true) PGM_MULTI(6, false) PGM_MULTI(2, true) PGM_MULTI(2, false)
+#undef PGM_MULTI
     return hipErrorInvalidValue;
 }
 
