@@ -128,8 +128,9 @@ def measured_traffic():
 
 def sweep_roofline(pgm, ctx, steps, run, torch, traffic=None, ops_per_eval=None, peak=None, unit="TOP/s",
                    op="v_sad_u16 (two 16-bit absolute differences), 192 per 8x8x6 patch distance", bound="alu"):
-    """Run `steps` steps with per-launch HIP events on; return (roofline of k_sweep, per-kind
-    breakdown). achieved = evaluations x ops_per_eval / launches / average launch duration."""
+    """Run `steps` steps with per-launch HIP events on; return (roofline of the half-sweep kernel
+    that takes the most time, per-kind breakdown). achieved = evaluations x ops_per_eval /
+    launches / average launch duration."""
     ops_per_eval = OPS_PER_EVAL if ops_per_eval is None else ops_per_eval
     peak = VALU_PEAK_TOPS if peak is None else peak
     pgm.pgm_profile(ctx, True)
@@ -146,7 +147,13 @@ def sweep_roofline(pgm, ctx, steps, run, torch, traffic=None, ops_per_eval=None,
             breakdown[name] = dict(launches_per_step=n / steps, ms_per_step=ms / steps,
                                    avg_launch_us=1000.0 * ms / n, evals=ev)
     pgm.pgm_profile(ctx, False)
-    sw = breakdown.get("sweep")
+    # the half-sweep kernel that takes the most time per step: k_sweep, or k_sweep_multi
+    # (several half-sweeps of a small level per launch) where every level is small
+    cand = [k for k in ("sweep", "sweep_multi") if k in breakdown]
+    which = max(cand, key=lambda k: breakdown[k]["ms_per_step"]) if cand else None
+    sw = breakdown.get(which) if which else None
+    if which != "sweep":
+        traffic = None   # the counted HBM bytes are those of k_sweep launches
     roof = None
     if sw:
         n_launch = sw["launches_per_step"] * steps
@@ -157,7 +164,8 @@ def sweep_roofline(pgm, ctx, steps, run, torch, traffic=None, ops_per_eval=None,
                 # the HBM side of the same launches, from the counted bytes (when current)
                 "hbm_GBps": (round(traffic / (sw["avg_launch_us"] * 1e-6) / 1e9, 1) if traffic else None),
                 "hbm_frac": (round(traffic / (sw["avg_launch_us"] * 1e-6) / 8.0e12, 4) if traffic else None),
-                "kernel": "k_sweep (propagation + random search half-sweep)",
+                "kernel": ("k_sweep (propagation + random search half-sweep)" if which == "sweep" else
+                           "k_sweep_multi (2-4 propagation + random search half-sweeps of a small level per launch)"),
                 "op": op,
                 "avg_launch_us": round(sw["avg_launch_us"], 3),
                 "ops_per_launch": round(ops_per_launch),

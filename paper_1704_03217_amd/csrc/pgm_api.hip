@@ -747,8 +747,11 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
                 hs_t[nhs] = t;
                 hs_c[nhs++] = colour;
             }
+        // (six-channel float features excepted: that kernel variant needs 295 registers per
+        // lane, one wave per SIMD)
         const bool multi = shared && nhs >= 2 && std::max(p->patch_fwd, p->patch_bwd) <= 8 &&
-                           !(c->sched & PGM_SCHED_SEPARATE) && (long long)g.nx * g.ny * npairs <= MULTI_MAX_SEEDS;
+                           !(Y.kind == 1 && Y.C2 == 6) && !(c->sched & PGM_SCHED_SEPARATE) &&
+                           (long long)g.nx * g.ny * npairs <= MULTI_MAX_SEEDS;
         int chunk[2 * 256], nch = 0;
         if (multi) {
             for (int h = 0; h + 4 <= nhs; h += 4) chunk[nch++] = 4;
