@@ -209,7 +209,7 @@ inline int sweep_blocks(int nx, int ny, int P) { return match_blocks(ny * ((nx +
 // Tiles of seeds of a launch of several half-sweeps (four-wave work-groups of 32 seed groups,
 // patch sides <= 8): 4 x 6 seeds, so that the rectangle of the first of up to four half-sweeps
 // (7 x 9 seeds) holds at most 32 seeds of its colour.
-constexpr int PAIR_TPB = 256;
+constexpr int MULTI_TPB = 256;
 inline int sweep_multi_blocks(int nx, int ny) { return ((nx + 3) / 4) * ((ny + 5) / 6); }
 
 // Launch wrappers (pgm_kernels.hip). Each returns hipSuccess or the launch error.

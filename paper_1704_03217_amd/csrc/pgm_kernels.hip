@@ -691,10 +691,10 @@ __global__ __launch_bounds__(MATCH_TPB) void k_sweep(SweepArgs a)
 // colour, so the launch writes the whole field once.
 constexpr int MULTI_TX = 4, MULTI_TY = 6, MULTI_MAXPH = 4;
 constexpr int MULTI_W = MULTI_TX + MULTI_MAXPH - 1, MULTI_H = MULTI_TY + MULTI_MAXPH - 1;
-static_assert((MULTI_W * MULTI_H + 1) / 2 <= PAIR_TPB / 8, "every half-sweep of a tile in one pass");
+static_assert((MULTI_W * MULTI_H + 1) / 2 <= MULTI_TPB / 8, "every half-sweep of a tile in one pass");
 
 template <int C2, int PMAX, bool FIXED, int KIND>
-__global__ __launch_bounds__(PAIR_TPB) void k_sweep_multi(SweepMultiArgs a)
+__global__ __launch_bounds__(MULTI_TPB) void k_sweep_multi(SweepMultiArgs a)
 {
     static_assert(PMAX == 8, "eight lanes per seed");
     using Row = RowT<C2, PMAX, FIXED, KIND>;
@@ -2273,9 +2273,9 @@ hipError_t launch_sweep_multi(const SweepMultiArgs& a, int C2, int kind, hipStre
     const dim3 grid((unsigned)nb);
 #define PGM_MULTI(C2_, FX_)                                                                              \
     if (C2 == C2_ && fixed == FX_) {                                                                      \
-        if (kind == 1) hipLaunchKernelGGL((k_sweep_multi<C2_, 8, FX_, 1>), grid, dim3(PAIR_TPB), 0, s, a);  \
-        else if (kind == 2) hipLaunchKernelGGL((k_sweep_multi<C2_, 8, FX_, 2>), grid, dim3(PAIR_TPB), 0, s, a); \
-        else hipLaunchKernelGGL((k_sweep_multi<C2_, 8, FX_, 0>), grid, dim3(PAIR_TPB), 0, s, a);            \
+        if (kind == 1) hipLaunchKernelGGL((k_sweep_multi<C2_, 8, FX_, 1>), grid, dim3(MULTI_TPB), 0, s, a);  \
+        else if (kind == 2) hipLaunchKernelGGL((k_sweep_multi<C2_, 8, FX_, 2>), grid, dim3(MULTI_TPB), 0, s, a); \
+        else hipLaunchKernelGGL((k_sweep_multi<C2_, 8, FX_, 0>), grid, dim3(MULTI_TPB), 0, s, a);            \
         return hipGetLastError();                                                                         \
     }
     PGM_MULTI(6, true) PGM_MULTI(6, false) PGM_MULTI(2, true) PGM_MULTI(2, false)
