@@ -61,8 +61,10 @@ long long dir_blocks(const pgm_params* p, int groups)
 enum { ENTER_INIT = 0, ENTER_DOWN_F = 1, ENTER_DOWN_FO = 2, ENTER_UP_FO = 3 };
 // largest level (seeds x pairs) entered by one fused launch
 constexpr long long FUSE_MAX_SEEDS = 8192;
-// largest level (seeds x pairs) whose half-sweeps run several per launch
-constexpr long long MULTI_MAX_SEEDS = 8192;
+// largest level (seeds x pairs) whose half-sweeps run up to four per launch (4 x 6-seed
+// tiles), and up to two (6 x 8-seed tiles: half as many work-groups, one round of the chip
+// where 4 x 6 tiles would take two)
+constexpr long long MULTI_MAX_SEEDS = 8192, PAIR_MAX_SEEDS = 16384;
 
 size_t take(size_t& cur, size_t bytes)
 {
@@ -204,7 +206,8 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
         const long long per_sweep = variant(p->patch_fwd) == variant(p->patch_bwd) ? 2 * sb(p->patch_fwd)
                                                                                    : sb(p->patch_fwd) + sb(p->patch_bwd);
         Y.cnt_cap[CNT_SWEEP] += 2LL * p->iters[l] * per_sweep;
-        Y.cnt_cap[CNT_MULTI] += 2LL * p->iters[l] * 2 * sweep_multi_blocks(Y.lnx[l], Y.lny[l]);   // one launch per half-sweep at most
+        Y.cnt_cap[CNT_MULTI] += 2LL * p->iters[l] * 2 *   // one launch per half-sweep at most
+                                std::max(sweep_multi_blocks(Y.lnx[l], Y.lny[l]), sweep_pair_blocks(Y.lnx[l], Y.lny[l]));
     }
     for (int k = 0; k < 5; k++) Y.cnt[k] = take(cur, (size_t)Y.cnt_cap[k] * 4 + 4);
     // partial evaluation sums of the count reduction: COUNT_SLICES x KINDS per pair
@@ -737,10 +740,11 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         memset(&la, 0, sizeof la);
         const bool in_lds = lds_level(k, la.lay);
         // Step 1's half-sweeps (iteration, colour), red then black. A small level's run
-        // several per launch (k_sweep_multi), each launch reading the field from one buffer
-        // and writing it whole to the other: chunks of 4, the rest as 2 or 3. With an odd
-        // number of launches the level's entry writes the second buffer, so that the last
-        // launch writes the level's own.
+        // several per launch, each launch reading the field from one buffer and writing it
+        // whole to the other: chunks of 4 with the rest as 2 or 3 (k_sweep_multi), or on a
+        // larger level chunks of 2 (k_sweep_pair) and a last odd one alone, in place on the
+        // buffer that holds the field. With an odd number of two-buffer launches the level's
+        // entry writes the second buffer, so that the last of them writes the level's own.
         int hs_t[2 * 256], hs_c[2 * 256], nhs = 0;   // iterations are at most 255
         for (int t = 0; t < (in_lds ? 0 : p->iters[l]); t++)
             for (int colour = ((fuse == 1 || fuse == 3) && t == 0) ? 1 : 0; colour < 2; colour++) {
@@ -749,11 +753,13 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
             }
         // (six-channel float features excepted: that kernel variant needs 295 registers per
         // lane, one wave per SIMD)
+        const long long lseeds = (long long)g.nx * g.ny * npairs;
         const bool multi = shared && nhs >= 2 && std::max(p->patch_fwd, p->patch_bwd) <= 8 &&
                            !(Y.kind == 1 && Y.C2 == 6) && !(c->sched & PGM_SCHED_SEPARATE) &&
-                           (long long)g.nx * g.ny * npairs <= MULTI_MAX_SEEDS;
-        int chunk[2 * 256], nch = 0;
-        if (multi) {
+                           lseeds <= PAIR_MAX_SEEDS;
+        const bool pairs_only = lseeds > MULTI_MAX_SEEDS;
+        int chunk[2 * 256], nch = 0, nflip = 0;
+        if (multi && !pairs_only) {
             for (int h = 0; h + 4 <= nhs; h += 4) chunk[nch++] = 4;
             const int rest = nhs % 4;
             if (rest == 1) {   // 4 + 1 as 3 + 2
@@ -762,8 +768,12 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
             } else if (rest) {
                 chunk[nch++] = rest;
             }
+        } else if (multi) {
+            for (int h = 0; h + 2 <= nhs; h += 2) chunk[nch++] = 2;
+            if (nhs & 1) chunk[nch++] = 1;
         }
-        const bool entry_second = multi && (nch & 1);
+        for (int q = 0; q < nch; q++) nflip += chunk[q] > 1;
+        const bool entry_second = multi && (nflip & 1);
         auto entry_dir = [&](int d) {
             DirArgs a = dirargs(d, l, k);
             if (entry_second) a.f = field2(d, l);
@@ -839,6 +849,23 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         }
         bool second = entry_second;   // which buffer holds the field
         for (int q = 0, h = 0; q < nch; q++) {
+            if (chunk[q] == 1) {   // alone, in place
+                SweepArgs a;
+                memset(&a, 0, sizeof a);
+                for (int d = 0; d < 2; d++) {
+                    a.d[d] = dirargs(d, l, k);
+                    a.d[d].f = second ? field2(d, l) : field(d, l);
+                }
+                a.g = g;
+                a.b = batch(2);
+                a.t = hs_t[h];
+                a.colour = hs_c[h];
+                a.nI = Y.st_nI[k];
+                a.cnt = ctable(CNT_SWEEP, 2LL * sweep_blocks(g.nx, g.ny, a.d[0].P));
+                PGM_HIP(c, timed(PGM_K_SWEEP, [&] { return launch_sweep(a, Y.C2, Y.kind, s); }));
+                h++;
+                continue;
+            }
             SweepMultiArgs a;
             memset(&a, 0, sizeof a);
             for (int d = 0; d < 2; d++) {
@@ -854,8 +881,10 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
                 a.c[m] = hs_c[h + m];
             }
             a.nI = Y.st_nI[k];
-            a.cnt = ctable(CNT_MULTI, 2LL * sweep_multi_blocks(g.nx, g.ny));
-            PGM_HIP(c, timed(PGM_K_SWEEP_MULTI, [&] { return launch_sweep_multi(a, Y.C2, Y.kind, s); }));
+            a.cnt = ctable(CNT_MULTI, 2LL * (pairs_only ? sweep_pair_blocks(g.nx, g.ny) : sweep_multi_blocks(g.nx, g.ny)));
+            PGM_HIP(c, timed(PGM_K_SWEEP_MULTI, [&] {
+                return pairs_only ? launch_sweep_pair(a, Y.C2, Y.kind, s) : launch_sweep_multi(a, Y.C2, Y.kind, s);
+            }));
             h += chunk[q];
             second = !second;
         }

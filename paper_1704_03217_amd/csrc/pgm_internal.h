@@ -211,6 +211,8 @@ inline int sweep_blocks(int nx, int ny, int P) { return match_blocks(ny * ((nx +
 // (7 x 9 seeds) holds at most 32 seeds of its colour.
 constexpr int MULTI_TPB = 256;
 inline int sweep_multi_blocks(int nx, int ny) { return ((nx + 3) / 4) * ((ny + 5) / 6); }
+// two half-sweeps per launch on 6 x 8-seed tiles (half as many work-groups)
+inline int sweep_pair_blocks(int nx, int ny) { return ((nx + 5) / 6) * ((ny + 7) / 8); }
 
 // Launch wrappers (pgm_kernels.hip). Each returns hipSuccess or the launch error.
 // Per-image pointers are those of pair 0; pair z's source is src_zs bytes further and its
@@ -257,6 +259,7 @@ hipError_t launch_gradient(GradArgs a, int npairs, int gray, int ksize, int feat
 hipError_t launch_init(const InitArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_sweep(const SweepArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_sweep_multi(const SweepMultiArgs& a, int C2, int kind, hipStream_t s);
+hipError_t launch_sweep_pair(const SweepMultiArgs& a, int C2, int kind, hipStream_t s);   // nph == 2
 hipError_t launch_down(const TransArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_up(const TransArgs& a, int C2, int kind, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);

@@ -799,6 +799,88 @@ __global__ __launch_bounds__(MULTI_TPB) void k_sweep_multi(SweepMultiArgs a)
     count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, r == 0);
 }
 
+// Two consecutive half-sweeps per launch on 6 x 8-seed tiles, for levels whose 4 x 6 tiles would
+// take the chip twice over: half as many work-groups. Work-group (x0, y0) owns the tile, one
+// 8-lane group per seed; the field is read only from the input buffer and the tile is written
+// whole to the output buffer. First pass: the tile's seeds of colour c[0] at iteration t[0] and
+// the seeds of that colour in the column and the row just outside the tile that the second
+// half-sweep's propagation members come from (their results stay in LDS: 24 + 4 + 3 seeds, one
+// pass of 32 groups). Second pass: the tile's seeds of the other colour at iteration t[1], their
+// members from LDS. Only the tile's own seeds are counted.
+constexpr int PAIR_TX = 6, PAIR_TY = 8;
+
+template <int C2, int PMAX, bool FIXED, int KIND>
+__global__ __launch_bounds__(MULTI_TPB) void k_sweep_pair(SweepMultiArgs a)
+{
+    static_assert(PMAX == 8, "eight lanes per seed");
+    using Row = RowT<C2, PMAX, FIXED, KIND>;
+    using Dist = typename Row::Dist;
+    constexpr int LPS = PMAX;
+    constexpr int EX = PAIR_TX + 2;                // row length of the tile and its border in LDS
+    constexpr int HALF = PAIR_TX * PAIR_TY / 2;     // seeds of one colour in a tile
+    static_assert(PAIR_TX % 2 == 0 && PAIR_TY % 2 == 0 && HALF + PAIR_TX / 2 + PAIR_TY / 2 <= MULTI_TPB / LPS,
+                  "one pass per colour");
+    __shared__ uint32_t first[(PAIR_TY + 2) * EX];   // first-pass displacements
+    const Geo& g = a.g;
+    const int c1 = a.c[0];
+    const int tiles_x = (g.nx + PAIR_TX - 1) / PAIR_TX;
+    const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
+    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
+    const DirArgs D = pair_dir(a.d[lb.dir], zo);
+    const Field out = pair_field(a.out[lb.dir], zo);
+    const int x0 = (lb.x % tiles_x) * PAIR_TX, y0 = (lb.x / tiles_x) * PAIR_TY;
+    const int r = threadIdx.x % LPS, grp = threadIdx.x / LPS;
+    // the second half-sweep's propagation members are (i - sx, j) and (i, j - sy)
+    const int k2 = a.t[1] & 3;
+    const int sx = (k2 == 0 || k2 == 3) ? 1 : -1, sy = (k2 == 0 || k2 == 2) ? 1 : -1;
+    uint32_t nev = 0;
+    {
+        int i = -1, j = -1;
+        bool own = false;
+        if (grp < HALF) {
+            j = y0 + grp / (PAIR_TX / 2);
+            i = x0 + 2 * (grp % (PAIR_TX / 2)) + ((c1 + j + x0) & 1);
+            own = true;
+        } else if (grp < HALF + PAIR_TY / 2) {   // the look-back column
+            i = sx == 1 ? x0 - 1 : x0 + PAIR_TX;
+            j = y0 + 2 * (grp - HALF) + ((c1 + i + y0) & 1);
+        } else if (grp < HALF + PAIR_TY / 2 + PAIR_TX / 2) {   // the look-back row
+            j = sy == 1 ? y0 - 1 : y0 + PAIR_TY;
+            i = x0 + 2 * (grp - HALF - PAIR_TY / 2) + ((c1 + j + x0) & 1);
+        }
+        if (i >= 0 && j >= 0 && i < g.nx && j < g.ny) {
+            const uint32_t* disp = D.f.disp;
+            const int s = j * g.nx + i;
+            const int slot = (j - y0 + 1) * EX + (i - x0 + 1);
+            const uint32_t n = sweep_seed_with<Row, LPS, true>(
+                D, g, i, j, a.t[0], a.nI, r,
+                [=](int ni, int nj) { return disp[clampi(nj, 0, g.ny - 1) * g.nx + clampi(ni, 0, g.nx - 1)]; },
+                [&](uint32_t cur, Dist cd, bool) {
+                    first[slot] = cur;
+                    if (own) {
+                        out.disp[s] = cur;
+                        ((Dist*)out.dist)[s] = cd;
+                    }
+                });
+            if (own) nev += n;
+        }
+    }
+    __syncthreads();
+    if (grp < HALF) {
+        const int j = y0 + grp / (PAIR_TX / 2);
+        const int i = x0 + 2 * (grp % (PAIR_TX / 2)) + ((1 - c1 + j + x0) & 1);
+        if (i < g.nx && j < g.ny) {
+            // (ni, nj) lies in the tile or its border: seeds of colour c[0] priced above (or
+            // outside the grid, where the value is ignored)
+            nev += sweep_seed_with<Row, LPS, true>(
+                D, g, i, j, a.t[1], a.nI, r, [&](int ni, int nj) { return first[(nj - y0 + 1) * EX + (ni - x0 + 1)]; },
+                PutSeed<Dist>{out, j * g.nx + i, true});
+        }
+    }
+    count_evals(zoff(a.cnt, zo), lb.dir * nbx + lb.x, nev, r == 0);
+}
+
 // ---------------------------------------------------------------------------------------
 // initial field at the coarsest level: random displacement in [-R, R]^2 (drawn in k_prep) or
 // the exact best displacement in that window (dy outer, dx inner, strictly smaller wins)
@@ -2280,6 +2362,28 @@ hipError_t launch_sweep_multi(const SweepMultiArgs& a, int C2, int kind, hipStre
     }
     PGM_MULTI(6, true) PGM_MULTI(6, false) PGM_MULTI(2, true) PGM_MULTI(2, false)
 #undef PGM_MULTI
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_pair(const SweepMultiArgs& a, int C2, int kind, hipStream_t s)
+{
+    const int P = a.d[0].P;
+    if (P > 8 || a.d[1].P > 8 || a.nph != 2 || a.c[1] != 1 - a.c[0] || (a.c[0] & ~1) || a.t[0] < 0 || a.t[1] < 0)
+        return hipErrorInvalidValue;
+    const bool fixed = P == 8;
+    const long long nb = (long long)sweep_pair_blocks(a.g.nx, a.g.ny) * a.b.ndir * a.b.npairs;
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nb);
+#define PGM_PAIR(C2_, FX_)                                                                              \
+    if (C2 == C2_ && fixed == FX_) {                                                                     \
+        if (kind == 1) hipLaunchKernelGGL((k_sweep_pair<C2_, 8, FX_, 1>), grid, dim3(MULTI_TPB), 0, s, a); \
+        else if (kind == 2) hipLaunchKernelGGL((k_sweep_pair<C2_, 8, FX_, 2>), grid, dim3(MULTI_TPB), 0, s, a); \
+        else hipLaunchKernelGGL((k_sweep_pair<C2_, 8, FX_, 0>), grid, dim3(MULTI_TPB), 0, s, a);            \
+        return hipGetLastError();                                                                        \
+    }
+    PGM_PAIR(6, true) PGM_PAIR(6, false) PGM_PAIR(2, true) PGM_PAIR(2, false)
+#undef PGM_PAIR
     return hipErrorInvalidValue;
 }
 
