@@ -147,9 +147,9 @@ def sweep_roofline(pgm, ctx, steps, run, torch, traffic=None, ops_per_eval=None,
             breakdown[name] = dict(launches_per_step=n / steps, ms_per_step=ms / steps,
                                    avg_launch_us=1000.0 * ms / n, evals=ev)
     pgm.pgm_profile(ctx, False)
-    # the half-sweep kernel that takes the most time per step: k_sweep, or k_sweep_multi
-    # (several half-sweeps of a small level per launch) where every level is small
-    cand = [k for k in ("sweep", "sweep_multi") if k in breakdown]
+    # the half-sweep kernel that takes the most time per step: k_sweep, k_sweep_multi (2-4
+    # half-sweeps of a small level per launch) or k_sweep_pair (two per launch)
+    cand = [k for k in ("sweep", "sweep_multi", "sweep_pair") if k in breakdown]
     which = max(cand, key=lambda k: breakdown[k]["ms_per_step"]) if cand else None
     sw = breakdown.get(which) if which else None
     if which != "sweep":
@@ -164,8 +164,10 @@ def sweep_roofline(pgm, ctx, steps, run, torch, traffic=None, ops_per_eval=None,
                 # the HBM side of the same launches, from the counted bytes (when current)
                 "hbm_GBps": (round(traffic / (sw["avg_launch_us"] * 1e-6) / 1e9, 1) if traffic else None),
                 "hbm_frac": (round(traffic / (sw["avg_launch_us"] * 1e-6) / 8.0e12, 4) if traffic else None),
-                "kernel": ("k_sweep (propagation + random search half-sweep)" if which == "sweep" else
-                           "k_sweep_multi (2-4 propagation + random search half-sweeps of a small level per launch)"),
+                "kernel": {"sweep": "k_sweep (propagation + random search half-sweep)",
+                           "sweep_multi": "k_sweep_multi (2-4 propagation + random search half-sweeps of a small "
+                                          "level per launch)",
+                           "sweep_pair": "k_sweep_pair (two propagation + random search half-sweeps per launch)"}[which],
                 "op": op,
                 "avg_launch_us": round(sw["avg_launch_us"], 3),
                 "ops_per_launch": round(ops_per_launch),

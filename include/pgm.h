@@ -302,10 +302,12 @@ PGM_API pgm_status pgm_dump_pyramid(void* ctx, int32_t level, int32_t image, uin
  * evaluations count under PGM_K_SWEEP; PGM_K_OUTPUT: the
  * matches of both directions and the compaction, so nothing is recorded under PGM_K_COMPACT;
  * PGM_K_REGION: small-region removal; PGM_K_SWEEP_MULTI: two to four half-sweeps of a small
- * level in one launch, whose evaluations count here): */
+ * level in one launch, PGM_K_SWEEP_PAIR: two half-sweeps of a somewhat larger level in one
+ * launch, whose evaluations count under each): */
 enum { PGM_K_PYRAMID = 0, PGM_K_GRADIENT = 1, PGM_K_PREP = 2, PGM_K_INIT = 3, PGM_K_DOWN = 4,
        PGM_K_UP = 5, PGM_K_SWEEP = 6, PGM_K_CHECK = 7, PGM_K_OUTPUT = 8, PGM_K_COMPACT = 9,
-       PGM_K_LEVEL = 10, PGM_K_REGION = 11, PGM_K_SWEEP_MULTI = 12, PGM_K_KINDS = 13 };
+       PGM_K_LEVEL = 10, PGM_K_REGION = 11, PGM_K_SWEEP_MULTI = 12, PGM_K_SWEEP_PAIR = 13,
+       PGM_K_KINDS = 14 };
 PGM_API pgm_status pgm_profile(void* ctx, int32_t enable);
 PGM_API pgm_status pgm_profile_read(void* ctx, int32_t kind, int64_t* host_launches,
                                     double* host_total_ms, uint64_t* host_evals);

@@ -82,9 +82,9 @@ EXPORTS = ("pgm_default_params", "pgm_query", "pgm_create", "pgm_match", "pgm_ma
 
 # kernel kinds of pgm_profile_read
 K_PYRAMID, K_GRADIENT, K_PREP, K_INIT, K_DOWN, K_UP, K_SWEEP, K_CHECK, K_OUTPUT, K_COMPACT, K_LEVEL, K_REGION, \
-    K_SWEEP_MULTI = range(13)
+    K_SWEEP_MULTI, K_SWEEP_PAIR = range(14)
 KIND_NAMES = ("pyramid", "gradient", "prep", "init", "down", "up", "sweep", "check", "output", "compact", "level",
-              "region", "sweep_multi")
+              "region", "sweep_multi", "sweep_pair")
 
 
 class PGMError(RuntimeError):

@@ -35,9 +35,9 @@ struct Layout {
     long long st_base[MAX_STAGES];                       // short2 offset of the stage's offsets
     int R_top = 0;
     // per-block evaluation counts of the matching launches, one table per kernel kind
-    // (init, down, up, sweep, multi-sweep launches)
-    size_t cnt[5] = {0, 0, 0, 0, 0};
-    long long cnt_cap[5] = {0, 0, 0, 0, 0};
+    // (init, down, up, sweep, multi-sweep launches, paired-sweep launches)
+    size_t cnt[6] = {0, 0, 0, 0, 0, 0};
+    long long cnt_cap[6] = {0, 0, 0, 0, 0, 0};
     size_t cntpart = 0;
     size_t cclabel = 0, ccsize = 0;
     // the random-number table is shared by all pairs of a batch; everything else is per pair
@@ -46,7 +46,7 @@ struct Layout {
     size_t total = 0;   // shared + one pair
 };
 
-enum { CNT_INIT = 0, CNT_DOWN = 1, CNT_UP = 2, CNT_SWEEP = 3, CNT_MULTI = 4 };
+enum { CNT_INIT = 0, CNT_DOWN = 1, CNT_UP = 2, CNT_SWEEP = 3, CNT_MULTI = 4, CNT_PAIR = 5 };
 
 // both directions share a launch when their patch sides select the same kernel variant
 int variant(int P) { return P == 8 ? 0 : P < 8 ? 1 : P == 16 ? 2 : 3; }
@@ -206,10 +206,11 @@ void plan(const pgm_params* p, int w, int h, Layout& Y)
         const long long per_sweep = variant(p->patch_fwd) == variant(p->patch_bwd) ? 2 * sb(p->patch_fwd)
                                                                                    : sb(p->patch_fwd) + sb(p->patch_bwd);
         Y.cnt_cap[CNT_SWEEP] += 2LL * p->iters[l] * per_sweep;
-        Y.cnt_cap[CNT_MULTI] += 2LL * p->iters[l] * 2 *   // one launch per half-sweep at most
-                                std::max(sweep_multi_blocks(Y.lnx[l], Y.lny[l]), sweep_pair_blocks(Y.lnx[l], Y.lny[l]));
+        // one launch per half-sweep at most
+        Y.cnt_cap[CNT_MULTI] += 2LL * p->iters[l] * 2 * sweep_multi_blocks(Y.lnx[l], Y.lny[l]);
+        Y.cnt_cap[CNT_PAIR] += 2LL * p->iters[l] * 2 * sweep_pair_blocks(Y.lnx[l], Y.lny[l]);
     }
-    for (int k = 0; k < 5; k++) Y.cnt[k] = take(cur, (size_t)Y.cnt_cap[k] * 4 + 4);
+    for (int k = 0; k < 6; k++) Y.cnt[k] = take(cur, (size_t)Y.cnt_cap[k] * 4 + 4);
     // partial evaluation sums of the count reduction: COUNT_SLICES x KINDS per pair
     Y.cntpart = take(cur, (size_t)COUNT_SLICES * CountArgs::KINDS * sizeof(unsigned long long));
     // region labels and sizes on the level-0 grid (small-region removal)
@@ -556,7 +557,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     // evaluation counts: each matching launch stores one count per work-group into its kind's
     // table (per pair); k_count adds them up at the end
     const bool counting = nev || c->prof || tab_counts;
-    long long cnt_off[5] = {0, 0, 0, 0, 0};
+    long long cnt_off[6] = {0, 0, 0, 0, 0, 0};
     auto ctable = [&](int kind, long long blocks) -> uint32_t* {
         if (!counting) return nullptr;
         uint32_t* t = (uint32_t*)(pw0 + Y.cnt[kind]) + cnt_off[kind];
@@ -881,10 +882,13 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
                 a.c[m] = hs_c[h + m];
             }
             a.nI = Y.st_nI[k];
-            a.cnt = ctable(CNT_MULTI, 2LL * (pairs_only ? sweep_pair_blocks(g.nx, g.ny) : sweep_multi_blocks(g.nx, g.ny)));
-            PGM_HIP(c, timed(PGM_K_SWEEP_MULTI, [&] {
-                return pairs_only ? launch_sweep_pair(a, Y.C2, Y.kind, s) : launch_sweep_multi(a, Y.C2, Y.kind, s);
-            }));
+            if (pairs_only) {
+                a.cnt = ctable(CNT_PAIR, 2LL * sweep_pair_blocks(g.nx, g.ny));
+                PGM_HIP(c, timed(PGM_K_SWEEP_PAIR, [&] { return launch_sweep_pair(a, Y.C2, Y.kind, s); }));
+            } else {
+                a.cnt = ctable(CNT_MULTI, 2LL * sweep_multi_blocks(g.nx, g.ny));
+                PGM_HIP(c, timed(PGM_K_SWEEP_MULTI, [&] { return launch_sweep_multi(a, Y.C2, Y.kind, s); }));
+            }
             h += chunk[q];
             second = !second;
         }
@@ -949,8 +953,8 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
     PGM_HIP(c, close_run());
     if (counting) {
         CountArgs ca;
-        const int kinds[5] = {PGM_K_INIT, PGM_K_DOWN, PGM_K_UP, PGM_K_SWEEP, PGM_K_SWEEP_MULTI};
-        for (int k = 0; k < 5; k++) {
+        const int kinds[6] = {PGM_K_INIT, PGM_K_DOWN, PGM_K_UP, PGM_K_SWEEP, PGM_K_SWEEP_MULTI, PGM_K_SWEEP_PAIR};
+        for (int k = 0; k < 6; k++) {
             ca.table[k] = (const uint32_t*)(pw0 + Y.cnt[k]);
             ca.n[k] = cnt_off[k];
             ca.kind[k] = kinds[k];

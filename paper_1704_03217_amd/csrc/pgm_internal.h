@@ -176,7 +176,7 @@ struct RngArgs {
 };
 
 struct CountArgs {
-    static constexpr int KINDS = 5;      // init, down, up, sweep, multi-sweep launches
+    static constexpr int KINDS = 6;      // init, down, up, sweep, multi-sweep and paired-sweep launches
     const uint32_t* table[KINDS];        // pair 0
     long long n[KINDS];
     int npairs;
