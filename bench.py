@@ -129,8 +129,8 @@ def measured_traffic():
 def sweep_roofline(pgm, ctx, steps, run, torch, traffic=None, ops_per_eval=None, peak=None, unit="TOP/s",
                    op="v_sad_u16 (two 16-bit absolute differences), 192 per 8x8x6 patch distance", bound="alu"):
     """Run `steps` steps with per-launch HIP events on; return (roofline of the half-sweep kernel
-    that takes the most time, per-kind breakdown). achieved = evaluations x ops_per_eval /
-    launches / average launch duration."""
+    that does the most distance evaluations, per-kind breakdown). achieved = evaluations x
+    ops_per_eval / launches / average launch duration."""
     ops_per_eval = OPS_PER_EVAL if ops_per_eval is None else ops_per_eval
     peak = VALU_PEAK_TOPS if peak is None else peak
     pgm.pgm_profile(ctx, True)
@@ -147,10 +147,11 @@ def sweep_roofline(pgm, ctx, steps, run, torch, traffic=None, ops_per_eval=None,
             breakdown[name] = dict(launches_per_step=n / steps, ms_per_step=ms / steps,
                                    avg_launch_us=1000.0 * ms / n, evals=ev)
     pgm.pgm_profile(ctx, False)
-    # the half-sweep kernel that takes the most time per step: k_sweep, k_sweep_multi (2-4
-    # half-sweeps of a small level per launch) or k_sweep_pair (two per launch)
+    # the half-sweep kernel that does the most distance evaluations (deterministic, unlike the
+    # times): k_sweep, k_sweep_multi (2-4 half-sweeps of a small level per launch) or
+    # k_sweep_pair (two per launch)
     cand = [k for k in ("sweep", "sweep_multi", "sweep_pair") if k in breakdown]
-    which = max(cand, key=lambda k: breakdown[k]["ms_per_step"]) if cand else None
+    which = max(cand, key=lambda k: breakdown[k]["evals"]) if cand else None
     sw = breakdown.get(which) if which else None
     if which != "sweep":
         traffic = None   # the counted HBM bytes are those of k_sweep launches
