@@ -262,17 +262,17 @@ def test_image_span_of_2_31_bytes_is_einval(matcher):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("size", [(160, 118), (330, 250)], ids=["160x118", "330x250"])
+@pytest.mark.parametrize("size", [(160, 118), (240, 200), (330, 250)], ids=["160x118", "240x200", "330x250"])
 @pytest.mark.parametrize("iters", [[1, 2, 3, 5], [4, 6, 7, 1], [2, 5, 8, 3]], ids=["1-2-3-5", "4-6-7-1", "2-5-8-3"])
 def test_multi_half_sweeps_every_count(matcher, iters, size):
-    """Small levels (up to 8192 seeds x pairs: every level of the 160x118 pair, levels 1-3 of
-    the 330x250 one, whose level 0 of 110x84 seeds keeps one launch per half-sweep) run up to
-    four half-sweeps per launch, each launch reading the field from one buffer and writing it
-    whole to the other, in chunks of 4 and a rest of 2 or 3, the level's entry writing the
-    second buffer when the number of launches is odd. Per-level iteration counts 1-8, with and
-    without the first half-sweep fused into the level's entry, on seed grids whose tiles are
-    cut by every border, against the oracle bit for bit; and the same under
-    PGM_SCHED_SEPARATE (one launch per half-sweep)."""
+    """Smaller levels run several half-sweeps per launch, each launch reading the field from one
+    buffer and writing it whole to the other, the level's entry writing the second buffer when
+    the number of such launches is odd: up to four per launch on levels of at most 8192 seeds
+    (every level of the 160x118 and 240x200 pairs, 80x67 seeds at level 0 of the latter), two
+    on 6x8 tiles with a last odd one in place at most 16384 (level 0 of the 330x250 pair,
+    110x84 seeds). Per-level iteration counts 1-8, with and without the first half-sweep fused
+    into the level's entry, on seed grids whose tiles are cut by every border, against the
+    oracle bit for bit; and the same under PGM_SCHED_SEPARATE (one launch per half-sweep)."""
     pair = synth.config_pair(1, 21, size)
     img1, img2 = pair.img1, pair.img2
     params = base_params(levels=4, iters=iters, seed_stride=3, radius=3, max_disp=24, rng_seed=4242)
