@@ -657,6 +657,7 @@ static pgm_status match_impl(pgm_ctx_s* c, const pgm_params* p, int32_t npairs, 
         g.w = Y.lw[l]; g.h = Y.lh[l]; g.pw = Y.lw[l] + 2 * PAD;
         g.nx = Y.lnx[l]; g.ny = Y.lny[l];
         g.stride = p->seed_stride; g.off = p->seed_stride / 2;
+        geo_divs(g);
         return g;
     };
     auto field = [&](int d, int l) {

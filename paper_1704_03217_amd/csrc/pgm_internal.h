@@ -57,12 +57,36 @@ struct DirArgs {
     int P;                 // patch side
 };
 
+// floor(n / d) for every 32-bit n by multiplication: M = ceil(2^64 / d) for d >= 2, whose
+// excess e = M d - 2^64 < d adds n e / (d 2^64) < 1 / d to n / d, too little to reach the next
+// integer, so floor(n M / 2^64) is the quotient; d == 1 passes n through. Set up on the host.
+struct DivM {
+    uint32_t d, lo, hi;    // the divisor and the low and high words of M
+};
+inline DivM div_magic(uint32_t d)
+{
+    DivM m{d, 0u, 0u};
+    if (d >= 2) {
+        const uint64_t M = ~0ull / d + 1;   // ceil(2^64 / d)
+        m.lo = (uint32_t)M;
+        m.hi = (uint32_t)(M >> 32);
+    }
+    return m;
+}
+
 struct Geo {
     int w, h;              // level image size
     int pw;                // padded row length in pixels (w + 2 PAD)
     int nx, ny;            // seed grid
     int stride, off;       // grid spacing and first seed position
+    DivM dnx, dhx, d2s;    // division by nx, by (nx + 1) / 2 and by 2 stride (geo_divs)
 };
+inline void geo_divs(Geo& g)
+{
+    g.dnx = div_magic((uint32_t)g.nx);
+    g.dhx = div_magic((uint32_t)(g.nx + 1) / 2);
+    g.d2s = div_magic((uint32_t)(2 * g.stride));
+}
 
 // Pairs of one batch: every per-pair workspace pointer of the kernel arguments points into
 // pair 0's slice; pair z's is `zs` bytes further (the random-number table is shared).
@@ -70,6 +94,7 @@ struct Batch {
     int npairs;
     int ndir;              // directions covered by the launch (1 or 2)
     long long zs;          // workspace bytes per pair
+    DivM dnb;              // division by the work-groups per direction and pair (set by the launcher)
 };
 
 struct SweepArgs {
@@ -90,6 +115,10 @@ struct SweepMultiArgs {
     Batch b;
     int nph, t[4], c[4], nI;
     uint32_t* cnt;         // per-block evaluation counts of this launch, pair 0 (or null)
+    // set by the launcher: division by the tiles per seed row, and per half-sweep the
+    // rectangle it updates relative to the tile (see k_sweep_multi)
+    DivM dtx;
+    uint32_t ph[4];
 };
 
 struct InitArgs {
@@ -256,12 +285,12 @@ struct PrepArgs {
 hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hipStream_t s);
 hipError_t launch_pyr(PyrArgs a, int npairs, hipStream_t s);
 hipError_t launch_gradient(GradArgs a, int npairs, int gray, int ksize, int feat, hipStream_t s);
-hipError_t launch_init(const InitArgs& a, int C2, int kind, hipStream_t s);
-hipError_t launch_sweep(const SweepArgs& a, int C2, int kind, hipStream_t s);
-hipError_t launch_sweep_multi(const SweepMultiArgs& a, int C2, int kind, hipStream_t s);
-hipError_t launch_sweep_pair(const SweepMultiArgs& a, int C2, int kind, hipStream_t s);   // nph == 2
-hipError_t launch_down(const TransArgs& a, int C2, int kind, hipStream_t s);
-hipError_t launch_up(const TransArgs& a, int C2, int kind, hipStream_t s);
+hipError_t launch_init(InitArgs a, int C2, int kind, hipStream_t s);
+hipError_t launch_sweep(SweepArgs a, int C2, int kind, hipStream_t s);
+hipError_t launch_sweep_multi(SweepMultiArgs a, int C2, int kind, hipStream_t s);
+hipError_t launch_sweep_pair(SweepMultiArgs a, int C2, int kind, hipStream_t s);   // nph == 2
+hipError_t launch_down(TransArgs a, int C2, int kind, hipStream_t s);
+hipError_t launch_up(TransArgs a, int C2, int kind, hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, hipStream_t s);
 // ENTER_LAUNCH_START: the check and the transition (k_enter_start); ENTER_LAUNCH_SWEEP: and the
 // first half-sweep (k_enter); ENTER_LAUNCH_INIT: the initial level's random starts and its

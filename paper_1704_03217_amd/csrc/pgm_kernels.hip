@@ -43,11 +43,18 @@ __device__ __forceinline__ int grid_pos(int i, int n, const Geo& g)
     return p < n - 1 ? p : n - 1;
 }
 
+// floor(n / m.d) with the host's multiplier (DivM): two multiplications
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const DivM& m)
+{
+    const uint64_t p = (uint64_t)n * m.hi + __umulhi(n, m.lo);
+    return m.d == 1 ? n : (uint32_t)(p >> 32);
+}
+
 // index of the grid seed nearest to pixel x >= 0 (ties go to the larger index)
 __device__ __forceinline__ int grid_near(int x, int nseeds, const Geo& g)
 {
     unsigned num = (unsigned)(2 * (x - g.off) + g.stride);   // >= 0 because off <= stride/2
-    int i = (int)(num / (unsigned)(2 * g.stride));
+    int i = (int)fdiv(num, g.d2s);                            // num / (2 stride)
     return i < nseeds - 1 ? i : nseeds - 1;
 }
 
@@ -408,19 +415,20 @@ __device__ __forceinline__ void load_own(Row& A, const void* Ga, const Geo& g, i
 // ids are dealt round robin to the 8 XCDs; this remap hands every XCD one contiguous range of
 // logical ids (a band of seeds of one pair, or whole pairs of a batch), so each XCD's L2
 // caches a compact part of the gradient images.
+// The launch holds b.dnb.d work-groups per direction and pair, b.ndir (1 or 2) directions.
 struct LBlock {
     int x, dir, z;
 };
-__device__ __forceinline__ LBlock logical_block(int nbx, int ndir)
+__device__ __forceinline__ LBlock logical_block(const Batch& bt)
 {
     const int N = gridDim.x, L = blockIdx.x;
     const int j = L & 7, q = (N + 7) >> 3, r = N & 7;
-    int id = (r == 0 || j < r) ? j * q + (L >> 3) : r * q + (j - r) * (q - 1) + (L >> 3);
+    const int id = (r == 0 || j < r) ? j * q + (L >> 3) : r * q + (j - r) * (q - 1) + (L >> 3);
+    const int rest = (int)fdiv((uint32_t)id, bt.dnb);
     LBlock b;
-    b.x = id % nbx;
-    id /= nbx;
-    b.dir = id % ndir;
-    b.z = id / ndir;
+    b.x = id - rest * (int)bt.dnb.d;
+    b.dir = bt.ndir == 2 ? (rest & 1) : 0;
+    b.z = bt.ndir == 2 ? (rest >> 1) : rest;
     return b;
 }
 
@@ -661,14 +669,14 @@ __global__ __launch_bounds__(MATCH_TPB) void k_sweep(SweepArgs a)
     constexpr int LPS = PMAX;
     constexpr int GPB = MATCH_TPB / LPS;
     const Geo& g = a.g;
-    const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
-    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const int nbx = (int)a.b.dnb.d;
+    const LBlock lb = logical_block(a.b);
     const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
     const DirArgs D = pair_dir(a.d[lb.dir], zo);
     const int r = threadIdx.x % LPS;
     const int gid = lb.x * GPB + threadIdx.x / LPS;
     const int hx = (g.nx + 1) >> 1;
-    const int j = gid / hx;
+    const int j = (int)fdiv((uint32_t)gid, g.dhx);   // gid / hx
     const int i = 2 * (gid - j * hx) + ((a.colour + j) & 1);
     uint32_t nev = 0;
     if (j < g.ny && i < g.nx) nev = sweep_seed<Row, LPS, true>(D, g, i, j, a.t, a.nI, r);
@@ -682,7 +690,8 @@ __global__ __launch_bounds__(MATCH_TPB) void k_sweep(SweepArgs a)
 // Work-group (x0, y0) owns a MULTI_TX x MULTI_TY tile of seeds, one 8-lane group per seed.
 // Half-sweep m = 0 .. nph-1 updates the seeds of colour c[m] at iteration t[m] inside a
 // rectangle R_m: R_{nph-1} is the tile, and R_m is R_{m+1} grown by one seed on the sides that
-// half-sweep m+1's propagation looks back to, so that every member it reads lies in R_m. The
+// half-sweep m+1's propagation looks back to, so that every member it reads lies in R_m (the
+// launcher lays the rectangles out once for all tiles, plan_multi). The
 // first half-sweep reads the field from the input buffer (which no work-group of the launch
 // writes), the second its own seeds' values from there too; everything else comes from the
 // results of the earlier half-sweeps, kept in LDS per colour over R_0. Every seed thus sees
@@ -704,48 +713,38 @@ __global__ __launch_bounds__(MULTI_TPB) void k_sweep_multi(SweepMultiArgs a)
     __shared__ Dist ldist[2][MULTI_W * MULTI_H];
     const Geo& g = a.g;
     const int nph = a.nph;   // 2..MULTI_MAXPH, checked by the launcher
-    const int tiles_x = (g.nx + MULTI_TX - 1) / MULTI_TX;
-    const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
-    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const int nbx = (int)a.b.dnb.d;
+    const LBlock lb = logical_block(a.b);
     const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
     const DirArgs D = pair_dir(a.d[lb.dir], zo);
     const Field out = pair_field(a.out[lb.dir], zo);
-    const int x0 = (lb.x % tiles_x) * MULTI_TX, y0 = (lb.x / tiles_x) * MULTI_TY;
+    const int ty = (int)fdiv((uint32_t)lb.x, a.dtx);   // tile row; a.dtx.d tiles per row
+    const int x0 = (lb.x - ty * (int)a.dtx.d) * MULTI_TX, y0 = ty * MULTI_TY;   // both even
     const int r = threadIdx.x % LPS, grp = threadIdx.x / LPS;
-    // the rectangles [xa, xb) x [ya, yb), from the tile outward
-    int xa[MULTI_MAXPH], xb[MULTI_MAXPH], ya[MULTI_MAXPH], yb[MULTI_MAXPH];
-    xa[MULTI_MAXPH - 1] = x0;
-    xb[MULTI_MAXPH - 1] = x0 + MULTI_TX;
-    ya[MULTI_MAXPH - 1] = y0;
-    yb[MULTI_MAXPH - 1] = y0 + MULTI_TY;
-#pragma unroll
-    for (int q = MULTI_MAXPH - 2; q >= 0; q--) {   // rectangle of half-sweep m = q - (MULTI_MAXPH - nph)
-        const int m1 = q + 1 - (MULTI_MAXPH - nph);   // the half-sweep after it
-        const int k = m1 > 0 ? a.t[m1] & 3 : 0;
-        const int sx = (k == 0 || k == 3) ? 1 : -1, sy = (k == 0 || k == 2) ? 1 : -1;
-        const bool grow = m1 > 0;
-        xa[q] = xa[q + 1] - (grow && sx == 1);
-        xb[q] = xb[q + 1] + (grow && sx == -1);
-        ya[q] = ya[q + 1] - (grow && sy == 1);
-        yb[q] = yb[q + 1] + (grow && sy == -1);
-    }
-    const int o = MULTI_MAXPH - nph;   // rectangle index of half-sweep 0
-    const int ox = xa[o], oy = ya[o];  // LDS cells are relative to R_0
+    // ph[m]: R_m = [x0 + ax, x0 + ax + W) x [y0 + ay, y0 + ay + H) as bits 0-3 ax + 4, 4-7
+    // ay + 4, 8-11 W, 12-15 H, 16 the colour parity (c[m] + ax + ay) & 1, 20-29 the multiplier
+    // ceil(1024 / V) with V = W (W odd) or W / 2, which divides every q < 65 exactly as q M >> 10
+    const int ox = x0 + (int)(a.ph[0] & 15u) - 4, oy = y0 + (int)((a.ph[0] >> 4) & 15u) - 4;   // R_0: LDS origin
     // group grp's seed of half-sweep m: the grp-th cell of colour c[m] of R_m in row order
     auto pick = [&](int m, int& x, int& y) {
-        const int c = a.c[m];
-        const int Xa = xa[o + m], Ya = ya[o + m], W = xb[o + m] - Xa, H = yb[o + m] - Ya;
+        const uint32_t w = a.ph[m];
+        const int Xa = x0 + (int)(w & 15u) - 4, Ya = y0 + (int)((w >> 4) & 15u) - 4;
+        const int W = (int)((w >> 8) & 15u), H = (int)((w >> 12) & 15u);
+        const int par = (int)((w >> 16) & 1u);   // (c[m] + Xa + Ya) & 1, as x0 + y0 is even
+        const int M = (int)(w >> 20);
         x = -1;
         y = -1;
         if (W & 1) {   // colours alternate along the whole row-major order
-            const int q = 2 * grp + ((c + Xa + Ya) & 1);
+            const int q = 2 * grp + par;
             if (q < W * H) {
-                x = Xa + q % W;
-                y = Ya + q / W;
+                const int yy = (q * M) >> 10;   // q / W
+                x = Xa + q - yy * W;
+                y = Ya + yy;
             }
         } else if (grp < (W / 2) * H) {
-            y = Ya + grp / (W / 2);
-            x = Xa + 2 * (grp % (W / 2)) + ((c + y + Xa) & 1);
+            const int yy = (grp * M) >> 10;   // grp / (W / 2)
+            y = Ya + yy;
+            x = Xa + 2 * (grp - yy * (W / 2)) + ((par + yy) & 1);
         }
         return x >= 0 && y >= 0 && x < g.nx && y < g.ny;   // cells outside the grid are skipped
     };
@@ -823,13 +822,13 @@ __global__ __launch_bounds__(MULTI_TPB) void k_sweep_pair(SweepMultiArgs a)
     __shared__ uint32_t first[(PAIR_TY + 2) * EX];   // first-pass displacements
     const Geo& g = a.g;
     const int c1 = a.c[0];
-    const int tiles_x = (g.nx + PAIR_TX - 1) / PAIR_TX;
-    const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
-    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const int nbx = (int)a.b.dnb.d;
+    const LBlock lb = logical_block(a.b);
     const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
     const DirArgs D = pair_dir(a.d[lb.dir], zo);
     const Field out = pair_field(a.out[lb.dir], zo);
-    const int x0 = (lb.x % tiles_x) * PAIR_TX, y0 = (lb.x / tiles_x) * PAIR_TY;
+    const int ty = (int)fdiv((uint32_t)lb.x, a.dtx);   // tile row; a.dtx.d tiles per row
+    const int x0 = (lb.x - ty * (int)a.dtx.d) * PAIR_TX, y0 = ty * PAIR_TY;
     const int r = threadIdx.x % LPS, grp = threadIdx.x / LPS;
     // the second half-sweep's propagation members are (i - sx, j) and (i, j - sy)
     const int k2 = a.t[1] & 3;
@@ -893,15 +892,15 @@ __global__ __launch_bounds__(MATCH_TPB) void k_init(InitArgs a)
     constexpr int LPS = PMAX;
     constexpr int GPB = MATCH_TPB / LPS;
     const Geo& g = a.g;
-    const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
-    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const int nbx = (int)a.b.dnb.d;
+    const LBlock lb = logical_block(a.b);
     const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
     const DirArgs D = pair_dir(a.d[lb.dir], zo);
     const int r = threadIdx.x % LPS;
     const int s = lb.x * GPB + threadIdx.x / LPS;
     uint32_t nev = 0;
     if (s < g.nx * g.ny) {
-        const int i = s % g.nx, j = s / g.nx;
+        const int j = (int)fdiv((uint32_t)s, g.dnx), i = s - j * g.nx;
         const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
         const int P = D.P;
         Row A;
@@ -947,8 +946,8 @@ __global__ __launch_bounds__(MATCH_TPB) void k_down(TransArgs a)
     constexpr int LPS = PMAX;
     constexpr int GPB = MATCH_TPB / LPS;
     const Geo& g = a.g;
-    const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
-    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const int nbx = (int)a.b.dnb.d;
+    const LBlock lb = logical_block(a.b);
     const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
     const DirArgs D = pair_dir(a.d[lb.dir], zo);
     const Field S = pair_field(a.src[lb.dir], zo);
@@ -956,7 +955,7 @@ __global__ __launch_bounds__(MATCH_TPB) void k_down(TransArgs a)
     const int s = lb.x * GPB + threadIdx.x / LPS;
     uint32_t nev = 0;
     if (s < g.nx * g.ny) {
-        const int i = s % g.nx, j = s / g.nx;
+        const int j = (int)fdiv((uint32_t)s, g.dnx), i = s - j * g.nx;
         const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
         const int ps = grid_near(py >> 1, a.gs.ny, a.gs) * a.gs.nx + grid_near(px >> 1, a.gs.nx, a.gs);
         // the parent's state and this seed's patch are read together
@@ -1001,8 +1000,8 @@ __global__ __launch_bounds__(MATCH_TPB) void k_up(TransArgs a)
     constexpr int GPB = MATCH_TPB / LPS;
     const Geo& g = a.g;     // coarse level being entered
     const Geo& f = a.gs;    // finer source level
-    const int nbx = gridDim.x / (a.b.ndir * a.b.npairs);
-    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const int nbx = (int)a.b.dnb.d;
+    const LBlock lb = logical_block(a.b);
     const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
     const DirArgs D = pair_dir(a.d[lb.dir], zo);
     const Field S = pair_field(a.src[lb.dir], zo);
@@ -1010,7 +1009,7 @@ __global__ __launch_bounds__(MATCH_TPB) void k_up(TransArgs a)
     const int s = lb.x * GPB + threadIdx.x / LPS;
     uint32_t nev = 0;
     if (s < g.nx * g.ny) {
-        const int ci = s % g.nx, cj = s / g.nx;
+        const int cj = (int)fdiv((uint32_t)s, g.dnx), ci = s - cj * g.nx;
         const int px = grid_pos(ci, g.w, g), py = grid_pos(cj, g.h, g);
         int sx = 0, sy = 0, cnt = 0;
         // children: finer seeds whose nearest coarse seed (as in k_down) is this one
@@ -1055,7 +1054,7 @@ __global__ __launch_bounds__(MATCH_TPB) void k_up(TransArgs a)
 // when it is needed.)
 __device__ __forceinline__ int check_partner(const Geo& g, int s, uint32_t d)
 {
-    const int i = s % g.nx, j = s / g.nx;
+    const int j = (int)fdiv((uint32_t)s, g.dnx), i = s - j * g.nx;
     const int qx = grid_pos(i, g.w, g) + d_x(d), qy = grid_pos(j, g.h, g) + d_y(d);
     return grid_near(qy, g.ny, g) * g.nx + grid_near(qx, g.nx, g);
 }
@@ -1208,8 +1207,8 @@ __device__ __forceinline__ void enter_body(const EnterArgs& a)
     using Row = RowT<C2, PMAX, FIXED, KIND>;
     constexpr int LPS = PMAX;
     constexpr int GPB = MATCH_TPB / LPS;
-    const int nbx = 2 * a.nb_col + a.nb_chk;
-    const LBlock lb = logical_block(nbx, a.b.ndir);
+    const int nbx = 2 * a.nb_col + a.nb_chk;   // == a.b.dnb.d
+    const LBlock lb = logical_block(a.b);
     const size_t zo = (size_t)lb.z * (size_t)a.b.zs;
     const Field S = pair_field(a.src[lb.dir], zo);       // the coarser field of this direction
     const Field O = pair_field(a.src[1 - lb.dir], zo);   // and of the opposite direction
@@ -1225,7 +1224,7 @@ __device__ __forceinline__ void enter_body(const EnterArgs& a)
         const int r = threadIdx.x % LPS;
         const int gid = (lb.x - colour * a.nb_col) * GPB + threadIdx.x / LPS;
         const int hx = (a.g.nx + 1) >> 1;
-        const int j = gid / hx;
+        const int j = (int)fdiv((uint32_t)gid, a.g.dhx);   // gid / hx
         const int i = 2 * (gid - j * hx) + ((colour + j) & 1);
         leader = r == 0;
         if (j < a.g.ny && i < a.g.nx) nev = enter_seed<Row, LPS, SWEEP, INIT>(a, D, S, O, i, j, colour == 0, r);
@@ -1330,7 +1329,7 @@ __global__ __launch_bounds__((LevelShape<PMAX, KIND == 1>::threads)) void k_leve
     for (int t = 0; t < a.iters; t++) {
         for (int colour = 0; colour < 2; colour++) {
             for (int q = threadIdx.x / LPS; q < per; q += NG) {
-                const int j = q / hx;
+                const int j = (int)fdiv((uint32_t)q, g.dhx);   // q / hx
                 const int i = 2 * (q - j * hx) + ((colour + j) & 1);
                 if (i < g.nx) nev += sweep_seed<Row, LPS, false>(L, g, i, j, t, a.nI, r);
             }
@@ -1414,7 +1413,7 @@ __global__ __launch_bounds__(256) void k_cc_union(RegionArgs a)
     const Field f = pair_field(a.f, zo);
     int32_t* L = zoff(a.label, zo);
     if (!(f.flags[s] & ST_INL)) return;
-    const int i = s % g.nx, j = s / g.nx;
+    const int j = (int)fdiv((uint32_t)s, g.dnx), i = s - j * g.nx;
     if (i + 1 < g.nx && (f.flags[s + 1] & ST_INL) && cc_linked(f, s, s + 1, a.link2)) cc_union(L, s, s + 1, n);
     if (j + 1 < g.ny && (f.flags[s + g.nx] & ST_INL) && cc_linked(f, s, s + g.nx, a.link2))
         cc_union(L, s, s + g.nx, n);
@@ -1486,7 +1485,7 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a)
     bool inl = false;
     pgm_match_t m;
     if (s < n) {
-        const int i = s % g.nx, j = s / g.nx;
+        const int j = (int)fdiv((uint32_t)s, g.dnx), i = s - j * g.nx;
         const uint32_t d = f.disp[s];
         const uint8_t fl = f.flags[s];
         m.x1 = grid_pos(i, g.w, g);
@@ -2323,6 +2322,7 @@ hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hi
         const bool fixed = P == pmax;                                                            \
         dim3 grid((unsigned)((long long)match_blocks((NGROUPS), P) * (ARGS).b.ndir * (ARGS).b.npairs)); \
         if ((NGROUPS) <= 0) return hipSuccess;                                                   \
+        (ARGS).b.dnb = div_magic((uint32_t)match_blocks((NGROUPS), P));                          \
         PGM_V(KERNEL, 6, 8, true) PGM_V(KERNEL, 6, 8, false) PGM_V(KERNEL, 6, 16, true)           \
         PGM_V(KERNEL, 6, 16, false) PGM_V(KERNEL, 2, 8, true) PGM_V(KERNEL, 2, 8, false)          \
         PGM_V(KERNEL, 2, 16, true) PGM_V(KERNEL, 2, 16, false)                                    \
@@ -2337,12 +2337,32 @@ hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hi
         return hipGetLastError();                                                                \
     }
 
-hipError_t launch_sweep(const SweepArgs& a, int C2, int kind, hipStream_t s)
+hipError_t launch_sweep(SweepArgs a, int C2, int kind, hipStream_t s)
 {
     PGM_DISPATCH(k_sweep, a, a.g.ny * ((a.g.nx + 1) / 2));
 }
 
-hipError_t launch_sweep_multi(const SweepMultiArgs& a, int C2, int kind, hipStream_t s)
+// The rectangles R_m of k_sweep_multi relative to the tile, one packed word per half-sweep:
+// R_{nph-1} is the tile, R_m is R_{m+1} grown by a seed on the sides half-sweep m+1 looks back to.
+static void plan_multi(SweepMultiArgs& a)
+{
+    int xa = 0, xb = MULTI_TX, ya = 0, yb = MULTI_TY;
+    for (int m = a.nph - 1; m >= 0; m--) {
+        if (m < a.nph - 1) {
+            const int k = a.t[m + 1] & 3;
+            const int sx = (k == 0 || k == 3) ? 1 : -1, sy = (k == 0 || k == 2) ? 1 : -1;
+            if (sx == 1) xa--; else xb++;
+            if (sy == 1) ya--; else yb++;
+        }
+        const int W = xb - xa, H = yb - ya;
+        const int V = (W & 1) ? W : W / 2;
+        const uint32_t M = (uint32_t)((1024 + V - 1) / V);
+        a.ph[m] = (uint32_t)(xa + 4) | (uint32_t)(ya + 4) << 4 | (uint32_t)W << 8 | (uint32_t)H << 12 |
+                  (uint32_t)((a.c[m] + xa + ya) & 1) << 16 | M << 20;
+    }
+}
+
+hipError_t launch_sweep_multi(SweepMultiArgs a, int C2, int kind, hipStream_t s)
 {
     const int P = a.d[0].P;
     if (P > 8 || a.d[1].P > 8 || a.nph < 2 || a.nph > MULTI_MAXPH) return hipErrorInvalidValue;
@@ -2353,6 +2373,9 @@ hipError_t launch_sweep_multi(const SweepMultiArgs& a, int C2, int kind, hipStre
     if (nb <= 0) return hipSuccess;
     if (nb > 0x7FFFFFFFLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb);
+    a.b.dnb = div_magic((uint32_t)sweep_multi_blocks(a.g.nx, a.g.ny));
+    a.dtx = div_magic((uint32_t)(a.g.nx + MULTI_TX - 1) / MULTI_TX);
+    plan_multi(a);
 #define PGM_MULTI(C2_, FX_)                                                                              \
     if (C2 == C2_ && fixed == FX_) {                                                                      \
         if (kind == 1) hipLaunchKernelGGL((k_sweep_multi<C2_, 8, FX_, 1>), grid, dim3(MULTI_TPB), 0, s, a);  \
@@ -2365,7 +2388,7 @@ hipError_t launch_sweep_multi(const SweepMultiArgs& a, int C2, int kind, hipStre
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep_pair(const SweepMultiArgs& a, int C2, int kind, hipStream_t s)
+hipError_t launch_sweep_pair(SweepMultiArgs a, int C2, int kind, hipStream_t s)
 {
     const int P = a.d[0].P;
     if (P > 8 || a.d[1].P > 8 || a.nph != 2 || a.c[1] != 1 - a.c[0] || (a.c[0] & ~1) || a.t[0] < 0 || a.t[1] < 0)
@@ -2375,6 +2398,8 @@ hipError_t launch_sweep_pair(const SweepMultiArgs& a, int C2, int kind, hipStrea
     if (nb <= 0) return hipSuccess;
     if (nb > 0x7FFFFFFFLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb);
+    a.b.dnb = div_magic((uint32_t)sweep_pair_blocks(a.g.nx, a.g.ny));
+    a.dtx = div_magic((uint32_t)(a.g.nx + PAIR_TX - 1) / PAIR_TX);
 #define PGM_PAIR(C2_, FX_)                                                                              \
     if (C2 == C2_ && fixed == FX_) {                                                                     \
         if (kind == 1) hipLaunchKernelGGL((k_sweep_pair<C2_, 8, FX_, 1>), grid, dim3(MULTI_TPB), 0, s, a); \
@@ -2387,17 +2412,17 @@ hipError_t launch_sweep_pair(const SweepMultiArgs& a, int C2, int kind, hipStrea
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_init(const InitArgs& a, int C2, int kind, hipStream_t s)
+hipError_t launch_init(InitArgs a, int C2, int kind, hipStream_t s)
 {
     PGM_DISPATCH(k_init, a, a.g.nx * a.g.ny);
 }
 
-hipError_t launch_down(const TransArgs& a, int C2, int kind, hipStream_t s)
+hipError_t launch_down(TransArgs a, int C2, int kind, hipStream_t s)
 {
     PGM_DISPATCH(k_down, a, a.g.nx * a.g.ny);
 }
 
-hipError_t launch_up(const TransArgs& a, int C2, int kind, hipStream_t s)
+hipError_t launch_up(TransArgs a, int C2, int kind, hipStream_t s)
 {
     PGM_DISPATCH(k_up, a, a.g.nx * a.g.ny);
 }
@@ -2412,6 +2437,7 @@ hipError_t launch_enter(EnterArgs a, int C2, int kind, int mode, hipStream_t s)
     const long long nb = (long long)(2 * a.nb_col + a.nb_chk) * a.b.ndir * a.b.npairs;
     if (nb > 0x7FFFFFFFLL || a.b.ndir != 2) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb);
+    a.b.dnb = div_magic((uint32_t)(2 * a.nb_col + a.nb_chk));
     // patch sides up to 8 only: three candidate patches of 16 rows do not fit the registers
     if (mode == ENTER_LAUNCH_SWEEP) {
         PGM_V(k_enter, 6, 8, true) PGM_V(k_enter, 6, 8, false) PGM_V(k_enter, 2, 8, true) PGM_V(k_enter, 2, 8, false)
