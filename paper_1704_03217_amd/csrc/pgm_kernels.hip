@@ -649,16 +649,31 @@ __device__ __forceinline__ uint32_t sweep_seed_with(const DirArgs& D, const Geo&
     return seed_finish<Row, LPS, BUF>(S, D, g, i, j, t, nI, r, nbr, put);
 }
 
-// the half-sweep step in place: neighbours from the field itself (read from clamped indices
-// and masked, so that every read of the phase is in flight at once), a changed seed written back
+// The displacements of the two propagation members of seed (i, j) at iteration t, read from
+// clamped indices (a member off the grid is ignored by seed_finish) before the seed's other
+// reads, as they start its longest chain of dependent reads; handed to seed_finish as its nbr.
+struct Members {
+    uint32_t n0, n1;   // the members (i - sx, j) and (i, j - sy)
+    int i;
+    __device__ __forceinline__ uint32_t operator()(int ni, int) const { return ni == i ? n1 : n0; }
+};
+__device__ __forceinline__ Members read_members(const uint32_t* disp, const Geo& g, int i, int j, int t)
+{
+    const int k = t & 3;
+    const int sx = (k == 0 || k == 3) ? 1 : -1, sy = (k == 0 || k == 2) ? 1 : -1;
+    Members m;
+    m.n0 = disp[clampi(j, 0, g.ny - 1) * g.nx + clampi(i - sx, 0, g.nx - 1)];
+    m.n1 = disp[clampi(j - sy, 0, g.ny - 1) * g.nx + clampi(i, 0, g.nx - 1)];
+    m.i = i;
+    return m;
+}
+
+// the half-sweep step in place: members from the field itself, a changed seed written back
 template <class Row, int LPS, bool BUF>
 __device__ __forceinline__ uint32_t sweep_seed(const DirArgs& D, const Geo& g, int i, int j, int t, int nI, int r)
 {
-    const uint32_t* disp = D.f.disp;
-    return sweep_seed_with<Row, LPS, BUF>(
-        D, g, i, j, t, nI, r,
-        [=](int ni, int nj) { return disp[clampi(nj, 0, g.ny - 1) * g.nx + clampi(ni, 0, g.nx - 1)]; },
-        PutSeed<typename Row::Dist>{D.f, j * g.nx + i, false});
+    const Members nb = read_members(D.f.disp, g, i, j, t);
+    return sweep_seed_with<Row, LPS, BUF>(D, g, i, j, t, nI, r, nb, PutSeed<typename Row::Dist>{D.f, j * g.nx + i, false});
 }
 
 // one half-sweep (Step 1, one colour of one iteration) of every seed of the launch
@@ -1502,13 +1517,19 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a)
         inl = (fl & ST_INL) != 0;
     }
     if (dir != 0 || (!compact && !n_out)) return;   // uniform over the block
-    // inliers before this block: the flags of its 256 x seeds, 16 per load (256-aligned array)
+    // inliers before this block: the flags of its 256 x seeds, 16 per load (256-aligned array),
+    // eight loads in flight per thread
     const uint4* fl4 = (const uint4*)f.flags;
+    const int nq = (int)blockIdx.x * 16;
     uint32_t v = 0;
-    for (int q = threadIdx.x; q < (int)blockIdx.x * 16; q += 256) {
-        const uint4 w = fl4[q];
-        v += __popc(w.x & 0x02020202u) + __popc(w.y & 0x02020202u) + __popc(w.z & 0x02020202u) +
-             __popc(w.w & 0x02020202u);
+    for (int q0 = threadIdx.x; q0 < nq; q0 += 8 * 256) {
+        uint4 w[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) w[u] = q0 + u * 256 < nq ? fl4[q0 + u * 256] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            v += __popc(w[u].x & 0x02020202u) + __popc(w[u].y & 0x02020202u) + __popc(w[u].z & 0x02020202u) +
+                 __popc(w[u].w & 0x02020202u);
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
