@@ -1276,18 +1276,19 @@ __global__ __launch_bounds__(MATCH_TPB) void k_enter_init(EnterArgs a)
 // ---------------------------------------------------------------------------------------
 
 // dst[q] = src[q] for q < n by the NT threads of the work-group, U loads in flight per thread
+// (whole rounds unguarded, so the values stay in registers; the rest one at a time)
 template <int NT, int U, class T>
 __device__ __forceinline__ void copy_in(T* dst, const T* src, int n)
 {
-    for (int q0 = threadIdx.x; q0 < n; q0 += U * NT) {
+    int q = threadIdx.x;
+    for (; q + (U - 1) * NT < n; q += U * NT) {
         T v[U];
 #pragma unroll
-        for (int u = 0; u < U; u++)
-            if (q0 + u * NT < n) v[u] = src[q0 + u * NT];
+        for (int u = 0; u < U; u++) v[u] = src[q + u * NT];
 #pragma unroll
-        for (int u = 0; u < U; u++)
-            if (q0 + u * NT < n) dst[q0 + u * NT] = v[u];
+        for (int u = 0; u < U; u++) dst[q + u * NT] = v[u];
     }
+    for (; q < n; q += NT) dst[q] = src[q];
 }
 
 template <int PMAX, bool F32>
@@ -2007,10 +2008,9 @@ __device__ __forceinline__ void grad_tile(const GradLevel& L, long long dst_zs, 
     constexpr int CH = GRAY ? 1 : 3;
     constexpr int C2 = 2 * CH;
     constexpr int K = KS / 2;
-    constexpr int SW = GRAY ? 1 : 2;   // dwords per staged pixel
     constexpr int NP = GRAY ? 1 : 3;   // row-sum planes
     constexpr int PL = GR_SV * GR_TW;  // dwords per plane
-    uint32_t* S = lds;                             // [GR_SV][GR_SU][SW]
+    uint32_t* S = lds;                             // [GR_SV][GR_SU][1 (gray) or 2 dwords]
     uint32_t* H = lds + GR_SV * GR_SU * 2;         // [NP][GR_SV][GR_TW]
     double* lin = (double*)(lds + GR_LIN_AT);
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
