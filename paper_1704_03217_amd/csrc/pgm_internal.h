@@ -73,6 +73,12 @@ inline DivM div_magic(uint32_t d)
     }
     return m;
 }
+// floor(n / m.d): n M / 2^64 as n hi + the high word of n lo, two multiplications
+__host__ __device__ inline uint32_t fdiv(uint32_t n, const DivM& m)
+{
+    const uint64_t p = (uint64_t)n * m.hi + (uint32_t)(((uint64_t)n * m.lo) >> 32);
+    return m.d == 1 ? n : (uint32_t)(p >> 32);
+}
 
 struct Geo {
     int w, h;              // level image size

@@ -43,13 +43,6 @@ __device__ __forceinline__ int grid_pos(int i, int n, const Geo& g)
     return p < n - 1 ? p : n - 1;
 }
 
-// floor(n / m.d) with the host's multiplier (DivM): two multiplications
-__device__ __forceinline__ uint32_t fdiv(uint32_t n, const DivM& m)
-{
-    const uint64_t p = (uint64_t)n * m.hi + __umulhi(n, m.lo);
-    return m.d == 1 ? n : (uint32_t)(p >> 32);
-}
-
 // index of the grid seed nearest to pixel x >= 0 (ties go to the larger index)
 __device__ __forceinline__ int grid_near(int x, int nseeds, const Geo& g)
 {

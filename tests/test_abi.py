@@ -247,3 +247,18 @@ def test_pgm_log_reports_failures_on_stderr():
     env["PGM_LOG"] = "0"
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
     assert "[pgm]" not in r.stderr
+
+
+def test_division_multipliers_are_exact(tmp_path):
+    """The kernels divide seed and work-group indices by launch-uniform values with host-
+    computed multipliers (DivM, fdiv); the same code, built for the host, must give n / d for
+    every divisor and dividend tried (all divisors up to 70000, powers of two and their
+    neighbours, random 32-bit divisors; edge and random dividends)."""
+    exe = tmp_path / "divm_check"
+    src = os.path.join(ROOT, "tests", "divm_check.hip")
+    hipcc = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc"
+    subprocess.check_call([hipcc, "-O2", "-std=c++17", "--offload-arch=gfx950",
+                           "-I", os.path.join(ROOT, "paper_1704_03217_amd", "csrc"), src, "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert int(out.stdout.split()[-1]) > 10_000_000
