@@ -407,7 +407,9 @@ __device__ __forceinline__ void load_own(Row& A, const void* Ga, const Geo& g, i
 // Logical block of a 1-D launch over nbx x ndir x npairs work-groups. Consecutive work-group
 // ids are dealt round robin to the 8 XCDs; this remap hands every XCD one contiguous range of
 // logical ids (a band of seeds of one pair, or whole pairs of a batch), so each XCD's L2
-// caches a compact part of the gradient images.
+// caches a compact part of the gradient images. The two directions of a block of seeds read
+// the same parts of both images (each image is one direction's own and the other's
+// candidates), so they are neighbours in that order and share an XCD.
 // The launch holds b.dnb.d work-groups per direction and pair, b.ndir (1 or 2) directions.
 struct LBlock {
     int x, dir, z;
@@ -417,11 +419,14 @@ __device__ __forceinline__ LBlock logical_block(const Batch& bt)
     const int N = gridDim.x, L = blockIdx.x;
     const int j = L & 7, q = (N + 7) >> 3, r = N & 7;
     const int id = (r == 0 || j < r) ? j * q + (L >> 3) : r * q + (j - r) * (q - 1) + (L >> 3);
-    const int rest = (int)fdiv((uint32_t)id, bt.dnb);
+    // both directions of one block of seeds are neighbours in the logical order
+    const int two = bt.ndir == 2;
+    const int xz = id >> two;
+    const int rest = (int)fdiv((uint32_t)xz, bt.dnb);
     LBlock b;
-    b.x = id - rest * (int)bt.dnb.d;
-    b.dir = bt.ndir == 2 ? (rest & 1) : 0;
-    b.z = bt.ndir == 2 ? (rest >> 1) : rest;
+    b.x = xz - rest * (int)bt.dnb.d;
+    b.dir = id & two;
+    b.z = rest;
     return b;
 }
 
