@@ -101,6 +101,7 @@ struct Batch {
     int ndir;              // directions covered by the launch (1 or 2)
     long long zs;          // workspace bytes per pair
     DivM dnb;              // division by the work-groups per direction and pair (set by the launcher)
+    int inter;             // both directions read the same two images (set by the launcher)
 };
 
 struct SweepArgs {

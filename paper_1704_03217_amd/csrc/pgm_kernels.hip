@@ -407,9 +407,10 @@ __device__ __forceinline__ void load_own(Row& A, const void* Ga, const Geo& g, i
 // Logical block of a 1-D launch over nbx x ndir x npairs work-groups. Consecutive work-group
 // ids are dealt round robin to the 8 XCDs; this remap hands every XCD one contiguous range of
 // logical ids (a band of seeds of one pair, or whole pairs of a batch), so each XCD's L2
-// caches a compact part of the gradient images. The two directions of a block of seeds read
-// the same parts of both images (each image is one direction's own and the other's
-// candidates), so they are neighbours in that order and share an XCD.
+// caches a compact part of the gradient images. When the two directions read the same two
+// images (each image one direction's own and the other's candidates: one colour space for
+// both), the two directions of a block of seeds are neighbours in that order and share an
+// XCD; with four images (a colour space per direction) each direction keeps its own range.
 // The launch holds b.dnb.d work-groups per direction and pair, b.ndir (1 or 2) directions.
 struct LBlock {
     int x, dir, z;
@@ -419,14 +420,15 @@ __device__ __forceinline__ LBlock logical_block(const Batch& bt)
     const int N = gridDim.x, L = blockIdx.x;
     const int j = L & 7, q = (N + 7) >> 3, r = N & 7;
     const int id = (r == 0 || j < r) ? j * q + (L >> 3) : r * q + (j - r) * (q - 1) + (L >> 3);
-    // both directions of one block of seeds are neighbours in the logical order
     const int two = bt.ndir == 2;
-    const int xz = id >> two;
+    const int alt = two & (bt.inter != 0);   // the directions alternate
+    const int seq = two & !alt;              // all blocks of one direction, then the other's
+    const int xz = id >> alt;
     const int rest = (int)fdiv((uint32_t)xz, bt.dnb);
     LBlock b;
     b.x = xz - rest * (int)bt.dnb.d;
-    b.dir = id & two;
-    b.z = rest;
+    b.dir = alt ? (id & 1) : (rest & seq);
+    b.z = rest >> seq;
     return b;
 }
 
@@ -2332,6 +2334,9 @@ hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hi
 
 #undef PGM_IMG_VARIANTS
 
+// whether the two directions of a launch read the same two gradient images (one colour space)
+static int same_images(const DirArgs d[2]) { return d[0].Ga == d[1].Gb && d[0].Gb == d[1].Ga; }
+
 // Kernel variants: patch side exactly 8 or 16 (fully unrolled rows), or any side up to 8 /
 // up to 16 with masked rows; 6 or 2 gradient channels; integer or float features.
 #define PGM_DISPATCH(KERNEL, ARGS, NGROUPS)                                               \
@@ -2342,6 +2347,7 @@ hipError_t launch_prep(PrepArgs a, int npairs, int gray, int ksize, int feat, hi
         dim3 grid((unsigned)((long long)match_blocks((NGROUPS), P) * (ARGS).b.ndir * (ARGS).b.npairs)); \
         if ((NGROUPS) <= 0) return hipSuccess;                                                   \
         (ARGS).b.dnb = div_magic((uint32_t)match_blocks((NGROUPS), P));                          \
+        (ARGS).b.inter = same_images((ARGS).d);                                                  \
         PGM_V(KERNEL, 6, 8, true) PGM_V(KERNEL, 6, 8, false) PGM_V(KERNEL, 6, 16, true)           \
         PGM_V(KERNEL, 6, 16, false) PGM_V(KERNEL, 2, 8, true) PGM_V(KERNEL, 2, 8, false)          \
         PGM_V(KERNEL, 2, 16, true) PGM_V(KERNEL, 2, 16, false)                                    \
@@ -2393,6 +2399,7 @@ hipError_t launch_sweep_multi(SweepMultiArgs a, int C2, int kind, hipStream_t s)
     if (nb > 0x7FFFFFFFLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb);
     a.b.dnb = div_magic((uint32_t)sweep_multi_blocks(a.g.nx, a.g.ny));
+    a.b.inter = same_images(a.d);
     a.dtx = div_magic((uint32_t)(a.g.nx + MULTI_TX - 1) / MULTI_TX);
     plan_multi(a);
 #define PGM_MULTI(C2_, FX_)                                                                              \
@@ -2418,6 +2425,7 @@ hipError_t launch_sweep_pair(SweepMultiArgs a, int C2, int kind, hipStream_t s)
     if (nb > 0x7FFFFFFFLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb);
     a.b.dnb = div_magic((uint32_t)sweep_pair_blocks(a.g.nx, a.g.ny));
+    a.b.inter = same_images(a.d);
     a.dtx = div_magic((uint32_t)(a.g.nx + PAIR_TX - 1) / PAIR_TX);
 #define PGM_PAIR(C2_, FX_)                                                                              \
     if (C2 == C2_ && fixed == FX_) {                                                                     \
@@ -2457,6 +2465,7 @@ hipError_t launch_enter(EnterArgs a, int C2, int kind, int mode, hipStream_t s)
     if (nb > 0x7FFFFFFFLL || a.b.ndir != 2) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb);
     a.b.dnb = div_magic((uint32_t)(2 * a.nb_col + a.nb_chk));
+    a.b.inter = same_images(a.d);
     // patch sides up to 8 only: three candidate patches of 16 rows do not fit the registers
     if (mode == ENTER_LAUNCH_SWEEP) {
         PGM_V(k_enter, 6, 8, true) PGM_V(k_enter, 6, 8, false) PGM_V(k_enter, 2, 8, true) PGM_V(k_enter, 2, 8, false)
