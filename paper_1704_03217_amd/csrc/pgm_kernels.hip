@@ -1498,6 +1498,15 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a)
     pgm_match_t* out = tz ? tz->out[dir] : a.out[dir] + (size_t)blockIdx.z * n;
     pgm_match_t* compact = tz ? tz->compact : (a.compact ? a.compact + (size_t)blockIdx.z * n : nullptr);
     int32_t* n_out = tz ? tz->n_in : (a.n_out ? a.n_out + blockIdx.z : nullptr);
+    const bool counts = dir == 0 && (compact || n_out);   // uniform over the block
+    // inliers before this block (compaction): the flags of its 256 x seeds, 16 per load
+    // (256-aligned array), eight loads in flight per thread; the first eight are issued
+    // together with the seed's own reads
+    const uint4* fl4 = (const uint4*)f.flags;
+    const int nq = counts ? (int)blockIdx.x * 16 : 0;
+    uint4 w[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) w[u] = (int)threadIdx.x + u * 256 < nq ? fl4[threadIdx.x + u * 256] : make_uint4(0u, 0u, 0u, 0u);
     bool inl = false;
     pgm_match_t m;
     if (s < n) {
@@ -1517,26 +1526,25 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a)
         out[s] = m;
         inl = (fl & ST_INL) != 0;
     }
-    if (dir != 0 || (!compact && !n_out)) return;   // uniform over the block
-    // inliers before this block: the flags of its 256 x seeds, 16 per load (256-aligned array),
-    // eight loads in flight per thread
-    const uint4* fl4 = (const uint4*)f.flags;
-    const int nq = (int)blockIdx.x * 16;
+    if (!counts) return;
     uint32_t v = 0;
-    for (int q0 = threadIdx.x; q0 < nq; q0 += 8 * 256) {
-        uint4 w[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) w[u] = q0 + u * 256 < nq ? fl4[q0 + u * 256] : make_uint4(0u, 0u, 0u, 0u);
+    for (int q0 = threadIdx.x;;) {
 #pragma unroll
         for (int u = 0; u < 8; u++)
             v += __popc(w[u].x & 0x02020202u) + __popc(w[u].y & 0x02020202u) + __popc(w[u].z & 0x02020202u) +
                  __popc(w[u].w & 0x02020202u);
-    }
+        q0 += 8 * 256;
+        if (q0 >= nq) break;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        for (int u = 0; u < 8; u++) w[u] = q0 + u * 256 < nq ? fl4[q0 + u * 256] : make_uint4(0u, 0u, 0u, 0u);
+    }
+    // the wave's total: DPP sums over rows of 16 lanes, then the four rows
+    const uint32_t rows = group_sum<16>(v);
+    const uint32_t wsum = (uint32_t)__builtin_amdgcn_readlane((int)rows, 0) + (uint32_t)__builtin_amdgcn_readlane((int)rows, 16) +
+                          (uint32_t)__builtin_amdgcn_readlane((int)rows, 32) + (uint32_t)__builtin_amdgcn_readlane((int)rows, 48);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long mask = __ballot(inl);
-    if (lane == 0) { part[wv] = v; wtot[wv] = (uint32_t)__popcll(mask); }
+    if (lane == 0) { part[wv] = wsum; wtot[wv] = (uint32_t)__popcll(mask); }
     __syncthreads();
     const uint32_t prefix = part[0] + part[1] + part[2] + part[3];
     uint32_t before = 0;
