@@ -918,13 +918,13 @@ __global__ __launch_bounds__(MATCH_TPB) void k_init(InitArgs a)
         const int j = (int)fdiv((uint32_t)s, g.dnx), i = s - j * g.nx;
         const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
         const int P = D.P;
+        const short2 o = a.exhaustive ? make_short2(0, 0) : D.rnd0[s];   // read before the patch
         Row A;
         load_own<true>(A, D.Ga, g, P, r, px, py);
         using Dist = typename Row::Dist;
         uint32_t best = UNINIT;
         Dist bd = NO_DIST;
         if (!a.exhaustive) {
-            const short2 o = D.rnd0[s];
             best = target(px, py, o.x, o.y, g);
             bd = patch_cost<Row, LPS, true>(A, D.Gb, g, P, r, px + d_x(best), py + d_y(best));
             nev++;
@@ -973,11 +973,11 @@ __global__ __launch_bounds__(MATCH_TPB) void k_down(TransArgs a)
         const int j = (int)fdiv((uint32_t)s, g.dnx), i = s - j * g.nx;
         const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
         const int ps = grid_near(py >> 1, a.gs.ny, a.gs) * a.gs.nx + grid_near(px >> 1, a.gs.nx, a.gs);
-        // the parent's state and this seed's patch are read together
-        Row A;
-        load_own<true>(A, D.Ga, g, D.P, r, px, py);
+        // the parent's state, then this seed's patch (all in flight together)
         const uint8_t pf = S.flags[ps];
         const uint32_t pd = S.disp[ps];
+        Row A;
+        load_own<true>(A, D.Ga, g, D.P, r, px, py);
         const bool par_inl = (pf & ST_INL) != 0;
         uint32_t disp = UNINIT;
         typename Row::Dist dist = NO_DIST;
@@ -1132,10 +1132,9 @@ __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs
     const int s = j * g.nx + i;
     const int px = grid_pos(i, g.w, g), py = grid_pos(j, g.h, g);
     const int P = D.P;
-    Row A;
-    load_own<true>(A, D.Ga, g, P, r, px, py);
     // m = 0: this seed; m = 1, 2: the neighbours (i - 1, j) and (i, j - 1) that the step at
-    // t = 0 propagates from (the first of the Delta orders of Eq. 4)
+    // t = 0 propagates from (the first of the Delta orders of Eq. 4). Their parents' states are
+    // read first (they start the longest chain of reads), then this seed's patch.
     int qx[3], qy[3], ps[3];
     bool on[3] = {false, false, false};
     uint32_t pd[3];
@@ -1155,6 +1154,8 @@ __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs
             pf[m] = S.flags[ps[m]];
         }
     }
+    Row A;
+    load_own<true>(A, D.Ga, g, P, r, px, py);
     const short2* R = D.rnd + (size_t)s * a.nI;   // offsets of the step at t = 0
     const short2 o0 = R[0], o1 = R[a.nI > 1 ? 1 : 0];
     __builtin_amdgcn_sched_barrier(0);
