@@ -574,7 +574,10 @@ struct SeedStart {
     int s, px, py;
 };
 
-template <class Row, int LPS, bool BUF>
+// FF: the seed's field and random offsets are read before its patch (the small launches of
+// k_sweep_multi and k_sweep_pair, whose propagation decisions wait on the field); the large
+// launches of k_sweep, bound by the texture addresser, keep the patch first.
+template <class Row, int LPS, bool BUF, bool FF = false>
 __device__ __forceinline__ void seed_start(SeedStart<Row>& S, const DirArgs& D, const Geo& g, int i, int j, int t,
                                            int nI, int r)
 {
@@ -582,13 +585,14 @@ __device__ __forceinline__ void seed_start(SeedStart<Row>& S, const DirArgs& D, 
     S.s = j * g.nx + i;
     S.px = grid_pos(i, g.w, g);
     S.py = grid_pos(j, g.h, g);
-    load_own<BUF>(S.A, D.Ga, g, D.P, r, S.px, S.py);
+    if constexpr (!FF) load_own<BUF>(S.A, D.Ga, g, D.P, r, S.px, S.py);
     S.cur0 = D.f.disp[S.s];
     S.cd0 = ((const Dist*)D.f.dist)[S.s];
     // Eq. 5 offsets of the first two random candidates (nI >= 1), fetched with the field
     S.R = D.rnd + ((size_t)t * (size_t)(g.nx * g.ny) + S.s) * nI;
     S.o0 = S.R[0];
     S.o1 = S.R[nI > 1 ? 1 : 0];
+    if constexpr (FF) load_own<BUF>(S.A, D.Ga, g, D.P, r, S.px, S.py);
 }
 
 template <class Row, int LPS, bool BUF, class Nbr, class Put>
@@ -640,12 +644,12 @@ __device__ __forceinline__ uint32_t seed_finish(const SeedStart<Row>& S, const D
     return decide_and_search<Row, LPS, BUF>(S.A, D, g, px, py, r, S.R, nI, S.o0, S.o1, cur0, cd0, c, ok, e, put);
 }
 
-template <class Row, int LPS, bool BUF, class Nbr, class Put>
+template <class Row, int LPS, bool BUF, bool FF = false, class Nbr, class Put>
 __device__ __forceinline__ uint32_t sweep_seed_with(const DirArgs& D, const Geo& g, int i, int j, int t, int nI, int r,
                                                     Nbr nbr, Put put)
 {
     SeedStart<Row> S;
-    seed_start<Row, LPS, BUF>(S, D, g, i, j, t, nI, r);
+    seed_start<Row, LPS, BUF, FF>(S, D, g, i, j, t, nI, r);
     return seed_finish<Row, LPS, BUF>(S, D, g, i, j, t, nI, r, nbr, put);
 }
 
@@ -767,7 +771,7 @@ __global__ __launch_bounds__(MULTI_TPB) void k_sweep_multi(SweepMultiArgs a)
     // its field, its random offsets) are issued before the barrier that ends that one; the
     // barrier waits for LDS only, so they stay in flight across it.
     auto start = [&](SeedStart<Row>& S, int m, int x, int y) {
-        seed_start<Row, LPS, true>(S, D, g, x, y, a.t[m], a.nI, r);
+        seed_start<Row, LPS, true, true>(S, D, g, x, y, a.t[m], a.nI, r);
         if (m >= 2) {   // the result of half-sweep m - 2, visible since the barrier that ended it
             const int cell = (y - oy) * MULTI_W + (x - ox);
             S.cur0 = ldisp[a.c[m]][cell];
@@ -867,7 +871,7 @@ __global__ __launch_bounds__(MULTI_TPB) void k_sweep_pair(SweepMultiArgs a)
             const uint32_t* disp = D.f.disp;
             const int s = j * g.nx + i;
             const int slot = (j - y0 + 1) * EX + (i - x0 + 1);
-            const uint32_t n = sweep_seed_with<Row, LPS, true>(
+            const uint32_t n = sweep_seed_with<Row, LPS, true, true>(
                 D, g, i, j, a.t[0], a.nI, r,
                 [=](int ni, int nj) { return disp[clampi(nj, 0, g.ny - 1) * g.nx + clampi(ni, 0, g.nx - 1)]; },
                 [&](uint32_t cur, Dist cd, bool) {
@@ -887,7 +891,7 @@ __global__ __launch_bounds__(MULTI_TPB) void k_sweep_pair(SweepMultiArgs a)
         if (i < g.nx && j < g.ny) {
             // (ni, nj) lies in the tile or its border: seeds of colour c[0] priced above (or
             // outside the grid, where the value is ignored)
-            nev += sweep_seed_with<Row, LPS, true>(
+            nev += sweep_seed_with<Row, LPS, true, true>(
                 D, g, i, j, a.t[1], a.nI, r, [&](int ni, int nj) { return first[(nj - y0 + 1) * EX + (ni - x0 + 1)]; },
                 PutSeed<Dist>{out, j * g.nx + i, true});
         }
