@@ -1077,6 +1077,17 @@ __device__ __forceinline__ int check_partner(const Geo& g, int s, uint32_t d)
     const int qx = grid_pos(i, g.w, g) + d_x(d), qy = grid_pos(j, g.h, g) + d_y(d);
     return grid_near(qy, g.ny, g) * g.nx + grid_near(qx, g.nx, g);
 }
+// the same decision from the opposite field's displacement od at check_partner(g, s, d), read
+// beforehand (whatever d: the partner index is inside the grid for any d)
+__device__ __forceinline__ bool check_decide(uint32_t d, uint32_t od, uint8_t fl, int fwd_bwd, int tau2, int rec_valid)
+{
+    bool ok = d != UNINIT;
+    if (fwd_bwd) {
+        const int ex = d_x(d) + d_x(od), ey = d_y(d) + d_y(od);
+        ok = ok && od != UNINIT && ex * ex + ey * ey <= tau2;
+    }
+    return rec_valid ? (ok && (fl & ST_REC)) : ok;
+}
 __device__ __forceinline__ bool check_inlier(const Field& O, const Geo& g, int s, uint32_t d, uint8_t fl, int fwd_bwd,
                                              int tau2, int rec_valid)
 {
@@ -1163,6 +1174,56 @@ __device__ __forceinline__ uint32_t enter_seed(const EnterArgs& a, const DirArgs
     const short2* R = D.rnd + (size_t)s * a.nI;   // offsets of the step at t = 0
     const short2 o0 = R[0], o1 = R[a.nI > 1 ? 1 : 0];
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (SWEEP && !INIT) {
+        // k_enter (small levels): the parents' checks read the opposite field while the patches
+        // at the starts the parents would give are priced, one round trip fewer; a price is
+        // used only where its start holds (the decisions are those of the path below)
+        uint32_t od[3], spec[3];
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            od[m] = a.fwd_bwd ? O.disp[check_partner(gs, ps[m], pd[m])] : UNINIT;
+            spec[m] = target(qx[m], qy[m], 2 * d_x(pd[m]), 2 * d_y(pd[m]), g);
+        }
+        if (!first) {   // this seed's start alone
+            const Dist ds = patch_cost<Row, LPS, true>(A, D.Gb, g, P, r, px + d_x(spec[0]), py + d_y(spec[0]));
+            const bool in0 = check_decide(pd[0], od[0], pf[0], a.fwd_bwd, a.tau2, a.rec_valid);
+            if (r == 0) {
+                D.f.flags[s] = (a.carry_record && in0) ? ST_REC : 0;
+                D.f.disp[s] = in0 ? spec[0] : UNINIT;
+                ((Dist*)D.f.dist)[s] = in0 ? ds : (Dist)NO_DIST;
+            }
+            return in0 ? 1u : 0u;
+        }
+        const uint32_t cs0 = target(px, py, d_x(spec[1]), d_y(spec[1]), g);
+        const uint32_t cs1 = target(px, py, d_x(spec[2]), d_y(spec[2]), g);
+        int tx[3] = {px + d_x(spec[0]), px + d_x(cs0), px + d_x(cs1)};
+        int ty[3] = {py + d_y(spec[0]), py + d_y(cs0), py + d_y(cs1)};
+        Dist pe[3];
+        patch_cost3<Row, LPS, true>(A, D.Gb, g, P, r, tx, ty, pe);
+        uint32_t st[3];
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+            const bool in = on[m] && check_decide(pd[m], od[m], pf[m], a.fwd_bwd, a.tau2, a.rec_valid);
+            st[m] = in ? spec[m] : UNINIT;
+            if (m == 0 && r == 0) D.f.flags[s] = (a.carry_record && in) ? ST_REC : 0;
+        }
+        const uint32_t cur0 = st[0];
+        const bool init0 = cur0 != UNINIT;
+        uint32_t c[2];
+        bool ok[2];
+#pragma unroll
+        for (int m = 0; m < 2; m++) {
+            ok[m] = st[m + 1] != UNINIT;
+            c[m] = ok[m] ? target(px, py, d_x(st[m + 1]), d_y(st[m + 1]), g) : cur0;
+        }
+        const bool need0 = ok[0] && !(init0 && c[0] == cur0);
+        const bool need1 = ok[1] && !(init0 && c[1] == cur0) && !(ok[0] && c[1] == c[0]);
+        const Dist cd0 = init0 ? pe[0] : (Dist)NO_DIST;
+        Dist e[2] = {need0 ? pe[1] : cd0, need1 ? pe[2] : cd0};
+        if (ok[1] && !need1 && !(init0 && c[1] == cur0)) e[1] = e[0];
+        return (init0 ? 1u : 0u) + decide_and_search<Row, LPS, true>(A, D, g, px, py, r, R, a.nI, o0, o1, cur0, cd0, c,
+                                                                      ok, e, PutSeed<Dist>{D.f, s, true});
+    }
     // the parents' checks (Steps 2-3 at the coarser level) and the starts of Eq. 6
     uint32_t st[3] = {UNINIT, UNINIT, UNINIT};
     bool inl[3] = {false, false, false};
